@@ -1,0 +1,55 @@
+"""Brute-force local alignment by enumerating every alignment.
+
+Independent of both the oracle and the GPU path: it never fills a dynamic
+programming matrix.  A local alignment of a (query) and b (reference) is a
+string of columns -- M (a_i over b_j), I (a_i over a gap) and D (a gap over
+b_j) -- covering a[i0..i1] and b[j0..j1].  Its score is the sum of the
+substitution scores of its M columns minus, for every maximal run of k
+consecutive I columns or k consecutive D columns, the affine cost
+o + (k-1)*e (Section II-B-1, generalised from the linear gap of the worked
+example to an affine one).
+
+An optimal alignment never begins or ends with a gap column when o >= 1
+(dropping it raises the score), so only alignments that begin and end with
+an M column are enumerated.  Among all alignments of maximal score S the
+reported end is the row-major-first one (smallest i1, then smallest j1) and
+the reported start, among optimal alignments with that end, the latest one
+(largest i0, then largest j0).  S == 0 gives all coordinates -1.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def brute_align(a, b, M, o, e):
+    """Return (score, q_start, q_end, r_start, r_end) by exhaustive search."""
+    a = [int(x) for x in a]
+    b = [int(x) for x in b]
+    n, m = len(a), len(b)
+    M = np.asarray(M)
+    best = 0
+    ends = {}  # (i1, j1) -> set of starts achieving the running best
+    results = []  # (score, i0, j0, i1, j1)
+    for i0 in range(n):
+        for j0 in range(m):
+            # explicit stack of (i, j, last_column, score); (i, j) = next unconsumed residues
+            stack = [(i0 + 1, j0 + 1, "M", int(M[a[i0], b[j0]]))]
+            while stack:
+                i, j, last, s = stack.pop()
+                if last == "M":
+                    results.append((s, i0, j0, i - 1, j - 1))
+                if i < n and j < m:
+                    stack.append((i + 1, j + 1, "M", s + int(M[a[i], b[j]])))
+                if i < n:
+                    stack.append((i + 1, j, "I", s - (e if last == "I" else o)))
+                if j < m:
+                    stack.append((i, j + 1, "D", s - (e if last == "D" else o)))
+    if not results:
+        return (0, -1, -1, -1, -1)
+    best = max(r[0] for r in results)
+    if best <= 0:
+        return (0, -1, -1, -1, -1)
+    opt = [r for r in results if r[0] == best]
+    i1, j1 = min((r[3], r[4]) for r in opt)
+    i0, j0 = max((r[1], r[2]) for r in opt if (r[3], r[4]) == (i1, j1))
+    return (best, i0, i1, j0, j1)

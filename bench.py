@@ -1,0 +1,156 @@
+#!/usr/bin/env python3
+"""Benchmark: batched affine-gap Smith-Waterman (score + start/end) on one GPU.
+
+One step = one sw_align_batch call over the whole workload, inputs already
+resident in device memory: classification and length binning, the forward
+sweep (score and end) and the reverse sweep (start) of every pair, and the
+result scatter.  Prints ONE JSON line.
+
+  python bench.py [--steps K] [--warmup W] [--workload dna_large] [--mode 0|1]
+
+GCUPS = sum over pairs of n*m (forward cells, the usual definition) per
+second of whole-call wall time, / 1e9.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# Algorithmic integer operations per DP cell: H-o (1), E (2), F (2),
+# diag+s (1), max of four terms with 0 (3), running best / argmax (3).
+OPS_PER_CELL = 12
+# MI355X: 256 CUs x 64 lanes x 2.4 GHz of 32-bit VALU issue; packed 16-bit
+# instructions carry two operations per lane.
+VALU_INT32_TOPS = 256 * 64 * 2.4e9 / 1e12
+VALU_INT16X2_TOPS = 2 * VALU_INT32_TOPS
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(batch, target_s=12.0):
+    """Time the CPU oracle (as it stands) on a bounded random sample of the
+    same workload using the host cores available to this process."""
+    import numpy as np
+    from oracle import oracle
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    cores = max(1, min(cores, 16))
+    rng = np.random.default_rng(2208)
+    ql, rl = batch.q_len().astype(np.int64), batch.r_len().astype(np.int64)
+    # calibration sample, then a sample sized for ~target_s seconds
+    n0 = min(batch.n_pairs, 20 * cores)
+    idx = rng.choice(batch.n_pairs, size=n0, replace=False)
+    t = time.perf_counter()
+    oracle.align_batch(batch, index=idx, threads=cores)
+    dt = max(time.perf_counter() - t, 1e-3)
+    rate = float(np.sum(ql[idx] * rl[idx])) / dt
+    mean_cells = float(np.mean(ql * rl))
+    n1 = int(min(batch.n_pairs, max(n0, target_s * rate / mean_cells)))
+    idx = rng.choice(batch.n_pairs, size=n1, replace=False)
+    t = time.perf_counter()
+    oracle.align_batch(batch, index=idx, threads=cores)
+    dt = time.perf_counter() - t
+    cells = float(np.sum(ql[idx] * rl[idx]))
+    return {"value": round(cells / dt / 1e9, 4), "unit": "GCUPS", "cores": cores, "kind": "oracle",
+            "sample": "%d random pairs of the same workload (%.3g forward cells, forward+reverse "
+                      "sweeps, %.1f s on %d threads)" % (n1, cells, dt, cores)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="dna_large")
+    ap.add_argument("--n-pairs", type=int, default=None, help="truncate the workload (testing only)")
+    ap.add_argument("--mode", type=int, default=None, help="0 = per-bin launches, 1 = persistent")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(pairs are independent; see DESIGN.md for how the work would shard)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2208_12350_amd import workloads as W
+    from paper_2208_12350_amd.binding import Aligner, DeviceBatch
+
+    log("generating workload %s ..." % args.workload)
+    t = time.time()
+    batch = W.make_workload(args.workload, n_pairs=args.n_pairs)
+    log("  %d pairs, %.3g forward cells (%.1f s)" % (batch.n_pairs, batch.cells(), time.time() - t))
+    dev = "cuda:0"
+    db = DeviceBatch.from_host(batch, dev)
+    al = Aligner(0, timing=1)
+    if args.mode is not None:
+        al.set_option("mode", args.mode)
+    out = torch.empty((batch.n_pairs, 5), dtype=torch.int32, device=dev)
+
+    for k in range(args.warmup):
+        al.align(db, out)
+        log("  warmup step %d done" % k)
+    torch.cuda.synchronize()
+    step_ms, plan_ms, fwd_ms, rev_ms = [], [], [], []
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        ts = time.perf_counter()
+        al.align(db, out)
+        step_ms.append((time.perf_counter() - ts) * 1e3)
+        p, f, r = al.timing()
+        plan_ms.append(p); fwd_ms.append(f); rev_ms.append(r)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    fwd_cells, rev_cells, i32_pairs = al.stats()
+    log("  timed %d steps in %.3f s" % (args.steps, elapsed))
+
+    ms_per_step = elapsed * 1e3 / args.steps
+    gcups = fwd_cells * args.steps / elapsed / 1e9
+    sweep_ms = float(np.mean(fwd_ms)) + float(np.mean(rev_ms))
+    int16 = i32_pairs < batch.n_pairs
+    peak = VALU_INT16X2_TOPS if int16 else VALU_INT32_TOPS
+    achieved = OPS_PER_CELL * (fwd_cells + rev_cells) / (sweep_ms / 1e3) / 1e12
+    res = {
+        "metric": "GCUPS, batched affine SW (score+coords), batched vs plain; p50/p99 latency",
+        "value": round(gcups, 2),
+        "unit": "GCUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "i16" if int16 else "i32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "pairs": batch.n_pairs, "forward_cells": int(fwd_cells),
+                   "reverse_cells": int(rev_cells), "int32_pairs": int(i32_pairs),
+                   "mode": al.get_option("mode")},
+        "latency_ms": {"p50": round(float(np.percentile(step_ms, 50)), 3),
+                       "p99": round(float(np.percentile(step_ms, 99)), 3)},
+        "phase_ms": {"plan": round(float(np.mean(plan_ms)), 3), "forward": round(float(np.mean(fwd_ms)), 3),
+                     "reverse": round(float(np.mean(rev_ms)), 3)},
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 2),
+                     "unit": "Tops/s", "frac": round(achieved / peak, 4), "traffic": None,
+                     "kernel": "forward+reverse sweeps",
+                     "ops_per_cell": OPS_PER_CELL},
+    }
+    al.close()
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a sample ...")
+        res["cpu_baseline"] = cpu_baseline(batch)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

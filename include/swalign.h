@@ -1,0 +1,142 @@
+/*
+ * swalign.h -- C ABI of the batched affine-gap Smith-Waterman library
+ * (libswalign.so, built for AMD Instinct MI355X / gfx950).
+ *
+ * What is computed (Section II-B-1 and Fig. 2 of arXiv 2208.12350, with the
+ * gap penalty generalised from the worked example's single linear cost to an
+ * affine open/extend pair, i.e. the E state of the ADEPT-V1 listing in
+ * Fig. 9):  for every pair (query a, reference b) the local-alignment score
+ * matrix H of the Gotoh recurrences
+ *
+ *     E[i][j] = max(E[i][j-1] - e, H[i][j-1] - o)
+ *     F[i][j] = max(F[i-1][j] - e, H[i-1][j] - o)
+ *     H[i][j] = max(0, H[i-1][j-1] + M[a_i][b_j], E[i][j], F[i][j])
+ *
+ * with zero first row/column, is swept once forward; its maximum S and the
+ * first cell holding S in row-major order give the end coordinates.  A second
+ * sweep of the same recurrence over the reversed prefixes a[q_end..0],
+ * b[r_end..0] stands in for the traceback of Fig. 2(c): its first cell
+ * holding S gives the start, which is the latest start of any S-scoring
+ * alignment that ends at (q_end, r_end).  A gap of length k costs
+ * o + (k-1)e.  Coordinates are 0-based and inclusive; a pair whose best
+ * score is 0 (including an empty query or reference) reports all -1.
+ *
+ * Threading: a handle may be used by one host thread at a time.
+ * Streams: `stream` is a hipStream_t passed as void*; NULL means the
+ * device's null stream.  All functions return one of the SW_* codes below
+ * (never throw); sw_last_error() gives a human-readable reason.
+ */
+#ifndef SWALIGN_H
+#define SWALIGN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define SW_OK          0
+#define SW_PENDING     1    /* sw_poll: request not finished yet */
+#define SW_EINVAL     -1    /* bad argument or invalid input data */
+#define SW_ENOMEM     -2    /* device or host allocation failed / budget exceeded */
+#define SW_ETOOLONG   -3    /* a sequence exceeds SW_MAX_QUERY / SW_MAX_REF */
+#define SW_EDEVICE    -4    /* a HIP runtime call failed */
+#define SW_EINTERNAL  -5    /* an internal consistency check failed */
+
+/* ---- limits ------------------------------------------------------------ */
+#define SW_MAX_QUERY     2048    /* query (row) length handled in one sweep */
+#define SW_MAX_REF      60000    /* reference (column) length */
+#define SW_MAX_ALPHABET    31    /* residue codes 0..alphabet-1 */
+#define SW_MAX_SCHEMES      4
+
+/* One result per pair, in the caller's pair order. */
+typedef struct {
+    int32_t score;
+    int32_t q_start, q_end;     /* query (row) coordinates, 0-based inclusive */
+    int32_t r_start, r_end;     /* reference (column) coordinates */
+} sw_result;
+
+/* A scoring scheme.  `matrix` is a HOST pointer to alphabet*alphabet int8
+ * scores, row-major, row = query residue, column = reference residue.
+ * Gap costs are positive integers with gap_open >= gap_extend >= 0 and
+ * gap_open >= 1. */
+typedef struct {
+    const int8_t* matrix;
+    int32_t alphabet;
+    int32_t gap_open;
+    int32_t gap_extend;
+} sw_scheme;
+
+/* A batch of pairs.  Every pointer is a DEVICE pointer on the handle's
+ * device, owned by the caller and left unmodified:
+ *   queries   uint8 residue codes of all queries, concatenated
+ *   q_off     int64[n_pairs+1], query i is queries[q_off[i] .. q_off[i+1])
+ *   refs      uint8 residue codes of all references, concatenated
+ *   r_off     int64[n_pairs+1]
+ *   scheme_id uint8[n_pairs] index into the scheme array, or NULL (all 0)
+ * Offsets must be non-decreasing; lengths may be zero. */
+typedef struct {
+    const uint8_t* queries;
+    const int64_t* q_off;
+    const uint8_t* refs;
+    const int64_t* r_off;
+    const uint8_t* scheme_id;
+    int64_t n_pairs;
+} sw_batch;
+
+typedef struct sw_handle sw_handle;
+
+/* Create a handle bound to HIP device `device`.  `tuning` is NULL (built-in
+ * defaults) or a string of `key=value` pairs separated by ';' or ',' (see
+ * sw_set_option for keys).  Returns NULL on failure. */
+sw_handle* sw_create(int device, const char* tuning);
+
+/* Release the handle and every device buffer it owns.  Waits for its work. */
+void sw_destroy(sw_handle* h);
+
+/* Reason for the last non-OK status returned on this handle. */
+const char* sw_last_error(sw_handle* h);
+
+/* Set a tuning or behaviour option (integer valued):
+ *   "mode"      0 = one plain launch per length bin, 1 = persistent launch
+ *               over a device work queue (default 1)
+ *   "graph"     1 = replay a captured hipGraph for repeated batch shapes
+ *   "validate"  1 = check residue codes (default 1); invalid residues make
+ *               the call return SW_EINVAL (results of those pairs undefined)
+ *   "precision" 0 = automatic int16/int32 routing (default), 32 = force int32
+ *   "timing"    1 = record HIP events around the phases of each call on the
+ *               caller's stream (read back with sw_last_timing)
+ * Returns SW_OK or SW_EINVAL for an unknown key / bad value. */
+int sw_set_option(sw_handle* h, const char* key, int64_t value);
+int sw_get_option(sw_handle* h, const char* key, int64_t* value);
+
+/* Align every pair of `batch` and write out[i] (a DEVICE pointer to
+ * n_pairs sw_result records) for pair i.  Work is enqueued on `stream`; the
+ * call returns after it has completed (it synchronises `stream`).
+ * `schemes` is a HOST array of n_schemes (1..SW_MAX_SCHEMES) schemes.
+ * Errors: SW_EINVAL (null pointer with n_pairs > 0, bad scheme, decreasing
+ * offsets, scheme id out of range, residue >= alphabet), SW_ETOOLONG (a
+ * query longer than SW_MAX_QUERY or reference longer than SW_MAX_REF),
+ * SW_ENOMEM, SW_EDEVICE.  On error the contents of `out` are undefined. */
+int sw_align_batch(sw_handle* h, const sw_batch* batch, const sw_scheme* schemes,
+                   int n_schemes, sw_result* out, void* stream);
+
+/* Statistics of the last sw_align_batch call on this handle: number of
+ * forward cells (sum of n*m), reverse cells (sum of (q_end+1)*(r_end+1) over
+ * pairs with a positive score) and the number of pairs routed to the int32
+ * path.  Any pointer may be NULL. */
+int sw_last_stats(sw_handle* h, int64_t* fwd_cells, int64_t* rev_cells, int64_t* int32_pairs);
+
+/* Device time in milliseconds of the phases of the last sw_align_batch call,
+ * measured with HIP events on the caller's stream; all zero unless the
+ * "timing" option is set.  plan = classification + sort + histogram copy,
+ * forward / reverse = the forward and reverse sweeps (every launch of each).
+ * Any pointer may be NULL. */
+int sw_last_timing(sw_handle* h, float* plan_ms, float* forward_ms, float* reverse_ms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SWALIGN_H */

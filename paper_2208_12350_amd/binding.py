@@ -1,0 +1,243 @@
+"""Thin ctypes binding of libswalign.so (include/swalign.h).
+
+Argument marshalling only: every step of the alignment runs in the HIP
+library.  PyTorch provides device memory and streams.  The functions keep the
+C names (sw_create, sw_align_batch, ...); ``Aligner`` wraps them for torch
+tensors.  There is no CPU fallback: if the library is missing or no GPU is
+present the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libswalign.so")
+
+SW_OK = 0
+SW_PENDING = 1
+SW_EINVAL = -1
+SW_ENOMEM = -2
+SW_ETOOLONG = -3
+SW_EDEVICE = -4
+SW_EINTERNAL = -5
+SW_MAX_QUERY = 2048
+SW_MAX_REF = 60000
+SW_MAX_ALPHABET = 31
+SW_MAX_SCHEMES = 4
+
+_ERRNAMES = {SW_EINVAL: "SW_EINVAL", SW_ENOMEM: "SW_ENOMEM", SW_ETOOLONG: "SW_ETOOLONG",
+             SW_EDEVICE: "SW_EDEVICE", SW_EINTERNAL: "SW_EINTERNAL"}
+
+EXPORTED = ("sw_create", "sw_destroy", "sw_last_error", "sw_set_option", "sw_get_option",
+            "sw_align_batch", "sw_last_stats", "sw_last_timing")
+
+
+class sw_result(ctypes.Structure):
+    _fields_ = [("score", ctypes.c_int32), ("q_start", ctypes.c_int32), ("q_end", ctypes.c_int32),
+                ("r_start", ctypes.c_int32), ("r_end", ctypes.c_int32)]
+
+
+class sw_scheme(ctypes.Structure):
+    _fields_ = [("matrix", ctypes.c_void_p), ("alphabet", ctypes.c_int32),
+                ("gap_open", ctypes.c_int32), ("gap_extend", ctypes.c_int32)]
+
+
+class sw_batch(ctypes.Structure):
+    _fields_ = [("queries", ctypes.c_void_p), ("q_off", ctypes.c_void_p), ("refs", ctypes.c_void_p),
+                ("r_off", ctypes.c_void_p), ("scheme_id", ctypes.c_void_p), ("n_pairs", ctypes.c_int64)]
+
+
+class SwError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("%s: %s" % (_ERRNAMES.get(code, str(code)), msg))
+        self.code = code
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libswalign.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("libswalign.so is not built (run __graft_entry__.build() or "
+                           "python paper_2208_12350_amd/build.py)")
+    lib = ctypes.CDLL(path)
+    lib.sw_create.restype = ctypes.c_void_p
+    lib.sw_create.argtypes = [ctypes.c_int, ctypes.c_char_p]
+    lib.sw_destroy.restype = None
+    lib.sw_destroy.argtypes = [ctypes.c_void_p]
+    lib.sw_last_error.restype = ctypes.c_char_p
+    lib.sw_last_error.argtypes = [ctypes.c_void_p]
+    lib.sw_set_option.restype = ctypes.c_int
+    lib.sw_set_option.argtypes = [ctypes.c_void_p, ctypes.c_char_p, ctypes.c_int64]
+    lib.sw_get_option.restype = ctypes.c_int
+    lib.sw_get_option.argtypes = [ctypes.c_void_p, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64)]
+    lib.sw_align_batch.restype = ctypes.c_int
+    lib.sw_align_batch.argtypes = [ctypes.c_void_p, ctypes.POINTER(sw_batch), ctypes.POINTER(sw_scheme),
+                                   ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
+    lib.sw_last_stats.restype = ctypes.c_int
+    lib.sw_last_stats.argtypes = [ctypes.c_void_p] + [ctypes.POINTER(ctypes.c_int64)] * 3
+    lib.sw_last_timing.restype = ctypes.c_int
+    lib.sw_last_timing.argtypes = [ctypes.c_void_p] + [ctypes.POINTER(ctypes.c_float)] * 3
+    _lib = lib
+    return lib
+
+
+# ---- C-named wrappers --------------------------------------------------------
+
+def sw_create(device: int = 0, tuning: Optional[str] = None) -> int:
+    h = load_library().sw_create(device, tuning.encode() if tuning else None)
+    if not h:
+        raise RuntimeError("sw_create(%d) failed (no such HIP device or bad tuning string)" % device)
+    return h
+
+
+def sw_destroy(h: int) -> None:
+    load_library().sw_destroy(h)
+
+
+def sw_last_error(h: int) -> str:
+    return load_library().sw_last_error(h).decode(errors="replace")
+
+
+def _check(h, rc):
+    if rc != SW_OK:
+        raise SwError(rc, sw_last_error(h))
+    return rc
+
+
+def sw_set_option(h: int, key: str, value: int) -> None:
+    _check(h, load_library().sw_set_option(h, key.encode(), int(value)))
+
+
+def sw_get_option(h: int, key: str) -> int:
+    v = ctypes.c_int64(0)
+    _check(h, load_library().sw_get_option(h, key.encode(), ctypes.byref(v)))
+    return int(v.value)
+
+
+def sw_align_batch(h: int, batch: sw_batch, schemes, n_schemes: int, out_ptr: int, stream_ptr) -> int:
+    """Raw call; returns the status code (does not raise)."""
+    return load_library().sw_align_batch(h, ctypes.byref(batch), schemes, n_schemes, out_ptr, stream_ptr)
+
+
+def sw_last_stats(h: int):
+    f, r, i = ctypes.c_int64(0), ctypes.c_int64(0), ctypes.c_int64(0)
+    _check(h, load_library().sw_last_stats(h, ctypes.byref(f), ctypes.byref(r), ctypes.byref(i)))
+    return int(f.value), int(r.value), int(i.value)
+
+
+def sw_last_timing(h: int):
+    a, b, c = ctypes.c_float(0), ctypes.c_float(0), ctypes.c_float(0)
+    _check(h, load_library().sw_last_timing(h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+    return float(a.value), float(b.value), float(c.value)
+
+
+# ---- torch-facing helpers ----------------------------------------------------
+
+RESULT_FIELDS = ("score", "q_start", "q_end", "r_start", "r_end")
+
+
+class DeviceBatch:
+    """A batch resident in device memory as torch tensors."""
+
+    def __init__(self, queries, q_off, refs, r_off, scheme_id, schemes):
+        self.queries = queries
+        self.q_off = q_off
+        self.refs = refs
+        self.r_off = r_off
+        self.scheme_id = scheme_id
+        self.schemes = list(schemes)
+
+    @property
+    def n_pairs(self) -> int:
+        return int(self.q_off.numel() - 1)
+
+    @staticmethod
+    def from_host(batch, device="cuda:0") -> "DeviceBatch":
+        import torch
+        t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a)).to(device=device, dtype=dt)
+        q = batch.queries if batch.queries.size else np.zeros(1, np.uint8)
+        r = batch.refs if batch.refs.size else np.zeros(1, np.uint8)
+        return DeviceBatch(t(q, torch.uint8), t(batch.q_off, torch.int64), t(r, torch.uint8),
+                           t(batch.r_off, torch.int64), t(batch.scheme_id, torch.uint8), batch.schemes)
+
+    def c_struct(self) -> sw_batch:
+        b = sw_batch()
+        b.queries = self.queries.data_ptr()
+        b.q_off = self.q_off.data_ptr()
+        b.refs = self.refs.data_ptr()
+        b.r_off = self.r_off.data_ptr()
+        b.scheme_id = self.scheme_id.data_ptr() if self.scheme_id is not None else None
+        b.n_pairs = self.n_pairs
+        return b
+
+
+def make_schemes(schemes: Sequence) -> "tuple":
+    """Host-side sw_scheme array (keeps the matrices alive in the tuple)."""
+    arr = (sw_scheme * max(1, len(schemes)))()
+    keep = []
+    for k, s in enumerate(schemes):
+        m = np.ascontiguousarray(s.matrix, dtype=np.int8)
+        keep.append(m)
+        arr[k].matrix = m.ctypes.data
+        arr[k].alphabet = int(m.shape[0])
+        arr[k].gap_open = int(s.gap_open)
+        arr[k].gap_extend = int(s.gap_extend)
+    return arr, keep
+
+
+class Aligner:
+    """Owns one sw_handle on one device."""
+
+    def __init__(self, device: int = 0, tuning: Optional[str] = None, **options):
+        self.device = device
+        self.h = sw_create(device, tuning)
+        for k, v in options.items():
+            sw_set_option(self.h, k, v)
+
+    def close(self):
+        if self.h:
+            sw_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_option(self, key, value):
+        sw_set_option(self.h, key, value)
+
+    def get_option(self, key):
+        return sw_get_option(self.h, key)
+
+    def align(self, dbatch: DeviceBatch, out=None, stream=None):
+        """Align a DeviceBatch; returns an int32 tensor [n_pairs, 5] on the
+        device (score, q_start, q_end, r_start, r_end)."""
+        import torch
+        dev = dbatch.q_off.device
+        if out is None:
+            out = torch.empty((dbatch.n_pairs, 5), dtype=torch.int32, device=dev)
+        assert out.is_contiguous() and out.dtype == torch.int32 and out.shape == (dbatch.n_pairs, 5)
+        arr, keep = make_schemes(dbatch.schemes)
+        s = stream if stream is not None else torch.cuda.current_stream(dev)
+        rc = sw_align_batch(self.h, dbatch.c_struct(), arr, len(dbatch.schemes),
+                            out.data_ptr() if dbatch.n_pairs else None, ctypes.c_void_p(s.cuda_stream))
+        _check(self.h, rc)
+        del keep
+        return out
+
+    def stats(self):
+        return sw_last_stats(self.h)
+
+    def timing(self):
+        return sw_last_timing(self.h)

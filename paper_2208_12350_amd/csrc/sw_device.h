@@ -1,0 +1,130 @@
+// sw_device.h -- device-side helpers shared by the gfx950 sweep kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sw_internal.h"
+
+namespace sw {
+
+template <int W>
+__device__ __forceinline__ int shift_in_group(int x) {
+    // Lane l receives lane l-1's value; the first lane of each W-lane group
+    // receives 0.  row_shr:1 shifts within 16-lane rows, wave_shr:1 across
+    // the whole wavefront; bound_ctrl zero-fills the lane with no source.
+    if constexpr (W == 16) {
+        return __builtin_amdgcn_update_dpp(0, x, 0x111, 0xF, 0xF, true);
+    } else {
+        static_assert(W == 64, "W must be 16 or 64");
+        return __builtin_amdgcn_update_dpp(0, x, 0x138, 0xF, 0xF, true);
+    }
+}
+
+__device__ __forceinline__ int sat_sub(int x, int y) {
+    // max(x - y, 0) for x >= 0, y >= 0
+    return (int)__builtin_elementwise_sub_sat((unsigned)x, (unsigned)y);
+}
+
+__device__ __forceinline__ int imax(int a, int b) { return a > b ? a : b; }
+
+struct PairJob {
+    int64_t qbase, rbase;
+    int n, m, dir, sid;
+    int fwd_score, fwd_qe, fwd_re;
+};
+
+__device__ __forceinline__ PairJob load_job(const KParams& P, int pair, int reverse) {
+    PairJob J;
+    J.dir = 1; J.n = 0; J.m = 0; J.qbase = 0; J.rbase = 0; J.sid = 0;
+    J.fwd_score = 0; J.fwd_qe = -1; J.fwd_re = -1;
+    if (pair < 0) return J;
+    J.sid = P.scheme_id ? (int)P.scheme_id[pair] : 0;
+    const int64_t q0 = P.q_off[pair], q1 = P.q_off[pair + 1];
+    const int64_t r0 = P.r_off[pair], r1 = P.r_off[pair + 1];
+    if (!reverse) {
+        J.qbase = q0; J.rbase = r0;
+        J.n = (int)(q1 - q0); J.m = (int)(r1 - r0);
+    } else {
+        const sw_result f = P.out[pair];
+        J.fwd_score = f.score; J.fwd_qe = f.q_end; J.fwd_re = f.r_end;
+        if (f.score > 0) {
+            J.n = f.q_end + 1; J.m = f.r_end + 1;
+            J.qbase = q0 + f.q_end; J.rbase = r0 + f.r_end;
+            J.dir = -1;
+        }
+    }
+    return J;
+}
+
+// Wave-scope ordering of LDS traffic: every lane's earlier LDS accesses are
+// complete and visible before any lane's later ones (the wavefront executes
+// in lock-step, so no workgroup barrier is needed).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Reference columns are streamed through LDS in chunks of kChunk sweep
+// steps.  While a chunk is swept, lanes read columns t0-W+1 .. t0+kChunk+1
+// (the loop reads two steps ahead), so a group's buffer holds at least
+// kChunk+W+2 entries: entry x is column t0-W+x.
+constexpr int kChunk = 128;
+
+template <int W>
+struct RefStager {
+    static constexpr int kPerLane = (kChunk + W + 2 + W - 1) / W;
+    static constexpr int kBuf = kPerLane * W;
+    int raw[kPerLane];
+
+    // Issue the loads of the chunk starting at sweep step t0.  Addresses are
+    // clamped into the pair's reference so that the loads are unconditional
+    // and stay in flight while the previous chunk is swept.
+    __device__ __forceinline__ void load(const uint8_t* refs, const PairJob& J, const void* dummy,
+                                         int t0, int l) {
+#pragma unroll
+        for (int k = 0; k < kPerLane; ++k) {
+            int j = t0 - W + l + k * W;
+            j = j < 0 ? 0 : (j >= J.m ? J.m - 1 : j);
+            const uint8_t* p = J.m > 0 ? refs + J.rbase + (int64_t)J.dir * j
+                                       : reinterpret_cast<const uint8_t*>(dummy);
+            raw[k] = *p;
+        }
+    }
+    // Write the chunk into the group's LDS buffer as matrix row offsets,
+    // replacing out-of-range columns and invalid residues by the padding code.
+    __device__ __forceinline__ void store(uint16_t* buf, const PairJob& J, int A, int t0, int l,
+                                          bool& bad) const {
+        const int sbase = J.sid * kMatBytes;
+#pragma unroll
+        for (int k = 0; k < kPerLane; ++k) {
+            const int j = t0 - W + l + k * W;
+            int b = raw[k];
+            const bool inside = j >= 0 && j < J.m;
+            bad |= inside && b >= A;
+            b = (inside && b < A) ? b : kPad;
+            buf[l + k * W] = (uint16_t)(sbase + b * kMatDim);
+        }
+    }
+};
+
+// Per-block copy of the scoring schemes: substitution tables and gap costs.
+struct SchemeLds {
+    int8_t mat[SW_MAX_SCHEMES * kMatBytes];
+    int32_t alphabet[SW_MAX_SCHEMES];
+    int32_t gap_open[SW_MAX_SCHEMES];
+    int32_t gap_extend[SW_MAX_SCHEMES];
+};
+
+__device__ __forceinline__ void load_schemes(SchemeLds& S, const KParams& P, int tid) {
+    for (int k = tid; k < SW_MAX_SCHEMES * kMatBytes / 4; k += kBlock)
+        reinterpret_cast<int32_t*>(S.mat)[k] = reinterpret_cast<const int32_t*>(P.mats)[k];
+    if (tid < SW_MAX_SCHEMES) {
+        S.alphabet[tid] = P.alphabet[tid];
+        S.gap_open[tid] = P.gap_open[tid];
+        S.gap_extend[tid] = P.gap_extend[tid];
+    }
+}
+
+}  // namespace sw

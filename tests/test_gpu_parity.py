@@ -1,0 +1,160 @@
+"""GPU parity: the HIP path against the CPU oracle, bit-exact on every field.
+
+Small cases are compared on every pair; the full-size workloads (the same
+launch configuration the benchmark times) are compared on a seeded sample of
+pairs, which the oracle recomputes one by one, and on properties that hold
+for every pair."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2208_12350_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("score", "q_start", "q_end", "r_start", "r_end")
+
+
+@pytest.fixture(scope="module")
+def aligner():
+    import torch
+    from paper_2208_12350_amd.binding import Aligner
+    assert torch.cuda.is_available()
+    a = Aligner(0)
+    yield a
+    a.close()
+
+
+def run_gpu(aligner, batch):
+    from paper_2208_12350_amd.binding import DeviceBatch
+    db = DeviceBatch.from_host(batch)
+    out = aligner.align(db)
+    return out.cpu().numpy()
+
+
+def as_tuples(o):
+    return np.stack([o[f] for f in FIELDS], axis=1).astype(np.int64)
+
+
+def assert_same(gpu, ora, batch, idx=None):
+    ora_t = as_tuples(ora)
+    g = gpu if idx is None else gpu[idx]
+    bad = np.flatnonzero(np.any(g != ora_t, axis=1))
+    if bad.size:
+        k = int(bad[0])
+        i = k if idx is None else int(idx[k])
+        q, r, s = batch.pair(i)
+        raise AssertionError("pair %d (n=%d m=%d scheme=%s): gpu %s oracle %s; %d mismatches"
+                             % (i, q.size, r.size, s.name, g[k].tolist(), ora_t[k].tolist(), bad.size))
+
+
+def test_hand_cases(aligner):
+    dna = W.dna_scheme()
+    pairs = [("AAAATTTT", "CAAAAGGTTTTC"), ("AC", "ACGAC"), ("AGAC", "ATAC"), ("AAAA", "CCCC"),
+             ("A", "A"), ("ACGT", "ACGT"), ("GGGACGTGGG", "TTACGTTT")]
+    b = W.from_pairs([(W.encode(x, "ACGT"), W.encode(y, "ACGT")) for x, y in pairs], [0] * len(pairs), [dna])
+    assert_same(run_gpu(aligner, b), O.align_batch(b), b)
+
+
+def test_tiny_random_all_gap_settings(aligner):
+    rng = np.random.default_rng(42)
+    for o, e in [(6, 1), (11, 1), (1, 1), (3, 0), (5, 2)]:
+        M = rng.integers(-4, 4, size=(6, 6))
+        np.fill_diagonal(M, rng.integers(1, 6, size=6))
+        sc = W.Scheme(np.ascontiguousarray(M.astype(np.int8)), o, e)
+        pairs = [(rng.integers(0, 6, size=int(rng.integers(0, 9))), rng.integers(0, 6, size=int(rng.integers(0, 12))))
+                 for _ in range(3000)]
+        b = W.from_pairs(pairs, [0] * len(pairs), [sc])
+        assert_same(run_gpu(aligner, b), O.align_batch(b), b)
+
+
+def test_dna_small_every_pair(aligner):
+    b = W.make_workload("dna_small")
+    assert_same(run_gpu(aligner, b), O.align_batch(b), b)
+
+
+EDGE_Q = [1, 2, 15, 16, 17, 31, 32, 33, 100, 255, 256, 257, 383, 384, 385, 511, 512, 513, 1023, 1024, 1025, 2047, 2048]
+EDGE_R = [1, 2, 15, 16, 17, 63, 64, 65, 127, 128, 129, 130, 131, 255, 256, 257, 1000, 6144]
+
+
+def test_edge_lengths(aligner):
+    rng = np.random.default_rng(7)
+    dna = W.dna_scheme()
+    pairs = []
+    for n in EDGE_Q:
+        for m in EDGE_R:
+            if n * m > 2_000_000:
+                continue
+            q = rng.integers(0, 4, size=n)
+            if m >= n and rng.random() < 0.5:
+                off = int(rng.integers(0, m - n + 1))
+                r = rng.integers(0, 4, size=m)
+                r[off:off + n] = q
+            else:
+                r = rng.integers(0, 4, size=m)
+            pairs.append((q, r))
+    b = W.from_pairs(pairs, [0] * len(pairs), [dna])
+    assert_same(run_gpu(aligner, b), O.align_batch(b), b)
+
+
+def test_all_mismatch_and_empty(aligner):
+    dna = W.dna_scheme()
+    pairs = [(np.zeros(50, np.uint8), np.ones(70, np.uint8)), (np.zeros(0, np.uint8), np.ones(7, np.uint8)),
+             (np.ones(9, np.uint8), np.zeros(0, np.uint8)), (np.zeros(0, np.uint8), np.zeros(0, np.uint8)),
+             (np.full(300, 2, np.uint8), np.full(500, 2, np.uint8))]
+    b = W.from_pairs(pairs, [0] * len(pairs), [dna])
+    assert_same(run_gpu(aligner, b), O.align_batch(b), b)
+
+
+def test_protein_sample(aligner):
+    b = W.make_workload("protein", n_pairs=1500)
+    assert_same(run_gpu(aligner, b), O.align_batch(b), b)
+
+
+def test_mixed_sample_two_schemes(aligner):
+    b = W.make_workload("mixed", n_pairs=3000)
+    assert_same(run_gpu(aligner, b), O.align_batch(b), b)
+
+
+def test_repeatable_and_order_invariant(aligner):
+    b = W.make_workload("dna_small", n_pairs=700, seed=99)
+    g1 = run_gpu(aligner, b)
+    g2 = run_gpu(aligner, b)
+    assert np.array_equal(g1, g2)
+    perm = np.random.default_rng(3).permutation(b.n_pairs)
+    gp = run_gpu(aligner, b.subset(perm))
+    assert np.array_equal(gp, g1[perm])
+
+
+def test_invalid_inputs_are_rejected(aligner):
+    from paper_2208_12350_amd.binding import SwError, SW_EINVAL, SW_ETOOLONG
+    dna = W.dna_scheme()
+    bad = W.from_pairs([(np.array([0, 1, 7], np.uint8), np.array([0, 1, 2], np.uint8))], [0], [dna])
+    with pytest.raises(SwError) as ei:
+        run_gpu(aligner, bad)
+    assert ei.value.code == SW_EINVAL
+    long_q = W.from_pairs([(np.zeros(2049, np.uint8), np.zeros(10, np.uint8))], [0], [dna])
+    with pytest.raises(SwError) as ei:
+        run_gpu(aligner, long_q)
+    assert ei.value.code == SW_ETOOLONG
+    bad_sid = W.from_pairs([(np.zeros(5, np.uint8), np.zeros(5, np.uint8))], [1], [dna])
+    with pytest.raises(SwError) as ei:
+        run_gpu(aligner, bad_sid)
+    assert ei.value.code == SW_EINVAL
+    # the handle still works after errors
+    ok = W.make_workload("dna_small", n_pairs=20)
+    assert_same(run_gpu(aligner, ok), O.align_batch(ok), ok)
+
+
+@pytest.mark.parametrize("name", ["dna_large", "protein"])
+def test_full_size_sampled(aligner, name):
+    b = W.make_workload(name)
+    g = run_gpu(aligner, b)
+    idx = np.sort(np.random.default_rng(11).choice(b.n_pairs, size=1500, replace=False))
+    assert_same(g, O.align_batch(b, index=idx), b, idx=idx)
+    # properties of every pair
+    ql, rl = b.q_len(), b.r_len()
+    s = g[:, 0]
+    assert np.all(s > 0)  # every pair embeds a mutated copy of its query
+    assert np.all((g[:, 1] >= 0) & (g[:, 1] <= g[:, 2]) & (g[:, 2] < ql))
+    assert np.all((g[:, 3] >= 0) & (g[:, 3] <= g[:, 4]) & (g[:, 4] < rl))

@@ -1,0 +1,42 @@
+"""CPU-only checks of the C ABI library: it loads, exports every function the
+header declares, and rejects bad arguments before touching a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "swalign.h")
+LIB = os.path.join(ROOT, "paper_2208_12350_amd", "libswalign.so")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sw_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for n in ("sw_create", "sw_destroy", "sw_last_error", "sw_align_batch", "sw_set_option"):
+        assert n in names
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libswalign.so not built")
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(LIB)
+    for n in _declared():
+        assert hasattr(lib, n), n
+    from paper_2208_12350_amd import binding
+    assert set(binding.EXPORTED) == set(_declared())
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libswalign.so not built")
+def test_null_handle_is_rejected():
+    from paper_2208_12350_amd import binding as B
+    lib = B.load_library()
+    assert lib.sw_align_batch(None, None, None, 1, None, None) == B.SW_EINVAL
+    assert lib.sw_set_option(None, b"mode", 0) == B.SW_EINVAL
+    assert lib.sw_last_error(None) == b"null handle"
+    lib.sw_destroy(None)

@@ -104,7 +104,10 @@ const char* sw_last_error(sw_handle* h);
  *   "graph"     1 = replay a captured hipGraph for repeated batch shapes
  *   "validate"  1 = check residue codes (default 1); invalid residues make
  *               the call return SW_EINVAL (results of those pairs undefined)
- *   "precision" 0 = automatic int16/int32 routing (default), 32 = force int32
+ *   "precision" 0 = automatic routing (default): a pair runs on the packed
+ *               int16 path when min(n, m) * (largest matrix score) <= 32640,
+ *               which bounds every intermediate value; otherwise on int32.
+ *               32 = force every pair onto the int32 path
  *   "timing"    1 = record HIP events around the phases of each call on the
  *               caller's stream (read back with sw_last_timing)
  * Returns SW_OK or SW_EINVAL for an unknown key / bad value. */

@@ -56,12 +56,29 @@ enum : int32_t {
 #include <hip/hip_runtime_api.h>
 
 namespace sw {
-int num_shapes();
-BinShape shape_at(int k);
-hipError_t launch_pass(int shape, const KParams& P, int first, int count, int reverse,
+using PassFn = void (*)(KParams, int, int, int);
+// A compiled sweep kernel: precision (32 or 16), lanes per group W, rows per lane R.
+struct ShapeEntry { int prec, W, R; PassFn fn; };
+const ShapeEntry* shapes_i32(int* n);
+const ShapeEntry* shapes_i16(int* n);
+// Pairs one workgroup of the given shape aligns.
+inline int pairs_per_block(const ShapeEntry& e) {
+    return kWavesPerBlock * (64 / e.W) * (e.prec == 16 ? 2 : 1);
+}
+hipError_t launch_pass(const ShapeEntry& e, const KParams& P, int first, int count, int reverse,
                        hipStream_t stream);
+// Classification inputs: bin_of_rows[sel * kLutRows + (n-1)/16] gives the bin
+// of a pair with query length n, where sel = 0 for the packed int16 path and
+// 1 for int32; a pair takes int16 when min(n, m) * max_score[s] <= i16_limit.
+constexpr int kLutRows = SW_MAX_QUERY / 16;
+struct ClassifyArgs {
+    int32_t max_score[SW_MAX_SCHEMES];
+    int32_t i16_limit;      // 0 disables the int16 path
+    int32_t n_schemes;
+    int32_t n_bins;
+};
 hipError_t launch_classify(const int64_t* q_off, const int64_t* r_off, const uint8_t* scheme_id,
-                           int64_t n_pairs, int n_schemes, const int8_t* bin_of_rows, int n_bins,
+                           int64_t n_pairs, const ClassifyArgs& C, const int8_t* bin_of_rows,
                            uint32_t* keys, int32_t* vals, sw_result* out, int32_t* flags,
                            int32_t* hist, int32_t* maxm, unsigned long long* fwd_cells,
                            hipStream_t stream);

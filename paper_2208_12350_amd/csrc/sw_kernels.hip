@@ -197,13 +197,14 @@ __global__ __launch_bounds__(kBlock) void sw_pass_i32(KParams P, int first, int 
 // (bin << 16 | (65535 - m)) so that a radix sort groups pairs by bin with
 // the longest references first.
 __global__ void sw_classify(const int64_t* q_off, const int64_t* r_off, const uint8_t* scheme_id,
-                            int64_t n_pairs, int n_schemes, const int8_t* bin_of_rows,
-                            int n_bins, uint32_t* keys, int32_t* vals, sw_result* out,
+                            int64_t n_pairs, ClassifyArgs C, const int8_t* bin_of_rows,
+                            uint32_t* keys, int32_t* vals, sw_result* out,
                             int32_t* flags, int32_t* hist, int32_t* maxm,
                             unsigned long long* fwd_cells) {
     __shared__ int32_t s_hist[64];
     __shared__ int32_t s_maxm[64];
     __shared__ unsigned long long s_cells;
+    const int n_bins = C.n_bins;
     for (int k = threadIdx.x; k < 64; k += blockDim.x) { s_hist[k] = 0; s_maxm[k] = 0; }
     if (threadIdx.x == 0) s_cells = 0;
     __syncthreads();
@@ -214,9 +215,13 @@ __global__ void sw_classify(const int64_t* q_off, const int64_t* r_off, const ui
         const int s = scheme_id ? (int)scheme_id[i] : 0;
         int bin = n_bins;  // trivial
         if (n < 0 || m < 0) atomicOr(&flags[kFlagBadOffsets], 1);
-        else if (s >= n_schemes) atomicOr(&flags[kFlagBadScheme], 1);
+        else if (s >= C.n_schemes) atomicOr(&flags[kFlagBadScheme], 1);
         else if (n > SW_MAX_QUERY || m > SW_MAX_REF) atomicOr(&flags[kFlagTooLong], 1);
-        else if (n > 0 && m > 0) bin = bin_of_rows[(n - 1) / 16];
+        else if (n > 0 && m > 0) {
+            const int64_t mn = n < m ? n : m;
+            const int sel = mn * C.max_score[s] <= C.i16_limit ? 0 : 1;
+            bin = bin_of_rows[sel * kLutRows + (n - 1) / 16];
+        }
         if (bin >= n_bins) {
             sw_result z;
             z.score = 0; z.q_start = z.q_end = z.r_start = z.r_end = -1;
@@ -240,18 +245,14 @@ __global__ void sw_classify(const int64_t* q_off, const int64_t* r_off, const ui
 }  // namespace sw
 
 // ---------------------------------------------------------------------------
-// Launch table of the compiled bin shapes.
+// Launch table of the compiled int32 bin shapes.
 // ---------------------------------------------------------------------------
 namespace sw {
-
-using PassFn = void (*)(KParams, int, int, int);
 
 template <int W, int R>
 static constexpr PassFn pass_i32() { return &sw_pass_i32<W, R>; }
 
-struct ShapeEntry { int prec, W, R; PassFn fn; };
-
-static const ShapeEntry kShapes[] = {
+static const ShapeEntry kShapesI32[] = {
     {32, 16, 2, pass_i32<16, 2>()},   {32, 16, 4, pass_i32<16, 4>()},
     {32, 16, 6, pass_i32<16, 6>()},   {32, 16, 8, pass_i32<16, 8>()},
     {32, 16, 10, pass_i32<16, 10>()}, {32, 16, 12, pass_i32<16, 12>()},
@@ -263,26 +264,22 @@ static const ShapeEntry kShapes[] = {
     {32, 64, 28, pass_i32<64, 28>()}, {32, 64, 32, pass_i32<64, 32>()},
 };
 
-int num_shapes() { return (int)(sizeof(kShapes) / sizeof(kShapes[0])); }
-
-BinShape shape_at(int k) {
-    BinShape s;
-    s.prec = (int16_t)kShapes[k].prec; s.W = (int16_t)kShapes[k].W; s.R = (int16_t)kShapes[k].R;
-    return s;
+const ShapeEntry* shapes_i32(int* n) {
+    *n = (int)(sizeof(kShapesI32) / sizeof(kShapesI32[0]));
+    return kShapesI32;
 }
 
-hipError_t launch_pass(int shape, const KParams& P, int first, int count, int reverse,
+hipError_t launch_pass(const ShapeEntry& e, const KParams& P, int first, int count, int reverse,
                        hipStream_t stream) {
-    const ShapeEntry& e = kShapes[shape];
-    const int pairs_per_block = kWavesPerBlock * (64 / e.W);
-    const int blocks = (count + pairs_per_block - 1) / pairs_per_block;
+    const int ppb = pairs_per_block(e);
+    const int blocks = (count + ppb - 1) / ppb;
     if (blocks == 0) return hipSuccess;
     hipLaunchKernelGGL(e.fn, dim3(blocks), dim3(kBlock), 0, stream, P, first, count, reverse);
     return hipGetLastError();
 }
 
 hipError_t launch_classify(const int64_t* q_off, const int64_t* r_off, const uint8_t* scheme_id,
-                           int64_t n_pairs, int n_schemes, const int8_t* bin_of_rows, int n_bins,
+                           int64_t n_pairs, const ClassifyArgs& C, const int8_t* bin_of_rows,
                            uint32_t* keys, int32_t* vals, sw_result* out, int32_t* flags,
                            int32_t* hist, int32_t* maxm, unsigned long long* fwd_cells,
                            hipStream_t stream) {
@@ -290,8 +287,8 @@ hipError_t launch_classify(const int64_t* q_off, const int64_t* r_off, const uin
     const int64_t blocks = (n_pairs + threads - 1) / threads;
     if (blocks == 0) return hipSuccess;
     hipLaunchKernelGGL(sw_classify, dim3((unsigned)blocks), dim3(threads), 0, stream, q_off, r_off,
-                       scheme_id, n_pairs, n_schemes, bin_of_rows, n_bins, keys, vals, out, flags,
-                       hist, maxm, fwd_cells);
+                       scheme_id, n_pairs, C, bin_of_rows, keys, vals, out, flags, hist, maxm,
+                       fwd_cells);
     return hipGetLastError();
 }
 

@@ -28,7 +28,7 @@ using namespace sw;
 
 namespace {
 
-constexpr int kLutEntries = SW_MAX_QUERY / 16;   // bin by 16-row buckets of query length
+constexpr int kLutEntries = 2 * kLutRows;       // [int16 | int32] x 16-row buckets of query length
 constexpr int kSmallInts = 256;                   // pinned host staging for hist/maxm/flags
 
 struct DeviceBuf {
@@ -49,8 +49,8 @@ struct sw_handle {
     hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     float t_plan = 0.f, t_fwd = 0.f, t_rev = 0.f;
 
-    std::vector<int> bin_shape;          // shape index of each bin
-    std::vector<int8_t> lut;             // (query length - 1) / 16 -> bin
+    std::vector<ShapeEntry> bins;        // the kernel shape of each bin
+    std::vector<int8_t> lut;             // precision x (query length - 1) / 16 -> bin
 
     int8_t* d_mats = nullptr;
     int8_t* d_lut = nullptr;
@@ -93,22 +93,30 @@ static int fail(sw_handle* h, int code, const char* fmt, ...) {
     } while (0)
 
 static void build_bins(sw_handle* h) {
-    // Default binning: queries up to 256 rows run on 16-lane groups, longer
-    // ones on 64-lane groups; the rows per lane R is the smallest compiled
-    // value covering the 16-row bucket's upper end.
-    h->bin_shape.clear();
-    for (int k = 0; k < num_shapes(); ++k) h->bin_shape.push_back(k);
+    // Bins 0.. are the packed int16 shapes, then the int32 shapes.  Default
+    // binning: queries up to 256 rows run on 16-lane groups, longer ones on
+    // 64-lane groups; the rows per lane R is the smallest compiled value
+    // covering the upper end of the query's 16-row bucket.
+    h->bins.clear();
+    int n16 = 0, n32 = 0;
+    const ShapeEntry* s16 = shapes_i16(&n16);
+    const ShapeEntry* s32 = shapes_i32(&n32);
+    for (int k = 0; k < n16; ++k) h->bins.push_back(s16[k]);
+    for (int k = 0; k < n32; ++k) h->bins.push_back(s32[k]);
     h->lut.assign(kLutEntries, -1);
-    for (int k = 0; k < kLutEntries; ++k) {
-        const int rows = 16 * (k + 1);
-        const int W = rows <= 256 ? 16 : 64;
-        int best = -1;
-        for (int b = 0; b < (int)h->bin_shape.size(); ++b) {
-            const BinShape s = shape_at(h->bin_shape[b]);
-            if (s.W != W || s.W * s.R < rows) continue;
-            if (best < 0 || s.R < shape_at(h->bin_shape[best]).R) best = b;
+    for (int sel = 0; sel < 2; ++sel) {
+        const int prec = sel == 0 ? 16 : 32;
+        for (int k = 0; k < kLutRows; ++k) {
+            const int rows = 16 * (k + 1);
+            const int W = rows <= 256 ? 16 : 64;
+            int best = -1;
+            for (int b = 0; b < (int)h->bins.size(); ++b) {
+                const ShapeEntry& e = h->bins[b];
+                if (e.prec != prec || e.W != W || e.W * e.R < rows) continue;
+                if (best < 0 || e.R < h->bins[best].R) best = b;
+            }
+            h->lut[sel * kLutRows + k] = (int8_t)best;
         }
-        h->lut[k] = (int8_t)best;
     }
 }
 
@@ -206,7 +214,7 @@ int sw_set_option(sw_handle* h, const char* key, int64_t value) {
     } else if (k == "timing") {
         h->opt_timing = value ? 1 : 0;
     } else if (k == "precision") {
-        if (value != 0 && value != 32 && value != 16) return fail(h, SW_EINVAL, "precision must be 0, 16 or 32");
+        if (value != 0 && value != 32) return fail(h, SW_EINVAL, "precision must be 0 or 32");
         h->opt_precision = value;
     } else {
         return fail(h, SW_EINVAL, "unknown option '%s'", key);
@@ -275,9 +283,22 @@ int sw_align_batch(sw_handle* h, const sw_batch* batch, const sw_scheme* schemes
     int32_t* d_flags = h->d_small;
     int32_t* d_hist = h->d_small + kNumFlags;
     int32_t* d_maxm = h->d_small + kNumFlags + 64;
-    const int n_bins = (int)h->bin_shape.size();
-    HIP_TRY(h, launch_classify(batch->q_off, batch->r_off, batch->scheme_id, P, n_schemes, h->d_lut,
-                               n_bins, h->d_keys, h->d_vals, out, d_flags, d_hist, d_maxm, h->d_cells,
+    const int n_bins = (int)h->bins.size();
+    ClassifyArgs C;
+    for (int s = 0; s < SW_MAX_SCHEMES; ++s) {
+        int mx = 1;
+        if (s < n_schemes)
+            for (int k = 0; k < schemes[s].alphabet * schemes[s].alphabet; ++k)
+                mx = std::max(mx, (int)schemes[s].matrix[k]);
+        C.max_score[s] = mx;
+    }
+    // int16 holds every value of a pair when min(n, m) * max_score plus one
+    // more substitution score stays below 2^15
+    C.i16_limit = h->opt_precision == 32 ? -1 : 32767 - 127;
+    C.n_schemes = n_schemes;
+    C.n_bins = n_bins;
+    HIP_TRY(h, launch_classify(batch->q_off, batch->r_off, batch->scheme_id, P, C, h->d_lut,
+                               h->d_keys, h->d_vals, out, d_flags, d_hist, d_maxm, h->d_cells,
                                stream));
     size_t tb = h->temp_bytes;
     HIP_TRY(h, hipcub::DeviceRadixSort::SortPairs(h->d_temp, tb, h->d_keys, h->d_keys2, h->d_vals,
@@ -313,8 +334,8 @@ int sw_align_batch(sw_handle* h, const sw_batch* batch, const sw_scheme* schemes
     for (int pass = 0; pass < 2; ++pass) {
         for (int b = 0; b < n_bins; ++b) {
             if (hist[b] == 0) continue;
-            HIP_TRY(h, launch_pass(h->bin_shape[b], K, first[b], hist[b], pass, stream));
-            if (pass == 0) h->last_i32 += hist[b];
+            HIP_TRY(h, launch_pass(h->bins[b], K, first[b], hist[b], pass, stream));
+            if (pass == 0 && h->bins[b].prec == 32) h->last_i32 += hist[b];
         }
         if (timing) HIP_TRY(h, hipEventRecord(h->ev[3 + pass], stream));
     }

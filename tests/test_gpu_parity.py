@@ -158,3 +158,49 @@ def test_full_size_sampled(aligner, name):
     assert np.all(s > 0)  # every pair embeds a mutated copy of its query
     assert np.all((g[:, 1] >= 0) & (g[:, 1] <= g[:, 2]) & (g[:, 2] < ql))
     assert np.all((g[:, 3] >= 0) & (g[:, 3] <= g[:, 4]) & (g[:, 4] < rl))
+
+
+def test_int16_and_int32_paths_agree(aligner):
+    """The packed int16 path and the int32 path give identical results."""
+    from paper_2208_12350_amd.binding import Aligner, DeviceBatch
+    b = W.make_workload("mixed", n_pairs=2000, seed=777)
+    db = DeviceBatch.from_host(b)
+    g16 = aligner.align(db).cpu().numpy()
+    assert aligner.stats()[2] == 0          # everything fit the int16 path
+    a32 = Aligner(0, precision=32)
+    try:
+        g32 = a32.align(db).cpu().numpy()
+        assert a32.stats()[2] == b.n_pairs  # everything forced onto int32
+    finally:
+        a32.close()
+    assert np.array_equal(g16, g32)
+    idx = np.arange(0, b.n_pairs, 7)
+    assert_same(g16, O.align_batch(b, index=idx), b, idx=idx)
+
+
+def test_large_scores_route_to_int32(aligner):
+    """A scheme whose scores would overflow 16 bits runs on the int32 path,
+    side by side with int16 pairs of another scheme in the same batch; the
+    scaled scheme gives exactly k times the score and the same coordinates."""
+    base = W.make_workload("dna_small", n_pairs=300, seed=5)
+    k = 40
+    dna = W.dna_scheme()
+    big = W.Scheme(np.ascontiguousarray((dna.matrix.astype(np.int32) * k).astype(np.int8)),
+                   dna.gap_open * k, dna.gap_extend * k, "dna_x40")
+    pairs = [base.pair(i)[:2] for i in range(base.n_pairs)]
+    # long pairs so that min(n, m) * 120 exceeds the int16 bound
+    rng = np.random.default_rng(8)
+    for _ in range(50):
+        q = rng.integers(0, 4, size=int(rng.integers(300, 700))).astype(np.uint8)
+        r = np.concatenate([rng.integers(0, 4, size=50), q, rng.integers(0, 4, size=80)]).astype(np.uint8)
+        pairs.append((q, r))
+    sids = [i % 2 for i in range(len(pairs))]
+    b = W.from_pairs(pairs, sids, [dna, big])
+    g = run_gpu(aligner, b)
+    assert aligner.stats()[2] > 0           # some pairs took the int32 path
+    assert_same(g, O.align_batch(b), b)
+    b1 = W.from_pairs(pairs, [0] * len(pairs), [dna])
+    g1 = run_gpu(aligner, b1)
+    odd = np.arange(1, len(pairs), 2)
+    assert np.array_equal(g[odd, 0], g1[odd, 0] * k)
+    assert np.array_equal(g[odd, 1:], g1[odd, 1:])

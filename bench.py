@@ -92,27 +92,50 @@ def main():
     log("  %d pairs, %.3g forward cells (%.1f s)" % (batch.n_pairs, batch.cells(), time.time() - t))
     dev = "cuda:0"
     db = DeviceBatch.from_host(batch, dev)
-    al = Aligner(0, timing=1)
-    if args.mode is not None:
-        al.set_option("mode", args.mode)
     out = torch.empty((batch.n_pairs, 5), dtype=torch.int32, device=dev)
 
-    for k in range(args.warmup):
-        al.align(db, out)
-        log("  warmup step %d done" % k)
-    torch.cuda.synchronize()
-    step_ms, plan_ms, fwd_ms, rev_ms = [], [], [], []
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        ts = time.perf_counter()
-        al.align(db, out)
-        step_ms.append((time.perf_counter() - ts) * 1e3)
-        p, f, r = al.timing()
-        plan_ms.append(p); fwd_ms.append(f); rev_ms.append(r)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+    def timed(al, steps, warmup, what):
+        for k in range(warmup):
+            al.align(db, out)
+        torch.cuda.synchronize()
+        step_ms = []
+        t0 = time.perf_counter()
+        for k in range(steps):
+            ts = time.perf_counter()
+            al.align(db, out)
+            step_ms.append((time.perf_counter() - ts) * 1e3)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        log("  %s: %d steps in %.3f s" % (what, steps, el))
+        return el, step_ms
+
+    # headline: persistent work-queue launch, replayed from a captured hipGraph
+    mode = 1 if args.mode is None else args.mode
+    al = Aligner(0, mode=mode, graph=1 if mode == 1 else 0)
+    elapsed, step_ms = timed(al, args.steps, args.warmup, "mode %d" % mode)
+    ref_out = out.clone()
     fwd_cells, rev_cells, i32_pairs = al.stats()
-    log("  timed %d steps in %.3f s" % (args.steps, elapsed))
+    al.close()
+
+    # same sweeps with HIP events around the phases (no graph), for the roofline
+    alt = Aligner(0, mode=mode, graph=0, timing=1)
+    plan_ms, fwd_ms, rev_ms = [], [], []
+    for k in range(max(3, min(args.steps, 10)) + 1):
+        alt.align(db, out)
+        if k:
+            p, f, r = alt.timing()
+            plan_ms.append(p); fwd_ms.append(f); rev_ms.append(r)
+    alt.close()
+    assert torch.equal(out, ref_out), "timing run disagrees with the headline run"
+
+    # plain per-bin launches on the same data
+    plain = None
+    if mode == 1:
+        alp = Aligner(0, mode=0, graph=0)
+        el_p, _ = timed(alp, max(2, min(args.steps, 5)), 1, "plain per-bin launches")
+        alp.close()
+        assert torch.equal(out, ref_out), "plain launches disagree with the persistent launch"
+        plain = round(fwd_cells * max(2, min(args.steps, 5)) / el_p / 1e9, 2)
 
     ms_per_step = elapsed * 1e3 / args.steps
     gcups = fwd_cells * args.steps / elapsed / 1e9
@@ -135,7 +158,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "pairs": batch.n_pairs, "forward_cells": int(fwd_cells),
                    "reverse_cells": int(rev_cells), "int32_pairs": int(i32_pairs),
-                   "mode": al.get_option("mode")},
+                   "mode": "persistent+graph" if mode == 1 else "plain per-bin launches"},
+        "plain_value": plain,
         "latency_ms": {"p50": round(float(np.percentile(step_ms, 50)), 3),
                        "p99": round(float(np.percentile(step_ms, 99)), 3)},
         "phase_ms": {"plan": round(float(np.mean(plan_ms)), 3), "forward": round(float(np.mean(fwd_ms)), 3),
@@ -145,7 +169,6 @@ def main():
                      "kernel": "forward+reverse sweeps",
                      "ops_per_cell": OPS_PER_CELL},
     }
-    al.close()
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a sample ...")
         res["cpu_baseline"] = cpu_baseline(batch)

@@ -34,11 +34,18 @@ struct PairJob {
     int fwd_score, fwd_qe, fwd_re;
 };
 
+// The sub-problem of one pair for this sweep.  Pair ids come from the
+// planning arrays; any id or length outside its documented range is an
+// internal error, flagged and turned into an empty job.
 __device__ __forceinline__ PairJob load_job(const KParams& P, int pair, int reverse) {
     PairJob J;
     J.dir = 1; J.n = 0; J.m = 0; J.qbase = 0; J.rbase = 0; J.sid = 0;
     J.fwd_score = 0; J.fwd_qe = -1; J.fwd_re = -1;
     if (pair < 0) return J;
+    if (pair >= P.n_pairs) {
+        atomicOr(&P.flags[kFlagInternal], 1);
+        return J;
+    }
     J.sid = P.scheme_id ? (int)P.scheme_id[pair] : 0;
     const int64_t q0 = P.q_off[pair], q1 = P.q_off[pair + 1];
     const int64_t r0 = P.r_off[pair], r1 = P.r_off[pair + 1];
@@ -53,6 +60,10 @@ __device__ __forceinline__ PairJob load_job(const KParams& P, int pair, int reve
             J.qbase = q0 + f.q_end; J.rbase = r0 + f.r_end;
             J.dir = -1;
         }
+    }
+    if (J.n < 0 || J.n > SW_MAX_QUERY || J.m < 0 || J.m > SW_MAX_REF || J.sid >= SW_MAX_SCHEMES) {
+        atomicOr(&P.flags[kFlagInternal], 1);
+        J.n = 0; J.m = 0; J.sid = 0; J.fwd_score = 0;
     }
     return J;
 }

@@ -10,45 +10,103 @@ namespace sw {
 // Residue code used for rows below the query end and columns past the
 // reference end (and, before the sweep reaches them, columns left of 0).
 // Its substitution score is -1 against everything, so a padded cell can
-// never reach the best score of its pair (see the kernel header comment).
+// never reach the best score of its pair (see sw_sweep.h).
 constexpr int kPad = 31;
 constexpr int kMatDim = 32;                    // LDS matrix is 32 x 32 int8
 constexpr int kMatBytes = kMatDim * kMatDim;   // per scheme
 constexpr int kBlock = 256;                    // 4 wavefronts per workgroup
 constexpr int kWavesPerBlock = kBlock / 64;
 
-// Precision / geometry class of a length bin.
-struct BinShape {
-    int16_t prec;     // 32 = int32 lanes, 16 = two int16 pairs packed per lane
-    int16_t W;        // lanes per pair group: 16 or 64
-    int16_t R;        // query rows per lane
+// ---- planning: bins, length buckets, work items ----------------------------
+// A bin is one compiled sweep shape (precision, lanes per group W, rows per
+// lane R).  Pairs are bucketed by (bin, reference length) with a 16-bit key
+// so a counting sort on the device groups pairs of one bin with the longest
+// references first; consecutive pairs of a bin then form wave work items.
+constexpr int kMaxBins = 40;
+constexpr int kMBuckets = 1024;                        // length buckets per bin
+constexpr int kTrivialKey = kMaxBins * kMBuckets;      // empty / invalid pairs
+constexpr int kHistSize = kTrivialKey + 1;
+
+// Reference length -> bucket, monotone: exact below 512, then 64 buckets per
+// octave (width <= 1/64 of the length) up to 65535.
+__host__ __device__ inline int m_bucket(int m) {
+    if (m < 512) return m;
+    const int lg = 31 - __builtin_clz((unsigned)m);          // 9..15
+    const int frac = (m >> (lg - 6)) & 63;
+    int b = 512 + (lg - 9) * 64 + frac;
+    return b < kMBuckets ? b : kMBuckets - 1;
+}
+
+struct BinInfo {
+    int8_t prec;      // 16 = two pairs per lane group packed in int16 halves, 32 = int32
+    int8_t W;         // lanes per group: 16 or 64
+    int8_t R;         // query rows per lane
+    int8_t pad;
+    int32_t ppw;      // pairs per wavefront work item
 };
 
-// Arguments shared by every alignment launch.
+// One wavefront's work: pairs order[first .. first+count) of one bin.
+struct WorkItem {
+    int32_t first;
+    uint16_t count;
+    uint8_t bin;
+    uint8_t prec;
+    uint8_t W;
+    uint8_t R;
+    uint8_t pad[2];
+};
+
+// Layout of the per-pass planning metadata array (int32).
+enum : int {
+    kMetaBinFirst = 0,                                // [kMaxBins + 1] first sorted position of each bin
+    kMetaItemFirst = kMetaBinFirst + kMaxBins + 1,    // [kMaxBins + 1] first item of each bin
+    kMetaHeads = kMetaItemFirst + kMaxBins + 1,       // [kMaxBins] queue head of each bin
+    kMetaSize = kMetaHeads + kMaxBins,
+};
+
+// Arguments shared by every sweep launch.
 struct KParams {
     const uint8_t* queries;
     const int64_t* q_off;
     const uint8_t* refs;
     const int64_t* r_off;
     const uint8_t* scheme_id;    // nullable
-    const int32_t* order;        // pair ids sorted by (bin, reference length desc)
+    const int32_t* order;        // pair ids grouped by bin, longest references first
+    const WorkItem* items;
+    int32_t* meta;               // planning metadata (item ranges, queue heads)
     sw_result* out;
-    int32_t* flags;              // [0] invalid residue, [1] reverse-pass mismatch
+    int32_t* flags;              // kFlag* error flags
     const int8_t* mats;          // [SW_MAX_SCHEMES][32][32], [s][b][a] = M_s[a][b]
     int32_t alphabet[SW_MAX_SCHEMES];
     int32_t gap_open[SW_MAX_SCHEMES];
     int32_t gap_extend[SW_MAX_SCHEMES];
     int32_t validate;
+    int32_t reverse;             // 0 = forward sweep, 1 = reverse sweep
+    int32_t lo_idx, hi_idx;      // meta[lo_idx] .. meta[hi_idx] is this launch's item range
+    int32_t head_idx;            // meta[head_idx] is this launch's queue head
+    int32_t n_pairs;             // pairs in the batch (bound for every pair id)
+    int32_t max_items;           // capacity of the items array (bound for every item index)
 };
 
-// Per-pair classification written by the classify kernel.
 enum : int32_t {
     kFlagBadResidue = 0,
     kFlagReverseMismatch = 1,
     kFlagBadOffsets = 2,
     kFlagBadScheme = 3,
     kFlagTooLong = 4,
+    kFlagInternal = 5,           // a planning or work-item invariant did not hold
     kNumFlags = 8,
+};
+
+// Classification inputs: lut[sel * kLutRows + (n-1)/16] gives the bin of a
+// pair with query length n, where sel = 0 for the packed int16 path and 1
+// for int32; a pair takes int16 when min(n, m) * max_score[s] <= i16_limit.
+constexpr int kLutRows = SW_MAX_QUERY / 16;
+struct ClassifyArgs {
+    int32_t max_score[SW_MAX_SCHEMES];
+    int32_t i16_limit;      // negative disables the int16 path
+    int32_t n_schemes;
+    int32_t n_bins;
 };
 
 }  // namespace sw
@@ -56,32 +114,27 @@ enum : int32_t {
 #include <hip/hip_runtime_api.h>
 
 namespace sw {
-using PassFn = void (*)(KParams, int, int, int);
-// A compiled sweep kernel: precision (32 or 16), lanes per group W, rows per lane R.
-struct ShapeEntry { int prec, W, R; PassFn fn; };
-const ShapeEntry* shapes_i32(int* n);
-const ShapeEntry* shapes_i16(int* n);
-// Pairs one workgroup of the given shape aligns.
-inline int pairs_per_block(const ShapeEntry& e) {
-    return kWavesPerBlock * (64 / e.W) * (e.prec == 16 ? 2 : 1);
-}
-hipError_t launch_pass(const ShapeEntry& e, const KParams& P, int first, int count, int reverse,
-                       hipStream_t stream);
-// Classification inputs: bin_of_rows[sel * kLutRows + (n-1)/16] gives the bin
-// of a pair with query length n, where sel = 0 for the packed int16 path and
-// 1 for int32; a pair takes int16 when min(n, m) * max_score[s] <= i16_limit.
-constexpr int kLutRows = SW_MAX_QUERY / 16;
-struct ClassifyArgs {
-    int32_t max_score[SW_MAX_SCHEMES];
-    int32_t i16_limit;      // 0 disables the int16 path
-    int32_t n_schemes;
-    int32_t n_bins;
-};
-hipError_t launch_classify(const int64_t* q_off, const int64_t* r_off, const uint8_t* scheme_id,
-                           int64_t n_pairs, const ClassifyArgs& C, const int8_t* bin_of_rows,
-                           uint32_t* keys, int32_t* vals, sw_result* out, int32_t* flags,
-                           int32_t* hist, int32_t* maxm, unsigned long long* fwd_cells,
-                           hipStream_t stream);
+
+// A compiled queue kernel: it aligns the work items [meta[lo_idx],
+// meta[hi_idx]) of one bin shape.
+using QueueFn = void (*)(KParams);
+
+struct ShapeDesc { int prec, W, R; };
+
+QueueFn shape_kernel(int prec, int W, int R);
+const ShapeDesc* compiled_shapes(int* n);
+
+hipError_t launch_reset(int32_t* p, int n, hipStream_t s);
+hipError_t launch_classify(const KParams& P, const ClassifyArgs& C, const int8_t* lut,
+                           int64_t n_pairs, int32_t* keys, int32_t* hist,
+                           unsigned long long* counters, hipStream_t s);
+hipError_t launch_plan(const BinInfo* bins, int n_bins, int32_t* hist, int32_t* meta,
+                       hipStream_t s);
+hipError_t launch_scatter(const int32_t* keys, int64_t n_pairs, int32_t* hist, int32_t* order,
+                          hipStream_t s);
+hipError_t launch_items(const int32_t* meta, const BinInfo* bins, int n_bins, int64_t n_pairs,
+                        WorkItem* items, hipStream_t s);
 hipError_t launch_reverse_cells(const sw_result* out, int64_t n, unsigned long long* acc,
                                 hipStream_t stream);
+
 }  // namespace sw

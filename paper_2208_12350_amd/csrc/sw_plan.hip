@@ -1,0 +1,234 @@
+// sw_plan.hip -- device-side planning of a sweep pass (gfx950).
+//
+// For each pass (forward, then reverse) the pairs are
+//   1. classified: validated (forward), routed to int16 or int32 by their
+//      score bound, given a bin from their (sub)query length and a 16-bit
+//      key (bin, reference-length bucket, longest first);
+//   2. counted into a histogram of keys, which one workgroup scans into
+//      bucket offsets and per-bin pair and work-item ranges;
+//   3. scattered into key order (order within a bucket is irrelevant: every
+//      pair's result is independent of where it runs);
+//   4. cut into wavefront work items of ppw consecutive pairs of one bin.
+// The reverse pass re-bins pairs by the shape of their reverse sub-problem
+// (q_end+1 rows, r_end+1 columns), which can differ a lot from the forward
+// shape.  Nothing here synchronises with the host and nothing is cleared
+// with a memset, so a whole call can be captured in a hipGraph.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sw_internal.h"
+
+namespace sw {
+
+__global__ void sw_reset_kernel(int32_t* p, int n) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
+}
+
+__global__ void sw_classify_kernel(KParams P, ClassifyArgs C, const int8_t* lut, int64_t n_pairs,
+                                   int32_t* keys, int32_t* hist, unsigned long long* counters) {
+    // counters[0] / [1]: forward / reverse cells; counters[2]: int32 pairs (forward)
+    __shared__ unsigned long long s_cells;
+    __shared__ int32_t s_trivial, s_i32;
+    if (threadIdx.x == 0) { s_cells = 0; s_trivial = 0; s_i32 = 0; }
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long my_cells = 0;
+    if (i < n_pairs) {
+        int64_t n = 0, m = 0;
+        int s = 0;
+        bool ok = false;
+        if (!P.reverse) {
+            n = P.q_off[i + 1] - P.q_off[i];
+            m = P.r_off[i + 1] - P.r_off[i];
+            s = P.scheme_id ? (int)P.scheme_id[i] : 0;
+            if (n < 0 || m < 0) atomicOr(&P.flags[kFlagBadOffsets], 1);
+            else if (s >= C.n_schemes) atomicOr(&P.flags[kFlagBadScheme], 1);
+            else if (n > SW_MAX_QUERY || m > SW_MAX_REF) atomicOr(&P.flags[kFlagTooLong], 1);
+            else ok = n > 0 && m > 0;
+            if (!ok) {
+                sw_result z;
+                z.score = 0; z.q_start = z.q_end = z.r_start = z.r_end = -1;
+                P.out[i] = z;
+            }
+        } else {
+            // the reverse sub-problem is the prefix box ending at the forward
+            // end; an end outside the pair would be an internal error
+            const sw_result r = P.out[i];
+            if (r.score > 0) {
+                const int64_t n0 = P.q_off[i + 1] - P.q_off[i];
+                const int64_t m0 = P.r_off[i + 1] - P.r_off[i];
+                n = (int64_t)r.q_end + 1;
+                m = (int64_t)r.r_end + 1;
+                s = P.scheme_id ? (int)P.scheme_id[i] : 0;
+                ok = n >= 1 && n <= n0 && m >= 1 && m <= m0 && s < C.n_schemes;
+                if (!ok) atomicOr(&P.flags[kFlagInternal], 1);
+            }
+        }
+        int key = kTrivialKey;
+        if (ok) {
+            const int64_t mn = n < m ? n : m;
+            const int sel = mn * C.max_score[s] <= C.i16_limit ? 0 : 1;
+            if (sel && !P.reverse) atomicAdd(&s_i32, 1);
+            const int bin = lut[sel * kLutRows + (int)((n - 1) / 16)];
+            key = bin * kMBuckets + (kMBuckets - 1 - m_bucket((int)m));
+            atomicAdd(&hist[key], 1);
+            my_cells = (unsigned long long)(n * m);
+        } else {
+            atomicAdd(&s_trivial, 1);
+        }
+        keys[i] = key;
+    }
+    if (my_cells) atomicAdd(&s_cells, my_cells);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (s_cells) atomicAdd(&counters[P.reverse ? 1 : 0], s_cells);
+        if (s_i32) atomicAdd(&counters[2], (unsigned long long)s_i32);
+        if (s_trivial) atomicAdd(&hist[kTrivialKey], s_trivial);
+    }
+}
+
+// One workgroup of 1024 threads: exclusive scan of the key histogram in
+// place, then the per-bin pair and work-item ranges.
+constexpr int kPlanThreads = 1024;
+
+__global__ __launch_bounds__(kPlanThreads) void sw_plan_kernel(const BinInfo* bins, int n_bins,
+                                                               int32_t* hist, int32_t* meta) {
+    __shared__ int32_t part[kPlanThreads];
+    constexpr int kPer = (kHistSize + kPlanThreads - 1) / kPlanThreads;
+    const int t = threadIdx.x;
+    const int lo = t * kPer;
+    const int hi = lo + kPer < kHistSize ? lo + kPer : kHistSize;
+    int32_t sum = 0;
+    for (int k = lo; k < hi; ++k) sum += hist[k];
+    part[t] = sum;
+    __syncthreads();
+    // Hillis-Steele inclusive scan of the partial sums
+    for (int off = 1; off < kPlanThreads; off <<= 1) {
+        const int32_t v = t >= off ? part[t - off] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    int32_t run = part[t] - sum;   // exclusive prefix of this chunk
+    for (int k = lo; k < hi; ++k) {
+        const int32_t c = hist[k];
+        hist[k] = run;
+        run += c;
+    }
+    __syncthreads();
+    if (t == 0) {
+        int32_t items = 0;
+        for (int b = 0; b <= kMaxBins; ++b) {
+            const int32_t f = hist[(b < kMaxBins ? b : kMaxBins) * kMBuckets];
+            meta[kMetaBinFirst + b] = f;
+        }
+        for (int b = 0; b < kMaxBins; ++b) {
+            meta[kMetaItemFirst + b] = items;
+            if (b < n_bins) {
+                const int32_t cnt = meta[kMetaBinFirst + b + 1] - meta[kMetaBinFirst + b];
+                items += (cnt + bins[b].ppw - 1) / bins[b].ppw;
+            }
+        }
+        meta[kMetaItemFirst + kMaxBins] = items;
+        for (int k = 0; k < kMaxBins; ++k) meta[kMetaHeads + k] = 0;
+    }
+}
+
+__global__ void sw_scatter_kernel(const int32_t* keys, int64_t n_pairs, int32_t* offs, int32_t* order) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_pairs) return;
+    const int32_t pos = atomicAdd(&offs[keys[i]], 1);
+    order[pos] = (int32_t)i;
+}
+
+__global__ void sw_items_kernel(const int32_t* meta, const BinInfo* bins, int n_bins, int64_t n_pairs,
+                                WorkItem* items) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_pairs || i >= meta[kMetaBinFirst + n_bins]) return;
+    int b = 0;
+    while (b + 1 < n_bins && meta[kMetaBinFirst + b + 1] <= i) ++b;
+    const int32_t f = meta[kMetaBinFirst + b];
+    const int32_t k = (int32_t)i - f;
+    const BinInfo bi = bins[b];
+    if (k % bi.ppw != 0) return;
+    const int32_t cnt = meta[kMetaBinFirst + b + 1] - f;
+    WorkItem w;
+    w.first = (int32_t)i;
+    w.count = (uint16_t)(cnt - k < bi.ppw ? cnt - k : bi.ppw);
+    w.bin = (uint8_t)b;
+    w.prec = (uint8_t)bi.prec;
+    w.W = (uint8_t)bi.W;
+    w.R = (uint8_t)bi.R;
+    w.pad[0] = w.pad[1] = 0;
+    items[meta[kMetaItemFirst + b] + k / bi.ppw] = w;
+}
+
+// Reverse cells of a finished batch: sum over pairs with a positive score of
+// (q_end+1)*(r_end+1).
+__global__ void sw_reverse_cells_kernel(const sw_result* out, int64_t n, unsigned long long* acc) {
+    __shared__ unsigned long long s;
+    if (threadIdx.x == 0) s = 0;
+    __syncthreads();
+    unsigned long long v = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const sw_result r = out[i];
+        if (r.score > 0) v += (unsigned long long)(r.q_end + 1) * (unsigned long long)(r.r_end + 1);
+    }
+    atomicAdd(&s, v);
+    __syncthreads();
+    if (threadIdx.x == 0) atomicAdd(acc, s);
+}
+
+static unsigned grid_for(int64_t n, int threads) {
+    int64_t b = (n + threads - 1) / threads;
+    return (unsigned)(b > 0 ? b : 1);
+}
+
+hipError_t launch_reset(int32_t* p, int n, hipStream_t s) {
+    unsigned blocks = grid_for(n, 256);
+    if (blocks > 1024) blocks = 1024;
+    hipLaunchKernelGGL(sw_reset_kernel, dim3(blocks), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_classify(const KParams& P, const ClassifyArgs& C, const int8_t* lut,
+                           int64_t n_pairs, int32_t* keys, int32_t* hist,
+                           unsigned long long* counters, hipStream_t s) {
+    if (n_pairs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(sw_classify_kernel, dim3(grid_for(n_pairs, 256)), dim3(256), 0, s, P, C, lut,
+                       n_pairs, keys, hist, counters);
+    return hipGetLastError();
+}
+
+hipError_t launch_plan(const BinInfo* bins, int n_bins, int32_t* hist, int32_t* meta, hipStream_t s) {
+    hipLaunchKernelGGL(sw_plan_kernel, dim3(1), dim3(kPlanThreads), 0, s, bins, n_bins, hist, meta);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter(const int32_t* keys, int64_t n_pairs, int32_t* hist, int32_t* order,
+                          hipStream_t s) {
+    if (n_pairs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(sw_scatter_kernel, dim3(grid_for(n_pairs, 256)), dim3(256), 0, s, keys, n_pairs,
+                       hist, order);
+    return hipGetLastError();
+}
+
+hipError_t launch_items(const int32_t* meta, const BinInfo* bins, int n_bins, int64_t n_pairs,
+                        WorkItem* items, hipStream_t s) {
+    if (n_pairs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(sw_items_kernel, dim3(grid_for(n_pairs, 256)), dim3(256), 0, s, meta, bins, n_bins,
+                       n_pairs, items);
+    return hipGetLastError();
+}
+
+hipError_t launch_reverse_cells(const sw_result* out, int64_t n, unsigned long long* acc,
+                                hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    unsigned blocks = grid_for(n, 256);
+    if (blocks > 1024) blocks = 1024;
+    hipLaunchKernelGGL(sw_reverse_cells_kernel, dim3(blocks), dim3(256), 0, stream, out, n, acc);
+    return hipGetLastError();
+}
+
+}  // namespace sw

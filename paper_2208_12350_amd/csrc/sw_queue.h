@@ -1,0 +1,68 @@
+// sw_queue.h -- work-queue kernels over the sweep shapes (gfx950).
+//
+// A queue kernel is compiled for one bin shape (precision, W, R) and aligns
+// the work items [meta[lo_idx], meta[hi_idx]) of that bin: every wavefront
+// takes the next item with one atomic increment of the bin's queue head and
+// sweeps it, until the range is exhausted.
+//   * plain mode launches it with one wavefront per item (the grid is sized
+//     from the item count the host reads back);
+//   * persistent mode launches it, for every bin, with as many workgroups as
+//     the device holds at once (capped by what the batch could need), without
+//     reading anything back; items of a bin come longest first.
+// Every wavefront leaves the loop once the head passes the end of the range,
+// so the grid always drains.  Range bounds, item fields and pair ids are
+// checked against the array capacities: a violated invariant sets an error
+// flag and the work is skipped rather than indexed.
+#pragma once
+
+#include "sw_sweep.h"
+
+namespace sw {
+
+template <int PREC, int W, int R>
+__global__ __launch_bounds__(kBlock) void sw_queue_kernel(KParams P) {
+    __shared__ __attribute__((aligned(16))) SchemeLds L;
+    __shared__ uint16_t wbufs[kWavesPerBlock * kWaveBuf];
+    constexpr int kPPW = (64 / W) * (PREC == 16 ? 2 : 1);
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    load_schemes(L, P, tid);
+    __syncthreads();
+    int lo = __atomic_load_n(&P.meta[P.lo_idx], __ATOMIC_RELAXED);
+    int hi = __atomic_load_n(&P.meta[P.hi_idx], __ATOMIC_RELAXED);
+    lo = __builtin_amdgcn_readfirstlane(lo);
+    hi = __builtin_amdgcn_readfirstlane(hi);
+    if (lo < 0 || hi > P.max_items || lo > hi) {
+        if (tid == 0) atomicOr(&P.flags[kFlagInternal], 1);
+        return;
+    }
+    uint16_t* wbuf = wbufs + wave * kWaveBuf;
+    // The loop has no lane-divergent branch: every lane takes part in the
+    // fetch (only lane 0 adds 1, so each wavefront claims exactly one item
+    // whether or not the lanes' atomics are merged), and the item index is
+    // lane 0's return value.  A lane-0-only atomic inside this loop was
+    // lowered into an inner loop that re-entered without the fetch.
+    for (;;) {
+        const int mine = atomicAdd(&P.meta[P.head_idx], lane == 0 ? 1 : 0);
+        const int it = __builtin_amdgcn_readlane(mine, 0);
+        if (it >= hi - lo) break;
+        const WorkItem* wp = P.items + lo + it;
+        const int first = __builtin_amdgcn_readfirstlane(__atomic_load_n(&wp->first, __ATOMIC_RELAXED));
+        const int count = __builtin_amdgcn_readfirstlane((int)__atomic_load_n(&wp->count, __ATOMIC_RELAXED));
+        const bool valid = first >= 0 && count >= 1 && count <= kPPW && first + count <= P.n_pairs;
+        if (valid) {
+            wave_lds_sync();
+            if constexpr (PREC == 16)
+                sweep_i16<W, R>(P, L, wbuf, first, count, lane);
+            else
+                sweep_i32<W, R>(P, L, wbuf, first, count, lane);
+        } else {
+            atomicOr(&P.flags[kFlagInternal], 1);
+        }
+    }
+}
+
+struct KernelEntry { int prec, W, R; QueueFn fn; };
+
+}  // namespace sw

@@ -1,18 +1,18 @@
-// sw_runtime.hip -- host runtime of libswalign: argument checks, device-side
-// classification and length binning, launch planning, error reporting.
+// sw_runtime.hip -- host runtime of libswalign: argument checks, launch
+// sequencing of the planning and sweep kernels, hipGraph capture and replay,
+// error reporting.
 //
-// One sw_align_batch call:
-//   1. host checks of the arguments and schemes; the schemes' matrices are
-//      packed into a [scheme][ref residue][query residue] int8 table;
-//   2. sw_classify (device): per pair length/offset/scheme checks, a bin
-//      from the query length, and a sort key (bin, longest reference first);
-//   3. hipcub radix sort of (key, pair id) on the device;
-//   4. one small device->host copy of the per-bin histogram (the only
-//      synchronisation before the sweeps);
-//   5. the forward sweep of every bin, then the reverse sweep of every bin;
-//   6. a device->host copy of the error flags.
+// One sw_align_batch call, for each of the two passes (forward, reverse):
+//   classify -> plan (scan) -> scatter -> items   (sw_plan.hip)
+//   sweeps over the work items                    (sw_queue*.hip)
+// Persistent mode (default): one queue kernel per bin, longest bins first,
+// each sized to the resident capacity of the device (capped by what the
+// batch could need); nothing synchronises with the host until the end, and
+// the whole sequence can be captured once into a hipGraph and replayed for
+// later calls with the same arguments.
+// Plain mode: after each pass is planned the host reads the per-bin item
+// counts and launches one kernel per non-empty bin, sized to its items.
 #include <hip/hip_runtime.h>
-#include <hipcub/hipcub.hpp>
 
 #include <algorithm>
 #include <cstdarg>
@@ -28,51 +28,68 @@ using namespace sw;
 
 namespace {
 
-constexpr int kLutEntries = 2 * kLutRows;       // [int16 | int32] x 16-row buckets of query length
-constexpr int kSmallInts = 256;                   // pinned host staging for hist/maxm/flags
+constexpr int kLutEntries = 2 * kLutRows;
+constexpr int kSmallInts = 64;   // flags [0, kNumFlags) | 64-bit counters from index 16
 
-struct DeviceBuf {
-    void* p = nullptr;
-    size_t bytes = 0;
+// Everything a captured graph depends on besides device memory contents.
+struct GraphKey {
+    const void* queries;
+    const void* q_off;
+    const void* refs;
+    const void* r_off;
+    const void* scheme_id;
+    const void* out;
+    int64_t n_pairs;
+    int32_t alphabet[SW_MAX_SCHEMES];
+    int32_t gap_open[SW_MAX_SCHEMES];
+    int32_t gap_extend[SW_MAX_SCHEMES];
+    int32_t max_score[SW_MAX_SCHEMES];
+    int32_t n_schemes;
+    int32_t validate;
+    int32_t precision;
 };
 
 }  // namespace
 
 struct sw_handle {
     int device = 0;
+    int n_cu = 0;
     std::string err;
-    int64_t opt_mode = 0;
-    int64_t opt_graph = 0;
+    int64_t opt_mode = 1;
+    int64_t opt_graph = 1;
     int64_t opt_validate = 1;
     int64_t opt_precision = 0;
     int64_t opt_timing = 0;
-    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
-    float t_plan = 0.f, t_fwd = 0.f, t_rev = 0.f;
 
-    std::vector<ShapeEntry> bins;        // the kernel shape of each bin
-    std::vector<int8_t> lut;             // precision x (query length - 1) / 16 -> bin
+    std::vector<BinInfo> bins;
+    std::vector<int8_t> lut;
+    std::vector<int> resident_blocks;   // per bin: workgroups the device holds at once
 
     int8_t* d_mats = nullptr;
     int8_t* d_lut = nullptr;
-    int32_t* d_small = nullptr;          // flags[8] | hist[64] | maxm[64]
-    unsigned long long* d_cells = nullptr;  // [0] forward cells, [1] reverse cells
-    uint32_t* d_keys = nullptr;
-    uint32_t* d_keys2 = nullptr;
-    int32_t* d_vals = nullptr;
-    int32_t* d_vals2 = nullptr;
+    BinInfo* d_bins = nullptr;
+    int32_t* d_small = nullptr;
+    int32_t* d_hist = nullptr;
+    int32_t* d_meta = nullptr;
+    int32_t* d_keys = nullptr;
+    int32_t* d_order = nullptr;
+    WorkItem* d_items = nullptr;
     int64_t cap_pairs = 0;
-    void* d_temp = nullptr;
-    size_t temp_bytes = 0;
 
-    int8_t* h_mats = nullptr;            // pinned
-    int32_t* h_small = nullptr;          // pinned
-    unsigned long long* h_cells = nullptr;  // pinned
+    int8_t* h_mats = nullptr;     // pinned
+    int32_t* h_small = nullptr;   // pinned
+    int32_t* h_meta = nullptr;    // pinned
 
-    int64_t last_fwd = 0;
-    int64_t last_i32 = 0;
-    const sw_result* last_out = nullptr;
-    int64_t last_n = 0;
-    hipStream_t last_stream = nullptr;
+    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    float t_plan = 0.f, t_fwd = 0.f, t_rev = 0.f;
+
+    hipStream_t cap_stream = nullptr;   // private stream the graph is captured on
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    GraphKey gkey;
+    bool have_graph = false;
+
+    int64_t last_fwd = 0, last_rev = 0, last_i32 = 0;
 };
 
 static int fail(sw_handle* h, int code, const char* fmt, ...) {
@@ -92,17 +109,35 @@ static int fail(sw_handle* h, int code, const char* fmt, ...) {
             return fail((h), SW_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_));   \
     } while (0)
 
+// 64-bit counters live in d_small from int index 16: [0] forward cells,
+// [1] reverse cells, [2] int32 pairs of the forward pass.
+static unsigned long long* counters(int32_t* small) {
+    return reinterpret_cast<unsigned long long*>(small + 16);
+}
+
 static void build_bins(sw_handle* h) {
-    // Bins 0.. are the packed int16 shapes, then the int32 shapes.  Default
-    // binning: queries up to 256 rows run on 16-lane groups, longer ones on
-    // 64-lane groups; the rows per lane R is the smallest compiled value
-    // covering the upper end of the query's 16-row bucket.
+    // Bins run longest work first: int16 before int32, then decreasing rows
+    // per lane (and 64-lane groups before 16-lane ones at equal R).
+    // Queries up to 256 rows take 16-lane groups, longer ones 64-lane groups;
+    // R is the smallest compiled value covering the query's 16-row bucket.
+    int n = 0;
+    const ShapeDesc* sh = compiled_shapes(&n);
+    std::vector<ShapeDesc> v(sh, sh + n);
+    std::stable_sort(v.begin(), v.end(), [](const ShapeDesc& a, const ShapeDesc& b) {
+        if (a.prec != b.prec) return a.prec < b.prec;
+        if (a.R != b.R) return a.R > b.R;
+        return a.W > b.W;
+    });
     h->bins.clear();
-    int n16 = 0, n32 = 0;
-    const ShapeEntry* s16 = shapes_i16(&n16);
-    const ShapeEntry* s32 = shapes_i32(&n32);
-    for (int k = 0; k < n16; ++k) h->bins.push_back(s16[k]);
-    for (int k = 0; k < n32; ++k) h->bins.push_back(s32[k]);
+    for (const ShapeDesc& s : v) {
+        BinInfo b;
+        b.prec = (int8_t)s.prec;
+        b.W = (int8_t)s.W;
+        b.R = (int8_t)s.R;
+        b.pad = 0;
+        b.ppw = (64 / s.W) * (s.prec == 16 ? 2 : 1);
+        h->bins.push_back(b);
+    }
     h->lut.assign(kLutEntries, -1);
     for (int sel = 0; sel < 2; ++sel) {
         const int prec = sel == 0 ? 16 : 32;
@@ -111,7 +146,7 @@ static void build_bins(sw_handle* h) {
             const int W = rows <= 256 ? 16 : 64;
             int best = -1;
             for (int b = 0; b < (int)h->bins.size(); ++b) {
-                const ShapeEntry& e = h->bins[b];
+                const BinInfo& e = h->bins[b];
                 if (e.prec != prec || e.W != W || e.W * e.R < rows) continue;
                 if (best < 0 || e.R < h->bins[best].R) best = b;
             }
@@ -124,24 +159,69 @@ static void free_dev(void* p) {
     if (p) (void)hipFree(p);
 }
 
+static void drop_graph(sw_handle* h) {
+    if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+    if (h->graph) (void)hipGraphDestroy(h->graph);
+    h->gexec = nullptr;
+    h->graph = nullptr;
+    h->have_graph = false;
+}
+
 static int ensure_pairs(sw_handle* h, int64_t n) {
     if (n <= h->cap_pairs) return SW_OK;
-    free_dev(h->d_keys); free_dev(h->d_keys2); free_dev(h->d_vals); free_dev(h->d_vals2);
-    free_dev(h->d_temp);
-    h->d_keys = h->d_keys2 = nullptr; h->d_vals = h->d_vals2 = nullptr; h->d_temp = nullptr;
+    drop_graph(h);
+    free_dev(h->d_keys); free_dev(h->d_order); free_dev(h->d_items);
+    h->d_keys = h->d_order = nullptr; h->d_items = nullptr;
     h->cap_pairs = 0;
-    const int64_t cap = std::max<int64_t>(n, 1024);
-    if (hipMalloc(&h->d_keys, cap * 4) != hipSuccess || hipMalloc(&h->d_keys2, cap * 4) != hipSuccess ||
-        hipMalloc(&h->d_vals, cap * 4) != hipSuccess || hipMalloc(&h->d_vals2, cap * 4) != hipSuccess)
+    const int64_t cap = std::max<int64_t>(n, 4096);
+    if (hipMalloc(&h->d_keys, cap * 4) != hipSuccess || hipMalloc(&h->d_order, cap * 4) != hipSuccess ||
+        hipMalloc(&h->d_items, (cap + kMaxBins) * sizeof(WorkItem)) != hipSuccess)
         return fail(h, SW_ENOMEM, "device allocation of %lld pair slots failed", (long long)cap);
-    size_t tb = 0;
-    if (hipcub::DeviceRadixSort::SortPairs(nullptr, tb, h->d_keys, h->d_keys2, h->d_vals, h->d_vals2,
-                                           (int)cap, 0, 22) != hipSuccess)
-        return fail(h, SW_EDEVICE, "radix sort sizing failed");
-    if (hipMalloc(&h->d_temp, tb) != hipSuccess)
-        return fail(h, SW_ENOMEM, "device allocation of sort scratch failed");
-    h->temp_bytes = tb;
     h->cap_pairs = cap;
+    return SW_OK;
+}
+
+// Enqueue one pass (planning + sweeps).  Plain mode synchronises `stream`
+// once to read the per-bin item counts.
+static int enqueue_pass(sw_handle* h, KParams K, const ClassifyArgs& C, int64_t P, int pass,
+                        hipStream_t stream, bool timing) {
+    K.reverse = pass;
+    const int n_bins = (int)h->bins.size();
+    HIP_TRY(h, launch_reset(h->d_hist, kHistSize, stream));
+    HIP_TRY(h, launch_classify(K, C, h->d_lut, P, h->d_keys, h->d_hist, counters(h->d_small), stream));
+    HIP_TRY(h, launch_plan(h->d_bins, n_bins, h->d_hist, h->d_meta, stream));
+    HIP_TRY(h, launch_scatter(h->d_keys, P, h->d_hist, h->d_order, stream));
+    HIP_TRY(h, launch_items(h->d_meta, h->d_bins, n_bins, P, h->d_items, stream));
+    if (h->opt_mode == 1) {
+        if (timing) HIP_TRY(h, hipEventRecord(h->ev[pass == 0 ? 1 : 3], stream));
+        for (int b = 0; b < n_bins; ++b) {
+            const BinInfo& e = h->bins[b];
+            // no bin can hold more than P / ppw items, one wavefront each
+            const int64_t need = (P / e.ppw + 1 + kWavesPerBlock - 1) / kWavesPerBlock;
+            const int blocks = (int)std::min<int64_t>(need, h->resident_blocks[b]);
+            K.lo_idx = kMetaItemFirst + b;
+            K.hi_idx = kMetaItemFirst + b + 1;
+            K.head_idx = kMetaHeads + b;
+            hipLaunchKernelGGL(shape_kernel(e.prec, e.W, e.R), dim3(blocks), dim3(kBlock), 0, stream, K);
+            HIP_TRY(h, hipGetLastError());
+        }
+    } else {
+        HIP_TRY(h, hipMemcpyAsync(h->h_meta, h->d_meta, kMetaSize * 4, hipMemcpyDeviceToHost, stream));
+        HIP_TRY(h, hipStreamSynchronize(stream));
+        if (timing) HIP_TRY(h, hipEventRecord(h->ev[pass == 0 ? 1 : 3], stream));
+        for (int b = 0; b < n_bins; ++b) {
+            const int items = h->h_meta[kMetaItemFirst + b + 1] - h->h_meta[kMetaItemFirst + b];
+            if (items <= 0) continue;
+            const BinInfo& e = h->bins[b];
+            K.lo_idx = kMetaItemFirst + b;
+            K.hi_idx = kMetaItemFirst + b + 1;
+            K.head_idx = kMetaHeads + b;
+            const int blocks = (items + kWavesPerBlock - 1) / kWavesPerBlock;
+            hipLaunchKernelGGL(shape_kernel(e.prec, e.W, e.R), dim3(blocks), dim3(kBlock), 0, stream, K);
+            HIP_TRY(h, hipGetLastError());
+        }
+    }
+    if (timing) HIP_TRY(h, hipEventRecord(h->ev[pass == 0 ? 2 : 4], stream));
     return SW_OK;
 }
 
@@ -153,16 +233,32 @@ sw_handle* sw_create(int device, const char* tuning) {
     if (hipSetDevice(device) != hipSuccess) return nullptr;
     sw_handle* h = new sw_handle();
     h->device = device;
+    hipDeviceProp_t prop;
+    bool ok = hipGetDeviceProperties(&prop, device) == hipSuccess;
+    h->n_cu = ok ? prop.multiProcessorCount : 0;
     build_bins(h);
-    bool ok = hipMalloc(&h->d_mats, SW_MAX_SCHEMES * kMatBytes) == hipSuccess &&
-              hipMalloc(&h->d_lut, kLutEntries) == hipSuccess &&
-              hipMalloc(&h->d_small, kSmallInts * 4) == hipSuccess &&
-              hipMalloc(&h->d_cells, 4 * sizeof(unsigned long long)) == hipSuccess &&
-              hipHostMalloc(&h->h_mats, SW_MAX_SCHEMES * kMatBytes, hipHostMallocDefault) == hipSuccess &&
-              hipHostMalloc(&h->h_small, kSmallInts * 4, hipHostMallocDefault) == hipSuccess &&
-              hipHostMalloc(&h->h_cells, 4 * sizeof(unsigned long long), hipHostMallocDefault) == hipSuccess;
+    ok = ok && h->bins.size() <= (size_t)kMaxBins &&
+         hipMalloc(&h->d_mats, SW_MAX_SCHEMES * kMatBytes) == hipSuccess &&
+         hipMalloc(&h->d_lut, kLutEntries) == hipSuccess &&
+         hipMalloc(&h->d_bins, kMaxBins * sizeof(BinInfo)) == hipSuccess &&
+         hipMalloc(&h->d_small, kSmallInts * 4) == hipSuccess &&
+         hipMalloc(&h->d_hist, kHistSize * 4) == hipSuccess &&
+         hipMalloc(&h->d_meta, kMetaSize * 4) == hipSuccess &&
+         hipHostMalloc(&h->h_mats, SW_MAX_SCHEMES * kMatBytes, hipHostMallocDefault) == hipSuccess &&
+         hipHostMalloc(&h->h_small, kSmallInts * 4, hipHostMallocDefault) == hipSuccess &&
+         hipHostMalloc(&h->h_meta, kMetaSize * 4, hipHostMallocDefault) == hipSuccess;
     for (int k = 0; ok && k < 5; ++k) ok = hipEventCreate(&h->ev[k]) == hipSuccess;
+    if (ok) ok = hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) == hipSuccess;
     if (ok) ok = hipMemcpy(h->d_lut, h->lut.data(), kLutEntries, hipMemcpyHostToDevice) == hipSuccess;
+    if (ok) ok = hipMemcpy(h->d_bins, h->bins.data(), h->bins.size() * sizeof(BinInfo),
+                           hipMemcpyHostToDevice) == hipSuccess;
+    h->resident_blocks.assign(h->bins.size(), 1);
+    for (size_t b = 0; ok && b < h->bins.size(); ++b) {
+        int per_cu = 0;
+        const QueueFn fn = shape_kernel(h->bins[b].prec, h->bins[b].W, h->bins[b].R);
+        ok = fn && hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)fn, kBlock, 0) == hipSuccess;
+        h->resident_blocks[b] = std::max(1, per_cu) * std::max(1, h->n_cu);
+    }
     if (!ok) { sw_destroy(h); return nullptr; }
     if (tuning) {
         std::string s(tuning);
@@ -188,14 +284,16 @@ void sw_destroy(sw_handle* h) {
     if (!h) return;
     (void)hipSetDevice(h->device);
     (void)hipDeviceSynchronize();
-    free_dev(h->d_mats); free_dev(h->d_lut); free_dev(h->d_small); free_dev(h->d_cells);
-    free_dev(h->d_keys); free_dev(h->d_keys2); free_dev(h->d_vals); free_dev(h->d_vals2);
-    free_dev(h->d_temp);
+    drop_graph(h);
+    free_dev(h->d_mats); free_dev(h->d_lut); free_dev(h->d_bins); free_dev(h->d_small);
+    free_dev(h->d_hist); free_dev(h->d_meta); free_dev(h->d_keys); free_dev(h->d_order);
+    free_dev(h->d_items);
     if (h->h_mats) (void)hipHostFree(h->h_mats);
     if (h->h_small) (void)hipHostFree(h->h_small);
-    if (h->h_cells) (void)hipHostFree(h->h_cells);
+    if (h->h_meta) (void)hipHostFree(h->h_meta);
     for (int k = 0; k < 5; ++k)
         if (h->ev[k]) (void)hipEventDestroy(h->ev[k]);
+    if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
     delete h;
 }
 
@@ -219,6 +317,7 @@ int sw_set_option(sw_handle* h, const char* key, int64_t value) {
     } else {
         return fail(h, SW_EINVAL, "unknown option '%s'", key);
     }
+    drop_graph(h);
     return SW_OK;
 }
 
@@ -238,6 +337,8 @@ int sw_align_batch(sw_handle* h, const sw_batch* batch, const sw_scheme* schemes
                    sw_result* out, void* stream_ptr) {
     if (!h) return SW_EINVAL;
     h->err.clear();
+    h->last_fwd = h->last_rev = h->last_i32 = 0;
+    h->t_plan = h->t_fwd = h->t_rev = 0.f;
     if (!batch || !schemes) return fail(h, SW_EINVAL, "null batch or schemes");
     if (n_schemes < 1 || n_schemes > SW_MAX_SCHEMES)
         return fail(h, SW_EINVAL, "n_schemes must be 1..%d", SW_MAX_SCHEMES);
@@ -252,121 +353,128 @@ int sw_align_batch(sw_handle* h, const sw_batch* batch, const sw_scheme* schemes
         if (sc.gap_open < 1 || sc.gap_extend < 0 || sc.gap_extend > sc.gap_open || sc.gap_open > 1000000)
             return fail(h, SW_EINVAL, "scheme %d: need 1 <= gap_open <= 1e6 and 0 <= gap_extend <= gap_open", s);
     }
-    h->last_fwd = 0; h->last_i32 = 0; h->last_out = out; h->last_n = P;
-    h->t_plan = h->t_fwd = h->t_rev = 0.f;
     if (P == 0) return SW_OK;
-    if (!batch->q_off || !batch->r_off || !out)
-        return fail(h, SW_EINVAL, "null offsets or output with n_pairs > 0");
+    if (!batch->q_off || !batch->r_off || !batch->queries || !batch->refs || !out)
+        return fail(h, SW_EINVAL, "null device pointer with n_pairs > 0");
     hipStream_t stream = (hipStream_t)stream_ptr;
-    h->last_stream = stream;
     HIP_TRY(h, hipSetDevice(h->device));
     int rc = ensure_pairs(h, P);
     if (rc != SW_OK) return rc;
 
     // substitution tables: [s][b][a] = M_s[a][b]; padding rows/columns score -1
+    ClassifyArgs C;
     for (int s = 0; s < SW_MAX_SCHEMES; ++s) {
         int8_t* T = h->h_mats + s * kMatBytes;
+        int mx = 1;
         for (int b = 0; b < kMatDim; ++b)
             for (int a = 0; a < kMatDim; ++a) {
                 int8_t v = -1;
-                if (s < n_schemes && a < schemes[s].alphabet && b < schemes[s].alphabet)
+                if (s < n_schemes && a < schemes[s].alphabet && b < schemes[s].alphabet) {
                     v = schemes[s].matrix[a * schemes[s].alphabet + b];
+                    mx = std::max(mx, (int)v);
+                }
                 T[b * kMatDim + a] = v;
             }
-    }
-    HIP_TRY(h, hipMemcpyAsync(h->d_mats, h->h_mats, SW_MAX_SCHEMES * kMatBytes, hipMemcpyHostToDevice, stream));
-    HIP_TRY(h, hipMemsetAsync(h->d_small, 0, kSmallInts * 4, stream));
-    HIP_TRY(h, hipMemsetAsync(h->d_cells, 0, 4 * sizeof(unsigned long long), stream));
-
-    const bool timing = h->opt_timing != 0;
-    if (timing) HIP_TRY(h, hipEventRecord(h->ev[0], stream));
-    int32_t* d_flags = h->d_small;
-    int32_t* d_hist = h->d_small + kNumFlags;
-    int32_t* d_maxm = h->d_small + kNumFlags + 64;
-    const int n_bins = (int)h->bins.size();
-    ClassifyArgs C;
-    for (int s = 0; s < SW_MAX_SCHEMES; ++s) {
-        int mx = 1;
-        if (s < n_schemes)
-            for (int k = 0; k < schemes[s].alphabet * schemes[s].alphabet; ++k)
-                mx = std::max(mx, (int)schemes[s].matrix[k]);
         C.max_score[s] = mx;
     }
     // int16 holds every value of a pair when min(n, m) * max_score plus one
     // more substitution score stays below 2^15
     C.i16_limit = h->opt_precision == 32 ? -1 : 32767 - 127;
     C.n_schemes = n_schemes;
-    C.n_bins = n_bins;
-    HIP_TRY(h, launch_classify(batch->q_off, batch->r_off, batch->scheme_id, P, C, h->d_lut,
-                               h->d_keys, h->d_vals, out, d_flags, d_hist, d_maxm, h->d_cells,
-                               stream));
-    size_t tb = h->temp_bytes;
-    HIP_TRY(h, hipcub::DeviceRadixSort::SortPairs(h->d_temp, tb, h->d_keys, h->d_keys2, h->d_vals,
-                                                  h->d_vals2, (int)P, 0, 22, stream));
-    HIP_TRY(h, hipMemcpyAsync(h->h_small, h->d_small, kSmallInts * 4, hipMemcpyDeviceToHost, stream));
-    if (timing) HIP_TRY(h, hipEventRecord(h->ev[1], stream));
-    HIP_TRY(h, hipMemcpyAsync(h->h_cells, h->d_cells, 4 * sizeof(unsigned long long), hipMemcpyDeviceToHost, stream));
-    HIP_TRY(h, hipStreamSynchronize(stream));
-    const int32_t* flags = h->h_small;
-    if (flags[kFlagBadOffsets]) return fail(h, SW_EINVAL, "offsets decrease");
-    if (flags[kFlagBadScheme]) return fail(h, SW_EINVAL, "scheme id out of range");
-    if (flags[kFlagTooLong])
-        return fail(h, SW_ETOOLONG, "a query exceeds %d or a reference exceeds %d residues", SW_MAX_QUERY, SW_MAX_REF);
-    h->last_fwd = (int64_t)h->h_cells[0];
-    if (!batch->queries || !batch->refs) {
-        if (h->last_fwd > 0) return fail(h, SW_EINVAL, "null queries or refs with non-empty sequences");
-    }
+    C.n_bins = (int)h->bins.size();
 
     KParams K;
+    memset(&K, 0, sizeof(K));
     K.queries = batch->queries; K.q_off = batch->q_off; K.refs = batch->refs; K.r_off = batch->r_off;
-    K.scheme_id = batch->scheme_id; K.order = h->d_vals2; K.out = out; K.flags = d_flags;
-    K.mats = h->d_mats; K.validate = (int32_t)h->opt_validate;
+    K.scheme_id = batch->scheme_id; K.order = h->d_order; K.items = h->d_items; K.meta = h->d_meta;
+    K.out = out; K.flags = h->d_small; K.mats = h->d_mats; K.validate = (int32_t)h->opt_validate;
+    K.n_pairs = (int32_t)P;
+    K.max_items = (int32_t)(h->cap_pairs + kMaxBins);
     for (int s = 0; s < SW_MAX_SCHEMES; ++s) {
         const bool v = s < n_schemes;
         K.alphabet[s] = v ? schemes[s].alphabet : 1;
         K.gap_open[s] = v ? schemes[s].gap_open : 1;
         K.gap_extend[s] = v ? schemes[s].gap_extend : 0;
     }
-    const int32_t* hist = h->h_small + kNumFlags;
-    std::vector<int> first(n_bins + 1, 0);
-    for (int b = 0; b < n_bins; ++b) first[b + 1] = first[b] + hist[b];
-    if (timing) HIP_TRY(h, hipEventRecord(h->ev[2], stream));
-    for (int pass = 0; pass < 2; ++pass) {
-        for (int b = 0; b < n_bins; ++b) {
-            if (hist[b] == 0) continue;
-            HIP_TRY(h, launch_pass(h->bins[b], K, first[b], hist[b], pass, stream));
-            if (pass == 0 && h->bins[b].prec == 32) h->last_i32 += hist[b];
+
+    const bool use_graph = h->opt_mode == 1 && h->opt_graph != 0;
+    const bool timing = h->opt_timing != 0 && !use_graph;
+    GraphKey key;
+    memset(&key, 0, sizeof(key));
+    key.queries = batch->queries; key.q_off = batch->q_off; key.refs = batch->refs;
+    key.r_off = batch->r_off; key.scheme_id = batch->scheme_id; key.out = out;
+    key.n_pairs = P;
+    memcpy(key.alphabet, K.alphabet, sizeof(key.alphabet));
+    memcpy(key.gap_open, K.gap_open, sizeof(key.gap_open));
+    memcpy(key.gap_extend, K.gap_extend, sizeof(key.gap_extend));
+    memcpy(key.max_score, C.max_score, sizeof(key.max_score));
+    key.n_schemes = n_schemes; key.validate = (int32_t)h->opt_validate; key.precision = (int32_t)h->opt_precision;
+
+    if (use_graph && h->have_graph && memcmp(&key, &h->gkey, sizeof(key)) == 0) {
+        HIP_TRY(h, hipGraphLaunch(h->gexec, stream));
+    } else {
+        // The graph is captured on the handle's private stream (the caller's
+        // stream may be the null stream, which cannot be captured) and then
+        // launched on the caller's stream.
+        hipStream_t es = use_graph ? h->cap_stream : stream;
+        if (use_graph) {
+            drop_graph(h);
+            HIP_TRY(h, hipStreamBeginCapture(es, hipStreamCaptureModeThreadLocal));
         }
-        if (timing) HIP_TRY(h, hipEventRecord(h->ev[3 + pass], stream));
+        int erc = SW_OK;
+        do {
+            if (timing && hipEventRecord(h->ev[0], es) != hipSuccess) { erc = fail(h, SW_EDEVICE, "event"); break; }
+            if (hipMemcpyAsync(h->d_mats, h->h_mats, SW_MAX_SCHEMES * kMatBytes, hipMemcpyHostToDevice, es) !=
+                hipSuccess) { erc = fail(h, SW_EDEVICE, "matrix upload failed"); break; }
+            if (launch_reset(h->d_small, kSmallInts, es) != hipSuccess) { erc = fail(h, SW_EDEVICE, "reset"); break; }
+            erc = enqueue_pass(h, K, C, P, 0, es, timing);
+            if (erc != SW_OK) break;
+            erc = enqueue_pass(h, K, C, P, 1, es, timing);
+        } while (0);
+        if (use_graph) {
+            hipGraph_t g = nullptr;
+            hipError_t ce = hipStreamEndCapture(es, &g);
+            if (erc != SW_OK) { if (g) (void)hipGraphDestroy(g); return erc; }
+            if (ce != hipSuccess) return fail(h, SW_EDEVICE, "graph capture failed: %s", hipGetErrorString(ce));
+            h->graph = g;
+            HIP_TRY(h, hipGraphInstantiate(&h->gexec, h->graph, nullptr, nullptr, 0));
+            h->gkey = key;
+            h->have_graph = true;
+            HIP_TRY(h, hipGraphLaunch(h->gexec, stream));
+        } else if (erc != SW_OK) {
+            return erc;
+        }
     }
-    HIP_TRY(h, hipMemcpyAsync(h->h_small, h->d_small, kNumFlags * 4, hipMemcpyDeviceToHost, stream));
+    HIP_TRY(h, hipMemcpyAsync(h->h_small, h->d_small, kSmallInts * 4, hipMemcpyDeviceToHost, stream));
     HIP_TRY(h, hipStreamSynchronize(stream));
+    const int32_t* flags = h->h_small;
+    const unsigned long long* cnt = counters(h->h_small);
+    h->last_fwd = (int64_t)cnt[0];
+    h->last_rev = (int64_t)cnt[1];
+    h->last_i32 = (int64_t)cnt[2];
     if (timing) {
-        HIP_TRY(h, hipEventElapsedTime(&h->t_plan, h->ev[0], h->ev[1]));
-        HIP_TRY(h, hipEventElapsedTime(&h->t_fwd, h->ev[2], h->ev[3]));
+        float a = 0, b = 0;
+        HIP_TRY(h, hipEventElapsedTime(&a, h->ev[0], h->ev[1]));
+        HIP_TRY(h, hipEventElapsedTime(&h->t_fwd, h->ev[1], h->ev[2]));
+        HIP_TRY(h, hipEventElapsedTime(&b, h->ev[2], h->ev[3]));
         HIP_TRY(h, hipEventElapsedTime(&h->t_rev, h->ev[3], h->ev[4]));
+        h->t_plan = a + b;
     }
+    if (flags[kFlagBadOffsets]) return fail(h, SW_EINVAL, "offsets decrease");
+    if (flags[kFlagBadScheme]) return fail(h, SW_EINVAL, "scheme id out of range");
+    if (flags[kFlagTooLong])
+        return fail(h, SW_ETOOLONG, "a query exceeds %d or a reference exceeds %d residues", SW_MAX_QUERY, SW_MAX_REF);
     if (flags[kFlagBadResidue]) return fail(h, SW_EINVAL, "residue code outside its scheme's alphabet");
     if (flags[kFlagReverseMismatch]) return fail(h, SW_EINTERNAL, "reverse sweep did not reproduce the forward score");
+    if (flags[kFlagInternal]) return fail(h, SW_EINTERNAL, "a planning invariant did not hold");
     return SW_OK;
 }
 
 int sw_last_stats(sw_handle* h, int64_t* fwd_cells, int64_t* rev_cells, int64_t* int32_pairs) {
     if (!h) return SW_EINVAL;
     if (fwd_cells) *fwd_cells = h->last_fwd;
+    if (rev_cells) *rev_cells = h->last_rev;
     if (int32_pairs) *int32_pairs = h->last_i32;
-    if (rev_cells) {
-        *rev_cells = 0;
-        if (h->last_out && h->last_n > 0) {
-            HIP_TRY(h, hipSetDevice(h->device));
-            HIP_TRY(h, hipMemsetAsync(h->d_cells + 1, 0, sizeof(unsigned long long), h->last_stream));
-            HIP_TRY(h, launch_reverse_cells(h->last_out, h->last_n, h->d_cells + 1, h->last_stream));
-            HIP_TRY(h, hipMemcpyAsync(h->h_cells, h->d_cells, 2 * sizeof(unsigned long long),
-                                      hipMemcpyDeviceToHost, h->last_stream));
-            HIP_TRY(h, hipStreamSynchronize(h->last_stream));
-            *rev_cells = (int64_t)h->h_cells[1];
-        }
-    }
     return SW_OK;
 }
 

@@ -1,5 +1,37 @@
-// sw_kernels_i16.hip -- packed 16-bit sweep kernel of libswalign (gfx950).
+// sw_sweep.h -- the forward/reverse sweep of one wavefront work item (gfx950).
 //
+// Hot path: the forward and reverse sweeps of the affine-gap Smith-Waterman
+// (Gotoh) recurrences of Section II-B-1 / Fig. 2, batched over many
+// independent query/reference pairs.
+//
+// Mapping onto CDNA4 (one pair per lane group, anti-diagonal sweep):
+//   * A wavefront (64 lanes) is split into 64/W groups of W lanes (W = 16 or
+//     64).  Each group owns one pair.  Lane l of a group owns query rows
+//     l*R .. l*R+R-1 in registers (H, E and the row's running best), so a
+//     group covers W*R >= n rows in a single sweep.
+//   * At step t lane l computes column j = t - l for its R rows, i.e. the
+//     group sweeps anti-diagonals of lane-blocks.  The value a lane needs from
+//     the row above its block (H and F of the last row of lane l-1 at
+//     column j) was produced by lane l-1 one step earlier and arrives through
+//     a DPP row/wave shift -- the same mechanism for every lane, with no
+//     divergent first-lane path (the lesson of Section V-A).  Lane 0 of a
+//     group receives zeros, the matrix's top boundary.
+//   * The reference of each group is staged in LDS as pre-scaled row offsets
+//     into the LDS substitution matrix, so one LDS byte read per cell gives
+//     M[a_i][b_j].  Columns left of 0 (ramp-up) and right of m (ramp-down)
+//     read a padding code whose score is -1.
+//   * No per-step barrier or warp vote: a wavefront runs in lock-step
+//     (Section V-B), and shared state is initialised once, by the lanes that
+//     use it (Section V-C).
+//
+// Exactness of the padding: E and F are carried clamped at zero
+// (E* = max(E, 0)), which leaves H unchanged because H takes a max with 0.  A
+// padded cell (row >= n or column >= m or < 0) scores at most
+// max(diag - 1, E, F) where diag <= S and E, F <= S - o, so with o >= 1 it is
+// strictly below the pair's best S and never changes S or its first cell;
+// real cells never depend on padded ones (they lie below or to the right).
+//
+// Packed int16 variant (sweep_i16):
 // Same anti-diagonal lane-group sweep as the int32 kernel, but every 32-bit
 // register carries two independent pairs: pair A in the low 16 bits and pair
 // B in the high 16 bits, so one packed VALU instruction (v_pk_*_i16/u16)
@@ -16,10 +48,160 @@
 // Row best per lane is tracked as a 32-bit key (H << 16) | (kColMax - j):
 // an unsigned max keeps the largest H and, among equal H, the smallest
 // column j -- the row-major-first maximum within a row.
+#pragma once
+
 #include "sw_device.h"
 #include "sw_internal.h"
 
 namespace sw {
+
+// LDS reference buffer of one wavefront, sized for the widest layout
+// (four 16-lane groups with two packed pairs each).
+constexpr int kWaveBuf = 4 * 2 * RefStager<16>::kBuf;
+// One sweep (forward or reverse per P.reverse) of the wave item
+// order[first .. first+count), one pair per W-lane group, int32 arithmetic.
+template <int W, int R>
+__device__ __forceinline__ void sweep_i32(const KParams& P, const SchemeLds& S, uint16_t* wbuf,
+                                          int first, int count, int lane) {
+    constexpr int G = 64 / W;
+    using Stager = RefStager<W>;
+    const int reverse = P.reverse;
+    const int g = lane / W;
+    const int l = lane % W;
+
+    const int pair = g < count ? P.order[first + g] : -1;
+    const PairJob J = load_job(P, pair, reverse);
+
+    // wave-uniform step count: longest reference in the wavefront + ramp
+    int mmax = J.m;
+    for (int off = 32; off > 0; off >>= 1) mmax = imax(mmax, __shfl_xor(mmax, off));
+    const int steps = __builtin_amdgcn_readfirstlane(mmax > 0 ? mmax + W - 1 : 0);
+
+    uint16_t* buf = wbuf + g * Stager::kBuf;
+    Stager stage;
+    stage.load(P.refs, J, P.order, 0, l);
+
+    // query rows of this lane (padding code below the query end)
+    int a[R];
+    {
+        int raw[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            int i = l * R + r;
+            i = i < J.n ? i : (J.n > 0 ? J.n - 1 : 0);
+            const uint8_t* p = J.n > 0 ? P.queries + J.qbase + (int64_t)J.dir * i
+                                       : reinterpret_cast<const uint8_t*>(P.order);
+            raw[r] = *p;
+        }
+        const int A = S.alphabet[J.sid];
+        bool bad = false;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const bool inside = l * R + r < J.n;
+            bad |= inside && raw[r] >= A;
+            a[r] = (inside && raw[r] < A) ? raw[r] : kPad;
+        }
+        stage.store(buf, J, A, 0, l, bad);
+        if (bad && P.validate) atomicOr(&P.flags[kFlagBadResidue], 1);
+    }
+    const int A = S.alphabet[J.sid];
+    const int go = S.gap_open[J.sid];
+    const int ge = S.gap_extend[J.sid];
+    wave_lds_sync();
+
+    int H[R], E[R], Hm[R], best[R], bj[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) { H[r] = 0; E[r] = 0; Hm[r] = 0; best[r] = 0; bj[r] = -1; }
+    int Hlast = 0, Flast = 0, Hup_prev = 0;
+    const uint16_t* rbl = buf + W - l;   // rbl[tt] = column t0 + tt - l
+
+    // software pipeline: scores of the current step and the matrix row of
+    // the next step are read one step ahead
+    int sc[R];
+    int bb_next = rbl[1];
+    {
+        const int bb0 = rbl[0];
+#pragma unroll
+        for (int r = 0; r < R; ++r) sc[r] = S.mat[bb0 + a[r]];
+    }
+    bool bad = false;
+    int j = -l;
+    for (int t0 = 0; t0 < steps; t0 += kChunk) {
+        const bool more = t0 + kChunk < steps;
+        if (more) stage.load(P.refs, J, P.order, t0 + kChunk, l);
+        const int tn = __builtin_amdgcn_readfirstlane(steps - t0 < kChunk ? steps - t0 : kChunk);
+        for (int tt = 0; tt < tn; ++tt) {
+            const int bb2 = rbl[tt + 2];
+            int sn[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) sn[r] = S.mat[bb_next + a[r]];
+            const int Hup = shift_in_group<W>(Hlast);
+            const int Fup = shift_in_group<W>(Flast);
+            int diag = Hup_prev;
+            Hup_prev = Hup;
+            int Hmu = sat_sub(Hup, go);
+            int F = Fup;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int en = imax(E[r] - ge, Hm[r]);
+                F = imax(F - ge, Hmu);
+                const int h = imax(imax(diag + sc[r], en), F);
+                diag = H[r];
+                H[r] = h;
+                E[r] = en;
+                Hm[r] = sat_sub(h, go);
+                Hmu = Hm[r];
+                if (h > best[r]) { best[r] = h; bj[r] = j; }
+            }
+            Hlast = H[R - 1];
+            Flast = F;
+#pragma unroll
+            for (int r = 0; r < R; ++r) sc[r] = sn[r];
+            bb_next = bb2;
+            ++j;
+        }
+        if (more) {
+            wave_lds_sync();
+            stage.store(buf, J, A, t0 + kChunk, l, bad);
+            wave_lds_sync();
+            // the two look-ahead reads of the next chunk's first steps were
+            // taken from the old buffer; the new buffer holds the same
+            // columns at entries W-l+0 and W-l+1, so re-read them
+            bb_next = rbl[1];
+            const int bb0 = rbl[0];
+#pragma unroll
+            for (int r = 0; r < R; ++r) sc[r] = S.mat[bb0 + a[r]];
+        }
+    }
+    if (bad && P.validate) atomicOr(&P.flags[kFlagBadResidue], 1);
+
+    // best of this lane in row-major order, then of the group
+    int lb = 0, li = -1, lj = -1;
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        if (best[r] > lb) { lb = best[r]; li = l * R + r; lj = bj[r]; }
+    for (int off = 1; off < W; off <<= 1) {
+        const int ob = __shfl_xor(lb, off);
+        const int oi = __shfl_xor(li, off);
+        const int oj = __shfl_xor(lj, off);
+        if (ob > lb || (ob == lb && oi < li)) { lb = ob; li = oi; lj = oj; }
+    }
+    if (l == 0 && pair >= 0) {
+        if (!reverse) {
+            sw_result res;
+            if (lb > 0) { res.score = lb; res.q_start = -1; res.q_end = li; res.r_start = -1; res.r_end = lj; }
+            else { res.score = 0; res.q_start = res.q_end = res.r_start = res.r_end = -1; }
+            P.out[pair] = res;
+        } else if (J.fwd_score > 0) {
+            if (lb != J.fwd_score) {
+                atomicOr(&P.flags[kFlagReverseMismatch], 1);
+            } else {
+                P.out[pair].q_start = J.fwd_qe - li;
+                P.out[pair].r_start = J.fwd_re - lj;
+            }
+        }
+    }
+}
 
 typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 typedef short s16x2 __attribute__((ext_vector_type(2)));
@@ -48,23 +230,18 @@ __device__ __forceinline__ u16x2 load_scores(const int8_t* mat, int addrA, int a
     return __builtin_bit_cast(u16x2, s);
 }
 
+// One sweep of the wave item order[first .. first+count), two pairs per
+// W-lane group packed into int16 halves.
 template <int W, int R>
-__global__ __launch_bounds__(kBlock) void sw_pass_i16(KParams P, int first, int count,
-                                                      int reverse) {
+__device__ __forceinline__ void sweep_i16(const KParams& P, const SchemeLds& S, uint16_t* wbuf,
+                                          int first, int count, int lane) {
     constexpr int G = 64 / W;
     using Stager = RefStager<W>;
-    __shared__ __attribute__((aligned(16))) SchemeLds S;
-    __shared__ uint16_t refbuf[kWavesPerBlock * G * 2 * Stager::kBuf];
-
-    const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int wave = tid >> 6;
+    const int reverse = P.reverse;
     const int g = lane / W;
     const int l = lane % W;
 
-    load_schemes(S, P, tid);
-
-    const int slot = ((blockIdx.x * kWavesPerBlock + wave) * G + g) * 2;
+    const int slot = g * 2;
     const int pairA = slot < count ? P.order[first + slot] : -1;
     const int pairB = slot + 1 < count ? P.order[first + slot + 1] : -1;
     const PairJob JA = load_job(P, pairA, reverse);
@@ -74,7 +251,7 @@ __global__ __launch_bounds__(kBlock) void sw_pass_i16(KParams P, int first, int 
     for (int off = 32; off > 0; off >>= 1) mmax = imax(mmax, __shfl_xor(mmax, off));
     const int steps = __builtin_amdgcn_readfirstlane(mmax > 0 ? mmax + W - 1 : 0);
 
-    uint16_t* bufA = refbuf + ((wave * G + g) * 2) * Stager::kBuf;
+    uint16_t* bufA = wbuf + (g * 2) * Stager::kBuf;
     uint16_t* bufB = bufA + Stager::kBuf;
     Stager stA, stB;
     stA.load(P.refs, JA, P.order, 0, l);
@@ -96,7 +273,6 @@ __global__ __launch_bounds__(kBlock) void sw_pass_i16(KParams P, int first, int 
             rawA[r] = *pA;
             rawB[r] = *pB;
         }
-        __syncthreads();   // scheme tables
         const int AA = S.alphabet[JA.sid], AB = S.alphabet[JB.sid];
         bool bad = false;
 #pragma unroll
@@ -233,26 +409,6 @@ __global__ __launch_bounds__(kBlock) void sw_pass_i16(KParams P, int first, int 
             }
         }
     }
-}
-
-template <int W, int R>
-static constexpr PassFn pass_i16() { return &sw_pass_i16<W, R>; }
-
-static const ShapeEntry kShapesI16[] = {
-    {16, 16, 2, pass_i16<16, 2>()},   {16, 16, 4, pass_i16<16, 4>()},
-    {16, 16, 6, pass_i16<16, 6>()},   {16, 16, 8, pass_i16<16, 8>()},
-    {16, 16, 10, pass_i16<16, 10>()}, {16, 16, 12, pass_i16<16, 12>()},
-    {16, 16, 14, pass_i16<16, 14>()}, {16, 16, 16, pass_i16<16, 16>()},
-    {16, 64, 6, pass_i16<64, 6>()},   {16, 64, 8, pass_i16<64, 8>()},
-    {16, 64, 10, pass_i16<64, 10>()}, {16, 64, 12, pass_i16<64, 12>()},
-    {16, 64, 14, pass_i16<64, 14>()}, {16, 64, 16, pass_i16<64, 16>()},
-    {16, 64, 20, pass_i16<64, 20>()}, {16, 64, 24, pass_i16<64, 24>()},
-    {16, 64, 28, pass_i16<64, 28>()}, {16, 64, 32, pass_i16<64, 32>()},
-};
-
-const ShapeEntry* shapes_i16(int* n) {
-    *n = (int)(sizeof(kShapesI16) / sizeof(kShapesI16[0]));
-    return kShapesI16;
 }
 
 }  // namespace sw

@@ -97,6 +97,26 @@ def test_edge_lengths(aligner):
     assert_same(run_gpu(aligner, b), O.align_batch(b), b)
 
 
+def test_many_items_per_wave_64_lane_groups(aligner):
+    """Regression: queries of 257-1024 rows run on 64-lane groups; with many
+    more work items than resident wavefronts every wavefront loops over
+    several items (a lane-0-only fetch at the head of that loop was once
+    lowered into an inner loop that never fetched again)."""
+    rng = np.random.default_rng(12)
+    dna = W.dna_scheme()
+    pairs = []
+    for _ in range(6000):
+        n = int(rng.integers(257, 700))
+        q = rng.integers(0, 4, size=n)
+        r = np.concatenate([rng.integers(0, 4, size=int(rng.integers(0, 50))), q,
+                            rng.integers(0, 4, size=int(rng.integers(0, 50)))])
+        pairs.append((q, r))
+    b = W.from_pairs(pairs, [0] * len(pairs), [dna])
+    g = run_gpu(aligner, b)
+    idx = np.arange(0, b.n_pairs, 13)
+    assert_same(g, O.align_batch(b, index=idx), b, idx=idx)
+
+
 def test_all_mismatch_and_empty(aligner):
     dna = W.dna_scheme()
     pairs = [(np.zeros(50, np.uint8), np.ones(70, np.uint8)), (np.zeros(0, np.uint8), np.ones(7, np.uint8)),
@@ -204,3 +224,35 @@ def test_large_scores_route_to_int32(aligner):
     odd = np.arange(1, len(pairs), 2)
     assert np.array_equal(g[odd, 0], g1[odd, 0] * k)
     assert np.array_equal(g[odd, 1:], g1[odd, 1:])
+
+
+def test_plain_persistent_and_graph_modes_agree():
+    """Plain per-bin launches, persistent launches and graph replays give the
+    same bits.  The captured graph is replayed several times, with other
+    eager GPU work and host synchronisation in between, and every replay is
+    checked (graphs must not depend on state left by an earlier replay)."""
+    import torch
+    from paper_2208_12350_amd.binding import Aligner, DeviceBatch
+    b = W.make_workload("mixed", n_pairs=2500, seed=4242)
+    db = DeviceBatch.from_host(b)
+    want = O.align_batch(b)
+    want = np.stack([want[f] for f in FIELDS], axis=1)
+    results = {}
+    for name, opts in (("plain", dict(mode=0, graph=0)), ("persistent", dict(mode=1, graph=0)),
+                       ("graph", dict(mode=1, graph=1))):
+        al = Aligner(0, **opts)
+        try:
+            out = torch.full((b.n_pairs, 5), -7, dtype=torch.int32, device="cuda:0")
+            for rep in range(4 if name == "graph" else 1):
+                out.fill_(-7)
+                al.align(db, out)
+                got = out.cpu().numpy()
+                assert np.array_equal(got, want), (name, rep)
+                # unrelated eager work between replays
+                x = torch.randn(1 << 20, device="cuda:0")
+                torch.cuda.synchronize()
+                assert float(x.abs().sum()) > 0
+            results[name] = al.stats()
+        finally:
+            al.close()
+    assert results["plain"] == results["persistent"] == results["graph"]

@@ -125,6 +125,17 @@ int sw_get_option(sw_handle* h, const char* key, int64_t* value);
 int sw_align_batch(sw_handle* h, const sw_batch* batch, const sw_scheme* schemes,
                    int n_schemes, sw_result* out, void* stream);
 
+/* Same as sw_align_batch for pairs given by explicit spans instead of
+ * prefix offsets: query i is queries[q_beg[i] .. q_end[i]) and reference i is
+ * refs[r_beg[i] .. r_end[i]); spans may overlap and appear in any order, so
+ * pairs can be drawn from a resident pool of sequences.  All pointers are
+ * DEVICE pointers except `schemes`; errors as for sw_align_batch (an end
+ * before its begin is SW_EINVAL). */
+int sw_align_spans(sw_handle* h, const uint8_t* queries, const int64_t* q_beg, const int64_t* q_end,
+                   const uint8_t* refs, const int64_t* r_beg, const int64_t* r_end,
+                   const uint8_t* scheme_id, int64_t n_pairs, const sw_scheme* schemes, int n_schemes,
+                   sw_result* out, void* stream);
+
 /* Statistics of the last sw_align_batch call on this handle: number of
  * forward cells (sum of n*m), reverse cells (sum of (q_end+1)*(r_end+1) over
  * pairs with a positive score) and the number of pairs routed to the int32
@@ -137,6 +148,50 @@ int sw_last_stats(sw_handle* h, int64_t* fwd_cells, int64_t* rev_cells, int64_t*
  * forward / reverse = the forward and reverse sweeps (every launch of each).
  * Any pointer may be NULL. */
 int sw_last_timing(sw_handle* h, float* plan_ms, float* forward_ms, float* reverse_ms);
+
+/* ---- serving: continuous batching over a device-resident pool ----------
+ *
+ * A server owns a device memory pool of `pool_bytes` (the admission budget),
+ * `slots` worker streams (1..16) and a copy of the schemes.  Requests are
+ * batches of pairs given as HOST arrays (same layout as sw_batch); submit
+ * checks them, stages a copy (the caller may free its arrays on return) and
+ * queues them.  An admission thread moves queued requests, first in first
+ * out, into the pool as soon as it has room; each free slot then takes every
+ * admitted request that fits `max_batch_pairs`, aligns them as one batch on
+ * its own stream, hands each request its results and releases its memory.
+ * Requests that arrive while others run are admitted and merged into the
+ * next batch of the first slot to free up, so work from different requests
+ * overlaps on the device.  Results are identical to aligning each request
+ * alone.  A server may be driven from several host threads. */
+typedef struct sw_server sw_server;
+
+/* Returns NULL on failure (bad scheme, no such device, allocation failure).
+ * `schemes` is a host array, copied. */
+sw_server* sw_server_create(int device, const sw_scheme* schemes, int n_schemes, int64_t pool_bytes,
+                            int slots, int64_t max_batch_pairs, const char* tuning);
+
+/* Stops the workers (after the batches already running) and frees the pool;
+ * requests not yet completed are dropped. */
+void sw_server_destroy(sw_server* s);
+const char* sw_server_last_error(sw_server* s);
+
+/* Queue a request.  Errors (the request is then not queued): SW_EINVAL (bad
+ * offsets, residue outside its scheme's alphabet, scheme id out of range,
+ * more pairs than max_batch_pairs), SW_ETOOLONG, SW_ENOMEM (the request alone
+ * needs more than the whole pool).  On success *ticket identifies it. */
+int sw_server_submit(sw_server* s, const uint8_t* queries, const int64_t* q_off, const uint8_t* refs,
+                     const int64_t* r_off, const uint8_t* scheme_id, int64_t n_pairs, uint64_t* ticket);
+
+/* Collect a request: SW_PENDING if not finished (and wait == 0); otherwise
+ * its status, with n_pairs results copied to the HOST array `out` and the
+ * time from submit to completion in *latency_ms.  A collected ticket is
+ * forgotten. */
+int sw_server_poll(sw_server* s, uint64_t ticket, sw_result* out, int wait, double* latency_ms);
+
+/* Peak pool bytes in use so far, pool capacity, requests completed, batches
+ * launched and pairs aligned.  Any pointer may be NULL. */
+int sw_server_stats(sw_server* s, int64_t* pool_peak_bytes, int64_t* pool_capacity, int64_t* requests_done,
+                    int64_t* batches, int64_t* pairs_done);
 
 #ifdef __cplusplus
 }

@@ -33,7 +33,9 @@ _ERRNAMES = {SW_EINVAL: "SW_EINVAL", SW_ENOMEM: "SW_ENOMEM", SW_ETOOLONG: "SW_ET
              SW_EDEVICE: "SW_EDEVICE", SW_EINTERNAL: "SW_EINTERNAL"}
 
 EXPORTED = ("sw_create", "sw_destroy", "sw_last_error", "sw_set_option", "sw_get_option",
-            "sw_align_batch", "sw_last_stats", "sw_last_timing")
+            "sw_align_batch", "sw_align_spans", "sw_last_stats", "sw_last_timing",
+            "sw_server_create", "sw_server_destroy", "sw_server_last_error", "sw_server_submit",
+            "sw_server_poll", "sw_server_stats")
 
 
 class sw_result(ctypes.Structure):
@@ -82,10 +84,28 @@ def load_library(path: str = LIB_PATH):
     lib.sw_align_batch.restype = ctypes.c_int
     lib.sw_align_batch.argtypes = [ctypes.c_void_p, ctypes.POINTER(sw_batch), ctypes.POINTER(sw_scheme),
                                    ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
+    lib.sw_align_spans.restype = ctypes.c_int
+    lib.sw_align_spans.argtypes = [ctypes.c_void_p] + [ctypes.c_void_p] * 7 + [ctypes.c_int64, ctypes.POINTER(sw_scheme),
+                                                                             ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
     lib.sw_last_stats.restype = ctypes.c_int
     lib.sw_last_stats.argtypes = [ctypes.c_void_p] + [ctypes.POINTER(ctypes.c_int64)] * 3
     lib.sw_last_timing.restype = ctypes.c_int
     lib.sw_last_timing.argtypes = [ctypes.c_void_p] + [ctypes.POINTER(ctypes.c_float)] * 3
+    lib.sw_server_create.restype = ctypes.c_void_p
+    lib.sw_server_create.argtypes = [ctypes.c_int, ctypes.POINTER(sw_scheme), ctypes.c_int, ctypes.c_int64,
+                                     ctypes.c_int, ctypes.c_int64, ctypes.c_char_p]
+    lib.sw_server_destroy.restype = None
+    lib.sw_server_destroy.argtypes = [ctypes.c_void_p]
+    lib.sw_server_last_error.restype = ctypes.c_char_p
+    lib.sw_server_last_error.argtypes = [ctypes.c_void_p]
+    lib.sw_server_submit.restype = ctypes.c_int
+    lib.sw_server_submit.argtypes = [ctypes.c_void_p] + [ctypes.c_void_p] * 5 + [ctypes.c_int64,
+                                                                                ctypes.POINTER(ctypes.c_uint64)]
+    lib.sw_server_poll.restype = ctypes.c_int
+    lib.sw_server_poll.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_int,
+                                   ctypes.POINTER(ctypes.c_double)]
+    lib.sw_server_stats.restype = ctypes.c_int
+    lib.sw_server_stats.argtypes = [ctypes.c_void_p] + [ctypes.POINTER(ctypes.c_int64)] * 5
     _lib = lib
     return lib
 
@@ -126,6 +146,13 @@ def sw_get_option(h: int, key: str) -> int:
 def sw_align_batch(h: int, batch: sw_batch, schemes, n_schemes: int, out_ptr: int, stream_ptr) -> int:
     """Raw call; returns the status code (does not raise)."""
     return load_library().sw_align_batch(h, ctypes.byref(batch), schemes, n_schemes, out_ptr, stream_ptr)
+
+
+def sw_align_spans(h: int, queries, q_beg, q_end, refs, r_beg, r_end, scheme_id, n_pairs: int, schemes,
+                   n_schemes: int, out_ptr, stream_ptr) -> int:
+    """Raw call with device pointers; returns the status code."""
+    return load_library().sw_align_spans(h, queries, q_beg, q_end, refs, r_beg, r_end, scheme_id, n_pairs,
+                                         schemes, n_schemes, out_ptr, stream_ptr)
 
 
 def sw_last_stats(h: int):
@@ -241,3 +268,70 @@ class Aligner:
 
     def timing(self):
         return sw_last_timing(self.h)
+
+
+class Server:
+    """Continuous-batching alignment server (sw_server_*).  Requests are
+    workloads.Batch objects (host arrays); results come back as int32
+    arrays [n_pairs, 5]."""
+
+    def __init__(self, schemes, device: int = 0, pool_bytes: int = 16 << 30, slots: int = 3,
+                 max_batch_pairs: int = 1 << 20, tuning: Optional[str] = None):
+        lib = load_library()
+        self._arr, self._keep = make_schemes(schemes)
+        self.n_schemes = len(schemes)
+        self.s = lib.sw_server_create(device, self._arr, len(schemes), int(pool_bytes), int(slots),
+                                      int(max_batch_pairs), tuning.encode() if tuning else None)
+        if not self.s:
+            raise RuntimeError("sw_server_create failed")
+
+    def close(self):
+        if self.s:
+            load_library().sw_server_destroy(self.s)
+            self.s = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _err(self):
+        return load_library().sw_server_last_error(self.s).decode(errors="replace")
+
+    def submit(self, batch) -> int:
+        """Queue a workloads.Batch whose scheme ids index this server's schemes."""
+        lib = load_library()
+        q = np.ascontiguousarray(batch.queries, np.uint8)
+        r = np.ascontiguousarray(batch.refs, np.uint8)
+        qo = np.ascontiguousarray(batch.q_off, np.int64)
+        ro = np.ascontiguousarray(batch.r_off, np.int64)
+        sid = np.ascontiguousarray(batch.scheme_id, np.uint8)
+        t = ctypes.c_uint64(0)
+        rc = lib.sw_server_submit(self.s, q.ctypes.data if q.size else None, qo.ctypes.data,
+                                  r.ctypes.data if r.size else None, ro.ctypes.data,
+                                  sid.ctypes.data if sid.size else None, batch.n_pairs, ctypes.byref(t))
+        if rc != SW_OK:
+            raise SwError(rc, self._err())
+        self._sizes = getattr(self, "_sizes", {})
+        self._sizes[int(t.value)] = batch.n_pairs
+        return int(t.value)
+
+    def poll(self, ticket: int, wait: bool = True):
+        """(results int32 [n, 5], latency_ms) or None if still pending."""
+        n = self._sizes.get(ticket, 0)
+        out = np.zeros((max(n, 1), 5), np.int32)
+        lat = ctypes.c_double(0)
+        rc = load_library().sw_server_poll(self.s, ticket, out.ctypes.data, 1 if wait else 0, ctypes.byref(lat))
+        if rc == SW_PENDING:
+            return None
+        self._sizes.pop(ticket, None)
+        if rc != SW_OK:
+            raise SwError(rc, self._err())
+        return out[:n], float(lat.value)
+
+    def stats(self):
+        vals = [ctypes.c_int64(0) for _ in range(5)]
+        load_library().sw_server_stats(self.s, *[ctypes.byref(v) for v in vals])
+        keys = ("pool_peak_bytes", "pool_capacity", "requests_done", "batches", "pairs_done")
+        return {k: int(v.value) for k, v in zip(keys, vals)}

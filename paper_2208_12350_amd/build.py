@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libswalign.so")
-SOURCES = ["sw_plan.hip", "sw_queue_i16.hip", "sw_queue_i32.hip", "sw_runtime.hip"]
+SOURCES = ["sw_plan.hip", "sw_queue_i16.hip", "sw_queue_i32.hip", "sw_runtime.hip", "sw_server.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950",

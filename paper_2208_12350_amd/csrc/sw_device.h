@@ -47,8 +47,8 @@ __device__ __forceinline__ PairJob load_job(const KParams& P, int pair, int reve
         return J;
     }
     J.sid = P.scheme_id ? (int)P.scheme_id[pair] : 0;
-    const int64_t q0 = P.q_off[pair], q1 = P.q_off[pair + 1];
-    const int64_t r0 = P.r_off[pair], r1 = P.r_off[pair + 1];
+    const int64_t q0 = P.q_beg[pair], q1 = P.q_end[pair];
+    const int64_t r0 = P.r_beg[pair], r1 = P.r_end[pair];
     if (!reverse) {
         J.qbase = q0; J.rbase = r0;
         J.n = (int)(q1 - q0); J.m = (int)(r1 - r0);

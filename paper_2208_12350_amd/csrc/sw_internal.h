@@ -67,9 +67,11 @@ enum : int {
 // Arguments shared by every sweep launch.
 struct KParams {
     const uint8_t* queries;
-    const int64_t* q_off;
+    const int64_t* q_beg;        // query i is queries[q_beg[i] .. q_end[i])
+    const int64_t* q_end;
     const uint8_t* refs;
-    const int64_t* r_off;
+    const int64_t* r_beg;        // reference i is refs[r_beg[i] .. r_end[i])
+    const int64_t* r_end;
     const uint8_t* scheme_id;    // nullable
     const int32_t* order;        // pair ids grouped by bin, longest references first
     const WorkItem* items;

@@ -38,8 +38,8 @@ __global__ void sw_classify_kernel(KParams P, ClassifyArgs C, const int8_t* lut,
         int s = 0;
         bool ok = false;
         if (!P.reverse) {
-            n = P.q_off[i + 1] - P.q_off[i];
-            m = P.r_off[i + 1] - P.r_off[i];
+            n = P.q_end[i] - P.q_beg[i];
+            m = P.r_end[i] - P.r_beg[i];
             s = P.scheme_id ? (int)P.scheme_id[i] : 0;
             if (n < 0 || m < 0) atomicOr(&P.flags[kFlagBadOffsets], 1);
             else if (s >= C.n_schemes) atomicOr(&P.flags[kFlagBadScheme], 1);
@@ -55,8 +55,8 @@ __global__ void sw_classify_kernel(KParams P, ClassifyArgs C, const int8_t* lut,
             // end; an end outside the pair would be an internal error
             const sw_result r = P.out[i];
             if (r.score > 0) {
-                const int64_t n0 = P.q_off[i + 1] - P.q_off[i];
-                const int64_t m0 = P.r_off[i + 1] - P.r_off[i];
+                const int64_t n0 = P.q_end[i] - P.q_beg[i];
+                const int64_t m0 = P.r_end[i] - P.r_beg[i];
                 n = (int64_t)r.q_end + 1;
                 m = (int64_t)r.r_end + 1;
                 s = P.scheme_id ? (int)P.scheme_id[i] : 0;

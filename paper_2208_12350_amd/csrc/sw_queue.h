@@ -27,16 +27,19 @@ __global__ __launch_bounds__(kBlock) void sw_queue_kernel(KParams P) {
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    load_schemes(L, P, tid);
-    __syncthreads();
+    // the range is read first: a launch for an empty bin (the host does not
+    // know which bins are empty) costs its workgroups two loads and an exit
     int lo = __atomic_load_n(&P.meta[P.lo_idx], __ATOMIC_RELAXED);
     int hi = __atomic_load_n(&P.meta[P.hi_idx], __ATOMIC_RELAXED);
     lo = __builtin_amdgcn_readfirstlane(lo);
     hi = __builtin_amdgcn_readfirstlane(hi);
+    if (lo == hi) return;
     if (lo < 0 || hi > P.max_items || lo > hi) {
         if (tid == 0) atomicOr(&P.flags[kFlagInternal], 1);
         return;
     }
+    load_schemes(L, P, tid);
+    __syncthreads();
     uint16_t* wbuf = wbufs + wave * kWaveBuf;
     // The loop has no lane-divergent branch: every lane takes part in the
     // fetch (only lane 0 adds 1, so each wavefront claims exactly one item

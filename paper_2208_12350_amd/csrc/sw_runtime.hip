@@ -34,9 +34,11 @@ constexpr int kSmallInts = 64;   // flags [0, kNumFlags) | 64-bit counters from 
 // Everything a captured graph depends on besides device memory contents.
 struct GraphKey {
     const void* queries;
-    const void* q_off;
+    const void* q_beg;
+    const void* q_end;
     const void* refs;
-    const void* r_off;
+    const void* r_beg;
+    const void* r_end;
     const void* scheme_id;
     const void* out;
     int64_t n_pairs;
@@ -84,6 +86,9 @@ struct sw_handle {
     float t_plan = 0.f, t_fwd = 0.f, t_rev = 0.f;
 
     hipStream_t cap_stream = nullptr;   // private stream the graph is captured on
+    static constexpr int kForks = 4;    // persistent mode spreads bins over these streams
+    hipStream_t fork[kForks] = {nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t fork_ev[kForks + 1] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     GraphKey gkey;
@@ -194,6 +199,13 @@ static int enqueue_pass(sw_handle* h, KParams K, const ClassifyArgs& C, int64_t 
     HIP_TRY(h, launch_items(h->d_meta, h->d_bins, n_bins, P, h->d_items, stream));
     if (h->opt_mode == 1) {
         if (timing) HIP_TRY(h, hipEventRecord(h->ev[pass == 0 ? 1 : 3], stream));
+        // Bins go round-robin, longest first, to kForks streams forked from
+        // `stream` and joined back into it: the bins' launch tails, and the
+        // launches of bins that turn out to be empty, overlap with the work
+        // of the other streams.
+        HIP_TRY(h, hipEventRecord(h->fork_ev[sw_handle::kForks], stream));
+        for (int f = 0; f < sw_handle::kForks; ++f)
+            HIP_TRY(h, hipStreamWaitEvent(h->fork[f], h->fork_ev[sw_handle::kForks], 0));
         for (int b = 0; b < n_bins; ++b) {
             const BinInfo& e = h->bins[b];
             // no bin can hold more than P / ppw items, one wavefront each
@@ -202,8 +214,13 @@ static int enqueue_pass(sw_handle* h, KParams K, const ClassifyArgs& C, int64_t 
             K.lo_idx = kMetaItemFirst + b;
             K.hi_idx = kMetaItemFirst + b + 1;
             K.head_idx = kMetaHeads + b;
-            hipLaunchKernelGGL(shape_kernel(e.prec, e.W, e.R), dim3(blocks), dim3(kBlock), 0, stream, K);
+            hipLaunchKernelGGL(shape_kernel(e.prec, e.W, e.R), dim3(blocks), dim3(kBlock), 0,
+                               h->fork[b % sw_handle::kForks], K);
             HIP_TRY(h, hipGetLastError());
+        }
+        for (int f = 0; f < sw_handle::kForks; ++f) {
+            HIP_TRY(h, hipEventRecord(h->fork_ev[f], h->fork[f]));
+            HIP_TRY(h, hipStreamWaitEvent(stream, h->fork_ev[f], 0));
         }
     } else {
         HIP_TRY(h, hipMemcpyAsync(h->h_meta, h->d_meta, kMetaSize * 4, hipMemcpyDeviceToHost, stream));
@@ -249,6 +266,10 @@ sw_handle* sw_create(int device, const char* tuning) {
          hipHostMalloc(&h->h_meta, kMetaSize * 4, hipHostMallocDefault) == hipSuccess;
     for (int k = 0; ok && k < 5; ++k) ok = hipEventCreate(&h->ev[k]) == hipSuccess;
     if (ok) ok = hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) == hipSuccess;
+    for (int f = 0; ok && f < sw_handle::kForks; ++f)
+        ok = hipStreamCreateWithFlags(&h->fork[f], hipStreamNonBlocking) == hipSuccess;
+    for (int f = 0; ok && f <= sw_handle::kForks; ++f)
+        ok = hipEventCreateWithFlags(&h->fork_ev[f], hipEventDisableTiming) == hipSuccess;
     if (ok) ok = hipMemcpy(h->d_lut, h->lut.data(), kLutEntries, hipMemcpyHostToDevice) == hipSuccess;
     if (ok) ok = hipMemcpy(h->d_bins, h->bins.data(), h->bins.size() * sizeof(BinInfo),
                            hipMemcpyHostToDevice) == hipSuccess;
@@ -294,6 +315,10 @@ void sw_destroy(sw_handle* h) {
     for (int k = 0; k < 5; ++k)
         if (h->ev[k]) (void)hipEventDestroy(h->ev[k]);
     if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+    for (int f = 0; f < sw_handle::kForks; ++f)
+        if (h->fork[f]) (void)hipStreamDestroy(h->fork[f]);
+    for (int f = 0; f <= sw_handle::kForks; ++f)
+        if (h->fork_ev[f]) (void)hipEventDestroy(h->fork_ev[f]);
     delete h;
 }
 
@@ -333,16 +358,23 @@ int sw_get_option(sw_handle* h, const char* key, int64_t* value) {
     return SW_OK;
 }
 
-int sw_align_batch(sw_handle* h, const sw_batch* batch, const sw_scheme* schemes, int n_schemes,
-                   sw_result* out, void* stream_ptr) {
+}  // extern "C"
+
+// Align pairs given as spans: query i is queries[q_beg[i] .. q_end[i]),
+// reference i is refs[r_beg[i] .. r_end[i]).  Shared by sw_align_batch
+// (spans from prefix offsets) and sw_align_spans.
+static int align_spans(sw_handle* h, const uint8_t* queries, const int64_t* q_beg, const int64_t* q_end,
+                       const uint8_t* refs, const int64_t* r_beg, const int64_t* r_end,
+                       const uint8_t* scheme_id, int64_t n_pairs, const sw_scheme* schemes,
+                       int n_schemes, sw_result* out, void* stream_ptr) {
     if (!h) return SW_EINVAL;
     h->err.clear();
     h->last_fwd = h->last_rev = h->last_i32 = 0;
     h->t_plan = h->t_fwd = h->t_rev = 0.f;
-    if (!batch || !schemes) return fail(h, SW_EINVAL, "null batch or schemes");
+    if (!schemes) return fail(h, SW_EINVAL, "null schemes");
     if (n_schemes < 1 || n_schemes > SW_MAX_SCHEMES)
         return fail(h, SW_EINVAL, "n_schemes must be 1..%d", SW_MAX_SCHEMES);
-    const int64_t P = batch->n_pairs;
+    const int64_t P = n_pairs;
     if (P < 0) return fail(h, SW_EINVAL, "negative n_pairs");
     if (P > (int64_t)0x7FFFFFFF) return fail(h, SW_EINVAL, "more than 2^31-1 pairs in one batch");
     for (int s = 0; s < n_schemes; ++s) {
@@ -354,7 +386,7 @@ int sw_align_batch(sw_handle* h, const sw_batch* batch, const sw_scheme* schemes
             return fail(h, SW_EINVAL, "scheme %d: need 1 <= gap_open <= 1e6 and 0 <= gap_extend <= gap_open", s);
     }
     if (P == 0) return SW_OK;
-    if (!batch->q_off || !batch->r_off || !batch->queries || !batch->refs || !out)
+    if (!q_beg || !q_end || !r_beg || !r_end || !queries || !refs || !out)
         return fail(h, SW_EINVAL, "null device pointer with n_pairs > 0");
     hipStream_t stream = (hipStream_t)stream_ptr;
     HIP_TRY(h, hipSetDevice(h->device));
@@ -385,8 +417,8 @@ int sw_align_batch(sw_handle* h, const sw_batch* batch, const sw_scheme* schemes
 
     KParams K;
     memset(&K, 0, sizeof(K));
-    K.queries = batch->queries; K.q_off = batch->q_off; K.refs = batch->refs; K.r_off = batch->r_off;
-    K.scheme_id = batch->scheme_id; K.order = h->d_order; K.items = h->d_items; K.meta = h->d_meta;
+    K.queries = queries; K.q_beg = q_beg; K.q_end = q_end; K.refs = refs; K.r_beg = r_beg; K.r_end = r_end;
+    K.scheme_id = scheme_id; K.order = h->d_order; K.items = h->d_items; K.meta = h->d_meta;
     K.out = out; K.flags = h->d_small; K.mats = h->d_mats; K.validate = (int32_t)h->opt_validate;
     K.n_pairs = (int32_t)P;
     K.max_items = (int32_t)(h->cap_pairs + kMaxBins);
@@ -401,8 +433,8 @@ int sw_align_batch(sw_handle* h, const sw_batch* batch, const sw_scheme* schemes
     const bool timing = h->opt_timing != 0 && !use_graph;
     GraphKey key;
     memset(&key, 0, sizeof(key));
-    key.queries = batch->queries; key.q_off = batch->q_off; key.refs = batch->refs;
-    key.r_off = batch->r_off; key.scheme_id = batch->scheme_id; key.out = out;
+    key.queries = queries; key.q_beg = q_beg; key.q_end = q_end; key.refs = refs;
+    key.r_beg = r_beg; key.r_end = r_end; key.scheme_id = scheme_id; key.out = out;
     key.n_pairs = P;
     memcpy(key.alphabet, K.alphabet, sizeof(key.alphabet));
     memcpy(key.gap_open, K.gap_open, sizeof(key.gap_open));
@@ -468,6 +500,26 @@ int sw_align_batch(sw_handle* h, const sw_batch* batch, const sw_scheme* schemes
     if (flags[kFlagReverseMismatch]) return fail(h, SW_EINTERNAL, "reverse sweep did not reproduce the forward score");
     if (flags[kFlagInternal]) return fail(h, SW_EINTERNAL, "a planning invariant did not hold");
     return SW_OK;
+}
+
+extern "C" {
+
+int sw_align_batch(sw_handle* h, const sw_batch* batch, const sw_scheme* schemes, int n_schemes,
+                   sw_result* out, void* stream_ptr) {
+    if (!h) return SW_EINVAL;
+    if (!batch) return fail(h, SW_EINVAL, "null batch");
+    const int64_t* qo = batch->q_off;
+    const int64_t* ro = batch->r_off;
+    return align_spans(h, batch->queries, qo, qo ? qo + 1 : nullptr, batch->refs, ro, ro ? ro + 1 : nullptr,
+                       batch->scheme_id, batch->n_pairs, schemes, n_schemes, out, stream_ptr);
+}
+
+int sw_align_spans(sw_handle* h, const uint8_t* queries, const int64_t* q_beg, const int64_t* q_end,
+                   const uint8_t* refs, const int64_t* r_beg, const int64_t* r_end,
+                   const uint8_t* scheme_id, int64_t n_pairs, const sw_scheme* schemes, int n_schemes,
+                   sw_result* out, void* stream) {
+    return align_spans(h, queries, q_beg, q_end, refs, r_beg, r_end, scheme_id, n_pairs, schemes, n_schemes,
+                       out, stream);
 }
 
 int sw_last_stats(sw_handle* h, int64_t* fwd_cells, int64_t* rev_cells, int64_t* int32_pairs) {

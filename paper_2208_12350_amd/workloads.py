@@ -275,16 +275,20 @@ def mixed_lengths(rng, n):
     return q, r
 
 
-def make_workload(name: str, n_pairs: Optional[int] = None, seed: Optional[int] = None) -> Batch:
+def make_workload(name: str, n_pairs: Optional[int] = None, seed: Optional[int] = None,
+                  scheme_seed: Optional[int] = None) -> Batch:
     """Generate one of the named workloads, optionally truncated to the first
     ``n_pairs`` draws (the draw order is fixed by the seed, so a smaller
-    n_pairs gives a prefix-like sample of the same distribution)."""
+    n_pairs gives a prefix-like sample of the same distribution).  The protein
+    matrix and residue frequencies are drawn from ``scheme_seed`` (default:
+    the same seed), so many batches can share one scoring scheme."""
     idx = WORKLOADS.index(name)
     seed = BASE_SEED + idx if seed is None else seed
+    scheme_seed = seed if scheme_seed is None else scheme_seed
     rng = np.random.default_rng(seed)
     dna = dna_scheme()
-    prot = protein_scheme(seed)
-    pi_prot = protein_frequencies(seed)
+    prot = protein_scheme(scheme_seed)
+    pi_prot = protein_frequencies(scheme_seed)
 
     if name == "dna_small":
         P = 1000 if n_pairs is None else n_pairs
@@ -376,7 +380,8 @@ def serving_stream(offered_cells_per_ms: float, n_requests: int, seed: Optional[
     rng = np.random.default_rng(base)
     reqs = []
     sizes = rng.integers(1, max_pairs + 1, size=n_requests)
-    batches = [make_workload("mixed", n_pairs=int(s), seed=base * 1000 + k) for k, s in enumerate(sizes)]
+    batches = [make_workload("mixed", n_pairs=int(s), seed=base * 1000 + k, scheme_seed=base)
+               for k, s in enumerate(sizes)]
     mean_cells = float(np.mean([b.cells() for b in batches]))
     lam = offered_cells_per_ms * 1e3 / mean_cells  # requests per second
     gaps = rng.exponential(1.0 / lam, size=n_requests)

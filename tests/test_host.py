@@ -40,3 +40,15 @@ def test_null_handle_is_rejected():
     assert lib.sw_set_option(None, b"mode", 0) == B.SW_EINVAL
     assert lib.sw_last_error(None) == b"null handle"
     lib.sw_destroy(None)
+
+
+def test_pool_allocator_native(tmp_path):
+    """Device-pool bookkeeping used for serving admission, tested on the host."""
+    import subprocess
+    src = os.path.join(ROOT, "tests", "native", "pool_test.cpp")
+    exe = str(tmp_path / "pool_test")
+    subprocess.check_call(["g++", "-O1", "-std=c++17", "-I", os.path.join(ROOT, "paper_2208_12350_amd", "csrc"),
+                           src, "-o", exe])
+    out = subprocess.run([exe], capture_output=True, text=True, timeout=120)
+    assert out.returncode == 0, out.stdout + out.stderr
+    assert "pool ok" in out.stdout

@@ -65,6 +65,97 @@ def cpu_baseline(batch, target_s=12.0):
                       "sweeps, %.1f s on %d threads)" % (n1, cells, dt, cores)}
 
 
+def serving_bench(args):
+    """Open-loop serving run: a Poisson stream of requests (each 1-5,000
+    pairs of the mixed draw) at each offered load, submitted to a
+    continuous-batching server with a 16 GiB device pool.  Latency of a
+    request runs from its scheduled arrival to its results being on the
+    host (so a submitter that falls behind is charged to the request)."""
+    import queue
+    import threading
+    import numpy as np
+    from paper_2208_12350_amd import workloads as W
+    from paper_2208_12350_amd.binding import Server
+
+    log("generating %d serving requests ..." % args.serving_requests)
+    t = time.time()
+    bodies = W.serving_requests(args.serving_requests)
+    cells = np.array([b.cells() for b in bodies], dtype=np.float64)
+    mean_cells = float(cells.mean())
+    log("  mean %.3g cells per request (%.1f s)" % (mean_cells, time.time() - t))
+    srv = Server(bodies[0].schemes, 0, pool_bytes=args.pool_gib << 30, slots=args.slots,
+                 max_batch_pairs=args.max_batch_pairs)
+    # warm-up: every slot sees a few batches before anything is timed
+    for b in bodies[:4 * args.slots]:
+        srv.poll(srv.submit(b), wait=True)
+
+    points = []
+    for li, load in enumerate(float(x) for x in args.loads.split(",")):
+        lam = load * 1e6 * 1e3 / mean_cells            # requests per second
+        n = int(np.clip(lam * args.window_s, 40, 500))
+        arrivals = W.poisson_arrivals(n, lam, 2208 + li)
+        which = [k % len(bodies) for k in range(n)]
+        lags = [0.0] * n
+        lat = [0.0] * n
+        done = [0.0] * n
+        handoff = queue.Queue()
+        errors = []
+
+        def collect():
+            for _ in range(n):
+                k, ticket = handoff.get()
+                try:
+                    _, ms = srv.poll(ticket, wait=True)
+                except Exception as e:   # noqa: BLE001 -- reported after the run
+                    errors.append(repr(e))
+                    ms = float("nan")
+                done[k] = time.perf_counter()
+                lat[k] = ms + lags[k] * 1e3
+
+        before = srv.stats()
+        th = threading.Thread(target=collect)
+        th.start()
+        t0 = time.perf_counter()
+        for k in range(n):
+            target = t0 + float(arrivals[k])
+            while True:
+                d = target - time.perf_counter()
+                if d <= 0:
+                    break
+                time.sleep(min(d, 0.001))
+            lags[k] = time.perf_counter() - target
+            handoff.put((k, srv.submit(bodies[which[k]])))
+        th.join()
+        if errors:
+            raise RuntimeError("serving requests failed: %s" % errors[:3])
+        after = srv.stats()
+        span = max(done) - t0
+        total = float(cells[which].sum())
+        batches = after["batches"] - before["batches"]
+        pt = {"offered_mcells_per_ms": load, "requests": n, "offered_gcups": round(load, 3),
+              "sustained_gcups": round(total / span / 1e9, 2), "span_s": round(span, 3),
+              "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
+              "requests_per_batch": round(n / max(1, batches), 2),
+              "submit_lag_p99_ms": round(float(np.percentile(lags, 99)) * 1e3, 3)}
+        log("  load %g M cells/ms: %s" % (load, pt))
+        points.append(pt)
+    st = srv.stats()
+    srv.close()
+    top = points[-1]
+    res = {
+        "metric": "GCUPS, batched affine SW (score+coords), batched vs plain; p50/p99 latency",
+        "value": top["sustained_gcups"], "unit": "GCUPS", "n_gpus": 1, "steps": len(points), "warmup": 4 * args.slots,
+        "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "i16", "data": "synthetic",
+        "config": {"workload": "serving", "distinct_requests": len(bodies), "mean_cells_per_request": int(mean_cells),
+                   "slots": args.slots, "max_batch_pairs": args.max_batch_pairs,
+                   "pool_bytes": args.pool_gib << 30, "pool_peak_bytes": st["pool_peak_bytes"]},
+        "latency_ms": {"p50": top["p50_ms"], "p99": top["p99_ms"]},
+        "serving": points,
+    }
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -73,13 +164,25 @@ def main():
     ap.add_argument("--workload", default="dna_large")
     ap.add_argument("--n-pairs", type=int, default=None, help="truncate the workload (testing only)")
     ap.add_argument("--mode", type=int, default=None, help="0 = per-bin launches, 1 = persistent")
+    ap.add_argument("--streams", type=int, default=4, help="streams the persistent launches spread over")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--loads", default="1,2,5,10,20,50,100,200,500,1000,2000",
+                    help="serving: offered loads in M cells/ms")
+    ap.add_argument("--window-s", type=float, default=6.0, help="serving: seconds of arrivals per load")
+    ap.add_argument("--serving-requests", type=int, default=300, help="serving: distinct request bodies")
+    ap.add_argument("--slots", type=int, default=3, help="serving: slot workers")
+    ap.add_argument("--max-batch-pairs", type=int, default=1 << 18, help="serving: pairs per merged batch")
+    ap.add_argument("--pool-gib", type=int, default=16, help="serving: device pool size")
     args = ap.parse_args()
 
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(pairs are independent; see DESIGN.md for how the work would shard)", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "serving":
+        serving_bench(args)
+        return
 
     import numpy as np
     import torch
@@ -111,14 +214,14 @@ def main():
 
     # headline: persistent work-queue launch, replayed from a captured hipGraph
     mode = 1 if args.mode is None else args.mode
-    al = Aligner(0, mode=mode, graph=1 if mode == 1 else 0)
+    al = Aligner(0, mode=mode, graph=1 if mode == 1 else 0, streams=args.streams)
     elapsed, step_ms = timed(al, args.steps, args.warmup, "mode %d" % mode)
     ref_out = out.clone()
     fwd_cells, rev_cells, i32_pairs = al.stats()
     al.close()
 
-    # same sweeps with HIP events around the phases (no graph), for the roofline
-    alt = Aligner(0, mode=mode, graph=0, timing=1)
+    # same call with HIP events around the phases (no graph replay)
+    alt = Aligner(0, mode=mode, graph=0, timing=1, streams=args.streams)
     plan_ms, fwd_ms, rev_ms = [], [], []
     for k in range(max(3, min(args.steps, 10)) + 1):
         alt.align(db, out)
@@ -127,6 +230,21 @@ def main():
             plan_ms.append(p); fwd_ms.append(f); rev_ms.append(r)
     alt.close()
     assert torch.equal(out, ref_out), "timing run disagrees with the headline run"
+
+    # roofline leg: the sweep launches serialised on one stream, a HIP event
+    # pair around each, cells per launch from the device counters
+    alr = Aligner(0, mode=mode, graph=0, timing=2)
+    per_launch = {}
+    roof_steps = max(3, min(args.steps, 10))
+    for k in range(roof_steps + 1):
+        alr.align(db, out)
+        if k:
+            for e in alr.bin_stats():
+                key = (e["pass"], e["precision"], e["lanes"], e["rows"])
+                acc = per_launch.setdefault(key, [0.0, 0, 0])
+                acc[0] += e["ms"]; acc[1] += e["cells"]; acc[2] += 1
+    alr.close()
+    assert torch.equal(out, ref_out), "roofline run disagrees with the headline run"
 
     # plain per-bin launches on the same data
     plain = None
@@ -139,10 +257,19 @@ def main():
 
     ms_per_step = elapsed * 1e3 / args.steps
     gcups = fwd_cells * args.steps / elapsed / 1e9
-    sweep_ms = float(np.mean(fwd_ms)) + float(np.mean(rev_ms))
     int16 = i32_pairs < batch.n_pairs
-    peak = VALU_INT16X2_TOPS if int16 else VALU_INT32_TOPS
-    achieved = OPS_PER_CELL * (fwd_cells + rev_cells) / (sweep_ms / 1e3) / 1e12
+    # dominant kernel: the (pass, shape) launch with the most device time
+    (dpass, dprec, dlanes, drows), (dms, dcells, dn) = max(per_launch.items(), key=lambda kv: kv[1][0])
+    launch_ms = dms / dn
+    cells_per_launch = dcells / dn
+    peak = VALU_INT16X2_TOPS if dprec == 16 else VALU_INT32_TOPS
+    achieved = OPS_PER_CELL * cells_per_launch / (launch_ms / 1e3) / 1e12
+    # every sweep launch together, each at its own precision's peak
+    fam_ms = sum(v[0] for v in per_launch.values()) / roof_steps
+    fam_ops = OPS_PER_CELL * sum(v[1] for v in per_launch.values()) / roof_steps
+    fam_peak_s = sum(OPS_PER_CELL * v[1] / roof_steps / ((VALU_INT16X2_TOPS if k[1] == 16 else VALU_INT32_TOPS) * 1e12)
+                     for k, v in per_launch.items())
+    kernel_name = "sw::sw_queue_kernel<%d, %d, %d, %s>" % (dprec, dlanes, drows, "true" if dpass else "false")
     res = {
         "metric": "GCUPS, batched affine SW (score+coords), batched vs plain; p50/p99 latency",
         "value": round(gcups, 2),
@@ -158,7 +285,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "pairs": batch.n_pairs, "forward_cells": int(fwd_cells),
                    "reverse_cells": int(rev_cells), "int32_pairs": int(i32_pairs),
-                   "mode": "persistent+graph" if mode == 1 else "plain per-bin launches"},
+                   "mode": "persistent+graph" if mode == 1 else "plain per-bin launches",
+                   "streams": args.streams if mode == 1 else 1},
         "plain_value": plain,
         "latency_ms": {"p50": round(float(np.percentile(step_ms, 50)), 3),
                        "p99": round(float(np.percentile(step_ms, 99)), 3)},
@@ -166,8 +294,10 @@ def main():
                      "reverse": round(float(np.mean(rev_ms)), 3)},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 2),
                      "unit": "Tops/s", "frac": round(achieved / peak, 4), "traffic": None,
-                     "kernel": "forward+reverse sweeps",
-                     "ops_per_cell": OPS_PER_CELL},
+                     "kernel": kernel_name, "launch_ms": round(launch_ms, 4),
+                     "cells_per_launch": int(cells_per_launch), "ops_per_cell": OPS_PER_CELL,
+                     "all_sweeps": {"ms": round(fam_ms, 3), "achieved": round(fam_ops / (fam_ms / 1e3) / 1e12, 3),
+                                    "frac": round(fam_peak_s / (fam_ms / 1e3), 4)}},
     }
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a sample ...")

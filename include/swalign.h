@@ -88,8 +88,10 @@ typedef struct {
 typedef struct sw_handle sw_handle;
 
 /* Create a handle bound to HIP device `device`.  `tuning` is NULL (built-in
- * defaults) or a string of `key=value` pairs separated by ';' or ',' (see
- * sw_set_option for keys).  Returns NULL on failure. */
+ * defaults) or a string of `key=value` pairs separated by ';' or ',': the
+ * keys of sw_set_option, plus "route16" / "route32" whose value is a
+ * routing table "WxR@rows_max/WxR@rows_max/..." (see sw_set_routing).
+ * Returns NULL on failure (including a malformed tuning string). */
 sw_handle* sw_create(int device, const char* tuning);
 
 /* Release the handle and every device buffer it owns.  Waits for its work. */
@@ -105,11 +107,18 @@ const char* sw_last_error(sw_handle* h);
  *   "validate"  1 = check residue codes (default 1); invalid residues make
  *               the call return SW_EINVAL (results of those pairs undefined)
  *   "precision" 0 = automatic routing (default): a pair runs on the packed
- *               int16 path when min(n, m) * (largest matrix score) <= 32640,
- *               which bounds every intermediate value; otherwise on int32.
+ *               int16 path when min(n, m) * (largest matrix score) <= 30592
+ *               and m <= 32000, which bounds every intermediate value;
+ *               otherwise on int32.
  *               32 = force every pair onto the int32 path
  *   "timing"    1 = record HIP events around the phases of each call on the
- *               caller's stream (read back with sw_last_timing)
+ *               caller's stream (read back with sw_last_timing);
+ *               2 = also around every sweep kernel launch, with the
+ *               launches serialised on the caller's stream (read back with
+ *               sw_last_bin_stats).  Timing turns graph replay off.
+ *   "streams"   1..4: persistent mode spreads the bins' kernels over this
+ *               many streams forked from (and joined back into) the
+ *               caller's stream (default 4)
  * Returns SW_OK or SW_EINVAL for an unknown key / bad value. */
 int sw_set_option(sw_handle* h, const char* key, int64_t value);
 int sw_get_option(sw_handle* h, const char* key, int64_t* value);
@@ -149,6 +158,49 @@ int sw_last_stats(sw_handle* h, int64_t* fwd_cells, int64_t* rev_cells, int64_t*
  * Any pointer may be NULL. */
 int sw_last_timing(sw_handle* h, float* plan_ms, float* forward_ms, float* reverse_ms);
 
+/* ---- routing: which sweep shape aligns which query length -------------
+ *
+ * A sweep shape is (lanes, rows): a group of `lanes` lanes (16, 32 or 64)
+ * shares one pair (two pairs packed per register at 16-bit precision), and
+ * each lane holds `rows` consecutive query rows, so a shape covers queries of
+ * up to lanes * rows residues in one sweep of m + lanes - 1 steps.
+ *
+ * sw_shapes lists the compiled shapes into HOST arrays of `capacity`
+ * entries (*n_out = the number of shapes; SW_EINVAL if capacity is short). */
+int sw_shapes(sw_handle* h, int32_t* precision, int32_t* lanes, int32_t* rows, int capacity, int* n_out);
+
+/* Route queries of one precision (16 or 32) by length: entry k sends the
+ * queries of rows_max[k-1]+1 .. rows_max[k] residues (rows_max[-1] = 0) to
+ * shape (lanes[k], rows[k]).  rows_max must increase in steps that are
+ * multiples of 16 and end at SW_MAX_QUERY; each shape must be compiled and
+ * cover its rows (lanes * rows >= rows_max).  n == 0 restores the built-in
+ * routing.  HOST arrays; SW_EINVAL on a malformed table (the routing is then
+ * unchanged).  Results never depend on the routing, only speed does. */
+int sw_set_routing(sw_handle* h, int precision, const int32_t* rows_max, const int32_t* lanes, const int32_t* rows,
+                   int n);
+/* The current routing of one precision, in the same form (merged runs). */
+int sw_get_routing(sw_handle* h, int precision, int32_t* rows_max, int32_t* lanes, int32_t* rows, int capacity,
+                   int* n_out);
+
+/* One sweep kernel launch of the last call: the bin of pairs of one shape
+ * (precision, lanes per pair group, query rows per lane) in one pass. */
+typedef struct sw_bin_stat {
+    int32_t pass;        /* 0 forward, 1 reverse */
+    int32_t precision;   /* 16 (two pairs packed per register) or 32 */
+    int32_t lanes;       /* lanes that share one pair */
+    int32_t rows;        /* query rows held by each lane */
+    int64_t pairs;       /* pairs the bin held in this pass */
+    int64_t cells;       /* DP cells of those pairs in this pass */
+    float ms;            /* kernel time (HIP events) with "timing" = 2, else 0 */
+    int32_t reserved;
+} sw_bin_stat;
+
+/* Per-launch statistics of the last call on this handle: writes up to
+ * `capacity` entries (every bin of the forward pass, then of the reverse
+ * pass) into the HOST array `out` and their number into *n_out.  Returns
+ * SW_EINVAL (with *n_out set to the number needed) if capacity is too small. */
+int sw_last_bin_stats(sw_handle* h, sw_bin_stat* out, int capacity, int* n_out);
+
 /* ---- serving: continuous batching over a device-resident pool ----------
  *
  * A server owns a device memory pool of `pool_bytes` (the admission budget),
@@ -184,7 +236,8 @@ int sw_server_submit(sw_server* s, const uint8_t* queries, const int64_t* q_off,
 
 /* Collect a request: SW_PENDING if not finished (and wait == 0); otherwise
  * its status, with n_pairs results copied to the HOST array `out` and the
- * time from submit to completion in *latency_ms.  A collected ticket is
+ * time from the submit call's entry (host checks and staging included) to
+ * the results being on the host in *latency_ms.  A collected ticket is
  * forgotten. */
 int sw_server_poll(sw_server* s, uint64_t ticket, sw_result* out, int wait, double* latency_ms);
 

@@ -33,7 +33,8 @@ _ERRNAMES = {SW_EINVAL: "SW_EINVAL", SW_ENOMEM: "SW_ENOMEM", SW_ETOOLONG: "SW_ET
              SW_EDEVICE: "SW_EDEVICE", SW_EINTERNAL: "SW_EINTERNAL"}
 
 EXPORTED = ("sw_create", "sw_destroy", "sw_last_error", "sw_set_option", "sw_get_option",
-            "sw_align_batch", "sw_align_spans", "sw_last_stats", "sw_last_timing",
+            "sw_align_batch", "sw_align_spans", "sw_last_stats", "sw_last_timing", "sw_last_bin_stats",
+            "sw_shapes", "sw_set_routing", "sw_get_routing",
             "sw_server_create", "sw_server_destroy", "sw_server_last_error", "sw_server_submit",
             "sw_server_poll", "sw_server_stats")
 
@@ -51,6 +52,12 @@ class sw_scheme(ctypes.Structure):
 class sw_batch(ctypes.Structure):
     _fields_ = [("queries", ctypes.c_void_p), ("q_off", ctypes.c_void_p), ("refs", ctypes.c_void_p),
                 ("r_off", ctypes.c_void_p), ("scheme_id", ctypes.c_void_p), ("n_pairs", ctypes.c_int64)]
+
+
+class sw_bin_stat(ctypes.Structure):
+    _fields_ = [("pass_", ctypes.c_int32), ("precision", ctypes.c_int32), ("lanes", ctypes.c_int32),
+                ("rows", ctypes.c_int32), ("pairs", ctypes.c_int64), ("cells", ctypes.c_int64),
+                ("ms", ctypes.c_float), ("reserved", ctypes.c_int32)]
 
 
 class SwError(RuntimeError):
@@ -91,6 +98,17 @@ def load_library(path: str = LIB_PATH):
     lib.sw_last_stats.argtypes = [ctypes.c_void_p] + [ctypes.POINTER(ctypes.c_int64)] * 3
     lib.sw_last_timing.restype = ctypes.c_int
     lib.sw_last_timing.argtypes = [ctypes.c_void_p] + [ctypes.POINTER(ctypes.c_float)] * 3
+    I32P = ctypes.POINTER(ctypes.c_int32)
+    lib.sw_shapes.restype = ctypes.c_int
+    lib.sw_shapes.argtypes = [ctypes.c_void_p, I32P, I32P, I32P, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
+    lib.sw_set_routing.restype = ctypes.c_int
+    lib.sw_set_routing.argtypes = [ctypes.c_void_p, ctypes.c_int, I32P, I32P, I32P, ctypes.c_int]
+    lib.sw_get_routing.restype = ctypes.c_int
+    lib.sw_get_routing.argtypes = [ctypes.c_void_p, ctypes.c_int, I32P, I32P, I32P, ctypes.c_int,
+                                   ctypes.POINTER(ctypes.c_int)]
+    lib.sw_last_bin_stats.restype = ctypes.c_int
+    lib.sw_last_bin_stats.argtypes = [ctypes.c_void_p, ctypes.POINTER(sw_bin_stat), ctypes.c_int,
+                                      ctypes.POINTER(ctypes.c_int)]
     lib.sw_server_create.restype = ctypes.c_void_p
     lib.sw_server_create.argtypes = [ctypes.c_int, ctypes.POINTER(sw_scheme), ctypes.c_int, ctypes.c_int64,
                                      ctypes.c_int, ctypes.c_int64, ctypes.c_char_p]
@@ -165,6 +183,55 @@ def sw_last_timing(h: int):
     a, b, c = ctypes.c_float(0), ctypes.c_float(0), ctypes.c_float(0)
     _check(h, load_library().sw_last_timing(h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
     return float(a.value), float(b.value), float(c.value)
+
+
+def sw_last_bin_stats(h: int):
+    """Per-launch statistics of the last call: a list of dicts with keys
+    pass, precision, lanes, rows, pairs, cells, ms."""
+    lib = load_library()
+    n = ctypes.c_int(0)
+    lib.sw_last_bin_stats(h, None, 0, ctypes.byref(n))
+    arr = (sw_bin_stat * max(1, n.value))()
+    _check(h, lib.sw_last_bin_stats(h, arr, n.value, ctypes.byref(n)))
+    return [{"pass": e.pass_, "precision": e.precision, "lanes": e.lanes, "rows": e.rows,
+             "pairs": int(e.pairs), "cells": int(e.cells), "ms": float(e.ms)} for e in arr[:n.value]]
+
+
+def _i32(n):
+    return (ctypes.c_int32 * max(1, n))()
+
+
+def sw_shapes(h: int):
+    """Compiled sweep shapes: list of (precision, lanes, rows)."""
+    lib = load_library()
+    n = ctypes.c_int(0)
+    lib.sw_shapes(h, None, None, None, 0, ctypes.byref(n))
+    p, w, r = _i32(n.value), _i32(n.value), _i32(n.value)
+    _check(h, lib.sw_shapes(h, p, w, r, n.value, ctypes.byref(n)))
+    return [(p[k], w[k], r[k]) for k in range(n.value)]
+
+
+def sw_set_routing(h: int, precision: int, table):
+    """table: list of (rows_max, lanes, rows); [] restores the default."""
+    n = len(table)
+    hi, w, r = _i32(n), _i32(n), _i32(n)
+    for k, (a, b, c) in enumerate(table):
+        hi[k], w[k], r[k] = int(a), int(b), int(c)
+    _check(h, load_library().sw_set_routing(h, precision, hi, w, r, n))
+
+
+def sw_get_routing(h: int, precision: int):
+    lib = load_library()
+    n = ctypes.c_int(0)
+    lib.sw_get_routing(h, precision, None, None, None, 0, ctypes.byref(n))
+    hi, w, r = _i32(n.value), _i32(n.value), _i32(n.value)
+    _check(h, lib.sw_get_routing(h, precision, hi, w, r, n.value, ctypes.byref(n)))
+    return [(hi[k], w[k], r[k]) for k in range(n.value)]
+
+
+def routing_string(precision: int, table) -> str:
+    """The tuning-string form of a routing table (sw_create's "route16=")."""
+    return "route%d=" % precision + "/".join("%dx%d@%d" % (w, r, hi) for hi, w, r in table)
 
 
 # ---- torch-facing helpers ----------------------------------------------------
@@ -268,6 +335,18 @@ class Aligner:
 
     def timing(self):
         return sw_last_timing(self.h)
+
+    def bin_stats(self):
+        return sw_last_bin_stats(self.h)
+
+    def shapes(self):
+        return sw_shapes(self.h)
+
+    def set_routing(self, precision: int, table):
+        sw_set_routing(self.h, precision, table)
+
+    def routing(self, precision: int):
+        return sw_get_routing(self.h, precision)
 
 
 class Server:

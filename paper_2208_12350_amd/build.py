@@ -10,7 +10,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libswalign.so")
-SOURCES = ["sw_plan.hip", "sw_queue_i16.hip", "sw_queue_i32.hip", "sw_runtime.hip", "sw_server.hip"]
+SOURCES = ["sw_plan.hip", "sw_queue_i16_w16.hip", "sw_queue_i16_w32.hip", "sw_queue_i16_w64.hip",
+           "sw_queue_i32.hip", "sw_runtime.hip", "sw_server.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950",

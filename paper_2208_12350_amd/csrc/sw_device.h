@@ -9,15 +9,21 @@
 namespace sw {
 
 template <int W>
-__device__ __forceinline__ int shift_in_group(int x) {
+__device__ __forceinline__ int shift_in_group(int x, int fill = 0) {
     // Lane l receives lane l-1's value; the first lane of each W-lane group
-    // receives 0.  row_shr:1 shifts within 16-lane rows, wave_shr:1 across
-    // the whole wavefront; bound_ctrl zero-fills the lane with no source.
+    // receives `fill`.  row_shr:1 shifts within 16-lane rows, wave_shr:1
+    // across the whole wavefront; with bound_ctrl off, a lane with no source
+    // keeps the `old` operand.  32-lane groups take the wave shift and
+    // select `fill` for lane 32 (its source, lane 31, belongs to the other
+    // group).
     if constexpr (W == 16) {
-        return __builtin_amdgcn_update_dpp(0, x, 0x111, 0xF, 0xF, true);
+        return __builtin_amdgcn_update_dpp(fill, x, 0x111, 0xF, 0xF, false);
+    } else if constexpr (W == 32) {
+        const int y = __builtin_amdgcn_update_dpp(fill, x, 0x138, 0xF, 0xF, false);
+        return (__lane_id() & 31) ? y : fill;
     } else {
-        static_assert(W == 64, "W must be 16 or 64");
-        return __builtin_amdgcn_update_dpp(0, x, 0x138, 0xF, 0xF, true);
+        static_assert(W == 64, "W must be 16, 32 or 64");
+        return __builtin_amdgcn_update_dpp(fill, x, 0x138, 0xF, 0xF, false);
     }
 }
 

@@ -19,10 +19,10 @@ constexpr int kWavesPerBlock = kBlock / 64;
 
 // ---- planning: bins, length buckets, work items ----------------------------
 // A bin is one compiled sweep shape (precision, lanes per group W, rows per
-// lane R).  Pairs are bucketed by (bin, reference length) with a 16-bit key
-// so a counting sort on the device groups pairs of one bin with the longest
+// lane R).  Pairs are bucketed by (bin, reference length) with one integer
+// key so a counting sort on the device groups pairs of one bin with the longest
 // references first; consecutive pairs of a bin then form wave work items.
-constexpr int kMaxBins = 40;
+constexpr int kMaxBins = 80;
 constexpr int kMBuckets = 1024;                        // length buckets per bin
 constexpr int kTrivialKey = kMaxBins * kMBuckets;      // empty / invalid pairs
 constexpr int kHistSize = kTrivialKey + 1;
@@ -64,6 +64,16 @@ enum : int {
     kMetaSize = kMetaHeads + kMaxBins,
 };
 
+// Layout of the 64-bit statistics counters of a call (cleared at its start).
+enum : int {
+    kCtrFwdCells = 0,
+    kCtrRevCells = 1,
+    kCtrI32Pairs = 2,
+    kCtrBinCells = 4,                        // [2 * kMaxBins] cells per (pass, bin)
+    kCtrBinPairs = kCtrBinCells + 2 * kMaxBins,   // [2 * kMaxBins] pairs per (pass, bin)
+    kNumCounters = kCtrBinPairs + 2 * kMaxBins,
+};
+
 // Arguments shared by every sweep launch.
 struct KParams {
     const uint8_t* queries;
@@ -100,6 +110,13 @@ enum : int32_t {
     kNumFlags = 8,
 };
 
+// Packed int16 path: values are stored plus kI16Bias so that they are
+// positive normal half-precision bit patterns (<= 0x7BFF); a pair takes the
+// path when min(n, m) * max_score <= kI16Limit and m <= kI16MaxRef.
+constexpr int kI16Bias = 1024;
+constexpr int kI16Limit = 0x7BFF - kI16Bias - 127;
+constexpr int kI16MaxRef = 32000;
+
 // Classification inputs: lut[sel * kLutRows + (n-1)/16] gives the bin of a
 // pair with query length n, where sel = 0 for the packed int16 path and 1
 // for int32; a pair takes int16 when min(n, m) * max_score[s] <= i16_limit.
@@ -123,7 +140,7 @@ using QueueFn = void (*)(KParams);
 
 struct ShapeDesc { int prec, W, R; };
 
-QueueFn shape_kernel(int prec, int W, int R);
+QueueFn shape_kernel(int prec, int W, int R, bool reverse);
 const ShapeDesc* compiled_shapes(int* n);
 
 hipError_t launch_reset(int32_t* p, int n, hipStream_t s);

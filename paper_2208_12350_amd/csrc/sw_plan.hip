@@ -26,10 +26,15 @@ __global__ void sw_reset_kernel(int32_t* p, int n) {
 
 __global__ void sw_classify_kernel(KParams P, ClassifyArgs C, const int8_t* lut, int64_t n_pairs,
                                    int32_t* keys, int32_t* hist, unsigned long long* counters) {
-    // counters[0] / [1]: forward / reverse cells; counters[2]: int32 pairs (forward)
+    // counters[0] / [1]: forward / reverse cells; counters[2]: int32 pairs
+    // (forward); per bin of this pass: cells and pairs (kCtrBinCells,
+    // kCtrBinPairs, indexed pass * kMaxBins + bin)
     __shared__ unsigned long long s_cells;
     __shared__ int32_t s_trivial, s_i32;
+    __shared__ unsigned long long s_bin_cells[kMaxBins];
+    __shared__ uint32_t s_bin_pairs[kMaxBins];
     if (threadIdx.x == 0) { s_cells = 0; s_trivial = 0; s_i32 = 0; }
+    if (threadIdx.x < kMaxBins) { s_bin_cells[threadIdx.x] = 0; s_bin_pairs[threadIdx.x] = 0; }
     __syncthreads();
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     unsigned long long my_cells = 0;
@@ -67,12 +72,14 @@ __global__ void sw_classify_kernel(KParams P, ClassifyArgs C, const int8_t* lut,
         int key = kTrivialKey;
         if (ok) {
             const int64_t mn = n < m ? n : m;
-            const int sel = mn * C.max_score[s] <= C.i16_limit ? 0 : 1;
+            const int sel = (mn * C.max_score[s] <= C.i16_limit && m <= kI16MaxRef) ? 0 : 1;
             if (sel && !P.reverse) atomicAdd(&s_i32, 1);
             const int bin = lut[sel * kLutRows + (int)((n - 1) / 16)];
             key = bin * kMBuckets + (kMBuckets - 1 - m_bucket((int)m));
             atomicAdd(&hist[key], 1);
             my_cells = (unsigned long long)(n * m);
+            atomicAdd(&s_bin_cells[bin], my_cells);
+            atomicAdd(&s_bin_pairs[bin], 1u);
         } else {
             atomicAdd(&s_trivial, 1);
         }
@@ -81,9 +88,14 @@ __global__ void sw_classify_kernel(KParams P, ClassifyArgs C, const int8_t* lut,
     if (my_cells) atomicAdd(&s_cells, my_cells);
     __syncthreads();
     if (threadIdx.x == 0) {
-        if (s_cells) atomicAdd(&counters[P.reverse ? 1 : 0], s_cells);
-        if (s_i32) atomicAdd(&counters[2], (unsigned long long)s_i32);
+        if (s_cells) atomicAdd(&counters[P.reverse ? kCtrRevCells : kCtrFwdCells], s_cells);
+        if (s_i32) atomicAdd(&counters[kCtrI32Pairs], (unsigned long long)s_i32);
         if (s_trivial) atomicAdd(&hist[kTrivialKey], s_trivial);
+    }
+    if (threadIdx.x < kMaxBins && s_bin_pairs[threadIdx.x]) {
+        const int slot = (P.reverse ? kMaxBins : 0) + threadIdx.x;
+        atomicAdd(&counters[kCtrBinCells + slot], s_bin_cells[threadIdx.x]);
+        atomicAdd(&counters[kCtrBinPairs + slot], (unsigned long long)s_bin_pairs[threadIdx.x]);
     }
 }
 

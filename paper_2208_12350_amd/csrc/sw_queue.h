@@ -1,6 +1,7 @@
 // sw_queue.h -- work-queue kernels over the sweep shapes (gfx950).
 //
-// A queue kernel is compiled for one bin shape (precision, W, R) and aligns
+// A queue kernel is compiled for one bin shape (precision, W, R) and one
+// direction (forward sweep, or reverse sweep when REV), and aligns
 // the work items [meta[lo_idx], meta[hi_idx]) of that bin: every wavefront
 // takes the next item with one atomic increment of the bin's queue head and
 // sweeps it, until the range is exhausted.
@@ -19,7 +20,7 @@
 
 namespace sw {
 
-template <int PREC, int W, int R>
+template <int PREC, int W, int R, bool REV>
 __global__ __launch_bounds__(kBlock) void sw_queue_kernel(KParams P) {
     __shared__ __attribute__((aligned(16))) SchemeLds L;
     __shared__ uint16_t wbufs[kWavesPerBlock * kWaveBuf];
@@ -57,15 +58,15 @@ __global__ __launch_bounds__(kBlock) void sw_queue_kernel(KParams P) {
         if (valid) {
             wave_lds_sync();
             if constexpr (PREC == 16)
-                sweep_i16<W, R>(P, L, wbuf, first, count, lane);
+                sweep_i16<W, R, REV>(P, L, wbuf, first, count, lane);
             else
-                sweep_i32<W, R>(P, L, wbuf, first, count, lane);
+                sweep_i32<W, R, REV>(P, L, wbuf, first, count, lane);
         } else {
             atomicOr(&P.flags[kFlagInternal], 1);
         }
     }
 }
 
-struct KernelEntry { int prec, W, R; QueueFn fn; };
+struct KernelEntry { int prec, W, R; QueueFn fwd, rev; };
 
 }  // namespace sw

@@ -1,0 +1,20 @@
+// sw_queue_i16_w16.hip -- queue kernels of the packed int16 sweep shapes with
+// 16-lane groups, 1..16 rows per lane (queries up to 256 residues).
+
+#include "sw_queue.h"
+
+namespace sw {
+
+extern const KernelEntry kI16W16Kernels[];
+extern const int kNumI16W16Kernels;
+
+#define SW_ENTRY(W, R) {16, W, R, &sw_queue_kernel<16, W, R, false>, &sw_queue_kernel<16, W, R, true>},
+const KernelEntry kI16W16Kernels[] = {
+    SW_ENTRY(16, 1) SW_ENTRY(16, 2) SW_ENTRY(16, 3) SW_ENTRY(16, 4) SW_ENTRY(16, 5) SW_ENTRY(16, 6)
+    SW_ENTRY(16, 7) SW_ENTRY(16, 8) SW_ENTRY(16, 9) SW_ENTRY(16, 10) SW_ENTRY(16, 11) SW_ENTRY(16, 12)
+    SW_ENTRY(16, 13) SW_ENTRY(16, 14) SW_ENTRY(16, 15) SW_ENTRY(16, 16)
+};
+#undef SW_ENTRY
+const int kNumI16W16Kernels = sizeof(kI16W16Kernels) / sizeof(kI16W16Kernels[0]);
+
+}  // namespace sw

@@ -1,10 +1,11 @@
-// sw_queue_i32.hip -- queue kernels of the int32 sweep shapes, and the
-// registry of every compiled shape.
+// sw_queue_i32.hip -- queue kernels of the int32 sweep shapes (the exact
+// fallback for pairs whose scores may not fit 16 bits), and the registry of
+// every compiled shape.
 #include "sw_queue.h"
 
 namespace sw {
 
-#define SW_ENTRY(W, R) {32, W, R, &sw_queue_kernel<32, W, R>},
+#define SW_ENTRY(W, R) {32, W, R, &sw_queue_kernel<32, W, R, false>, &sw_queue_kernel<32, W, R, true>},
 static const KernelEntry kI32Kernels[] = {
     SW_ENTRY(16, 2) SW_ENTRY(16, 4) SW_ENTRY(16, 6) SW_ENTRY(16, 8) SW_ENTRY(16, 10)
     SW_ENTRY(16, 12) SW_ENTRY(16, 14) SW_ENTRY(16, 16)
@@ -13,29 +14,50 @@ static const KernelEntry kI32Kernels[] = {
 };
 #undef SW_ENTRY
 
-extern const KernelEntry kI16Kernels[];
-extern const int kNumI16Kernels;
+extern const KernelEntry kI16W16Kernels[];
+extern const int kNumI16W16Kernels;
+extern const KernelEntry kI16W32Kernels[];
+extern const int kNumI16W32Kernels;
+extern const KernelEntry kI16W64Kernels[];
+extern const int kNumI16W64Kernels;
 
-static ShapeDesc g_shapes[64];
-static int g_nshapes = 0;
+namespace {
+
+struct Table { const KernelEntry* e; int n; };
+
+Table table(int k) {
+    switch (k) {
+        case 0: return {kI16W16Kernels, kNumI16W16Kernels};
+        case 1: return {kI16W32Kernels, kNumI16W32Kernels};
+        case 2: return {kI16W64Kernels, kNumI16W64Kernels};
+        default: return {kI32Kernels, (int)(sizeof(kI32Kernels) / sizeof(kI32Kernels[0]))};
+    }
+}
+
+constexpr int kTables = 4;
+ShapeDesc g_shapes[kMaxBins];
+int g_nshapes = 0;
+
+}  // namespace
 
 const ShapeDesc* compiled_shapes(int* n) {
     if (g_nshapes == 0) {
-        for (int k = 0; k < kNumI16Kernels; ++k)
-            g_shapes[g_nshapes++] = {kI16Kernels[k].prec, kI16Kernels[k].W, kI16Kernels[k].R};
-        for (const KernelEntry& e : kI32Kernels) g_shapes[g_nshapes++] = {e.prec, e.W, e.R};
+        for (int t = 0; t < kTables; ++t) {
+            const Table tb = table(t);
+            for (int k = 0; k < tb.n && g_nshapes < kMaxBins; ++k)
+                g_shapes[g_nshapes++] = {tb.e[k].prec, tb.e[k].W, tb.e[k].R};
+        }
     }
     *n = g_nshapes;
     return g_shapes;
 }
 
-QueueFn shape_kernel(int prec, int W, int R) {
-    if (prec == 16) {
-        for (int k = 0; k < kNumI16Kernels; ++k)
-            if (kI16Kernels[k].W == W && kI16Kernels[k].R == R) return kI16Kernels[k].fn;
-    } else {
-        for (const KernelEntry& e : kI32Kernels)
-            if (e.W == W && e.R == R) return e.fn;
+QueueFn shape_kernel(int prec, int W, int R, bool reverse) {
+    for (int t = 0; t < kTables; ++t) {
+        const Table tb = table(t);
+        for (int k = 0; k < tb.n; ++k)
+            if (tb.e[k].prec == prec && tb.e[k].W == W && tb.e[k].R == R)
+                return reverse ? tb.e[k].rev : tb.e[k].fwd;
     }
     return nullptr;
 }

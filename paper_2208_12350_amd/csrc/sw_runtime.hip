@@ -29,7 +29,8 @@ using namespace sw;
 namespace {
 
 constexpr int kLutEntries = 2 * kLutRows;
-constexpr int kSmallInts = 64;   // flags [0, kNumFlags) | 64-bit counters from index 16
+constexpr int kCtrBase = 16;     // int index of the first 64-bit counter
+constexpr int kSmallInts = kCtrBase + 2 * kNumCounters;   // flags [0, kNumFlags) | counters
 
 // Everything a captured graph depends on besides device memory contents.
 struct GraphKey {
@@ -62,10 +63,14 @@ struct sw_handle {
     int64_t opt_validate = 1;
     int64_t opt_precision = 0;
     int64_t opt_timing = 0;
+    int64_t opt_streams = 4;
 
     std::vector<BinInfo> bins;
-    std::vector<int8_t> lut;
-    std::vector<int> resident_blocks;   // per bin: workgroups the device holds at once
+    std::vector<int> route[2];          // per precision (int16, int32) and 16-row bucket: bin
+    std::vector<int8_t> lut;            // device copy of route
+    std::vector<char> bin_used;         // bins some route points at
+    bool lut_dirty = true;
+    std::vector<int> resident_blocks[2];   // per pass and bin: workgroups the device holds at once
 
     int8_t* d_mats = nullptr;
     int8_t* d_lut = nullptr;
@@ -84,6 +89,9 @@ struct sw_handle {
 
     hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     float t_plan = 0.f, t_fwd = 0.f, t_rev = 0.f;
+    // per (pass, bin) event pairs for "timing" = 2, created on first use
+    std::vector<hipEvent_t> bin_ev;
+    std::vector<sw_bin_stat> bin_stats;
 
     hipStream_t cap_stream = nullptr;   // private stream the graph is captured on
     static constexpr int kForks = 4;    // persistent mode spreads bins over these streams
@@ -114,23 +122,20 @@ static int fail(sw_handle* h, int code, const char* fmt, ...) {
             return fail((h), SW_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_));   \
     } while (0)
 
-// 64-bit counters live in d_small from int index 16: [0] forward cells,
-// [1] reverse cells, [2] int32 pairs of the forward pass.
+// 64-bit counters live in d_small from int index kCtrBase (layout kCtr*).
 static unsigned long long* counters(int32_t* small) {
-    return reinterpret_cast<unsigned long long*>(small + 16);
+    return reinterpret_cast<unsigned long long*>(small + kCtrBase);
 }
 
 static void build_bins(sw_handle* h) {
     // Bins run longest work first: int16 before int32, then decreasing rows
-    // per lane (and 64-lane groups before 16-lane ones at equal R).
-    // Queries up to 256 rows take 16-lane groups, longer ones 64-lane groups;
-    // R is the smallest compiled value covering the query's 16-row bucket.
+    // per group (W * R), wider groups first at equal rows.
     int n = 0;
     const ShapeDesc* sh = compiled_shapes(&n);
     std::vector<ShapeDesc> v(sh, sh + n);
     std::stable_sort(v.begin(), v.end(), [](const ShapeDesc& a, const ShapeDesc& b) {
         if (a.prec != b.prec) return a.prec < b.prec;
-        if (a.R != b.R) return a.R > b.R;
+        if (a.W * a.R != b.W * b.R) return a.W * a.R > b.W * b.R;
         return a.W > b.W;
     });
     h->bins.clear();
@@ -143,21 +148,98 @@ static void build_bins(sw_handle* h) {
         b.ppw = (64 / s.W) * (s.prec == 16 ? 2 : 1);
         h->bins.push_back(b);
     }
-    h->lut.assign(kLutEntries, -1);
-    for (int sel = 0; sel < 2; ++sel) {
-        const int prec = sel == 0 ? 16 : 32;
-        for (int k = 0; k < kLutRows; ++k) {
-            const int rows = 16 * (k + 1);
-            const int W = rows <= 256 ? 16 : 64;
-            int best = -1;
-            for (int b = 0; b < (int)h->bins.size(); ++b) {
-                const BinInfo& e = h->bins[b];
-                if (e.prec != prec || e.W != W || e.W * e.R < rows) continue;
-                if (best < 0 || e.R < h->bins[best].R) best = b;
+}
+
+static int find_bin(const sw_handle* h, int prec, int W, int R) {
+    for (int b = 0; b < (int)h->bins.size(); ++b)
+        if (h->bins[b].prec == prec && h->bins[b].W == W && h->bins[b].R == R) return b;
+    return -1;
+}
+
+// Default routing of one precision: each 16-row bucket goes to the covering
+// shape with the fewest lane-row slots per pair, W*R*(m + W - 1), for a
+// reference of twice the query length plus 64 (the sweep of a W-lane group
+// takes m + W - 1 steps).  Ties go to the narrower group.
+static void default_routing(sw_handle* h, int sel) {
+    const int prec = sel == 0 ? 16 : 32;
+    for (int k = 0; k < kLutRows; ++k) {
+        const int rows = 16 * (k + 1);
+        const double m = 2.0 * rows + 64.0;
+        int best = -1;
+        double best_cost = 0;
+        for (int b = 0; b < (int)h->bins.size(); ++b) {
+            const BinInfo& e = h->bins[b];
+            if (e.prec != prec || e.W * e.R < rows) continue;
+            const double cost = (double)e.W * e.R * (m + e.W - 1);
+            if (best < 0 || cost < best_cost || (cost == best_cost && e.W < h->bins[best].W)) {
+                best = b;
+                best_cost = cost;
             }
-            h->lut[sel * kLutRows + k] = (int8_t)best;
         }
+        h->route[sel][k] = best;
     }
+}
+
+static void rebuild_lut(sw_handle* h) {
+    h->lut.assign(kLutEntries, -1);
+    h->bin_used.assign(h->bins.size(), 0);
+    for (int sel = 0; sel < 2; ++sel)
+        for (int k = 0; k < kLutRows; ++k) {
+            const int b = h->route[sel][k];
+            h->lut[sel * kLutRows + k] = (int8_t)b;
+            if (b >= 0) h->bin_used[b] = 1;
+        }
+    h->lut_dirty = true;
+}
+
+// Install a routing table for one precision (sel 0 = int16, 1 = int32):
+// queries of rows_max[k-1]+1 .. rows_max[k] residues go to shape
+// (lanes[k], rows[k]).  n == 0 restores the default.
+static int set_routing(sw_handle* h, int sel, const int32_t* rows_max, const int32_t* lanes,
+                       const int32_t* rows, int n) {
+    const int prec = sel == 0 ? 16 : 32;
+    if (n == 0) {
+        default_routing(h, sel);
+        rebuild_lut(h);
+        return SW_OK;
+    }
+    if (n < 0 || n > kLutRows || !rows_max || !lanes || !rows)
+        return fail(h, SW_EINVAL, "routing needs 1..%d entries", kLutRows);
+    std::vector<int> r(kLutRows, -1);
+    int prev = 0;
+    for (int e = 0; e < n; ++e) {
+        const int hi = rows_max[e];
+        if (hi <= prev || hi % 16 != 0 || hi > SW_MAX_QUERY)
+            return fail(h, SW_EINVAL, "routing entry %d: rows_max must increase in steps of 16 up to %d", e,
+                        SW_MAX_QUERY);
+        const int b = find_bin(h, prec, lanes[e], rows[e]);
+        if (b < 0) return fail(h, SW_EINVAL, "routing entry %d: no compiled int%d shape %dx%d", e, prec, lanes[e], rows[e]);
+        if (lanes[e] * rows[e] < hi)
+            return fail(h, SW_EINVAL, "routing entry %d: shape %dx%d covers %d rows, fewer than %d", e, lanes[e],
+                        rows[e], lanes[e] * rows[e], hi);
+        for (int k = prev / 16; k < hi / 16; ++k) r[k] = b;
+        prev = hi;
+    }
+    if (prev != SW_MAX_QUERY) return fail(h, SW_EINVAL, "routing must end at rows_max = %d", SW_MAX_QUERY);
+    for (int k = 0; k < kLutRows; ++k) h->route[sel][k] = r[k];
+    rebuild_lut(h);
+    return SW_OK;
+}
+
+// "16x4@64/16x8@128/..." -> routing entries (shape W x R up to rows_max)
+static int parse_routing(sw_handle* h, int sel, const std::string& v) {
+    std::vector<int32_t> hi, W, R;
+    size_t pos = 0;
+    while (pos < v.size()) {
+        size_t end = v.find('/', pos);
+        if (end == std::string::npos) end = v.size();
+        int a = 0, b = 0, c = 0;
+        if (sscanf(v.substr(pos, end - pos).c_str(), "%dx%d@%d", &a, &b, &c) != 3)
+            return fail(h, SW_EINVAL, "bad routing entry '%s'", v.substr(pos, end - pos).c_str());
+        W.push_back(a); R.push_back(b); hi.push_back(c);
+        pos = end + 1;
+    }
+    return set_routing(h, sel, hi.data(), W.data(), R.data(), (int)hi.size());
 }
 
 static void free_dev(void* p) {
@@ -197,28 +279,36 @@ static int enqueue_pass(sw_handle* h, KParams K, const ClassifyArgs& C, int64_t 
     HIP_TRY(h, launch_plan(h->d_bins, n_bins, h->d_hist, h->d_meta, stream));
     HIP_TRY(h, launch_scatter(h->d_keys, P, h->d_hist, h->d_order, stream));
     HIP_TRY(h, launch_items(h->d_meta, h->d_bins, n_bins, P, h->d_items, stream));
+    const bool per_bin = timing && h->opt_timing == 2;
+    if (timing && h->opt_mode == 1) HIP_TRY(h, hipEventRecord(h->ev[pass == 0 ? 1 : 3], stream));
     if (h->opt_mode == 1) {
-        if (timing) HIP_TRY(h, hipEventRecord(h->ev[pass == 0 ? 1 : 3], stream));
-        // Bins go round-robin, longest first, to kForks streams forked from
-        // `stream` and joined back into it: the bins' launch tails, and the
+        // Bins go round-robin, longest first, to the forked streams, which
+        // are joined back into `stream`: the bins' launch tails, and the
         // launches of bins that turn out to be empty, overlap with the work
-        // of the other streams.
-        HIP_TRY(h, hipEventRecord(h->fork_ev[sw_handle::kForks], stream));
-        for (int f = 0; f < sw_handle::kForks; ++f)
-            HIP_TRY(h, hipStreamWaitEvent(h->fork[f], h->fork_ev[sw_handle::kForks], 0));
+        // of the other streams.  Per-launch timing serialises them.
+        const int forks = per_bin ? 0 : (int)h->opt_streams;
+        int launched = 0;
+        if (forks > 1) {
+            HIP_TRY(h, hipEventRecord(h->fork_ev[sw_handle::kForks], stream));
+            for (int f = 0; f < forks; ++f)
+                HIP_TRY(h, hipStreamWaitEvent(h->fork[f], h->fork_ev[sw_handle::kForks], 0));
+        }
         for (int b = 0; b < n_bins; ++b) {
+            if (!h->bin_used[b]) continue;
             const BinInfo& e = h->bins[b];
             // no bin can hold more than P / ppw items, one wavefront each
             const int64_t need = (P / e.ppw + 1 + kWavesPerBlock - 1) / kWavesPerBlock;
-            const int blocks = (int)std::min<int64_t>(need, h->resident_blocks[b]);
+            const int blocks = (int)std::min<int64_t>(need, h->resident_blocks[pass][b]);
             K.lo_idx = kMetaItemFirst + b;
             K.hi_idx = kMetaItemFirst + b + 1;
             K.head_idx = kMetaHeads + b;
-            hipLaunchKernelGGL(shape_kernel(e.prec, e.W, e.R), dim3(blocks), dim3(kBlock), 0,
-                               h->fork[b % sw_handle::kForks], K);
+            hipStream_t ls = forks > 1 ? h->fork[launched++ % forks] : stream;
+            if (per_bin) HIP_TRY(h, hipEventRecord(h->bin_ev[(pass * kMaxBins + b) * 2], ls));
+            hipLaunchKernelGGL(shape_kernel(e.prec, e.W, e.R, pass != 0), dim3(blocks), dim3(kBlock), 0, ls, K);
             HIP_TRY(h, hipGetLastError());
+            if (per_bin) HIP_TRY(h, hipEventRecord(h->bin_ev[(pass * kMaxBins + b) * 2 + 1], ls));
         }
-        for (int f = 0; f < sw_handle::kForks; ++f) {
+        for (int f = 0; forks > 1 && f < forks; ++f) {
             HIP_TRY(h, hipEventRecord(h->fork_ev[f], h->fork[f]));
             HIP_TRY(h, hipStreamWaitEvent(stream, h->fork_ev[f], 0));
         }
@@ -234,8 +324,10 @@ static int enqueue_pass(sw_handle* h, KParams K, const ClassifyArgs& C, int64_t 
             K.hi_idx = kMetaItemFirst + b + 1;
             K.head_idx = kMetaHeads + b;
             const int blocks = (items + kWavesPerBlock - 1) / kWavesPerBlock;
-            hipLaunchKernelGGL(shape_kernel(e.prec, e.W, e.R), dim3(blocks), dim3(kBlock), 0, stream, K);
+            if (per_bin) HIP_TRY(h, hipEventRecord(h->bin_ev[(pass * kMaxBins + b) * 2], stream));
+            hipLaunchKernelGGL(shape_kernel(e.prec, e.W, e.R, pass != 0), dim3(blocks), dim3(kBlock), 0, stream, K);
             HIP_TRY(h, hipGetLastError());
+            if (per_bin) HIP_TRY(h, hipEventRecord(h->bin_ev[(pass * kMaxBins + b) * 2 + 1], stream));
         }
     }
     if (timing) HIP_TRY(h, hipEventRecord(h->ev[pass == 0 ? 2 : 4], stream));
@@ -254,6 +346,11 @@ sw_handle* sw_create(int device, const char* tuning) {
     bool ok = hipGetDeviceProperties(&prop, device) == hipSuccess;
     h->n_cu = ok ? prop.multiProcessorCount : 0;
     build_bins(h);
+    for (int sel = 0; sel < 2; ++sel) {
+        h->route[sel].assign(kLutRows, -1);
+        default_routing(h, sel);
+    }
+    rebuild_lut(h);
     ok = ok && h->bins.size() <= (size_t)kMaxBins &&
          hipMalloc(&h->d_mats, SW_MAX_SCHEMES * kMatBytes) == hipSuccess &&
          hipMalloc(&h->d_lut, kLutEntries) == hipSuccess &&
@@ -270,15 +367,17 @@ sw_handle* sw_create(int device, const char* tuning) {
         ok = hipStreamCreateWithFlags(&h->fork[f], hipStreamNonBlocking) == hipSuccess;
     for (int f = 0; ok && f <= sw_handle::kForks; ++f)
         ok = hipEventCreateWithFlags(&h->fork_ev[f], hipEventDisableTiming) == hipSuccess;
-    if (ok) ok = hipMemcpy(h->d_lut, h->lut.data(), kLutEntries, hipMemcpyHostToDevice) == hipSuccess;
     if (ok) ok = hipMemcpy(h->d_bins, h->bins.data(), h->bins.size() * sizeof(BinInfo),
                            hipMemcpyHostToDevice) == hipSuccess;
-    h->resident_blocks.assign(h->bins.size(), 1);
-    for (size_t b = 0; ok && b < h->bins.size(); ++b) {
-        int per_cu = 0;
-        const QueueFn fn = shape_kernel(h->bins[b].prec, h->bins[b].W, h->bins[b].R);
-        ok = fn && hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)fn, kBlock, 0) == hipSuccess;
-        h->resident_blocks[b] = std::max(1, per_cu) * std::max(1, h->n_cu);
+    for (int pass = 0; pass < 2; ++pass) {
+        h->resident_blocks[pass].assign(h->bins.size(), 1);
+        for (size_t b = 0; ok && b < h->bins.size(); ++b) {
+            int per_cu = 0;
+            const QueueFn fn = shape_kernel(h->bins[b].prec, h->bins[b].W, h->bins[b].R, pass != 0);
+            ok = fn && hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)fn, kBlock, 0) ==
+                           hipSuccess;
+            h->resident_blocks[pass][b] = std::max(1, per_cu) * std::max(1, h->n_cu);
+        }
     }
     if (!ok) { sw_destroy(h); return nullptr; }
     if (tuning) {
@@ -290,7 +389,12 @@ sw_handle* sw_create(int device, const char* tuning) {
             std::string kv = s.substr(pos, end - pos);
             size_t eq = kv.find('=');
             if (eq != std::string::npos) {
-                if (sw_set_option(h, kv.substr(0, eq).c_str(), atoll(kv.substr(eq + 1).c_str())) != SW_OK) {
+                const std::string key = kv.substr(0, eq), val = kv.substr(eq + 1);
+                int rc;
+                if (key == "route16") rc = parse_routing(h, 0, val);
+                else if (key == "route32") rc = parse_routing(h, 1, val);
+                else rc = sw_set_option(h, key.c_str(), atoll(val.c_str()));
+                if (rc != SW_OK) {
                     sw_destroy(h);
                     return nullptr;
                 }
@@ -314,6 +418,8 @@ void sw_destroy(sw_handle* h) {
     if (h->h_meta) (void)hipHostFree(h->h_meta);
     for (int k = 0; k < 5; ++k)
         if (h->ev[k]) (void)hipEventDestroy(h->ev[k]);
+    for (hipEvent_t e : h->bin_ev)
+        if (e) (void)hipEventDestroy(e);
     if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
     for (int f = 0; f < sw_handle::kForks; ++f)
         if (h->fork[f]) (void)hipStreamDestroy(h->fork[f]);
@@ -335,7 +441,16 @@ int sw_set_option(sw_handle* h, const char* key, int64_t value) {
     } else if (k == "validate") {
         h->opt_validate = value ? 1 : 0;
     } else if (k == "timing") {
-        h->opt_timing = value ? 1 : 0;
+        if (value < 0 || value > 2) return fail(h, SW_EINVAL, "timing must be 0, 1 or 2");
+        if (value == 2 && h->bin_ev.empty()) {
+            h->bin_ev.assign(2 * kMaxBins * 2, nullptr);
+            for (hipEvent_t& e : h->bin_ev)
+                if (hipEventCreate(&e) != hipSuccess) return fail(h, SW_EDEVICE, "event creation failed");
+        }
+        h->opt_timing = value;
+    } else if (k == "streams") {
+        if (value < 1 || value > sw_handle::kForks) return fail(h, SW_EINVAL, "streams must be 1..%d", sw_handle::kForks);
+        h->opt_streams = value;
     } else if (k == "precision") {
         if (value != 0 && value != 32) return fail(h, SW_EINVAL, "precision must be 0 or 32");
         h->opt_precision = value;
@@ -354,6 +469,7 @@ int sw_get_option(sw_handle* h, const char* key, int64_t* value) {
     else if (k == "validate") *value = h->opt_validate;
     else if (k == "precision") *value = h->opt_precision;
     else if (k == "timing") *value = h->opt_timing;
+    else if (k == "streams") *value = h->opt_streams;
     else return fail(h, SW_EINVAL, "unknown option '%s'", key);
     return SW_OK;
 }
@@ -371,6 +487,7 @@ static int align_spans(sw_handle* h, const uint8_t* queries, const int64_t* q_be
     h->err.clear();
     h->last_fwd = h->last_rev = h->last_i32 = 0;
     h->t_plan = h->t_fwd = h->t_rev = 0.f;
+    h->bin_stats.clear();
     if (!schemes) return fail(h, SW_EINVAL, "null schemes");
     if (n_schemes < 1 || n_schemes > SW_MAX_SCHEMES)
         return fail(h, SW_EINVAL, "n_schemes must be 1..%d", SW_MAX_SCHEMES);
@@ -392,6 +509,11 @@ static int align_spans(sw_handle* h, const uint8_t* queries, const int64_t* q_be
     HIP_TRY(h, hipSetDevice(h->device));
     int rc = ensure_pairs(h, P);
     if (rc != SW_OK) return rc;
+    if (h->lut_dirty) {
+        drop_graph(h);
+        HIP_TRY(h, hipMemcpy(h->d_lut, h->lut.data(), kLutEntries, hipMemcpyHostToDevice));
+        h->lut_dirty = false;
+    }
 
     // substitution tables: [s][b][a] = M_s[a][b]; padding rows/columns score -1
     ClassifyArgs C;
@@ -409,9 +531,9 @@ static int align_spans(sw_handle* h, const uint8_t* queries, const int64_t* q_be
             }
         C.max_score[s] = mx;
     }
-    // int16 holds every value of a pair when min(n, m) * max_score plus one
-    // more substitution score stays below 2^15
-    C.i16_limit = h->opt_precision == 32 ? -1 : 32767 - 127;
+    // the packed path holds every value of a pair when its score bound
+    // min(n, m) * max_score is at most kI16Limit
+    C.i16_limit = h->opt_precision == 32 ? -1 : kI16Limit;
     C.n_schemes = n_schemes;
     C.n_bins = (int)h->bins.size();
 
@@ -429,8 +551,8 @@ static int align_spans(sw_handle* h, const uint8_t* queries, const int64_t* q_be
         K.gap_extend[s] = v ? schemes[s].gap_extend : 0;
     }
 
-    const bool use_graph = h->opt_mode == 1 && h->opt_graph != 0;
-    const bool timing = h->opt_timing != 0 && !use_graph;
+    const bool timing = h->opt_timing != 0;
+    const bool use_graph = h->opt_mode == 1 && h->opt_graph != 0 && !timing;
     GraphKey key;
     memset(&key, 0, sizeof(key));
     key.queries = queries; key.q_beg = q_beg; key.q_end = q_end; key.refs = refs;
@@ -481,9 +603,21 @@ static int align_spans(sw_handle* h, const uint8_t* queries, const int64_t* q_be
     HIP_TRY(h, hipStreamSynchronize(stream));
     const int32_t* flags = h->h_small;
     const unsigned long long* cnt = counters(h->h_small);
-    h->last_fwd = (int64_t)cnt[0];
-    h->last_rev = (int64_t)cnt[1];
-    h->last_i32 = (int64_t)cnt[2];
+    h->last_fwd = (int64_t)cnt[kCtrFwdCells];
+    h->last_rev = (int64_t)cnt[kCtrRevCells];
+    h->last_i32 = (int64_t)cnt[kCtrI32Pairs];
+    for (int pass = 0; pass < 2; ++pass)
+        for (int b = 0; b < (int)h->bins.size(); ++b) {
+            sw_bin_stat st;
+            memset(&st, 0, sizeof(st));
+            st.pass = pass;
+            st.precision = h->bins[b].prec;
+            st.lanes = h->bins[b].W;
+            st.rows = h->bins[b].R;
+            st.cells = (int64_t)cnt[kCtrBinCells + pass * kMaxBins + b];
+            st.pairs = (int64_t)cnt[kCtrBinPairs + pass * kMaxBins + b];
+            h->bin_stats.push_back(st);
+        }
     if (timing) {
         float a = 0, b = 0;
         HIP_TRY(h, hipEventElapsedTime(&a, h->ev[0], h->ev[1]));
@@ -491,6 +625,16 @@ static int align_spans(sw_handle* h, const uint8_t* queries, const int64_t* q_be
         HIP_TRY(h, hipEventElapsedTime(&b, h->ev[2], h->ev[3]));
         HIP_TRY(h, hipEventElapsedTime(&h->t_rev, h->ev[3], h->ev[4]));
         h->t_plan = a + b;
+        if (h->opt_timing == 2)
+            for (int pass = 0; pass < 2; ++pass)
+                for (int b = 0; b < (int)h->bins.size(); ++b) {
+                    sw_bin_stat& st = h->bin_stats[pass * h->bins.size() + b];
+                    // plain mode launches nothing for an empty bin, and no
+                    // mode launches a bin that no route points at
+                    if ((h->opt_mode == 0 && st.pairs == 0) || !h->bin_used[b]) continue;
+                    HIP_TRY(h, hipEventElapsedTime(&st.ms, h->bin_ev[(pass * kMaxBins + b) * 2],
+                                                   h->bin_ev[(pass * kMaxBins + b) * 2 + 1]));
+                }
     }
     if (flags[kFlagBadOffsets]) return fail(h, SW_EINVAL, "offsets decrease");
     if (flags[kFlagBadScheme]) return fail(h, SW_EINVAL, "scheme id out of range");
@@ -527,6 +671,59 @@ int sw_last_stats(sw_handle* h, int64_t* fwd_cells, int64_t* rev_cells, int64_t*
     if (fwd_cells) *fwd_cells = h->last_fwd;
     if (rev_cells) *rev_cells = h->last_rev;
     if (int32_pairs) *int32_pairs = h->last_i32;
+    return SW_OK;
+}
+
+int sw_shapes(sw_handle* h, int32_t* precision, int32_t* lanes, int32_t* rows, int capacity, int* n_out) {
+    if (!h) return SW_EINVAL;
+    const int n = (int)h->bins.size();
+    if (n_out) *n_out = n;
+    if (!precision || !lanes || !rows || capacity < n) return fail(h, SW_EINVAL, "need room for %d shapes", n);
+    for (int b = 0; b < n; ++b) {
+        precision[b] = h->bins[b].prec;
+        lanes[b] = h->bins[b].W;
+        rows[b] = h->bins[b].R;
+    }
+    return SW_OK;
+}
+
+int sw_set_routing(sw_handle* h, int precision, const int32_t* rows_max, const int32_t* lanes, const int32_t* rows,
+                   int n) {
+    if (!h) return SW_EINVAL;
+    if (precision != 16 && precision != 32) return fail(h, SW_EINVAL, "precision must be 16 or 32");
+    return set_routing(h, precision == 16 ? 0 : 1, rows_max, lanes, rows, n);
+}
+
+int sw_get_routing(sw_handle* h, int precision, int32_t* rows_max, int32_t* lanes, int32_t* rows, int capacity,
+                   int* n_out) {
+    if (!h) return SW_EINVAL;
+    if (precision != 16 && precision != 32) return fail(h, SW_EINVAL, "precision must be 16 or 32");
+    const std::vector<int>& r = h->route[precision == 16 ? 0 : 1];
+    std::vector<int32_t> hi, W, R;
+    for (int k = 0; k < kLutRows; ++k) {
+        const bool last = k + 1 == kLutRows || r[k + 1] != r[k];
+        if (!last) continue;
+        hi.push_back(16 * (k + 1));
+        W.push_back(r[k] >= 0 ? h->bins[r[k]].W : 0);
+        R.push_back(r[k] >= 0 ? h->bins[r[k]].R : 0);
+    }
+    const int n = (int)hi.size();
+    if (n_out) *n_out = n;
+    if (!rows_max || !lanes || !rows || capacity < n) return fail(h, SW_EINVAL, "need room for %d entries", n);
+    for (int e = 0; e < n; ++e) {
+        rows_max[e] = hi[e];
+        lanes[e] = W[e];
+        rows[e] = R[e];
+    }
+    return SW_OK;
+}
+
+int sw_last_bin_stats(sw_handle* h, sw_bin_stat* out, int capacity, int* n_out) {
+    if (!h) return SW_EINVAL;
+    const int n = (int)h->bin_stats.size();
+    if (n_out) *n_out = n;
+    if (n > 0 && (!out || capacity < n)) return fail(h, SW_EINVAL, "need room for %d entries", n);
+    for (int k = 0; k < n; ++k) out[k] = h->bin_stats[k];
     return SW_OK;
 }
 

@@ -331,6 +331,7 @@ int sw_server_submit(sw_server* S, const uint8_t* queries, const int64_t* q_off,
     if (n_pairs > S->max_pairs) return sfail(S, SW_EINVAL, "request larger than the slot pair budget");
     if (n_pairs > 0 && (!q_off || !r_off)) return sfail(S, SW_EINVAL, "null offsets");
     std::unique_ptr<Request> r(new Request());
+    r->t_submit = Clock::now();   // latency includes the host checks and staging
     r->n_pairs = n_pairs;
     // host checks: the whole request is rejected here rather than failing a
     // merged batch later
@@ -366,7 +367,6 @@ int sw_server_submit(sw_server* S, const uint8_t* queries, const int64_t* q_off,
     r->pool_bytes = PoolAllocator::round_up(r->seq_bytes) + span_block_bytes(n_pairs);
     if (r->pool_bytes > S->alloc.capacity())
         return sfail(S, SW_ENOMEM, "request needs %lld bytes, more than the whole pool", (long long)r->pool_bytes);
-    r->t_submit = Clock::now();
     std::lock_guard<std::mutex> g(S->mu);
     r->ticket = S->next_ticket++;
     *ticket = r->ticket;

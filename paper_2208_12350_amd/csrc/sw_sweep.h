@@ -5,8 +5,8 @@
 // independent query/reference pairs.
 //
 // Mapping onto CDNA4 (one pair per lane group, anti-diagonal sweep):
-//   * A wavefront (64 lanes) is split into 64/W groups of W lanes (W = 16 or
-//     64).  Each group owns one pair.  Lane l of a group owns query rows
+//   * A wavefront (64 lanes) is split into 64/W groups of W lanes (W = 16,
+//     32 or 64).  Each group owns one pair.  Lane l of a group owns query rows
 //     l*R .. l*R+R-1 in registers (H, E and the row's running best), so a
 //     group covers W*R >= n rows in a single sweep.
 //   * At step t lane l computes column j = t - l for its R rows, i.e. the
@@ -39,15 +39,28 @@
 // host pairs them up from the same length bin (similar query and reference
 // lengths, so little padding).
 //
-// Range: the host routes a pair here only when min(n, m) * max_score fits
-// in 15 bits, which bounds every H, E, F and H + M[a][b] of the pair (and of
-// its reverse sweep, whose values never exceed the forward maximum).  E, F
-// and H - o are carried saturated at 0 (v_pk_sub_u16 with clamp), exactly as
-// the int32 kernel clamps them, so the packed arithmetic is exact.
+// Biased values: every H, E and F of the packed path is stored plus a bias
+// K = kI16Bias (1024), so "zero" is K.  All stored values then lie in
+// [K, 0x7BFF]: bit patterns of positive normal half-precision numbers, whose
+// numeric order is their integer order.  A three-way maximum of two packed
+// halves is therefore one v_pk_maximum3_f16 on the raw patterns (it never
+// rounds: it returns one of its inputs).  The clamps E* = max(E, 0) and
+// F* = max(F, 0) become a third operand K of that maximum, and with E, F >= K
+// the clamp of H at zero comes for free: H = max3(diag + M[a][b], E, F).
+// diag + M[a][b] may fall below K (a mismatch next to a zero cell), even
+// into the denormal range, but it is then below E >= K and never selected.
 //
-// Row best per lane is tracked as a 32-bit key (H << 16) | (kColMax - j):
-// an unsigned max keeps the largest H and, among equal H, the smallest
-// column j -- the row-major-first maximum within a row.
+// Range: the host routes a pair here only when min(n, m) * max_score <=
+// kI16Limit, which keeps K + H + max_score <= 0x7BFF for every cell of the
+// pair (and of its reverse sweep, whose values never exceed the forward
+// maximum), and when m <= kI16MaxRef, which keeps the column field of the
+// keys below to 15 bits.
+//
+// Row best: rows r (even) and r+1 of a lane share one 32-bit key per pair,
+// (H << 16) | (rowbit << 15) | (kColMax - j) with rowbit = 1 for row r.  An
+// unsigned max (v_max3_u32 over both rows) keeps the largest H, then the
+// upper row, then the smallest column j: the row-major-first maximum of the
+// two rows.
 #pragma once
 
 #include "sw_device.h"
@@ -58,14 +71,14 @@ namespace sw {
 // LDS reference buffer of one wavefront, sized for the widest layout
 // (four 16-lane groups with two packed pairs each).
 constexpr int kWaveBuf = 4 * 2 * RefStager<16>::kBuf;
-// One sweep (forward or reverse per P.reverse) of the wave item
+// One sweep (forward, or reverse when REV) of the wave item
 // order[first .. first+count), one pair per W-lane group, int32 arithmetic.
-template <int W, int R>
+template <int W, int R, bool REV>
 __device__ __forceinline__ void sweep_i32(const KParams& P, const SchemeLds& S, uint16_t* wbuf,
                                           int first, int count, int lane) {
     constexpr int G = 64 / W;
     using Stager = RefStager<W>;
-    const int reverse = P.reverse;
+    constexpr int reverse = REV ? 1 : 0;
     const int g = lane / W;
     const int l = lane % W;
 
@@ -109,14 +122,17 @@ __device__ __forceinline__ void sweep_i32(const KParams& P, const SchemeLds& S, 
     const int ge = S.gap_extend[J.sid];
     wave_lds_sync();
 
-    int H[R], E[R], Hm[R], best[R], bj[R];
+    // E[r] holds E of row r at the column the lane sweeps next: it is
+    // advanced right after that row's H is computed, so H - o is never kept
+    int H[R], E[R], best[R], bj[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) { H[r] = 0; E[r] = 0; Hm[r] = 0; best[r] = 0; bj[r] = -1; }
+    for (int r = 0; r < R; ++r) { H[r] = 0; E[r] = 0; best[r] = 0; bj[r] = -1; }
     int Hlast = 0, Flast = 0, Hup_prev = 0;
     const uint16_t* rbl = buf + W - l;   // rbl[tt] = column t0 + tt - l
 
-    // software pipeline: scores of the current step and the matrix row of
-    // the next step are read one step ahead
+    // software pipeline: a row's score for the next step is read as soon as
+    // its score for this step is used, and the matrix row offset of the
+    // next step one step before that
     int sc[R];
     int bb_next = rbl[1];
     {
@@ -132,9 +148,6 @@ __device__ __forceinline__ void sweep_i32(const KParams& P, const SchemeLds& S, 
         const int tn = __builtin_amdgcn_readfirstlane(steps - t0 < kChunk ? steps - t0 : kChunk);
         for (int tt = 0; tt < tn; ++tt) {
             const int bb2 = rbl[tt + 2];
-            int sn[R];
-#pragma unroll
-            for (int r = 0; r < R; ++r) sn[r] = S.mat[bb_next + a[r]];
             const int Hup = shift_in_group<W>(Hlast);
             const int Fup = shift_in_group<W>(Flast);
             int diag = Hup_prev;
@@ -143,20 +156,17 @@ __device__ __forceinline__ void sweep_i32(const KParams& P, const SchemeLds& S, 
             int F = Fup;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                const int en = imax(E[r] - ge, Hm[r]);
                 F = imax(F - ge, Hmu);
-                const int h = imax(imax(diag + sc[r], en), F);
+                const int h = imax(imax(diag + sc[r], E[r]), F);
+                sc[r] = S.mat[bb_next + a[r]];
                 diag = H[r];
                 H[r] = h;
-                E[r] = en;
-                Hm[r] = sat_sub(h, go);
-                Hmu = Hm[r];
+                Hmu = sat_sub(h, go);
+                E[r] = imax(E[r] - ge, Hmu);
                 if (h > best[r]) { best[r] = h; bj[r] = j; }
             }
             Hlast = H[R - 1];
             Flast = F;
-#pragma unroll
-            for (int r = 0; r < R; ++r) sc[r] = sn[r];
             bb_next = bb2;
             ++j;
         }
@@ -205,20 +215,27 @@ __device__ __forceinline__ void sweep_i32(const KParams& P, const SchemeLds& S, 
 
 typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 typedef short s16x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
 
-// Columns are encoded as kColMax - j in the low half of a key; j ranges over
-// -(W-1) .. SW_MAX_REF + W - 2, so kColMax - j stays within 0..65535.
-constexpr int kColMax = 65535 - 64;
+// Columns are encoded as kColMax - j in the low 15 bits of a key; j ranges
+// over -(W-1) .. kI16MaxRef + W - 2, so kColMax - j stays within 0..32767.
+constexpr int kColMax = 32767 - 63;
+static_assert(kI16MaxRef + 64 - 2 <= kColMax, "column field of the keys overflows");
 
 __device__ __forceinline__ uint32_t u32(u16x2 v) { return __builtin_bit_cast(uint32_t, v); }
 __device__ __forceinline__ u16x2 pk(uint32_t v) { return __builtin_bit_cast(u16x2, v); }
 
-// max(x - y, 0) per 16-bit half, for non-negative halves
+// max(x - y, 0) per 16-bit half
 __device__ __forceinline__ u16x2 pk_sat_sub(u16x2 x, u16x2 y) { return __builtin_elementwise_sub_sat(x, y); }
-__device__ __forceinline__ u16x2 pk_max_u(u16x2 x, u16x2 y) { return __builtin_elementwise_max(x, y); }
-__device__ __forceinline__ u16x2 pk_max_s(u16x2 x, u16x2 y) {
-    return __builtin_bit_cast(u16x2, __builtin_elementwise_max(__builtin_bit_cast(s16x2, x),
-                                                               __builtin_bit_cast(s16x2, y)));
+// max of three per 16-bit half, for halves that are positive normal
+// half-precision patterns (see above); one v_pk_maximum3_f16
+__device__ __forceinline__ u16x2 pk_max3(u16x2 x, u16x2 y, u16x2 z) {
+    const f16x2 a = __builtin_bit_cast(f16x2, x), b = __builtin_bit_cast(f16x2, y), c = __builtin_bit_cast(f16x2, z);
+    return __builtin_bit_cast(u16x2, __builtin_elementwise_maximum(__builtin_elementwise_maximum(a, b), c));
+}
+__device__ __forceinline__ uint32_t umax3(uint32_t a, uint32_t b, uint32_t c) {
+    const uint32_t m = a > b ? a : b;
+    return m > c ? m : c;
 }
 
 // Scores of one step for both pairs: low half M[aA][bA], high half M[aB][bB],
@@ -232,12 +249,14 @@ __device__ __forceinline__ u16x2 load_scores(const int8_t* mat, int addrA, int a
 
 // One sweep of the wave item order[first .. first+count), two pairs per
 // W-lane group packed into int16 halves.
-template <int W, int R>
+template <int W, int R, bool REV>
 __device__ __forceinline__ void sweep_i16(const KParams& P, const SchemeLds& S, uint16_t* wbuf,
                                           int first, int count, int lane) {
-    constexpr int G = 64 / W;
     using Stager = RefStager<W>;
-    const int reverse = P.reverse;
+    constexpr int reverse = REV ? 1 : 0;
+    constexpr int RP = (R + 1) / 2;                 // row pairs per lane
+    constexpr uint32_t K = kI16Bias;
+    constexpr uint32_t K2 = K | (K << 16);
     const int g = lane / W;
     const int l = lane % W;
 
@@ -291,18 +310,25 @@ __device__ __forceinline__ void sweep_i16(const KParams& P, const SchemeLds& S, 
     const int AA = S.alphabet[JA.sid], AB = S.alphabet[JB.sid];
     const u16x2 go2 = pk((uint32_t)S.gap_open[JA.sid] | ((uint32_t)S.gap_open[JB.sid] << 16));
     const u16x2 ge2 = pk((uint32_t)S.gap_extend[JA.sid] | ((uint32_t)S.gap_extend[JB.sid] << 16));
+    const u16x2 zero = pk(K2);
     wave_lds_sync();
 
-    u16x2 H[R], E[R], Hm[R];
-    uint32_t kA[R], kB[R];
+    // H[r], E[r] (biased): H of row r at the last column swept, E of row r
+    // at the next column (advanced right after the row's H, so H - o is
+    // never kept).  kA/kB: keys of row pairs.
+    u16x2 H[R], E[R];
+    uint32_t kA[RP], kB[RP];
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        H[r] = pk(0u); E[r] = pk(0u); Hm[r] = pk(0u); kA[r] = 0u; kB[r] = 0u;
-    }
-    uint32_t Hlast = 0, Flast = 0, Hup_prev = 0;
+    for (int r = 0; r < R; ++r) { H[r] = zero; E[r] = zero; }
+#pragma unroll
+    for (int p = 0; p < RP; ++p) { kA[p] = 0u; kB[p] = 0u; }
+    uint32_t Hlast = K2, Flast = K2, Hup_prev = K2;
     const uint16_t* rblA = bufA + W - l;
     const uint16_t* rblB = bufB + W - l;
 
+    // software pipeline: a row's score for the next step is read as soon as
+    // its score for this step is used, and the matrix row offset of the
+    // next step one step before that
     u16x2 sc[R];
     int bbA_next = rblA[1], bbB_next = rblB[1];
     {
@@ -322,36 +348,38 @@ __device__ __forceinline__ void sweep_i16(const KParams& P, const SchemeLds& S, 
         for (int tt = 0; tt < tn; ++tt) {
             const int bbA2 = rblA[tt + 2];
             const int bbB2 = rblB[tt + 2];
-            u16x2 sn[R];
-#pragma unroll
-            for (int r = 0; r < R; ++r)
-                sn[r] = load_scores(S.mat, bbA_next + (int)(apk[r] & 0xFFFF), bbB_next + (int)(apk[r] >> 16));
-            const u16x2 Hup = pk((uint32_t)shift_in_group<W>((int)Hlast));
-            const u16x2 Fup = pk((uint32_t)shift_in_group<W>((int)Flast));
+            const u16x2 Hup = pk((uint32_t)shift_in_group<W>((int)Hlast, (int)K2));
+            const u16x2 Fup = pk((uint32_t)shift_in_group<W>((int)Flast, (int)K2));
             u16x2 diag = pk(Hup_prev);
             Hup_prev = u32(Hup);
             u16x2 Hmu = pk_sat_sub(Hup, go2);
             u16x2 F = Fup;
+            const uint32_t jc1 = jc | 0x8000u;   // upper row of a pair wins ties
+            uint32_t keyA0 = 0, keyB0 = 0;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                const u16x2 en = pk_max_u(pk_sat_sub(E[r], ge2), Hm[r]);
-                F = pk_max_u(pk_sat_sub(F, ge2), Hmu);
-                const u16x2 h = pk_max_s(pk_max_s(diag + sc[r], en), F);
+                F = pk_max3(pk_sat_sub(F, ge2), Hmu, zero);
+                const u16x2 h = pk_max3(diag + sc[r], E[r], F);
+                sc[r] = load_scores(S.mat, bbA_next + (int)(apk[r] & 0xFFFF), bbB_next + (int)(apk[r] >> 16));
                 diag = H[r];
                 H[r] = h;
-                E[r] = en;
-                Hm[r] = pk_sat_sub(h, go2);
-                Hmu = Hm[r];
+                Hmu = pk_sat_sub(h, go2);
+                E[r] = pk_max3(pk_sat_sub(E[r], ge2), Hmu, zero);
                 const uint32_t hv = u32(h);
-                const uint32_t keyA = (hv << 16) | jc;
-                const uint32_t keyB = (hv & 0xFFFF0000u) | jc;
-                kA[r] = kA[r] > keyA ? kA[r] : keyA;
-                kB[r] = kB[r] > keyB ? kB[r] : keyB;
+                if ((r & 1) == 0) {
+                    keyA0 = (hv << 16) | jc1;
+                    keyB0 = (hv & 0xFFFF0000u) | jc1;
+                    if (r == R - 1) {
+                        kA[r / 2] = kA[r / 2] > keyA0 ? kA[r / 2] : keyA0;
+                        kB[r / 2] = kB[r / 2] > keyB0 ? kB[r / 2] : keyB0;
+                    }
+                } else {
+                    kA[r / 2] = umax3(kA[r / 2], keyA0, (hv << 16) | jc);
+                    kB[r / 2] = umax3(kB[r / 2], keyB0, (hv & 0xFFFF0000u) | jc);
+                }
             }
             Hlast = u32(H[R - 1]);
             Flast = u32(F);
-#pragma unroll
-            for (int r = 0; r < R; ++r) sc[r] = sn[r];
             bbA_next = bbA2;
             bbB_next = bbB2;
             --jc;
@@ -372,12 +400,17 @@ __device__ __forceinline__ void sweep_i16(const KParams& P, const SchemeLds& S, 
     if (bad && P.validate) atomicOr(&P.flags[kFlagBadResidue], 1);
 
     // per pair: best of this lane in row-major order, then of the group
+    // (scores unbiased; a best of 0 leaves the coordinates at -1)
     int lb[2] = {0, 0}, li[2] = {-1, -1}, lj[2] = {-1, -1};
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int hA = (int)(kA[r] >> 16), hB = (int)(kB[r] >> 16);
-        if (hA > lb[0]) { lb[0] = hA; li[0] = l * R + r; lj[0] = kColMax - (int)(kA[r] & 0xFFFF); }
-        if (hB > lb[1]) { lb[1] = hB; li[1] = l * R + r; lj[1] = kColMax - (int)(kB[r] & 0xFFFF); }
+    for (int p = 0; p < RP; ++p) {
+        const uint32_t ks[2] = {kA[p], kB[p]};
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int h = (int)(ks[q] >> 16) - (int)K;
+            const int row = l * R + 2 * p + ((ks[q] & 0x8000u) ? 0 : 1);
+            if (h > lb[q]) { lb[q] = h; li[q] = row; lj[q] = kColMax - (int)(ks[q] & 0x7FFFu); }
+        }
     }
 #pragma unroll
     for (int p = 0; p < 2; ++p) {

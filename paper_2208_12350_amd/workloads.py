@@ -371,21 +371,31 @@ class Request:
     batch: Batch
 
 
+def serving_requests(n_requests: int, seed: Optional[int] = None, max_pairs: int = 5000) -> List[Batch]:
+    """The request bodies of a serving stream: each a batch of U{1..max_pairs}
+    pairs from the mixed draw with its own seed; all share one protein
+    scheme, drawn from the stream's base seed."""
+    base = BASE_SEED + WORKLOADS.index("serving") if seed is None else seed
+    rng = np.random.default_rng(base)
+    sizes = rng.integers(1, max_pairs + 1, size=n_requests)
+    return [make_workload("mixed", n_pairs=int(s), seed=base * 1000 + k, scheme_seed=base)
+            for k, s in enumerate(sizes)]
+
+
+def poisson_arrivals(n: int, rate_per_s: float, seed: int) -> np.ndarray:
+    """Arrival times (seconds from 0) of a Poisson process of the given rate."""
+    rng = np.random.default_rng(seed)
+    return np.cumsum(rng.exponential(1.0 / rate_per_s, size=n))
+
+
 def serving_stream(offered_cells_per_ms: float, n_requests: int, seed: Optional[int] = None,
                    max_pairs: int = 5000) -> List[Request]:
     """Poisson stream of requests at the offered load.  Each request is a
     batch of U{1..max_pairs} pairs from the mixed draw with its own seed; the
     arrival rate is the offered load divided by the mean cells per request."""
     base = BASE_SEED + WORKLOADS.index("serving") if seed is None else seed
-    rng = np.random.default_rng(base)
-    reqs = []
-    sizes = rng.integers(1, max_pairs + 1, size=n_requests)
-    batches = [make_workload("mixed", n_pairs=int(s), seed=base * 1000 + k, scheme_seed=base)
-               for k, s in enumerate(sizes)]
+    batches = serving_requests(n_requests, base, max_pairs)
     mean_cells = float(np.mean([b.cells() for b in batches]))
     lam = offered_cells_per_ms * 1e3 / mean_cells  # requests per second
-    gaps = rng.exponential(1.0 / lam, size=n_requests)
-    t = np.cumsum(gaps)
-    for k in range(n_requests):
-        reqs.append(Request(float(t[k]), batches[k]))
-    return reqs
+    t = poisson_arrivals(n_requests, lam, base + 1)
+    return [Request(float(t[k]), batches[k]) for k in range(n_requests)]

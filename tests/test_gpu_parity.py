@@ -256,3 +256,135 @@ def test_plain_persistent_and_graph_modes_agree():
         finally:
             al.close()
     assert results["plain"] == results["persistent"] == results["graph"]
+
+
+@pytest.mark.gpu
+def test_streams_and_per_launch_timing_agree():
+    """Persistent launches over 1..4 streams and the serialised per-launch
+    timing mode give the same bits; per-launch statistics add up to the
+    call's totals (cells per pass, one pair per non-trivial pair)."""
+    import torch
+    from paper_2208_12350_amd.binding import Aligner, DeviceBatch
+    b = W.make_workload("mixed", n_pairs=1800, seed=5151)
+    db = DeviceBatch.from_host(b)
+    want = O.align_batch(b)
+    want_arr = np.stack([want[f] for f in FIELDS], axis=1)
+    nontrivial = int(np.sum((b.q_len() > 0) & (b.r_len() > 0)))
+    positive = int(np.sum(want["score"] > 0))
+    for opts in (dict(streams=1), dict(streams=2), dict(streams=4), dict(timing=2),
+                 dict(mode=0, graph=0, timing=2)):
+        al = Aligner(0, **opts)
+        try:
+            out = torch.full((b.n_pairs, 5), -7, dtype=torch.int32, device="cuda:0")
+            al.align(db, out)
+            assert np.array_equal(out.cpu().numpy(), want_arr), opts
+            fwd, rev, _ = al.stats()
+            st = al.bin_stats()
+            assert sum(e["cells"] for e in st if e["pass"] == 0) == fwd
+            assert sum(e["cells"] for e in st if e["pass"] == 1) == rev
+            assert sum(e["pairs"] for e in st if e["pass"] == 0) == nontrivial
+            assert sum(e["pairs"] for e in st if e["pass"] == 1) == positive
+            if opts.get("timing") == 2:
+                assert all(e["ms"] > 0 for e in st if e["pairs"] > 0), opts
+            else:
+                assert all(e["ms"] == 0 for e in st)
+        finally:
+            al.close()
+
+
+def _routing(widths):
+    """A routing table that, for each 16-row bucket, uses the first listed
+    group width whose compiled shapes cover it, with the smallest R."""
+    R_OF = {16: range(1, 17), 32: range(5, 17), 64: range(9, 33)}
+    table = []
+    for hi in range(16, 2049, 16):
+        for w in widths:
+            rs = [r for r in R_OF[w] if w * r >= hi]
+            if rs:
+                table.append((hi, w, rs[0]))
+                break
+    return table
+
+
+@pytest.mark.gpu
+def test_routing_choices_agree():
+    """Results never depend on which shape sweeps a pair: 16-, 32- and
+    64-lane routings all reproduce the oracle."""
+    import torch
+    from paper_2208_12350_amd.binding import Aligner, DeviceBatch
+    b = W.make_workload("mixed", n_pairs=1500, seed=6161)
+    db = DeviceBatch.from_host(b)
+    want = O.align_batch(b)
+    want_arr = np.stack([want[f] for f in FIELDS], axis=1)
+    al = Aligner(0)
+    try:
+        default = al.routing(16)
+        assert default[-1][0] == 2048
+        for widths in ((64,), (32, 64), (16, 32, 64), (16, 64)):
+            al.set_routing(16, _routing(widths))
+            got_table = al.routing(16)
+            assert got_table[-1][0] == 2048
+            out = torch.full((b.n_pairs, 5), -7, dtype=torch.int32, device="cuda:0")
+            al.align(db, out)
+            assert np.array_equal(out.cpu().numpy(), want_arr), widths
+            used = {(e["lanes"], e["rows"]) for e in al.bin_stats() if e["pairs"] > 0 and e["precision"] == 16}
+            assert {w for w, _ in used} <= set(widths), (widths, used)
+        al.set_routing(16, [])
+        assert al.routing(16) == default
+    finally:
+        al.close()
+
+
+@pytest.mark.gpu
+def test_routing_rejects_bad_tables():
+    from paper_2208_12350_amd.binding import Aligner, SwError
+    al = Aligner(0)
+    try:
+        before = al.routing(16)
+        for bad in ([(2048, 16, 16)],                       # 256 rows cannot cover 2048
+                    [(1024, 64, 16), (512, 64, 32)],         # rows_max decreasing
+                    [(1000, 64, 16), (2048, 64, 32)],        # not a multiple of 16
+                    [(1024, 64, 16)],                        # does not reach 2048
+                    [(2048, 64, 33)],                        # not compiled
+                    [(2048, 48, 48)]):                       # not compiled
+            with pytest.raises(SwError):
+                al.set_routing(16, bad)
+            assert al.routing(16) == before
+        with pytest.raises(SwError):
+            al.set_routing(8, [(2048, 64, 32)])
+    finally:
+        al.close()
+
+
+@pytest.mark.gpu
+def test_int16_range_edges(aligner):
+    """Pairs at the edges of the packed path's range: int8 extreme scores
+    (+127 / -128, gap open 127) with min(n, m) * 127 just below and just
+    above the int16 bound, and references just below and above the packed
+    path's length limit.  Every pair must match the oracle, and exactly the
+    pairs beyond a bound take the int32 path."""
+    A = 4
+    mat = np.full((A, A), -128, dtype=np.int8)
+    np.fill_diagonal(mat, 127)
+    ext = W.Scheme(np.ascontiguousarray(mat), 127, 1, "extreme")
+    rng = np.random.default_rng(99)
+    lim_n = 30592 // 127                     # 240: the longest query on the packed path
+    pairs, expect_i32 = [], 0
+    for n in (lim_n - 1, lim_n, lim_n + 1, lim_n + 2):
+        q = rng.integers(0, A, size=n).astype(np.uint8)
+        pairs.append((q, q.copy()))                                   # self-alignment: S = 127 n
+        r = np.concatenate([rng.integers(0, A, size=30), q, rng.integers(0, A, size=17)]).astype(np.uint8)
+        pairs.append((q, r))
+        expect_i32 += 2 if n > lim_n else 0
+    for m in (31999, 32000, 32001, 40000, 60000):
+        q = rng.integers(0, A, size=60).astype(np.uint8)
+        r = rng.integers(0, A, size=m).astype(np.uint8)
+        r[m // 3:m // 3 + 60] = q
+        pairs.append((q, r))
+        expect_i32 += 1 if m > 32000 else 0
+    b = W.from_pairs(pairs, [0] * len(pairs), [ext])
+    g = run_gpu(aligner, b)
+    assert aligner.stats()[2] == expect_i32
+    want = O.align_batch(b)
+    assert_same(g, want, b)
+    assert g[0, 0] == 127 * (lim_n - 1) and g[2, 0] == 127 * lim_n

@@ -34,6 +34,44 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def stored_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` on `workload` from a committed
+    counter summary (profiles/*_traffic.txt), or None when there is none or
+    when the kernel sources changed since the counters were taken."""
+    import glob
+    import hashlib
+    here = os.path.join(ROOT, "profiles")
+    for path in sorted(glob.glob(os.path.join(here, "*_traffic.txt"))):
+        kv = {}
+        with open(path) as f:
+            for line in f:
+                if ":" in line and not line.startswith("#"):
+                    k, v = line.split(":", 1)
+                    kv[k.strip()] = v.strip()
+        if kv.get("kernel") != kernel or kv.get("workload") != workload:
+            continue
+        if kv.get("sources_sha256") != kernel_sources_sha256():
+            return None
+        try:
+            return float(kv["traffic_bytes_per_launch"])
+        except (KeyError, ValueError):
+            return None
+    return None
+
+
+def kernel_sources_sha256():
+    """Digest of the HIP sources the sweep kernels are built from."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2208_12350_amd", "csrc")
+    for path in sorted(glob.glob(os.path.join(csrc, "*.h")) + glob.glob(os.path.join(csrc, "sw_queue*.hip"))):
+        h.update(os.path.basename(path).encode())
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
 def cpu_baseline(batch, target_s=12.0):
     """Time the CPU oracle (as it stands) on a bounded random sample of the
     same workload using the host cores available to this process."""
@@ -63,6 +101,51 @@ def cpu_baseline(batch, target_s=12.0):
     return {"value": round(cells / dt / 1e9, 4), "unit": "GCUPS", "cores": cores, "kind": "oracle",
             "sample": "%d random pairs of the same workload (%.3g forward cells, forward+reverse "
                       "sweeps, %.1f s on %d threads)" % (n1, cells, dt, cores)}
+
+
+def roofline_leg(args, db, out, tuning, mode):
+    """The sweep launches serialised on one stream with a HIP event pair
+    around each (library option timing=2) and cells per launch from the
+    device counters.  The dominant kernel is the (pass, shape) launch with
+    the most device time; achieved = 12 * its cells / its average time."""
+    from paper_2208_12350_amd.binding import Aligner
+    alr = Aligner(0, tuning, mode=mode, graph=0, timing=2)
+    per_launch = {}
+    roof_steps = max(3, min(args.steps, 10))
+    for k in range(roof_steps + 1):
+        alr.align(db, out)
+        if k:
+            for e in alr.bin_stats():
+                key = (e["pass"], e["precision"], e["lanes"], e["rows"])
+                acc = per_launch.setdefault(key, [0.0, 0, 0])
+                acc[0] += e["ms"]; acc[1] += e["cells"]; acc[2] += 1
+    alr.close()
+    (dpass, dprec, dlanes, drows), (dms, dcells, dn) = max(per_launch.items(), key=lambda kv: kv[1][0])
+    launch_ms = dms / dn
+    cells_per_launch = dcells / dn
+    peak = VALU_INT16X2_TOPS if dprec == 16 else VALU_INT32_TOPS
+    achieved = OPS_PER_CELL * cells_per_launch / (launch_ms / 1e3) / 1e12
+    # every sweep launch of a step together, each at its own precision's peak
+    fam_ms = sum(v[0] for v in per_launch.values()) / roof_steps
+    fam_ops = OPS_PER_CELL * sum(v[1] for v in per_launch.values()) / roof_steps
+    fam_peak_s = sum(OPS_PER_CELL * v[1] / roof_steps / ((VALU_INT16X2_TOPS if k[1] == 16 else VALU_INT32_TOPS) * 1e12)
+                     for k, v in per_launch.items())
+    kernel_name = "sw::sw_queue_kernel<%d, %d, %d, %s>" % (dprec, dlanes, drows, "true" if dpass else "false")
+    return {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 2),
+            "unit": "Tops/s", "frac": round(achieved / peak, 4),
+            "traffic": stored_traffic(kernel_name, args.workload),
+            "kernel": kernel_name, "launches": dn, "launch_ms": round(launch_ms, 4),
+            "cells_per_launch": int(cells_per_launch), "ops_per_cell": OPS_PER_CELL,
+            "all_sweeps": {"ms": round(fam_ms, 3), "achieved": round(fam_ops / (fam_ms / 1e3) / 1e12, 3),
+                           "frac": round(fam_peak_s / (fam_ms / 1e3), 4)}}
+
+
+def roofline_only(args, batch, db, out, tuning, mode):
+    """Only the roofline leg (for profiling it alone): one JSON line."""
+    roof = roofline_leg(args, db, out, tuning, mode)
+    print(json.dumps({"leg": "roofline", "config": {"workload": args.workload, "pairs": batch.n_pairs,
+                                                    "routing": tuning or "built-in"},
+                      "roofline": roof}), flush=True)
 
 
 def serving_bench(args):
@@ -113,6 +196,7 @@ def serving_bench(args):
                 lat[k] = ms + lags[k] * 1e3
 
         before = srv.stats()
+        tb = srv.timing()
         th = threading.Thread(target=collect)
         th.start()
         t0 = time.perf_counter()
@@ -129,6 +213,7 @@ def serving_bench(args):
         if errors:
             raise RuntimeError("serving requests failed: %s" % errors[:3])
         after = srv.stats()
+        ta = srv.timing()
         span = max(done) - t0
         total = float(cells[which].sum())
         batches = after["batches"] - before["batches"]
@@ -136,6 +221,8 @@ def serving_bench(args):
               "sustained_gcups": round(total / span / 1e9, 2), "span_s": round(span, 3),
               "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
               "requests_per_batch": round(n / max(1, batches), 2),
+              "admit_ms_per_request": round((ta["admit_ms"] - tb["admit_ms"]) / n, 3),
+              "align_ms_per_batch": round((ta["align_ms"] - tb["align_ms"]) / max(1, batches), 3),
               "submit_lag_p99_ms": round(float(np.percentile(lags, 99)) * 1e3, 3)}
         log("  load %g M cells/ms: %s" % (load, pt))
         points.append(pt)
@@ -166,6 +253,11 @@ def main():
     ap.add_argument("--mode", type=int, default=None, help="0 = per-bin launches, 1 = persistent")
     ap.add_argument("--streams", type=int, default=4, help="streams the persistent launches spread over")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="keep the built-in routing")
+    ap.add_argument("--routing", default=None, help="use this routing string instead of tuning")
+    ap.add_argument("--roofline-only", action="store_true", help="run only the per-launch roofline leg")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first copy 1 GiB device to device three times (counter calibration)")
     ap.add_argument("--loads", default="1,2,5,10,20,50,100,200,500,1000,2000",
                     help="serving: offered loads in M cells/ms")
     ap.add_argument("--window-s", type=float, default=6.0, help="serving: seconds of arrivals per load")
@@ -197,6 +289,27 @@ def main():
     db = DeviceBatch.from_host(batch, dev)
     out = torch.empty((batch.n_pairs, 5), dtype=torch.int32, device=dev)
 
+    # routing autotuner (untimed): per-shape rates from probe launches, then
+    # the routing that minimises the predicted sweep time of a sample
+    tuning, tune_s = args.routing, 0.0
+    if args.calibrate_copy:
+        # a plain copy of known size, for scaling HBM byte counters
+        src = torch.empty(1 << 30, dtype=torch.uint8, device=dev).fill_(1)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    if tuning is None and not args.no_tune:
+        from paper_2208_12350_amd import autotune as T
+        from paper_2208_12350_amd.binding import routing_string
+        log("autotuning the routing ...")
+        rng = np.random.default_rng(5)
+        idx = rng.choice(batch.n_pairs, size=min(batch.n_pairs, 50000), replace=False)
+        table, _, tune_s = T.tune(batch.q_len()[idx], batch.r_len()[idx], 0, 16, log=log)
+        tuning = routing_string(16, table)
+        log("  %s (%.1f s)" % (tuning, tune_s))
+
     def timed(al, steps, warmup, what):
         for k in range(warmup):
             al.align(db, out)
@@ -212,16 +325,20 @@ def main():
         log("  %s: %d steps in %.3f s" % (what, steps, el))
         return el, step_ms
 
-    # headline: persistent work-queue launch, replayed from a captured hipGraph
     mode = 1 if args.mode is None else args.mode
-    al = Aligner(0, mode=mode, graph=1 if mode == 1 else 0, streams=args.streams)
+    if args.roofline_only:
+        roofline_only(args, batch, db, out, tuning, mode)
+        return
+
+    # headline: persistent work-queue launch, replayed from a captured hipGraph
+    al = Aligner(0, tuning, mode=mode, graph=1 if mode == 1 else 0, streams=args.streams)
     elapsed, step_ms = timed(al, args.steps, args.warmup, "mode %d" % mode)
     ref_out = out.clone()
     fwd_cells, rev_cells, i32_pairs = al.stats()
     al.close()
 
     # same call with HIP events around the phases (no graph replay)
-    alt = Aligner(0, mode=mode, graph=0, timing=1, streams=args.streams)
+    alt = Aligner(0, tuning, mode=mode, graph=0, timing=1, streams=args.streams)
     plan_ms, fwd_ms, rev_ms = [], [], []
     for k in range(max(3, min(args.steps, 10)) + 1):
         alt.align(db, out)
@@ -231,25 +348,13 @@ def main():
     alt.close()
     assert torch.equal(out, ref_out), "timing run disagrees with the headline run"
 
-    # roofline leg: the sweep launches serialised on one stream, a HIP event
-    # pair around each, cells per launch from the device counters
-    alr = Aligner(0, mode=mode, graph=0, timing=2)
-    per_launch = {}
-    roof_steps = max(3, min(args.steps, 10))
-    for k in range(roof_steps + 1):
-        alr.align(db, out)
-        if k:
-            for e in alr.bin_stats():
-                key = (e["pass"], e["precision"], e["lanes"], e["rows"])
-                acc = per_launch.setdefault(key, [0.0, 0, 0])
-                acc[0] += e["ms"]; acc[1] += e["cells"]; acc[2] += 1
-    alr.close()
+    roof = roofline_leg(args, db, out, tuning, mode)
     assert torch.equal(out, ref_out), "roofline run disagrees with the headline run"
 
     # plain per-bin launches on the same data
     plain = None
     if mode == 1:
-        alp = Aligner(0, mode=0, graph=0)
+        alp = Aligner(0, tuning, mode=0, graph=0)
         el_p, _ = timed(alp, max(2, min(args.steps, 5)), 1, "plain per-bin launches")
         alp.close()
         assert torch.equal(out, ref_out), "plain launches disagree with the persistent launch"
@@ -258,18 +363,6 @@ def main():
     ms_per_step = elapsed * 1e3 / args.steps
     gcups = fwd_cells * args.steps / elapsed / 1e9
     int16 = i32_pairs < batch.n_pairs
-    # dominant kernel: the (pass, shape) launch with the most device time
-    (dpass, dprec, dlanes, drows), (dms, dcells, dn) = max(per_launch.items(), key=lambda kv: kv[1][0])
-    launch_ms = dms / dn
-    cells_per_launch = dcells / dn
-    peak = VALU_INT16X2_TOPS if dprec == 16 else VALU_INT32_TOPS
-    achieved = OPS_PER_CELL * cells_per_launch / (launch_ms / 1e3) / 1e12
-    # every sweep launch together, each at its own precision's peak
-    fam_ms = sum(v[0] for v in per_launch.values()) / roof_steps
-    fam_ops = OPS_PER_CELL * sum(v[1] for v in per_launch.values()) / roof_steps
-    fam_peak_s = sum(OPS_PER_CELL * v[1] / roof_steps / ((VALU_INT16X2_TOPS if k[1] == 16 else VALU_INT32_TOPS) * 1e12)
-                     for k, v in per_launch.items())
-    kernel_name = "sw::sw_queue_kernel<%d, %d, %d, %s>" % (dprec, dlanes, drows, "true" if dpass else "false")
     res = {
         "metric": "GCUPS, batched affine SW (score+coords), batched vs plain; p50/p99 latency",
         "value": round(gcups, 2),
@@ -286,18 +379,14 @@ def main():
         "config": {"workload": args.workload, "pairs": batch.n_pairs, "forward_cells": int(fwd_cells),
                    "reverse_cells": int(rev_cells), "int32_pairs": int(i32_pairs),
                    "mode": "persistent+graph" if mode == 1 else "plain per-bin launches",
-                   "streams": args.streams if mode == 1 else 1},
+                   "streams": args.streams if mode == 1 else 1,
+                   "routing": tuning or "built-in", "tuning_s": round(tune_s, 2)},
         "plain_value": plain,
         "latency_ms": {"p50": round(float(np.percentile(step_ms, 50)), 3),
                        "p99": round(float(np.percentile(step_ms, 99)), 3)},
         "phase_ms": {"plan": round(float(np.mean(plan_ms)), 3), "forward": round(float(np.mean(fwd_ms)), 3),
                      "reverse": round(float(np.mean(rev_ms)), 3)},
-        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 2),
-                     "unit": "Tops/s", "frac": round(achieved / peak, 4), "traffic": None,
-                     "kernel": kernel_name, "launch_ms": round(launch_ms, 4),
-                     "cells_per_launch": int(cells_per_launch), "ops_per_cell": OPS_PER_CELL,
-                     "all_sweeps": {"ms": round(fam_ms, 3), "achieved": round(fam_ops / (fam_ms / 1e3) / 1e12, 3),
-                                    "frac": round(fam_peak_s / (fam_ms / 1e3), 4)}},
+        "roofline": roof,
     }
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a sample ...")

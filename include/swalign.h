@@ -103,7 +103,9 @@ const char* sw_last_error(sw_handle* h);
 /* Set a tuning or behaviour option (integer valued):
  *   "mode"      0 = one plain launch per length bin, 1 = persistent launch
  *               over a device work queue (default 1)
- *   "graph"     1 = replay a captured hipGraph for repeated batch shapes
+ *   "graph"     1 = capture the call into a hipGraph and replay it while
+ *               the buffers, schemes and options stay the same (the batch
+ *               size may change up to the capacity); default 1
  *   "validate"  1 = check residue codes (default 1); invalid residues make
  *               the call return SW_EINVAL (results of those pairs undefined)
  *   "precision" 0 = automatic routing (default): a pair runs on the packed
@@ -116,11 +118,19 @@ const char* sw_last_error(sw_handle* h);
  *               2 = also around every sweep kernel launch, with the
  *               launches serialised on the caller's stream (read back with
  *               sw_last_bin_stats).  Timing turns graph replay off.
+ *   "capacity"  reserve workspace for this many pairs now (it otherwise
+ *               grows to the largest batch seen).  Launch grids and captured
+ *               graphs are sized for the capacity and read the batch size
+ *               from device memory, so one graph serves every batch with the
+ *               same buffers and at most that many pairs
  *   "streams"   1..4: persistent mode spreads the bins' kernels over this
  *               many streams forked from (and joined back into) the
  *               caller's stream (default 4)
  * Returns SW_OK or SW_EINVAL for an unknown key / bad value. */
 int sw_set_option(sw_handle* h, const char* key, int64_t value);
+/* Read an option, or the read-only "captures" (graphs captured so far) and
+ * "capture_refusals" (captures the runtime refused; those calls ran their
+ * kernels without a graph). */
 int sw_get_option(sw_handle* h, const char* key, int64_t* value);
 
 /* Align every pair of `batch` and write out[i] (a DEVICE pointer to
@@ -157,6 +167,12 @@ int sw_last_stats(sw_handle* h, int64_t* fwd_cells, int64_t* rev_cells, int64_t*
  * forward / reverse = the forward and reverse sweeps (every launch of each).
  * Any pointer may be NULL. */
 int sw_last_timing(sw_handle* h, float* plan_ms, float* forward_ms, float* reverse_ms);
+
+/* Host wall time in milliseconds of the last call: from entry until all its
+ * work was enqueued (argument checks, planning launches, sweep launches or
+ * graph launch), and the wait for the device after that.  Always recorded;
+ * any pointer may be NULL. */
+int sw_last_host_timing(sw_handle* h, double* enqueue_ms, double* wait_ms);
 
 /* ---- routing: which sweep shape aligns which query length -------------
  *
@@ -245,6 +261,11 @@ int sw_server_poll(sw_server* s, uint64_t ticket, sw_result* out, int wait, doub
  * launched and pairs aligned.  Any pointer may be NULL. */
 int sw_server_stats(sw_server* s, int64_t* pool_peak_bytes, int64_t* pool_capacity, int64_t* requests_done,
                     int64_t* batches, int64_t* pairs_done);
+
+/* Cumulative wall time in milliseconds the server spent admitting requests
+ * (staging and copying them into the pool), aligning merged batches, and
+ * fetching their results to the host.  Any pointer may be NULL. */
+int sw_server_timing(sw_server* s, double* admit_ms, double* align_ms, double* fetch_ms);
 
 #ifdef __cplusplus
 }

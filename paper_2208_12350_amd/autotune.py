@@ -1,0 +1,176 @@
+"""Autotuner for the sweep routing: which shape (lanes per pair W, query rows
+per lane R) aligns which query lengths, i.e. the group width, the tile
+height and the bin edges of the length binning.
+
+Two steps:
+
+1. ``measure_rates``: every compiled shape of a precision sweeps a
+   homogeneous probe batch (queries of exactly W*R residues, references of
+   a given length) with a routing that sends the probe to that shape; the
+   per-launch HIP-event time of the forward sweep gives the shape's rate in
+   lane-row slots per millisecond.  A slot is one (row, column) position a
+   lane group sweeps, padding included: a pair of n rows and m columns on
+   shape (W, R) costs W * R * (m + W - 1) slots.
+2. ``choose_routing``: for each 16-row bucket of query lengths, the covering
+   shape with the least predicted time for the pairs of that bucket in a
+   sample of the workload, time = slots / rate.  Pure host arithmetic, so it
+   is tested without a GPU.
+
+The result is a routing table [(rows_max, W, R), ...] for
+``Aligner.set_routing`` or, as a string, for the tuning argument of
+``sw_create``.  Results never depend on the routing; only speed does.
+"""
+from __future__ import annotations
+
+import time
+from typing import Dict, List, Optional, Sequence, Tuple
+
+import numpy as np
+
+MAX_QUERY = 2048
+BUCKET = 16
+
+Shape = Tuple[int, int]          # (W, R)
+Table = List[Tuple[int, int, int]]
+
+
+def slots(m: np.ndarray, shape: Shape) -> np.ndarray:
+    """Lane-row slots a group of shape (W, R) sweeps for pairs with
+    references of m residues (their query must fit in W * R rows)."""
+    W, R = shape
+    return W * R * (np.asarray(m, dtype=np.float64) + W - 1)
+
+
+def choose_routing(q_len: np.ndarray, r_len: np.ndarray, rates: Dict[Shape, float],
+                   default_m: float = 512.0) -> Table:
+    """Routing table minimising the predicted sweep time of the sample
+    (q_len, r_len) under per-shape rates (slots per ms).  Buckets with no
+    sample pair use a reference length of twice the bucket's rows plus 64
+    (or ``default_m``, whichever is larger)."""
+    if not rates:
+        raise ValueError("no shape rates")
+    q_len = np.asarray(q_len, dtype=np.int64)
+    r_len = np.asarray(r_len, dtype=np.int64)
+    keep = (q_len > 0) & (r_len > 0)
+    q_len, r_len = q_len[keep], r_len[keep]
+    bucket = (np.minimum(q_len, MAX_QUERY) - 1) // BUCKET
+    choice = []
+    for k in range(MAX_QUERY // BUCKET):
+        rows = BUCKET * (k + 1)
+        m = r_len[bucket == k]
+        if m.size == 0:
+            m = np.array([max(default_m, 2.0 * rows + 64)])
+        best, best_t = None, None
+        for shape, rate in rates.items():
+            W, R = shape
+            if W * R < rows or rate <= 0:
+                continue
+            t = float(np.sum(slots(m, shape))) / rate
+            if best is None or t < best_t or (t == best_t and W * R < best[0] * best[1]):
+                best, best_t = shape, t
+        if best is None:
+            raise ValueError("no measured shape covers %d rows" % rows)
+        choice.append(best)
+    return merge(choice)
+
+
+def merge(choice: Sequence[Shape]) -> Table:
+    """Per-bucket shapes -> routing table of merged runs."""
+    table: Table = []
+    for k, (W, R) in enumerate(choice):
+        hi = BUCKET * (k + 1)
+        if table and (table[-1][1], table[-1][2]) == (W, R):
+            table[-1] = (hi, W, R)
+        else:
+            table.append((hi, W, R))
+    return table
+
+
+def expand(table: Table) -> List[Shape]:
+    """Routing table -> the shape of every 16-row bucket."""
+    out, prev = [], 0
+    for hi, W, R in table:
+        out.extend([(W, R)] * ((hi - prev) // BUCKET))
+        prev = hi
+    return out
+
+
+def predicted_ms(q_len, r_len, table: Table, rates: Dict[Shape, float]) -> float:
+    """Predicted sweep time of a sample under a routing table."""
+    shapes = expand(table)
+    q_len = np.asarray(q_len, dtype=np.int64)
+    r_len = np.asarray(r_len, dtype=np.int64)
+    keep = (q_len > 0) & (r_len > 0)
+    q_len, r_len = q_len[keep], r_len[keep]
+    bucket = (np.minimum(q_len, MAX_QUERY) - 1) // BUCKET
+    total = 0.0
+    for k, shape in enumerate(shapes):
+        m = r_len[bucket == k]
+        if m.size:
+            total += float(np.sum(slots(m, shape))) / rates[shape]
+    return total
+
+
+def _probe_batch(W: int, R: int, m: int, n_pairs: int, seed: int):
+    from . import workloads as WL
+    rng = np.random.default_rng(seed)
+    n = W * R
+    q = rng.integers(0, 4, size=n_pairs * n).astype(np.uint8)
+    r = rng.integers(0, 4, size=n_pairs * m).astype(np.uint8)
+    q_off = np.arange(n_pairs + 1, dtype=np.int64) * n
+    r_off = np.arange(n_pairs + 1, dtype=np.int64) * m
+    return WL.Batch(q, q_off, r, r_off, np.zeros(n_pairs, np.uint8), [WL.dna_scheme()], "probe", seed)
+
+
+def measure_rates(device: int = 0, precision: int = 16, m: int = 512, target_cells: float = 4e9,
+                  repeats: int = 2, shapes: Optional[Sequence[Shape]] = None,
+                  log=None) -> Dict[Shape, float]:
+    """Slots per millisecond of the forward sweep of every compiled shape of
+    `precision` (or of `shapes`), from per-launch HIP-event timing."""
+    import torch
+    from .binding import Aligner, DeviceBatch
+
+    al = Aligner(device, timing=2, precision=32 if precision == 32 else 0)
+    try:
+        compiled = [(w, r) for p, w, r in al.shapes() if p == precision]
+        todo = list(shapes) if shapes is not None else compiled
+        big = max(compiled, key=lambda s: s[0] * s[1])
+        rates: Dict[Shape, float] = {}
+        for W, R in todo:
+            ppw = (64 // W) * (2 if precision == 16 else 1)
+            n_pairs = int(np.clip(target_cells / (W * R * m), 2048 * ppw // 4, 400_000))
+            n_pairs -= n_pairs % ppw
+            b = _probe_batch(W, R, m, n_pairs, seed=W * 1000 + R)
+            db = DeviceBatch.from_host(b, "cuda:%d" % device)
+            out = torch.empty((n_pairs, 5), dtype=torch.int32, device="cuda:%d" % device)
+            table = [(W * R, W, R)]
+            if W * R < MAX_QUERY:
+                table.append((MAX_QUERY, big[0], big[1]))
+            al.set_routing(precision, table)
+            ms = []
+            for k in range(repeats + 1):
+                al.align(db, out)
+                if k:
+                    for e in al.bin_stats():
+                        if (e["pass"], e["precision"], e["lanes"], e["rows"]) == (0, precision, W, R):
+                            ms.append(e["ms"])
+            t = float(np.median(ms))
+            rates[(W, R)] = float(np.sum(slots(np.full(n_pairs, m), (W, R)))) / t
+            if log:
+                log("  shape %dx%d: %d pairs, %.3f ms, %.3g slots/ms" % (W, R, n_pairs, t, rates[(W, R)]))
+            del db, out
+        al.set_routing(precision, [])
+        return rates
+    finally:
+        al.close()
+
+
+def tune(q_len, r_len, device: int = 0, precision: int = 16, log=None, **kw):
+    """Measure the shapes and choose a routing for the sample (q_len, r_len).
+    Returns (table, rates, seconds spent)."""
+    t0 = time.time()
+    m = int(np.clip(np.median(np.asarray(r_len)[np.asarray(r_len) > 0]) if np.any(np.asarray(r_len) > 0) else 512,
+                    64, 4096))
+    rates = measure_rates(device, precision, m=m, log=log, **kw)
+    table = choose_routing(q_len, r_len, rates)
+    return table, rates, time.time() - t0

@@ -33,10 +33,10 @@ _ERRNAMES = {SW_EINVAL: "SW_EINVAL", SW_ENOMEM: "SW_ENOMEM", SW_ETOOLONG: "SW_ET
              SW_EDEVICE: "SW_EDEVICE", SW_EINTERNAL: "SW_EINTERNAL"}
 
 EXPORTED = ("sw_create", "sw_destroy", "sw_last_error", "sw_set_option", "sw_get_option",
-            "sw_align_batch", "sw_align_spans", "sw_last_stats", "sw_last_timing", "sw_last_bin_stats",
+            "sw_align_batch", "sw_align_spans", "sw_last_stats", "sw_last_timing", "sw_last_host_timing", "sw_last_bin_stats",
             "sw_shapes", "sw_set_routing", "sw_get_routing",
             "sw_server_create", "sw_server_destroy", "sw_server_last_error", "sw_server_submit",
-            "sw_server_poll", "sw_server_stats")
+            "sw_server_poll", "sw_server_stats", "sw_server_timing")
 
 
 class sw_result(ctypes.Structure):
@@ -99,6 +99,8 @@ def load_library(path: str = LIB_PATH):
     lib.sw_last_timing.restype = ctypes.c_int
     lib.sw_last_timing.argtypes = [ctypes.c_void_p] + [ctypes.POINTER(ctypes.c_float)] * 3
     I32P = ctypes.POINTER(ctypes.c_int32)
+    lib.sw_last_host_timing.restype = ctypes.c_int
+    lib.sw_last_host_timing.argtypes = [ctypes.c_void_p] + [ctypes.POINTER(ctypes.c_double)] * 2
     lib.sw_shapes.restype = ctypes.c_int
     lib.sw_shapes.argtypes = [ctypes.c_void_p, I32P, I32P, I32P, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
     lib.sw_set_routing.restype = ctypes.c_int
@@ -112,6 +114,8 @@ def load_library(path: str = LIB_PATH):
     lib.sw_server_create.restype = ctypes.c_void_p
     lib.sw_server_create.argtypes = [ctypes.c_int, ctypes.POINTER(sw_scheme), ctypes.c_int, ctypes.c_int64,
                                      ctypes.c_int, ctypes.c_int64, ctypes.c_char_p]
+    lib.sw_server_timing.restype = ctypes.c_int
+    lib.sw_server_timing.argtypes = [ctypes.c_void_p] + [ctypes.POINTER(ctypes.c_double)] * 3
     lib.sw_server_destroy.restype = None
     lib.sw_server_destroy.argtypes = [ctypes.c_void_p]
     lib.sw_server_last_error.restype = ctypes.c_char_p
@@ -339,6 +343,12 @@ class Aligner:
     def bin_stats(self):
         return sw_last_bin_stats(self.h)
 
+    def host_timing(self):
+        """(enqueue_ms, wait_ms) of the last call, host wall time."""
+        a, b = ctypes.c_double(0), ctypes.c_double(0)
+        _check(self.h, load_library().sw_last_host_timing(self.h, ctypes.byref(a), ctypes.byref(b)))
+        return float(a.value), float(b.value)
+
     def shapes(self):
         return sw_shapes(self.h)
 
@@ -408,6 +418,12 @@ class Server:
         if rc != SW_OK:
             raise SwError(rc, self._err())
         return out[:n], float(lat.value)
+
+    def timing(self):
+        """Cumulative ms spent admitting, aligning and fetching."""
+        vals = [ctypes.c_double(0) for _ in range(3)]
+        load_library().sw_server_timing(self.s, *[ctypes.byref(v) for v in vals])
+        return {k: float(v.value) for k, v in zip(("admit_ms", "align_ms", "fetch_ms"), vals)}
 
     def stats(self):
         vals = [ctypes.c_int64(0) for _ in range(5)]

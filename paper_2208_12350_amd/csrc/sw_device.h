@@ -48,7 +48,7 @@ __device__ __forceinline__ PairJob load_job(const KParams& P, int pair, int reve
     J.dir = 1; J.n = 0; J.m = 0; J.qbase = 0; J.rbase = 0; J.sid = 0;
     J.fwd_score = 0; J.fwd_qe = -1; J.fwd_re = -1;
     if (pair < 0) return J;
-    if (pair >= P.n_pairs) {
+    if (pair >= *P.n_dev) {
         atomicOr(&P.flags[kFlagInternal], 1);
         return J;
     }

@@ -96,7 +96,8 @@ struct KParams {
     int32_t reverse;             // 0 = forward sweep, 1 = reverse sweep
     int32_t lo_idx, hi_idx;      // meta[lo_idx] .. meta[hi_idx] is this launch's item range
     int32_t head_idx;            // meta[head_idx] is this launch's queue head
-    int32_t n_pairs;             // pairs in the batch (bound for every pair id)
+    const int32_t* n_dev;        // device copy of the number of pairs in the batch
+    int32_t n_pairs;             // pair capacity the grids are sized for (>= *n_dev)
     int32_t max_items;           // capacity of the items array (bound for every item index)
 };
 
@@ -144,16 +145,17 @@ QueueFn shape_kernel(int prec, int W, int R, bool reverse);
 const ShapeDesc* compiled_shapes(int* n);
 
 hipError_t launch_reset(int32_t* p, int n, hipStream_t s);
+// The planning launches are sized for `cap` pairs; the kernels take the
+// batch size from device memory (P.n_dev / n_dev), so a captured graph can be
+// replayed for any batch of at most `cap` pairs.
 hipError_t launch_classify(const KParams& P, const ClassifyArgs& C, const int8_t* lut,
-                           int64_t n_pairs, int32_t* keys, int32_t* hist,
+                           int64_t cap, int32_t* keys, int32_t* hist,
                            unsigned long long* counters, hipStream_t s);
 hipError_t launch_plan(const BinInfo* bins, int n_bins, int32_t* hist, int32_t* meta,
                        hipStream_t s);
-hipError_t launch_scatter(const int32_t* keys, int64_t n_pairs, int32_t* hist, int32_t* order,
-                          hipStream_t s);
-hipError_t launch_items(const int32_t* meta, const BinInfo* bins, int n_bins, int64_t n_pairs,
-                        WorkItem* items, hipStream_t s);
-hipError_t launch_reverse_cells(const sw_result* out, int64_t n, unsigned long long* acc,
-                                hipStream_t stream);
+hipError_t launch_scatter(const int32_t* keys, const int32_t* n_dev, int64_t cap, int32_t* hist,
+                          int32_t* order, hipStream_t s);
+hipError_t launch_items(const int32_t* meta, const BinInfo* bins, int n_bins, const int32_t* n_dev,
+                        int64_t cap, WorkItem* items, hipStream_t s);
 
 }  // namespace sw

@@ -24,8 +24,9 @@ __global__ void sw_reset_kernel(int32_t* p, int n) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
 }
 
-__global__ void sw_classify_kernel(KParams P, ClassifyArgs C, const int8_t* lut, int64_t n_pairs,
+__global__ void sw_classify_kernel(KParams P, ClassifyArgs C, const int8_t* lut,
                                    int32_t* keys, int32_t* hist, unsigned long long* counters) {
+    const int64_t n_pairs = *P.n_dev;
     // counters[0] / [1]: forward / reverse cells; counters[2]: int32 pairs
     // (forward); per bin of this pass: cells and pairs (kCtrBinCells,
     // kCtrBinPairs, indexed pass * kMaxBins + bin)
@@ -100,63 +101,100 @@ __global__ void sw_classify_kernel(KParams P, ClassifyArgs C, const int8_t* lut,
 }
 
 // One workgroup of 1024 threads: exclusive scan of the key histogram in
-// place, then the per-bin pair and work-item ranges.
+// place, then the per-bin pair and work-item ranges.  The histogram is
+// scanned in segments staged through LDS (coalesced loads and stores; each
+// thread then sums a run of kRun consecutive entries, padded by one word per
+// run against bank conflicts), with wave-level shuffle scans in between.
 constexpr int kPlanThreads = 1024;
+constexpr int kRun = 16;
+constexpr int kSeg = kPlanThreads * kRun;
+
+__device__ __forceinline__ int lds_slot(int e) { return e + e / kRun; }
+
+// Inclusive scan within a wavefront.
+__device__ __forceinline__ int32_t wave_scan(int32_t v, int lane) {
+    for (int off = 1; off < 64; off <<= 1) {
+        const int32_t u = __shfl_up(v, off);
+        if (lane >= off) v += u;
+    }
+    return v;
+}
 
 __global__ __launch_bounds__(kPlanThreads) void sw_plan_kernel(const BinInfo* bins, int n_bins,
                                                                int32_t* hist, int32_t* meta) {
-    __shared__ int32_t part[kPlanThreads];
-    constexpr int kPer = (kHistSize + kPlanThreads - 1) / kPlanThreads;
+    __shared__ int32_t seg[kSeg + kSeg / kRun];
+    __shared__ int32_t wave_tot[kPlanThreads / 64];
+    __shared__ int32_t bin_items[kMaxBins + 1];
     const int t = threadIdx.x;
-    const int lo = t * kPer;
-    const int hi = lo + kPer < kHistSize ? lo + kPer : kHistSize;
-    int32_t sum = 0;
-    for (int k = lo; k < hi; ++k) sum += hist[k];
-    part[t] = sum;
+    const int lane = t & 63, wave = t >> 6;
+    int32_t carry = 0;   // sum of all earlier segments (same value in every thread)
+    for (int base = 0; base < kHistSize; base += kSeg) {
+        const int n = kHistSize - base < kSeg ? kHistSize - base : kSeg;
+        for (int e = t; e < kSeg; e += kPlanThreads) seg[lds_slot(e)] = e < n ? hist[base + e] : 0;
+        __syncthreads();
+        int32_t sum = 0;
+#pragma unroll
+        for (int k = 0; k < kRun; ++k) sum += seg[lds_slot(t * kRun + k)];
+        const int32_t incl = wave_scan(sum, lane);
+        if (lane == 63) wave_tot[wave] = incl;
+        __syncthreads();
+        int32_t before = 0, total = 0;
+        for (int w = 0; w < kPlanThreads / 64; ++w) {
+            const int32_t x = wave_tot[w];
+            before += w < wave ? x : 0;
+            total += x;
+        }
+        int32_t run = carry + before + incl - sum;   // exclusive prefix of this thread's run
+#pragma unroll
+        for (int k = 0; k < kRun; ++k) {
+            const int slot = lds_slot(t * kRun + k);
+            const int32_t c = seg[slot];
+            seg[slot] = run;
+            run += c;
+        }
+        __syncthreads();
+        for (int e = t; e < n; e += kPlanThreads) hist[base + e] = seg[lds_slot(e)];
+        carry += total;
+        __syncthreads();
+    }
+    // per-bin ranges: the bin's first sorted position is the scanned count
+    // of its first key; its items are its pairs in groups of ppw
+    if (t <= kMaxBins) {
+        const int32_t f = hist[t * kMBuckets];   // t == kMaxBins: the trivial key
+        meta[kMetaBinFirst + t] = f;
+        bin_items[t] = f;
+    }
+    if (t < kMaxBins) meta[kMetaHeads + t] = 0;
     __syncthreads();
-    // Hillis-Steele inclusive scan of the partial sums
-    for (int off = 1; off < kPlanThreads; off <<= 1) {
-        const int32_t v = t >= off ? part[t - off] : 0;
-        __syncthreads();
-        part[t] += v;
-        __syncthreads();
+    int32_t my_items = 0;
+    if (t < n_bins && t < kMaxBins) {
+        const int32_t cnt = bin_items[t + 1] - bin_items[t];
+        my_items = (cnt + bins[t].ppw - 1) / bins[t].ppw;
     }
-    int32_t run = part[t] - sum;   // exclusive prefix of this chunk
-    for (int k = lo; k < hi; ++k) {
-        const int32_t c = hist[k];
-        hist[k] = run;
-        run += c;
-    }
+    __syncthreads();
+    if (t < kMaxBins) bin_items[t] = my_items;
     __syncthreads();
     if (t == 0) {
         int32_t items = 0;
-        for (int b = 0; b <= kMaxBins; ++b) {
-            const int32_t f = hist[(b < kMaxBins ? b : kMaxBins) * kMBuckets];
-            meta[kMetaBinFirst + b] = f;
-        }
         for (int b = 0; b < kMaxBins; ++b) {
             meta[kMetaItemFirst + b] = items;
-            if (b < n_bins) {
-                const int32_t cnt = meta[kMetaBinFirst + b + 1] - meta[kMetaBinFirst + b];
-                items += (cnt + bins[b].ppw - 1) / bins[b].ppw;
-            }
+            items += bin_items[b];
         }
         meta[kMetaItemFirst + kMaxBins] = items;
-        for (int k = 0; k < kMaxBins; ++k) meta[kMetaHeads + k] = 0;
     }
 }
 
-__global__ void sw_scatter_kernel(const int32_t* keys, int64_t n_pairs, int32_t* offs, int32_t* order) {
+__global__ void sw_scatter_kernel(const int32_t* keys, const int32_t* n_dev, int32_t* offs, int32_t* order) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_pairs) return;
+    if (i >= *n_dev) return;
     const int32_t pos = atomicAdd(&offs[keys[i]], 1);
     order[pos] = (int32_t)i;
 }
 
-__global__ void sw_items_kernel(const int32_t* meta, const BinInfo* bins, int n_bins, int64_t n_pairs,
+__global__ void sw_items_kernel(const int32_t* meta, const BinInfo* bins, int n_bins, const int32_t* n_dev,
                                 WorkItem* items) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_pairs || i >= meta[kMetaBinFirst + n_bins]) return;
+    if (i >= *n_dev || i >= meta[kMetaBinFirst + n_bins]) return;
     int b = 0;
     while (b + 1 < n_bins && meta[kMetaBinFirst + b + 1] <= i) ++b;
     const int32_t f = meta[kMetaBinFirst + b];
@@ -175,23 +213,6 @@ __global__ void sw_items_kernel(const int32_t* meta, const BinInfo* bins, int n_
     items[meta[kMetaItemFirst + b] + k / bi.ppw] = w;
 }
 
-// Reverse cells of a finished batch: sum over pairs with a positive score of
-// (q_end+1)*(r_end+1).
-__global__ void sw_reverse_cells_kernel(const sw_result* out, int64_t n, unsigned long long* acc) {
-    __shared__ unsigned long long s;
-    if (threadIdx.x == 0) s = 0;
-    __syncthreads();
-    unsigned long long v = 0;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const sw_result r = out[i];
-        if (r.score > 0) v += (unsigned long long)(r.q_end + 1) * (unsigned long long)(r.r_end + 1);
-    }
-    atomicAdd(&s, v);
-    __syncthreads();
-    if (threadIdx.x == 0) atomicAdd(acc, s);
-}
-
 static unsigned grid_for(int64_t n, int threads) {
     int64_t b = (n + threads - 1) / threads;
     return (unsigned)(b > 0 ? b : 1);
@@ -205,11 +226,11 @@ hipError_t launch_reset(int32_t* p, int n, hipStream_t s) {
 }
 
 hipError_t launch_classify(const KParams& P, const ClassifyArgs& C, const int8_t* lut,
-                           int64_t n_pairs, int32_t* keys, int32_t* hist,
+                           int64_t cap, int32_t* keys, int32_t* hist,
                            unsigned long long* counters, hipStream_t s) {
-    if (n_pairs <= 0) return hipSuccess;
-    hipLaunchKernelGGL(sw_classify_kernel, dim3(grid_for(n_pairs, 256)), dim3(256), 0, s, P, C, lut,
-                       n_pairs, keys, hist, counters);
+    if (cap <= 0) return hipSuccess;
+    hipLaunchKernelGGL(sw_classify_kernel, dim3(grid_for(cap, 256)), dim3(256), 0, s, P, C, lut,
+                       keys, hist, counters);
     return hipGetLastError();
 }
 
@@ -218,29 +239,22 @@ hipError_t launch_plan(const BinInfo* bins, int n_bins, int32_t* hist, int32_t* 
     return hipGetLastError();
 }
 
-hipError_t launch_scatter(const int32_t* keys, int64_t n_pairs, int32_t* hist, int32_t* order,
-                          hipStream_t s) {
-    if (n_pairs <= 0) return hipSuccess;
-    hipLaunchKernelGGL(sw_scatter_kernel, dim3(grid_for(n_pairs, 256)), dim3(256), 0, s, keys, n_pairs,
+hipError_t launch_scatter(const int32_t* keys, const int32_t* n_dev, int64_t cap, int32_t* hist,
+                          int32_t* order, hipStream_t s) {
+    if (cap <= 0) return hipSuccess;
+    hipLaunchKernelGGL(sw_scatter_kernel, dim3(grid_for(cap, 256)), dim3(256), 0, s, keys, n_dev,
                        hist, order);
     return hipGetLastError();
 }
 
-hipError_t launch_items(const int32_t* meta, const BinInfo* bins, int n_bins, int64_t n_pairs,
-                        WorkItem* items, hipStream_t s) {
-    if (n_pairs <= 0) return hipSuccess;
-    hipLaunchKernelGGL(sw_items_kernel, dim3(grid_for(n_pairs, 256)), dim3(256), 0, s, meta, bins, n_bins,
-                       n_pairs, items);
+hipError_t launch_items(const int32_t* meta, const BinInfo* bins, int n_bins, const int32_t* n_dev,
+                        int64_t cap, WorkItem* items, hipStream_t s) {
+    if (cap <= 0) return hipSuccess;
+    hipLaunchKernelGGL(sw_items_kernel, dim3(grid_for(cap, 256)), dim3(256), 0, s, meta, bins, n_bins,
+                       n_dev, items);
     return hipGetLastError();
 }
 
-hipError_t launch_reverse_cells(const sw_result* out, int64_t n, unsigned long long* acc,
-                                hipStream_t stream) {
-    if (n <= 0) return hipSuccess;
-    unsigned blocks = grid_for(n, 256);
-    if (blocks > 1024) blocks = 1024;
-    hipLaunchKernelGGL(sw_reverse_cells_kernel, dim3(blocks), dim3(256), 0, stream, out, n, acc);
-    return hipGetLastError();
-}
+
 
 }  // namespace sw

@@ -39,6 +39,7 @@ __global__ __launch_bounds__(kBlock) void sw_queue_kernel(KParams P) {
         if (tid == 0) atomicOr(&P.flags[kFlagInternal], 1);
         return;
     }
+    const int n_pairs = __builtin_amdgcn_readfirstlane(*P.n_dev);
     load_schemes(L, P, tid);
     __syncthreads();
     uint16_t* wbuf = wbufs + wave * kWaveBuf;
@@ -54,7 +55,7 @@ __global__ __launch_bounds__(kBlock) void sw_queue_kernel(KParams P) {
         const WorkItem* wp = P.items + lo + it;
         const int first = __builtin_amdgcn_readfirstlane(__atomic_load_n(&wp->first, __ATOMIC_RELAXED));
         const int count = __builtin_amdgcn_readfirstlane((int)__atomic_load_n(&wp->count, __ATOMIC_RELAXED));
-        const bool valid = first >= 0 && count >= 1 && count <= kPPW && first + count <= P.n_pairs;
+        const bool valid = first >= 0 && count >= 1 && count <= kPPW && first + count <= n_pairs;
         if (valid) {
             wave_lds_sync();
             if constexpr (PREC == 16)

@@ -15,10 +15,12 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -27,6 +29,8 @@
 using namespace sw;
 
 namespace {
+
+std::mutex g_capture_mu;   // one graph capture at a time in the process
 
 constexpr int kLutEntries = 2 * kLutRows;
 constexpr int kCtrBase = 16;     // int index of the first 64-bit counter
@@ -42,7 +46,7 @@ struct GraphKey {
     const void* r_end;
     const void* scheme_id;
     const void* out;
-    int64_t n_pairs;
+    int64_t cap_pairs;     // grids are sized for it; the batch size itself is read on the device
     int32_t alphabet[SW_MAX_SCHEMES];
     int32_t gap_open[SW_MAX_SCHEMES];
     int32_t gap_extend[SW_MAX_SCHEMES];
@@ -76,6 +80,7 @@ struct sw_handle {
     int8_t* d_lut = nullptr;
     BinInfo* d_bins = nullptr;
     int32_t* d_small = nullptr;
+    int32_t* d_n = nullptr;       // batch size, copied from h_n at the start of each call
     int32_t* d_hist = nullptr;
     int32_t* d_meta = nullptr;
     int32_t* d_keys = nullptr;
@@ -86,9 +91,11 @@ struct sw_handle {
     int8_t* h_mats = nullptr;     // pinned
     int32_t* h_small = nullptr;   // pinned
     int32_t* h_meta = nullptr;    // pinned
+    int32_t* h_n = nullptr;       // pinned
 
     hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     float t_plan = 0.f, t_fwd = 0.f, t_rev = 0.f;
+    double t_enqueue = 0.0, t_wait = 0.0;   // host milliseconds of the last call
     // per (pass, bin) event pairs for "timing" = 2, created on first use
     std::vector<hipEvent_t> bin_ev;
     std::vector<sw_bin_stat> bin_stats;
@@ -101,6 +108,8 @@ struct sw_handle {
     hipGraphExec_t gexec = nullptr;
     GraphKey gkey;
     bool have_graph = false;
+    int64_t n_captures = 0;
+    int64_t n_capture_refusals = 0;
 
     int64_t last_fwd = 0, last_rev = 0, last_i32 = 0;
 };
@@ -270,15 +279,15 @@ static int ensure_pairs(sw_handle* h, int64_t n) {
 
 // Enqueue one pass (planning + sweeps).  Plain mode synchronises `stream`
 // once to read the per-bin item counts.
-static int enqueue_pass(sw_handle* h, KParams K, const ClassifyArgs& C, int64_t P, int pass,
+static int enqueue_pass(sw_handle* h, KParams K, const ClassifyArgs& C, int64_t cap, int pass,
                         hipStream_t stream, bool timing) {
     K.reverse = pass;
     const int n_bins = (int)h->bins.size();
     HIP_TRY(h, launch_reset(h->d_hist, kHistSize, stream));
-    HIP_TRY(h, launch_classify(K, C, h->d_lut, P, h->d_keys, h->d_hist, counters(h->d_small), stream));
+    HIP_TRY(h, launch_classify(K, C, h->d_lut, cap, h->d_keys, h->d_hist, counters(h->d_small), stream));
     HIP_TRY(h, launch_plan(h->d_bins, n_bins, h->d_hist, h->d_meta, stream));
-    HIP_TRY(h, launch_scatter(h->d_keys, P, h->d_hist, h->d_order, stream));
-    HIP_TRY(h, launch_items(h->d_meta, h->d_bins, n_bins, P, h->d_items, stream));
+    HIP_TRY(h, launch_scatter(h->d_keys, h->d_n, cap, h->d_hist, h->d_order, stream));
+    HIP_TRY(h, launch_items(h->d_meta, h->d_bins, n_bins, h->d_n, cap, h->d_items, stream));
     const bool per_bin = timing && h->opt_timing == 2;
     if (timing && h->opt_mode == 1) HIP_TRY(h, hipEventRecord(h->ev[pass == 0 ? 1 : 3], stream));
     if (h->opt_mode == 1) {
@@ -296,8 +305,8 @@ static int enqueue_pass(sw_handle* h, KParams K, const ClassifyArgs& C, int64_t 
         for (int b = 0; b < n_bins; ++b) {
             if (!h->bin_used[b]) continue;
             const BinInfo& e = h->bins[b];
-            // no bin can hold more than P / ppw items, one wavefront each
-            const int64_t need = (P / e.ppw + 1 + kWavesPerBlock - 1) / kWavesPerBlock;
+            // no bin can hold more than cap / ppw items, one wavefront each
+            const int64_t need = (cap / e.ppw + 1 + kWavesPerBlock - 1) / kWavesPerBlock;
             const int blocks = (int)std::min<int64_t>(need, h->resident_blocks[pass][b]);
             K.lo_idx = kMetaItemFirst + b;
             K.hi_idx = kMetaItemFirst + b + 1;
@@ -356,13 +365,14 @@ sw_handle* sw_create(int device, const char* tuning) {
          hipMalloc(&h->d_lut, kLutEntries) == hipSuccess &&
          hipMalloc(&h->d_bins, kMaxBins * sizeof(BinInfo)) == hipSuccess &&
          hipMalloc(&h->d_small, kSmallInts * 4) == hipSuccess &&
+         hipMalloc(&h->d_n, 16) == hipSuccess &&
+         hipHostMalloc(&h->h_n, 16, hipHostMallocDefault) == hipSuccess &&
          hipMalloc(&h->d_hist, kHistSize * 4) == hipSuccess &&
          hipMalloc(&h->d_meta, kMetaSize * 4) == hipSuccess &&
          hipHostMalloc(&h->h_mats, SW_MAX_SCHEMES * kMatBytes, hipHostMallocDefault) == hipSuccess &&
          hipHostMalloc(&h->h_small, kSmallInts * 4, hipHostMallocDefault) == hipSuccess &&
          hipHostMalloc(&h->h_meta, kMetaSize * 4, hipHostMallocDefault) == hipSuccess;
     for (int k = 0; ok && k < 5; ++k) ok = hipEventCreate(&h->ev[k]) == hipSuccess;
-    if (ok) ok = hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) == hipSuccess;
     for (int f = 0; ok && f < sw_handle::kForks; ++f)
         ok = hipStreamCreateWithFlags(&h->fork[f], hipStreamNonBlocking) == hipSuccess;
     for (int f = 0; ok && f <= sw_handle::kForks; ++f)
@@ -410,7 +420,8 @@ void sw_destroy(sw_handle* h) {
     (void)hipSetDevice(h->device);
     (void)hipDeviceSynchronize();
     drop_graph(h);
-    free_dev(h->d_mats); free_dev(h->d_lut); free_dev(h->d_bins); free_dev(h->d_small);
+    free_dev(h->d_mats); free_dev(h->d_lut); free_dev(h->d_bins); free_dev(h->d_small); free_dev(h->d_n);
+    if (h->h_n) (void)hipHostFree(h->h_n);
     free_dev(h->d_hist); free_dev(h->d_meta); free_dev(h->d_keys); free_dev(h->d_order);
     free_dev(h->d_items);
     if (h->h_mats) (void)hipHostFree(h->h_mats);
@@ -448,6 +459,14 @@ int sw_set_option(sw_handle* h, const char* key, int64_t value) {
                 if (hipEventCreate(&e) != hipSuccess) return fail(h, SW_EDEVICE, "event creation failed");
         }
         h->opt_timing = value;
+    } else if (k == "capacity") {
+        // reserve workspace for this many pairs up front (grids and graphs are
+        // sized for the capacity, so batches up to it reuse one graph)
+        if (value < 0 || value > (int64_t)0x7FFFFFFF) return fail(h, SW_EINVAL, "capacity must be 0..2^31-1");
+        (void)hipSetDevice(h->device);
+        const int rc = ensure_pairs(h, value);
+        if (rc != SW_OK) return rc;
+        return SW_OK;
     } else if (k == "streams") {
         if (value < 1 || value > sw_handle::kForks) return fail(h, SW_EINVAL, "streams must be 1..%d", sw_handle::kForks);
         h->opt_streams = value;
@@ -470,6 +489,9 @@ int sw_get_option(sw_handle* h, const char* key, int64_t* value) {
     else if (k == "precision") *value = h->opt_precision;
     else if (k == "timing") *value = h->opt_timing;
     else if (k == "streams") *value = h->opt_streams;
+    else if (k == "capacity") *value = h->cap_pairs;
+    else if (k == "captures") *value = h->n_captures;
+    else if (k == "capture_refusals") *value = h->n_capture_refusals;
     else return fail(h, SW_EINVAL, "unknown option '%s'", key);
     return SW_OK;
 }
@@ -485,8 +507,10 @@ static int align_spans(sw_handle* h, const uint8_t* queries, const int64_t* q_be
                        int n_schemes, sw_result* out, void* stream_ptr) {
     if (!h) return SW_EINVAL;
     h->err.clear();
+    const auto t_entry = std::chrono::steady_clock::now();
     h->last_fwd = h->last_rev = h->last_i32 = 0;
     h->t_plan = h->t_fwd = h->t_rev = 0.f;
+    h->t_enqueue = h->t_wait = 0.0;
     h->bin_stats.clear();
     if (!schemes) return fail(h, SW_EINVAL, "null schemes");
     if (n_schemes < 1 || n_schemes > SW_MAX_SCHEMES)
@@ -542,8 +566,10 @@ static int align_spans(sw_handle* h, const uint8_t* queries, const int64_t* q_be
     K.queries = queries; K.q_beg = q_beg; K.q_end = q_end; K.refs = refs; K.r_beg = r_beg; K.r_end = r_end;
     K.scheme_id = scheme_id; K.order = h->d_order; K.items = h->d_items; K.meta = h->d_meta;
     K.out = out; K.flags = h->d_small; K.mats = h->d_mats; K.validate = (int32_t)h->opt_validate;
-    K.n_pairs = (int32_t)P;
+    K.n_dev = h->d_n;
+    K.n_pairs = (int32_t)h->cap_pairs;
     K.max_items = (int32_t)(h->cap_pairs + kMaxBins);
+    h->h_n[0] = (int32_t)P;
     for (int s = 0; s < SW_MAX_SCHEMES; ++s) {
         const bool v = s < n_schemes;
         K.alphabet[s] = v ? schemes[s].alphabet : 1;
@@ -557,7 +583,7 @@ static int align_spans(sw_handle* h, const uint8_t* queries, const int64_t* q_be
     memset(&key, 0, sizeof(key));
     key.queries = queries; key.q_beg = q_beg; key.q_end = q_end; key.refs = refs;
     key.r_beg = r_beg; key.r_end = r_end; key.scheme_id = scheme_id; key.out = out;
-    key.n_pairs = P;
+    key.cap_pairs = h->cap_pairs;
     memcpy(key.alphabet, K.alphabet, sizeof(key.alphabet));
     memcpy(key.gap_open, K.gap_open, sizeof(key.gap_open));
     memcpy(key.gap_extend, K.gap_extend, sizeof(key.gap_extend));
@@ -570,37 +596,77 @@ static int align_spans(sw_handle* h, const uint8_t* queries, const int64_t* q_be
         // The graph is captured on the handle's private stream (the caller's
         // stream may be the null stream, which cannot be captured) and then
         // launched on the caller's stream.
-        hipStream_t es = use_graph ? h->cap_stream : stream;
+        // Captures are serialised across the handles of the process (the
+        // runtime has refused a capture begun while another thread was
+        // capturing); if one is refused anyway, this call runs eagerly on the
+        // caller's stream and a later call captures.
+        std::unique_lock<std::mutex> capture_lock(g_capture_mu, std::defer_lock);
+        bool capturing = false;
         if (use_graph) {
             drop_graph(h);
-            HIP_TRY(h, hipStreamBeginCapture(es, hipStreamCaptureModeThreadLocal));
+            // created on first use, so that the fork streams, created with
+            // the handle, take consecutive hardware queues
+            if (!h->cap_stream) HIP_TRY(h, hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+            capture_lock.lock();
+            capturing = hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
+            if (!capturing) {
+                (void)hipGetLastError();
+                capture_lock.unlock();
+                ++h->n_capture_refusals;
+            }
         }
-        int erc = SW_OK;
-        do {
-            if (timing && hipEventRecord(h->ev[0], es) != hipSuccess) { erc = fail(h, SW_EDEVICE, "event"); break; }
+        auto enqueue_all = [&](hipStream_t es) -> int {
+            if (timing && hipEventRecord(h->ev[0], es) != hipSuccess) return fail(h, SW_EDEVICE, "event");
             if (hipMemcpyAsync(h->d_mats, h->h_mats, SW_MAX_SCHEMES * kMatBytes, hipMemcpyHostToDevice, es) !=
-                hipSuccess) { erc = fail(h, SW_EDEVICE, "matrix upload failed"); break; }
-            if (launch_reset(h->d_small, kSmallInts, es) != hipSuccess) { erc = fail(h, SW_EDEVICE, "reset"); break; }
-            erc = enqueue_pass(h, K, C, P, 0, es, timing);
-            if (erc != SW_OK) break;
-            erc = enqueue_pass(h, K, C, P, 1, es, timing);
-        } while (0);
-        if (use_graph) {
+                hipSuccess)
+                return fail(h, SW_EDEVICE, "matrix upload failed");
+            if (launch_reset(h->d_small, kSmallInts, es) != hipSuccess) return fail(h, SW_EDEVICE, "reset");
+            // the batch size travels through device memory, so a captured
+            // graph serves every batch of at most cap_pairs pairs
+            if (hipMemcpyAsync(h->d_n, h->h_n, 4, hipMemcpyHostToDevice, es) != hipSuccess)
+                return fail(h, SW_EDEVICE, "batch size upload failed");
+            const int rc0 = enqueue_pass(h, K, C, h->cap_pairs, 0, es, timing);
+            if (rc0 != SW_OK) return rc0;
+            return enqueue_pass(h, K, C, h->cap_pairs, 1, es, timing);
+        };
+        bool eager = !capturing;
+        if (capturing) {
+            const int erc = enqueue_all(h->cap_stream);
             hipGraph_t g = nullptr;
-            hipError_t ce = hipStreamEndCapture(es, &g);
-            if (erc != SW_OK) { if (g) (void)hipGraphDestroy(g); return erc; }
-            if (ce != hipSuccess) return fail(h, SW_EDEVICE, "graph capture failed: %s", hipGetErrorString(ce));
-            h->graph = g;
-            HIP_TRY(h, hipGraphInstantiate(&h->gexec, h->graph, nullptr, nullptr, 0));
-            h->gkey = key;
-            h->have_graph = true;
-            HIP_TRY(h, hipGraphLaunch(h->gexec, stream));
-        } else if (erc != SW_OK) {
-            return erc;
+            const hipError_t ce = hipStreamEndCapture(h->cap_stream, &g);
+            if (erc == SW_OK && ce == hipSuccess && g) {
+                h->graph = g;
+                ++h->n_captures;
+                HIP_TRY(h, hipGraphInstantiate(&h->gexec, h->graph, nullptr, nullptr, 0));
+                capture_lock.unlock();
+                h->gkey = key;
+                h->have_graph = true;
+                HIP_TRY(h, hipGraphLaunch(h->gexec, stream));
+            } else {
+                // nothing captured has run: discard it and run the call eagerly
+                if (g) (void)hipGraphDestroy(g);
+                (void)hipGetLastError();
+                capture_lock.unlock();
+                ++h->n_capture_refusals;
+                for (int f = 0; f < sw_handle::kForks; ++f) {
+                    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+                    if (hipStreamIsCapturing(h->fork[f], &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
+                        return fail(h, SW_EDEVICE, "a stream stayed in capture after a failed capture");
+                }
+                h->err.clear();
+                eager = true;
+            }
+        }
+        if (eager) {
+            const int erc = enqueue_all(stream);
+            if (erc != SW_OK) return erc;
         }
     }
+    const auto t_enq = std::chrono::steady_clock::now();
     HIP_TRY(h, hipMemcpyAsync(h->h_small, h->d_small, kSmallInts * 4, hipMemcpyDeviceToHost, stream));
     HIP_TRY(h, hipStreamSynchronize(stream));
+    h->t_enqueue = std::chrono::duration<double, std::milli>(t_enq - t_entry).count();
+    h->t_wait = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_enq).count();
     const int32_t* flags = h->h_small;
     const unsigned long long* cnt = counters(h->h_small);
     h->last_fwd = (int64_t)cnt[kCtrFwdCells];
@@ -724,6 +790,13 @@ int sw_last_bin_stats(sw_handle* h, sw_bin_stat* out, int capacity, int* n_out) 
     if (n_out) *n_out = n;
     if (n > 0 && (!out || capacity < n)) return fail(h, SW_EINVAL, "need room for %d entries", n);
     for (int k = 0; k < n; ++k) out[k] = h->bin_stats[k];
+    return SW_OK;
+}
+
+int sw_last_host_timing(sw_handle* h, double* enqueue_ms, double* wait_ms) {
+    if (!h) return SW_EINVAL;
+    if (enqueue_ms) *enqueue_ms = h->t_enqueue;
+    if (wait_ms) *wait_ms = h->t_wait;
     return SW_OK;
 }
 

@@ -96,6 +96,7 @@ struct sw_server {
     PoolAllocator alloc;
     std::vector<std::unique_ptr<Slot>> slots;
     hipStream_t admit_stream = nullptr;
+    uint8_t* stage = nullptr;           // pinned host staging of the admission thread
     std::thread admit_th;
 
     std::mutex mu;
@@ -105,7 +106,12 @@ struct sw_server {
     uint64_t next_ticket = 1;
     bool stop = false;
     int64_t n_done = 0, n_batches = 0, pairs_done = 0;
+    double t_admit = 0, t_align = 0, t_fetch = 0;   // cumulative milliseconds
 };
+
+// Pageable host memory is copied to the device through this pinned staging
+// buffer, in chunks of at most its size.
+constexpr int64_t kStageBytes = 32 << 20;
 
 static int sfail(sw_server* s, int code, const char* fmt, ...) {
     char buf[512];
@@ -138,21 +144,43 @@ static void admission_loop(sw_server* S) {
         S->waiting.pop_front();
         r->pool_off = off;
         lk.unlock();
-        // sequences, then the absolute spans and scheme ids of the request
+        const Clock::time_point t0 = Clock::now();
+        // pool block: sequences, then the absolute spans and scheme ids of
+        // the request; assembled in pinned memory chunk by chunk and copied
         const int64_t seq = PoolAllocator::round_up(r->seq_bytes);
-        std::vector<int64_t> abs(r->spans.size());
-        for (size_t k = 0; k < abs.size(); ++k) abs[k] = r->spans[k] + off;
+        const int64_t total = seq + 33 * r->n_pairs;
         bool ok = true;
-        if (r->seq_bytes > 0)
-            ok = hipMemcpyAsync(S->pool + off, r->data.data(), r->seq_bytes, hipMemcpyHostToDevice,
-                                S->admit_stream) == hipSuccess;
-        if (ok && r->n_pairs > 0)
-            ok = hipMemcpyAsync(S->pool + off + seq, abs.data(), 32 * r->n_pairs, hipMemcpyHostToDevice,
-                                S->admit_stream) == hipSuccess &&
-                 hipMemcpyAsync(S->pool + off + seq + 32 * r->n_pairs, r->sid.data(), r->n_pairs,
-                                hipMemcpyHostToDevice, S->admit_stream) == hipSuccess;
-        if (ok) ok = hipStreamSynchronize(S->admit_stream) == hipSuccess;
+        for (int64_t c0 = 0; ok && c0 < total; c0 += kStageBytes) {
+            const int64_t c1 = std::min(total, c0 + kStageBytes);
+            for (int64_t x = c0; x < c1;) {
+                if (x < r->seq_bytes) {
+                    const int64_t e = std::min(c1, r->seq_bytes);
+                    memcpy(S->stage + (x - c0), r->data.data() + x, e - x);
+                    x = e;
+                } else if (x < seq) {
+                    const int64_t e = std::min(c1, seq);
+                    memset(S->stage + (x - c0), 0, e - x);
+                    x = e;
+                } else if (x < seq + 32 * r->n_pairs) {
+                    // spans are 8-byte values and seq is 256-aligned, so a
+                    // chunk boundary (a multiple of kStageBytes) never splits one
+                    const int64_t e = std::min(c1, seq + 32 * r->n_pairs);
+                    int64_t* dst = reinterpret_cast<int64_t*>(S->stage + (x - c0));
+                    for (int64_t k = (x - seq) / 8; k < (e - seq) / 8; ++k) *dst++ = r->spans[k] + off;
+                    x = e;
+                } else {
+                    const int64_t b = x - seq - 32 * r->n_pairs;
+                    memcpy(S->stage + (x - c0), r->sid.data() + b, c1 - x);
+                    x = c1;
+                }
+            }
+            ok = hipMemcpyAsync(S->pool + off + c0, S->stage, c1 - c0, hipMemcpyHostToDevice, S->admit_stream) ==
+                     hipSuccess &&
+                 hipStreamSynchronize(S->admit_stream) == hipSuccess;
+        }
+        const double ms = std::chrono::duration<double, std::milli>(Clock::now() - t0).count();
         lk.lock();
+        S->t_admit += ms;
         std::vector<uint8_t>().swap(r->data);
         if (!ok) {
             S->alloc.release(off);
@@ -188,6 +216,7 @@ static void slot_loop(sw_server* S, Slot* slot) {
         lk.unlock();
         int status = SW_OK;
         const int64_t P = total;
+        const Clock::time_point t0 = Clock::now();
         for (size_t k = 0, at = 0; k < batch.size(); ++k) {
             const Request* r = batch[k];
             slot->h_segs[k].src = r->pool_off + PoolAllocator::round_up(r->seq_bytes);
@@ -211,6 +240,7 @@ static void slot_loop(sw_server* S, Slot* slot) {
                                     qb + 3 * S->max_pairs, slot->d_sid, P, S->schemes.data(),
                                     (int)S->schemes.size(), slot->d_out, slot->stream);
         }
+        const Clock::time_point t1 = Clock::now();
         if (status == SW_OK && P > 0) {
             if (hipMemcpyAsync(slot->h_out, slot->d_out, P * sizeof(sw_result), hipMemcpyDeviceToHost,
                                slot->stream) != hipSuccess ||
@@ -220,6 +250,8 @@ static void slot_loop(sw_server* S, Slot* slot) {
         std::string why = status == SW_OK ? std::string() : std::string(sw_last_error(slot->h));
         lk.lock();
         const Clock::time_point now = Clock::now();
+        S->t_align += std::chrono::duration<double, std::milli>(t1 - t0).count();
+        S->t_fetch += std::chrono::duration<double, std::milli>(now - t1).count();
         for (size_t k = 0, at = 0; k < batch.size(); ++k) {
             Request* r = batch[k];
             if (status == SW_OK) r->results.assign(slot->h_out + at, slot->h_out + at + r->n_pairs);
@@ -263,12 +295,16 @@ sw_server* sw_server_create(int device, const sw_scheme* schemes, int n_schemes,
     }
     for (int k = 0; k < n_schemes; ++k) S->schemes[k].matrix = S->mats[k].data();
     bool ok = hipMalloc(&S->pool, pool_bytes) == hipSuccess &&
+              hipHostMalloc(&S->stage, kStageBytes, hipHostMallocDefault) == hipSuccess &&
               hipStreamCreateWithFlags(&S->admit_stream, hipStreamNonBlocking) == hipSuccess;
     if (ok) S->alloc.reset(pool_bytes);
     for (int k = 0; ok && k < n_slots; ++k) {
         std::unique_ptr<Slot> sl(new Slot());
         sl->h = sw_create(device, tuning);
+        // slots run their calls without graph capture: captures on several
+        // threads at once have been invalidated by the runtime
         ok = sl->h && sw_set_option(sl->h, "graph", 0) == SW_OK &&
+             sw_set_option(sl->h, "capacity", max_batch_pairs) == SW_OK &&
              hipStreamCreateWithFlags(&sl->stream, hipStreamNonBlocking) == hipSuccess &&
              hipMalloc(&sl->d_spans, 32 * max_batch_pairs) == hipSuccess &&
              hipMalloc(&sl->d_sid, max_batch_pairs) == hipSuccess &&
@@ -312,6 +348,7 @@ void sw_server_destroy(sw_server* S) {
         if (sl->h_out) (void)hipHostFree(sl->h_out);
     }
     if (S->admit_stream) (void)hipStreamDestroy(S->admit_stream);
+    if (S->stage) (void)hipHostFree(S->stage);
     if (S->pool) (void)hipFree(S->pool);
     delete S;
 }
@@ -410,6 +447,15 @@ int sw_server_stats(sw_server* S, int64_t* pool_peak_bytes, int64_t* pool_capaci
     if (requests_done) *requests_done = S->n_done;
     if (batches) *batches = S->n_batches;
     if (pairs_done) *pairs_done = S->pairs_done;
+    return SW_OK;
+}
+
+int sw_server_timing(sw_server* S, double* admit_ms, double* align_ms, double* fetch_ms) {
+    if (!S) return SW_EINVAL;
+    std::lock_guard<std::mutex> g(S->mu);
+    if (admit_ms) *admit_ms = S->t_admit;
+    if (align_ms) *align_ms = S->t_align;
+    if (fetch_ms) *fetch_ms = S->t_fetch;
     return SW_OK;
 }
 

@@ -4,6 +4,8 @@ Small cases are compared on every pair; the full-size workloads (the same
 launch configuration the benchmark times) are compared on a seeded sample of
 pairs, which the oracle recomputes one by one, and on properties that hold
 for every pair."""
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -388,3 +390,36 @@ def test_int16_range_edges(aligner):
     want = O.align_batch(b)
     assert_same(g, want, b)
     assert g[0, 0] == 127 * (lim_n - 1) and g[2, 0] == 127 * lim_n
+
+
+@pytest.mark.gpu
+def test_graph_replays_across_batch_sizes():
+    """One captured graph serves batches of different sizes on the same
+    buffers: the batch size is read on the device at every replay, so pairs
+    beyond it are never touched and every prefix matches the oracle."""
+    import torch
+    from paper_2208_12350_amd.binding import (Aligner, DeviceBatch, make_schemes, sw_align_batch,
+                                              sw_get_option)
+    b = W.make_workload("mixed", n_pairs=3000, seed=9191)
+    db = DeviceBatch.from_host(b)
+    want = O.align_batch(b)
+    want = np.stack([want[f] for f in FIELDS], axis=1)
+    al = Aligner(0, capacity=3000)
+    arr, keep = make_schemes(db.schemes)
+    out = torch.empty((b.n_pairs, 5), dtype=torch.int32, device="cuda:0")
+    stream = torch.cuda.current_stream()
+    try:
+        for n in (3000, 1200, 1, 2999, 1200, 0, 3000):
+            out.fill_(-7)
+            cb = db.c_struct()
+            cb.n_pairs = n
+            rc = sw_align_batch(al.h, cb, arr, len(db.schemes), out.data_ptr(), ctypes.c_void_p(stream.cuda_stream))
+            assert rc == 0, al.h
+            got = out.cpu().numpy()
+            assert np.array_equal(got[:n], want[:n]), n
+            assert (got[n:] == -7).all(), n
+            x = torch.randn(1 << 18, device="cuda:0")        # unrelated eager work between replays
+            assert float(x.abs().sum()) > 0
+        assert sw_get_option(al.h, "captures") == 1
+    finally:
+        al.close()

@@ -130,7 +130,11 @@ def roofline_leg(args, db, out, tuning, mode):
     fam_ops = OPS_PER_CELL * sum(v[1] for v in per_launch.values()) / roof_steps
     fam_peak_s = sum(OPS_PER_CELL * v[1] / roof_steps / ((VALU_INT16X2_TOPS if k[1] == 16 else VALU_INT32_TOPS) * 1e12)
                      for k, v in per_launch.items())
-    kernel_name = "sw::sw_queue_kernel<%d, %d, %d, %s>" % (dprec, dlanes, drows, "true" if dpass else "false")
+    direction = "true" if dpass else "false"
+    if dlanes > 64:
+        kernel_name = "sw::sw_coop_kernel<%d, %s>" % (drows, direction)
+    else:
+        kernel_name = "sw::sw_queue_kernel<%d, %d, %d, %s>" % (dprec, dlanes, drows, direction)
     return {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 2),
             "unit": "Tops/s", "frac": round(achieved / peak, 4),
             "traffic": stored_traffic(kernel_name, args.workload),
@@ -304,11 +308,17 @@ def main():
         from paper_2208_12350_amd import autotune as T
         from paper_2208_12350_amd.binding import routing_string
         log("autotuning the routing ...")
+        t_tune = time.time()
         rng = np.random.default_rng(5)
         idx = rng.choice(batch.n_pairs, size=min(batch.n_pairs, 50000), replace=False)
-        table, _, tune_s = T.tune(batch.q_len()[idx], batch.r_len()[idx], 0, 16, log=log)
+        ql, rl = batch.q_len()[idx], batch.r_len()[idx]
+        m_med = int(np.clip(np.median(rl[rl > 0]) if np.any(rl > 0) else 512, 64, 4096))
+        rates = T.measure_rates(0, 16, m=m_med, log=log)
+        cands = T.candidate_tables(ql, rl, rates, list(rates))
+        name, table, _ = T.pick_by_timing(db, cands, 0, log=log)
         tuning = routing_string(16, table)
-        log("  %s (%.1f s)" % (tuning, tune_s))
+        tune_s = time.time() - t_tune
+        log("  picked %s: %s (%.1f s)" % (name, tuning, tune_s))
 
     def timed(al, steps, warmup, what):
         for k in range(warmup):

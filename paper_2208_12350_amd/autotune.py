@@ -16,6 +16,12 @@ Two steps:
    sample of the workload, time = slots / rate.  Pure host arithmetic, so it
    is tested without a GPU.
 
+3. ``pick_by_timing``: the rate model ignores the critical path of the
+   longest pairs, which bounds small batches and the tail of large ones; so
+   the model's table and variants that put long queries on cooperative
+   256-lane groups (``candidate_tables``) are each timed on the batch
+   itself, and the fastest wins.
+
 The result is a routing table [(rows_max, W, R), ...] for
 ``Aligner.set_routing`` or, as a string, for the tuning argument of
 ``sw_create``.  Results never depend on the routing; only speed does.
@@ -137,7 +143,7 @@ def measure_rates(device: int = 0, precision: int = 16, m: int = 512, target_cel
         big = max(compiled, key=lambda s: s[0] * s[1])
         rates: Dict[Shape, float] = {}
         for W, R in todo:
-            ppw = (64 // W) * (2 if precision == 16 else 1)
+            ppw = (64 // W if W <= 64 else 1) * (2 if precision == 16 else 1)
             n_pairs = int(np.clip(target_cells / (W * R * m), 2048 * ppw // 4, 400_000))
             n_pairs -= n_pairs % ppw
             b = _probe_batch(W, R, m, n_pairs, seed=W * 1000 + R)
@@ -163,6 +169,62 @@ def measure_rates(device: int = 0, precision: int = 16, m: int = 512, target_cel
         return rates
     finally:
         al.close()
+
+
+def with_wide_groups(table: Table, rows_above: int, shapes: Sequence[Shape], width: int = 256) -> Table:
+    """`table` with the queries longer than `rows_above` moved to the
+    narrowest covering shape of `width` lanes (cooperative groups cut the
+    latency of long pairs, which bounds small batches and batch tails)."""
+    wide = sorted(r for w, r in shapes if w == width)
+    if not wide:
+        return list(table)
+    choice = expand(table)
+    for k in range(len(choice)):
+        rows = BUCKET * (k + 1)
+        if rows > rows_above:
+            fit = [r for r in wide if width * r >= rows]
+            if fit:
+                choice[k] = (width, fit[0])
+    return merge(choice)
+
+
+def candidate_tables(q_len, r_len, rates: Dict[Shape, float], shapes: Sequence[Shape]) -> Dict[str, Table]:
+    """Routings worth timing on the real batch: the rate model's choice, and
+    the same with long queries on cooperative 256-lane groups."""
+    model = choose_routing(q_len, r_len, rates)
+    out = {"model": model}
+    for above in (512, 768, 1024):
+        t = with_wide_groups(model, above, shapes)
+        if t != model and t not in out.values():
+            out["model+coop>%d" % above] = t
+    return out
+
+
+def pick_by_timing(dbatch, tables: Dict[str, Table], device: int = 0, repeats: int = 2, log=None):
+    """Time one call per repeat of each routing on the batch itself (graph
+    replay, the headline configuration) and return (name, table, ms)."""
+    import torch
+    from .binding import Aligner, routing_string
+    out = torch.empty((dbatch.n_pairs, 5), dtype=torch.int32, device="cuda:%d" % device)
+    best = None
+    for name, table in tables.items():
+        al = Aligner(device, routing_string(16, table))
+        try:
+            al.align(dbatch, out)
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(repeats):
+                t = time.perf_counter()
+                al.align(dbatch, out)
+                ts.append((time.perf_counter() - t) * 1e3)
+        finally:
+            al.close()
+        ms = float(np.median(ts))
+        if log:
+            log("  candidate %s: %.3f ms" % (name, ms))
+        if best is None or ms < best[2]:
+            best = (name, table, ms)
+    return best
 
 
 def tune(q_len, r_len, device: int = 0, precision: int = 16, log=None, **kw):

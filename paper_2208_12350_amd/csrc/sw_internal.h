@@ -38,22 +38,26 @@ __host__ __device__ inline int m_bucket(int m) {
 }
 
 struct BinInfo {
-    int8_t prec;      // 16 = two pairs per lane group packed in int16 halves, 32 = int32
-    int8_t W;         // lanes per group: 16 or 64
-    int8_t R;         // query rows per lane
-    int8_t pad;
-    int32_t ppw;      // pairs per wavefront work item
+    uint8_t prec;     // 16 = two pairs per lane group packed in int16 halves, 32 = int32
+    uint8_t R;        // query rows per lane
+    uint16_t W;       // lanes per group: 16, 32, 64, or 256 (a workgroup's four wavefronts)
+    int32_t ppw;      // pairs per work item
 };
 
-// One wavefront's work: pairs order[first .. first+count) of one bin.
+// Pairs per work item of a shape: a wavefront's groups (times two packed
+// pairs at 16 bits), or for a cooperative group the two pairs of one
+// workgroup.  Work items per workgroup: its four wavefronts, or one.
+__host__ __device__ inline int pairs_per_item(int prec, int W) {
+    return (W <= 64 ? 64 / W : 1) * (prec == 16 ? 2 : 1);
+}
+__host__ __device__ inline int items_per_block(int W) { return W <= 64 ? kWavesPerBlock : 1; }
+
+// One work item: pairs order[first .. first+count) of one bin.
 struct WorkItem {
     int32_t first;
     uint16_t count;
     uint8_t bin;
-    uint8_t prec;
-    uint8_t W;
-    uint8_t R;
-    uint8_t pad[2];
+    uint8_t pad;
 };
 
 // Layout of the per-pass planning metadata array (int32).

@@ -206,10 +206,7 @@ __global__ void sw_items_kernel(const int32_t* meta, const BinInfo* bins, int n_
     w.first = (int32_t)i;
     w.count = (uint16_t)(cnt - k < bi.ppw ? cnt - k : bi.ppw);
     w.bin = (uint8_t)b;
-    w.prec = (uint8_t)bi.prec;
-    w.W = (uint8_t)bi.W;
-    w.R = (uint8_t)bi.R;
-    w.pad[0] = w.pad[1] = 0;
+    w.pad = 0;
     items[meta[kMetaItemFirst + b] + k / bi.ppw] = w;
 }
 

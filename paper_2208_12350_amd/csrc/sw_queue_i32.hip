@@ -20,6 +20,8 @@ extern const KernelEntry kI16W32Kernels[];
 extern const int kNumI16W32Kernels;
 extern const KernelEntry kI16W64Kernels[];
 extern const int kNumI16W64Kernels;
+extern const KernelEntry kI16W256Kernels[];
+extern const int kNumI16W256Kernels;
 
 namespace {
 
@@ -30,11 +32,12 @@ Table table(int k) {
         case 0: return {kI16W16Kernels, kNumI16W16Kernels};
         case 1: return {kI16W32Kernels, kNumI16W32Kernels};
         case 2: return {kI16W64Kernels, kNumI16W64Kernels};
+        case 3: return {kI16W256Kernels, kNumI16W256Kernels};
         default: return {kI32Kernels, (int)(sizeof(kI32Kernels) / sizeof(kI32Kernels[0]))};
     }
 }
 
-constexpr int kTables = 4;
+constexpr int kTables = 5;
 ShapeDesc g_shapes[kMaxBins];
 int g_nshapes = 0;
 

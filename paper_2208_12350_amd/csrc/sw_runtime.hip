@@ -150,11 +150,10 @@ static void build_bins(sw_handle* h) {
     h->bins.clear();
     for (const ShapeDesc& s : v) {
         BinInfo b;
-        b.prec = (int8_t)s.prec;
-        b.W = (int8_t)s.W;
-        b.R = (int8_t)s.R;
-        b.pad = 0;
-        b.ppw = (64 / s.W) * (s.prec == 16 ? 2 : 1);
+        b.prec = (uint8_t)s.prec;
+        b.W = (uint16_t)s.W;
+        b.R = (uint8_t)s.R;
+        b.ppw = pairs_per_item(s.prec, s.W);
         h->bins.push_back(b);
     }
 }
@@ -168,7 +167,10 @@ static int find_bin(const sw_handle* h, int prec, int W, int R) {
 // Default routing of one precision: each 16-row bucket goes to the covering
 // shape with the fewest lane-row slots per pair, W*R*(m + W - 1), for a
 // reference of twice the query length plus 64 (the sweep of a W-lane group
-// takes m + W - 1 steps).  Ties go to the narrower group.
+// takes m + W - 1 steps).  Ties go to the narrower group.  Queries above 512
+// rows go to cooperative 256-lane groups when they are compiled: their
+// per-pair latency is about four times shorter than a 64-lane group's, and
+// that latency bounds small batches and the tails of large ones.
 static void default_routing(sw_handle* h, int sel) {
     const int prec = sel == 0 ? 16 : 32;
     for (int k = 0; k < kLutRows; ++k) {
@@ -176,9 +178,13 @@ static void default_routing(sw_handle* h, int sel) {
         const double m = 2.0 * rows + 64.0;
         int best = -1;
         double best_cost = 0;
+        bool have_coop = false;
+        for (const BinInfo& e : h->bins)
+            have_coop |= e.prec == prec && e.W > 64 && e.W * e.R >= rows;
+        const bool coop = have_coop && rows > 512;
         for (int b = 0; b < (int)h->bins.size(); ++b) {
             const BinInfo& e = h->bins[b];
-            if (e.prec != prec || e.W * e.R < rows) continue;
+            if (e.prec != prec || e.W * e.R < rows || (e.W > 64) != coop) continue;
             const double cost = (double)e.W * e.R * (m + e.W - 1);
             if (best < 0 || cost < best_cost || (cost == best_cost && e.W < h->bins[best].W)) {
                 best = b;
@@ -305,8 +311,9 @@ static int enqueue_pass(sw_handle* h, KParams K, const ClassifyArgs& C, int64_t 
         for (int b = 0; b < n_bins; ++b) {
             if (!h->bin_used[b]) continue;
             const BinInfo& e = h->bins[b];
-            // no bin can hold more than cap / ppw items, one wavefront each
-            const int64_t need = (cap / e.ppw + 1 + kWavesPerBlock - 1) / kWavesPerBlock;
+            // no bin can hold more than cap / ppw items
+            const int ipb = items_per_block(e.W);
+            const int64_t need = (cap / e.ppw + 1 + ipb - 1) / ipb;
             const int blocks = (int)std::min<int64_t>(need, h->resident_blocks[pass][b]);
             K.lo_idx = kMetaItemFirst + b;
             K.hi_idx = kMetaItemFirst + b + 1;
@@ -332,7 +339,7 @@ static int enqueue_pass(sw_handle* h, KParams K, const ClassifyArgs& C, int64_t 
             K.lo_idx = kMetaItemFirst + b;
             K.hi_idx = kMetaItemFirst + b + 1;
             K.head_idx = kMetaHeads + b;
-            const int blocks = (items + kWavesPerBlock - 1) / kWavesPerBlock;
+            const int blocks = (items + items_per_block(e.W) - 1) / items_per_block(e.W);
             if (per_bin) HIP_TRY(h, hipEventRecord(h->bin_ev[(pass * kMaxBins + b) * 2], stream));
             hipLaunchKernelGGL(shape_kernel(e.prec, e.W, e.R, pass != 0), dim3(blocks), dim3(kBlock), 0, stream, K);
             HIP_TRY(h, hipGetLastError());

@@ -218,9 +218,10 @@ typedef short s16x2 __attribute__((ext_vector_type(2)));
 typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
 
 // Columns are encoded as kColMax - j in the low 15 bits of a key; j ranges
-// over -(W-1) .. kI16MaxRef + W - 2, so kColMax - j stays within 0..32767.
-constexpr int kColMax = 32767 - 63;
-static_assert(kI16MaxRef + 64 - 2 <= kColMax, "column field of the keys overflows");
+// over -(W-1) .. kI16MaxRef + W - 2 for groups of up to 256 lanes, so
+// kColMax - j stays within 0..32767.
+constexpr int kColMax = 32767 - 255;
+static_assert(kI16MaxRef + 256 - 2 <= kColMax, "column field of the keys overflows");
 
 __device__ __forceinline__ uint32_t u32(u16x2 v) { return __builtin_bit_cast(uint32_t, v); }
 __device__ __forceinline__ u16x2 pk(uint32_t v) { return __builtin_bit_cast(u16x2, v); }

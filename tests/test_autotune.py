@@ -7,7 +7,8 @@ import pytest
 from paper_2208_12350_amd import autotune as T
 from paper_2208_12350_amd import workloads as W
 
-SHAPES16 = [(16, r) for r in range(1, 17)] + [(32, r) for r in range(5, 17)] + [(64, r) for r in range(9, 33)]
+SHAPES16 = ([(16, r) for r in range(1, 17)] + [(32, r) for r in range(5, 17)] + [(64, r) for r in range(9, 33)]
+            + [(256, r) for r in range(3, 9)])
 
 
 def _valid(table):
@@ -84,3 +85,25 @@ def test_merge_expand_round_trip_and_string():
 def test_no_covering_shape_is_an_error():
     with pytest.raises(ValueError):
         T.choose_routing(np.array([100]), np.array([200]), {(16, 4): 1.0})
+
+
+def test_wide_group_variants():
+    rates = {s: 1.0 for s in SHAPES16}
+    q = np.array([100, 300, 700, 1500, 2048])
+    r = np.array([200, 600, 1500, 3000, 4000])
+    cands = T.candidate_tables(q, r, rates, SHAPES16)
+    assert "model" in cands
+    for name, table in cands.items():
+        _valid(table)
+        if name == "model":
+            continue
+        above = int(name.split(">")[1])
+        for k, (w, rr) in enumerate(T.expand(table)):
+            rows = 16 * (k + 1)
+            if rows > above:
+                assert w == 256 and 256 * rr >= rows and 256 * (rr - 1) < max(rows, 256 * 3)
+            else:
+                assert (w, rr) == T.expand(cands["model"])[k]
+    # no cooperative shapes compiled: nothing to vary
+    only = [s for s in SHAPES16 if s[0] != 256]
+    assert list(T.candidate_tables(q, r, {s: 1.0 for s in only}, only)) == ["model"]

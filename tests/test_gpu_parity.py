@@ -297,7 +297,7 @@ def test_streams_and_per_launch_timing_agree():
 def _routing(widths):
     """A routing table that, for each 16-row bucket, uses the first listed
     group width whose compiled shapes cover it, with the smallest R."""
-    R_OF = {16: range(1, 17), 32: range(5, 17), 64: range(9, 33)}
+    R_OF = {16: range(1, 17), 32: range(5, 17), 64: range(9, 33), 256: range(3, 9)}
     table = []
     for hi in range(16, 2049, 16):
         for w in widths:
@@ -322,7 +322,7 @@ def test_routing_choices_agree():
     try:
         default = al.routing(16)
         assert default[-1][0] == 2048
-        for widths in ((64,), (32, 64), (16, 32, 64), (16, 64)):
+        for widths in ((64,), (32, 64), (16, 32, 64), (16, 64), (256,), (16, 32, 256)):
             al.set_routing(16, _routing(widths))
             got_table = al.routing(16)
             assert got_table[-1][0] == 2048

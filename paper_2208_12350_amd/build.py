@@ -10,6 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libswalign.so")
+PROBE_LIB = os.path.join(HERE, "libswprobe.so")
 SOURCES = ["sw_plan.hip", "sw_queue_i16_w16.hip", "sw_queue_i16_w32.hip", "sw_queue_i16_w64.hip",
            "sw_queue_i16_w256.hip",
            "sw_queue_i32.hip", "sw_runtime.hip", "sw_server.hip"]
@@ -50,6 +51,13 @@ def build(verbose: bool = False) -> str:
     link = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
     subprocess.check_call(link)
     os.replace(tmp, LIB)
+    # the VALU issue-rate probe, a separate library outside the alignment path
+    tmp = PROBE_LIB + ".tmp%d" % os.getpid()
+    cmd = [HIPCC] + FLAGS + ["-shared", os.path.join(CSRC, "sw_probe.hip"), "-o", tmp]
+    r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)
+    if r.returncode != 0:
+        raise RuntimeError("hipcc failed:\n" + " ".join(cmd) + "\n" + r.stdout.decode(errors="replace"))
+    os.replace(tmp, PROBE_LIB)
     if verbose:
         print("built %s in %.1fs" % (LIB, time.time() - t0))
     return LIB

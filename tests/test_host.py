@@ -52,3 +52,19 @@ def test_pool_allocator_native(tmp_path):
     out = subprocess.run([exe], capture_output=True, text=True, timeout=120)
     assert out.returncode == 0, out.stdout + out.stderr
     assert "pool ok" in out.stdout
+
+
+PROBE_LIB = os.path.join(ROOT, "paper_2208_12350_amd", "libswprobe.so")
+
+
+@pytest.mark.skipif(not os.path.exists(PROBE_LIB), reason="libswprobe.so not built")
+def test_probe_library_exports_and_rejects_bad_arguments():
+    lib = ctypes.CDLL(PROBE_LIB)
+    text = re.sub(r"/\*.*?\*/", "", open(os.path.join(ROOT, "include", "swprobe.h")).read(), flags=re.S)
+    for n in set(re.findall(r"\b(sw_[a-z_]+)\s*\(", text)):
+        assert hasattr(lib, n), n
+    lib.sw_probe_valu.restype = ctypes.c_int
+    v = ctypes.c_double(0)
+    assert lib.sw_probe_valu(0, 9, 10, 1, ctypes.byref(v)) == -1       # unknown kind
+    assert lib.sw_probe_valu(0, 0, 0, 1, ctypes.byref(v)) == -1        # no iterations
+    assert lib.sw_probe_valu(0, 0, 10, 1, None) == -1

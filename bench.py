@@ -116,11 +116,11 @@ def roofline_leg(args, db, out, tuning, mode):
         alr.align(db, out)
         if k:
             for e in alr.bin_stats():
-                key = (e["pass"], e["precision"], e["lanes"], e["rows"])
+                key = (e["pass"], e["precision"], e["lanes"], e["rows"], e["column"])
                 acc = per_launch.setdefault(key, [0.0, 0, 0])
                 acc[0] += e["ms"]; acc[1] += e["cells"]; acc[2] += 1
     alr.close()
-    (dpass, dprec, dlanes, drows), (dms, dcells, dn) = max(per_launch.items(), key=lambda kv: kv[1][0])
+    (dpass, dprec, dlanes, drows, dcol), (dms, dcells, dn) = max(per_launch.items(), key=lambda kv: kv[1][0])
     launch_ms = dms / dn
     cells_per_launch = dcells / dn
     peak = VALU_INT16X2_TOPS if dprec == 16 else VALU_INT32_TOPS
@@ -134,7 +134,8 @@ def roofline_leg(args, db, out, tuning, mode):
     if dlanes > 64:
         kernel_name = "sw::sw_coop_kernel<%d, %s>" % (drows, direction)
     else:
-        kernel_name = "sw::sw_queue_kernel<%d, %d, %d, %s>" % (dprec, dlanes, drows, direction)
+        kernel_name = "sw::sw_queue_kernel<%d, %d, %d, %s, %s>" % (dprec, dlanes, drows, direction,
+                                                                  "true" if dcol else "false")
     return {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 2),
             "unit": "Tops/s", "frac": round(achieved / peak, 4),
             "traffic": stored_traffic(kernel_name, args.workload),
@@ -313,8 +314,11 @@ def main():
         idx = rng.choice(batch.n_pairs, size=min(batch.n_pairs, 50000), replace=False)
         ql, rl = batch.q_len()[idx], batch.r_len()[idx]
         m_med = int(np.clip(np.median(rl[rl > 0]) if np.any(rl > 0) else 512, 64, 4096))
-        rates = T.measure_rates(0, 16, m=m_med, log=log)
-        cands = T.candidate_tables(ql, rl, rates, list(rates))
+        rates = T.measure_rates(0, 16, m=m_med, log=log, scheme=T.dominant_scheme(batch))
+        probe = Aligner(0)
+        builtin = probe.routing(16)
+        probe.close()
+        cands = T.candidate_tables(ql, rl, rates, list(rates), builtin=builtin)
         name, table, _ = T.pick_by_timing(db, cands, 0, log=log)
         tuning = routing_string(16, table)
         tune_s = time.time() - t_tune

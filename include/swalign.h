@@ -123,6 +123,10 @@ const char* sw_last_error(sw_handle* h);
  *               graphs are sized for the capacity and read the batch size
  *               from device memory, so one graph serves every batch with the
  *               same buffers and at most that many pairs
+ *   "colpath"   1 = pairs whose scheme has at most 4 residues (and whose
+ *               scores plus gap_open fit a byte) read their substitution
+ *               scores from per-column words instead of table lookups
+ *               (default 1; 0 = always table lookups)
  *   "streams"   1..4: persistent mode spreads the bins' kernels over this
  *               many streams forked from (and joined back into) the
  *               caller's stream (default 4)
@@ -199,7 +203,11 @@ int sw_get_routing(sw_handle* h, int precision, int32_t* rows_max, int32_t* lane
                    int* n_out);
 
 /* One sweep kernel launch of the last call: the bin of pairs of one shape
- * (precision, lanes per pair group, query rows per lane) in one pass. */
+ * (precision, lanes per pair group, query rows per lane) in one pass, and of
+ * one score source (column words for small alphabets, or table lookups).
+ * A work item straddling a bin's column/table boundary runs in the table
+ * kernel, so up to (pairs per item - 1) column-path pairs of a bin may be
+ * counted against the column entry but swept by the table kernel. */
 typedef struct sw_bin_stat {
     int32_t pass;        /* 0 forward, 1 reverse */
     int32_t precision;   /* 16 (two pairs packed per register) or 32 */
@@ -208,12 +216,13 @@ typedef struct sw_bin_stat {
     int64_t pairs;       /* pairs the bin held in this pass */
     int64_t cells;       /* DP cells of those pairs in this pass */
     float ms;            /* kernel time (HIP events) with "timing" = 2, else 0 */
-    int32_t reserved;
+    int32_t column;      /* 1 = the column-word kernel, 0 = the table-lookup kernel */
 } sw_bin_stat;
 
 /* Per-launch statistics of the last call on this handle: writes up to
- * `capacity` entries (every bin of the forward pass, then of the reverse
- * pass) into the HOST array `out` and their number into *n_out.  Returns
+ * `capacity` entries (every kernel of every bin of the forward pass, then
+ * of the reverse pass) into the HOST array `out` and their number into
+ * *n_out.  Returns
  * SW_EINVAL (with *n_out set to the number needed) if capacity is too small. */
 int sw_last_bin_stats(sw_handle* h, sw_bin_stat* out, int capacity, int* n_out);
 

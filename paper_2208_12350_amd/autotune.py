@@ -117,22 +117,36 @@ def predicted_ms(q_len, r_len, table: Table, rates: Dict[Shape, float]) -> float
     return total
 
 
-def _probe_batch(W: int, R: int, m: int, n_pairs: int, seed: int):
+def _probe_batch(W: int, R: int, m: int, n_pairs: int, seed: int, scheme):
     from . import workloads as WL
     rng = np.random.default_rng(seed)
     n = W * R
-    q = rng.integers(0, 4, size=n_pairs * n).astype(np.uint8)
-    r = rng.integers(0, 4, size=n_pairs * m).astype(np.uint8)
+    A = scheme.alphabet
+    q = rng.integers(0, A, size=n_pairs * n).astype(np.uint8)
+    r = rng.integers(0, A, size=n_pairs * m).astype(np.uint8)
     q_off = np.arange(n_pairs + 1, dtype=np.int64) * n
     r_off = np.arange(n_pairs + 1, dtype=np.int64) * m
-    return WL.Batch(q, q_off, r, r_off, np.zeros(n_pairs, np.uint8), [WL.dna_scheme()], "probe", seed)
+    return WL.Batch(q, q_off, r, r_off, np.zeros(n_pairs, np.uint8), [scheme], "probe", seed)
+
+
+def dominant_scheme(batch):
+    """The scheme of a batch that carries the most forward cells (its
+    substitution scores decide which kernel variant the probes should time)."""
+    cells = (batch.q_len().astype(np.int64) * batch.r_len().astype(np.int64))
+    per = np.bincount(batch.scheme_id.astype(np.int64), weights=cells.astype(np.float64),
+                      minlength=len(batch.schemes))
+    return batch.schemes[int(np.argmax(per))]
 
 
 def measure_rates(device: int = 0, precision: int = 16, m: int = 512, target_cells: float = 4e9,
                   repeats: int = 2, shapes: Optional[Sequence[Shape]] = None,
-                  log=None) -> Dict[Shape, float]:
+                  log=None, scheme=None) -> Dict[Shape, float]:
     """Slots per millisecond of the forward sweep of every compiled shape of
-    `precision` (or of `shapes`), from per-launch HIP-event timing."""
+    `precision` (or of `shapes`), from per-launch HIP-event timing, on
+    random sequences scored by `scheme` (default: the DNA scheme; a small
+    alphabet runs the column-word kernels, a large one the table kernels)."""
+    from . import workloads as WL
+    scheme = scheme if scheme is not None else WL.dna_scheme()
     import torch
     from .binding import Aligner, DeviceBatch
 
@@ -146,7 +160,7 @@ def measure_rates(device: int = 0, precision: int = 16, m: int = 512, target_cel
             ppw = (64 // W if W <= 64 else 1) * (2 if precision == 16 else 1)
             n_pairs = int(np.clip(target_cells / (W * R * m), 2048 * ppw // 4, 400_000))
             n_pairs -= n_pairs % ppw
-            b = _probe_batch(W, R, m, n_pairs, seed=W * 1000 + R)
+            b = _probe_batch(W, R, m, n_pairs, seed=W * 1000 + R, scheme=scheme)
             db = DeviceBatch.from_host(b, "cuda:%d" % device)
             out = torch.empty((n_pairs, 5), dtype=torch.int32, device="cuda:%d" % device)
             table = [(W * R, W, R)]
@@ -157,9 +171,8 @@ def measure_rates(device: int = 0, precision: int = 16, m: int = 512, target_cel
             for k in range(repeats + 1):
                 al.align(db, out)
                 if k:
-                    for e in al.bin_stats():
-                        if (e["pass"], e["precision"], e["lanes"], e["rows"]) == (0, precision, W, R):
-                            ms.append(e["ms"])
+                    ms.append(sum(e["ms"] for e in al.bin_stats()
+                                  if (e["pass"], e["precision"], e["lanes"], e["rows"]) == (0, precision, W, R)))
             t = float(np.median(ms))
             rates[(W, R)] = float(np.sum(slots(np.full(n_pairs, m), (W, R)))) / t
             if log:
@@ -188,11 +201,15 @@ def with_wide_groups(table: Table, rows_above: int, shapes: Sequence[Shape], wid
     return merge(choice)
 
 
-def candidate_tables(q_len, r_len, rates: Dict[Shape, float], shapes: Sequence[Shape]) -> Dict[str, Table]:
-    """Routings worth timing on the real batch: the rate model's choice, and
-    the same with long queries on cooperative 256-lane groups."""
+def candidate_tables(q_len, r_len, rates: Dict[Shape, float], shapes: Sequence[Shape],
+                     builtin: Optional[Table] = None) -> Dict[str, Table]:
+    """Routings worth timing on the real batch: the rate model's choice, the
+    same with long queries on cooperative 256-lane groups, and the library's
+    built-in routing."""
     model = choose_routing(q_len, r_len, rates)
     out = {"model": model}
+    if builtin is not None and builtin != model:
+        out["builtin"] = list(builtin)
     for above in (512, 768, 1024):
         t = with_wide_groups(model, above, shapes)
         if t != model and t not in out.values():

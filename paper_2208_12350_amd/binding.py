@@ -57,7 +57,7 @@ class sw_batch(ctypes.Structure):
 class sw_bin_stat(ctypes.Structure):
     _fields_ = [("pass_", ctypes.c_int32), ("precision", ctypes.c_int32), ("lanes", ctypes.c_int32),
                 ("rows", ctypes.c_int32), ("pairs", ctypes.c_int64), ("cells", ctypes.c_int64),
-                ("ms", ctypes.c_float), ("reserved", ctypes.c_int32)]
+                ("ms", ctypes.c_float), ("column", ctypes.c_int32)]
 
 
 class SwError(RuntimeError):
@@ -191,13 +191,13 @@ def sw_last_timing(h: int):
 
 def sw_last_bin_stats(h: int):
     """Per-launch statistics of the last call: a list of dicts with keys
-    pass, precision, lanes, rows, pairs, cells, ms."""
+    pass, precision, lanes, rows, column, pairs, cells, ms."""
     lib = load_library()
     n = ctypes.c_int(0)
     lib.sw_last_bin_stats(h, None, 0, ctypes.byref(n))
     arr = (sw_bin_stat * max(1, n.value))()
     _check(h, lib.sw_last_bin_stats(h, arr, n.value, ctypes.byref(n)))
-    return [{"pass": e.pass_, "precision": e.precision, "lanes": e.lanes, "rows": e.rows,
+    return [{"pass": e.pass_, "precision": e.precision, "lanes": e.lanes, "rows": e.rows, "column": e.column,
              "pairs": int(e.pairs), "cells": int(e.cells), "ms": float(e.ms)} for e in arr[:n.value]]
 
 

@@ -124,20 +124,40 @@ struct RefStager {
             buf[l + k * W] = (uint16_t)(sbase + b * kMatDim);
         }
     }
+    // Small-alphabet path: write the chunk as column words (bytes M[a][b] + o
+    // for a = 0..3); out-of-range columns and invalid residues get word 0,
+    // i.e. a score of -o for every row.
+    __device__ __forceinline__ void store_col(uint32_t* buf, const PairJob& J, int A, const uint32_t* colw,
+                                              int t0, int l, bool& bad) const {
+#pragma unroll
+        for (int k = 0; k < kPerLane; ++k) {
+            const int j = t0 - W + l + k * W;
+            const int b = raw[k];
+            const bool inside = j >= 0 && j < J.m;
+            bad |= inside && b >= A;
+            buf[l + k * W] = (inside && b < A) ? colw[b] : 0u;
+        }
+    }
 };
 
-// Per-block copy of the scoring schemes: substitution tables and gap costs.
+// Per-block copy of the scoring schemes: substitution tables, column words
+// of the small-alphabet path and gap costs.
 struct SchemeLds {
     int8_t mat[SW_MAX_SCHEMES * kMatBytes];
+    uint32_t colw[SW_MAX_SCHEMES][kMatDim];
     int32_t alphabet[SW_MAX_SCHEMES];
     int32_t gap_open[SW_MAX_SCHEMES];
     int32_t gap_extend[SW_MAX_SCHEMES];
+    int32_t col_ok[SW_MAX_SCHEMES];
 };
 
 __device__ __forceinline__ void load_schemes(SchemeLds& S, const KParams& P, int tid) {
     for (int k = tid; k < SW_MAX_SCHEMES * kMatBytes / 4; k += kBlock)
         reinterpret_cast<int32_t*>(S.mat)[k] = reinterpret_cast<const int32_t*>(P.mats)[k];
+    for (int k = tid; k < SW_MAX_SCHEMES * kMatDim; k += kBlock)
+        (&S.colw[0][0])[k] = reinterpret_cast<const uint32_t*>(P.mats + SW_MAX_SCHEMES * kMatBytes)[k];
     if (tid < SW_MAX_SCHEMES) {
+        S.col_ok[tid] = P.col_ok[tid];
         S.alphabet[tid] = P.alphabet[tid];
         S.gap_open[tid] = P.gap_open[tid];
         S.gap_extend[tid] = P.gap_extend[tid];

@@ -14,6 +14,10 @@ namespace sw {
 constexpr int kPad = 31;
 constexpr int kMatDim = 32;                    // LDS matrix is 32 x 32 int8
 constexpr int kMatBytes = kMatDim * kMatDim;   // per scheme
+// After the matrices, per scheme and reference residue b: the column word
+// of the small-alphabet path, bytes M[a][b] + o for a = 0..3 (see sw_sweep.h).
+constexpr int kColWordsBytes = SW_MAX_SCHEMES * kMatDim * 4;
+constexpr int kSchemeBytes = SW_MAX_SCHEMES * kMatBytes + kColWordsBytes;
 constexpr int kBlock = 256;                    // 4 wavefronts per workgroup
 constexpr int kWavesPerBlock = kBlock / 64;
 
@@ -27,21 +31,25 @@ constexpr int kMBuckets = 1024;                        // length buckets per bin
 constexpr int kTrivialKey = kMaxBins * kMBuckets;      // empty / invalid pairs
 constexpr int kHistSize = kTrivialKey + 1;
 
-// Reference length -> bucket, monotone: exact below 512, then 64 buckets per
-// octave (width <= 1/64 of the length) up to 65535.
+// Reference length -> bucket within one half of a bin's key range,
+// monotone: exact below 256, then 32 buckets per octave (width <= 1/32 of
+// the length) up to 65535.
+constexpr int kMHalf = kMBuckets / 2;
 __host__ __device__ inline int m_bucket(int m) {
-    if (m < 512) return m;
-    const int lg = 31 - __builtin_clz((unsigned)m);          // 9..15
-    const int frac = (m >> (lg - 6)) & 63;
-    int b = 512 + (lg - 9) * 64 + frac;
-    return b < kMBuckets ? b : kMBuckets - 1;
+    if (m < 256) return m;
+    const int lg = 31 - __builtin_clz((unsigned)m);          // 8..15
+    const int frac = (m >> (lg - 5)) & 31;
+    int b = 256 + (lg - 8) * 32 + frac;
+    return b < kMHalf ? b : kMHalf - 1;
 }
 
 struct BinInfo {
     uint8_t prec;     // 16 = two pairs per lane group packed in int16 halves, 32 = int32
     uint8_t R;        // query rows per lane
     uint16_t W;       // lanes per group: 16, 32, 64, or 256 (a workgroup's four wavefronts)
-    int32_t ppw;      // pairs per work item
+    uint16_t ppw;     // pairs per work item
+    uint8_t col;      // 1 = the shape has a column-word kernel (small alphabets)
+    uint8_t pad;
 };
 
 // Pairs per work item of a shape: a wavefront's groups (times two packed
@@ -61,11 +69,17 @@ struct WorkItem {
 };
 
 // Layout of the per-pass planning metadata array (int32).
+// Within a bin, items [first, split) hold only pairs of column-path schemes
+// and go to the shape's column-word kernel; [split, next bin's first) go to
+// its table-lookup kernel (split == first for shapes without a column
+// kernel).  Each of the two has its own queue head.
 enum : int {
     kMetaBinFirst = 0,                                // [kMaxBins + 1] first sorted position of each bin
     kMetaItemFirst = kMetaBinFirst + kMaxBins + 1,    // [kMaxBins + 1] first item of each bin
-    kMetaHeads = kMetaItemFirst + kMaxBins + 1,       // [kMaxBins] queue head of each bin
-    kMetaSize = kMetaHeads + kMaxBins,
+    kMetaItemSplit = kMetaItemFirst + kMaxBins + 1,   // [kMaxBins] first table-lookup item of each bin
+    kMetaHeads = kMetaItemSplit + kMaxBins,           // [kMaxBins] queue head of each bin's table-lookup items
+    kMetaColHeads = kMetaHeads + kMaxBins,            // [kMaxBins] and of its column-word items
+    kMetaSize = kMetaColHeads + kMaxBins,
 };
 
 // Layout of the 64-bit statistics counters of a call (cleared at its start).
@@ -75,7 +89,9 @@ enum : int {
     kCtrI32Pairs = 2,
     kCtrBinCells = 4,                        // [2 * kMaxBins] cells per (pass, bin)
     kCtrBinPairs = kCtrBinCells + 2 * kMaxBins,   // [2 * kMaxBins] pairs per (pass, bin)
-    kNumCounters = kCtrBinPairs + 2 * kMaxBins,
+    kCtrBinColCells = kCtrBinPairs + 2 * kMaxBins,   // [2 * kMaxBins] cells of column-path pairs
+    kCtrBinColPairs = kCtrBinColCells + 2 * kMaxBins,   // [2 * kMaxBins] column-path pairs
+    kNumCounters = kCtrBinColPairs + 2 * kMaxBins,
 };
 
 // Arguments shared by every sweep launch.
@@ -96,6 +112,7 @@ struct KParams {
     int32_t alphabet[SW_MAX_SCHEMES];
     int32_t gap_open[SW_MAX_SCHEMES];
     int32_t gap_extend[SW_MAX_SCHEMES];
+    int32_t col_ok[SW_MAX_SCHEMES];   // scheme can take the small-alphabet column path
     int32_t validate;
     int32_t reverse;             // 0 = forward sweep, 1 = reverse sweep
     int32_t lo_idx, hi_idx;      // meta[lo_idx] .. meta[hi_idx] is this launch's item range
@@ -128,6 +145,7 @@ constexpr int kI16MaxRef = 32000;
 constexpr int kLutRows = SW_MAX_QUERY / 16;
 struct ClassifyArgs {
     int32_t max_score[SW_MAX_SCHEMES];
+    int32_t col_ok[SW_MAX_SCHEMES];
     int32_t i16_limit;      // negative disables the int16 path
     int32_t n_schemes;
     int32_t n_bins;
@@ -145,14 +163,16 @@ using QueueFn = void (*)(KParams);
 
 struct ShapeDesc { int prec, W, R; };
 
-QueueFn shape_kernel(int prec, int W, int R, bool reverse);
+// The kernel of a compiled shape; `col` selects its column-word variant
+// (nullptr when the shape has none).
+QueueFn shape_kernel(int prec, int W, int R, bool reverse, bool col = false);
 const ShapeDesc* compiled_shapes(int* n);
 
 hipError_t launch_reset(int32_t* p, int n, hipStream_t s);
 // The planning launches are sized for `cap` pairs; the kernels take the
 // batch size from device memory (P.n_dev / n_dev), so a captured graph can be
 // replayed for any batch of at most `cap` pairs.
-hipError_t launch_classify(const KParams& P, const ClassifyArgs& C, const int8_t* lut,
+hipError_t launch_classify(const KParams& P, const ClassifyArgs& C, const int8_t* lut, const BinInfo* bins,
                            int64_t cap, int32_t* keys, int32_t* hist,
                            unsigned long long* counters, hipStream_t s);
 hipError_t launch_plan(const BinInfo* bins, int n_bins, int32_t* hist, int32_t* meta,

@@ -24,7 +24,7 @@ __global__ void sw_reset_kernel(int32_t* p, int n) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
 }
 
-__global__ void sw_classify_kernel(KParams P, ClassifyArgs C, const int8_t* lut,
+__global__ void sw_classify_kernel(KParams P, ClassifyArgs C, const int8_t* lut, const BinInfo* bins,
                                    int32_t* keys, int32_t* hist, unsigned long long* counters) {
     const int64_t n_pairs = *P.n_dev;
     // counters[0] / [1]: forward / reverse cells; counters[2]: int32 pairs
@@ -32,10 +32,13 @@ __global__ void sw_classify_kernel(KParams P, ClassifyArgs C, const int8_t* lut,
     // kCtrBinPairs, indexed pass * kMaxBins + bin)
     __shared__ unsigned long long s_cells;
     __shared__ int32_t s_trivial, s_i32;
-    __shared__ unsigned long long s_bin_cells[kMaxBins];
-    __shared__ uint32_t s_bin_pairs[kMaxBins];
+    __shared__ unsigned long long s_bin_cells[2][kMaxBins];   // [column path?][bin]
+    __shared__ uint32_t s_bin_pairs[2][kMaxBins];
     if (threadIdx.x == 0) { s_cells = 0; s_trivial = 0; s_i32 = 0; }
-    if (threadIdx.x < kMaxBins) { s_bin_cells[threadIdx.x] = 0; s_bin_pairs[threadIdx.x] = 0; }
+    if (threadIdx.x < kMaxBins) {
+        s_bin_cells[0][threadIdx.x] = s_bin_cells[1][threadIdx.x] = 0;
+        s_bin_pairs[0][threadIdx.x] = s_bin_pairs[1][threadIdx.x] = 0;
+    }
     __syncthreads();
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     unsigned long long my_cells = 0;
@@ -76,11 +79,15 @@ __global__ void sw_classify_kernel(KParams P, ClassifyArgs C, const int8_t* lut,
             const int sel = (mn * C.max_score[s] <= C.i16_limit && m <= kI16MaxRef) ? 0 : 1;
             if (sel && !P.reverse) atomicAdd(&s_i32, 1);
             const int bin = lut[sel * kLutRows + (int)((n - 1) / 16)];
-            key = bin * kMBuckets + (kMBuckets - 1 - m_bucket((int)m));
+            // within a bin: pairs of column-path schemes first (the bin's
+            // column-word kernel takes them), each part by decreasing
+            // reference length; only packed-int16 pairs use column words
+            const int col = (sel == 0 && C.col_ok[s] && bins[bin].col) ? 1 : 0;
+            key = bin * kMBuckets + (col ? 0 : kMHalf) + (kMHalf - 1 - m_bucket((int)m));
             atomicAdd(&hist[key], 1);
             my_cells = (unsigned long long)(n * m);
-            atomicAdd(&s_bin_cells[bin], my_cells);
-            atomicAdd(&s_bin_pairs[bin], 1u);
+            atomicAdd(&s_bin_cells[col][bin], my_cells);
+            atomicAdd(&s_bin_pairs[col][bin], 1u);
         } else {
             atomicAdd(&s_trivial, 1);
         }
@@ -93,10 +100,18 @@ __global__ void sw_classify_kernel(KParams P, ClassifyArgs C, const int8_t* lut,
         if (s_i32) atomicAdd(&counters[kCtrI32Pairs], (unsigned long long)s_i32);
         if (s_trivial) atomicAdd(&hist[kTrivialKey], s_trivial);
     }
-    if (threadIdx.x < kMaxBins && s_bin_pairs[threadIdx.x]) {
-        const int slot = (P.reverse ? kMaxBins : 0) + threadIdx.x;
-        atomicAdd(&counters[kCtrBinCells + slot], s_bin_cells[threadIdx.x]);
-        atomicAdd(&counters[kCtrBinPairs + slot], (unsigned long long)s_bin_pairs[threadIdx.x]);
+    if (threadIdx.x < kMaxBins) {
+        const int b = threadIdx.x;
+        const int slot = (P.reverse ? kMaxBins : 0) + b;
+        const unsigned long long pairs = s_bin_pairs[0][b] + s_bin_pairs[1][b];
+        if (pairs) {
+            atomicAdd(&counters[kCtrBinCells + slot], s_bin_cells[0][b] + s_bin_cells[1][b]);
+            atomicAdd(&counters[kCtrBinPairs + slot], pairs);
+        }
+        if (s_bin_pairs[1][b]) {
+            atomicAdd(&counters[kCtrBinColCells + slot], s_bin_cells[1][b]);
+            atomicAdd(&counters[kCtrBinColPairs + slot], (unsigned long long)s_bin_pairs[1][b]);
+        }
     }
 }
 
@@ -158,18 +173,29 @@ __global__ __launch_bounds__(kPlanThreads) void sw_plan_kernel(const BinInfo* bi
         __syncthreads();
     }
     // per-bin ranges: the bin's first sorted position is the scanned count
-    // of its first key; its items are its pairs in groups of ppw
+    // of its first key; its items are its pairs in groups of ppw, the
+    // column-path pairs (the first half of its keys) first
+    int32_t my_col = 0;
     if (t <= kMaxBins) {
         const int32_t f = hist[t * kMBuckets];   // t == kMaxBins: the trivial key
         meta[kMetaBinFirst + t] = f;
         bin_items[t] = f;
+        if (t < kMaxBins) my_col = hist[t * kMBuckets + kMHalf] - f;
     }
-    if (t < kMaxBins) meta[kMetaHeads + t] = 0;
+    if (t < kMaxBins) {
+        meta[kMetaHeads + t] = 0;
+        meta[kMetaColHeads + t] = 0;
+    }
     __syncthreads();
-    int32_t my_items = 0;
+    int32_t my_items = 0, my_col_items = 0;
     if (t < n_bins && t < kMaxBins) {
         const int32_t cnt = bin_items[t + 1] - bin_items[t];
-        my_items = (cnt + bins[t].ppw - 1) / bins[t].ppw;
+        const int ppw = bins[t].ppw;
+        my_items = (cnt + ppw - 1) / ppw;
+        // whole items of column-path pairs (all of the bin's items when it
+        // holds nothing else); the item straddling the boundary, if any,
+        // goes to the table-lookup kernel
+        if (bins[t].col) my_col_items = my_col == cnt ? my_items : my_col / ppw;
     }
     __syncthreads();
     if (t < kMaxBins) bin_items[t] = my_items;
@@ -182,6 +208,8 @@ __global__ __launch_bounds__(kPlanThreads) void sw_plan_kernel(const BinInfo* bi
         }
         meta[kMetaItemFirst + kMaxBins] = items;
     }
+    __syncthreads();
+    if (t < kMaxBins) meta[kMetaItemSplit + t] = meta[kMetaItemFirst + t] + my_col_items;
 }
 
 __global__ void sw_scatter_kernel(const int32_t* keys, const int32_t* n_dev, int32_t* offs, int32_t* order) {
@@ -222,11 +250,11 @@ hipError_t launch_reset(int32_t* p, int n, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_classify(const KParams& P, const ClassifyArgs& C, const int8_t* lut,
+hipError_t launch_classify(const KParams& P, const ClassifyArgs& C, const int8_t* lut, const BinInfo* bins,
                            int64_t cap, int32_t* keys, int32_t* hist,
                            unsigned long long* counters, hipStream_t s) {
     if (cap <= 0) return hipSuccess;
-    hipLaunchKernelGGL(sw_classify_kernel, dim3(grid_for(cap, 256)), dim3(256), 0, s, P, C, lut,
+    hipLaunchKernelGGL(sw_classify_kernel, dim3(grid_for(cap, 256)), dim3(256), 0, s, P, C, lut, bins,
                        keys, hist, counters);
     return hipGetLastError();
 }

@@ -1,7 +1,8 @@
 // sw_queue.h -- work-queue kernels over the sweep shapes (gfx950).
 //
-// A queue kernel is compiled for one bin shape (precision, W, R) and one
-// direction (forward sweep, or reverse sweep when REV), and aligns
+// A queue kernel is compiled for one bin shape (precision, W, R), one
+// direction (forward sweep, or reverse sweep when REV) and one score source
+// (column words when COL, table lookups otherwise), and aligns
 // the work items [meta[lo_idx], meta[hi_idx]) of that bin: every wavefront
 // takes the next item with one atomic increment of the bin's queue head and
 // sweeps it, until the range is exhausted.
@@ -20,7 +21,7 @@
 
 namespace sw {
 
-template <int PREC, int W, int R, bool REV>
+template <int PREC, int W, int R, bool REV, bool COL>
 __global__ __launch_bounds__(kBlock) void sw_queue_kernel(KParams P) {
     __shared__ __attribute__((aligned(16))) SchemeLds L;
     __shared__ uint16_t wbufs[kWavesPerBlock * kWaveBuf];
@@ -58,7 +59,9 @@ __global__ __launch_bounds__(kBlock) void sw_queue_kernel(KParams P) {
         const bool valid = first >= 0 && count >= 1 && count <= kPPW && first + count <= n_pairs;
         if (valid) {
             wave_lds_sync();
-            if constexpr (PREC == 16)
+            if constexpr (COL)
+                sweep_i16_col<W, R, REV>(P, L, wbuf, first, count, lane);
+            else if constexpr (PREC == 16)
                 sweep_i16<W, R, REV>(P, L, wbuf, first, count, lane);
             else
                 sweep_i32<W, R, REV>(P, L, wbuf, first, count, lane);
@@ -68,6 +71,7 @@ __global__ __launch_bounds__(kBlock) void sw_queue_kernel(KParams P) {
     }
 }
 
-struct KernelEntry { int prec, W, R; QueueFn fwd, rev; };
+// fwd/rev: table-lookup kernels; cfwd/crev: column-word kernels (or null)
+struct KernelEntry { int prec, W, R; QueueFn fwd, rev, cfwd, crev; };
 
 }  // namespace sw

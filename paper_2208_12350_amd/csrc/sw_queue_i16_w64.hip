@@ -8,7 +8,9 @@ namespace sw {
 extern const KernelEntry kI16W64Kernels[];
 extern const int kNumI16W64Kernels;
 
-#define SW_ENTRY(W, R) {16, W, R, &sw_queue_kernel<16, W, R, false>, &sw_queue_kernel<16, W, R, true>},
+#define SW_ENTRY(W, R) \
+    {16, W, R, &sw_queue_kernel<16, W, R, false, false>, &sw_queue_kernel<16, W, R, true, false>, \
+     &sw_queue_kernel<16, W, R, false, true>, &sw_queue_kernel<16, W, R, true, true>},
 const KernelEntry kI16W64Kernels[] = {
     SW_ENTRY(64, 9) SW_ENTRY(64, 10) SW_ENTRY(64, 11) SW_ENTRY(64, 12) SW_ENTRY(64, 13) SW_ENTRY(64, 14)
     SW_ENTRY(64, 15) SW_ENTRY(64, 16) SW_ENTRY(64, 17) SW_ENTRY(64, 18) SW_ENTRY(64, 19) SW_ENTRY(64, 20)

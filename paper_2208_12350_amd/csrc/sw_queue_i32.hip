@@ -5,7 +5,8 @@
 
 namespace sw {
 
-#define SW_ENTRY(W, R) {32, W, R, &sw_queue_kernel<32, W, R, false>, &sw_queue_kernel<32, W, R, true>},
+#define SW_ENTRY(W, R) \
+    {32, W, R, &sw_queue_kernel<32, W, R, false, false>, &sw_queue_kernel<32, W, R, true, false>, nullptr, nullptr},
 static const KernelEntry kI32Kernels[] = {
     SW_ENTRY(16, 2) SW_ENTRY(16, 4) SW_ENTRY(16, 6) SW_ENTRY(16, 8) SW_ENTRY(16, 10)
     SW_ENTRY(16, 12) SW_ENTRY(16, 14) SW_ENTRY(16, 16)
@@ -55,12 +56,14 @@ const ShapeDesc* compiled_shapes(int* n) {
     return g_shapes;
 }
 
-QueueFn shape_kernel(int prec, int W, int R, bool reverse) {
+QueueFn shape_kernel(int prec, int W, int R, bool reverse, bool col) {
     for (int t = 0; t < kTables; ++t) {
         const Table tb = table(t);
         for (int k = 0; k < tb.n; ++k)
-            if (tb.e[k].prec == prec && tb.e[k].W == W && tb.e[k].R == R)
+            if (tb.e[k].prec == prec && tb.e[k].W == W && tb.e[k].R == R) {
+                if (col) return reverse ? tb.e[k].crev : tb.e[k].cfwd;
                 return reverse ? tb.e[k].rev : tb.e[k].fwd;
+            }
     }
     return nullptr;
 }

@@ -51,6 +51,7 @@ struct GraphKey {
     int32_t gap_open[SW_MAX_SCHEMES];
     int32_t gap_extend[SW_MAX_SCHEMES];
     int32_t max_score[SW_MAX_SCHEMES];
+    int32_t col_ok[SW_MAX_SCHEMES];
     int32_t n_schemes;
     int32_t validate;
     int32_t precision;
@@ -68,13 +69,14 @@ struct sw_handle {
     int64_t opt_precision = 0;
     int64_t opt_timing = 0;
     int64_t opt_streams = 4;
+    int64_t opt_colpath = 1;
 
     std::vector<BinInfo> bins;
     std::vector<int> route[2];          // per precision (int16, int32) and 16-row bucket: bin
     std::vector<int8_t> lut;            // device copy of route
     std::vector<char> bin_used;         // bins some route points at
     bool lut_dirty = true;
-    std::vector<int> resident_blocks[2];   // per pass and bin: workgroups the device holds at once
+    std::vector<int> resident_blocks[2][2];   // per pass, variant and bin: workgroups the device holds at once
 
     int8_t* d_mats = nullptr;
     int8_t* d_lut = nullptr;
@@ -98,6 +100,7 @@ struct sw_handle {
     double t_enqueue = 0.0, t_wait = 0.0;   // host milliseconds of the last call
     // per (pass, bin) event pairs for "timing" = 2, created on first use
     std::vector<hipEvent_t> bin_ev;
+    std::vector<char> bin_launched;     // per (pass, bin, variant) of the last call
     std::vector<sw_bin_stat> bin_stats;
 
     hipStream_t cap_stream = nullptr;   // private stream the graph is captured on
@@ -153,7 +156,9 @@ static void build_bins(sw_handle* h) {
         b.prec = (uint8_t)s.prec;
         b.W = (uint16_t)s.W;
         b.R = (uint8_t)s.R;
-        b.ppw = pairs_per_item(s.prec, s.W);
+        b.ppw = (uint16_t)pairs_per_item(s.prec, s.W);
+        b.col = shape_kernel(s.prec, s.W, s.R, false, true) != nullptr ? 1 : 0;
+        b.pad = 0;
         h->bins.push_back(b);
     }
 }
@@ -283,6 +288,16 @@ static int ensure_pairs(sw_handle* h, int64_t n) {
     return SW_OK;
 }
 
+// Item range and queue head of bin b's column-word kernel (v = 1) or
+// table-lookup kernel (v = 0).
+static void set_range(KParams& K, int b, int v) {
+    K.lo_idx = v ? kMetaItemFirst + b : kMetaItemSplit + b;
+    K.hi_idx = v ? kMetaItemSplit + b : kMetaItemFirst + b + 1;
+    K.head_idx = v ? kMetaColHeads + b : kMetaHeads + b;
+}
+
+static int bin_ev_index(int pass, int b, int v, int end) { return ((pass * kMaxBins + b) * 2 + v) * 2 + end; }
+
 // Enqueue one pass (planning + sweeps).  Plain mode synchronises `stream`
 // once to read the per-bin item counts.
 static int enqueue_pass(sw_handle* h, KParams K, const ClassifyArgs& C, int64_t cap, int pass,
@@ -290,7 +305,7 @@ static int enqueue_pass(sw_handle* h, KParams K, const ClassifyArgs& C, int64_t 
     K.reverse = pass;
     const int n_bins = (int)h->bins.size();
     HIP_TRY(h, launch_reset(h->d_hist, kHistSize, stream));
-    HIP_TRY(h, launch_classify(K, C, h->d_lut, cap, h->d_keys, h->d_hist, counters(h->d_small), stream));
+    HIP_TRY(h, launch_classify(K, C, h->d_lut, h->d_bins, cap, h->d_keys, h->d_hist, counters(h->d_small), stream));
     HIP_TRY(h, launch_plan(h->d_bins, n_bins, h->d_hist, h->d_meta, stream));
     HIP_TRY(h, launch_scatter(h->d_keys, h->d_n, cap, h->d_hist, h->d_order, stream));
     HIP_TRY(h, launch_items(h->d_meta, h->d_bins, n_bins, h->d_n, cap, h->d_items, stream));
@@ -314,15 +329,19 @@ static int enqueue_pass(sw_handle* h, KParams K, const ClassifyArgs& C, int64_t 
             // no bin can hold more than cap / ppw items
             const int ipb = items_per_block(e.W);
             const int64_t need = (cap / e.ppw + 1 + ipb - 1) / ipb;
-            const int blocks = (int)std::min<int64_t>(need, h->resident_blocks[pass][b]);
-            K.lo_idx = kMetaItemFirst + b;
-            K.hi_idx = kMetaItemFirst + b + 1;
-            K.head_idx = kMetaHeads + b;
-            hipStream_t ls = forks > 1 ? h->fork[launched++ % forks] : stream;
-            if (per_bin) HIP_TRY(h, hipEventRecord(h->bin_ev[(pass * kMaxBins + b) * 2], ls));
-            hipLaunchKernelGGL(shape_kernel(e.prec, e.W, e.R, pass != 0), dim3(blocks), dim3(kBlock), 0, ls, K);
-            HIP_TRY(h, hipGetLastError());
-            if (per_bin) HIP_TRY(h, hipEventRecord(h->bin_ev[(pass * kMaxBins + b) * 2 + 1], ls));
+            for (int v = e.col ? 1 : 0; v >= 0; --v) {   // column-word kernel first
+                const int blocks = (int)std::min<int64_t>(need, h->resident_blocks[pass][v][b]);
+                set_range(K, b, v);
+                // a bin's kernels share a stream; bins go round-robin
+                hipStream_t ls = forks > 1 ? h->fork[launched % forks] : stream;
+                if (per_bin) HIP_TRY(h, hipEventRecord(h->bin_ev[bin_ev_index(pass, b, v, 0)], ls));
+                hipLaunchKernelGGL(shape_kernel(e.prec, e.W, e.R, pass != 0, v == 1), dim3(blocks), dim3(kBlock), 0,
+                                   ls, K);
+                HIP_TRY(h, hipGetLastError());
+                if (per_bin) HIP_TRY(h, hipEventRecord(h->bin_ev[bin_ev_index(pass, b, v, 1)], ls));
+                if (per_bin) h->bin_launched[bin_ev_index(pass, b, v, 0) / 2] = 1;
+            }
+            ++launched;
         }
         for (int f = 0; forks > 1 && f < forks; ++f) {
             HIP_TRY(h, hipEventRecord(h->fork_ev[f], h->fork[f]));
@@ -333,17 +352,19 @@ static int enqueue_pass(sw_handle* h, KParams K, const ClassifyArgs& C, int64_t 
         HIP_TRY(h, hipStreamSynchronize(stream));
         if (timing) HIP_TRY(h, hipEventRecord(h->ev[pass == 0 ? 1 : 3], stream));
         for (int b = 0; b < n_bins; ++b) {
-            const int items = h->h_meta[kMetaItemFirst + b + 1] - h->h_meta[kMetaItemFirst + b];
-            if (items <= 0) continue;
             const BinInfo& e = h->bins[b];
-            K.lo_idx = kMetaItemFirst + b;
-            K.hi_idx = kMetaItemFirst + b + 1;
-            K.head_idx = kMetaHeads + b;
-            const int blocks = (items + items_per_block(e.W) - 1) / items_per_block(e.W);
-            if (per_bin) HIP_TRY(h, hipEventRecord(h->bin_ev[(pass * kMaxBins + b) * 2], stream));
-            hipLaunchKernelGGL(shape_kernel(e.prec, e.W, e.R, pass != 0), dim3(blocks), dim3(kBlock), 0, stream, K);
-            HIP_TRY(h, hipGetLastError());
-            if (per_bin) HIP_TRY(h, hipEventRecord(h->bin_ev[(pass * kMaxBins + b) * 2 + 1], stream));
+            for (int v = e.col ? 1 : 0; v >= 0; --v) {
+                set_range(K, b, v);
+                const int items = h->h_meta[K.hi_idx] - h->h_meta[K.lo_idx];
+                if (items <= 0) continue;
+                const int blocks = (items + items_per_block(e.W) - 1) / items_per_block(e.W);
+                if (per_bin) HIP_TRY(h, hipEventRecord(h->bin_ev[bin_ev_index(pass, b, v, 0)], stream));
+                hipLaunchKernelGGL(shape_kernel(e.prec, e.W, e.R, pass != 0, v == 1), dim3(blocks), dim3(kBlock), 0,
+                                   stream, K);
+                HIP_TRY(h, hipGetLastError());
+                if (per_bin) HIP_TRY(h, hipEventRecord(h->bin_ev[bin_ev_index(pass, b, v, 1)], stream));
+                if (per_bin) h->bin_launched[bin_ev_index(pass, b, v, 0) / 2] = 1;
+            }
         }
     }
     if (timing) HIP_TRY(h, hipEventRecord(h->ev[pass == 0 ? 2 : 4], stream));
@@ -368,7 +389,7 @@ sw_handle* sw_create(int device, const char* tuning) {
     }
     rebuild_lut(h);
     ok = ok && h->bins.size() <= (size_t)kMaxBins &&
-         hipMalloc(&h->d_mats, SW_MAX_SCHEMES * kMatBytes) == hipSuccess &&
+         hipMalloc(&h->d_mats, kSchemeBytes) == hipSuccess &&
          hipMalloc(&h->d_lut, kLutEntries) == hipSuccess &&
          hipMalloc(&h->d_bins, kMaxBins * sizeof(BinInfo)) == hipSuccess &&
          hipMalloc(&h->d_small, kSmallInts * 4) == hipSuccess &&
@@ -376,7 +397,7 @@ sw_handle* sw_create(int device, const char* tuning) {
          hipHostMalloc(&h->h_n, 16, hipHostMallocDefault) == hipSuccess &&
          hipMalloc(&h->d_hist, kHistSize * 4) == hipSuccess &&
          hipMalloc(&h->d_meta, kMetaSize * 4) == hipSuccess &&
-         hipHostMalloc(&h->h_mats, SW_MAX_SCHEMES * kMatBytes, hipHostMallocDefault) == hipSuccess &&
+         hipHostMalloc(&h->h_mats, kSchemeBytes, hipHostMallocDefault) == hipSuccess &&
          hipHostMalloc(&h->h_small, kSmallInts * 4, hipHostMallocDefault) == hipSuccess &&
          hipHostMalloc(&h->h_meta, kMetaSize * 4, hipHostMallocDefault) == hipSuccess;
     for (int k = 0; ok && k < 5; ++k) ok = hipEventCreate(&h->ev[k]) == hipSuccess;
@@ -386,16 +407,18 @@ sw_handle* sw_create(int device, const char* tuning) {
         ok = hipEventCreateWithFlags(&h->fork_ev[f], hipEventDisableTiming) == hipSuccess;
     if (ok) ok = hipMemcpy(h->d_bins, h->bins.data(), h->bins.size() * sizeof(BinInfo),
                            hipMemcpyHostToDevice) == hipSuccess;
-    for (int pass = 0; pass < 2; ++pass) {
-        h->resident_blocks[pass].assign(h->bins.size(), 1);
-        for (size_t b = 0; ok && b < h->bins.size(); ++b) {
-            int per_cu = 0;
-            const QueueFn fn = shape_kernel(h->bins[b].prec, h->bins[b].W, h->bins[b].R, pass != 0);
-            ok = fn && hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)fn, kBlock, 0) ==
-                           hipSuccess;
-            h->resident_blocks[pass][b] = std::max(1, per_cu) * std::max(1, h->n_cu);
+    for (int pass = 0; pass < 2; ++pass)
+        for (int v = 0; v < 2; ++v) {
+            h->resident_blocks[pass][v].assign(h->bins.size(), 1);
+            for (size_t b = 0; ok && b < h->bins.size(); ++b) {
+                if (v == 1 && !h->bins[b].col) continue;
+                int per_cu = 0;
+                const QueueFn fn = shape_kernel(h->bins[b].prec, h->bins[b].W, h->bins[b].R, pass != 0, v == 1);
+                ok = fn && hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)fn, kBlock, 0) ==
+                               hipSuccess;
+                h->resident_blocks[pass][v][b] = std::max(1, per_cu) * std::max(1, h->n_cu);
+            }
         }
-    }
     if (!ok) { sw_destroy(h); return nullptr; }
     if (tuning) {
         std::string s(tuning);
@@ -461,11 +484,13 @@ int sw_set_option(sw_handle* h, const char* key, int64_t value) {
     } else if (k == "timing") {
         if (value < 0 || value > 2) return fail(h, SW_EINVAL, "timing must be 0, 1 or 2");
         if (value == 2 && h->bin_ev.empty()) {
-            h->bin_ev.assign(2 * kMaxBins * 2, nullptr);
+            h->bin_ev.assign(2 * kMaxBins * 2 * 2, nullptr);
             for (hipEvent_t& e : h->bin_ev)
                 if (hipEventCreate(&e) != hipSuccess) return fail(h, SW_EDEVICE, "event creation failed");
         }
         h->opt_timing = value;
+    } else if (k == "colpath") {
+        h->opt_colpath = value ? 1 : 0;
     } else if (k == "capacity") {
         // reserve workspace for this many pairs up front (grids and graphs are
         // sized for the capacity, so batches up to it reuse one graph)
@@ -497,6 +522,7 @@ int sw_get_option(sw_handle* h, const char* key, int64_t* value) {
     else if (k == "timing") *value = h->opt_timing;
     else if (k == "streams") *value = h->opt_streams;
     else if (k == "capacity") *value = h->cap_pairs;
+    else if (k == "colpath") *value = h->opt_colpath;
     else if (k == "captures") *value = h->n_captures;
     else if (k == "capture_refusals") *value = h->n_capture_refusals;
     else return fail(h, SW_EINVAL, "unknown option '%s'", key);
@@ -519,6 +545,7 @@ static int align_spans(sw_handle* h, const uint8_t* queries, const int64_t* q_be
     h->t_plan = h->t_fwd = h->t_rev = 0.f;
     h->t_enqueue = h->t_wait = 0.0;
     h->bin_stats.clear();
+    h->bin_launched.assign(2 * kMaxBins * 2, 0);
     if (!schemes) return fail(h, SW_EINVAL, "null schemes");
     if (n_schemes < 1 || n_schemes > SW_MAX_SCHEMES)
         return fail(h, SW_EINVAL, "n_schemes must be 1..%d", SW_MAX_SCHEMES);
@@ -561,6 +588,23 @@ static int align_spans(sw_handle* h, const uint8_t* queries, const int64_t* q_be
                 T[b * kMatDim + a] = v;
             }
         C.max_score[s] = mx;
+        // small-alphabet column path: alphabet <= 4, 1 <= o <= kI16Bias and
+        // every M[a][b] + o a byte; column word of residue b = bytes
+        // M[a][b] + o, a = 0..3 (0 for residues outside the alphabet)
+        uint32_t* cw = reinterpret_cast<uint32_t*>(h->h_mats + SW_MAX_SCHEMES * kMatBytes) + s * kMatDim;
+        bool ok = s < n_schemes && schemes[s].alphabet <= 4 && schemes[s].gap_open >= 1 &&
+                  schemes[s].gap_open <= kI16Bias;
+        for (int b = 0; b < kMatDim; ++b) {
+            uint32_t w = 0;
+            for (int a = 0; ok && a < 4; ++a) {
+                if (a >= schemes[s].alphabet || b >= schemes[s].alphabet) continue;
+                const int v = schemes[s].matrix[a * schemes[s].alphabet + b] + schemes[s].gap_open;
+                if (v < 0 || v > 255) ok = false;
+                w |= (uint32_t)(v & 0xFF) << (8 * a);
+            }
+            cw[b] = w;
+        }
+        C.col_ok[s] = ok ? 1 : 0;
     }
     // the packed path holds every value of a pair when its score bound
     // min(n, m) * max_score is at most kI16Limit
@@ -582,6 +626,8 @@ static int align_spans(sw_handle* h, const uint8_t* queries, const int64_t* q_be
         K.alphabet[s] = v ? schemes[s].alphabet : 1;
         K.gap_open[s] = v ? schemes[s].gap_open : 1;
         K.gap_extend[s] = v ? schemes[s].gap_extend : 0;
+        K.col_ok[s] = C.col_ok[s] && h->opt_colpath;
+        C.col_ok[s] = K.col_ok[s];
     }
 
     const bool timing = h->opt_timing != 0;
@@ -595,6 +641,7 @@ static int align_spans(sw_handle* h, const uint8_t* queries, const int64_t* q_be
     memcpy(key.gap_open, K.gap_open, sizeof(key.gap_open));
     memcpy(key.gap_extend, K.gap_extend, sizeof(key.gap_extend));
     memcpy(key.max_score, C.max_score, sizeof(key.max_score));
+    memcpy(key.col_ok, C.col_ok, sizeof(key.col_ok));
     key.n_schemes = n_schemes; key.validate = (int32_t)h->opt_validate; key.precision = (int32_t)h->opt_precision;
 
     if (use_graph && h->have_graph && memcmp(&key, &h->gkey, sizeof(key)) == 0) {
@@ -624,7 +671,7 @@ static int align_spans(sw_handle* h, const uint8_t* queries, const int64_t* q_be
         }
         auto enqueue_all = [&](hipStream_t es) -> int {
             if (timing && hipEventRecord(h->ev[0], es) != hipSuccess) return fail(h, SW_EDEVICE, "event");
-            if (hipMemcpyAsync(h->d_mats, h->h_mats, SW_MAX_SCHEMES * kMatBytes, hipMemcpyHostToDevice, es) !=
+            if (hipMemcpyAsync(h->d_mats, h->h_mats, kSchemeBytes, hipMemcpyHostToDevice, es) !=
                 hipSuccess)
                 return fail(h, SW_EDEVICE, "matrix upload failed");
             if (launch_reset(h->d_small, kSmallInts, es) != hipSuccess) return fail(h, SW_EDEVICE, "reset");
@@ -680,17 +727,22 @@ static int align_spans(sw_handle* h, const uint8_t* queries, const int64_t* q_be
     h->last_rev = (int64_t)cnt[kCtrRevCells];
     h->last_i32 = (int64_t)cnt[kCtrI32Pairs];
     for (int pass = 0; pass < 2; ++pass)
-        for (int b = 0; b < (int)h->bins.size(); ++b) {
-            sw_bin_stat st;
-            memset(&st, 0, sizeof(st));
-            st.pass = pass;
-            st.precision = h->bins[b].prec;
-            st.lanes = h->bins[b].W;
-            st.rows = h->bins[b].R;
-            st.cells = (int64_t)cnt[kCtrBinCells + pass * kMaxBins + b];
-            st.pairs = (int64_t)cnt[kCtrBinPairs + pass * kMaxBins + b];
-            h->bin_stats.push_back(st);
-        }
+        for (int b = 0; b < (int)h->bins.size(); ++b)
+            for (int v = h->bins[b].col ? 1 : 0; v >= 0; --v) {
+                sw_bin_stat st;
+                memset(&st, 0, sizeof(st));
+                st.pass = pass;
+                st.precision = h->bins[b].prec;
+                st.lanes = h->bins[b].W;
+                st.rows = h->bins[b].R;
+                st.column = v;
+                const int i = pass * kMaxBins + b;
+                const int64_t col_cells = (int64_t)cnt[kCtrBinColCells + i];
+                const int64_t col_pairs = (int64_t)cnt[kCtrBinColPairs + i];
+                st.cells = v ? col_cells : (int64_t)cnt[kCtrBinCells + i] - col_cells;
+                st.pairs = v ? col_pairs : (int64_t)cnt[kCtrBinPairs + i] - col_pairs;
+                h->bin_stats.push_back(st);
+            }
     if (timing) {
         float a = 0, b = 0;
         HIP_TRY(h, hipEventElapsedTime(&a, h->ev[0], h->ev[1]));
@@ -699,15 +751,14 @@ static int align_spans(sw_handle* h, const uint8_t* queries, const int64_t* q_be
         HIP_TRY(h, hipEventElapsedTime(&h->t_rev, h->ev[3], h->ev[4]));
         h->t_plan = a + b;
         if (h->opt_timing == 2)
-            for (int pass = 0; pass < 2; ++pass)
-                for (int b = 0; b < (int)h->bins.size(); ++b) {
-                    sw_bin_stat& st = h->bin_stats[pass * h->bins.size() + b];
-                    // plain mode launches nothing for an empty bin, and no
-                    // mode launches a bin that no route points at
-                    if ((h->opt_mode == 0 && st.pairs == 0) || !h->bin_used[b]) continue;
-                    HIP_TRY(h, hipEventElapsedTime(&st.ms, h->bin_ev[(pass * kMaxBins + b) * 2],
-                                                   h->bin_ev[(pass * kMaxBins + b) * 2 + 1]));
-                }
+            for (sw_bin_stat& st : h->bin_stats) {
+                // only launched kernels have events (plain mode skips empty
+                // item ranges; no mode launches a bin no route points at)
+                const int b = find_bin(h, st.precision, st.lanes, st.rows);
+                const int i = bin_ev_index(st.pass, b, st.column, 0);
+                if (!h->bin_launched[i / 2]) continue;
+                HIP_TRY(h, hipEventElapsedTime(&st.ms, h->bin_ev[i], h->bin_ev[i + 1]));
+            }
     }
     if (flags[kFlagBadOffsets]) return fail(h, SW_EINVAL, "offsets decrease");
     if (flags[kFlagBadScheme]) return fail(h, SW_EINVAL, "scheme id out of range");

@@ -68,9 +68,10 @@
 
 namespace sw {
 
-// LDS reference buffer of one wavefront, sized for the widest layout
-// (four 16-lane groups with two packed pairs each).
-constexpr int kWaveBuf = 4 * 2 * RefStager<16>::kBuf;
+// LDS reference buffer of one wavefront (in 16-bit entries), sized for the
+// widest layout (four 16-lane groups with two packed pairs each) of 32-bit
+// column words.
+constexpr int kWaveBuf = 2 * 4 * 2 * RefStager<16>::kBuf;
 // One sweep (forward, or reverse when REV) of the wave item
 // order[first .. first+count), one pair per W-lane group, int32 arithmetic.
 template <int W, int R, bool REV>
@@ -402,6 +403,206 @@ __device__ __forceinline__ void sweep_i16(const KParams& P, const SchemeLds& S, 
 
     // per pair: best of this lane in row-major order, then of the group
     // (scores unbiased; a best of 0 leaves the coordinates at -1)
+    int lb[2] = {0, 0}, li[2] = {-1, -1}, lj[2] = {-1, -1};
+#pragma unroll
+    for (int p = 0; p < RP; ++p) {
+        const uint32_t ks[2] = {kA[p], kB[p]};
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int h = (int)(ks[q] >> 16) - (int)K;
+            const int row = l * R + 2 * p + ((ks[q] & 0x8000u) ? 0 : 1);
+            if (h > lb[q]) { lb[q] = h; li[q] = row; lj[q] = kColMax - (int)(ks[q] & 0x7FFFu); }
+        }
+    }
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+        for (int off = 1; off < W; off <<= 1) {
+            const int ob = __shfl_xor(lb[p], off);
+            const int oi = __shfl_xor(li[p], off);
+            const int oj = __shfl_xor(lj[p], off);
+            if (ob > lb[p] || (ob == lb[p] && oi < li[p])) { lb[p] = ob; li[p] = oi; lj[p] = oj; }
+        }
+    }
+    if (l == 0) {
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+            const int pair = p == 0 ? pairA : pairB;
+            const PairJob& J = p == 0 ? JA : JB;
+            if (pair < 0) continue;
+            if (!reverse) {
+                sw_result res;
+                if (lb[p] > 0) { res.score = lb[p]; res.q_start = -1; res.q_end = li[p]; res.r_start = -1; res.r_end = lj[p]; }
+                else { res.score = 0; res.q_start = res.q_end = res.r_start = res.r_end = -1; }
+                P.out[pair] = res;
+            } else if (J.fwd_score > 0) {
+                if (lb[p] != J.fwd_score) {
+                    atomicOr(&P.flags[kFlagReverseMismatch], 1);
+                } else {
+                    P.out[pair].q_start = J.fwd_qe - li[p];
+                    P.out[pair].r_start = J.fwd_re - lj[p];
+                }
+            }
+        }
+    }
+}
+
+// Small-alphabet ("column word") variant of sweep_i16, for wave items whose
+// pairs all use schemes with at most four residues whose scores plus the gap
+// open cost fit a byte.  The staged reference holds, per column b, one
+// 32-bit word with bytes M[a][b] + o for a = 0..3, so a row's score is one
+// v_perm_b32 of the two pairs' column words with a per-row selector (the
+// query residues), instead of two address computations and two LDS reads.
+// The selector takes a zero byte for rows past the query end, and padding
+// columns hold word 0: both score -o <= -1, as the padding code does.
+//
+// The score arrives biased by +o, so each row keeps Hm = H - o (biased by K;
+// exact because o <= K) instead of H:  H(i-1,j-1) + M = Hm(i-1,j-1) + (M + o).
+// Hm is what E and F need anyway, and what the lane exchange carries, so
+// the row update is  F = max3(F - e, Hm_up, K);  h = max3(Hm_diag + s', E, F);
+// Hm = h - o;  E = max3(E - e, Hm, K);  keys from h.  The top boundary is
+// Hm = K - o, F = K.
+template <int W, int R, bool REV>
+__device__ __forceinline__ void sweep_i16_col(const KParams& P, const SchemeLds& S, uint16_t* wbuf,
+                                              int first, int count, int lane) {
+    using Stager = RefStager<W>;
+    constexpr int reverse = REV ? 1 : 0;
+    constexpr int RP = (R + 1) / 2;
+    constexpr uint32_t K = kI16Bias;
+    constexpr uint32_t K2 = K | (K << 16);
+    const int g = lane / W;
+    const int l = lane % W;
+
+    const int slot = g * 2;
+    const int pairA = slot < count ? P.order[first + slot] : -1;
+    const int pairB = slot + 1 < count ? P.order[first + slot + 1] : -1;
+    const PairJob JA = load_job(P, pairA, reverse);
+    const PairJob JB = load_job(P, pairB, reverse);
+
+    int mmax = imax(JA.m, JB.m);
+    for (int off = 32; off > 0; off >>= 1) mmax = imax(mmax, __shfl_xor(mmax, off));
+    const int steps = __builtin_amdgcn_readfirstlane(mmax > 0 ? mmax + W - 1 : 0);
+
+    // 32-bit column words: the wave buffer holds twice as many bytes
+    uint32_t* bufA = reinterpret_cast<uint32_t*>(wbuf) + (g * 2) * Stager::kBuf;
+    uint32_t* bufB = bufA + Stager::kBuf;
+    Stager stA, stB;
+    stA.load(P.refs, JA, P.order, 0, l);
+    stB.load(P.refs, JB, P.order, 0, l);
+
+    // per-row selectors: byte 0 picks pair A's score from its column word
+    // (bytes 0..3 of the perm input), byte 2 pair B's (bytes 4..7); bytes 1
+    // and 3 are zero (selector 0x0C), as is a row past the query end
+    uint32_t sel[R];
+    {
+        int rawA[R], rawB[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int i = l * R + r;
+            const int iA = i < JA.n ? i : (JA.n > 0 ? JA.n - 1 : 0);
+            const int iB = i < JB.n ? i : (JB.n > 0 ? JB.n - 1 : 0);
+            const uint8_t* pA = JA.n > 0 ? P.queries + JA.qbase + (int64_t)JA.dir * iA
+                                         : reinterpret_cast<const uint8_t*>(P.order);
+            const uint8_t* pB = JB.n > 0 ? P.queries + JB.qbase + (int64_t)JB.dir * iB
+                                         : reinterpret_cast<const uint8_t*>(P.order);
+            rawA[r] = *pA;
+            rawB[r] = *pB;
+        }
+        const int AA = S.alphabet[JA.sid], AB = S.alphabet[JB.sid];
+        bool bad = false;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int i = l * R + r;
+            const bool inA = i < JA.n, inB = i < JB.n;
+            bad |= (inA && rawA[r] >= AA) || (inB && rawB[r] >= AB);
+            const uint32_t a = (inA && rawA[r] < AA) ? (uint32_t)rawA[r] : 0x0Cu;
+            const uint32_t b = (inB && rawB[r] < AB) ? (uint32_t)(4 + rawB[r]) : 0x0Cu;
+            sel[r] = a | 0x0C00u | (b << 16) | 0x0C000000u;
+        }
+        stA.store_col(bufA, JA, AA, S.colw[JA.sid], 0, l, bad);
+        stB.store_col(bufB, JB, AB, S.colw[JB.sid], 0, l, bad);
+        if (bad && P.validate) atomicOr(&P.flags[kFlagBadResidue], 1);
+    }
+    const int AA = S.alphabet[JA.sid], AB = S.alphabet[JB.sid];
+    const uint32_t goA = (uint32_t)S.gap_open[JA.sid], goB = (uint32_t)S.gap_open[JB.sid];
+    const u16x2 go2 = pk(goA | (goB << 16));
+    const u16x2 ge2 = pk((uint32_t)S.gap_extend[JA.sid] | ((uint32_t)S.gap_extend[JB.sid] << 16));
+    const u16x2 zero = pk(K2);
+    const uint32_t hm_top = (K - goA) | ((K - goB) << 16);   // Hm of the zero boundary
+    wave_lds_sync();
+
+    // Hm[r]: H - o of row r at the last column swept; E[r]: E of row r at the
+    // next column; kA/kB: keys of row pairs (from H itself)
+    u16x2 Hm[R], E[R];
+    uint32_t kA[RP], kB[RP];
+#pragma unroll
+    for (int r = 0; r < R; ++r) { Hm[r] = pk(hm_top); E[r] = zero; }
+#pragma unroll
+    for (int p = 0; p < RP; ++p) { kA[p] = 0u; kB[p] = 0u; }
+    uint32_t Hlast = hm_top, Flast = K2, Hup_prev = hm_top;
+    const uint32_t* rblA = bufA + W - l;
+    const uint32_t* rblB = bufB + W - l;
+
+    uint32_t cA = rblA[0], cB = rblB[0];            // column words of this step
+    uint32_t cA_next = rblA[1], cB_next = rblB[1];  // and of the next
+    bool bad = false;
+    uint32_t jc = (uint32_t)(kColMax + l);
+    for (int t0 = 0; t0 < steps; t0 += kChunk) {
+        const bool more = t0 + kChunk < steps;
+        if (more) {
+            stA.load(P.refs, JA, P.order, t0 + kChunk, l);
+            stB.load(P.refs, JB, P.order, t0 + kChunk, l);
+        }
+        const int tn = __builtin_amdgcn_readfirstlane(steps - t0 < kChunk ? steps - t0 : kChunk);
+        for (int tt = 0; tt < tn; ++tt) {
+            const uint32_t cA2 = rblA[tt + 2];
+            const uint32_t cB2 = rblB[tt + 2];
+            const u16x2 Hmu0 = pk((uint32_t)shift_in_group<W>((int)Hlast, (int)hm_top));
+            const u16x2 Fup = pk((uint32_t)shift_in_group<W>((int)Flast, (int)K2));
+            u16x2 diag = pk(Hup_prev);
+            Hup_prev = u32(Hmu0);
+            u16x2 Hmu = Hmu0;
+            u16x2 F = Fup;
+            const uint32_t jc1 = jc | 0x8000u;
+            uint32_t keyA0 = 0, keyB0 = 0;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                F = pk_max3(pk_sat_sub(F, ge2), Hmu, zero);
+                const u16x2 s = pk(__builtin_amdgcn_perm(cB, cA, sel[r]));
+                const u16x2 h = pk_max3(diag + s, E[r], F);
+                diag = Hm[r];
+                Hmu = h - go2;
+                Hm[r] = Hmu;
+                E[r] = pk_max3(pk_sat_sub(E[r], ge2), Hmu, zero);
+                const uint32_t hv = u32(h);
+                if ((r & 1) == 0) {
+                    keyA0 = (hv << 16) | jc1;
+                    keyB0 = (hv & 0xFFFF0000u) | jc1;
+                    if (r == R - 1) {
+                        kA[r / 2] = kA[r / 2] > keyA0 ? kA[r / 2] : keyA0;
+                        kB[r / 2] = kB[r / 2] > keyB0 ? kB[r / 2] : keyB0;
+                    }
+                } else {
+                    kA[r / 2] = umax3(kA[r / 2], keyA0, (hv << 16) | jc);
+                    kB[r / 2] = umax3(kB[r / 2], keyB0, (hv & 0xFFFF0000u) | jc);
+                }
+            }
+            Hlast = u32(Hm[R - 1]);
+            Flast = u32(F);
+            cA = cA_next; cB = cB_next;
+            cA_next = cA2; cB_next = cB2;
+            --jc;
+        }
+        if (more) {
+            wave_lds_sync();
+            stA.store_col(bufA, JA, AA, S.colw[JA.sid], t0 + kChunk, l, bad);
+            stB.store_col(bufB, JB, AB, S.colw[JB.sid], t0 + kChunk, l, bad);
+            wave_lds_sync();
+            cA = rblA[0]; cB = rblB[0];
+            cA_next = rblA[1]; cB_next = rblB[1];
+        }
+    }
+    if (bad && P.validate) atomicOr(&P.flags[kFlagBadResidue], 1);
+
     int lb[2] = {0, 0}, li[2] = {-1, -1}, lj[2] = {-1, -1};
 #pragma unroll
     for (int p = 0; p < RP; ++p) {

@@ -107,3 +107,16 @@ def test_wide_group_variants():
     # no cooperative shapes compiled: nothing to vary
     only = [s for s in SHAPES16 if s[0] != 256]
     assert list(T.candidate_tables(q, r, {s: 1.0 for s in only}, only)) == ["model"]
+
+
+def test_dominant_scheme_and_builtin_candidate():
+    b = W.make_workload("mixed", n_pairs=3000, seed=11)
+    assert T.dominant_scheme(b).name == "dna"                 # 80% of the pairs
+    p = W.make_workload("protein", n_pairs=200, seed=12)
+    assert T.dominant_scheme(p).name == "protein"
+    rates = {s: 1.0 for s in SHAPES16}
+    q, r = b.q_len(), b.r_len()
+    builtin = [(256, 16, 16), (512, 32, 16), (2048, 256, 8)]
+    cands = T.candidate_tables(q, r, rates, SHAPES16, builtin=builtin)
+    assert cands["builtin"] == builtin
+    assert "builtin" not in T.candidate_tables(q, r, rates, SHAPES16, builtin=cands["model"])

@@ -27,6 +27,21 @@ __device__ __forceinline__ int shift_in_group(int x, int fill = 0) {
     }
 }
 
+// shift_in_group with a zero fill: bound_ctrl writes the zero, so no fill
+// register has to be set up.
+template <int W>
+__device__ __forceinline__ int shift_in_group_zero(int x) {
+    if constexpr (W == 16) {
+        return __builtin_amdgcn_update_dpp(0, x, 0x111, 0xF, 0xF, true);
+    } else if constexpr (W == 32) {
+        const int y = __builtin_amdgcn_update_dpp(0, x, 0x138, 0xF, 0xF, true);
+        return (__lane_id() & 31) ? y : 0;
+    } else {
+        static_assert(W == 64, "W must be 16, 32 or 64");
+        return __builtin_amdgcn_update_dpp(0, x, 0x138, 0xF, 0xF, true);
+    }
+}
+
 __device__ __forceinline__ int sat_sub(int x, int y) {
     // max(x - y, 0) for x >= 0, y >= 0
     return (int)__builtin_elementwise_sub_sat((unsigned)x, (unsigned)y);

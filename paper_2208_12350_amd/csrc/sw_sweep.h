@@ -351,7 +351,9 @@ __device__ __forceinline__ void sweep_i16(const KParams& P, const SchemeLds& S, 
             const int bbA2 = rblA[tt + 2];
             const int bbB2 = rblB[tt + 2];
             const u16x2 Hup = pk((uint32_t)shift_in_group<W>((int)Hlast, (int)K2));
-            const u16x2 Fup = pk((uint32_t)shift_in_group<W>((int)Flast, (int)K2));
+            // F above the group is 0 (K); a zero fill gives the same F below
+            // because of the max with K
+            const u16x2 Fup = pk((uint32_t)shift_in_group_zero<W>((int)Flast));
             u16x2 diag = pk(Hup_prev);
             Hup_prev = u32(Hup);
             u16x2 Hmu = pk_sat_sub(Hup, go2);
@@ -542,10 +544,51 @@ __device__ __forceinline__ void sweep_i16_col(const KParams& P, const SchemeLds&
     const uint32_t* rblA = bufA + W - l;
     const uint32_t* rblB = bufB + W - l;
 
-    uint32_t cA = rblA[0], cB = rblB[0];            // column words of this step
-    uint32_t cA_next = rblA[1], cB_next = rblB[1];  // and of the next
+    // Column words of even steps live in (a0, b0), of odd steps in (a1, b1);
+    // a step reloads its pair with the words two steps ahead as soon as its
+    // rows are done, so the steps are unrolled by two and no register
+    // rotates.
     bool bad = false;
     uint32_t jc = (uint32_t)(kColMax + l);
+    auto step = [&](uint32_t& ca, uint32_t& cb, int ahead) {
+        const u16x2 Hmu0 = pk((uint32_t)shift_in_group<W>((int)Hlast, (int)hm_top));
+        // F above the group is 0 (K); a zero fill gives the same F below
+        // because of the max with K
+        const u16x2 Fup = pk((uint32_t)shift_in_group_zero<W>((int)Flast));
+        u16x2 diag = pk(Hup_prev);
+        Hup_prev = u32(Hmu0);
+        u16x2 Hmu = Hmu0;
+        u16x2 F = Fup;
+        const uint32_t jc1 = jc | 0x8000u;
+        uint32_t keyA0 = 0, keyB0 = 0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            F = pk_max3(pk_sat_sub(F, ge2), Hmu, zero);
+            const u16x2 sc = pk(__builtin_amdgcn_perm(cb, ca, sel[r]));
+            const u16x2 h = pk_max3(diag + sc, E[r], F);
+            diag = Hm[r];
+            Hmu = h - go2;
+            Hm[r] = Hmu;
+            E[r] = pk_max3(pk_sat_sub(E[r], ge2), Hmu, zero);
+            const uint32_t hv = u32(h);
+            if ((r & 1) == 0) {
+                keyA0 = (hv << 16) | jc1;
+                keyB0 = (hv & 0xFFFF0000u) | jc1;
+                if (r == R - 1) {
+                    kA[r / 2] = kA[r / 2] > keyA0 ? kA[r / 2] : keyA0;
+                    kB[r / 2] = kB[r / 2] > keyB0 ? kB[r / 2] : keyB0;
+                }
+            } else {
+                kA[r / 2] = umax3(kA[r / 2], keyA0, (hv << 16) | jc);
+                kB[r / 2] = umax3(kB[r / 2], keyB0, (hv & 0xFFFF0000u) | jc);
+            }
+        }
+        ca = rblA[ahead];
+        cb = rblB[ahead];
+        Hlast = u32(Hm[R - 1]);
+        Flast = u32(F);
+        --jc;
+    };
     for (int t0 = 0; t0 < steps; t0 += kChunk) {
         const bool more = t0 + kChunk < steps;
         if (more) {
@@ -553,52 +596,18 @@ __device__ __forceinline__ void sweep_i16_col(const KParams& P, const SchemeLds&
             stB.load(P.refs, JB, P.order, t0 + kChunk, l);
         }
         const int tn = __builtin_amdgcn_readfirstlane(steps - t0 < kChunk ? steps - t0 : kChunk);
-        for (int tt = 0; tt < tn; ++tt) {
-            const uint32_t cA2 = rblA[tt + 2];
-            const uint32_t cB2 = rblB[tt + 2];
-            const u16x2 Hmu0 = pk((uint32_t)shift_in_group<W>((int)Hlast, (int)hm_top));
-            const u16x2 Fup = pk((uint32_t)shift_in_group<W>((int)Flast, (int)K2));
-            u16x2 diag = pk(Hup_prev);
-            Hup_prev = u32(Hmu0);
-            u16x2 Hmu = Hmu0;
-            u16x2 F = Fup;
-            const uint32_t jc1 = jc | 0x8000u;
-            uint32_t keyA0 = 0, keyB0 = 0;
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                F = pk_max3(pk_sat_sub(F, ge2), Hmu, zero);
-                const u16x2 s = pk(__builtin_amdgcn_perm(cB, cA, sel[r]));
-                const u16x2 h = pk_max3(diag + s, E[r], F);
-                diag = Hm[r];
-                Hmu = h - go2;
-                Hm[r] = Hmu;
-                E[r] = pk_max3(pk_sat_sub(E[r], ge2), Hmu, zero);
-                const uint32_t hv = u32(h);
-                if ((r & 1) == 0) {
-                    keyA0 = (hv << 16) | jc1;
-                    keyB0 = (hv & 0xFFFF0000u) | jc1;
-                    if (r == R - 1) {
-                        kA[r / 2] = kA[r / 2] > keyA0 ? kA[r / 2] : keyA0;
-                        kB[r / 2] = kB[r / 2] > keyB0 ? kB[r / 2] : keyB0;
-                    }
-                } else {
-                    kA[r / 2] = umax3(kA[r / 2], keyA0, (hv << 16) | jc);
-                    kB[r / 2] = umax3(kB[r / 2], keyB0, (hv & 0xFFFF0000u) | jc);
-                }
-            }
-            Hlast = u32(Hm[R - 1]);
-            Flast = u32(F);
-            cA = cA_next; cB = cB_next;
-            cA_next = cA2; cB_next = cB2;
-            --jc;
+        uint32_t a0 = rblA[0], b0 = rblB[0], a1 = rblA[1], b1 = rblB[1];
+        int tt = 0;
+        for (; tt + 1 < tn; tt += 2) {
+            step(a0, b0, tt + 2);
+            step(a1, b1, tt + 3);
         }
+        if (tt < tn) step(a0, b0, tt + 2);
         if (more) {
             wave_lds_sync();
             stA.store_col(bufA, JA, AA, S.colw[JA.sid], t0 + kChunk, l, bad);
             stB.store_col(bufB, JB, AB, S.colw[JB.sid], t0 + kChunk, l, bad);
             wave_lds_sync();
-            cA = rblA[0]; cB = rblB[0];
-            cA_next = rblA[1]; cB_next = rblB[1];
         }
     }
     if (bad && P.validate) atomicOr(&P.flags[kFlagBadResidue], 1);

@@ -54,6 +54,15 @@ def _load():
         lib.oracle_align_pair.restype = ctypes.c_int
         lib.oracle_align_pair.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
                                           ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]
+        lib.oracle_cigar_pair.restype = ctypes.c_int
+        lib.oracle_cigar_pair.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64,
+                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                          ctypes.c_void_p]
+        lib.oracle_cigar_batch.restype = ctypes.c_int
+        lib.oracle_cigar_batch.argtypes = [ctypes.c_void_p] * 5 + [ctypes.c_int64, ctypes.c_void_p,
+                                                                    ctypes.c_int, ctypes.c_void_p,
+                                                                    ctypes.c_int64] + [ctypes.c_void_p] * 4 + [
+                                                                    ctypes.c_int]
         lib.oracle_score_matrix.restype = ctypes.c_int
         lib.oracle_score_matrix.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
                                             ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]
@@ -136,3 +145,68 @@ def score_matrix(a, b, scheme) -> np.ndarray:
         raise ValueError("oracle: allocation failure")
     del keep
     return H
+
+
+# SAM/BAM operation codes of the runs ((length << 4) | op)
+OP_I, OP_D, OP_EQ, OP_X = 1, 2, 7, 8
+_OP_CHAR = {OP_I: "I", OP_D: "D", OP_EQ: "=", OP_X: "X"}
+
+
+def cigar_string(runs) -> str:
+    """Runs ((length << 4) | op) -> text such as '4=1I5='."""
+    return "".join("%d%s" % (int(r) >> 4, _OP_CHAR[int(r) & 15]) for r in runs)
+
+
+def cigar_pair(a, b, scheme):
+    """Result and alignment path of one pair: ((score, q_start, q_end,
+    r_start, r_end), runs as a uint32 array)."""
+    lib = _load()
+    a = np.ascontiguousarray(a, dtype=np.uint8)
+    b = np.ascontiguousarray(b, dtype=np.uint8)
+    arr, keep = _schemes_array([scheme])
+    res = np.zeros(1, dtype=RESULT_DTYPE)
+    if lib.oracle_align_pair(_ptr(a), a.size, _ptr(b), b.size, ctypes.addressof(arr), res.ctypes.data) != 0:
+        raise ValueError("oracle: invalid input")
+    runs = np.zeros(max(1, a.size + b.size), dtype=np.uint32)
+    n = ctypes.c_int64(0)
+    if lib.oracle_cigar_pair(_ptr(a), a.size, _ptr(b), b.size, ctypes.addressof(arr), res.ctypes.data,
+                             runs.ctypes.data, runs.size, ctypes.byref(n)) != 0:
+        raise ValueError("oracle: traceback failed")
+    del keep
+    r = res[0]
+    return ((int(r["score"]), int(r["q_start"]), int(r["q_end"]), int(r["r_start"]), int(r["r_end"])),
+            runs[:n.value].copy())
+
+
+def cigar_batch(batch, index: Optional[Sequence[int]] = None, threads: Optional[int] = None,
+                results: Optional[np.ndarray] = None):
+    """Results and alignment paths of all pairs of a workloads.Batch (or of
+    the subset ``index``).  Returns (results, runs, run_off, n_runs): the
+    runs of the k-th pair are runs[run_off[k] : run_off[k] + n_runs[k]].
+    ``results`` (of the same pairs, in the same order) skips the alignment."""
+    lib = _load()
+    res = align_batch(batch, index=index, threads=threads) if results is None else \
+        np.ascontiguousarray(results, dtype=RESULT_DTYPE)
+    queries = np.ascontiguousarray(batch.queries, dtype=np.uint8)
+    refs = np.ascontiguousarray(batch.refs, dtype=np.uint8)
+    q_off = np.ascontiguousarray(batch.q_off, dtype=np.int64)
+    r_off = np.ascontiguousarray(batch.r_off, dtype=np.int64)
+    sid = np.ascontiguousarray(batch.scheme_id, dtype=np.uint8)
+    idx = None if index is None else np.ascontiguousarray(np.asarray(index, dtype=np.int64))
+    pairs = np.arange(batch.n_pairs) if idx is None else idx
+    cap = (q_off[pairs + 1] - q_off[pairs]) + (r_off[pairs + 1] - r_off[pairs])
+    run_off = np.zeros(pairs.size + 1, dtype=np.int64)
+    np.cumsum(cap, out=run_off[1:])
+    runs = np.zeros(max(1, int(run_off[-1])), dtype=np.uint32)
+    n_runs = np.zeros(pairs.size, dtype=np.int64)
+    if pairs.size:
+        arr, keep = _schemes_array(batch.schemes)
+        rc = lib.oracle_cigar_batch(_ptr(queries), q_off.ctypes.data, _ptr(refs), r_off.ctypes.data,
+                                    sid.ctypes.data, batch.n_pairs, ctypes.addressof(arr), len(batch.schemes),
+                                    None if idx is None else idx.ctypes.data, 0 if idx is None else idx.size,
+                                    res.ctypes.data, run_off.ctypes.data, runs.ctypes.data, n_runs.ctypes.data,
+                                    int(threads or os.cpu_count() or 1))
+        del keep
+        if rc != 0:
+            raise ValueError("oracle: traceback failed")
+    return res, runs, run_off, n_runs

@@ -224,3 +224,194 @@ int oracle_score_matrix(const uint8_t* a, int64_t n, const uint8_t* b, int64_t m
     free(E); free(F);
     return 0;
 }
+
+/*
+ * Alignment path (the traceback of Fig. 2(c)), as run-length columns.
+ *
+ * Given the result of oracle_align_pair, the path is recovered inside the
+ * box a[q_start..q_end] x b[r_start..r_end]: the Gotoh matrices of the box
+ * alone are filled (same recurrences, local, H = 0 / E = F = -inf on the
+ * box's top row and left column) and followed back from the box's last cell,
+ * whose H equals S, until H reaches 0.  Every S-scoring alignment that ends at
+ * (q_end, r_end) and lies in the box starts at the box corner (a later start
+ * would contradict the latest-start rule), so the walk must stop exactly
+ * there; anything else is reported as an error.
+ *
+ * Among equally scoring paths the walk takes, at each cell, the first valid
+ * choice of:
+ *   in H:  the diagonal (H == H[i-1][j-1] + M), then F (a query residue over
+ *          a gap), then E (a reference residue over a gap);
+ *   in F:  opening the gap here (F == H[i-1][j] - o), then extending it;
+ *   in E:  opening the gap here (E == H[i][j-1] - o), then extending it.
+ * Read from the end, this is the smallest sequence of choices in that order.
+ *
+ * Columns are emitted as runs (length << 4) | op with the SAM/BAM operation
+ * codes: 7 '=' (equal residue codes), 8 'X' (other substitution), 1 'I'
+ * (query residue over a gap), 2 'D' (reference residue over a gap), from the
+ * first column of the alignment to the last.  S == 0 gives no runs.
+ * Returns 0, or -1 on inconsistent input, allocation failure or when more
+ * than `cap` runs would be needed.
+ */
+enum { ORACLE_OP_I = 1, ORACLE_OP_D = 2, ORACLE_OP_EQ = 7, ORACLE_OP_X = 8 };
+
+int oracle_cigar_pair(const uint8_t* a, int64_t n, const uint8_t* b, int64_t m,
+                      const oracle_scheme* sc, const oracle_result* res,
+                      uint32_t* runs, int64_t cap, int64_t* n_runs)
+{
+    *n_runs = 0;
+    if (res->score == 0) return 0;
+    const int64_t qs = res->q_start, qe = res->q_end, rs = res->r_start, re = res->r_end;
+    if (res->score < 0 || qs < 0 || qs > qe || qe >= n || rs < 0 || rs > re || re >= m) return -1;
+    const int64_t o = sc->gap_open, e = sc->gap_extend;
+    const int A = sc->alphabet;
+    const int64_t nb = qe - qs + 1, mb = re - rs + 1, W = mb + 1;
+    const uint8_t* x = a + qs;
+    const uint8_t* y = b + rs;
+    for (int64_t i = 0; i < nb; ++i) if (x[i] >= A) return -1;
+    for (int64_t j = 0; j < mb; ++j) if (y[j] >= A) return -1;
+    const size_t cells = (size_t)(nb + 1) * (size_t)(mb + 1);
+    int64_t* H = (int64_t*)malloc(sizeof(int64_t) * cells);
+    int64_t* E = (int64_t*)malloc(sizeof(int64_t) * cells);
+    int64_t* F = (int64_t*)malloc(sizeof(int64_t) * cells);
+    char* ops = (char*)malloc((size_t)(nb + mb));
+    int rc = -1;
+    if (!H || !E || !F || !ops) goto done;
+    for (int64_t i = 0; i <= nb; ++i)
+        for (int64_t j = 0; j <= mb; ++j) {
+            if (i == 0 || j == 0) {
+                H[i * W + j] = 0; E[i * W + j] = ORACLE_NEG_INF; F[i * W + j] = ORACLE_NEG_INF;
+                continue;
+            }
+            E[i * W + j] = max2(E[i * W + j - 1] - e, H[i * W + j - 1] - o);
+            F[i * W + j] = max2(F[(i - 1) * W + j] - e, H[(i - 1) * W + j] - o);
+            int64_t h = H[(i - 1) * W + j - 1] + sc->matrix[x[i - 1] * A + y[j - 1]];
+            h = max2(h, E[i * W + j]);
+            h = max2(h, F[i * W + j]);
+            H[i * W + j] = max2(h, 0);
+        }
+    if (H[nb * W + mb] != res->score) goto done;
+    {
+        int64_t i = nb, j = mb, k = 0;
+        char state = 'H';
+        for (;;) {
+            if (state == 'H') {
+                const int64_t h = H[i * W + j];
+                if (h == 0) break;
+                if (h == H[(i - 1) * W + j - 1] + sc->matrix[x[i - 1] * A + y[j - 1]]) {
+                    ops[k++] = x[i - 1] == y[j - 1] ? '=' : 'X';
+                    --i; --j;
+                } else if (h == F[i * W + j]) {
+                    state = 'F';
+                } else if (h == E[i * W + j]) {
+                    state = 'E';
+                } else {
+                    goto done;
+                }
+            } else if (state == 'F') {
+                ops[k++] = 'I';
+                if (i < 2 && F[i * W + j] != H[(i - 1) * W + j] - o) goto done;
+                state = F[i * W + j] == H[(i - 1) * W + j] - o ? 'H' : 'F';
+                if (state == 'F' && F[i * W + j] != F[(i - 1) * W + j] - e) goto done;
+                --i;
+            } else {
+                ops[k++] = 'D';
+                if (j < 2 && E[i * W + j] != H[i * W + j - 1] - o) goto done;
+                state = E[i * W + j] == H[i * W + j - 1] - o ? 'H' : 'E';
+                if (state == 'E' && E[i * W + j] != E[i * W + j - 1] - e) goto done;
+                --j;
+            }
+            if (k > nb + mb) goto done;
+        }
+        if (i != 0 || j != 0) goto done;
+        /* ops[] runs from the last column back to the first */
+        int64_t r = 0;
+        for (int64_t p = k - 1; p >= 0;) {
+            int64_t q = p;
+            while (q > 0 && ops[q - 1] == ops[p]) --q;
+            const uint32_t len = (uint32_t)(p - q + 1);
+            const uint32_t code = ops[p] == '=' ? ORACLE_OP_EQ : ops[p] == 'X' ? ORACLE_OP_X
+                                : ops[p] == 'I' ? ORACLE_OP_I : ORACLE_OP_D;
+            if (r >= cap) goto done;
+            runs[r++] = (len << 4) | code;
+            p = q - 1;
+        }
+        *n_runs = r;
+        rc = 0;
+    }
+done:
+    free(H); free(E); free(F); free(ops);
+    return rc;
+}
+
+typedef struct {
+    const uint8_t* queries; const int64_t* q_off;
+    const uint8_t* refs; const int64_t* r_off;
+    const uint8_t* scheme_id; int64_t n_pairs;
+    const oracle_scheme* schemes; int n_schemes;
+    const int64_t* index; int64_t n_index;
+    const oracle_result* res;     /* res[k]: result of the k-th pair run */
+    const int64_t* run_off;       /* runs of the k-th pair go to runs[run_off[k] .. run_off[k+1]) */
+    uint32_t* runs;
+    int64_t* n_runs;
+    int64_t next;
+    int error;
+    pthread_mutex_t lock;
+} oracle_cigar_job;
+
+static void* oracle_cigar_worker(void* arg)
+{
+    oracle_cigar_job* J = (oracle_cigar_job*)arg;
+    const int64_t total = J->index ? J->n_index : J->n_pairs;
+    for (;;) {
+        int64_t k;
+        pthread_mutex_lock(&J->lock);
+        k = J->next++;
+        pthread_mutex_unlock(&J->lock);
+        if (k >= total) break;
+        int64_t i = J->index ? J->index[k] : k;
+        int sid = J->scheme_id ? J->scheme_id[i] : 0;
+        if (i < 0 || i >= J->n_pairs || sid >= J->n_schemes) { J->error = 1; continue; }
+        const int64_t qa = J->q_off[i], qb = J->q_off[i + 1];
+        const int64_t ra = J->r_off[i], rb = J->r_off[i + 1];
+        if (oracle_cigar_pair(J->queries + qa, qb - qa, J->refs + ra, rb - ra, &J->schemes[sid],
+                              &J->res[k], J->runs + J->run_off[k], J->run_off[k + 1] - J->run_off[k],
+                              &J->n_runs[k]) != 0)
+            J->error = 1;
+    }
+    return NULL;
+}
+
+/*
+ * Alignment paths of a batch (or of the subset `index`, as in
+ * oracle_align_batch), given the results `res` of those pairs in the same
+ * order.  Returns 0, or -1 if any pair failed.
+ */
+int oracle_cigar_batch(const uint8_t* queries, const int64_t* q_off,
+                       const uint8_t* refs, const int64_t* r_off,
+                       const uint8_t* scheme_id, int64_t n_pairs,
+                       const oracle_scheme* schemes, int n_schemes,
+                       const int64_t* index, int64_t n_index,
+                       const oracle_result* res, const int64_t* run_off,
+                       uint32_t* runs, int64_t* n_runs, int n_threads)
+{
+    oracle_cigar_job J;
+    J.queries = queries; J.q_off = q_off; J.refs = refs; J.r_off = r_off;
+    J.scheme_id = scheme_id; J.n_pairs = n_pairs;
+    J.schemes = schemes; J.n_schemes = n_schemes;
+    J.index = index; J.n_index = n_index;
+    J.res = res; J.run_off = run_off; J.runs = runs; J.n_runs = n_runs;
+    J.next = 0; J.error = 0;
+    pthread_mutex_init(&J.lock, NULL);
+    if (n_threads < 1) n_threads = 1;
+    if (n_threads > 256) n_threads = 256;
+    pthread_t th[256];
+    int started = 0;
+    for (int t = 0; t < n_threads; ++t) {
+        if (pthread_create(&th[t], NULL, oracle_cigar_worker, &J) != 0) break;
+        ++started;
+    }
+    if (started == 0) oracle_cigar_worker(&J);
+    for (int t = 0; t < started; ++t) pthread_join(th[t], NULL);
+    pthread_mutex_destroy(&J.lock);
+    return J.error ? -1 : 0;
+}

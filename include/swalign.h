@@ -130,6 +130,8 @@ const char* sw_last_error(sw_handle* h);
  *   "streams"   1..4: persistent mode spreads the bins' kernels over this
  *               many streams forked from (and joined back into) the
  *               caller's stream (default 4)
+ *   "cigar_workspace"  device bytes for the path records of sw_align_cigar
+ *               (default 8 GiB, at least about 123 MB)
  * Returns SW_OK or SW_EINVAL for an unknown key / bad value. */
 int sw_set_option(sw_handle* h, const char* key, int64_t value);
 /* Read an option, or the read-only "captures" (graphs captured so far) and
@@ -178,6 +180,48 @@ int sw_last_timing(sw_handle* h, float* plan_ms, float* forward_ms, float* rever
  * any pointer may be NULL. */
 int sw_last_host_timing(sw_handle* h, double* enqueue_ms, double* wait_ms);
 
+/* ---- alignment paths (the traceback of Fig. 2(c)) ----------------------
+ *
+ * The path of a pair is recovered inside its result box a[q_start..q_end] x
+ * b[r_start..r_end]: every alignment of score S that ends at (q_end, r_end)
+ * within the box starts at (q_start, r_start), so it is a traceback of the
+ * box's own Gotoh matrices from the box's last cell.  Among equally scoring
+ * paths the traceback takes, at each cell and read from the end backwards,
+ * the first valid choice of: a substitution column, then a query residue
+ * over a gap, then a reference residue over a gap; inside a gap, opening it
+ * here before extending it further back.
+ *
+ * A path is written as runs, uint32 (length << 4) | op, from the first
+ * column of the alignment to the last, with the SAM/BAM operation codes: */
+#define SW_OP_I   1   /* query residue over a gap (insertion to the reference) */
+#define SW_OP_D   2   /* reference residue over a gap (deletion from the reference) */
+#define SW_OP_EQ  7   /* substitution column, equal residue codes */
+#define SW_OP_X   8   /* substitution column, different residue codes */
+
+/* Align every pair of `batch` as sw_align_batch does (out[i] as there) and
+ * write its path: pair i's runs go to cigar[cigar_off[i] ..
+ * cigar_off[i+1]) and their number to cigar_len[i] (0 when the score is 0).
+ * cigar_off (int64[n_pairs+1], non-decreasing), cigar (uint32) and
+ * cigar_len (int32[n_pairs]) are DEVICE pointers owned by the caller; a room
+ * of q_len + r_len runs per pair always suffices.  The paths are found by a
+ * sweep of each box that stores 4 bits per cell in a device workspace (option
+ * "cigar_workspace", default 8 GiB; batches whose boxes need more are done in
+ * chunks), then a walk back per pair.  Synchronises `stream`; not captured in
+ * a graph.  Errors: those of sw_align_batch; SW_EINVAL when a pair's room
+ * is too small (its cigar_len is -1, the other pairs' paths are written);
+ * SW_ENOMEM when the workspace cannot be allocated. */
+int sw_align_cigar(sw_handle* h, const sw_batch* batch, const sw_scheme* schemes, int n_schemes,
+                   sw_result* out, const int64_t* cigar_off, uint32_t* cigar, int32_t* cigar_len,
+                   void* stream);
+
+/* Statistics of the last sw_align_cigar call: cells of the path boxes (sum
+ * of (q_end-q_start+1)*(r_end-r_start+1)), bytes of path records, chunks,
+ * and with the "timing" option the device milliseconds of the box sweeps
+ * and of the walks (per box-sweep shape with "timing" = 2: the entries of
+ * sw_last_bin_stats with pass 2).  Any pointer may be NULL. */
+int sw_last_cigar_stats(sw_handle* h, int64_t* box_cells, int64_t* record_bytes, int32_t* chunks,
+                        float* sweep_ms, float* walk_ms);
+
 /* ---- routing: which sweep shape aligns which query length -------------
  *
  * A sweep shape is (lanes, rows): a group of `lanes` lanes (16, 32 or 64)
@@ -209,7 +253,7 @@ int sw_get_routing(sw_handle* h, int precision, int32_t* rows_max, int32_t* lane
  * kernel, so up to (pairs per item - 1) column-path pairs of a bin may be
  * counted against the column entry but swept by the table kernel. */
 typedef struct sw_bin_stat {
-    int32_t pass;        /* 0 forward, 1 reverse */
+    int32_t pass;        /* 0 forward, 1 reverse, 2 path boxes (sw_align_cigar) */
     int32_t precision;   /* 16 (two pairs packed per register) or 32 */
     int32_t lanes;       /* lanes that share one pair */
     int32_t rows;        /* query rows held by each lane */

@@ -34,7 +34,7 @@ _ERRNAMES = {SW_EINVAL: "SW_EINVAL", SW_ENOMEM: "SW_ENOMEM", SW_ETOOLONG: "SW_ET
 
 EXPORTED = ("sw_create", "sw_destroy", "sw_last_error", "sw_set_option", "sw_get_option",
             "sw_align_batch", "sw_align_spans", "sw_last_stats", "sw_last_timing", "sw_last_host_timing", "sw_last_bin_stats",
-            "sw_shapes", "sw_set_routing", "sw_get_routing",
+            "sw_shapes", "sw_set_routing", "sw_get_routing", "sw_align_cigar", "sw_last_cigar_stats",
             "sw_server_create", "sw_server_destroy", "sw_server_last_error", "sw_server_submit",
             "sw_server_poll", "sw_server_stats", "sw_server_timing")
 
@@ -111,6 +111,13 @@ def load_library(path: str = LIB_PATH):
     lib.sw_last_bin_stats.restype = ctypes.c_int
     lib.sw_last_bin_stats.argtypes = [ctypes.c_void_p, ctypes.POINTER(sw_bin_stat), ctypes.c_int,
                                       ctypes.POINTER(ctypes.c_int)]
+    lib.sw_align_cigar.restype = ctypes.c_int
+    lib.sw_align_cigar.argtypes = [ctypes.c_void_p, ctypes.POINTER(sw_batch), ctypes.POINTER(sw_scheme),
+                                   ctypes.c_int] + [ctypes.c_void_p] * 5
+    lib.sw_last_cigar_stats.restype = ctypes.c_int
+    lib.sw_last_cigar_stats.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64),
+                                        ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32),
+                                        ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)]
     lib.sw_server_create.restype = ctypes.c_void_p
     lib.sw_server_create.argtypes = [ctypes.c_int, ctypes.POINTER(sw_scheme), ctypes.c_int, ctypes.c_int64,
                                      ctypes.c_int, ctypes.c_int64, ctypes.c_char_p]
@@ -175,6 +182,23 @@ def sw_align_spans(h: int, queries, q_beg, q_end, refs, r_beg, r_end, scheme_id,
     """Raw call with device pointers; returns the status code."""
     return load_library().sw_align_spans(h, queries, q_beg, q_end, refs, r_beg, r_end, scheme_id, n_pairs,
                                          schemes, n_schemes, out_ptr, stream_ptr)
+
+
+def sw_align_cigar(h: int, batch: sw_batch, schemes, n_schemes: int, out_ptr, cigar_off_ptr, cigar_ptr,
+                   cigar_len_ptr, stream_ptr) -> int:
+    """Raw call with device pointers; returns the status code."""
+    return load_library().sw_align_cigar(h, ctypes.byref(batch), schemes, n_schemes, out_ptr, cigar_off_ptr,
+                                         cigar_ptr, cigar_len_ptr, stream_ptr)
+
+
+def sw_last_cigar_stats(h: int):
+    """(box_cells, record_bytes, chunks, sweep_ms, walk_ms) of the last
+    sw_align_cigar call."""
+    c, b, k = ctypes.c_int64(0), ctypes.c_int64(0), ctypes.c_int32(0)
+    s, w = ctypes.c_float(0), ctypes.c_float(0)
+    _check(h, load_library().sw_last_cigar_stats(h, ctypes.byref(c), ctypes.byref(b), ctypes.byref(k),
+                                                 ctypes.byref(s), ctypes.byref(w)))
+    return int(c.value), int(b.value), int(k.value), float(s.value), float(w.value)
 
 
 def sw_last_stats(h: int):
@@ -333,6 +357,42 @@ class Aligner:
         _check(self.h, rc)
         del keep
         return out
+
+    def align_cigar(self, dbatch: DeviceBatch, out=None, cigar_off=None, cigar=None, cigar_len=None, stream=None):
+        """Align a DeviceBatch and recover every pair's path.  Returns (out,
+        cigar_off, cigar, cigar_len) on the device: results as for align();
+        pair i's runs ((length << 4) | SAM op code) are
+        cigar[cigar_off[i] : cigar_off[i] + cigar_len[i]].  By default each
+        pair gets room for q_len + r_len runs, which always suffices."""
+        import torch
+        dev = dbatch.q_off.device
+        n = dbatch.n_pairs
+        if out is None:
+            out = torch.empty((n, 5), dtype=torch.int32, device=dev)
+        if cigar_off is None:
+            room = (dbatch.q_off[1:] - dbatch.q_off[:-1]) + (dbatch.r_off[1:] - dbatch.r_off[:-1])
+            cigar_off = torch.zeros(n + 1, dtype=torch.int64, device=dev)
+            if n:
+                torch.cumsum(room, 0, out=cigar_off[1:])
+        if cigar is None:
+            cigar = torch.empty(max(1, int(cigar_off[-1].item())), dtype=torch.int32, device=dev)
+        if cigar_len is None:
+            cigar_len = torch.empty(max(1, n), dtype=torch.int32, device=dev)
+        assert out.is_contiguous() and out.dtype == torch.int32 and out.shape == (n, 5)
+        assert cigar_off.is_contiguous() and cigar_off.dtype == torch.int64 and cigar_off.numel() == n + 1
+        assert cigar.is_contiguous() and cigar.dtype in (torch.int32, torch.uint32)
+        assert cigar_len.is_contiguous() and cigar_len.dtype == torch.int32 and cigar_len.numel() >= n
+        arr, keep = make_schemes(dbatch.schemes)
+        s = stream if stream is not None else torch.cuda.current_stream(dev)
+        rc = sw_align_cigar(self.h, dbatch.c_struct(), arr, len(dbatch.schemes),
+                            out.data_ptr() if n else None, cigar_off.data_ptr(), cigar.data_ptr(),
+                            cigar_len.data_ptr(), ctypes.c_void_p(s.cuda_stream))
+        _check(self.h, rc)
+        del keep
+        return out, cigar_off, cigar, cigar_len
+
+    def cigar_stats(self):
+        return sw_last_cigar_stats(self.h)
 
     def stats(self):
         return sw_last_stats(self.h)

@@ -87,11 +87,14 @@ enum : int {
     kCtrFwdCells = 0,
     kCtrRevCells = 1,
     kCtrI32Pairs = 2,
+    kCtrTraceCells = 3,                      // cells of the path boxes (alignment paths)
     kCtrBinCells = 4,                        // [2 * kMaxBins] cells per (pass, bin)
     kCtrBinPairs = kCtrBinCells + 2 * kMaxBins,   // [2 * kMaxBins] pairs per (pass, bin)
     kCtrBinColCells = kCtrBinPairs + 2 * kMaxBins,   // [2 * kMaxBins] cells of column-path pairs
     kCtrBinColPairs = kCtrBinColCells + 2 * kMaxBins,   // [2 * kMaxBins] column-path pairs
-    kNumCounters = kCtrBinColPairs + 2 * kMaxBins,
+    kCtrTraceBinCells = kCtrBinColPairs + 2 * kMaxBins,   // [kMaxBins] box cells per path-sweep bin
+    kCtrTraceBinPairs = kCtrTraceBinCells + kMaxBins,      // [kMaxBins] pairs per path-sweep bin
+    kNumCounters = kCtrTraceBinPairs + kMaxBins,
 };
 
 // Arguments shared by every sweep launch.
@@ -129,6 +132,7 @@ enum : int32_t {
     kFlagBadScheme = 3,
     kFlagTooLong = 4,
     kFlagInternal = 5,           // a planning or work-item invariant did not hold
+    kFlagPathRoom = 6,           // an alignment path needs more runs than its output room
     kNumFlags = 8,
 };
 
@@ -181,5 +185,45 @@ hipError_t launch_scatter(const int32_t* keys, const int32_t* n_dev, int64_t cap
                           int32_t* order, hipStream_t s);
 hipError_t launch_items(const int32_t* meta, const BinInfo* bins, int n_bins, const int32_t* n_dev,
                         int64_t cap, WorkItem* items, hipStream_t s);
+
+// ---- alignment paths (sw_trace.hip) ----------------------------------------
+// The path of a pair is recovered in its result box a[q_start..q_end] x
+// b[r_start..r_end]: a sweep of the box writes 4 bits per cell (the
+// traceback choices) into a device record, and a walk from the box's last
+// cell reads them back.  Records of a batch are laid out back to back in pair
+// order (rec_off, an exclusive scan of their sizes) and produced in chunks:
+// chunk c holds the pairs whose record starts in [c * chunk_bytes,
+// (c + 1) * chunk_bytes), at offset rec_off - c * chunk_bytes of the workspace.
+struct TraceArgs {
+    uint8_t* ws;                 // workspace of the current chunk
+    const int64_t* rec_off;      // [n_pairs + 1] record byte offsets (the last = total)
+    int64_t chunk_bytes;
+    int64_t ws_bytes;            // workspace capacity (>= chunk_bytes + the largest record)
+    int32_t chunk;
+    int32_t n_bins;
+    const int8_t* lut;           // [kLutRows] path-sweep bin of each 16-row bucket of box rows
+    const BinInfo* bins;         // path-sweep bins
+};
+
+// Path-sweep shapes (int32, one pair per W-lane group, R a multiple of 8).
+using TraceFn = void (*)(KParams, TraceArgs);
+const ShapeDesc* trace_shapes(int* n);
+TraceFn trace_kernel(int W, int R);
+// Record bytes of a box of m columns on shape (W, R): (m + W - 1) sweep
+// steps, each W lanes x R rows x 4 bits.
+__host__ __device__ inline int64_t trace_record_bytes(int W, int R, int64_t m) {
+    return (m + W - 1) * (int64_t)W * R / 2;
+}
+// The largest record any pair can need (64 lanes x 32 rows, the longest reference).
+constexpr int64_t kMaxRecordBytes = (int64_t)(SW_MAX_REF + 63) * 64 * 32 / 2;
+
+hipError_t launch_trace_sizes(const KParams& P, const TraceArgs& T, int64_t cap, int64_t* rec_off,
+                              int64_t* block_sums, unsigned long long* counters, hipStream_t s);
+hipError_t launch_trace_classify(const KParams& P, const TraceArgs& T, int64_t cap, int32_t* keys,
+                                 int32_t* hist, unsigned long long* counters, hipStream_t s);
+hipError_t launch_trace_walk(const KParams& P, const TraceArgs& T, int64_t cap, const int64_t* path_off,
+                             uint32_t* path, int32_t* path_len, hipStream_t s);
+// Blocks of the size scan for `cap` pairs (the length of block_sums minus one).
+int64_t trace_scan_blocks(int64_t cap);
 
 }  // namespace sw

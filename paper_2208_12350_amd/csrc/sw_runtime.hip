@@ -115,6 +115,24 @@ struct sw_handle {
     int64_t n_capture_refusals = 0;
 
     int64_t last_fwd = 0, last_rev = 0, last_i32 = 0;
+
+    // alignment paths (sw_align_cigar)
+    std::vector<BinInfo> tbins;          // path-sweep shapes
+    std::vector<int> tresident;          // workgroups the device holds at once, per path-sweep bin
+    BinInfo* d_tbins = nullptr;
+    int8_t* d_tlut = nullptr;            // [kLutRows] path-sweep bin per 16-row bucket of box rows
+    int64_t* d_rec_off = nullptr;        // [trace_cap + 1]
+    int64_t* d_bsum = nullptr;           // [scan blocks + 1]
+    int64_t trace_cap = 0;
+    uint8_t* d_ws = nullptr;             // path records of one chunk
+    int64_t ws_alloc = 0;
+    int64_t opt_path_ws = (int64_t)8 << 30;
+    int64_t* h_i64 = nullptr;            // pinned
+    hipEvent_t tev[4] = {nullptr, nullptr, nullptr, nullptr};
+    std::vector<hipEvent_t> tbin_ev;     // per path-sweep bin: start, end ("timing" = 2)
+    int64_t last_path_cells = 0, last_path_bytes = 0;
+    int32_t last_path_chunks = 0;
+    float t_path_sweep = 0.f, t_path_walk = 0.f;
 };
 
 static int fail(sw_handle* h, int code, const char* fmt, ...) {
@@ -371,6 +389,57 @@ static int enqueue_pass(sw_handle* h, KParams K, const ClassifyArgs& C, int64_t 
     return SW_OK;
 }
 
+// Path-sweep bins and their routing: each 16-row bucket of box rows goes to
+// the covering shape with the fewest lane-row slots for a box of twice as
+// many columns plus 64 (as the score routing's default).
+static bool init_paths(sw_handle* h) {
+    int n = 0;
+    const ShapeDesc* sh = trace_shapes(&n);
+    h->tbins.clear();
+    for (int k = 0; k < n; ++k) {
+        BinInfo b;
+        b.prec = 32;
+        b.W = (uint16_t)sh[k].W;
+        b.R = (uint8_t)sh[k].R;
+        b.ppw = (uint16_t)pairs_per_item(32, sh[k].W);
+        b.col = 0;
+        b.pad = 0;
+        h->tbins.push_back(b);
+    }
+    if (h->tbins.empty() || h->tbins.size() > (size_t)kMaxBins) return false;
+    std::vector<int8_t> lut(kLutRows, -1);
+    for (int k = 0; k < kLutRows; ++k) {
+        const int rows = 16 * (k + 1);
+        const double m = 2.0 * rows + 64.0;
+        int best = -1;
+        double best_cost = 0;
+        for (int b = 0; b < (int)h->tbins.size(); ++b) {
+            const BinInfo& e = h->tbins[b];
+            if (e.W * e.R < rows) continue;
+            const double cost = (double)e.W * e.R * (m + e.W - 1);
+            if (best < 0 || cost < best_cost) { best = b; best_cost = cost; }
+        }
+        if (best < 0) return false;
+        lut[k] = (int8_t)best;
+    }
+    h->tresident.assign(h->tbins.size(), 1);
+    for (size_t b = 0; b < h->tbins.size(); ++b) {
+        int per_cu = 0;
+        const TraceFn fn = trace_kernel(h->tbins[b].W, h->tbins[b].R);
+        if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)fn, kBlock, 0) != hipSuccess)
+            return false;
+        h->tresident[b] = std::max(1, per_cu) * std::max(1, h->n_cu);
+    }
+    bool ok = hipMalloc(&h->d_tbins, kMaxBins * sizeof(BinInfo)) == hipSuccess &&
+              hipMalloc(&h->d_tlut, kLutRows) == hipSuccess &&
+              hipHostMalloc(&h->h_i64, 16, hipHostMallocDefault) == hipSuccess &&
+              hipMemcpy(h->d_tbins, h->tbins.data(), h->tbins.size() * sizeof(BinInfo), hipMemcpyHostToDevice) ==
+                  hipSuccess &&
+              hipMemcpy(h->d_tlut, lut.data(), kLutRows, hipMemcpyHostToDevice) == hipSuccess;
+    for (int k = 0; ok && k < 4; ++k) ok = hipEventCreate(&h->tev[k]) == hipSuccess;
+    return ok;
+}
+
 extern "C" {
 
 sw_handle* sw_create(int device, const char* tuning) {
@@ -419,6 +488,7 @@ sw_handle* sw_create(int device, const char* tuning) {
                 h->resident_blocks[pass][v][b] = std::max(1, per_cu) * std::max(1, h->n_cu);
             }
         }
+    if (ok) ok = init_paths(h);
     if (!ok) { sw_destroy(h); return nullptr; }
     if (tuning) {
         std::string s(tuning);
@@ -454,6 +524,12 @@ void sw_destroy(sw_handle* h) {
     if (h->h_n) (void)hipHostFree(h->h_n);
     free_dev(h->d_hist); free_dev(h->d_meta); free_dev(h->d_keys); free_dev(h->d_order);
     free_dev(h->d_items);
+    free_dev(h->d_tbins); free_dev(h->d_tlut); free_dev(h->d_rec_off); free_dev(h->d_bsum); free_dev(h->d_ws);
+    if (h->h_i64) (void)hipHostFree(h->h_i64);
+    for (int k = 0; k < 4; ++k)
+        if (h->tev[k]) (void)hipEventDestroy(h->tev[k]);
+    for (hipEvent_t e : h->tbin_ev)
+        if (e) (void)hipEventDestroy(e);
     if (h->h_mats) (void)hipHostFree(h->h_mats);
     if (h->h_small) (void)hipHostFree(h->h_small);
     if (h->h_meta) (void)hipHostFree(h->h_meta);
@@ -502,6 +578,13 @@ int sw_set_option(sw_handle* h, const char* key, int64_t value) {
     } else if (k == "streams") {
         if (value < 1 || value > sw_handle::kForks) return fail(h, SW_EINVAL, "streams must be 1..%d", sw_handle::kForks);
         h->opt_streams = value;
+    } else if (k == "cigar_workspace") {
+        // device bytes for path records; a batch whose records need more is
+        // processed in chunks (each chunk needs room for the largest record)
+        if (value < 2 * kMaxRecordBytes)
+            return fail(h, SW_EINVAL, "cigar_workspace must be at least %lld bytes", (long long)(2 * kMaxRecordBytes));
+        h->opt_path_ws = value;
+        return SW_OK;
     } else if (k == "precision") {
         if (value != 0 && value != 32) return fail(h, SW_EINVAL, "precision must be 0 or 32");
         h->opt_precision = value;
@@ -523,6 +606,7 @@ int sw_get_option(sw_handle* h, const char* key, int64_t* value) {
     else if (k == "streams") *value = h->opt_streams;
     else if (k == "capacity") *value = h->cap_pairs;
     else if (k == "colpath") *value = h->opt_colpath;
+    else if (k == "cigar_workspace") *value = h->opt_path_ws;
     else if (k == "captures") *value = h->n_captures;
     else if (k == "capture_refusals") *value = h->n_capture_refusals;
     else return fail(h, SW_EINVAL, "unknown option '%s'", key);
@@ -863,6 +947,187 @@ int sw_last_timing(sw_handle* h, float* plan_ms, float* forward_ms, float* rever
     if (plan_ms) *plan_ms = h->t_plan;
     if (forward_ms) *forward_ms = h->t_fwd;
     if (reverse_ms) *reverse_ms = h->t_rev;
+    return SW_OK;
+}
+
+}  // extern "C"
+
+// ---- alignment paths ---------------------------------------------------------
+
+static int ensure_path_buffers(sw_handle* h, int64_t cap) {
+    if (cap <= h->trace_cap) return SW_OK;
+    free_dev(h->d_rec_off); free_dev(h->d_bsum);
+    h->d_rec_off = nullptr; h->d_bsum = nullptr;
+    h->trace_cap = 0;
+    if (hipMalloc(&h->d_rec_off, (cap + 1) * 8) != hipSuccess ||
+        hipMalloc(&h->d_bsum, (trace_scan_blocks(cap) + 1) * 8) != hipSuccess)
+        return fail(h, SW_ENOMEM, "device allocation of path offsets for %lld pairs failed", (long long)cap);
+    h->trace_cap = cap;
+    return SW_OK;
+}
+
+// Paths of the pairs whose results are in `out` (written by the score passes
+// of the same call): record layout, then per chunk planning, path sweeps and
+// walks.  Synchronises `stream` once to read the records' total size (and
+// once per chunk when timing).
+static int trace_paths(sw_handle* h, const sw_batch* batch, const sw_scheme* schemes, int n_schemes,
+                       sw_result* out, const int64_t* path_off, uint32_t* path, int32_t* path_len,
+                       hipStream_t stream) {
+    const int64_t P = batch->n_pairs;
+    const bool timing = h->opt_timing != 0;
+    const bool per_bin = h->opt_timing == 2;
+    const int n_tb = (int)h->tbins.size();
+    if (per_bin && h->tbin_ev.empty()) {
+        h->tbin_ev.assign(2 * n_tb, nullptr);
+        for (hipEvent_t& e : h->tbin_ev)
+            if (hipEventCreate(&e) != hipSuccess) return fail(h, SW_EDEVICE, "event creation failed");
+    }
+    const int64_t cap = h->cap_pairs;
+    int rc = ensure_path_buffers(h, cap);
+    if (rc != SW_OK) return rc;
+
+    KParams K;
+    memset(&K, 0, sizeof(K));
+    K.queries = batch->queries; K.q_beg = batch->q_off; K.q_end = batch->q_off + 1;
+    K.refs = batch->refs; K.r_beg = batch->r_off; K.r_end = batch->r_off + 1;
+    K.scheme_id = batch->scheme_id; K.order = h->d_order; K.items = h->d_items; K.meta = h->d_meta;
+    K.out = out; K.flags = h->d_small; K.mats = h->d_mats; K.validate = 0;
+    K.n_dev = h->d_n;
+    K.n_pairs = (int32_t)cap;
+    K.max_items = (int32_t)(cap + kMaxBins);
+    for (int s = 0; s < SW_MAX_SCHEMES; ++s) {
+        const bool v = s < n_schemes;
+        K.alphabet[s] = v ? schemes[s].alphabet : 1;
+        K.gap_open[s] = v ? schemes[s].gap_open : 1;
+        K.gap_extend[s] = v ? schemes[s].gap_extend : 0;
+    }
+    TraceArgs T;
+    memset(&T, 0, sizeof(T));
+    T.rec_off = h->d_rec_off;
+    T.lut = h->d_tlut;
+    T.bins = h->d_tbins;
+    T.n_bins = n_tb;
+    T.chunk_bytes = 1;
+
+    HIP_TRY(h, launch_reset(h->d_small, kSmallInts, stream));
+    if (timing) HIP_TRY(h, hipEventRecord(h->tev[0], stream));
+    HIP_TRY(h, launch_trace_sizes(K, T, cap, h->d_rec_off, h->d_bsum, counters(h->d_small), stream));
+    HIP_TRY(h, hipMemcpyAsync(h->h_i64, h->d_rec_off + P, 8, hipMemcpyDeviceToHost, stream));
+    HIP_TRY(h, hipStreamSynchronize(stream));
+    const int64_t total = h->h_i64[0];
+    if (total < 0) return fail(h, SW_EINTERNAL, "negative path record size");
+
+    // chunking: the workspace holds one chunk's records; records start in
+    // [c * C, (c + 1) * C) and none is larger than kMaxRecordBytes
+    int64_t C, ws;
+    if (total + 256 <= h->opt_path_ws) {
+        C = std::max<int64_t>(total, 1);
+        ws = (total + 255) & ~(int64_t)255;
+    } else {
+        C = (h->opt_path_ws - kMaxRecordBytes) & ~(int64_t)255;
+        ws = C + kMaxRecordBytes;
+    }
+    const int chunks = total > 0 ? (int)((total + C - 1) / C) : 1;
+    ws = std::max<int64_t>(ws, 256);
+    if (ws > h->ws_alloc) {
+        free_dev(h->d_ws);
+        h->d_ws = nullptr;
+        h->ws_alloc = 0;
+        if (hipMalloc(&h->d_ws, ws) != hipSuccess)
+            return fail(h, SW_ENOMEM, "device allocation of %lld path record bytes failed", (long long)ws);
+        h->ws_alloc = ws;
+    }
+    T.ws = h->d_ws;
+    T.ws_bytes = h->ws_alloc;
+    T.chunk_bytes = C;
+    h->last_path_bytes = total;
+    h->last_path_chunks = chunks;
+    h->t_path_sweep = h->t_path_walk = 0.f;
+    std::vector<float> bin_ms(n_tb, 0.f);
+
+    for (int c = 0; c < chunks; ++c) {
+        T.chunk = c;
+        HIP_TRY(h, launch_reset(h->d_hist, kHistSize, stream));
+        HIP_TRY(h, launch_trace_classify(K, T, cap, h->d_keys, h->d_hist, counters(h->d_small), stream));
+        HIP_TRY(h, launch_plan(h->d_tbins, n_tb, h->d_hist, h->d_meta, stream));
+        HIP_TRY(h, launch_scatter(h->d_keys, h->d_n, cap, h->d_hist, h->d_order, stream));
+        HIP_TRY(h, launch_items(h->d_meta, h->d_tbins, n_tb, h->d_n, cap, h->d_items, stream));
+        if (timing) HIP_TRY(h, hipEventRecord(h->tev[1], stream));
+        // longest boxes first; each bin's kernel fills the device
+        for (int b = n_tb - 1; b >= 0; --b) {
+            const BinInfo& e = h->tbins[b];
+            const int64_t need = (cap / e.ppw + 1 + kWavesPerBlock - 1) / kWavesPerBlock;
+            const int blocks = (int)std::min<int64_t>(need, h->tresident[b]);
+            set_range(K, b, 0);
+            if (per_bin) HIP_TRY(h, hipEventRecord(h->tbin_ev[2 * b], stream));
+            hipLaunchKernelGGL(trace_kernel(e.W, e.R), dim3(blocks), dim3(kBlock), 0, stream, K, T);
+            HIP_TRY(h, hipGetLastError());
+            if (per_bin) HIP_TRY(h, hipEventRecord(h->tbin_ev[2 * b + 1], stream));
+        }
+        if (timing) HIP_TRY(h, hipEventRecord(h->tev[2], stream));
+        HIP_TRY(h, launch_trace_walk(K, T, cap, path_off, path, path_len, stream));
+        if (timing) {
+            HIP_TRY(h, hipEventRecord(h->tev[3], stream));
+            HIP_TRY(h, hipEventSynchronize(h->tev[3]));
+            float a = 0, w = 0;
+            HIP_TRY(h, hipEventElapsedTime(&a, h->tev[1], h->tev[2]));
+            HIP_TRY(h, hipEventElapsedTime(&w, h->tev[2], h->tev[3]));
+            h->t_path_sweep += a;
+            h->t_path_walk += w;
+            for (int b = 0; per_bin && b < n_tb; ++b) {
+                float ms = 0;
+                HIP_TRY(h, hipEventElapsedTime(&ms, h->tbin_ev[2 * b], h->tbin_ev[2 * b + 1]));
+                bin_ms[b] += ms;
+            }
+        }
+    }
+    HIP_TRY(h, hipMemcpyAsync(h->h_small, h->d_small, kSmallInts * 4, hipMemcpyDeviceToHost, stream));
+    HIP_TRY(h, hipStreamSynchronize(stream));
+    const int32_t* flags = h->h_small;
+    const unsigned long long* cnt = counters(h->h_small);
+    h->last_path_cells = (int64_t)cnt[kCtrTraceCells];
+    for (int b = 0; b < n_tb; ++b) {
+        sw_bin_stat st;
+        memset(&st, 0, sizeof(st));
+        st.pass = 2;
+        st.precision = 32;
+        st.lanes = h->tbins[b].W;
+        st.rows = h->tbins[b].R;
+        st.pairs = (int64_t)cnt[kCtrTraceBinPairs + b];
+        st.cells = (int64_t)cnt[kCtrTraceBinCells + b];
+        st.ms = bin_ms[b];
+        h->bin_stats.push_back(st);
+    }
+    if (flags[kFlagInternal]) return fail(h, SW_EINTERNAL, "an alignment path could not be recovered");
+    if (flags[kFlagPathRoom])
+        return fail(h, SW_EINVAL, "the output room of a pair is too small for its path (cigar_len = -1)");
+    return SW_OK;
+}
+
+extern "C" {
+
+int sw_align_cigar(sw_handle* h, const sw_batch* batch, const sw_scheme* schemes, int n_schemes, sw_result* out,
+                   const int64_t* cigar_off, uint32_t* cigar, int32_t* cigar_len, void* stream) {
+    if (!h) return SW_EINVAL;
+    if (!batch) return fail(h, SW_EINVAL, "null batch");
+    h->last_path_cells = h->last_path_bytes = 0;
+    h->last_path_chunks = 0;
+    h->t_path_sweep = h->t_path_walk = 0.f;
+    if (batch->n_pairs > 0 && (!cigar_off || !cigar || !cigar_len))
+        return fail(h, SW_EINVAL, "null cigar buffer with n_pairs > 0");
+    const int rc = sw_align_batch(h, batch, schemes, n_schemes, out, stream);
+    if (rc != SW_OK || batch->n_pairs == 0) return rc;
+    return trace_paths(h, batch, schemes, n_schemes, out, cigar_off, cigar, cigar_len, (hipStream_t)stream);
+}
+
+int sw_last_cigar_stats(sw_handle* h, int64_t* box_cells, int64_t* record_bytes, int32_t* chunks, float* sweep_ms,
+                        float* walk_ms) {
+    if (!h) return SW_EINVAL;
+    if (box_cells) *box_cells = h->last_path_cells;
+    if (record_bytes) *record_bytes = h->last_path_bytes;
+    if (chunks) *chunks = h->last_path_chunks;
+    if (sweep_ms) *sweep_ms = h->t_path_sweep;
+    if (walk_ms) *walk_ms = h->t_path_walk;
     return SW_OK;
 }
 

@@ -1,0 +1,527 @@
+// sw_trace.hip -- alignment paths on gfx950: the traceback of Fig. 2(c),
+// recovered inside each pair's result box.
+//
+// The score path gives, per pair, S and the box a[q_start..q_end] x
+// b[r_start..r_end].  Every S-scoring alignment that ends at the box's last
+// cell and stays in the box starts at its first cell (a later start would
+// contradict the latest-start rule of the reverse sweep), so the path is a
+// traceback of the box's own local Gotoh matrices from its last cell.  Two
+// steps, per chunk of pairs:
+//
+//   1. Path sweep: the box is swept like the forward pass (one pair per
+//      W-lane group, R rows per lane, anti-diagonal steps with DPP lane
+//      shifts; int32), and every cell leaves 4 bits in a device record:
+//        bits 0-1  the first valid source of H: 0 diagonal, 1 F (a query
+//                  residue over a gap), 2 E (a reference residue over a gap)
+//        bit 2     F opens here (F == H(i-1, j) - o)
+//        bit 3     E opens here (E == H(i, j-1) - o)
+//      Step t of lane l holds rows l*R .. l*R+R-1 of column t - l, so a step
+//      of the group is one coalesced store of W * R / 2 bytes.
+//   2. Walk: one thread per pair follows the bits back from the box's last
+//      cell, preferring at each choice the first valid option in the order
+//      above and opening a gap over extending it, and writes the path as
+//      runs (length << 4) | op with the SAM codes 7 '=', 8 'X', 1 'I', 2 'D'.
+//
+// E and F are carried clamped at zero, as in the score sweeps; a clamped
+// value only differs on cells whose H is 0, which no path visits (every
+// prefix of an optimal path scores above 0).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sw_device.h"
+#include "sw_internal.h"
+
+namespace sw {
+
+// The box of one pair as a forward sub-problem; an empty job for a pair
+// without an alignment, and an internal error for a box outside its pair or
+// taller than `max_rows`.
+__device__ __forceinline__ PairJob box_job(const KParams& P, int pair, int max_rows) {
+    PairJob J;
+    J.dir = 1; J.n = 0; J.m = 0; J.qbase = 0; J.rbase = 0; J.sid = 0;
+    J.fwd_score = 0; J.fwd_qe = -1; J.fwd_re = -1;
+    if (pair < 0) return J;
+    if (pair >= *P.n_dev) {
+        atomicOr(&P.flags[kFlagInternal], 1);
+        return J;
+    }
+    const sw_result r = P.out[pair];
+    if (r.score <= 0) return J;
+    const int64_t q0 = P.q_beg[pair], q1 = P.q_end[pair];
+    const int64_t r0 = P.r_beg[pair], r1 = P.r_end[pair];
+    const int sid = P.scheme_id ? (int)P.scheme_id[pair] : 0;
+    const bool ok = r.q_start >= 0 && r.q_start <= r.q_end && r.q_end < q1 - q0 && r.r_start >= 0 &&
+                    r.r_start <= r.r_end && r.r_end < r1 - r0 && r.q_end - r.q_start < max_rows &&
+                    r.r_end - r.r_start < SW_MAX_REF && sid < SW_MAX_SCHEMES;
+    if (!ok) {
+        atomicOr(&P.flags[kFlagInternal], 1);
+        return J;
+    }
+    J.sid = sid;
+    J.n = r.q_end - r.q_start + 1;
+    J.m = r.r_end - r.r_start + 1;
+    J.qbase = q0 + r.q_start;
+    J.rbase = r0 + r.r_start;
+    J.fwd_score = r.score;
+    return J;
+}
+
+// Path sweep of the wave item order[first .. first+count), one pair per
+// W-lane group.
+template <int W, int R>
+__device__ __forceinline__ void sweep_trace(const KParams& P, const TraceArgs& T, const SchemeLds& S,
+                                            uint16_t* wbuf, int first, int count, int lane) {
+    static_assert(R % 8 == 0 && R >= 8 && R <= 32, "a lane's record of one step is whole dwords of 8 rows");
+    constexpr int NW = R / 8;
+    using Stager = RefStager<W>;
+    const int g = lane / W;
+    const int l = lane % W;
+
+    const int pair = g < count ? P.order[first + g] : -1;
+    PairJob J = box_job(P, pair, W * R);
+    uint32_t* rec = nullptr;
+    if (J.m > 0) {
+        const int64_t off = T.rec_off[pair] - (int64_t)T.chunk * T.chunk_bytes;
+        const int64_t bytes = trace_record_bytes(W, R, J.m);
+        if (off < 0 || off + bytes > T.ws_bytes || (off & 15) != 0) {
+            atomicOr(&P.flags[kFlagInternal], 1);
+            J.n = 0; J.m = 0;
+        } else {
+            rec = reinterpret_cast<uint32_t*>(T.ws + off);
+        }
+    }
+    const int my_steps = J.m > 0 ? J.m + W - 1 : 0;
+    int mmax = J.m;
+    for (int off = 32; off > 0; off >>= 1) mmax = imax(mmax, __shfl_xor(mmax, off));
+    const int steps = __builtin_amdgcn_readfirstlane(mmax > 0 ? mmax + W - 1 : 0);
+
+    uint16_t* buf = wbuf + g * Stager::kBuf;
+    Stager stage;
+    stage.load(P.refs, J, P.order, 0, l);
+    const int A = S.alphabet[J.sid];
+    int a[R];
+    {
+        int raw[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            int i = l * R + r;
+            i = i < J.n ? i : (J.n > 0 ? J.n - 1 : 0);
+            const uint8_t* p = J.n > 0 ? P.queries + J.qbase + i : reinterpret_cast<const uint8_t*>(P.order);
+            raw[r] = *p;
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) a[r] = (l * R + r < J.n && raw[r] < A) ? raw[r] : kPad;
+    }
+    bool bad = false;   // residues were checked by the score passes
+    stage.store(buf, J, A, 0, l, bad);
+    const int go = S.gap_open[J.sid];
+    const int ge = S.gap_extend[J.sid];
+    wave_lds_sync();
+
+    int H[R], E[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) { H[r] = 0; E[r] = 0; }
+    int Hlast = 0, Flast = 0, Hup_prev = 0;
+    const uint16_t* rbl = buf + W - l;   // rbl[tt] = column t0 + tt - l
+    int sc[R];
+    int bb_next = rbl[1];
+    {
+        const int bb0 = rbl[0];
+#pragma unroll
+        for (int r = 0; r < R; ++r) sc[r] = S.mat[bb0 + a[r]];
+    }
+    uint32_t* rp = rec ? rec + l * NW : nullptr;   // this lane's record of step 0
+    for (int t0 = 0; t0 < steps; t0 += kChunk) {
+        const bool more = t0 + kChunk < steps;
+        if (more) stage.load(P.refs, J, P.order, t0 + kChunk, l);
+        const int tn = __builtin_amdgcn_readfirstlane(steps - t0 < kChunk ? steps - t0 : kChunk);
+        for (int tt = 0; tt < tn; ++tt) {
+            const int bb2 = rbl[tt + 2];
+            const int Hup = shift_in_group<W>(Hlast);
+            const int Fup = shift_in_group<W>(Flast);
+            int diag = Hup_prev;
+            Hup_prev = Hup;
+            int Hmu = sat_sub(Hup, go);
+            int F = Fup;
+            uint32_t wv[NW];
+#pragma unroll
+            for (int k = 0; k < NW; ++k) wv[k] = 0;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                F = imax(F - ge, Hmu);
+                const int d = diag + sc[r];
+                const int h = imax(imax(d, E[r]), F);
+                const uint32_t code = h == d ? 0u : (h == F ? 1u : 2u);
+                const uint32_t fo = F == Hmu ? 4u : 0u;
+                const uint32_t eo = E[r] == sat_sub(H[r], go) ? 8u : 0u;
+                wv[r / 8] |= (code | fo | eo) << (4 * (r % 8));
+                sc[r] = S.mat[bb_next + a[r]];
+                diag = H[r];
+                H[r] = h;
+                Hmu = sat_sub(h, go);
+                E[r] = imax(E[r] - ge, Hmu);
+            }
+            Hlast = H[R - 1];
+            Flast = F;
+            bb_next = bb2;
+            if (t0 + tt < my_steps) {
+                if constexpr (NW == 1) {
+                    rp[0] = wv[0];
+                } else if constexpr (NW == 2) {
+                    *reinterpret_cast<uint2*>(rp) = make_uint2(wv[0], wv[1]);
+                } else if constexpr (NW == 4) {
+                    *reinterpret_cast<uint4*>(rp) = make_uint4(wv[0], wv[1], wv[2], wv[3]);
+                } else {
+#pragma unroll
+                    for (int k = 0; k < NW; ++k) rp[k] = wv[k];
+                }
+                rp += W * NW;
+            }
+        }
+        if (more) {
+            wave_lds_sync();
+            stage.store(buf, J, A, t0 + kChunk, l, bad);
+            wave_lds_sync();
+            bb_next = rbl[1];
+            const int bb0 = rbl[0];
+#pragma unroll
+            for (int r = 0; r < R; ++r) sc[r] = S.mat[bb0 + a[r]];
+        }
+    }
+}
+
+// LDS reference buffer of one wavefront (16-bit entries): four 16-lane
+// groups, the widest layout.
+constexpr int kTraceWaveBuf = 4 * RefStager<16>::kBuf;
+
+// Work-queue kernel of one path-sweep shape (same fetch loop as the score
+// sweeps' queue kernels).
+template <int W, int R>
+__global__ __launch_bounds__(kBlock) void sw_trace_kernel(KParams P, TraceArgs T) {
+    __shared__ __attribute__((aligned(16))) SchemeLds L;
+    __shared__ uint16_t wbufs[kWavesPerBlock * kTraceWaveBuf];
+    constexpr int kPPW = 64 / W;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    int lo = __atomic_load_n(&P.meta[P.lo_idx], __ATOMIC_RELAXED);
+    int hi = __atomic_load_n(&P.meta[P.hi_idx], __ATOMIC_RELAXED);
+    lo = __builtin_amdgcn_readfirstlane(lo);
+    hi = __builtin_amdgcn_readfirstlane(hi);
+    if (lo == hi) return;
+    if (lo < 0 || hi > P.max_items || lo > hi) {
+        if (tid == 0) atomicOr(&P.flags[kFlagInternal], 1);
+        return;
+    }
+    const int n_pairs = __builtin_amdgcn_readfirstlane(*P.n_dev);
+    load_schemes(L, P, tid);
+    __syncthreads();
+    uint16_t* wbuf = wbufs + wave * kTraceWaveBuf;
+    for (;;) {
+        const int mine = atomicAdd(&P.meta[P.head_idx], lane == 0 ? 1 : 0);
+        const int it = __builtin_amdgcn_readlane(mine, 0);
+        if (it >= hi - lo) break;
+        const WorkItem* wp = P.items + lo + it;
+        const int first = __builtin_amdgcn_readfirstlane(__atomic_load_n(&wp->first, __ATOMIC_RELAXED));
+        const int count = __builtin_amdgcn_readfirstlane((int)__atomic_load_n(&wp->count, __ATOMIC_RELAXED));
+        const bool valid = first >= 0 && count >= 1 && count <= kPPW && first + count <= n_pairs;
+        if (valid) {
+            wave_lds_sync();
+            sweep_trace<W, R>(P, T, L, wbuf, first, count, lane);
+        } else {
+            atomicOr(&P.flags[kFlagInternal], 1);
+        }
+    }
+}
+
+#define SW_TRACE_SHAPES(X) X(16, 8) X(16, 16) X(32, 16) X(64, 16) X(64, 24) X(64, 32)
+
+namespace {
+struct TraceEntry { int W, R; TraceFn fn; };
+#define SW_TRACE_ENTRY(W, R) {W, R, &sw_trace_kernel<W, R>},
+const TraceEntry kTraceKernels[] = {SW_TRACE_SHAPES(SW_TRACE_ENTRY)};
+#undef SW_TRACE_ENTRY
+constexpr int kNumTrace = sizeof(kTraceKernels) / sizeof(kTraceKernels[0]);
+ShapeDesc g_trace_shapes[kNumTrace];
+}  // namespace
+
+const ShapeDesc* trace_shapes(int* n) {
+    for (int k = 0; k < kNumTrace; ++k) g_trace_shapes[k] = {32, kTraceKernels[k].W, kTraceKernels[k].R};
+    *n = kNumTrace;
+    return g_trace_shapes;
+}
+
+TraceFn trace_kernel(int W, int R) {
+    for (int k = 0; k < kNumTrace; ++k)
+        if (kTraceKernels[k].W == W && kTraceKernels[k].R == R) return kTraceKernels[k].fn;
+    return nullptr;
+}
+
+// ---- record sizes and offsets ----------------------------------------------
+constexpr int kScanThreads = 1024;
+
+__device__ __forceinline__ long long wave_scan64(long long v, int lane) {
+    for (int off = 1; off < 64; off <<= 1) {
+        const long long u = __shfl_up(v, off);
+        if (lane >= off) v += u;
+    }
+    return v;
+}
+
+// Exclusive scan within one block of kScanThreads values; returns the
+// block total through *total.
+__device__ __forceinline__ long long block_exclusive_scan(long long v, long long* total) {
+    __shared__ long long wave_tot[kScanThreads / 64];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const long long incl = wave_scan64(v, lane);
+    if (lane == 63) wave_tot[wave] = incl;
+    __syncthreads();
+    long long before = 0, all = 0;
+    for (int w = 0; w < kScanThreads / 64; ++w) {
+        const long long x = wave_tot[w];
+        before += w < wave ? x : 0;
+        all += x;
+    }
+    __syncthreads();
+    *total = all;
+    return before + incl - v;
+}
+
+// Record size of every pair (0 without an alignment), scanned per block:
+// rec_off[i] = offset within the block, block_sums[b] = the block's total.
+// Also counts the box cells.
+__global__ __launch_bounds__(kScanThreads) void sw_trace_size_kernel(KParams P, TraceArgs T, int64_t* rec_off,
+                                                                     int64_t* block_sums,
+                                                                     unsigned long long* counters) {
+    const int64_t n = *P.n_dev;
+    const int64_t i = (int64_t)blockIdx.x * kScanThreads + threadIdx.x;
+    long long bytes = 0;
+    unsigned long long cells = 0;
+    if (i < n) {
+        const sw_result r = P.out[i];
+        if (r.score > 0) {
+            const int64_t nq = P.q_end[i] - P.q_beg[i], nr = P.r_end[i] - P.r_beg[i];
+            const int rows = r.q_end - r.q_start + 1, cols = r.r_end - r.r_start + 1;
+            if (r.q_start < 0 || rows < 1 || r.q_end >= nq || rows > SW_MAX_QUERY || r.r_start < 0 || cols < 1 ||
+                r.r_end >= nr || cols > SW_MAX_REF) {
+                atomicOr(&P.flags[kFlagInternal], 1);
+            } else {
+                const int b = T.lut[(rows - 1) / 16];
+                if (b < 0 || b >= T.n_bins || T.bins[b].W * T.bins[b].R < rows) {
+                    atomicOr(&P.flags[kFlagInternal], 1);
+                } else {
+                    bytes = trace_record_bytes(T.bins[b].W, T.bins[b].R, cols);
+                    bytes = (bytes + 15) & ~15ll;
+                    cells = (unsigned long long)rows * (unsigned long long)cols;
+                }
+            }
+        }
+    }
+    long long total;
+    const long long ex = block_exclusive_scan(bytes, &total);
+    if (i <= n) rec_off[i] = ex;
+    if (threadIdx.x == 0) block_sums[blockIdx.x] = total;
+    // box cells of the block
+    __shared__ unsigned long long s_cells;
+    if (threadIdx.x == 0) s_cells = 0;
+    __syncthreads();
+    if (cells) atomicAdd(&s_cells, cells);
+    __syncthreads();
+    if (threadIdx.x == 0 && s_cells) atomicAdd(&counters[kCtrTraceCells], s_cells);
+}
+
+// Exclusive scan of the block totals in place (one block); block_sums[nb]
+// receives the grand total.
+__global__ __launch_bounds__(kScanThreads) void sw_trace_scan_sums_kernel(int64_t* block_sums, int64_t nb) {
+    long long carry = 0;
+    for (int64_t base = 0; base < nb; base += kScanThreads) {
+        const int64_t k = base + threadIdx.x;
+        const long long v = k < nb ? block_sums[k] : 0;
+        long long total;
+        const long long ex = block_exclusive_scan(v, &total);
+        if (k < nb) block_sums[k] = carry + ex;
+        carry += total;
+    }
+    if (threadIdx.x == 0) block_sums[nb] = carry;
+}
+
+// rec_off[i] += the offset of its block; rec_off[n] = the total.
+__global__ __launch_bounds__(kScanThreads) void sw_trace_add_kernel(const KParams P, int64_t* rec_off,
+                                                                    const int64_t* block_sums, int64_t nb) {
+    const int64_t n = *P.n_dev;
+    const int64_t i = (int64_t)blockIdx.x * kScanThreads + threadIdx.x;
+    if (i < n) rec_off[i] += block_sums[blockIdx.x];
+    if (i == n) rec_off[n] = block_sums[nb];
+}
+
+int64_t trace_scan_blocks(int64_t cap) { return (cap + 1 + kScanThreads - 1) / kScanThreads; }
+
+hipError_t launch_trace_sizes(const KParams& P, const TraceArgs& T, int64_t cap, int64_t* rec_off,
+                              int64_t* block_sums, unsigned long long* counters, hipStream_t s) {
+    const int64_t nb = trace_scan_blocks(cap);
+    hipLaunchKernelGGL(sw_trace_size_kernel, dim3((unsigned)nb), dim3(kScanThreads), 0, s, P, T, rec_off,
+                       block_sums, counters);
+    hipLaunchKernelGGL(sw_trace_scan_sums_kernel, dim3(1), dim3(kScanThreads), 0, s, block_sums, nb);
+    hipLaunchKernelGGL(sw_trace_add_kernel, dim3((unsigned)nb), dim3(kScanThreads), 0, s, P, rec_off,
+                       (const int64_t*)block_sums, nb);
+    return hipGetLastError();
+}
+
+// ---- planning of one chunk ---------------------------------------------------
+// Keys as in the score passes' classification: (bin, reference-length
+// bucket, longest first); pairs outside the chunk or without an alignment
+// get the trivial key.
+__global__ void sw_trace_classify_kernel(KParams P, TraceArgs T, int32_t* keys, int32_t* hist,
+                                         unsigned long long* counters) {
+    __shared__ unsigned long long s_cells[kMaxBins];
+    __shared__ uint32_t s_pairs[kMaxBins];
+    __shared__ int32_t s_trivial;
+    if (threadIdx.x < kMaxBins) { s_cells[threadIdx.x] = 0; s_pairs[threadIdx.x] = 0; }
+    if (threadIdx.x == 0) s_trivial = 0;
+    __syncthreads();
+    const int64_t n = *P.n_dev;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        int key = kTrivialKey;
+        const sw_result r = P.out[i];
+        if (r.score > 0 && T.rec_off[i] / T.chunk_bytes == T.chunk) {
+            const int rows = r.q_end - r.q_start + 1, cols = r.r_end - r.r_start + 1;
+            // sizes were validated when the records were laid out
+            if (rows >= 1 && rows <= SW_MAX_QUERY && cols >= 1 && cols <= SW_MAX_REF) {
+                const int b = T.lut[(rows - 1) / 16];
+                if (b >= 0 && b < T.n_bins) {
+                    key = b * kMBuckets + kMHalf + (kMHalf - 1 - m_bucket(cols));
+                    atomicAdd(&s_cells[b], (unsigned long long)rows * (unsigned long long)cols);
+                    atomicAdd(&s_pairs[b], 1u);
+                }
+            }
+        }
+        if (key == kTrivialKey) atomicAdd(&s_trivial, 1);
+        else atomicAdd(&hist[key], 1);
+        keys[i] = key;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && s_trivial) atomicAdd(&hist[kTrivialKey], s_trivial);
+    if (threadIdx.x < kMaxBins && s_pairs[threadIdx.x]) {
+        atomicAdd(&counters[kCtrTraceBinCells + threadIdx.x], s_cells[threadIdx.x]);
+        atomicAdd(&counters[kCtrTraceBinPairs + threadIdx.x], (unsigned long long)s_pairs[threadIdx.x]);
+    }
+}
+
+hipError_t launch_trace_classify(const KParams& P, const TraceArgs& T, int64_t cap, int32_t* keys,
+                                 int32_t* hist, unsigned long long* counters, hipStream_t s) {
+    if (cap <= 0) return hipSuccess;
+    const unsigned blocks = (unsigned)((cap + 255) / 256);
+    hipLaunchKernelGGL(sw_trace_classify_kernel, dim3(blocks), dim3(256), 0, s, P, T, keys, hist, counters);
+    return hipGetLastError();
+}
+
+// ---- walk ------------------------------------------------------------------------
+// One thread per pair of the chunk.  Runs are written from the end of the
+// pair's output room backwards while the path is followed back, then moved
+// to its start.  A path that leaves its box or does not end at the box's
+// first cell is an internal error; one that needs more runs than its room
+// sets kFlagPathRoom.  Either way the pair's run count becomes -1.
+__global__ void sw_trace_walk_kernel(KParams P, TraceArgs T, const int64_t* path_off, uint32_t* path,
+                                     int32_t* path_len) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= *P.n_dev) return;
+    const sw_result r = P.out[i];
+    if (r.score <= 0) {
+        if (T.chunk == 0) path_len[i] = 0;
+        return;
+    }
+    const int64_t off = T.rec_off[i];
+    if (off / T.chunk_bytes != T.chunk) return;
+    const int rows = r.q_end - r.q_start + 1, cols = r.r_end - r.r_start + 1;
+    const int b = (rows >= 1 && rows <= SW_MAX_QUERY) ? T.lut[(rows - 1) / 16] : -1;
+    const int64_t beg = path_off[i], end = path_off[i + 1];
+    if (b < 0 || b >= T.n_bins || cols < 1 || end < beg) {
+        atomicOr(&P.flags[end < beg ? kFlagPathRoom : kFlagInternal], 1);
+        path_len[i] = -1;
+        return;
+    }
+    const int W = T.bins[b].W, R = T.bins[b].R;
+    const int64_t rel = off - (int64_t)T.chunk * T.chunk_bytes;
+    if (W * R < rows || rel < 0 || rel + trace_record_bytes(W, R, cols) > T.ws_bytes) {
+        atomicOr(&P.flags[kFlagInternal], 1);
+        path_len[i] = -1;
+        return;
+    }
+    const uint8_t* rec = T.ws + rel;
+    const uint8_t* qa = P.queries + P.q_beg[i] + r.q_start;
+    const uint8_t* rb = P.refs + P.r_beg[i] + r.r_start;
+    const int64_t room = end - beg;
+    int x = rows - 1, y = cols - 1;
+    int state = 0;   // 0 = H, 1 = F (query gap), 2 = E (reference gap)
+    int64_t k = 0;   // runs written
+    uint32_t op = 0, len = 0;
+    int err = 0;     // 1 internal, 2 room
+    const int64_t limit = 2 * ((int64_t)rows + cols) + 2;
+    bool done = false;
+    for (int64_t it = 0; it < limit && !err; ++it) {
+        const int lane = x / R, rr = x - lane * R;
+        const int64_t byte = ((int64_t)(y + lane) * W + lane) * (R / 2) + (rr >> 1);
+        const uint32_t nib = (rec[byte] >> (4 * (rr & 1))) & 15u;
+        uint32_t o;
+        if (state == 0) {
+            const uint32_t code = nib & 3u;
+            if (code == 1u) { state = 1; continue; }
+            if (code == 2u) { state = 2; continue; }
+            if (code != 0u) { err = 1; break; }
+            o = qa[x] == rb[y] ? 7u : 8u;
+            --x; --y;
+        } else if (state == 1) {
+            o = 1u;
+            state = (nib & 4u) ? 0 : 1;
+            --x;
+        } else {
+            o = 2u;
+            state = (nib & 8u) ? 0 : 2;
+            --y;
+        }
+        if (o == op) {
+            ++len;
+        } else {
+            if (len) {
+                if (k >= room) { err = 2; break; }
+                path[end - 1 - k] = (len << 4) | op;
+                ++k;
+            }
+            op = o;
+            len = 1;
+        }
+        if (x < 0 || y < 0) {
+            // the first column of the path must be the box's first cell
+            done = x == -1 && y == -1 && state == 0 && (o == 7u || o == 8u);
+            if (!done) err = 1;
+            break;
+        }
+    }
+    if (!err && !done) err = 1;
+    if (!err) {
+        if (k >= room) err = 2;
+        else {
+            path[end - 1 - k] = (len << 4) | op;
+            ++k;
+        }
+    }
+    if (err) {
+        atomicOr(&P.flags[err == 2 ? kFlagPathRoom : kFlagInternal], 1);
+        path_len[i] = -1;
+        return;
+    }
+    // runs sit at path[end-k .. end) in order; move them to the room's start
+    for (int64_t q = 0; q < k; ++q) path[beg + q] = path[end - k + q];
+    path_len[i] = (int32_t)k;
+}
+
+hipError_t launch_trace_walk(const KParams& P, const TraceArgs& T, int64_t cap, const int64_t* path_off,
+                             uint32_t* path, int32_t* path_len, hipStream_t s) {
+    if (cap <= 0) return hipSuccess;
+    const unsigned blocks = (unsigned)((cap + 255) / 256);
+    hipLaunchKernelGGL(sw_trace_walk_kernel, dim3(blocks), dim3(256), 0, s, P, T, path_off, path, path_len);
+    return hipGetLastError();
+}
+
+}  // namespace sw

@@ -1,0 +1,211 @@
+"""GPU parity of the alignment paths (sw_align_cigar) against the oracle's
+traceback: the runs of every compared pair must be identical, and the
+results must equal the score path's.  Small cases are compared on every
+pair; the full-size DNA workload on a seeded sample, and on properties that
+hold for every pair (the runs consume exactly the result box)."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2208_12350_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("score", "q_start", "q_end", "r_start", "r_end")
+
+
+@pytest.fixture(scope="module")
+def aligner():
+    import torch
+    from paper_2208_12350_amd.binding import Aligner
+    assert torch.cuda.is_available()
+    a = Aligner(0)
+    yield a
+    a.close()
+
+
+def gpu_paths(aligner, batch, **kw):
+    """(results [n, 5], runs uint32, cigar_off, cigar_len) on the host."""
+    from paper_2208_12350_amd.binding import DeviceBatch
+    db = DeviceBatch.from_host(batch)
+    out, off, cig, ln = aligner.align_cigar(db, **kw)
+    return (out.cpu().numpy().astype(np.int64), cig.cpu().numpy().view(np.uint32),
+            off.cpu().numpy(), ln.cpu().numpy()[:batch.n_pairs])
+
+
+def assert_paths_equal(batch, gpu, idx=None):
+    res, runs, off, ln = gpu
+    idx = np.arange(batch.n_pairs) if idx is None else np.asarray(idx)
+    ores, oruns, ooff, onr = O.cigar_batch(batch, index=idx)
+    want = np.stack([ores[f] for f in FIELDS], axis=1).astype(np.int64)
+    bad = np.flatnonzero(np.any(res[idx] != want, axis=1))
+    assert bad.size == 0, ("results differ", int(idx[bad[0]]), res[idx[bad[0]]].tolist(), want[bad[0]].tolist())
+    for k, i in enumerate(idx):
+        g = runs[off[i]:off[i] + ln[i]]
+        o = oruns[ooff[k]:ooff[k] + onr[k]]
+        if ln[i] != onr[k] or not np.array_equal(g, o):
+            q, r, s = batch.pair(int(i))
+            raise AssertionError("pair %d (n=%d m=%d %s) result %s: gpu %s oracle %s"
+                                 % (i, q.size, r.size, s.name, res[i].tolist(), O.cigar_string(g),
+                                    O.cigar_string(o)))
+
+
+def _fig2():
+    M = np.full((4, 4), -2, np.int8)
+    np.fill_diagonal(M, 2)
+    return W.Scheme(M, 1, 1, "fig2")
+
+
+def test_golden_cases(aligner):
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "cigar_cases.txt")
+    pairs, sids, want = [], [], []
+    with open(path) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            name, q, r, cig = line.split()
+            pairs.append((W.encode(q, "ACGT"), W.encode(r, "ACGT")))
+            sids.append(0 if name == "dna" else 1)
+            want.append(cig)
+    b = W.from_pairs(pairs, sids, [W.dna_scheme(), _fig2()])
+    res, runs, off, ln = gpu_paths(aligner, b)
+    got = [O.cigar_string(runs[off[i]:off[i] + ln[i]]) or "*" for i in range(b.n_pairs)]
+    assert got == want
+
+
+def test_tiny_random_all_gap_settings(aligner):
+    rng = np.random.default_rng(7)
+    for o, e in [(6, 1), (1, 1), (3, 0), (5, 2), (2, 1)]:
+        M = rng.integers(-4, 4, size=(4, 4))
+        np.fill_diagonal(M, rng.integers(2, 6, size=4))
+        sc = W.Scheme(np.ascontiguousarray(M.astype(np.int8)), o, e)
+        pairs = [(rng.integers(0, 4, size=int(rng.integers(0, 20))), rng.integers(0, 4, size=int(rng.integers(0, 24))))
+                 for _ in range(1500)]
+        b = W.from_pairs(pairs, [0] * len(pairs), [sc])
+        assert_paths_equal(b, gpu_paths(aligner, b))
+
+
+def test_dna_small_every_pair(aligner):
+    b = W.make_workload("dna_small")
+    assert_paths_equal(b, gpu_paths(aligner, b))
+
+
+def test_protein_and_mixed_samples(aligner):
+    for name, n in (("protein", 1500), ("mixed", 3000)):
+        b = W.make_workload(name, n_pairs=n)
+        gpu = gpu_paths(aligner, b)
+        # every pair below 4M box cells, plus a few of the largest boxes
+        res = gpu[0]
+        cells = (res[:, 2] - res[:, 1] + 1) * (res[:, 4] - res[:, 3] + 1) * (res[:, 0] > 0)
+        idx = np.flatnonzero(cells < 4_000_000)
+        idx = np.concatenate([idx, np.argsort(cells)[-3:]])
+        assert_paths_equal(b, gpu, idx)
+
+
+def test_edge_shapes(aligner):
+    # box heights around every shape boundary, long boxes, identical and
+    # unrelated sequences, empty inputs
+    rng = np.random.default_rng(11)
+    dna = W.dna_scheme()
+    pairs = []
+    for n in (1, 2, 7, 8, 9, 127, 128, 129, 255, 256, 257, 511, 512, 513, 1023, 1024, 1025, 1535, 1536, 1537,
+              2047, 2048):
+        q = rng.integers(0, 4, size=n).astype(np.uint8)
+        r = np.concatenate([rng.integers(0, 4, size=int(rng.integers(0, 40))), q,
+                            rng.integers(0, 4, size=int(rng.integers(0, 40)))]).astype(np.uint8)
+        pairs.append((q, r))
+        mut = q.copy()
+        flip = rng.random(n) < 0.1
+        mut[flip] = (mut[flip] + 1) % 4
+        pairs.append((mut, r))
+    pairs.append((np.zeros(0, np.uint8), rng.integers(0, 4, size=10).astype(np.uint8)))
+    pairs.append((rng.integers(0, 4, size=10).astype(np.uint8), np.zeros(0, np.uint8)))
+    pairs.append((np.zeros(50, np.uint8), np.ones(60, np.uint8)))        # no positive cell
+    pairs.append((rng.integers(0, 4, size=300).astype(np.uint8), rng.integers(0, 4, size=5000).astype(np.uint8)))
+    b = W.from_pairs(pairs, [0] * len(pairs), [dna])
+    assert_paths_equal(b, gpu_paths(aligner, b))
+
+
+def test_results_equal_score_path(aligner):
+    from paper_2208_12350_amd.binding import DeviceBatch
+    b = W.make_workload("mixed", n_pairs=5000)
+    db = DeviceBatch.from_host(b)
+    plain = aligner.align(db).cpu().numpy()
+    out, _, _, ln = aligner.align_cigar(db)
+    assert np.array_equal(out.cpu().numpy(), plain)
+    assert np.all((ln.cpu().numpy() > 0) == (plain[:, 0] > 0))
+
+
+def _consumed(runs, off, ln, ops):
+    """Per pair, the residues consumed by runs whose op is in `ops`."""
+    n = ln.size
+    total = np.zeros(n, np.int64)
+    lens = (runs >> 4).astype(np.int64)
+    take = np.isin(runs & 15, ops)
+    vals = np.where(take, lens, 0)
+    csum = np.concatenate([[0], np.cumsum(vals)])
+    start = off[:n]
+    total = csum[start + ln] - csum[start]
+    return total
+
+
+def test_full_size_dna_large_sampled(aligner):
+    b = W.make_workload("dna_large")
+    res, runs, off, ln = gpu_paths(aligner, b)
+    pos = res[:, 0] > 0
+    assert np.all(ln[pos] >= 1) and np.all(ln[~pos] == 0)
+    # every path consumes exactly its box
+    q_used = _consumed(runs, off, ln, (7, 8, 1))
+    r_used = _consumed(runs, off, ln, (7, 8, 2))
+    assert np.array_equal(q_used[pos], res[pos, 2] - res[pos, 1] + 1)
+    assert np.array_equal(r_used[pos], res[pos, 4] - res[pos, 3] + 1)
+    # first and last runs are substitution columns
+    first = runs[off[:-1][pos]] & 15
+    last = runs[off[:-1][pos] + ln[pos] - 1] & 15
+    assert np.all(np.isin(first, (7, 8))) and np.all(np.isin(last, (7, 8)))
+    idx = np.random.default_rng(3).choice(b.n_pairs, size=400, replace=False)
+    assert_paths_equal(b, (res, runs, off, ln), np.sort(idx))
+
+
+def test_chunked_workspace_gives_the_same_paths(aligner):
+    from paper_2208_12350_amd.binding import Aligner
+    b = W.make_workload("dna_large", n_pairs=20000)
+    whole = gpu_paths(aligner, b)
+    _, rec_bytes, chunks, _, _ = aligner.cigar_stats()
+    assert chunks == 1
+    small = Aligner(0, cigar_workspace=130_000_000)
+    try:
+        parts = gpu_paths(small, b)
+        _, rec2, chunks2, _, _ = small.cigar_stats()
+    finally:
+        small.close()
+    assert rec2 == rec_bytes and chunks2 >= 3, (rec2, chunks2)
+    for x, y in zip(whole, parts):
+        assert np.array_equal(x, y)
+
+
+def test_small_room_is_reported(aligner):
+    import torch
+    from paper_2208_12350_amd.binding import DeviceBatch, SwError
+    b = W.make_workload("dna_small", n_pairs=300)
+    db = DeviceBatch.from_host(b)
+    n = b.n_pairs
+    off = torch.arange(n + 1, dtype=torch.int64, device="cuda:0") * 2   # room for 2 runs each
+    with pytest.raises(SwError):
+        aligner.align_cigar(db, cigar_off=off)
+    # recompute the lengths the oracle needs
+    ores, oruns, ooff, onr = O.cigar_batch(b)
+    _, _, _, ln = aligner.align_cigar(DeviceBatch.from_host(b))   # a fresh, big enough room
+    ln = ln.cpu().numpy()[:n]
+    assert np.array_equal(ln, onr)
+    # and the failing call marked exactly the pairs that need more than 2 runs
+    out = torch.empty((n, 5), dtype=torch.int32, device="cuda:0")
+    cig = torch.empty(2 * n, dtype=torch.int32, device="cuda:0")
+    cl = torch.empty(n, dtype=torch.int32, device="cuda:0")
+    with pytest.raises(SwError):
+        aligner.align_cigar(db, out=out, cigar_off=off, cigar=cig, cigar_len=cl)
+    cl = cl.cpu().numpy()
+    assert np.array_equal(cl == -1, onr > 2)
+    assert np.array_equal(cl[onr <= 2], onr[onr <= 2])

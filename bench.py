@@ -10,6 +10,10 @@ result scatter.  Prints ONE JSON line.
 
 GCUPS = sum over pairs of n*m (forward cells, the usual definition) per
 second of whole-call wall time, / 1e9.
+
+The "cigar" object of the line times sw_align_cigar on the same batch: the
+same results plus every pair's alignment path (SAM runs), with the roofline
+of the box-sweep kernel that records the traceback choices.
 """
 import argparse
 import json
@@ -24,6 +28,10 @@ if ROOT not in sys.path:
 # Algorithmic integer operations per DP cell: H-o (1), E (2), F (2),
 # diag+s (1), max of four terms with 0 (3), running best / argmax (3).
 OPS_PER_CELL = 12
+# Alignment paths: per cell of a result box, the recurrence without the
+# running best (9) plus the traceback choices it records: H from the
+# diagonal? from F? (2), F opens? (1), E opens? (1).
+PATH_OPS_PER_CELL = 13
 # MI355X: 256 CUs x 64 lanes x 2.4 GHz of 32-bit VALU issue; packed 16-bit
 # instructions carry two operations per lane.
 VALU_INT32_TOPS = 256 * 64 * 2.4e9 / 1e12
@@ -145,6 +153,56 @@ def roofline_leg(args, db, out, tuning, mode):
                            "frac": round(fam_peak_s / (fam_ms / 1e3), 4)}}
 
 
+def cigar_leg(args, db, out, ref_out, tuning, score_ms):
+    """sw_align_cigar on the same batch: results plus every pair's path.
+    GCUPS counts forward cells per second of whole-call wall time, as the
+    headline does.  The box sweeps' kernels are then timed per launch (the
+    library's timing=2, launches serialised) for their roofline:
+    PATH_OPS_PER_CELL per box cell against the int32 VALU peak."""
+    import numpy as np
+    import torch
+    from paper_2208_12350_amd.binding import Aligner
+    al = Aligner(0, tuning)
+    res = al.align_cigar(db, out=out)
+    torch.cuda.synchronize()
+    steps = max(2, min(args.steps, 5))
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        al.align_cigar(db, out=res[0], cigar_off=res[1], cigar=res[2], cigar_len=res[3])
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    assert torch.equal(out, ref_out), "the paths call disagrees with the headline run"
+    fwd = al.stats()[0]
+    box_cells, rec_bytes, chunks, _, _ = al.cigar_stats()
+    al.close()
+    alt = Aligner(0, tuning, timing=2)
+    sweep_ms, walk_ms, per_bin = [], [], {}
+    for k in range(3):
+        alt.align_cigar(db, out=res[0], cigar_off=res[1], cigar=res[2], cigar_len=res[3])
+        _, _, _, sm, wm = alt.cigar_stats()
+        sweep_ms.append(sm); walk_ms.append(wm)
+        for e in alt.bin_stats():
+            if e["pass"] == 2 and e["pairs"]:
+                acc = per_bin.setdefault((e["lanes"], e["rows"]), [0.0, 0])
+                acc[0] += e["ms"]; acc[1] += e["cells"]
+    alt.close()
+    (W_, R_), (dms, dcells) = max(per_bin.items(), key=lambda kv: kv[1][0])
+    achieved = PATH_OPS_PER_CELL * dcells / (dms / 1e3) / 1e12
+    n_chunks_launches = 3 * chunks
+    log("  paths: %d calls in %.3f s" % (steps, el))
+    return {"value": round(fwd * steps / el / 1e9, 2), "unit": "GCUPS",
+            "ms_per_call": round(el * 1e3 / steps, 3), "score_only_ms": round(score_ms, 3),
+            "box_cells": int(box_cells), "record_gb": round(rec_bytes / 1e9, 3), "chunks": chunks,
+            "sweep_ms": round(float(np.mean(sweep_ms)), 3), "walk_ms": round(float(np.mean(walk_ms)), 3),
+            "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_INT32_TOPS, 2),
+                         "unit": "Tops/s", "frac": round(achieved / VALU_INT32_TOPS, 4), "traffic": None,
+                         "kernel": "sw::sw_trace_kernel<%d, %d>" % (W_, R_),
+                         "launch_ms": round(dms / n_chunks_launches, 4),
+                         "cells_per_launch": int(dcells / n_chunks_launches),
+                         "ops_per_cell": PATH_OPS_PER_CELL,
+                         "record_bytes_per_cell": 0.5}}
+
+
 def roofline_only(args, batch, db, out, tuning, mode):
     """Only the roofline leg (for profiling it alone): one JSON line."""
     roof = roofline_leg(args, db, out, tuning, mode)
@@ -261,6 +319,8 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="keep the built-in routing")
     ap.add_argument("--routing", default=None, help="use this routing string instead of tuning")
     ap.add_argument("--roofline-only", action="store_true", help="run only the per-launch roofline leg")
+    ap.add_argument("--no-cigar", action="store_true", help="skip the alignment-path (CIGAR) leg")
+    ap.add_argument("--cigar-only", action="store_true", help="run only the alignment-path leg")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy 1 GiB device to device three times (counter calibration)")
     ap.add_argument("--loads", default="1,2,5,10,20,50,100,200,500,1000,2000",
@@ -343,6 +403,14 @@ def main():
     if args.roofline_only:
         roofline_only(args, batch, db, out, tuning, mode)
         return
+    if args.cigar_only:
+        al = Aligner(0, tuning)
+        al.align(db, out)
+        ref = out.clone()
+        al.close()
+        print(json.dumps({"leg": "cigar", "config": {"workload": args.workload, "pairs": batch.n_pairs},
+                          "cigar": cigar_leg(args, db, out, ref, tuning, 0.0)}), flush=True)
+        return
 
     # headline: persistent work-queue launch, replayed from a captured hipGraph
     al = Aligner(0, tuning, mode=mode, graph=1 if mode == 1 else 0, streams=args.streams)
@@ -376,6 +444,7 @@ def main():
 
     ms_per_step = elapsed * 1e3 / args.steps
     gcups = fwd_cells * args.steps / elapsed / 1e9
+    cigar = None if args.no_cigar else cigar_leg(args, db, out, ref_out, tuning, ms_per_step)
     int16 = i32_pairs < batch.n_pairs
     res = {
         "metric": "GCUPS, batched affine SW (score+coords), batched vs plain; p50/p99 latency",
@@ -401,6 +470,7 @@ def main():
         "phase_ms": {"plan": round(float(np.mean(plan_ms)), 3), "forward": round(float(np.mean(fwd_ms)), 3),
                      "reverse": round(float(np.mean(rev_ms)), 3)},
         "roofline": roof,
+        "cigar": cigar,
     }
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a sample ...")

@@ -201,14 +201,16 @@ struct TraceArgs {
     int64_t ws_bytes;            // workspace capacity (>= chunk_bytes + the largest record)
     int32_t chunk;
     int32_t n_bins;
-    const int8_t* lut;           // [kLutRows] path-sweep bin of each 16-row bucket of box rows
+    int32_t i16_limit;           // pairs with S <= i16_limit take the packed int16 path sweep
+    const int8_t* lut;           // [2 * kLutRows] path-sweep bin per (int16 / int32, 16-row bucket of box rows)
     const BinInfo* bins;         // path-sweep bins
 };
 
-// Path-sweep shapes (int32, one pair per W-lane group, R a multiple of 8).
+// Path-sweep shapes (precision 16: two pairs per W-lane group; 32: one;
+// R a multiple of 8).
 using TraceFn = void (*)(KParams, TraceArgs);
 const ShapeDesc* trace_shapes(int* n);
-TraceFn trace_kernel(int W, int R);
+TraceFn trace_kernel(int prec, int W, int R);
 // Record bytes of a box of m columns on shape (W, R): (m + W - 1) sweep
 // steps, each W lanes x R rows x 4 bits.
 __host__ __device__ inline int64_t trace_record_bytes(int W, int R, int64_t m) {

@@ -120,7 +120,7 @@ struct sw_handle {
     std::vector<BinInfo> tbins;          // path-sweep shapes
     std::vector<int> tresident;          // workgroups the device holds at once, per path-sweep bin
     BinInfo* d_tbins = nullptr;
-    int8_t* d_tlut = nullptr;            // [kLutRows] path-sweep bin per 16-row bucket of box rows
+    int8_t* d_tlut = nullptr;            // [2 * kLutRows] path-sweep bin per (precision, 16-row bucket of box rows)
     int64_t* d_rec_off = nullptr;        // [trace_cap + 1]
     int64_t* d_bsum = nullptr;           // [scan blocks + 1]
     int64_t trace_cap = 0;
@@ -389,53 +389,55 @@ static int enqueue_pass(sw_handle* h, KParams K, const ClassifyArgs& C, int64_t 
     return SW_OK;
 }
 
-// Path-sweep bins and their routing: each 16-row bucket of box rows goes to
-// the covering shape with the fewest lane-row slots for a box of twice as
-// many columns plus 64 (as the score routing's default).
+// Path-sweep bins and their routing: for each precision (packed int16,
+// int32), each 16-row bucket of box rows goes to the covering shape with the
+// fewest lane-row slots for a box of twice as many columns plus 64 (as the
+// score routing's default).
 static bool init_paths(sw_handle* h) {
     int n = 0;
     const ShapeDesc* sh = trace_shapes(&n);
     h->tbins.clear();
     for (int k = 0; k < n; ++k) {
         BinInfo b;
-        b.prec = 32;
+        b.prec = (uint8_t)sh[k].prec;
         b.W = (uint16_t)sh[k].W;
         b.R = (uint8_t)sh[k].R;
-        b.ppw = (uint16_t)pairs_per_item(32, sh[k].W);
+        b.ppw = (uint16_t)pairs_per_item(sh[k].prec, sh[k].W);
         b.col = 0;
         b.pad = 0;
         h->tbins.push_back(b);
     }
     if (h->tbins.empty() || h->tbins.size() > (size_t)kMaxBins) return false;
-    std::vector<int8_t> lut(kLutRows, -1);
-    for (int k = 0; k < kLutRows; ++k) {
-        const int rows = 16 * (k + 1);
-        const double m = 2.0 * rows + 64.0;
-        int best = -1;
-        double best_cost = 0;
-        for (int b = 0; b < (int)h->tbins.size(); ++b) {
-            const BinInfo& e = h->tbins[b];
-            if (e.W * e.R < rows) continue;
-            const double cost = (double)e.W * e.R * (m + e.W - 1);
-            if (best < 0 || cost < best_cost) { best = b; best_cost = cost; }
+    std::vector<int8_t> lut(2 * kLutRows, -1);
+    for (int sel = 0; sel < 2; ++sel)
+        for (int k = 0; k < kLutRows; ++k) {
+            const int rows = 16 * (k + 1);
+            const double m = 2.0 * rows + 64.0;
+            int best = -1;
+            double best_cost = 0;
+            for (int b = 0; b < (int)h->tbins.size(); ++b) {
+                const BinInfo& e = h->tbins[b];
+                if (e.prec != (sel == 0 ? 16 : 32) || e.W * e.R < rows) continue;
+                const double cost = (double)e.W * e.R * (m + e.W - 1);
+                if (best < 0 || cost < best_cost) { best = b; best_cost = cost; }
+            }
+            if (best < 0) return false;
+            lut[sel * kLutRows + k] = (int8_t)best;
         }
-        if (best < 0) return false;
-        lut[k] = (int8_t)best;
-    }
     h->tresident.assign(h->tbins.size(), 1);
     for (size_t b = 0; b < h->tbins.size(); ++b) {
         int per_cu = 0;
-        const TraceFn fn = trace_kernel(h->tbins[b].W, h->tbins[b].R);
+        const TraceFn fn = trace_kernel(h->tbins[b].prec, h->tbins[b].W, h->tbins[b].R);
         if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)fn, kBlock, 0) != hipSuccess)
             return false;
         h->tresident[b] = std::max(1, per_cu) * std::max(1, h->n_cu);
     }
     bool ok = hipMalloc(&h->d_tbins, kMaxBins * sizeof(BinInfo)) == hipSuccess &&
-              hipMalloc(&h->d_tlut, kLutRows) == hipSuccess &&
+              hipMalloc(&h->d_tlut, 2 * kLutRows) == hipSuccess &&
               hipHostMalloc(&h->h_i64, 16, hipHostMallocDefault) == hipSuccess &&
               hipMemcpy(h->d_tbins, h->tbins.data(), h->tbins.size() * sizeof(BinInfo), hipMemcpyHostToDevice) ==
                   hipSuccess &&
-              hipMemcpy(h->d_tlut, lut.data(), kLutRows, hipMemcpyHostToDevice) == hipSuccess;
+              hipMemcpy(h->d_tlut, lut.data(), 2 * kLutRows, hipMemcpyHostToDevice) == hipSuccess;
     for (int k = 0; ok && k < 4; ++k) ok = hipEventCreate(&h->tev[k]) == hipSuccess;
     return ok;
 }
@@ -1005,6 +1007,7 @@ static int trace_paths(sw_handle* h, const sw_batch* batch, const sw_scheme* sch
     memset(&T, 0, sizeof(T));
     T.rec_off = h->d_rec_off;
     T.lut = h->d_tlut;
+    T.i16_limit = h->opt_precision == 32 ? -1 : kI16Limit;
     T.bins = h->d_tbins;
     T.n_bins = n_tb;
     T.chunk_bytes = 1;
@@ -1060,7 +1063,7 @@ static int trace_paths(sw_handle* h, const sw_batch* batch, const sw_scheme* sch
             const int blocks = (int)std::min<int64_t>(need, h->tresident[b]);
             set_range(K, b, 0);
             if (per_bin) HIP_TRY(h, hipEventRecord(h->tbin_ev[2 * b], stream));
-            hipLaunchKernelGGL(trace_kernel(e.W, e.R), dim3(blocks), dim3(kBlock), 0, stream, K, T);
+            hipLaunchKernelGGL(trace_kernel(e.prec, e.W, e.R), dim3(blocks), dim3(kBlock), 0, stream, K, T);
             HIP_TRY(h, hipGetLastError());
             if (per_bin) HIP_TRY(h, hipEventRecord(h->tbin_ev[2 * b + 1], stream));
         }
@@ -1090,7 +1093,7 @@ static int trace_paths(sw_handle* h, const sw_batch* batch, const sw_scheme* sch
         sw_bin_stat st;
         memset(&st, 0, sizeof(st));
         st.pass = 2;
-        st.precision = 32;
+        st.precision = h->tbins[b].prec;
         st.lanes = h->tbins[b].W;
         st.rows = h->tbins[b].R;
         st.pairs = (int64_t)cnt[kCtrTraceBinPairs + b];

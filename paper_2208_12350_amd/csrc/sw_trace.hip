@@ -8,15 +8,20 @@
 // traceback of the box's own local Gotoh matrices from its last cell.  Two
 // steps, per chunk of pairs:
 //
-//   1. Path sweep: the box is swept like the forward pass (one pair per
-//      W-lane group, R rows per lane, anti-diagonal steps with DPP lane
-//      shifts; int32), and every cell leaves 4 bits in a device record:
+//   1. Path sweep: the box is swept like the forward pass (W-lane groups, R
+//      rows per lane, anti-diagonal steps with DPP lane shifts; two pairs
+//      per group packed in biased int16 halves when S fits, else one pair
+//      in int32), and every cell leaves 4 bits in a device record:
 //        bits 0-1  the first valid source of H: 0 diagonal, 1 F (a query
 //                  residue over a gap), 2 E (a reference residue over a gap)
-//        bit 2     F opens here (F == H(i-1, j) - o)
-//        bit 3     E opens here (E == H(i, j-1) - o)
+//        bit 2     F does not open here (F != H(i-1, j) - o: it extends)
+//        bit 3     E does not open here (E != H(i, j-1) - o)
 //      Step t of lane l holds rows l*R .. l*R+R-1 of column t - l, so a step
-//      of the group is one coalesced store of W * R / 2 bytes.
+//      of the group is one coalesced store of W * R / 2 bytes per pair.
+//      The bits are computed without compares: for x >= y, min(x - y, 1) or
+//      min(x ^ y, 1) is 1 exactly when x != y, per 32-bit lane or per 16-bit
+//      half (v_min_u32 / v_pk_min_u16), and the source code is
+//      (h != diag) << (h != F).
 //   2. Walk: one thread per pair follows the bits back from the box's last
 //      cell, preferring at each choice the first valid option in the order
 //      above and opening a gap over extending it, and writes the path as
@@ -30,6 +35,7 @@
 
 #include "sw_device.h"
 #include "sw_internal.h"
+#include "sw_sweep.h"
 
 namespace sw {
 
@@ -66,8 +72,28 @@ __device__ __forceinline__ PairJob box_job(const KParams& P, int pair, int max_r
     return J;
 }
 
+// One lane's record of one step: NW dwords (8 rows each).
+template <int NW>
+__device__ __forceinline__ void store_record(uint32_t* rp, const uint32_t* v) {
+    if constexpr (NW == 1) {
+        rp[0] = v[0];
+    } else if constexpr (NW == 2) {
+        *reinterpret_cast<uint2*>(rp) = make_uint2(v[0], v[1]);
+    } else if constexpr (NW == 4) {
+        *reinterpret_cast<uint4*>(rp) = make_uint4(v[0], v[1], v[2], v[3]);
+    } else {
+#pragma unroll
+        for (int k = 0; k < NW; ++k) rp[k] = v[k];
+    }
+}
+
+// 1 if x != 0, else 0 (one v_min_u32)
+__device__ __forceinline__ uint32_t ne01(uint32_t x) { return x < 1u ? x : 1u; }
+// per 16-bit half: 1 if the half != 0, else 0 (one v_pk_min_u16)
+__device__ __forceinline__ u16x2 pk_ne01(u16x2 x) { return __builtin_elementwise_min(x, pk(0x00010001u)); }
+
 // Path sweep of the wave item order[first .. first+count), one pair per
-// W-lane group.
+// W-lane group, int32.
 template <int W, int R>
 __device__ __forceinline__ void sweep_trace(const KParams& P, const TraceArgs& T, const SchemeLds& S,
                                             uint16_t* wbuf, int first, int count, int lane) {
@@ -151,10 +177,12 @@ __device__ __forceinline__ void sweep_trace(const KParams& P, const TraceArgs& T
                 F = imax(F - ge, Hmu);
                 const int d = diag + sc[r];
                 const int h = imax(imax(d, E[r]), F);
-                const uint32_t code = h == d ? 0u : (h == F ? 1u : 2u);
-                const uint32_t fo = F == Hmu ? 4u : 0u;
-                const uint32_t eo = E[r] == sat_sub(H[r], go) ? 8u : 0u;
-                wv[r / 8] |= (code | fo | eo) << (4 * (r % 8));
+                const uint32_t nd = ne01((uint32_t)(h ^ d));
+                const uint32_t nf = ne01((uint32_t)(h ^ F));
+                const uint32_t fx = ne01((uint32_t)(F - Hmu));
+                const uint32_t ex = ne01((uint32_t)(E[r] - sat_sub(H[r], go)));
+                const uint32_t nib = ((nd << nf) | (fx << 2)) | (ex << 3);
+                wv[r / 8] |= nib << (4 * (r % 8));
                 sc[r] = S.mat[bb_next + a[r]];
                 diag = H[r];
                 H[r] = h;
@@ -165,16 +193,7 @@ __device__ __forceinline__ void sweep_trace(const KParams& P, const TraceArgs& T
             Flast = F;
             bb_next = bb2;
             if (t0 + tt < my_steps) {
-                if constexpr (NW == 1) {
-                    rp[0] = wv[0];
-                } else if constexpr (NW == 2) {
-                    *reinterpret_cast<uint2*>(rp) = make_uint2(wv[0], wv[1]);
-                } else if constexpr (NW == 4) {
-                    *reinterpret_cast<uint4*>(rp) = make_uint4(wv[0], wv[1], wv[2], wv[3]);
-                } else {
-#pragma unroll
-                    for (int k = 0; k < NW; ++k) rp[k] = wv[k];
-                }
+                store_record<NW>(rp, wv);
                 rp += W * NW;
             }
         }
@@ -190,17 +209,182 @@ __device__ __forceinline__ void sweep_trace(const KParams& P, const TraceArgs& T
     }
 }
 
+// Record of one pair of the packed path sweep: its byte offset in the
+// workspace, checked against the chunk; nullptr for no job.
+__device__ __forceinline__ uint32_t* trace_record(const KParams& P, const TraceArgs& T, int pair, PairJob& J, int W,
+                                                  int R) {
+    if (J.m <= 0) return nullptr;
+    const int64_t off = T.rec_off[pair] - (int64_t)T.chunk * T.chunk_bytes;
+    const int64_t bytes = trace_record_bytes(W, R, J.m);
+    if (off < 0 || off + bytes > T.ws_bytes || (off & 15) != 0) {
+        atomicOr(&P.flags[kFlagInternal], 1);
+        J.n = 0; J.m = 0;
+        return nullptr;
+    }
+    return reinterpret_cast<uint32_t*>(T.ws + off);
+}
+
+// Path sweep of the wave item, two pairs per W-lane group packed in int16
+// halves (pair A low, pair B high), biased by kI16Bias as in the packed
+// score sweep: a pair runs here when S <= kI16Limit, which bounds every
+// value of its box.  The 4-bit codes of rows 4q..4q+3 of both pairs build up
+// in one register (pair A in the low half); two v_perm_b32 split each
+// 8 rows into pair A's and pair B's record dword.
+template <int W, int R>
+__device__ __forceinline__ void sweep_trace_i16(const KParams& P, const TraceArgs& T, const SchemeLds& S,
+                                                uint16_t* wbuf, int first, int count, int lane) {
+    static_assert(R % 8 == 0 && R >= 8 && R <= 32, "a lane's record of one step is whole dwords of 8 rows");
+    constexpr int NW = R / 8;
+    constexpr uint32_t K = kI16Bias;
+    constexpr uint32_t K2 = K | (K << 16);
+    using Stager = RefStager<W>;
+    const int g = lane / W;
+    const int l = lane % W;
+
+    const int slot = g * 2;
+    const int pairA = slot < count ? P.order[first + slot] : -1;
+    const int pairB = slot + 1 < count ? P.order[first + slot + 1] : -1;
+    PairJob JA = box_job(P, pairA, W * R);
+    PairJob JB = box_job(P, pairB, W * R);
+    uint32_t* recA = trace_record(P, T, pairA, JA, W, R);
+    uint32_t* recB = trace_record(P, T, pairB, JB, W, R);
+    const int stepsA = JA.m > 0 ? JA.m + W - 1 : 0;
+    const int stepsB = JB.m > 0 ? JB.m + W - 1 : 0;
+    int mmax = imax(JA.m, JB.m);
+    for (int off = 32; off > 0; off >>= 1) mmax = imax(mmax, __shfl_xor(mmax, off));
+    const int steps = __builtin_amdgcn_readfirstlane(mmax > 0 ? mmax + W - 1 : 0);
+
+    uint16_t* bufA = wbuf + (g * 2) * Stager::kBuf;
+    uint16_t* bufB = bufA + Stager::kBuf;
+    Stager stA, stB;
+    stA.load(P.refs, JA, P.order, 0, l);
+    stB.load(P.refs, JB, P.order, 0, l);
+    const int AA = S.alphabet[JA.sid], AB = S.alphabet[JB.sid];
+    uint32_t apk[R];
+    {
+        int rawA[R], rawB[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int i = l * R + r;
+            const int iA = i < JA.n ? i : (JA.n > 0 ? JA.n - 1 : 0);
+            const int iB = i < JB.n ? i : (JB.n > 0 ? JB.n - 1 : 0);
+            const uint8_t* pA = JA.n > 0 ? P.queries + JA.qbase + iA : reinterpret_cast<const uint8_t*>(P.order);
+            const uint8_t* pB = JB.n > 0 ? P.queries + JB.qbase + iB : reinterpret_cast<const uint8_t*>(P.order);
+            rawA[r] = *pA;
+            rawB[r] = *pB;
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int i = l * R + r;
+            const uint32_t a = (i < JA.n && rawA[r] < AA) ? rawA[r] : kPad;
+            const uint32_t b = (i < JB.n && rawB[r] < AB) ? rawB[r] : kPad;
+            apk[r] = a | (b << 16);
+        }
+    }
+    bool bad = false;   // residues were checked by the score passes
+    stA.store(bufA, JA, AA, 0, l, bad);
+    stB.store(bufB, JB, AB, 0, l, bad);
+    const u16x2 go2 = pk((uint32_t)S.gap_open[JA.sid] | ((uint32_t)S.gap_open[JB.sid] << 16));
+    const u16x2 ge2 = pk((uint32_t)S.gap_extend[JA.sid] | ((uint32_t)S.gap_extend[JB.sid] << 16));
+    const u16x2 zero = pk(K2);
+    wave_lds_sync();
+
+    u16x2 H[R], E[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) { H[r] = zero; E[r] = zero; }
+    uint32_t Hlast = K2, Flast = K2, Hup_prev = K2;
+    const uint16_t* rblA = bufA + W - l;
+    const uint16_t* rblB = bufB + W - l;
+    u16x2 sc[R];
+    int bbA_next = rblA[1], bbB_next = rblB[1];
+    {
+        const int a0 = rblA[0], b0 = rblB[0];
+#pragma unroll
+        for (int r = 0; r < R; ++r) sc[r] = load_scores(S.mat, a0 + (int)(apk[r] & 0xFFFF), b0 + (int)(apk[r] >> 16));
+    }
+    uint32_t* rpA = recA ? recA + l * NW : nullptr;
+    uint32_t* rpB = recB ? recB + l * NW : nullptr;
+    for (int t0 = 0; t0 < steps; t0 += kChunk) {
+        const bool more = t0 + kChunk < steps;
+        if (more) {
+            stA.load(P.refs, JA, P.order, t0 + kChunk, l);
+            stB.load(P.refs, JB, P.order, t0 + kChunk, l);
+        }
+        const int tn = __builtin_amdgcn_readfirstlane(steps - t0 < kChunk ? steps - t0 : kChunk);
+        for (int tt = 0; tt < tn; ++tt) {
+            const int bbA2 = rblA[tt + 2];
+            const int bbB2 = rblB[tt + 2];
+            const u16x2 Hup = pk((uint32_t)shift_in_group<W>((int)Hlast, (int)K2));
+            const u16x2 Fup = pk((uint32_t)shift_in_group_zero<W>((int)Flast));
+            u16x2 diag = pk(Hup_prev);
+            Hup_prev = u32(Hup);
+            u16x2 Hmu = pk_sat_sub(Hup, go2);
+            u16x2 F = Fup;
+            uint32_t w[R / 4];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                F = pk_max3(pk_sat_sub(F, ge2), Hmu, zero);
+                const u16x2 d = diag + sc[r];
+                const u16x2 h = pk_max3(d, E[r], F);
+                const u16x2 nd = pk_ne01(h ^ d);
+                const u16x2 nf = pk_ne01(h ^ F);
+                const u16x2 fx = pk_ne01(F ^ Hmu);
+                const u16x2 ex = pk_ne01(E[r] ^ pk_sat_sub(H[r], go2));
+                const uint32_t nib = (u32(nd << nf) | (u32(fx) << 2)) | (u32(ex) << 3);
+                if (r % 4 == 0) w[r / 4] = nib;
+                else w[r / 4] |= nib << (4 * (r % 4));
+                sc[r] = load_scores(S.mat, bbA_next + (int)(apk[r] & 0xFFFF), bbB_next + (int)(apk[r] >> 16));
+                diag = H[r];
+                H[r] = h;
+                Hmu = pk_sat_sub(h, go2);
+                E[r] = pk_max3(pk_sat_sub(E[r], ge2), Hmu, zero);
+            }
+            Hlast = u32(H[R - 1]);
+            Flast = u32(F);
+            bbA_next = bbA2;
+            bbB_next = bbB2;
+            uint32_t va[NW], vb[NW];
+#pragma unroll
+            for (int k = 0; k < NW; ++k) {
+                va[k] = __builtin_amdgcn_perm(w[2 * k + 1], w[2 * k], 0x05040100u);
+                vb[k] = __builtin_amdgcn_perm(w[2 * k + 1], w[2 * k], 0x07060302u);
+            }
+            const int t = t0 + tt;
+            if (t < stepsA) {
+                store_record<NW>(rpA, va);
+                rpA += W * NW;
+            }
+            if (t < stepsB) {
+                store_record<NW>(rpB, vb);
+                rpB += W * NW;
+            }
+        }
+        if (more) {
+            wave_lds_sync();
+            stA.store(bufA, JA, AA, t0 + kChunk, l, bad);
+            stB.store(bufB, JB, AB, t0 + kChunk, l, bad);
+            wave_lds_sync();
+            bbA_next = rblA[1];
+            bbB_next = rblB[1];
+            const int a0 = rblA[0], b0 = rblB[0];
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                sc[r] = load_scores(S.mat, a0 + (int)(apk[r] & 0xFFFF), b0 + (int)(apk[r] >> 16));
+        }
+    }
+}
+
 // LDS reference buffer of one wavefront (16-bit entries): four 16-lane
-// groups, the widest layout.
-constexpr int kTraceWaveBuf = 4 * RefStager<16>::kBuf;
+// groups of two packed pairs, the widest layout.
+constexpr int kTraceWaveBuf = 8 * RefStager<16>::kBuf;
 
 // Work-queue kernel of one path-sweep shape (same fetch loop as the score
 // sweeps' queue kernels).
-template <int W, int R>
+template <int PREC, int W, int R>
 __global__ __launch_bounds__(kBlock) void sw_trace_kernel(KParams P, TraceArgs T) {
     __shared__ __attribute__((aligned(16))) SchemeLds L;
     __shared__ uint16_t wbufs[kWavesPerBlock * kTraceWaveBuf];
-    constexpr int kPPW = 64 / W;
+    constexpr int kPPW = (64 / W) * (PREC == 16 ? 2 : 1);
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
@@ -227,34 +411,45 @@ __global__ __launch_bounds__(kBlock) void sw_trace_kernel(KParams P, TraceArgs T
         const bool valid = first >= 0 && count >= 1 && count <= kPPW && first + count <= n_pairs;
         if (valid) {
             wave_lds_sync();
-            sweep_trace<W, R>(P, T, L, wbuf, first, count, lane);
+            if constexpr (PREC == 16)
+                sweep_trace_i16<W, R>(P, T, L, wbuf, first, count, lane);
+            else
+                sweep_trace<W, R>(P, T, L, wbuf, first, count, lane);
         } else {
             atomicOr(&P.flags[kFlagInternal], 1);
         }
     }
 }
 
-#define SW_TRACE_SHAPES(X) X(16, 8) X(16, 16) X(32, 16) X(64, 16) X(64, 24) X(64, 32)
+#define SW_TRACE_SHAPES(X, P) X(P, 16, 8) X(P, 16, 16) X(P, 32, 16) X(P, 64, 16) X(P, 64, 24) X(P, 64, 32)
 
 namespace {
-struct TraceEntry { int W, R; TraceFn fn; };
-#define SW_TRACE_ENTRY(W, R) {W, R, &sw_trace_kernel<W, R>},
-const TraceEntry kTraceKernels[] = {SW_TRACE_SHAPES(SW_TRACE_ENTRY)};
+struct TraceEntry { int prec, W, R; TraceFn fn; };
+#define SW_TRACE_ENTRY(P, W, R) {P, W, R, &sw_trace_kernel<P, W, R>},
+const TraceEntry kTraceKernels[] = {SW_TRACE_SHAPES(SW_TRACE_ENTRY, 16) SW_TRACE_SHAPES(SW_TRACE_ENTRY, 32)};
 #undef SW_TRACE_ENTRY
 constexpr int kNumTrace = sizeof(kTraceKernels) / sizeof(kTraceKernels[0]);
 ShapeDesc g_trace_shapes[kNumTrace];
 }  // namespace
 
 const ShapeDesc* trace_shapes(int* n) {
-    for (int k = 0; k < kNumTrace; ++k) g_trace_shapes[k] = {32, kTraceKernels[k].W, kTraceKernels[k].R};
+    for (int k = 0; k < kNumTrace; ++k)
+        g_trace_shapes[k] = {kTraceKernels[k].prec, kTraceKernels[k].W, kTraceKernels[k].R};
     *n = kNumTrace;
     return g_trace_shapes;
 }
 
-TraceFn trace_kernel(int W, int R) {
+TraceFn trace_kernel(int prec, int W, int R) {
     for (int k = 0; k < kNumTrace; ++k)
-        if (kTraceKernels[k].W == W && kTraceKernels[k].R == R) return kTraceKernels[k].fn;
+        if (kTraceKernels[k].prec == prec && kTraceKernels[k].W == W && kTraceKernels[k].R == R)
+            return kTraceKernels[k].fn;
     return nullptr;
+}
+
+// Path-sweep bin of a pair: packed int16 when its score allows, by box rows.
+__device__ __forceinline__ int trace_bin(const TraceArgs& T, int score, int rows) {
+    const int sel = score <= T.i16_limit ? 0 : 1;
+    return T.lut[sel * kLutRows + (rows - 1) / 16];
 }
 
 // ---- record sizes and offsets ----------------------------------------------
@@ -306,7 +501,7 @@ __global__ __launch_bounds__(kScanThreads) void sw_trace_size_kernel(KParams P, 
                 r.r_end >= nr || cols > SW_MAX_REF) {
                 atomicOr(&P.flags[kFlagInternal], 1);
             } else {
-                const int b = T.lut[(rows - 1) / 16];
+                const int b = trace_bin(T, r.score, rows);
                 if (b < 0 || b >= T.n_bins || T.bins[b].W * T.bins[b].R < rows) {
                     atomicOr(&P.flags[kFlagInternal], 1);
                 } else {
@@ -388,7 +583,7 @@ __global__ void sw_trace_classify_kernel(KParams P, TraceArgs T, int32_t* keys, 
             const int rows = r.q_end - r.q_start + 1, cols = r.r_end - r.r_start + 1;
             // sizes were validated when the records were laid out
             if (rows >= 1 && rows <= SW_MAX_QUERY && cols >= 1 && cols <= SW_MAX_REF) {
-                const int b = T.lut[(rows - 1) / 16];
+                const int b = trace_bin(T, r.score, rows);
                 if (b >= 0 && b < T.n_bins) {
                     key = b * kMBuckets + kMHalf + (kMHalf - 1 - m_bucket(cols));
                     atomicAdd(&s_cells[b], (unsigned long long)rows * (unsigned long long)cols);
@@ -434,7 +629,7 @@ __global__ void sw_trace_walk_kernel(KParams P, TraceArgs T, const int64_t* path
     const int64_t off = T.rec_off[i];
     if (off / T.chunk_bytes != T.chunk) return;
     const int rows = r.q_end - r.q_start + 1, cols = r.r_end - r.r_start + 1;
-    const int b = (rows >= 1 && rows <= SW_MAX_QUERY) ? T.lut[(rows - 1) / 16] : -1;
+    const int b = (rows >= 1 && rows <= SW_MAX_QUERY) ? trace_bin(T, r.score, rows) : -1;
     const int64_t beg = path_off[i], end = path_off[i + 1];
     if (b < 0 || b >= T.n_bins || cols < 1 || end < beg) {
         atomicOr(&P.flags[end < beg ? kFlagPathRoom : kFlagInternal], 1);
@@ -473,11 +668,11 @@ __global__ void sw_trace_walk_kernel(KParams P, TraceArgs T, const int64_t* path
             --x; --y;
         } else if (state == 1) {
             o = 1u;
-            state = (nib & 4u) ? 0 : 1;
+            state = (nib & 4u) ? 1 : 0;
             --x;
         } else {
             o = 2u;
-            state = (nib & 8u) ? 0 : 2;
+            state = (nib & 8u) ? 2 : 0;
             --y;
         }
         if (o == op) {

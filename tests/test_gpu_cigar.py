@@ -209,3 +209,36 @@ def test_small_room_is_reported(aligner):
     cl = cl.cpu().numpy()
     assert np.array_equal(cl == -1, onr > 2)
     assert np.array_equal(cl[onr <= 2], onr[onr <= 2])
+
+
+def test_int16_and_int32_path_sweeps_agree(aligner):
+    # the packed int16 path sweep takes every pair whose score fits; forcing
+    # int32 must give the same paths
+    from paper_2208_12350_amd.binding import Aligner
+    b = W.make_workload("mixed", n_pairs=4000)
+    packed = gpu_paths(aligner, b)
+    wide = Aligner(0, precision=32)
+    try:
+        plain = gpu_paths(wide, b)
+    finally:
+        wide.close()
+    for x, y in zip(packed, plain):
+        assert np.array_equal(x, y)
+
+
+def test_large_scores_take_the_int32_path_sweep(aligner):
+    rng = np.random.default_rng(5)
+    M = np.full((4, 4), -60, np.int8)
+    np.fill_diagonal(M, 100)
+    sc = W.Scheme(M, 120, 20)
+    pairs = []
+    for n in (500, 700, 900, 1200):
+        q = rng.integers(0, 4, size=n).astype(np.uint8)
+        r = q.copy()
+        r[rng.random(n) < 0.05] = 0
+        r = np.concatenate([rng.integers(0, 4, size=30), r[: n // 2], rng.integers(0, 4, size=3), r[n // 2:]])
+        pairs.append((q, r.astype(np.uint8)))
+    b = W.from_pairs(pairs, [0] * len(pairs), [sc])
+    gpu = gpu_paths(aligner, b)
+    assert np.all(gpu[0][:, 0] > 30592)
+    assert_paths_equal(b, gpu)

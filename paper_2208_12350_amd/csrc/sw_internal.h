@@ -211,13 +211,16 @@ struct TraceArgs {
 using TraceFn = void (*)(KParams, TraceArgs);
 const ShapeDesc* trace_shapes(int* n);
 TraceFn trace_kernel(int prec, int W, int R);
-// Record bytes of a box of m columns on shape (W, R): (m + W - 1) sweep
-// steps, each W lanes x R rows x 4 bits.
+// Records are written in blocks of kStage sweep steps.
+constexpr int kStage = 8;
+// Record bytes of a box of m columns on shape (W, R): m + W - 1 sweep steps
+// rounded up to whole blocks, each step W lanes x R rows x 4 bits.
 __host__ __device__ inline int64_t trace_record_bytes(int W, int R, int64_t m) {
-    return (m + W - 1) * (int64_t)W * R / 2;
+    const int64_t steps = (m + W - 1 + kStage - 1) / kStage * kStage;
+    return steps * (int64_t)W * R / 2;
 }
 // The largest record any pair can need (64 lanes x 32 rows, the longest reference).
-constexpr int64_t kMaxRecordBytes = (int64_t)(SW_MAX_REF + 63) * 64 * 32 / 2;
+constexpr int64_t kMaxRecordBytes = (int64_t)(SW_MAX_REF + 63 + kStage - 1) / kStage * kStage * 64 * 32 / 2;
 
 hipError_t launch_trace_sizes(const KParams& P, const TraceArgs& T, int64_t cap, int64_t* rec_off,
                               int64_t* block_sums, unsigned long long* counters, hipStream_t s);

@@ -16,8 +16,14 @@
 //                  residue over a gap), 2 E (a reference residue over a gap)
 //        bit 2     F does not open here (F != H(i-1, j) - o: it extends)
 //        bit 3     E does not open here (E != H(i, j-1) - o)
-//      Step t of lane l holds rows l*R .. l*R+R-1 of column t - l, so a step
-//      of the group is one coalesced store of W * R / 2 bytes per pair.
+//      Step t of lane l holds rows l*R .. l*R+R-1 of column t - l.  Records
+//      are laid out in blocks of kStage steps: block b of lane l is the
+//      4R bytes at (b * W + l) * 4R, step t = 8b + s at byte s * R/2, row k
+//      in byte k/2 (low nibble for even k).  The sweep stages a block's
+//      steps in LDS and writes it out as full 16-byte chunks per lane (a
+//      pair's block of all W lanes is one contiguous W * 4R bytes); the
+//      walk moves mostly along one lane's steps, so one block read serves
+//      up to 8 of its steps.
 //      The bits are computed without compares: for x >= y, min(x - y, 1) or
 //      min(x ^ y, 1) is 1 exactly when x != y, per 32-bit lane or per 16-bit
 //      half (v_min_u32 / v_pk_min_u16), and the source code is
@@ -72,33 +78,74 @@ __device__ __forceinline__ PairJob box_job(const KParams& P, int pair, int max_r
     return J;
 }
 
-// One lane's record of one step: NW dwords (8 rows each).
-template <int NW>
-__device__ __forceinline__ void store_record(uint32_t* rp, const uint32_t* v) {
-    if constexpr (NW == 1) {
-        rp[0] = v[0];
-    } else if constexpr (NW == 2) {
-        *reinterpret_cast<uint2*>(rp) = make_uint2(v[0], v[1]);
-    } else if constexpr (NW == 4) {
-        *reinterpret_cast<uint4*>(rp) = make_uint4(v[0], v[1], v[2], v[3]);
-    } else {
+// Record staging of one wavefront: the steps of the current block of each
+// of its PPW pairs, step-major in LDS ([step][pair][lane][NW dwords], so the
+// per-step writes of a wavefront are contiguous), copied out in the
+// lane-major record layout when the block is complete.
+template <int W, int R, int PPW>
+struct RecordStage {
+    static constexpr int NW = R / 8;                        // dwords per lane and step
+    static constexpr int kDwords = kStage * PPW * W * NW;   // per wavefront
+    uint32_t* lds;
+
+    __device__ __forceinline__ void put(int p, int l, int t, const uint32_t* v) const {
+        uint32_t* d = lds + (((t & (kStage - 1)) * PPW + p) * W + l) * NW;
 #pragma unroll
-        for (int k = 0; k < NW; ++k) rp[k] = v[k];
+        for (int k = 0; k < NW; ++k) d[k] = v[k];
     }
+    // Copy block b of pair p (all W lanes, W * R dwords) to its record
+    // (lane-major: dword d = l * R + s * NW + k), 16 bytes per lane at a time.
+    __device__ __forceinline__ void flush(int p, uint32_t* rec, int b, int lane) const {
+        uint32_t* dst = rec + (int64_t)b * W * R;
+#pragma unroll
+        for (int c0 = 0; c0 < W * R / 4; c0 += 64) {
+            const int c = c0 + lane;
+            if (W * R / 4 >= c0 + 64 || c < W * R / 4) {
+                uint32_t v[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int d = 4 * c + q;
+                    const int l = d / R, rem = d % R;
+                    v[q] = lds[((rem / NW) * PPW + p) * W * NW + l * NW + rem % NW];
+                }
+                *reinterpret_cast<uint4*>(dst + 4 * c) = make_uint4(v[0], v[1], v[2], v[3]);
+            }
+        }
+    }
+};
+
+__device__ __forceinline__ uint32_t* readlane_ptr(uint32_t* p, int lane) {
+    const uint64_t v = reinterpret_cast<uint64_t>(p);
+    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)v, lane);
+    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(v >> 32), lane);
+    return reinterpret_cast<uint32_t*>(((uint64_t)hi << 32) | lo);
 }
 
-// 1 if x != 0, else 0 (one v_min_u32)
-__device__ __forceinline__ uint32_t ne01(uint32_t x) { return x < 1u ? x : 1u; }
+// 1 if x != 0, else 0: one v_min_u32.  Written as an instruction because
+// the compiler otherwise turns min(x, 1) into a compare and a select (two
+// instructions with a wait state between them, and per 16-bit half in the
+// packed form).
+__device__ __forceinline__ uint32_t ne01(uint32_t x) {
+    uint32_t r;
+    asm("v_min_u32 %0, 1, %1" : "=v"(r) : "v"(x));
+    return r;
+}
 // per 16-bit half: 1 if the half != 0, else 0 (one v_pk_min_u16)
-__device__ __forceinline__ u16x2 pk_ne01(u16x2 x) { return __builtin_elementwise_min(x, pk(0x00010001u)); }
+__device__ __forceinline__ u16x2 pk_ne01(u16x2 x) {
+    uint32_t r;
+    asm("v_pk_min_u16 %0, %1, %2" : "=v"(r) : "v"(u32(x)), "s"(0x00010001u));
+    return pk(r);
+}
 
 // Path sweep of the wave item order[first .. first+count), one pair per
 // W-lane group, int32.
 template <int W, int R>
 __device__ __forceinline__ void sweep_trace(const KParams& P, const TraceArgs& T, const SchemeLds& S,
-                                            uint16_t* wbuf, int first, int count, int lane) {
+                                            uint16_t* wbuf, uint32_t* stg, int first, int count, int lane) {
     static_assert(R % 8 == 0 && R >= 8 && R <= 32, "a lane's record of one step is whole dwords of 8 rows");
     constexpr int NW = R / 8;
+    constexpr int G = 64 / W;
+    const RecordStage<W, R, G> rs{stg};
     using Stager = RefStager<W>;
     const int g = lane / W;
     const int l = lane % W;
@@ -156,7 +203,6 @@ __device__ __forceinline__ void sweep_trace(const KParams& P, const TraceArgs& T
 #pragma unroll
         for (int r = 0; r < R; ++r) sc[r] = S.mat[bb0 + a[r]];
     }
-    uint32_t* rp = rec ? rec + l * NW : nullptr;   // this lane's record of step 0
     for (int t0 = 0; t0 < steps; t0 += kChunk) {
         const bool more = t0 + kChunk < steps;
         if (more) stage.load(P.refs, J, P.order, t0 + kChunk, l);
@@ -192,9 +238,17 @@ __device__ __forceinline__ void sweep_trace(const KParams& P, const TraceArgs& T
             Hlast = H[R - 1];
             Flast = F;
             bb_next = bb2;
-            if (t0 + tt < my_steps) {
-                store_record<NW>(rp, wv);
-                rp += W * NW;
+            const int t = t0 + tt;
+            rs.put(g, l, t, wv);
+            if ((t & (kStage - 1)) == kStage - 1 || t == steps - 1) {
+                wave_lds_sync();
+#pragma unroll
+                for (int p = 0; p < G; ++p) {
+                    uint32_t* rp = readlane_ptr(rec, p * W);
+                    const int sp = __builtin_amdgcn_readlane(my_steps, p * W);
+                    if (rp && (t & ~(kStage - 1)) < sp) rs.flush(p, rp, t / kStage, lane);
+                }
+                wave_lds_sync();
             }
         }
         if (more) {
@@ -232,9 +286,11 @@ __device__ __forceinline__ uint32_t* trace_record(const KParams& P, const TraceA
 // 8 rows into pair A's and pair B's record dword.
 template <int W, int R>
 __device__ __forceinline__ void sweep_trace_i16(const KParams& P, const TraceArgs& T, const SchemeLds& S,
-                                                uint16_t* wbuf, int first, int count, int lane) {
+                                                uint16_t* wbuf, uint32_t* stg, int first, int count, int lane) {
     static_assert(R % 8 == 0 && R >= 8 && R <= 32, "a lane's record of one step is whole dwords of 8 rows");
     constexpr int NW = R / 8;
+    constexpr int G = 64 / W;
+    const RecordStage<W, R, 2 * G> rs{stg};
     constexpr uint32_t K = kI16Bias;
     constexpr uint32_t K2 = K | (K << 16);
     using Stager = RefStager<W>;
@@ -302,8 +358,6 @@ __device__ __forceinline__ void sweep_trace_i16(const KParams& P, const TraceArg
 #pragma unroll
         for (int r = 0; r < R; ++r) sc[r] = load_scores(S.mat, a0 + (int)(apk[r] & 0xFFFF), b0 + (int)(apk[r] >> 16));
     }
-    uint32_t* rpA = recA ? recA + l * NW : nullptr;
-    uint32_t* rpB = recB ? recB + l * NW : nullptr;
     for (int t0 = 0; t0 < steps; t0 += kChunk) {
         const bool more = t0 + kChunk < steps;
         if (more) {
@@ -350,13 +404,17 @@ __device__ __forceinline__ void sweep_trace_i16(const KParams& P, const TraceArg
                 vb[k] = __builtin_amdgcn_perm(w[2 * k + 1], w[2 * k], 0x07060302u);
             }
             const int t = t0 + tt;
-            if (t < stepsA) {
-                store_record<NW>(rpA, va);
-                rpA += W * NW;
-            }
-            if (t < stepsB) {
-                store_record<NW>(rpB, vb);
-                rpB += W * NW;
+            rs.put(2 * g, l, t, va);
+            rs.put(2 * g + 1, l, t, vb);
+            if ((t & (kStage - 1)) == kStage - 1 || t == steps - 1) {
+                wave_lds_sync();
+#pragma unroll
+                for (int p = 0; p < 2 * G; ++p) {
+                    uint32_t* rp = readlane_ptr((p & 1) ? recB : recA, (p / 2) * W);
+                    const int sp = __builtin_amdgcn_readlane((p & 1) ? stepsB : stepsA, (p / 2) * W);
+                    if (rp && (t & ~(kStage - 1)) < sp) rs.flush(p, rp, t / kStage, lane);
+                }
+                wave_lds_sync();
             }
         }
         if (more) {
@@ -382,9 +440,11 @@ constexpr int kTraceWaveBuf = 8 * RefStager<16>::kBuf;
 // sweeps' queue kernels).
 template <int PREC, int W, int R>
 __global__ __launch_bounds__(kBlock) void sw_trace_kernel(KParams P, TraceArgs T) {
+    constexpr int kPPW = (64 / W) * (PREC == 16 ? 2 : 1);
+    constexpr int kStageDwords = RecordStage<W, R, kPPW>::kDwords;
     __shared__ __attribute__((aligned(16))) SchemeLds L;
     __shared__ uint16_t wbufs[kWavesPerBlock * kTraceWaveBuf];
-    constexpr int kPPW = (64 / W) * (PREC == 16 ? 2 : 1);
+    __shared__ __attribute__((aligned(16))) uint32_t stages[kWavesPerBlock * kStageDwords];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
@@ -412,9 +472,9 @@ __global__ __launch_bounds__(kBlock) void sw_trace_kernel(KParams P, TraceArgs T
         if (valid) {
             wave_lds_sync();
             if constexpr (PREC == 16)
-                sweep_trace_i16<W, R>(P, T, L, wbuf, first, count, lane);
+                sweep_trace_i16<W, R>(P, T, L, wbuf, stages + wave * kStageDwords, first, count, lane);
             else
-                sweep_trace<W, R>(P, T, L, wbuf, first, count, lane);
+                sweep_trace<W, R>(P, T, L, wbuf, stages + wave * kStageDwords, first, count, lane);
         } else {
             atomicOr(&P.flags[kFlagInternal], 1);
         }
@@ -617,8 +677,28 @@ hipError_t launch_trace_classify(const KParams& P, const TraceArgs& T, int64_t c
 // to its start.  A path that leaves its box or does not end at the box's
 // first cell is an internal error; one that needs more runs than its room
 // sets kFlagPathRoom.  Either way the pair's run count becomes -1.
-__global__ void sw_trace_walk_kernel(KParams P, TraceArgs T, const int64_t* path_off, uint32_t* path,
-                                     int32_t* path_len) {
+constexpr int kWalkSlot = 33;   // dwords per thread: a block of up to 32, padded against bank conflicts
+
+// The 16 residues around a position, read as one aligned 16-byte load (an
+// aligned 16-byte block never crosses a page, so it is readable whenever
+// the residue itself is); a walk moves backwards through each sequence, so
+// one load serves up to 16 of its steps.
+__device__ __forceinline__ uint32_t window_at(const uint8_t* seq, int x, uintptr_t& base, uint32_t& w0, uint32_t& w1,
+                                              uint32_t& w2, uint32_t& w3) {
+    const uintptr_t a = reinterpret_cast<uintptr_t>(seq + x);
+    const uintptr_t b = a & ~(uintptr_t)15;
+    if (b != base) {
+        const uint4 v = *reinterpret_cast<const uint4*>(b);
+        w0 = v.x; w1 = v.y; w2 = v.z; w3 = v.w;
+        base = b;
+    }
+    const uint32_t o = (uint32_t)(a - b);
+    const uint32_t w = o < 8 ? (o < 4 ? w0 : w1) : (o < 12 ? w2 : w3);
+    return (w >> (8 * (o & 3))) & 0xFFu;
+}
+
+__global__ __launch_bounds__(256) void sw_trace_walk_kernel(KParams P, TraceArgs T, const int64_t* path_off,
+                                                            uint32_t* path, int32_t* path_len) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= *P.n_dev) return;
     const sw_result r = P.out[i];
@@ -643,9 +723,15 @@ __global__ void sw_trace_walk_kernel(KParams P, TraceArgs T, const int64_t* path
         path_len[i] = -1;
         return;
     }
-    const uint8_t* rec = T.ws + rel;
+    const uint32_t* rec = reinterpret_cast<const uint32_t*>(T.ws + rel);
+    // this thread's copy of the record block it reads (R dwords)
+    __shared__ uint32_t cache[256 * kWalkSlot];
+    uint32_t* slot = cache + threadIdx.x * kWalkSlot;
+    int64_t cached = -1;
     const uint8_t* qa = P.queries + P.q_beg[i] + r.q_start;
     const uint8_t* rb = P.refs + P.r_beg[i] + r.r_start;
+    uintptr_t qbase = ~(uintptr_t)0, rbase = ~(uintptr_t)0;
+    uint32_t q0 = 0, q1 = 0, q2 = 0, q3 = 0, r0 = 0, r1 = 0, r2 = 0, r3 = 0;
     const int64_t room = end - beg;
     int x = rows - 1, y = cols - 1;
     int state = 0;   // 0 = H, 1 = F (query gap), 2 = E (reference gap)
@@ -656,15 +742,25 @@ __global__ void sw_trace_walk_kernel(KParams P, TraceArgs T, const int64_t* path
     bool done = false;
     for (int64_t it = 0; it < limit && !err; ++it) {
         const int lane = x / R, rr = x - lane * R;
-        const int64_t byte = ((int64_t)(y + lane) * W + lane) * (R / 2) + (rr >> 1);
-        const uint32_t nib = (rec[byte] >> (4 * (rr & 1))) & 15u;
+        const int t = y + lane;
+        const int64_t blk = (int64_t)(t / kStage) * W + lane;
+        if (blk != cached) {
+            const uint4* src = reinterpret_cast<const uint4*>(rec + blk * R);
+            for (int q = 0; q < R / 4; ++q) {
+                const uint4 v = src[q];
+                slot[4 * q] = v.x; slot[4 * q + 1] = v.y; slot[4 * q + 2] = v.z; slot[4 * q + 3] = v.w;
+            }
+            cached = blk;
+        }
+        const int byte = (t % kStage) * (R / 2) + (rr >> 1);
+        const uint32_t nib = (slot[byte >> 2] >> (8 * (byte & 3) + 4 * (rr & 1))) & 15u;
         uint32_t o;
         if (state == 0) {
             const uint32_t code = nib & 3u;
             if (code == 1u) { state = 1; continue; }
             if (code == 2u) { state = 2; continue; }
             if (code != 0u) { err = 1; break; }
-            o = qa[x] == rb[y] ? 7u : 8u;
+            o = window_at(qa, x, qbase, q0, q1, q2, q3) == window_at(rb, y, rbase, r0, r1, r2, r3) ? 7u : 8u;
             --x; --y;
         } else if (state == 1) {
             o = 1u;

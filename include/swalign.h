@@ -131,7 +131,7 @@ const char* sw_last_error(sw_handle* h);
  *               many streams forked from (and joined back into) the
  *               caller's stream (default 4)
  *   "cigar_workspace"  device bytes for the path records of sw_align_cigar
- *               (default 8 GiB, at least about 123 MB)
+ *               (default 32 GiB, at least about 123 MB)
  * Returns SW_OK or SW_EINVAL for an unknown key / bad value. */
 int sw_set_option(sw_handle* h, const char* key, int64_t value);
 /* Read an option, or the read-only "captures" (graphs captured so far) and
@@ -205,7 +205,7 @@ int sw_last_host_timing(sw_handle* h, double* enqueue_ms, double* wait_ms);
  * cigar_len (int32[n_pairs]) are DEVICE pointers owned by the caller; a room
  * of q_len + r_len runs per pair always suffices.  The paths are found by a
  * sweep of each box that stores 4 bits per cell in a device workspace (option
- * "cigar_workspace", default 8 GiB; batches whose boxes need more are done in
+ * "cigar_workspace", default 32 GiB; batches whose boxes need more are done in
  * chunks), then a walk back per pair.  Synchronises `stream`; not captured in
  * a graph.  Errors: those of sw_align_batch; SW_EINVAL when a pair's room
  * is too small (its cigar_len is -1, the other pairs' paths are written);
@@ -216,9 +216,10 @@ int sw_align_cigar(sw_handle* h, const sw_batch* batch, const sw_scheme* schemes
 
 /* Statistics of the last sw_align_cigar call: cells of the path boxes (sum
  * of (q_end-q_start+1)*(r_end-r_start+1)), bytes of path records, chunks,
- * and with the "timing" option the device milliseconds of the box sweeps
- * and of the walks (per box-sweep shape with "timing" = 2: the entries of
- * sw_last_bin_stats with pass 2).  Any pointer may be NULL. */
+ * and with the "timing" option (which serialises the launches) the device
+ * milliseconds of the box sweeps and of the walks; the box sweeps of each
+ * shape are also the entries of sw_last_bin_stats with pass 2.  Any pointer
+ * may be NULL. */
 int sw_last_cigar_stats(sw_handle* h, int64_t* box_cells, int64_t* record_bytes, int32_t* chunks,
                         float* sweep_ms, float* walk_ms);
 

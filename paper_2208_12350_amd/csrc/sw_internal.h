@@ -207,7 +207,7 @@ struct TraceArgs {
 };
 
 // Path-sweep shapes (precision 16: two pairs per W-lane group; 32: one;
-// R a multiple of 8).
+// R a multiple of 4).
 using TraceFn = void (*)(KParams, TraceArgs);
 const ShapeDesc* trace_shapes(int* n);
 TraceFn trace_kernel(int prec, int W, int R);
@@ -224,9 +224,12 @@ constexpr int64_t kMaxRecordBytes = (int64_t)(SW_MAX_REF + 63 + kStage - 1) / kS
 
 hipError_t launch_trace_sizes(const KParams& P, const TraceArgs& T, int64_t cap, int64_t* rec_off,
                               int64_t* block_sums, unsigned long long* counters, hipStream_t s);
+// Planning of one chunk; in chunk 0 it also sets path_len = 0 for pairs
+// without an alignment.
 hipError_t launch_trace_classify(const KParams& P, const TraceArgs& T, int64_t cap, int32_t* keys,
-                                 int32_t* hist, unsigned long long* counters, hipStream_t s);
-hipError_t launch_trace_walk(const KParams& P, const TraceArgs& T, int64_t cap, const int64_t* path_off,
+                                 int32_t* hist, unsigned long long* counters, int32_t* path_len, hipStream_t s);
+// Walks of the pairs of one path-sweep bin (after the bin's sweep).
+hipError_t launch_trace_walk(const KParams& P, const TraceArgs& T, int bin, int blocks, const int64_t* path_off,
                              uint32_t* path, int32_t* path_len, hipStream_t s);
 // Blocks of the size scan for `cap` pairs (the length of block_sums minus one).
 int64_t trace_scan_blocks(int64_t cap);

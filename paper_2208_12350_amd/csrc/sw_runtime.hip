@@ -126,10 +126,9 @@ struct sw_handle {
     int64_t trace_cap = 0;
     uint8_t* d_ws = nullptr;             // path records of one chunk
     int64_t ws_alloc = 0;
-    int64_t opt_path_ws = (int64_t)8 << 30;
+    int64_t opt_path_ws = (int64_t)32 << 30;
     int64_t* h_i64 = nullptr;            // pinned
-    hipEvent_t tev[4] = {nullptr, nullptr, nullptr, nullptr};
-    std::vector<hipEvent_t> tbin_ev;     // per path-sweep bin: start, end ("timing" = 2)
+    std::vector<hipEvent_t> tbin_ev;     // per path-sweep bin: sweep start, sweep end, walk end ("timing")
     int64_t last_path_cells = 0, last_path_bytes = 0;
     int32_t last_path_chunks = 0;
     float t_path_sweep = 0.f, t_path_walk = 0.f;
@@ -391,8 +390,8 @@ static int enqueue_pass(sw_handle* h, KParams K, const ClassifyArgs& C, int64_t 
 
 // Path-sweep bins and their routing: for each precision (packed int16,
 // int32), each 16-row bucket of box rows goes to the covering shape with the
-// fewest lane-row slots for a box of twice as many columns plus 64 (as the
-// score routing's default).
+// fewest lane-row slots for a box of as many columns plus 32 (a result box
+// is about as wide as it is tall).
 static bool init_paths(sw_handle* h) {
     int n = 0;
     const ShapeDesc* sh = trace_shapes(&n);
@@ -412,7 +411,7 @@ static bool init_paths(sw_handle* h) {
     for (int sel = 0; sel < 2; ++sel)
         for (int k = 0; k < kLutRows; ++k) {
             const int rows = 16 * (k + 1);
-            const double m = 2.0 * rows + 64.0;
+            const double m = rows + 32.0;
             int best = -1;
             double best_cost = 0;
             for (int b = 0; b < (int)h->tbins.size(); ++b) {
@@ -438,7 +437,6 @@ static bool init_paths(sw_handle* h) {
               hipMemcpy(h->d_tbins, h->tbins.data(), h->tbins.size() * sizeof(BinInfo), hipMemcpyHostToDevice) ==
                   hipSuccess &&
               hipMemcpy(h->d_tlut, lut.data(), 2 * kLutRows, hipMemcpyHostToDevice) == hipSuccess;
-    for (int k = 0; ok && k < 4; ++k) ok = hipEventCreate(&h->tev[k]) == hipSuccess;
     return ok;
 }
 
@@ -528,8 +526,6 @@ void sw_destroy(sw_handle* h) {
     free_dev(h->d_items);
     free_dev(h->d_tbins); free_dev(h->d_tlut); free_dev(h->d_rec_off); free_dev(h->d_bsum); free_dev(h->d_ws);
     if (h->h_i64) (void)hipHostFree(h->h_i64);
-    for (int k = 0; k < 4; ++k)
-        if (h->tev[k]) (void)hipEventDestroy(h->tev[k]);
     for (hipEvent_t e : h->tbin_ev)
         if (e) (void)hipEventDestroy(e);
     if (h->h_mats) (void)hipHostFree(h->h_mats);
@@ -977,10 +973,9 @@ static int trace_paths(sw_handle* h, const sw_batch* batch, const sw_scheme* sch
                        hipStream_t stream) {
     const int64_t P = batch->n_pairs;
     const bool timing = h->opt_timing != 0;
-    const bool per_bin = h->opt_timing == 2;
     const int n_tb = (int)h->tbins.size();
-    if (per_bin && h->tbin_ev.empty()) {
-        h->tbin_ev.assign(2 * n_tb, nullptr);
+    if (timing && h->tbin_ev.empty()) {
+        h->tbin_ev.assign(3 * n_tb, nullptr);
         for (hipEvent_t& e : h->tbin_ev)
             if (hipEventCreate(&e) != hipSuccess) return fail(h, SW_EDEVICE, "event creation failed");
     }
@@ -1013,7 +1008,6 @@ static int trace_paths(sw_handle* h, const sw_batch* batch, const sw_scheme* sch
     T.chunk_bytes = 1;
 
     HIP_TRY(h, launch_reset(h->d_small, kSmallInts, stream));
-    if (timing) HIP_TRY(h, hipEventRecord(h->tev[0], stream));
     HIP_TRY(h, launch_trace_sizes(K, T, cap, h->d_rec_off, h->d_bsum, counters(h->d_small), stream));
     HIP_TRY(h, hipMemcpyAsync(h->h_i64, h->d_rec_off + P, 8, hipMemcpyDeviceToHost, stream));
     HIP_TRY(h, hipStreamSynchronize(stream));
@@ -1051,36 +1045,49 @@ static int trace_paths(sw_handle* h, const sw_batch* batch, const sw_scheme* sch
     for (int c = 0; c < chunks; ++c) {
         T.chunk = c;
         HIP_TRY(h, launch_reset(h->d_hist, kHistSize, stream));
-        HIP_TRY(h, launch_trace_classify(K, T, cap, h->d_keys, h->d_hist, counters(h->d_small), stream));
+        HIP_TRY(h, launch_trace_classify(K, T, cap, h->d_keys, h->d_hist, counters(h->d_small), path_len, stream));
         HIP_TRY(h, launch_plan(h->d_tbins, n_tb, h->d_hist, h->d_meta, stream));
         HIP_TRY(h, launch_scatter(h->d_keys, h->d_n, cap, h->d_hist, h->d_order, stream));
         HIP_TRY(h, launch_items(h->d_meta, h->d_tbins, n_tb, h->d_n, cap, h->d_items, stream));
-        if (timing) HIP_TRY(h, hipEventRecord(h->tev[1], stream));
-        // longest boxes first; each bin's kernel fills the device
+        // longest boxes first: each bin's sweep (sized to fill the device),
+        // then its walks, on one stream; bins go round-robin to the forked
+        // streams (joined back at the end of the chunk), so that walks and
+        // launch tails overlap other bins' sweeps.  Timing serialises
+        // everything on the caller's stream.
+        const int forks = timing ? 0 : (int)h->opt_streams;
+        const int walk_blocks = (int)std::min<int64_t>((cap + 255) / 256, 4 * std::max(1, h->n_cu));
+        if (forks > 1) {
+            HIP_TRY(h, hipEventRecord(h->fork_ev[sw_handle::kForks], stream));
+            for (int f = 0; f < forks; ++f)
+                HIP_TRY(h, hipStreamWaitEvent(h->fork[f], h->fork_ev[sw_handle::kForks], 0));
+        }
+        int launched = 0;
         for (int b = n_tb - 1; b >= 0; --b) {
             const BinInfo& e = h->tbins[b];
             const int64_t need = (cap / e.ppw + 1 + kWavesPerBlock - 1) / kWavesPerBlock;
             const int blocks = (int)std::min<int64_t>(need, h->tresident[b]);
             set_range(K, b, 0);
-            if (per_bin) HIP_TRY(h, hipEventRecord(h->tbin_ev[2 * b], stream));
-            hipLaunchKernelGGL(trace_kernel(e.prec, e.W, e.R), dim3(blocks), dim3(kBlock), 0, stream, K, T);
+            hipStream_t ls = forks > 1 ? h->fork[launched++ % forks] : stream;
+            if (timing) HIP_TRY(h, hipEventRecord(h->tbin_ev[3 * b], ls));
+            hipLaunchKernelGGL(trace_kernel(e.prec, e.W, e.R), dim3(blocks), dim3(kBlock), 0, ls, K, T);
             HIP_TRY(h, hipGetLastError());
-            if (per_bin) HIP_TRY(h, hipEventRecord(h->tbin_ev[2 * b + 1], stream));
+            if (timing) HIP_TRY(h, hipEventRecord(h->tbin_ev[3 * b + 1], ls));
+            HIP_TRY(h, launch_trace_walk(K, T, b, walk_blocks, path_off, path, path_len, ls));
+            if (timing) HIP_TRY(h, hipEventRecord(h->tbin_ev[3 * b + 2], ls));
         }
-        if (timing) HIP_TRY(h, hipEventRecord(h->tev[2], stream));
-        HIP_TRY(h, launch_trace_walk(K, T, cap, path_off, path, path_len, stream));
+        for (int f = 0; forks > 1 && f < forks; ++f) {
+            HIP_TRY(h, hipEventRecord(h->fork_ev[f], h->fork[f]));
+            HIP_TRY(h, hipStreamWaitEvent(stream, h->fork_ev[f], 0));
+        }
         if (timing) {
-            HIP_TRY(h, hipEventRecord(h->tev[3], stream));
-            HIP_TRY(h, hipEventSynchronize(h->tev[3]));
-            float a = 0, w = 0;
-            HIP_TRY(h, hipEventElapsedTime(&a, h->tev[1], h->tev[2]));
-            HIP_TRY(h, hipEventElapsedTime(&w, h->tev[2], h->tev[3]));
-            h->t_path_sweep += a;
-            h->t_path_walk += w;
-            for (int b = 0; per_bin && b < n_tb; ++b) {
-                float ms = 0;
-                HIP_TRY(h, hipEventElapsedTime(&ms, h->tbin_ev[2 * b], h->tbin_ev[2 * b + 1]));
-                bin_ms[b] += ms;
+            HIP_TRY(h, hipStreamSynchronize(stream));
+            for (int b = 0; b < n_tb; ++b) {
+                float a = 0, w = 0;
+                HIP_TRY(h, hipEventElapsedTime(&a, h->tbin_ev[3 * b], h->tbin_ev[3 * b + 1]));
+                HIP_TRY(h, hipEventElapsedTime(&w, h->tbin_ev[3 * b + 1], h->tbin_ev[3 * b + 2]));
+                h->t_path_sweep += a;
+                h->t_path_walk += w;
+                bin_ms[b] += a;
             }
         }
     }

@@ -16,7 +16,8 @@
 //                  residue over a gap), 2 E (a reference residue over a gap)
 //        bit 2     F does not open here (F != H(i-1, j) - o: it extends)
 //        bit 3     E does not open here (E != H(i, j-1) - o)
-//      Step t of lane l holds rows l*R .. l*R+R-1 of column t - l.  Records
+//      Step t of lane l holds rows l*R .. l*R+R-1 of column t - l (R a
+//      multiple of 4).  Records
 //      are laid out in blocks of kStage steps: block b of lane l is the
 //      4R bytes at (b * W + l) * 4R, step t = 8b + s at byte s * R/2, row k
 //      in byte k/2 (low nibble for even k).  The sweep stages a block's
@@ -78,38 +79,45 @@ __device__ __forceinline__ PairJob box_job(const KParams& P, int pair, int max_r
     return J;
 }
 
-// Record staging of one wavefront: the steps of the current block of each
-// of its PPW pairs, step-major in LDS ([step][pair][lane][NW dwords], so the
-// per-step writes of a wavefront are contiguous), copied out in the
-// lane-major record layout when the block is complete.
+// Record staging of one wavefront: the current block (kStage steps) of each
+// of its PPW pairs, in LDS in the record layout itself (pair p's block is
+// W lanes x 4R bytes, lane-major), so that a complete block is copied out
+// with 16-byte loads and stores.  A lane's step is R/2 bytes: R/8 dwords of
+// 8 rows, and for R % 8 == 4 a 16-bit tail of 4 rows.
 template <int W, int R, int PPW>
 struct RecordStage {
-    static constexpr int NW = R / 8;                        // dwords per lane and step
-    static constexpr int kDwords = kStage * PPW * W * NW;   // per wavefront
+    static_assert(R % 4 == 0 && R >= 4 && R <= 32, "a lane's step is whole 16-bit units of 4 rows");
+    static constexpr int NW = R / 8;                    // whole dwords per lane and step
+    static constexpr int kDwords = PPW * W * R;         // per wavefront (4R bytes per lane and block)
     uint32_t* lds;
 
-    __device__ __forceinline__ void put(int p, int l, int t, const uint32_t* v) const {
-        uint32_t* d = lds + (((t & (kStage - 1)) * PPW + p) * W + l) * NW;
+    __device__ __forceinline__ void put(int p, int l, int t, const uint32_t* v, uint32_t tail) const {
+        const int byte = ((p * W + l) * kStage + (t & (kStage - 1))) * (R / 2);
+        if constexpr (R % 8 == 0) {
+            uint32_t* d = lds + byte / 4;
 #pragma unroll
-        for (int k = 0; k < NW; ++k) d[k] = v[k];
+            for (int k = 0; k < NW; ++k) d[k] = v[k];
+        } else {
+            // R/2 = 4k + 2 bytes: only 16-bit alignment is guaranteed
+            uint16_t* d = reinterpret_cast<uint16_t*>(lds) + byte / 2;
+#pragma unroll
+            for (int k = 0; k < NW; ++k) {
+                d[2 * k] = (uint16_t)v[k];
+                d[2 * k + 1] = (uint16_t)(v[k] >> 16);
+            }
+            d[2 * NW] = (uint16_t)tail;
+        }
     }
-    // Copy block b of pair p (all W lanes, W * R dwords) to its record
-    // (lane-major: dword d = l * R + s * NW + k), 16 bytes per lane at a time.
+    // Copy block b of pair p (W * R dwords) to its record, 16 bytes per
+    // lane at a time.
     __device__ __forceinline__ void flush(int p, uint32_t* rec, int b, int lane) const {
         uint32_t* dst = rec + (int64_t)b * W * R;
+        const uint32_t* src = lds + p * W * R;
 #pragma unroll
         for (int c0 = 0; c0 < W * R / 4; c0 += 64) {
             const int c = c0 + lane;
-            if (W * R / 4 >= c0 + 64 || c < W * R / 4) {
-                uint32_t v[4];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int d = 4 * c + q;
-                    const int l = d / R, rem = d % R;
-                    v[q] = lds[((rem / NW) * PPW + p) * W * NW + l * NW + rem % NW];
-                }
-                *reinterpret_cast<uint4*>(dst + 4 * c) = make_uint4(v[0], v[1], v[2], v[3]);
-            }
+            if (W * R / 4 >= c0 + 64 || c < W * R / 4)
+                *reinterpret_cast<uint4*>(dst + 4 * c) = *reinterpret_cast<const uint4*>(src + 4 * c);
         }
     }
 };
@@ -142,8 +150,7 @@ __device__ __forceinline__ u16x2 pk_ne01(u16x2 x) {
 template <int W, int R>
 __device__ __forceinline__ void sweep_trace(const KParams& P, const TraceArgs& T, const SchemeLds& S,
                                             uint16_t* wbuf, uint32_t* stg, int first, int count, int lane) {
-    static_assert(R % 8 == 0 && R >= 8 && R <= 32, "a lane's record of one step is whole dwords of 8 rows");
-    constexpr int NW = R / 8;
+    constexpr int NW = (R + 7) / 8;   // dwords of 8 rows (the last one half used when R % 8 == 4)
     constexpr int G = 64 / W;
     const RecordStage<W, R, G> rs{stg};
     using Stager = RefStager<W>;
@@ -239,7 +246,7 @@ __device__ __forceinline__ void sweep_trace(const KParams& P, const TraceArgs& T
             Flast = F;
             bb_next = bb2;
             const int t = t0 + tt;
-            rs.put(g, l, t, wv);
+            rs.put(g, l, t, wv, wv[NW - 1]);
             if ((t & (kStage - 1)) == kStage - 1 || t == steps - 1) {
                 wave_lds_sync();
 #pragma unroll
@@ -287,8 +294,7 @@ __device__ __forceinline__ uint32_t* trace_record(const KParams& P, const TraceA
 template <int W, int R>
 __device__ __forceinline__ void sweep_trace_i16(const KParams& P, const TraceArgs& T, const SchemeLds& S,
                                                 uint16_t* wbuf, uint32_t* stg, int first, int count, int lane) {
-    static_assert(R % 8 == 0 && R >= 8 && R <= 32, "a lane's record of one step is whole dwords of 8 rows");
-    constexpr int NW = R / 8;
+    constexpr int NW = R / 8;   // whole dwords of 8 rows per pair; R % 8 == 4 adds a 16-bit tail
     constexpr int G = 64 / W;
     const RecordStage<W, R, 2 * G> rs{stg};
     constexpr uint32_t K = kI16Bias;
@@ -397,15 +403,16 @@ __device__ __forceinline__ void sweep_trace_i16(const KParams& P, const TraceArg
             Flast = u32(F);
             bbA_next = bbA2;
             bbB_next = bbB2;
-            uint32_t va[NW], vb[NW];
+            uint32_t va[NW + 1], vb[NW + 1];
 #pragma unroll
             for (int k = 0; k < NW; ++k) {
                 va[k] = __builtin_amdgcn_perm(w[2 * k + 1], w[2 * k], 0x05040100u);
                 vb[k] = __builtin_amdgcn_perm(w[2 * k + 1], w[2 * k], 0x07060302u);
             }
+            const uint32_t tail = w[R / 4 - 1];
             const int t = t0 + tt;
-            rs.put(2 * g, l, t, va);
-            rs.put(2 * g + 1, l, t, vb);
+            rs.put(2 * g, l, t, va, tail);
+            rs.put(2 * g + 1, l, t, vb, tail >> 16);
             if ((t & (kStage - 1)) == kStage - 1 || t == steps - 1) {
                 wave_lds_sync();
 #pragma unroll
@@ -481,7 +488,9 @@ __global__ __launch_bounds__(kBlock) void sw_trace_kernel(KParams P, TraceArgs T
     }
 }
 
-#define SW_TRACE_SHAPES(X, P) X(P, 16, 8) X(P, 16, 16) X(P, 32, 16) X(P, 64, 16) X(P, 64, 24) X(P, 64, 32)
+#define SW_TRACE_SHAPES(X, P)                                                                          \
+    X(P, 16, 4) X(P, 16, 8) X(P, 16, 12) X(P, 16, 16) X(P, 32, 12) X(P, 32, 16) X(P, 64, 12) X(P, 64, 16) \
+    X(P, 64, 20) X(P, 64, 24) X(P, 64, 28) X(P, 64, 32)
 
 namespace {
 struct TraceEntry { int prec, W, R; TraceFn fn; };
@@ -627,7 +636,7 @@ hipError_t launch_trace_sizes(const KParams& P, const TraceArgs& T, int64_t cap,
 // bucket, longest first); pairs outside the chunk or without an alignment
 // get the trivial key.
 __global__ void sw_trace_classify_kernel(KParams P, TraceArgs T, int32_t* keys, int32_t* hist,
-                                         unsigned long long* counters) {
+                                         unsigned long long* counters, int32_t* path_len) {
     __shared__ unsigned long long s_cells[kMaxBins];
     __shared__ uint32_t s_pairs[kMaxBins];
     __shared__ int32_t s_trivial;
@@ -639,6 +648,7 @@ __global__ void sw_trace_classify_kernel(KParams P, TraceArgs T, int32_t* keys, 
     if (i < n) {
         int key = kTrivialKey;
         const sw_result r = P.out[i];
+        if (r.score <= 0 && T.chunk == 0) path_len[i] = 0;   // no alignment, no path
         if (r.score > 0 && T.rec_off[i] / T.chunk_bytes == T.chunk) {
             const int rows = r.q_end - r.q_start + 1, cols = r.r_end - r.r_start + 1;
             // sizes were validated when the records were laid out
@@ -664,10 +674,11 @@ __global__ void sw_trace_classify_kernel(KParams P, TraceArgs T, int32_t* keys, 
 }
 
 hipError_t launch_trace_classify(const KParams& P, const TraceArgs& T, int64_t cap, int32_t* keys,
-                                 int32_t* hist, unsigned long long* counters, hipStream_t s) {
+                                 int32_t* hist, unsigned long long* counters, int32_t* path_len, hipStream_t s) {
     if (cap <= 0) return hipSuccess;
     const unsigned blocks = (unsigned)((cap + 255) / 256);
-    hipLaunchKernelGGL(sw_trace_classify_kernel, dim3(blocks), dim3(256), 0, s, P, T, keys, hist, counters);
+    hipLaunchKernelGGL(sw_trace_classify_kernel, dim3(blocks), dim3(256), 0, s, P, T, keys, hist, counters,
+                       path_len);
     return hipGetLastError();
 }
 
@@ -697,19 +708,13 @@ __device__ __forceinline__ uint32_t window_at(const uint8_t* seq, int x, uintptr
     return (w >> (8 * (o & 3))) & 0xFFu;
 }
 
-__global__ __launch_bounds__(256) void sw_trace_walk_kernel(KParams P, TraceArgs T, const int64_t* path_off,
-                                                            uint32_t* path, int32_t* path_len) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= *P.n_dev) return;
+// Walk of pair i (whose record is in the current chunk).
+__device__ __forceinline__ void walk_pair(const KParams& P, const TraceArgs& T, int i, const int64_t* path_off,
+                                          uint32_t* path, int32_t* path_len, uint32_t* slot) {
     const sw_result r = P.out[i];
-    if (r.score <= 0) {
-        if (T.chunk == 0) path_len[i] = 0;
-        return;
-    }
     const int64_t off = T.rec_off[i];
-    if (off / T.chunk_bytes != T.chunk) return;
     const int rows = r.q_end - r.q_start + 1, cols = r.r_end - r.r_start + 1;
-    const int b = (rows >= 1 && rows <= SW_MAX_QUERY) ? trace_bin(T, r.score, rows) : -1;
+    const int b = (r.score > 0 && rows >= 1 && rows <= SW_MAX_QUERY) ? trace_bin(T, r.score, rows) : -1;
     const int64_t beg = path_off[i], end = path_off[i + 1];
     if (b < 0 || b >= T.n_bins || cols < 1 || end < beg) {
         atomicOr(&P.flags[end < beg ? kFlagPathRoom : kFlagInternal], 1);
@@ -724,10 +729,7 @@ __global__ __launch_bounds__(256) void sw_trace_walk_kernel(KParams P, TraceArgs
         return;
     }
     const uint32_t* rec = reinterpret_cast<const uint32_t*>(T.ws + rel);
-    // this thread's copy of the record block it reads (R dwords)
-    __shared__ uint32_t cache[256 * kWalkSlot];
-    uint32_t* slot = cache + threadIdx.x * kWalkSlot;
-    int64_t cached = -1;
+    int64_t cached = -1;   // record block held in `slot` (this thread's LDS copy, R dwords)
     const uint8_t* qa = P.queries + P.q_beg[i] + r.q_start;
     const uint8_t* rb = P.refs + P.r_beg[i] + r.r_start;
     uintptr_t qbase = ~(uintptr_t)0, rbase = ~(uintptr_t)0;
@@ -807,11 +809,31 @@ __global__ __launch_bounds__(256) void sw_trace_walk_kernel(KParams P, TraceArgs
     path_len[i] = (int32_t)k;
 }
 
-hipError_t launch_trace_walk(const KParams& P, const TraceArgs& T, int64_t cap, const int64_t* path_off,
+// One bin's walks: its pairs are order[meta[bin first] .. meta[next bin first]).
+__global__ __launch_bounds__(256) void sw_trace_walk_kernel(KParams P, TraceArgs T, int bin, const int64_t* path_off,
+                                                            uint32_t* path, int32_t* path_len) {
+    __shared__ uint32_t cache[256 * kWalkSlot];
+    uint32_t* slot = cache + threadIdx.x * kWalkSlot;
+    const int lo = P.meta[kMetaBinFirst + bin], hi = P.meta[kMetaBinFirst + bin + 1];
+    if (lo < 0 || lo > hi || hi > P.n_pairs) {
+        if (threadIdx.x == 0) atomicOr(&P.flags[kFlagInternal], 1);
+        return;
+    }
+    const int n = *P.n_dev;
+    for (int k = lo + (int)(blockIdx.x * blockDim.x + threadIdx.x); k < hi; k += (int)(gridDim.x * blockDim.x)) {
+        const int i = P.order[k];
+        if (i < 0 || i >= n) {
+            atomicOr(&P.flags[kFlagInternal], 1);
+            continue;
+        }
+        walk_pair(P, T, i, path_off, path, path_len, slot);
+    }
+}
+
+hipError_t launch_trace_walk(const KParams& P, const TraceArgs& T, int bin, int blocks, const int64_t* path_off,
                              uint32_t* path, int32_t* path_len, hipStream_t s) {
-    if (cap <= 0) return hipSuccess;
-    const unsigned blocks = (unsigned)((cap + 255) / 256);
-    hipLaunchKernelGGL(sw_trace_walk_kernel, dim3(blocks), dim3(256), 0, s, P, T, path_off, path, path_len);
+    hipLaunchKernelGGL(sw_trace_walk_kernel, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, s, P, T, bin, path_off, path,
+                       path_len);
     return hipGetLastError();
 }
 

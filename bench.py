@@ -177,28 +177,30 @@ def cigar_leg(args, db, out, ref_out, tuning, score_ms):
     al.close()
     alt = Aligner(0, tuning, timing=2)
     sweep_ms, walk_ms, per_bin = [], [], {}
-    for k in range(3):
+    reps = 3
+    for k in range(reps):
         alt.align_cigar(db, out=res[0], cigar_off=res[1], cigar=res[2], cigar_len=res[3])
         _, _, _, sm, wm = alt.cigar_stats()
         sweep_ms.append(sm); walk_ms.append(wm)
         for e in alt.bin_stats():
             if e["pass"] == 2 and e["pairs"]:
-                acc = per_bin.setdefault((e["lanes"], e["rows"]), [0.0, 0])
+                acc = per_bin.setdefault((e["precision"], e["lanes"], e["rows"]), [0.0, 0])
                 acc[0] += e["ms"]; acc[1] += e["cells"]
     alt.close()
-    (W_, R_), (dms, dcells) = max(per_bin.items(), key=lambda kv: kv[1][0])
+    (P_, W_, R_), (dms, dcells) = max(per_bin.items(), key=lambda kv: kv[1][0])
+    peak = VALU_INT16X2_TOPS if P_ == 16 else VALU_INT32_TOPS
     achieved = PATH_OPS_PER_CELL * dcells / (dms / 1e3) / 1e12
-    n_chunks_launches = 3 * chunks
+    launches = reps * chunks
     log("  paths: %d calls in %.3f s" % (steps, el))
     return {"value": round(fwd * steps / el / 1e9, 2), "unit": "GCUPS",
             "ms_per_call": round(el * 1e3 / steps, 3), "score_only_ms": round(score_ms, 3),
             "box_cells": int(box_cells), "record_gb": round(rec_bytes / 1e9, 3), "chunks": chunks,
             "sweep_ms": round(float(np.mean(sweep_ms)), 3), "walk_ms": round(float(np.mean(walk_ms)), 3),
-            "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_INT32_TOPS, 2),
-                         "unit": "Tops/s", "frac": round(achieved / VALU_INT32_TOPS, 4), "traffic": None,
-                         "kernel": "sw::sw_trace_kernel<%d, %d>" % (W_, R_),
-                         "launch_ms": round(dms / n_chunks_launches, 4),
-                         "cells_per_launch": int(dcells / n_chunks_launches),
+            "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 2),
+                         "unit": "Tops/s", "frac": round(achieved / peak, 4), "traffic": None,
+                         "kernel": "sw::sw_trace_kernel<%d, %d, %d>" % (P_, W_, R_), "launches": launches,
+                         "launch_ms": round(dms / launches, 4),
+                         "cells_per_launch": int(dcells / launches),
                          "ops_per_cell": PATH_OPS_PER_CELL,
                          "record_bytes_per_cell": 0.5}}
 

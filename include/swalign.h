@@ -161,6 +161,18 @@ int sw_align_spans(sw_handle* h, const uint8_t* queries, const int64_t* q_beg, c
                    const uint8_t* scheme_id, int64_t n_pairs, const sw_scheme* schemes, int n_schemes,
                    sw_result* out, void* stream);
 
+/* Database search: align one query against every reference of a set, as
+ * sw_align_batch would align the pairs (query, reference i); out[i] is the
+ * result of reference i.  `query` (q_len residues), `refs` and `r_off`
+ * (int64[n_refs+1], non-decreasing; reference i is refs[r_off[i] ..
+ * r_off[i+1])) are DEVICE pointers owned by the caller; `scheme` is one HOST
+ * scheme.  The query is stored once and every pair's span points at it; the
+ * spans are kept on the device between calls with the same query length, so
+ * repeated searches replay one captured graph.  Errors as for sw_align_batch
+ * (SW_ETOOLONG for q_len > SW_MAX_QUERY). */
+int sw_search(sw_handle* h, const uint8_t* query, int64_t q_len, const uint8_t* refs, const int64_t* r_off,
+              int64_t n_refs, const sw_scheme* scheme, sw_result* out, void* stream);
+
 /* Statistics of the last sw_align_batch call on this handle: number of
  * forward cells (sum of n*m), reverse cells (sum of (q_end+1)*(r_end+1) over
  * pairs with a positive score) and the number of pairs routed to the int32

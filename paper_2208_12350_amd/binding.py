@@ -34,7 +34,7 @@ _ERRNAMES = {SW_EINVAL: "SW_EINVAL", SW_ENOMEM: "SW_ENOMEM", SW_ETOOLONG: "SW_ET
 
 EXPORTED = ("sw_create", "sw_destroy", "sw_last_error", "sw_set_option", "sw_get_option",
             "sw_align_batch", "sw_align_spans", "sw_last_stats", "sw_last_timing", "sw_last_host_timing", "sw_last_bin_stats",
-            "sw_shapes", "sw_set_routing", "sw_get_routing", "sw_align_cigar", "sw_last_cigar_stats",
+            "sw_shapes", "sw_set_routing", "sw_get_routing", "sw_align_cigar", "sw_last_cigar_stats", "sw_search",
             "sw_server_create", "sw_server_destroy", "sw_server_last_error", "sw_server_submit",
             "sw_server_poll", "sw_server_stats", "sw_server_timing")
 
@@ -118,6 +118,9 @@ def load_library(path: str = LIB_PATH):
     lib.sw_last_cigar_stats.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64),
                                         ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32),
                                         ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)]
+    lib.sw_search.restype = ctypes.c_int
+    lib.sw_search.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                              ctypes.c_int64, ctypes.POINTER(sw_scheme), ctypes.c_void_p, ctypes.c_void_p]
     lib.sw_server_create.restype = ctypes.c_void_p
     lib.sw_server_create.argtypes = [ctypes.c_int, ctypes.POINTER(sw_scheme), ctypes.c_int, ctypes.c_int64,
                                      ctypes.c_int, ctypes.c_int64, ctypes.c_char_p]
@@ -390,6 +393,27 @@ class Aligner:
         _check(self.h, rc)
         del keep
         return out, cigar_off, cigar, cigar_len
+
+    def search(self, query, refs, r_off, scheme, out=None, stream=None):
+        """Align one query (a uint8 device tensor) against every reference
+        (refs: uint8 device tensor, r_off: int64 device tensor [n+1]) with one
+        scheme; returns an int32 tensor [n, 5] on the device."""
+        import torch
+        n = int(r_off.numel()) - 1
+        if out is None:
+            out = torch.empty((n, 5), dtype=torch.int32, device=r_off.device)
+        assert out.is_contiguous() and out.dtype == torch.int32 and out.shape == (n, 5)
+        for t in (query, refs):
+            assert t.dtype == torch.uint8 and t.is_contiguous()
+        assert r_off.dtype == torch.int64 and r_off.is_contiguous()
+        arr, keep = make_schemes([scheme])
+        s = stream if stream is not None else torch.cuda.current_stream(r_off.device)
+        rc = load_library().sw_search(self.h, query.data_ptr() if query.numel() else None, int(query.numel()),
+                                      refs.data_ptr() if refs.numel() else None, r_off.data_ptr(), n, arr,
+                                      out.data_ptr() if n else None, ctypes.c_void_p(s.cuda_stream))
+        _check(self.h, rc)
+        del keep
+        return out
 
     def cigar_stats(self):
         return sw_last_cigar_stats(self.h)

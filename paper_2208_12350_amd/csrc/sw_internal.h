@@ -173,6 +173,8 @@ QueueFn shape_kernel(int prec, int W, int R, bool reverse, bool col = false);
 const ShapeDesc* compiled_shapes(int* n);
 
 hipError_t launch_reset(int32_t* p, int n, hipStream_t s);
+// beg[0..n) = 0, end[0..n) = len (the query spans of a database search)
+hipError_t launch_fill_span(int64_t* beg, int64_t* end, int64_t n, int64_t len, hipStream_t s);
 // The planning launches are sized for `cap` pairs; the kernels take the
 // batch size from device memory (P.n_dev / n_dev), so a captured graph can be
 // replayed for any batch of at most `cap` pairs.

@@ -238,9 +238,24 @@ __global__ void sw_items_kernel(const int32_t* meta, const BinInfo* bins, int n_
     items[meta[kMetaItemFirst + b] + k / bi.ppw] = w;
 }
 
+__global__ void sw_fill_span_kernel(int64_t* beg, int64_t* end, int64_t n, int64_t len) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        beg[i] = 0;
+        end[i] = len;
+    }
+}
+
 static unsigned grid_for(int64_t n, int threads) {
     int64_t b = (n + threads - 1) / threads;
     return (unsigned)(b > 0 ? b : 1);
+}
+
+hipError_t launch_fill_span(int64_t* beg, int64_t* end, int64_t n, int64_t len, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    unsigned blocks = grid_for(n, 256);
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(sw_fill_span_kernel, dim3(blocks), dim3(256), 0, s, beg, end, n, len);
+    return hipGetLastError();
 }
 
 hipError_t launch_reset(int32_t* p, int n, hipStream_t s) {

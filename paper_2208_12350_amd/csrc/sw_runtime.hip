@@ -132,6 +132,11 @@ struct sw_handle {
     int64_t last_path_cells = 0, last_path_bytes = 0;
     int32_t last_path_chunks = 0;
     float t_path_sweep = 0.f, t_path_walk = 0.f;
+
+    // database search (sw_search): the shared query's span for every pair
+    int64_t* d_qspan = nullptr;          // [2 * search_cap]: begins, then ends
+    int64_t search_cap = 0;
+    int64_t search_len = -1;             // query length the spans hold
 };
 
 static int fail(sw_handle* h, int code, const char* fmt, ...) {
@@ -525,6 +530,7 @@ void sw_destroy(sw_handle* h) {
     free_dev(h->d_hist); free_dev(h->d_meta); free_dev(h->d_keys); free_dev(h->d_order);
     free_dev(h->d_items);
     free_dev(h->d_tbins); free_dev(h->d_tlut); free_dev(h->d_rec_off); free_dev(h->d_bsum); free_dev(h->d_ws);
+    free_dev(h->d_qspan);
     if (h->h_i64) (void)hipHostFree(h->h_i64);
     for (hipEvent_t e : h->tbin_ev)
         if (e) (void)hipEventDestroy(e);
@@ -1142,3 +1148,42 @@ int sw_last_cigar_stats(sw_handle* h, int64_t* box_cells, int64_t* record_bytes,
 }
 
 }  // extern "C"
+
+// ---- database search ---------------------------------------------------------------
+
+extern "C" int sw_search(sw_handle* h, const uint8_t* query, int64_t q_len, const uint8_t* refs,
+                         const int64_t* r_off, int64_t n_refs, const sw_scheme* scheme, sw_result* out,
+                         void* stream_ptr) {
+    if (!h) return SW_EINVAL;
+    h->err.clear();
+    if (n_refs < 0 || n_refs > (int64_t)0x7FFFFFFF) return fail(h, SW_EINVAL, "n_refs must be 0..2^31-1");
+    if (q_len < 0) return fail(h, SW_EINVAL, "negative query length");
+    if (q_len > SW_MAX_QUERY)
+        return fail(h, SW_ETOOLONG, "a query exceeds %d or a reference exceeds %d residues", SW_MAX_QUERY, SW_MAX_REF);
+    if (!scheme) return fail(h, SW_EINVAL, "null scheme");
+    if (n_refs == 0) return SW_OK;
+    if (!refs || !r_off || !out || (q_len > 0 && !query))
+        return fail(h, SW_EINVAL, "null device pointer with n_refs > 0");
+    hipStream_t stream = (hipStream_t)stream_ptr;
+    HIP_TRY(h, hipSetDevice(h->device));
+    if (n_refs > h->search_cap) {
+        drop_graph(h);
+        free_dev(h->d_qspan);
+        h->d_qspan = nullptr;
+        h->search_cap = 0;
+        h->search_len = -1;
+        const int64_t cap = std::max<int64_t>(n_refs, 4096);
+        if (hipMalloc(&h->d_qspan, 2 * cap * 8) != hipSuccess)
+            return fail(h, SW_ENOMEM, "device allocation of %lld query spans failed", (long long)cap);
+        h->search_cap = cap;
+    }
+    int64_t* beg = h->d_qspan;
+    int64_t* end = h->d_qspan + h->search_cap;
+    if (q_len != h->search_len) {
+        // every pair reads the same query: spans [0, q_len) over `query`
+        HIP_TRY(h, launch_fill_span(beg, end, h->search_cap, q_len, stream));
+        h->search_len = q_len;
+    }
+    const uint8_t* qptr = query ? query : refs;   // an empty query is never read
+    return align_spans(h, qptr, beg, end, refs, r_off, r_off + 1, nullptr, n_refs, scheme, 1, out, stream);
+}

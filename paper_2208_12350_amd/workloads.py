@@ -166,7 +166,7 @@ def _substitute(rng, orig: np.ndarray, pi: Optional[np.ndarray], A: int) -> np.n
 
 
 def mutate_embed(rng, q_lens: np.ndarray, r_lens: np.ndarray, p_sub: float,
-                 p_indel: float, pi: Optional[np.ndarray], A: int):
+                 p_indel: float, pi: Optional[np.ndarray], A: int, queries: Optional[np.ndarray] = None):
     """Draw queries of the given lengths and references that embed a mutated
     copy of each query.
 
@@ -177,7 +177,8 @@ def mutate_embed(rng, q_lens: np.ndarray, r_lens: np.ndarray, p_sub: float,
     max(L_r, |copy|); the copy sits at an offset drawn uniformly from
     0..L_r-|copy| and the flanks are iid pi.
 
-    Returns (queries, q_off, refs, r_off) for these pairs.
+    Returns (queries, q_off, refs, r_off) for these pairs.  `queries`
+    (concatenated, of the given lengths) replaces the drawn queries.
     """
     q_lens = np.asarray(q_lens, dtype=np.int64)
     r_lens = np.asarray(r_lens, dtype=np.int64)
@@ -185,7 +186,12 @@ def mutate_embed(rng, q_lens: np.ndarray, r_lens: np.ndarray, p_sub: float,
     q_off = np.zeros(P + 1, np.int64)
     q_off[1:] = np.cumsum(q_lens)
     Q = int(q_off[-1])
-    queries = _draw(rng, Q, pi, A)
+    if queries is None:
+        queries = _draw(rng, Q, pi, A)
+    else:
+        queries = np.ascontiguousarray(queries, dtype=np.uint8)
+        if queries.size != Q:
+            raise ValueError("queries do not match q_lens")
 
     u_indel = rng.random(Q)
     u_kind = rng.random(Q)
@@ -399,3 +405,79 @@ def serving_stream(offered_cells_per_ms: float, n_requests: int, seed: Optional[
     lam = offered_cells_per_ms * 1e3 / mean_cells  # requests per second
     t = poisson_arrivals(n_requests, lam, base + 1)
     return [Request(float(t[k]), batches[k]) for k in range(n_requests)]
+
+
+# ---- database search: one query against many references ---------------------
+
+@dataclasses.dataclass
+class SearchSet:
+    """One query and a set of references (the flat layout of sw_search)."""
+
+    query: np.ndarray
+    refs: np.ndarray
+    r_off: np.ndarray
+    scheme: Scheme
+    name: str = ""
+    seed: int = 0
+    homolog: Optional[np.ndarray] = None   # bool [n_refs]: the reference embeds a copy of the query
+
+    @property
+    def n_refs(self) -> int:
+        return int(self.r_off.shape[0] - 1)
+
+    def cells(self) -> int:
+        return int(self.query.size) * int(self.r_off[-1] - self.r_off[0])
+
+    def as_batch(self, index=None) -> Batch:
+        """The same pairs as a Batch (the query copied for each pair), or the
+        pairs `index` only."""
+        idx = np.arange(self.n_refs) if index is None else np.asarray(index, dtype=np.int64)
+        n = self.query.size
+        q = np.tile(self.query, idx.size)
+        qo = np.arange(idx.size + 1, dtype=np.int64) * n
+        lens = (self.r_off[idx + 1] - self.r_off[idx]).astype(np.int64)
+        ro = np.zeros(idx.size + 1, np.int64)
+        np.cumsum(lens, out=ro[1:])
+        r = np.concatenate([self.refs[self.r_off[i]:self.r_off[i + 1]] for i in idx]) if idx.size else \
+            np.zeros(0, np.uint8)
+        return Batch(q, qo, r.astype(np.uint8), ro, np.zeros(idx.size, np.uint8), [self.scheme],
+                     self.name + "[batch]", self.seed)
+
+
+SEARCHES = ("search_protein", "search_dna")
+
+
+def make_search(name: str, n_refs: Optional[int] = None, seed: Optional[int] = None) -> SearchSet:
+    """A database search: one query against references of which 1% embed a
+    mutated copy of it (the homologues a search is for) and the rest are
+    unrelated sequences of the same residue distribution.
+      search_protein: query of 400 residues, 200,000 references of
+        U{100..1000}, the protein scheme and mutation rates of "protein";
+      search_dna: query of 256 residues, 1,000,000 references of U{200..600},
+        the DNA scheme and mutation rates of "dna_large"."""
+    idx = SEARCHES.index(name)
+    seed = BASE_SEED + 100 + idx if seed is None else seed
+    rng = np.random.default_rng(seed)
+    if name == "search_protein":
+        n_q, P, lo, hi, A = 400, 200_000, 100, 1000, 20
+        scheme, pi, p_sub, p_indel = protein_scheme(seed), protein_frequencies(seed), 0.30, 0.03
+    else:
+        n_q, P, lo, hi, A = 256, 1_000_000, 200, 600, 4
+        scheme, pi, p_sub, p_indel = dna_scheme(), None, 0.10, 0.02
+    P = P if n_refs is None else n_refs
+    query = _draw(rng, n_q, pi, A)
+    r_len = _uniform_lengths(rng, P, lo, hi)
+    homolog = rng.random(P) < 0.01
+    parts_r = []
+    r_off = np.zeros(P + 1, np.int64)
+    # homologues: mutated embeddings of the query
+    h_idx = np.flatnonzero(homolog)
+    _, _, hr, hro = mutate_embed(rng, np.full(h_idx.size, n_q), r_len[h_idx], p_sub, p_indel, pi, A,
+                                 queries=np.tile(query, h_idx.size))
+    lens = r_len.astype(np.int64).copy()
+    lens[h_idx] = np.diff(hro)
+    r_off[1:] = np.cumsum(lens)
+    refs = _draw(rng, int(r_off[-1]), pi, A)
+    for k, i in enumerate(h_idx):
+        refs[r_off[i]:r_off[i + 1]] = hr[hro[k]:hro[k + 1]]
+    return SearchSet(query, refs, r_off, scheme, name, seed, homolog)

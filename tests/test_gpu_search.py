@@ -1,0 +1,82 @@
+"""Database search (sw_search, one query against many references) against
+the oracle: every pair of a small set, a sample of the full-size DNA search,
+properties over all pairs, and agreement with sw_align_batch on the same
+pairs given one by one."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2208_12350_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+FIELDS = ("score", "q_start", "q_end", "r_start", "r_end")
+
+
+@pytest.fixture(scope="module")
+def aligner():
+    import torch
+    from paper_2208_12350_amd.binding import Aligner
+    assert torch.cuda.is_available()
+    a = Aligner(0)
+    yield a
+    a.close()
+
+
+def run_search(aligner, s, query=None):
+    import torch
+    dev = "cuda:0"
+    q = torch.from_numpy(np.ascontiguousarray(s.query if query is None else query)).to(dev)
+    r = torch.from_numpy(s.refs).to(dev)
+    ro = torch.from_numpy(s.r_off).to(dev)
+    return aligner.search(q, r, ro, s.scheme).cpu().numpy().astype(np.int64)
+
+
+def oracle_rows(s, idx):
+    o = O.align_batch(s.as_batch(idx))
+    return np.stack([o[f] for f in FIELDS], axis=1).astype(np.int64)
+
+
+def test_protein_search_every_pair(aligner):
+    s = W.make_search("search_protein", n_refs=3000)
+    got = run_search(aligner, s)
+    assert np.array_equal(got, oracle_rows(s, np.arange(s.n_refs)))
+
+
+def test_full_size_dna_search_sampled(aligner):
+    s = W.make_search("search_dna")
+    got = run_search(aligner, s)
+    idx = np.sort(np.random.default_rng(4).choice(s.n_refs, size=300, replace=False))
+    idx = np.union1d(idx, np.flatnonzero(s.homolog)[:50])
+    assert np.array_equal(got[idx], oracle_rows(s, idx))
+    # every homologue outscores every unrelated reference
+    assert got[s.homolog, 0].min() > got[~s.homolog, 0].max()
+    # coordinates lie inside the query and each reference
+    pos = got[:, 0] > 0
+    rl = np.diff(s.r_off)
+    assert np.all((got[pos, 1] >= 0) & (got[pos, 1] <= got[pos, 2]) & (got[pos, 2] < s.query.size))
+    assert np.all((got[pos, 3] >= 0) & (got[pos, 3] <= got[pos, 4]) & (got[pos, 4] < rl[pos]))
+
+
+def test_search_equals_batch_and_changes_query_length(aligner):
+    from paper_2208_12350_amd.binding import DeviceBatch
+    s = W.make_search("search_protein", n_refs=5000)
+    got = run_search(aligner, s)
+    b = s.as_batch()
+    want = aligner.align(DeviceBatch.from_host(b)).cpu().numpy().astype(np.int64)
+    assert np.array_equal(got, want)
+    # a shorter query, then the original again (the stored spans are refilled)
+    short = s.query[:123].copy()
+    got2 = run_search(aligner, s, short)
+    s2 = W.SearchSet(short, s.refs, s.r_off, s.scheme)
+    idx = np.arange(0, s.n_refs, 7)
+    assert np.array_equal(got2[idx], oracle_rows(s2, idx))
+    assert np.array_equal(run_search(aligner, s), got)
+
+
+def test_empty_and_too_long_queries(aligner):
+    from paper_2208_12350_amd.binding import SwError
+    s = W.make_search("search_dna", n_refs=100)
+    got = run_search(aligner, s, np.zeros(0, np.uint8))
+    assert np.all(got == [0, -1, -1, -1, -1])
+    with pytest.raises(SwError):
+        run_search(aligner, s, np.zeros(2049, np.uint8))

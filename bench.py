@@ -68,12 +68,14 @@ def stored_traffic(kernel, workload):
 
 
 def kernel_sources_sha256():
-    """Digest of the HIP sources the sweep kernels are built from."""
+    """Digest of the HIP sources the sweep kernels (score and path sweeps)
+    are built from."""
     import glob
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2208_12350_amd", "csrc")
-    for path in sorted(glob.glob(os.path.join(csrc, "*.h")) + glob.glob(os.path.join(csrc, "sw_queue*.hip"))):
+    for path in sorted(glob.glob(os.path.join(csrc, "*.h")) + glob.glob(os.path.join(csrc, "sw_queue*.hip")) +
+                       glob.glob(os.path.join(csrc, "sw_trace.hip"))):
         h.update(os.path.basename(path).encode())
         with open(path, "rb") as f:
             h.update(f.read())
@@ -191,14 +193,16 @@ def cigar_leg(args, db, out, ref_out, tuning, score_ms):
     peak = VALU_INT16X2_TOPS if P_ == 16 else VALU_INT32_TOPS
     achieved = PATH_OPS_PER_CELL * dcells / (dms / 1e3) / 1e12
     launches = reps * chunks
+    kernel_name = "sw::sw_trace_kernel<%d, %d, %d>" % (P_, W_, R_)
     log("  paths: %d calls in %.3f s" % (steps, el))
     return {"value": round(fwd * steps / el / 1e9, 2), "unit": "GCUPS",
             "ms_per_call": round(el * 1e3 / steps, 3), "score_only_ms": round(score_ms, 3),
             "box_cells": int(box_cells), "record_gb": round(rec_bytes / 1e9, 3), "chunks": chunks,
             "sweep_ms": round(float(np.mean(sweep_ms)), 3), "walk_ms": round(float(np.mean(walk_ms)), 3),
             "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 2),
-                         "unit": "Tops/s", "frac": round(achieved / peak, 4), "traffic": None,
-                         "kernel": "sw::sw_trace_kernel<%d, %d, %d>" % (P_, W_, R_), "launches": launches,
+                         "unit": "Tops/s", "frac": round(achieved / peak, 4),
+                         "traffic": stored_traffic(kernel_name, args.workload),
+                         "kernel": kernel_name, "launches": launches,
                          "launch_ms": round(dms / launches, 4),
                          "cells_per_launch": int(dcells / launches),
                          "ops_per_cell": PATH_OPS_PER_CELL,

@@ -11,6 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libswalign.so")
 PROBE_LIB = os.path.join(HERE, "libswprobe.so")
+STENCIL_LIB = os.path.join(HERE, "libswstencil.so")
 SOURCES = ["sw_plan.hip", "sw_queue_i16_w16.hip", "sw_queue_i16_w32.hip", "sw_queue_i16_w64.hip",
            "sw_queue_i16_w256.hip",
            "sw_queue_i32.hip", "sw_trace.hip", "sw_runtime.hip", "sw_server.hip"]
@@ -58,6 +59,13 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError("hipcc failed:\n" + " ".join(cmd) + "\n" + r.stdout.decode(errors="replace"))
     os.replace(tmp, PROBE_LIB)
+    # the grid diffusion library (the second workload), also separate
+    tmp = STENCIL_LIB + ".tmp%d" % os.getpid()
+    cmd = [HIPCC] + FLAGS + ["-shared", os.path.join(CSRC, "sw_stencil.hip"), "-o", tmp]
+    r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)
+    if r.returncode != 0:
+        raise RuntimeError("hipcc failed:\n" + " ".join(cmd) + "\n" + r.stdout.decode(errors="replace"))
+    os.replace(tmp, STENCIL_LIB)
     if verbose:
         print("built %s in %.1fs" % (LIB, time.time() - t0))
     return LIB

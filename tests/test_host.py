@@ -68,3 +68,24 @@ def test_probe_library_exports_and_rejects_bad_arguments():
     assert lib.sw_probe_valu(0, 9, 10, 1, ctypes.byref(v)) == -1       # unknown kind
     assert lib.sw_probe_valu(0, 0, 0, 1, ctypes.byref(v)) == -1        # no iterations
     assert lib.sw_probe_valu(0, 0, 10, 1, None) == -1
+
+
+STENCIL_LIB = os.path.join(ROOT, "paper_2208_12350_amd", "libswstencil.so")
+
+
+@pytest.mark.skipif(not os.path.exists(STENCIL_LIB), reason="libswstencil.so not built")
+def test_stencil_library_exports_and_rejects_bad_arguments():
+    lib = ctypes.CDLL(STENCIL_LIB)
+    text = re.sub(r"/\*.*?\*/", "", open(os.path.join(ROOT, "include", "swstencil.h")).read(), flags=re.S)
+    names = set(re.findall(r"\b(sw_[a-z_]+)\s*\(", text))
+    from paper_2208_12350_amd import stencil
+    assert names == set(stencil.EXPORTED)
+    for n in names:
+        assert hasattr(lib, n), n
+    L = stencil.load_library()
+    # argument errors are reported before any launch
+    assert L.sw_diffuse_padded(None, None, 4, 4, 6, 0.5, None) == -1
+    assert L.sw_diffuse_padded(1, 2, 4, 4, 5, 0.5, None) == -1            # pitch < nx + 2
+    assert L.sw_diffuse_padded(1, 2, 4, 4, 6, 1.5, None) == -1            # D outside [0, 1]
+    assert L.sw_diffuse_checked(1, 2, 0, 4, 0.5, None) == -1
+    assert L.sw_pad_grid(1, 2, 4, 4, 3, None) == -1

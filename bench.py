@@ -374,6 +374,80 @@ def search_bench(args):
     print(json.dumps(res), flush=True)
 
 
+def stencil_bench(args):
+    """Grid diffusion (the paper's second workload, libswstencil): K steps on
+    a zero-padded grid and on an unpadded grid with bounds checks, timed with
+    HIP events on the launch stream.  Algorithmic traffic is 8 bytes per
+    point and step (one float read, one written); the roofline is HBM."""
+    import numpy as np
+    import torch
+    from paper_2208_12350_amd import stencil as K
+    sizes = [int(x) for x in args.grid.split(",")]
+    steps = max(2, args.steps)
+    D = 0.15
+    rows = []
+    for n in sizes:
+        rng = torch.Generator(device="cuda").manual_seed(n)
+        g = torch.rand((n, n), generator=rng, device="cuda", dtype=torch.float32)
+        res = {}
+        for form in ("padded", "checked"):
+            if form == "padded":
+                a = K.pad(g)
+                b = a.clone()
+                step = lambda s, d: K.diffuse_padded(s, d, n, n, D)
+            else:
+                a, b = g.clone(), torch.empty_like(g)
+                step = lambda s, d: K.diffuse_checked(s, d, D)
+            for _ in range(args.warmup):
+                step(a, b)
+                a, b = b, a
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(steps):
+                step(a, b)
+                a, b = b, a
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / steps
+            res[form] = (ms, a if form == "padded" else a)
+            del b
+        out_p = res["padded"][1][1:n + 1, 1:n + 1]
+        assert torch.equal(out_p, res["checked"][1]), "padded and checked grids differ"
+        pts = n * n
+        ms_p, ms_c = res["padded"][0], res["checked"][0]
+        rows.append({"grid": "%dx%d" % (n, n), "step_ms_padded": round(ms_p, 4), "step_ms_checked": round(ms_c, 4),
+                     "gpoints_per_s_padded": round(pts / ms_p / 1e6, 2),
+                     "gpoints_per_s_checked": round(pts / ms_c / 1e6, 2),
+                     "padding_speedup": round(ms_c / ms_p, 3),
+                     "roofline": {"bound": "hbm", "achieved": round(8 * pts / ms_p / 1e6, 1), "peak": 8000.0,
+                                  "unit": "GB/s", "frac": round(8 * pts / ms_p / 1e6 / 8000.0, 4),
+                                  "traffic": None}})
+        del res, g
+        torch.cuda.empty_cache()
+    big = rows[-1]
+    out = {"metric": "grid diffusion steps: Gpoints/s (padded vs bounds-checked)",
+           "value": big["gpoints_per_s_padded"], "unit": "Gpoints/s", "n_gpus": 1, "steps": steps,
+           "warmup": args.warmup, "ms_per_step": big["step_ms_padded"], "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "stencil", "grids": args.grid, "D": D}, "grids": rows,
+           "roofline": big["roofline"]}
+    if not args.no_cpu_baseline:
+        from oracle import stencil as S
+        n = 2500
+        c = np.random.default_rng(1).random((n, n))
+        t = time.perf_counter()
+        k = 0
+        while time.perf_counter() - t < 10.0 or k < 1:
+            c = S.diffuse(c, D)
+            k += 1
+        dt = time.perf_counter() - t
+        out["cpu_baseline"] = {"value": round(k * n * n / dt / 1e9, 4), "unit": "Gpoints/s", "cores": 1,
+                               "kind": "oracle", "sample": "%d steps of the fp64 numpy oracle on a 2500x2500 grid "
+                                                           "(%.1f s, one thread)" % (k, dt)}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -388,6 +462,7 @@ def main():
     ap.add_argument("--routing", default=None, help="use this routing string instead of tuning")
     ap.add_argument("--roofline-only", action="store_true", help="run only the per-launch roofline leg")
     ap.add_argument("--no-cigar", action="store_true", help="skip the alignment-path (CIGAR) leg")
+    ap.add_argument("--grid", default="2500,16384", help="stencil: square grid sizes")
     ap.add_argument("--cigar-only", action="store_true", help="run only the alignment-path leg")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy 1 GiB device to device three times (counter calibration)")
@@ -410,6 +485,9 @@ def main():
         return
     if args.workload.startswith("search_"):
         search_bench(args)
+        return
+    if args.workload == "stencil":
+        stencil_bench(args)
         return
 
     import numpy as np

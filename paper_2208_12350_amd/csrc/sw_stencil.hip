@@ -15,7 +15,8 @@
 //     strip's left and right neighbour columns);
 //   * it slides down its rows with three rows in registers, so every value
 //     is read from memory once per strip (plus 2 halo rows per 64 and 2 halo
-//     columns per 62); left and right neighbours come from the adjacent
+//     columns per 62), loading 8 rows ahead so that a wavefront keeps 8
+//     loads in flight; left and right neighbours come from the adjacent
 //     lanes through DPP wave shifts, not from memory;
 //   * the horizontal triple sum of a row, (left + centre) + right, is formed
 //     once when the row is loaded and reused for the two output rows next to
@@ -78,15 +79,26 @@ __device__ __forceinline__ void diffuse_strip(const Grid& src, const Store& stor
     float mid = src.at(x, y0);
     float l_mid = lane_left(mid), r_mid = lane_right(mid);
     float h_mid = (l_mid + mid) + r_mid;
-    for (int y = y0; y < y1; ++y) {
-        const float down = src.at(x, y + 1);
-        const float l_down = lane_left(down), r_down = lane_right(down);
-        const float h_down = (l_down + down) + r_down;
-        const float nbrs = (h_up + h_down) + (l_mid + r_mid);
-        const float v = fmaf(share, nbrs, keep * mid);
-        if (out_lane) store(x, y, v);
-        h_up = h_mid;
-        mid = down; l_mid = l_down; r_mid = r_down; h_mid = h_down;
+    // rows are loaded kAhead at a time, so that many loads of a wavefront
+    // are in flight together (a row past the grid reads the last border
+    // row, or 0, and is never used)
+    constexpr int kAhead = 8;
+    for (int y = y0; y < y1; y += kAhead) {
+        float next[kAhead];
+#pragma unroll
+        for (int k = 0; k < kAhead; ++k) next[k] = src.at(x, y + 1 + k < ny ? y + 1 + k : ny);
+#pragma unroll
+        for (int k = 0; k < kAhead; ++k) {
+            if (y + k >= y1) break;
+            const float down = next[k];
+            const float l_down = lane_left(down), r_down = lane_right(down);
+            const float h_down = (l_down + down) + r_down;
+            const float nbrs = (h_up + h_down) + (l_mid + r_mid);
+            const float v = fmaf(share, nbrs, keep * mid);
+            if (out_lane) store(x, y + k, v);
+            h_up = h_mid;
+            mid = down; l_mid = l_down; r_mid = r_down; h_mid = h_down;
+        }
     }
 }
 

@@ -390,9 +390,11 @@ def stencil_bench(args):
         rng = torch.Generator(device="cuda").manual_seed(n)
         g = torch.rand((n, n), generator=rng, device="cuda", dtype=torch.float32)
         res = {}
-        for form in ("padded", "checked"):
-            if form == "padded":
-                a = K.pad(g)
+        # "padded_1col": the same padded step with a pitch that is not a
+        # multiple of 4, which selects the kernel with one column per lane
+        for form in ("padded", "checked", "padded_1col"):
+            if form.startswith("padded"):
+                a = K.pad(g, K.padded_pitch(n) + (1 if form == "padded_1col" else 0))
                 b = a.clone()
                 step = lambda s, d: K.diffuse_padded(s, d, n, n, D)
             else:
@@ -410,13 +412,14 @@ def stencil_bench(args):
             e1.record()
             torch.cuda.synchronize()
             ms = e0.elapsed_time(e1) / steps
-            res[form] = (ms, a if form == "padded" else a)
+            res[form] = (ms, a[1:n + 1, 1:n + 1] if form.startswith("padded") else a)
             del b
-        out_p = res["padded"][1][1:n + 1, 1:n + 1]
-        assert torch.equal(out_p, res["checked"][1]), "padded and checked grids differ"
+        assert torch.equal(res["padded"][1], res["checked"][1]), "padded and checked grids differ"
+        assert torch.equal(res["padded"][1], res["padded_1col"][1]), "4- and 1-column kernels differ"
         pts = n * n
         ms_p, ms_c = res["padded"][0], res["checked"][0]
         rows.append({"grid": "%dx%d" % (n, n), "step_ms_padded": round(ms_p, 4), "step_ms_checked": round(ms_c, 4),
+                     "step_ms_padded_1col": round(res["padded_1col"][0], 4),
                      "gpoints_per_s_padded": round(pts / ms_p / 1e6, 2),
                      "gpoints_per_s_checked": round(pts / ms_c / 1e6, 2),
                      "padding_speedup": round(ms_c / ms_p, 3),

@@ -36,12 +36,15 @@ extern "C" {
 
 /* One diffusion step on the padded layout: reads the nx x ny interior of
  * `src` and its zero border (no bounds checks), writes the interior of
- * `dst` (its border is left as it is). */
+ * `dst` (its border is left as it is).  With pitch a multiple of 4 and both
+ * pointers 16-byte aligned, each lane handles 4 columns (16-byte accesses);
+ * the results are the same either way. */
 int sw_diffuse_padded(const float* src, float* dst, int32_t nx, int32_t ny, int32_t pitch, float D,
                       void* stream);
 
 /* The same step on the unpadded layout: every neighbour read is checked
- * against the grid bounds and reads as 0 outside. */
+ * against the grid bounds and reads as 0 outside.  With nx a multiple of 4
+ * and both pointers 16-byte aligned, each lane handles 4 columns. */
 int sw_diffuse_checked(const float* src, float* dst, int32_t nx, int32_t ny, float D, void* stream);
 
 /* Copy an unpadded nx x ny grid into the padded layout, writing the zero

@@ -21,7 +21,11 @@
 //   * the horizontal triple sum of a row, (left + centre) + right, is formed
 //     once when the row is loaded and reused for the two output rows next to
 //     it, so a point costs one load, two lane shifts, seven adds and one
-//     multiply-add.
+//     multiply-add;
+//   * on 16-byte aligned rows (a padded pitch, or an unpadded width, that is
+//     a multiple of 4 floats) each lane holds 4 columns instead
+//     (diffuse_strip4), so a wavefront reads and writes 1 KiB per
+//     instruction.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -102,6 +106,163 @@ __device__ __forceinline__ void diffuse_strip(const Grid& src, const Store& stor
     }
 }
 
+// The 4-columns-per-lane form (one 16-byte load per lane and row, 1 KiB per
+// wavefront instruction).  Lane l of strip s holds the aligned group of
+// columns x0 = kSpan * s + 4 l - kOff .. x0 + 3; lanes 0 and 63 supply the
+// strip's halo and the outputs are the kSpan columns with local index
+// 4 l + k in [kOff, kOff + kSpan).  On the padded grid the group starts one
+// column left of an aligned padded column (kOff = 1, 252 outputs of 256
+// columns); on the unpadded grid whole groups are the halo (kOff = 4, 248
+// outputs).  Every output is formed by the same expression, in the same
+// order, as in diffuse_strip, so all forms give bit-identical grids.
+//
+// Memory behaviour, chosen by timing repeated steps (each reading the grid
+// the previous one wrote) on 2500^2 .. 16384^2 grids; the thresholds are
+// the 256 MB last-level cache (MALL):
+//   * source and destination fit in it together: ordinary loads and stores,
+//     8 rows per wavefront, so the next step reads from cache;
+//   * the source fits in twice its size: ordinary loads (halo rows and
+//     columns that neighbouring strips share hit in cache), nontemporal
+//     stores, 8 rows per wavefront;
+//   * larger: nontemporal loads and stores, 16 rows per wavefront, 16 rows
+//     in flight;
+//   * consecutive blocks go to the 8 XCDs in turn, so block b runs tile
+//     (b mod 8) * (blocks / 8) + b / 8: each XCD's L2 holds one contiguous
+//     band of strips and rows, and strips that share a halo share an L2.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+template <bool STREAM>
+__device__ __forceinline__ f32x4 load4(const float* p) {
+    const f32x4* q = reinterpret_cast<const f32x4*>(p);
+    if constexpr (STREAM) return __builtin_nontemporal_load(q);
+    else return *q;
+}
+
+struct PaddedRows4 {
+    static constexpr int kSpan = 252, kOff = 1;
+    const float* g;
+    int pitch;
+    template <bool STREAM>
+    __device__ __forceinline__ f32x4 load(int x0, int y) const {
+        // padded row y + 1, padded columns x0 + 1 .. x0 + 4; a group past the
+        // row's end (spare lanes of the last strip) is clamped and feeds no
+        // stored output
+        const int c = x0 + 1 + 4 <= pitch ? x0 + 1 : pitch - 4;
+        return load4<STREAM>(g + (int64_t)(y + 1) * pitch + c);
+    }
+    // the zero border is in memory: nothing to fix
+    __device__ __forceinline__ f32x4 fix(f32x4 q, int, int) const { return q; }
+};
+struct CheckedRows4 {
+    static constexpr int kSpan = 248, kOff = 4;
+    const float* g;
+    int nx, ny;   // nx is a multiple of 4, so a group is wholly in or out
+    template <bool STREAM>
+    __device__ __forceinline__ f32x4 load(int x0, int y) const {
+        // an unconditional load of the nearest group inside the grid (one a
+        // neighbouring lane or row reads anyway), so that every load of a
+        // wavefront stays in flight; fix() applies the bounds test when the
+        // row is used
+        const int yc = y < 0 ? 0 : (y >= ny ? ny - 1 : y);
+        const int xc = x0 < 0 ? 0 : (x0 >= nx ? nx - 4 : x0);
+        return load4<STREAM>(g + (int64_t)yc * nx + xc);
+    }
+    __device__ __forceinline__ f32x4 fix(f32x4 q, int x0, int y) const {
+        return (y >= 0 && y < ny && x0 >= 0 && x0 < nx) ? q : f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    }
+};
+struct PaddedStore4 {
+    float* g;
+    int pitch;
+    __device__ __forceinline__ float* at(int x0, int y) const { return g + (int64_t)(y + 1) * pitch + x0 + 1; }
+};
+struct PlainStore4 {
+    float* g;
+    int nx;
+    __device__ __forceinline__ float* at(int x0, int y) const { return g + (int64_t)y * nx + x0; }
+};
+
+template <int AHEAD, bool STREAM, bool STREAM_OUT, class Rows, class Store>
+__device__ __forceinline__ void diffuse_strip4(const Rows& src, const Store& dst, int nx, int ny, int rows,
+                                               float keep, float share) {
+    constexpr int kSpan = Rows::kSpan, kOff = Rows::kOff;
+    const int per_xcd = (int)gridDim.x / 8;   // gridDim.x is a multiple of 8
+    const int tile = ((int)blockIdx.x % 8) * per_xcd + (int)blockIdx.x / 8;
+    const int lane = threadIdx.x & 63;
+    const int wave = tile * 4 + (int)(threadIdx.x >> 6);
+    const int strips = (nx + kSpan - 1) / kSpan;
+    const int strip = wave % strips;
+    const int y0 = (wave / strips) * rows;
+    if (y0 >= ny) return;
+    const int y1 = y0 + rows < ny ? y0 + rows : ny;
+    const int x0 = strip * kSpan + 4 * lane - kOff;
+    bool out[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) out[k] = 4 * lane + k >= kOff && 4 * lane + k < kOff + kSpan && x0 + k < nx;
+    const bool full = out[0] && out[3];
+    // a row's values, side neighbours and horizontal triple sums
+    struct Row { float v[4], l[4], r[4], h[4]; };
+    auto prep = [&](const f32x4 q) {
+        Row w;
+        w.v[0] = q.x; w.v[1] = q.y; w.v[2] = q.z; w.v[3] = q.w;
+        const float from_left = lane_left(w.v[3]), from_right = lane_right(w.v[0]);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            w.l[k] = k > 0 ? w.v[k - 1] : from_left;
+            w.r[k] = k < 3 ? w.v[k + 1] : from_right;
+            w.h[k] = (w.l[k] + w.v[k]) + w.r[k];
+        }
+        return w;
+    };
+    Row up = prep(src.fix(src.template load<STREAM>(x0, y0 - 1), x0, y0 - 1));
+    Row mid = prep(src.fix(src.template load<STREAM>(x0, y0), x0, y0));
+    for (int y = y0; y < y1; y += AHEAD) {
+        f32x4 next[AHEAD];
+#pragma unroll
+        for (int k = 0; k < AHEAD; ++k) next[k] = src.template load<STREAM>(x0, y + 1 + k < ny ? y + 1 + k : ny);
+#pragma unroll
+        for (int k = 0; k < AHEAD; ++k) {
+            if (y + k >= y1) break;
+            const Row down = prep(src.fix(next[k], x0, y + 1 + k));
+            float v[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const float nbrs = (up.h[e] + down.h[e]) + (mid.l[e] + mid.r[e]);
+                v[e] = fmaf(share, nbrs, keep * mid.v[e]);
+            }
+            float* d = dst.at(x0, y + k);
+            if (full) {
+                const f32x4 o = {v[0], v[1], v[2], v[3]};
+                if constexpr (STREAM_OUT) __builtin_nontemporal_store(o, reinterpret_cast<f32x4*>(d));
+                else *reinterpret_cast<f32x4*>(d) = o;
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (out[e]) d[e] = v[e];
+            }
+            up = mid;
+            mid = down;
+        }
+    }
+}
+
+constexpr int64_t kCacheBytes = (int64_t)256 << 20;
+constexpr int kRowsCached = 8, kRowsStream = 16;
+
+template <int AHEAD, bool STREAM, bool STREAM_OUT>
+__global__ __launch_bounds__(256) void diffuse_padded4_kernel(const float* src, float* dst, int nx, int ny, int pitch,
+                                                              int rows, float keep, float share) {
+    diffuse_strip4<AHEAD, STREAM, STREAM_OUT>(PaddedRows4{src, pitch}, PaddedStore4{dst, pitch}, nx, ny, rows, keep,
+                                              share);
+}
+
+template <int AHEAD, bool STREAM, bool STREAM_OUT>
+__global__ __launch_bounds__(256) void diffuse_checked4_kernel(const float* src, float* dst, int nx, int ny, int rows,
+                                                               float keep, float share) {
+    diffuse_strip4<AHEAD, STREAM, STREAM_OUT>(CheckedRows4{src, nx, ny}, PlainStore4{dst, nx}, nx, ny, rows, keep,
+                                              share);
+}
+
 struct PaddedStore {
     float* g;
     int pitch;
@@ -131,15 +292,49 @@ __global__ void pad_grid_kernel(const float* grid, float* padded, int nx, int ny
     }
 }
 
-unsigned waves_blocks(int nx, int ny) {
-    const int64_t strips = (nx + kStrip - 1) / kStrip;
-    const int64_t waves = strips * ((ny + kRows - 1) / kRows);
+unsigned waves_blocks(int nx, int ny, int span, int rows = kRows) {
+    const int64_t strips = (nx + span - 1) / span;
+    const int64_t waves = strips * ((ny + rows - 1) / rows);
     return (unsigned)((waves + 3) / 4);
 }
+
+// blocks of the 4-column kernels: a multiple of 8 (the XCD-grouped order)
+unsigned blocks4(int nx, int ny, int span, int rows) { return (waves_blocks(nx, ny, span, rows) + 7) / 8 * 8; }
+
+bool aligned16(const void* a, const void* b) { return ((uintptr_t)a | (uintptr_t)b) % 16 == 0; }
 
 bool bad_args(const void* a, const void* b, int nx, int ny, float D) {
     return !a || !b || nx < 1 || ny < 1 || !(D >= 0.0f && D <= 1.0f) || (int64_t)nx * ny > ((int64_t)1 << 40);
 }
+
+// Launches the 4-column kernel of the memory regime that an array of
+// `bytes` bytes falls in.
+template <template <int, bool, bool> class K, class... Args>
+void launch4(int64_t bytes, int nx, int ny, int span, hipStream_t st, Args... args) {
+    if (2 * bytes <= kCacheBytes)
+        K<8, false, false>::launch(blocks4(nx, ny, span, kRowsCached), st, kRowsCached, args...);
+    else if (bytes <= 2 * kCacheBytes)
+        K<8, false, true>::launch(blocks4(nx, ny, span, kRowsCached), st, kRowsCached, args...);
+    else
+        K<16, true, true>::launch(blocks4(nx, ny, span, kRowsStream), st, kRowsStream, args...);
+}
+
+template <int A, bool S, bool SO>
+struct Padded4 {
+    static void launch(unsigned blocks, hipStream_t st, int rows, const float* src, float* dst, int nx, int ny,
+                       int pitch, float keep, float share) {
+        hipLaunchKernelGGL((diffuse_padded4_kernel<A, S, SO>), dim3(blocks), dim3(256), 0, st, src, dst, nx, ny, pitch,
+                           rows, keep, share);
+    }
+};
+template <int A, bool S, bool SO>
+struct Checked4 {
+    static void launch(unsigned blocks, hipStream_t st, int rows, const float* src, float* dst, int nx, int ny,
+                       float keep, float share) {
+        hipLaunchKernelGGL((diffuse_checked4_kernel<A, S, SO>), dim3(blocks), dim3(256), 0, st, src, dst, nx, ny,
+                           rows, keep, share);
+    }
+};
 
 }  // namespace
 
@@ -147,15 +342,26 @@ extern "C" {
 
 int sw_diffuse_padded(const float* src, float* dst, int32_t nx, int32_t ny, int32_t pitch, float D, void* stream) {
     if (bad_args(src, dst, nx, ny, D) || pitch < nx + 2) return -1;
-    hipLaunchKernelGGL(diffuse_padded_kernel, dim3(waves_blocks(nx, ny)), dim3(256), 0, (hipStream_t)stream, src, dst,
-                       nx, ny, pitch, 1.0f - D, D / 8.0f);
+    const hipStream_t st = (hipStream_t)stream;
+    const float keep = 1.0f - D, share = D / 8.0f;
+    if (pitch % 4 != 0 || !aligned16(src, dst))
+        hipLaunchKernelGGL(diffuse_padded_kernel, dim3(waves_blocks(nx, ny, kStrip)), dim3(256), 0, st, src, dst, nx,
+                           ny, pitch, keep, share);
+    else
+        launch4<Padded4>((int64_t)(ny + 2) * pitch * 4, nx, ny, PaddedRows4::kSpan, st, src, dst, nx, ny, pitch, keep,
+                         share);
     return hipGetLastError() == hipSuccess ? 0 : -4;
 }
 
 int sw_diffuse_checked(const float* src, float* dst, int32_t nx, int32_t ny, float D, void* stream) {
     if (bad_args(src, dst, nx, ny, D)) return -1;
-    hipLaunchKernelGGL(diffuse_checked_kernel, dim3(waves_blocks(nx, ny)), dim3(256), 0, (hipStream_t)stream, src,
-                       dst, nx, ny, 1.0f - D, D / 8.0f);
+    const hipStream_t st = (hipStream_t)stream;
+    const float keep = 1.0f - D, share = D / 8.0f;
+    if (nx % 4 != 0 || !aligned16(src, dst))
+        hipLaunchKernelGGL(diffuse_checked_kernel, dim3(waves_blocks(nx, ny, kStrip)), dim3(256), 0, st, src, dst, nx,
+                           ny, keep, share);
+    else
+        launch4<Checked4>((int64_t)ny * nx * 4, nx, ny, CheckedRows4::kSpan, st, src, dst, nx, ny, keep, share);
     return hipGetLastError() == hipSuccess ? 0 : -4;
 }
 

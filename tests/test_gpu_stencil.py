@@ -13,13 +13,13 @@ from oracle import stencil as S
 pytestmark = pytest.mark.gpu
 
 
-def run(grid, D, steps, padded):
+def run(grid, D, steps, padded, pitch=None):
     import torch
     from paper_2208_12350_amd import stencil as K
     g = torch.from_numpy(np.ascontiguousarray(grid, dtype=np.float32)).cuda()
     ny, nx = g.shape
     if padded:
-        a = K.pad(g)
+        a = K.pad(g, pitch)
         b = a.clone()
         for _ in range(steps):
             K.diffuse_padded(a, b, nx, ny, D)
@@ -48,6 +48,25 @@ def test_one_step_matches_oracle_and_forms_agree(shape):
         q = run(c, D, 1, False)
         assert np.array_equal(p, q)                       # same arithmetic, bounds logic aside
         assert np.max(np.abs(p - want)) <= 1e-6
+
+
+# row widths around the 4-column kernel's 252-column strips, and pitches
+# that select it (a multiple of 4, the tightest one included) or the
+# 1-column kernel (any other pitch)
+WIDE = [(5, 2, 4), (5, 2, 5), (7, 250, 252), (7, 251, 256), (7, 252, 254), (7, 253, 256), (9, 254, 256),
+        (9, 254, 257), (3, 504, 508), (3, 505, 507), (66, 1000, 1024), (66, 1000, 1003)]
+
+
+@pytest.mark.parametrize("shape", WIDE)
+def test_pitch_choices_give_identical_steps(shape):
+    ny, nx, pitch = shape
+    rng = np.random.default_rng(ny * 7919 + nx * 31 + pitch)
+    c = rng.random((ny, nx)).astype(np.float32)
+    D = 0.3
+    want = S.diffuse(c.astype(np.float64), D, 3)
+    got = run(c, D, 3, True, pitch)
+    assert np.array_equal(got, run(c, D, 3, False))
+    assert np.max(np.abs(got - want)) <= 3e-6
 
 
 def test_many_steps_and_a_point_source():
@@ -82,3 +101,37 @@ def test_paper_grid_size_sampled():
     p = run(c, D, steps, True)
     assert np.max(np.abs(p - want)) <= 1e-6 * steps
     assert np.array_equal(p, run(c, D, steps, False))
+
+
+def test_streaming_size_sampled():
+    # a grid whose arrays exceed 512 MiB takes the streaming-load kernels;
+    # padded, bounds-checked and 1-column forms must agree bit for bit, and
+    # windows of the result (corners, edges, interior) match the oracle run
+    # on the window with its 1-point halo
+    import torch
+    from paper_2208_12350_amd import stencil as K
+    ny, nx, D = 11800, 11600, 0.2
+    assert nx * ny * 4 > 512 << 20
+    g = torch.rand((ny, nx), generator=torch.Generator(device="cuda").manual_seed(4), device="cuda")
+    outs = []
+    for pitch in (K.padded_pitch(nx), K.padded_pitch(nx) + 1):
+        a = K.pad(g, pitch)
+        b = a.clone()
+        K.diffuse_padded(a, b, nx, ny, D)
+        outs.append(b[1:ny + 1, 1:nx + 1].contiguous())
+        del a, b
+    c = torch.empty_like(g)
+    K.diffuse_checked(g, c, D)
+    torch.cuda.synchronize()
+    assert torch.equal(outs[0], outs[1]) and torch.equal(outs[0], c)
+    rng = np.random.default_rng(12)
+    wins = [(0, 0), (0, nx - 300), (ny - 64, 0), (ny - 64, nx - 300), (0, 5000), (6000, 0)]
+    wins += [(int(rng.integers(1, ny - 65)), int(rng.integers(1, nx - 301))) for _ in range(6)]
+    for y, x in wins:
+        ya, yb, xa, xb = max(y - 1, 0), min(y + 65, ny), max(x - 1, 0), min(x + 301, nx)
+        src = g[ya:yb, xa:xb].cpu().numpy().astype(np.float64)
+        want = S.diffuse(src, D)[y - ya:y - ya + 64, x - xa:x - xa + 300]
+        # the window's own edge rows/columns inside the grid lack their outer
+        # neighbours; only the centre 64 x 300 points are compared
+        got = c[y:y + 64, x:x + 300].cpu().numpy()
+        assert np.max(np.abs(got - want)) <= 1e-6, (y, x)

@@ -187,14 +187,14 @@ def cigar_leg(args, db, out, ref_out, tuning, score_ms):
         sweep_ms.append(sm); walk_ms.append(wm)
         for e in alt.bin_stats():
             if e["pass"] == 2 and e["pairs"]:
-                acc = per_bin.setdefault((e["precision"], e["lanes"], e["rows"]), [0.0, 0])
+                acc = per_bin.setdefault((e["precision"], e["lanes"], e["rows"], e["column"]), [0.0, 0])
                 acc[0] += e["ms"]; acc[1] += e["cells"]
     alt.close()
-    (P_, W_, R_), (dms, dcells) = max(per_bin.items(), key=lambda kv: kv[1][0])
+    (P_, W_, R_, C_), (dms, dcells) = max(per_bin.items(), key=lambda kv: kv[1][0])
     peak = VALU_INT16X2_TOPS if P_ == 16 else VALU_INT32_TOPS
     achieved = PATH_OPS_PER_CELL * dcells / (dms / 1e3) / 1e12
     launches = reps * chunks
-    kernel_name = "sw::sw_trace_kernel<%d, %d, %d>" % (P_, W_, R_)
+    kernel_name = "sw::sw_trace_kernel<%d, %d, %d, %s>" % (P_, W_, R_, "true" if C_ else "false")
     log("  paths: %d calls in %.3f s" % (steps, el))
     return {"value": round(fwd * steps / el / 1e9, 2), "unit": "GCUPS",
             "ms_per_call": round(el * 1e3 / steps, 3), "score_only_ms": round(score_ms, 3),

@@ -230,8 +230,11 @@ int sw_align_cigar(sw_handle* h, const sw_batch* batch, const sw_scheme* schemes
  * of (q_end-q_start+1)*(r_end-r_start+1)), bytes of path records, chunks,
  * and with the "timing" option (which serialises the launches) the device
  * milliseconds of the box sweeps and of the walks; the box sweeps of each
- * shape are also the entries of sw_last_bin_stats with pass 2.  Any pointer
- * may be NULL. */
+ * shape are also the entries of sw_last_bin_stats with pass 2 (packed
+ * int16 shapes have a column-word kernel, used when every scheme of the
+ * call has at most four residues whose scores plus the gap open cost fit a
+ * byte, beside the table-lookup one; both write the same records).  Any
+ * pointer may be NULL. */
 int sw_last_cigar_stats(sw_handle* h, int64_t* box_cells, int64_t* record_bytes, int32_t* chunks,
                         float* sweep_ms, float* walk_ms);
 

@@ -212,7 +212,7 @@ struct TraceArgs {
 // R a multiple of 4).
 using TraceFn = void (*)(KParams, TraceArgs);
 const ShapeDesc* trace_shapes(int* n);
-TraceFn trace_kernel(int prec, int W, int R);
+TraceFn trace_kernel(int prec, int W, int R, bool col = false);
 // Records are written in blocks of kStage sweep steps.
 constexpr int kStage = 8;
 // Record bytes of a box of m columns on shape (W, R): m + W - 1 sweep steps

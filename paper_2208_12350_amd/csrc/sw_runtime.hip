@@ -119,6 +119,8 @@ struct sw_handle {
     // alignment paths (sw_align_cigar)
     std::vector<BinInfo> tbins;          // path-sweep shapes
     std::vector<int> tresident;          // workgroups the device holds at once, per path-sweep bin
+    std::vector<int> tresident_col;      // and for its column-word kernel
+    int32_t last_col_ok[SW_MAX_SCHEMES] = {0};   // column-word eligibility of the last score call's schemes
     BinInfo* d_tbins = nullptr;
     int8_t* d_tlut = nullptr;            // [2 * kLutRows] path-sweep bin per (precision, 16-row bucket of box rows)
     int64_t* d_rec_off = nullptr;        // [trace_cap + 1]
@@ -407,7 +409,7 @@ static bool init_paths(sw_handle* h) {
         b.W = (uint16_t)sh[k].W;
         b.R = (uint8_t)sh[k].R;
         b.ppw = (uint16_t)pairs_per_item(sh[k].prec, sh[k].W);
-        b.col = 0;
+        b.col = trace_kernel(sh[k].prec, sh[k].W, sh[k].R, true) != nullptr ? 1 : 0;
         b.pad = 0;
         h->tbins.push_back(b);
     }
@@ -429,12 +431,17 @@ static bool init_paths(sw_handle* h) {
             lut[sel * kLutRows + k] = (int8_t)best;
         }
     h->tresident.assign(h->tbins.size(), 1);
+    h->tresident_col.assign(h->tbins.size(), 1);
     for (size_t b = 0; b < h->tbins.size(); ++b) {
-        int per_cu = 0;
-        const TraceFn fn = trace_kernel(h->tbins[b].prec, h->tbins[b].W, h->tbins[b].R);
-        if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)fn, kBlock, 0) != hipSuccess)
-            return false;
-        h->tresident[b] = std::max(1, per_cu) * std::max(1, h->n_cu);
+        for (int v = 0; v < 2; ++v) {
+            if (v == 1 && !h->tbins[b].col) continue;
+            int per_cu = 0;
+            const TraceFn fn = trace_kernel(h->tbins[b].prec, h->tbins[b].W, h->tbins[b].R, v == 1);
+            if (!fn ||
+                hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)fn, kBlock, 0) != hipSuccess)
+                return false;
+            (v ? h->tresident_col : h->tresident)[b] = std::max(1, per_cu) * std::max(1, h->n_cu);
+        }
     }
     bool ok = hipMalloc(&h->d_tbins, kMaxBins * sizeof(BinInfo)) == hipSuccess &&
               hipMalloc(&h->d_tlut, 2 * kLutRows) == hipSuccess &&
@@ -716,6 +723,7 @@ static int align_spans(sw_handle* h, const uint8_t* queries, const int64_t* q_be
         K.gap_extend[s] = v ? schemes[s].gap_extend : 0;
         K.col_ok[s] = C.col_ok[s] && h->opt_colpath;
         C.col_ok[s] = K.col_ok[s];
+        h->last_col_ok[s] = K.col_ok[s];
     }
 
     const bool timing = h->opt_timing != 0;
@@ -1004,6 +1012,14 @@ static int trace_paths(sw_handle* h, const sw_batch* batch, const sw_scheme* sch
         K.gap_open[s] = v ? schemes[s].gap_open : 1;
         K.gap_extend[s] = v ? schemes[s].gap_extend : 0;
     }
+    // The column-word path sweep takes a call only when every scheme can use
+    // it (the score call just made uploaded their column words): each packed
+    // bin then runs its column-word kernel alone.  Splitting a bin's pairs
+    // between the two kernels costs more in launch tails (each kernel waits
+    // for its own longest box) than the column words save.
+    bool all_col = n_schemes > 0;
+    for (int s = 0; s < n_schemes && s < SW_MAX_SCHEMES; ++s) all_col = all_col && h->last_col_ok[s] != 0;
+    for (int s = 0; s < SW_MAX_SCHEMES; ++s) K.col_ok[s] = all_col && s < n_schemes ? 1 : 0;
     TraceArgs T;
     memset(&T, 0, sizeof(T));
     T.rec_off = h->d_rec_off;
@@ -1071,11 +1087,15 @@ static int trace_paths(sw_handle* h, const sw_batch* batch, const sw_scheme* sch
         for (int b = n_tb - 1; b >= 0; --b) {
             const BinInfo& e = h->tbins[b];
             const int64_t need = (cap / e.ppw + 1 + kWavesPerBlock - 1) / kWavesPerBlock;
-            const int blocks = (int)std::min<int64_t>(need, h->tresident[b]);
-            set_range(K, b, 0);
             hipStream_t ls = forks > 1 ? h->fork[launched++ % forks] : stream;
             if (timing) HIP_TRY(h, hipEventRecord(h->tbin_ev[3 * b], ls));
-            hipLaunchKernelGGL(trace_kernel(e.prec, e.W, e.R), dim3(blocks), dim3(kBlock), 0, ls, K, T);
+            // the column-word kernel takes the bin's small-alphabet items,
+            // the table kernel the rest; a kernel with no items returns at once
+            // one kernel per bin: the column-word one when the call allows it
+            const int v = e.col && all_col ? 1 : 0;
+            const int blocks = (int)std::min<int64_t>(need, (v ? h->tresident_col : h->tresident)[b]);
+            set_range(K, b, v);
+            hipLaunchKernelGGL(trace_kernel(e.prec, e.W, e.R, v == 1), dim3(blocks), dim3(kBlock), 0, ls, K, T);
             HIP_TRY(h, hipGetLastError());
             if (timing) HIP_TRY(h, hipEventRecord(h->tbin_ev[3 * b + 1], ls));
             HIP_TRY(h, launch_trace_walk(K, T, b, walk_blocks, path_off, path, path_len, ls));
@@ -1109,6 +1129,7 @@ static int trace_paths(sw_handle* h, const sw_batch* batch, const sw_scheme* sch
         st.precision = h->tbins[b].prec;
         st.lanes = h->tbins[b].W;
         st.rows = h->tbins[b].R;
+        st.column = h->tbins[b].col && all_col ? 1 : 0;
         st.pairs = (int64_t)cnt[kCtrTraceBinPairs + b];
         st.cells = (int64_t)cnt[kCtrTraceBinCells + b];
         st.ms = bin_ms[b];

@@ -439,18 +439,178 @@ __device__ __forceinline__ void sweep_trace_i16(const KParams& P, const TraceArg
     }
 }
 
+// Small-alphabet ("column word") form of sweep_trace_i16, for wave items
+// whose pairs all use schemes with at most four residues whose scores plus
+// the gap open cost fit a byte.  The reference is staged as one 32-bit word
+// per column holding M[a][b] + o for a = 0..3, so a row's score is one
+// v_perm_b32 of the two pairs' words with the row's selector; rows past the
+// box and padding columns read a zero byte, i.e. a score of -o <= -1, as
+// the padding code does in the table form.  Each row keeps Hm = H - o:
+// H(i-1, j-1) + M = Hm(i-1, j-1) + (M + o), and Hm is what E, F, the lane
+// exchange and the E-extends test need.  Every H, E and F, and therefore
+// every record bit, equals the table form's.
+template <int W, int R>
+__device__ __forceinline__ void sweep_trace_i16_col(const KParams& P, const TraceArgs& T, const SchemeLds& S,
+                                                    uint16_t* wbuf, uint32_t* stg, int first, int count,
+                                                    int lane) {
+    constexpr int NW = R / 8;
+    constexpr int G = 64 / W;
+    const RecordStage<W, R, 2 * G> rs{stg};
+    constexpr uint32_t K = kI16Bias;
+    constexpr uint32_t K2 = K | (K << 16);
+    using Stager = RefStager<W>;
+    const int g = lane / W;
+    const int l = lane % W;
+
+    const int slot = g * 2;
+    const int pairA = slot < count ? P.order[first + slot] : -1;
+    const int pairB = slot + 1 < count ? P.order[first + slot + 1] : -1;
+    PairJob JA = box_job(P, pairA, W * R);
+    PairJob JB = box_job(P, pairB, W * R);
+    uint32_t* recA = trace_record(P, T, pairA, JA, W, R);
+    uint32_t* recB = trace_record(P, T, pairB, JB, W, R);
+    const int stepsA = JA.m > 0 ? JA.m + W - 1 : 0;
+    const int stepsB = JB.m > 0 ? JB.m + W - 1 : 0;
+    int mmax = imax(JA.m, JB.m);
+    for (int off = 32; off > 0; off >>= 1) mmax = imax(mmax, __shfl_xor(mmax, off));
+    const int steps = __builtin_amdgcn_readfirstlane(mmax > 0 ? mmax + W - 1 : 0);
+
+    // 32-bit column words: the wave buffer holds twice as many bytes
+    uint32_t* bufA = reinterpret_cast<uint32_t*>(wbuf) + (g * 2) * Stager::kBuf;
+    uint32_t* bufB = bufA + Stager::kBuf;
+    Stager stA, stB;
+    stA.load(P.refs, JA, P.order, 0, l);
+    stB.load(P.refs, JB, P.order, 0, l);
+    const int AA = S.alphabet[JA.sid], AB = S.alphabet[JB.sid];
+    // per-row selectors: byte 0 picks pair A's score from its column word
+    // (bytes 0..3 of the perm input), byte 2 pair B's (bytes 4..7); bytes 1
+    // and 3, and a row past the box, select zero (0x0C)
+    uint32_t sel[R];
+    {
+        int rawA[R], rawB[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int i = l * R + r;
+            const int iA = i < JA.n ? i : (JA.n > 0 ? JA.n - 1 : 0);
+            const int iB = i < JB.n ? i : (JB.n > 0 ? JB.n - 1 : 0);
+            const uint8_t* pA = JA.n > 0 ? P.queries + JA.qbase + iA : reinterpret_cast<const uint8_t*>(P.order);
+            const uint8_t* pB = JB.n > 0 ? P.queries + JB.qbase + iB : reinterpret_cast<const uint8_t*>(P.order);
+            rawA[r] = *pA;
+            rawB[r] = *pB;
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int i = l * R + r;
+            const uint32_t a = (i < JA.n && rawA[r] < AA) ? (uint32_t)rawA[r] : 0x0Cu;
+            const uint32_t b = (i < JB.n && rawB[r] < AB) ? (uint32_t)(4 + rawB[r]) : 0x0Cu;
+            sel[r] = a | 0x0C00u | (b << 16) | 0x0C000000u;
+        }
+    }
+    bool bad = false;   // residues were checked by the score passes
+    stA.store_col(bufA, JA, AA, S.colw[JA.sid], 0, l, bad);
+    stB.store_col(bufB, JB, AB, S.colw[JB.sid], 0, l, bad);
+    const uint32_t goA = (uint32_t)S.gap_open[JA.sid], goB = (uint32_t)S.gap_open[JB.sid];
+    const u16x2 go2 = pk(goA | (goB << 16));
+    const u16x2 ge2 = pk((uint32_t)S.gap_extend[JA.sid] | ((uint32_t)S.gap_extend[JB.sid] << 16));
+    const u16x2 zero = pk(K2);
+    const uint32_t hm_top = (K - goA) | ((K - goB) << 16);   // Hm of the zero boundary
+    wave_lds_sync();
+
+    // Hm[r]: H - o of row r at the last column swept; E[r]: E of row r at the
+    // next column
+    u16x2 Hm[R], E[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) { Hm[r] = pk(hm_top); E[r] = zero; }
+    uint32_t Hlast = hm_top, Flast = K2, Hup_prev = hm_top;
+    const uint32_t* rblA = bufA + W - l;   // rblA[tt] = column word of step t0 + tt
+    const uint32_t* rblB = bufB + W - l;
+    uint32_t nxA = rblA[0], nxB = rblB[0];
+    for (int t0 = 0; t0 < steps; t0 += kChunk) {
+        const bool more = t0 + kChunk < steps;
+        if (more) {
+            stA.load(P.refs, JA, P.order, t0 + kChunk, l);
+            stB.load(P.refs, JB, P.order, t0 + kChunk, l);
+        }
+        const int tn = __builtin_amdgcn_readfirstlane(steps - t0 < kChunk ? steps - t0 : kChunk);
+        for (int tt = 0; tt < tn; ++tt) {
+            const uint32_t ca = nxA, cb = nxB;
+            nxA = rblA[tt + 1];
+            nxB = rblB[tt + 1];
+            const u16x2 Hmu0 = pk((uint32_t)shift_in_group<W>((int)Hlast, (int)hm_top));
+            // F above the group is 0 (K); a zero fill gives the same F below
+            // because of the max with K
+            const u16x2 Fup = pk((uint32_t)shift_in_group_zero<W>((int)Flast));
+            u16x2 diag = pk(Hup_prev);
+            Hup_prev = u32(Hmu0);
+            u16x2 Hmu = Hmu0;
+            u16x2 F = Fup;
+            uint32_t w[R / 4];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                F = pk_max3(pk_sat_sub(F, ge2), Hmu, zero);
+                const u16x2 d = diag + pk(__builtin_amdgcn_perm(cb, ca, sel[r]));
+                const u16x2 h = pk_max3(d, E[r], F);
+                const u16x2 nd = pk_ne01(h ^ d);
+                const u16x2 nf = pk_ne01(h ^ F);
+                const u16x2 fx = pk_ne01(F ^ Hmu);
+                const u16x2 ex = pk_ne01(E[r] ^ Hm[r]);
+                const uint32_t nib = (u32(nd << nf) | (u32(fx) << 2)) | (u32(ex) << 3);
+                if (r % 4 == 0) w[r / 4] = nib;
+                else w[r / 4] |= nib << (4 * (r % 4));
+                diag = Hm[r];
+                Hmu = h - go2;
+                Hm[r] = Hmu;
+                E[r] = pk_max3(pk_sat_sub(E[r], ge2), Hmu, zero);
+            }
+            Hlast = u32(Hm[R - 1]);
+            Flast = u32(F);
+            uint32_t va[NW + 1], vb[NW + 1];
+#pragma unroll
+            for (int k = 0; k < NW; ++k) {
+                va[k] = __builtin_amdgcn_perm(w[2 * k + 1], w[2 * k], 0x05040100u);
+                vb[k] = __builtin_amdgcn_perm(w[2 * k + 1], w[2 * k], 0x07060302u);
+            }
+            const uint32_t tail = w[R / 4 - 1];
+            const int t = t0 + tt;
+            rs.put(2 * g, l, t, va, tail);
+            rs.put(2 * g + 1, l, t, vb, tail >> 16);
+            if ((t & (kStage - 1)) == kStage - 1 || t == steps - 1) {
+                wave_lds_sync();
+#pragma unroll
+                for (int p = 0; p < 2 * G; ++p) {
+                    uint32_t* rp = readlane_ptr((p & 1) ? recB : recA, (p / 2) * W);
+                    const int sp = __builtin_amdgcn_readlane((p & 1) ? stepsB : stepsA, (p / 2) * W);
+                    if (rp && (t & ~(kStage - 1)) < sp) rs.flush(p, rp, t / kStage, lane);
+                }
+                wave_lds_sync();
+            }
+        }
+        if (more) {
+            wave_lds_sync();
+            stA.store_col(bufA, JA, AA, S.colw[JA.sid], t0 + kChunk, l, bad);
+            stB.store_col(bufB, JB, AB, S.colw[JB.sid], t0 + kChunk, l, bad);
+            wave_lds_sync();
+            nxA = rblA[0];
+            nxB = rblB[0];
+        }
+    }
+}
+
 // LDS reference buffer of one wavefront (16-bit entries): four 16-lane
 // groups of two packed pairs, the widest layout.
 constexpr int kTraceWaveBuf = 8 * RefStager<16>::kBuf;
+// and of its column-word form (32-bit entries)
+constexpr int kTraceWaveBufCol = 2 * kTraceWaveBuf;
 
 // Work-queue kernel of one path-sweep shape (same fetch loop as the score
 // sweeps' queue kernels).
-template <int PREC, int W, int R>
+template <int PREC, int W, int R, bool COL>
 __global__ __launch_bounds__(kBlock) void sw_trace_kernel(KParams P, TraceArgs T) {
     constexpr int kPPW = (64 / W) * (PREC == 16 ? 2 : 1);
     constexpr int kStageDwords = RecordStage<W, R, kPPW>::kDwords;
+    constexpr int kWaveBuf = COL ? kTraceWaveBufCol : kTraceWaveBuf;
     __shared__ __attribute__((aligned(16))) SchemeLds L;
-    __shared__ uint16_t wbufs[kWavesPerBlock * kTraceWaveBuf];
+    __shared__ __attribute__((aligned(16))) uint16_t wbufs[kWavesPerBlock * kWaveBuf];
     __shared__ __attribute__((aligned(16))) uint32_t stages[kWavesPerBlock * kStageDwords];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -467,7 +627,7 @@ __global__ __launch_bounds__(kBlock) void sw_trace_kernel(KParams P, TraceArgs T
     const int n_pairs = __builtin_amdgcn_readfirstlane(*P.n_dev);
     load_schemes(L, P, tid);
     __syncthreads();
-    uint16_t* wbuf = wbufs + wave * kTraceWaveBuf;
+    uint16_t* wbuf = wbufs + wave * kWaveBuf;
     for (;;) {
         const int mine = atomicAdd(&P.meta[P.head_idx], lane == 0 ? 1 : 0);
         const int it = __builtin_amdgcn_readlane(mine, 0);
@@ -478,7 +638,9 @@ __global__ __launch_bounds__(kBlock) void sw_trace_kernel(KParams P, TraceArgs T
         const bool valid = first >= 0 && count >= 1 && count <= kPPW && first + count <= n_pairs;
         if (valid) {
             wave_lds_sync();
-            if constexpr (PREC == 16)
+            if constexpr (PREC == 16 && COL)
+                sweep_trace_i16_col<W, R>(P, T, L, wbuf, stages + wave * kStageDwords, first, count, lane);
+            else if constexpr (PREC == 16)
                 sweep_trace_i16<W, R>(P, T, L, wbuf, stages + wave * kStageDwords, first, count, lane);
             else
                 sweep_trace<W, R>(P, T, L, wbuf, stages + wave * kStageDwords, first, count, lane);
@@ -493,10 +655,12 @@ __global__ __launch_bounds__(kBlock) void sw_trace_kernel(KParams P, TraceArgs T
     X(P, 64, 20) X(P, 64, 24) X(P, 64, 28) X(P, 64, 32)
 
 namespace {
-struct TraceEntry { int prec, W, R; TraceFn fn; };
-#define SW_TRACE_ENTRY(P, W, R) {P, W, R, &sw_trace_kernel<P, W, R>},
-const TraceEntry kTraceKernels[] = {SW_TRACE_SHAPES(SW_TRACE_ENTRY, 16) SW_TRACE_SHAPES(SW_TRACE_ENTRY, 32)};
-#undef SW_TRACE_ENTRY
+struct TraceEntry { int prec, W, R; TraceFn fn, col; };
+#define SW_TRACE_ENTRY16(P, W, R) {P, W, R, &sw_trace_kernel<P, W, R, false>, &sw_trace_kernel<P, W, R, true>},
+#define SW_TRACE_ENTRY32(P, W, R) {P, W, R, &sw_trace_kernel<P, W, R, false>, nullptr},
+const TraceEntry kTraceKernels[] = {SW_TRACE_SHAPES(SW_TRACE_ENTRY16, 16) SW_TRACE_SHAPES(SW_TRACE_ENTRY32, 32)};
+#undef SW_TRACE_ENTRY16
+#undef SW_TRACE_ENTRY32
 constexpr int kNumTrace = sizeof(kTraceKernels) / sizeof(kTraceKernels[0]);
 ShapeDesc g_trace_shapes[kNumTrace];
 }  // namespace
@@ -508,10 +672,10 @@ const ShapeDesc* trace_shapes(int* n) {
     return g_trace_shapes;
 }
 
-TraceFn trace_kernel(int prec, int W, int R) {
+TraceFn trace_kernel(int prec, int W, int R, bool col) {
     for (int k = 0; k < kNumTrace; ++k)
         if (kTraceKernels[k].prec == prec && kTraceKernels[k].W == W && kTraceKernels[k].R == R)
-            return kTraceKernels[k].fn;
+            return col ? kTraceKernels[k].col : kTraceKernels[k].fn;
     return nullptr;
 }
 
@@ -655,7 +819,12 @@ __global__ void sw_trace_classify_kernel(KParams P, TraceArgs T, int32_t* keys, 
             if (rows >= 1 && rows <= SW_MAX_QUERY && cols >= 1 && cols <= SW_MAX_REF) {
                 const int b = trace_bin(T, r.score, rows);
                 if (b >= 0 && b < T.n_bins) {
-                    key = b * kMBuckets + kMHalf + (kMHalf - 1 - m_bucket(cols));
+                    // pairs of column-path schemes first (the bin's
+                    // column-word kernel takes them; the host enables the
+                    // column path only when every scheme of the call has it)
+                    const int sid = P.scheme_id ? (int)P.scheme_id[i] : 0;
+                    const int col = (T.bins[b].col && sid < SW_MAX_SCHEMES && P.col_ok[sid]) ? 1 : 0;
+                    key = b * kMBuckets + (col ? 0 : kMHalf) + (kMHalf - 1 - m_bucket(cols));
                     atomicAdd(&s_cells[b], (unsigned long long)rows * (unsigned long long)cols);
                     atomicAdd(&s_pairs[b], 1u);
                 }

@@ -242,3 +242,43 @@ def test_large_scores_take_the_int32_path_sweep(aligner):
     gpu = gpu_paths(aligner, b)
     assert np.all(gpu[0][:, 0] > 30592)
     assert_paths_equal(b, gpu)
+
+
+def test_column_word_and_table_path_sweeps_agree(aligner):
+    # when every scheme of a call has at most four residues whose scores
+    # plus the gap open cost fit a byte, the packed path sweep reads column
+    # words; with colpath=0 every pair takes the table form, which must write
+    # the same records.  A call with one scheme outside that set takes the
+    # table form throughout.
+    from paper_2208_12350_amd.binding import Aligner
+    rng = np.random.default_rng(21)
+    M = rng.integers(-5, 1, size=(4, 4))
+    np.fill_diagonal(M, rng.integers(1, 6, size=4))
+    col_scheme = W.Scheme(np.ascontiguousarray(M.astype(np.int8)), 7, 2)      # M + o >= 0
+    M = rng.integers(-9, 1, size=(4, 4))
+    np.fill_diagonal(M, 4)
+    M[0, 1] = -9
+    table_scheme = W.Scheme(np.ascontiguousarray(M.astype(np.int8)), 2, 1)    # M + o < 0
+    pairs = []
+    for k in range(3000):
+        n = int(rng.integers(1, 700))
+        q = rng.integers(0, 4, size=n).astype(np.uint8)
+        r = np.concatenate([rng.integers(0, 4, size=int(rng.integers(0, 60))), q,
+                            rng.integers(0, 4, size=int(rng.integers(0, 60)))]).astype(np.uint8)
+        flip = rng.random(r.size) < 0.08
+        r[flip] = (r[flip] + 1) % 4
+        pairs.append((q, r))
+    batches = [W.from_pairs(pairs, [k % 2 for k in range(len(pairs))], [W.dna_scheme(), col_scheme]),
+               W.from_pairs(pairs, [k % 3 for k in range(len(pairs))], [W.dna_scheme(), col_scheme, table_scheme])]
+    table = Aligner(0, colpath=0)
+    try:
+        for b, want_col in zip(batches, (1, 0)):
+            col = gpu_paths(aligner, b)
+            used = {e["column"] for e in aligner.bin_stats() if e["pass"] == 2 and e["pairs"] and e["precision"] == 16}
+            assert used == {want_col}, used
+            plain = gpu_paths(table, b)
+            for x, y in zip(col, plain):
+                assert np.array_equal(x, y)
+            assert_paths_equal(b, col, np.arange(0, b.n_pairs, 7))
+    finally:
+        table.close()

@@ -58,6 +58,32 @@ struct PairJob {
 // The sub-problem of one pair for this sweep.  Pair ids come from the
 // planning arrays; any id or length outside its documented range is an
 // internal error, flagged and turned into an empty job.
+// Extent of the reverse sweep of a pair whose forward pass found best score
+// S > 0 ending at (qe, re): rows n = qe + 1 and columns m = re + 1 of the
+// reversed prefixes, cut to the part that can hold a cell of score S.
+// Every such cell (p, q) closes an alignment of score S that spans exactly p
+// query and q reference residues (the forward end is the row-major-first
+// maximum, so no S-scoring alignment from it ends earlier).  Such an
+// alignment has at most min(p, q) aligned pairs, each scoring at most Mx,
+// and at least |p - q| gap residues, which cost at least
+// o + (k - 1) e for k of them when o >= e (k o when o < e).  So q - p is at
+// most the largest k whose cost fits in Mx p - S, and likewise p - q.
+// Cells right of or below the cut are never needed by those inside it, so
+// the cut leaves every value inside, and the first S cell, unchanged.
+__device__ __forceinline__ int gap_room(int64_t slack, int o, int e) {
+    // largest number of gap residues whose least cost is at most `slack`
+    if (o <= 0 || e < 0) return SW_MAX_REF;   // no bound
+    if (slack < (int64_t)o) return 0;
+    const int64_t k = o < e ? slack / o : (e == 0 ? (int64_t)SW_MAX_REF : 1 + (slack - o) / e);
+    return k < (int64_t)SW_MAX_REF ? (int)k : SW_MAX_REF;
+}
+__device__ __forceinline__ void reverse_extent(int S, int Mx, int o, int e, int& n, int& m) {
+    const int mq = n + gap_room((int64_t)Mx * n - S, o, e);
+    if (m > mq) m = mq;
+    const int np = m + gap_room((int64_t)Mx * m - S, o, e);
+    if (n > np) n = np;
+}
+
 __device__ __forceinline__ PairJob load_job(const KParams& P, int pair, int reverse) {
     PairJob J;
     J.dir = 1; J.n = 0; J.m = 0; J.qbase = 0; J.rbase = 0; J.sid = 0;
@@ -80,6 +106,8 @@ __device__ __forceinline__ PairJob load_job(const KParams& P, int pair, int reve
             J.n = f.q_end + 1; J.m = f.r_end + 1;
             J.qbase = q0 + f.q_end; J.rbase = r0 + f.r_end;
             J.dir = -1;
+            if (J.sid < SW_MAX_SCHEMES)
+                reverse_extent(f.score, P.max_score[J.sid], P.gap_open[J.sid], P.gap_extend[J.sid], J.n, J.m);
         }
     }
     if (J.n < 0 || J.n > SW_MAX_QUERY || J.m < 0 || J.m > SW_MAX_REF || J.sid >= SW_MAX_SCHEMES) {

@@ -116,6 +116,7 @@ struct KParams {
     int32_t gap_open[SW_MAX_SCHEMES];
     int32_t gap_extend[SW_MAX_SCHEMES];
     int32_t col_ok[SW_MAX_SCHEMES];   // scheme can take the small-alphabet column path
+    int32_t max_score[SW_MAX_SCHEMES];   // largest substitution score (at least 1)
     int32_t validate;
     int32_t reverse;             // 0 = forward sweep, 1 = reverse sweep
     int32_t lo_idx, hi_idx;      // meta[lo_idx] .. meta[hi_idx] is this launch's item range

@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "sw_device.h"
 #include "sw_internal.h"
 
 namespace sw {
@@ -70,7 +71,16 @@ __global__ void sw_classify_kernel(KParams P, ClassifyArgs C, const int8_t* lut,
                 m = (int64_t)r.r_end + 1;
                 s = P.scheme_id ? (int)P.scheme_id[i] : 0;
                 ok = n >= 1 && n <= n0 && m >= 1 && m <= m0 && s < C.n_schemes;
-                if (!ok) atomicOr(&P.flags[kFlagInternal], 1);
+                if (!ok) {
+                    atomicOr(&P.flags[kFlagInternal], 1);
+                } else {
+                    // the part of the prefixes that can hold the start (the
+                    // sweep cuts its job the same way)
+                    int nn = (int)n, mm = (int)m;
+                    reverse_extent(r.score, P.max_score[s], P.gap_open[s], P.gap_extend[s], nn, mm);
+                    n = nn;
+                    m = mm;
+                }
             }
         }
         int key = kTrivialKey;

@@ -721,6 +721,7 @@ static int align_spans(sw_handle* h, const uint8_t* queries, const int64_t* q_be
         K.alphabet[s] = v ? schemes[s].alphabet : 1;
         K.gap_open[s] = v ? schemes[s].gap_open : 1;
         K.gap_extend[s] = v ? schemes[s].gap_extend : 0;
+        K.max_score[s] = C.max_score[s];
         K.col_ok[s] = C.col_ok[s] && h->opt_colpath;
         C.col_ok[s] = K.col_ok[s];
         h->last_col_ok[s] = K.col_ok[s];

@@ -505,8 +505,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(pairs are independent; see DESIGN.md for how the work would shard)", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path (pairs are independent, "
+              "so a batch would shard by pairs across GPUs with no communication)", file=sys.stderr)
         sys.exit(2)
 
     if args.workload == "serving":

@@ -232,8 +232,8 @@ hipError_t launch_trace_sizes(const KParams& P, const TraceArgs& T, int64_t cap,
 hipError_t launch_trace_classify(const KParams& P, const TraceArgs& T, int64_t cap, int32_t* keys,
                                  int32_t* hist, unsigned long long* counters, int32_t* path_len, hipStream_t s);
 // Walks of the pairs of one path-sweep bin (after the bin's sweep).
-hipError_t launch_trace_walk(const KParams& P, const TraceArgs& T, int bin, int blocks, const int64_t* path_off,
-                             uint32_t* path, int32_t* path_len, hipStream_t s);
+hipError_t launch_trace_walk(const KParams& P, const TraceArgs& T, int bin, int blocks, int active,
+                             const int64_t* path_off, uint32_t* path, int32_t* path_len, hipStream_t s);
 // Blocks of the size scan for `cap` pairs (the length of block_sums minus one).
 int64_t trace_scan_blocks(int64_t cap);
 

@@ -857,7 +857,9 @@ hipError_t launch_trace_classify(const KParams& P, const TraceArgs& T, int64_t c
 // to its start.  A path that leaves its box or does not end at the box's
 // first cell is an internal error; one that needs more runs than its room
 // sets kFlagPathRoom.  Either way the pair's run count becomes -1.
-constexpr int kWalkSlot = 33;   // dwords per thread: a block of up to 32, padded against bank conflicts
+// dwords per thread: two record blocks of up to 32 dwords, padded against
+// bank conflicts
+constexpr int kWalkSlot = 65;
 
 // The 16 residues around a position, read as one aligned 16-byte load (an
 // aligned 16-byte block never crosses a page, so it is readable whenever
@@ -892,13 +894,18 @@ __device__ __forceinline__ void walk_pair(const KParams& P, const TraceArgs& T, 
     }
     const int W = T.bins[b].W, R = T.bins[b].R;
     const int64_t rel = off - (int64_t)T.chunk * T.chunk_bytes;
-    if (W * R < rows || rel < 0 || rel + trace_record_bytes(W, R, cols) > T.ws_bytes) {
+    if (W * R < rows || R > 32 || (R & 3) != 0 || rel < 0 || rel + trace_record_bytes(W, R, cols) > T.ws_bytes) {
         atomicOr(&P.flags[kFlagInternal], 1);
         path_len[i] = -1;
         return;
     }
     const uint32_t* rec = reinterpret_cast<const uint32_t*>(T.ws + rel);
-    int64_t cached = -1;   // record block held in `slot` (this thread's LDS copy, R dwords)
+    // `slot` (this thread's LDS copy) holds the record blocks of steps
+    // [8 c_tb, 8 c_tb + 8) and, when c_tb >= 1, [8 c_tb - 8, 8 c_tb) of lane
+    // c_lane: a walk only moves to the same or earlier steps, so the second
+    // block is the next one it needs in that lane.  Both are fetched in one
+    // round trip, every 16-byte load issued before the first is waited for.
+    int c_lane = -1, c_tb = -1;
     const uint8_t* qa = P.queries + P.q_beg[i] + r.q_start;
     const uint8_t* rb = P.refs + P.r_beg[i] + r.r_start;
     uintptr_t qbase = ~(uintptr_t)0, rbase = ~(uintptr_t)0;
@@ -914,17 +921,35 @@ __device__ __forceinline__ void walk_pair(const KParams& P, const TraceArgs& T, 
     for (int64_t it = 0; it < limit && !err; ++it) {
         const int lane = x / R, rr = x - lane * R;
         const int t = y + lane;
-        const int64_t blk = (int64_t)(t / kStage) * W + lane;
-        if (blk != cached) {
-            const uint4* src = reinterpret_cast<const uint4*>(rec + blk * R);
-            for (int q = 0; q < R / 4; ++q) {
-                const uint4 v = src[q];
-                slot[4 * q] = v.x; slot[4 * q + 1] = v.y; slot[4 * q + 2] = v.z; slot[4 * q + 3] = v.w;
+        const int tb = t / kStage;
+        if (lane != c_lane || tb > c_tb || tb < c_tb - 1) {
+            const int nq = R / 4;   // 16-byte pieces per block (R <= 32)
+            const uint4* src0 = reinterpret_cast<const uint4*>(rec + ((int64_t)tb * W + lane) * R);
+            const uint4* src1 = reinterpret_cast<const uint4*>(rec + ((int64_t)(tb - 1) * W + lane) * R);
+            const bool two = tb >= 1;
+            uint4 v0[8], v1[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                if (q < nq) v0[q] = src0[q];
+                if (q < nq && two) v1[q] = src1[q];
             }
-            cached = blk;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                if (q < nq) {
+                    slot[4 * q] = v0[q].x; slot[4 * q + 1] = v0[q].y;
+                    slot[4 * q + 2] = v0[q].z; slot[4 * q + 3] = v0[q].w;
+                }
+                if (q < nq && two) {
+                    slot[R + 4 * q] = v1[q].x; slot[R + 4 * q + 1] = v1[q].y;
+                    slot[R + 4 * q + 2] = v1[q].z; slot[R + 4 * q + 3] = v1[q].w;
+                }
+            }
+            c_lane = lane;
+            c_tb = tb;
         }
+        const uint32_t* blkp = slot + (c_tb - tb) * R;
         const int byte = (t % kStage) * (R / 2) + (rr >> 1);
-        const uint32_t nib = (slot[byte >> 2] >> (8 * (byte & 3) + 4 * (rr & 1))) & 15u;
+        const uint32_t nib = (blkp[byte >> 2] >> (8 * (byte & 3) + 4 * (rr & 1))) & 15u;
         uint32_t o;
         if (state == 0) {
             const uint32_t code = nib & 3u;
@@ -979,17 +1004,24 @@ __device__ __forceinline__ void walk_pair(const KParams& P, const TraceArgs& T, 
 }
 
 // One bin's walks: its pairs are order[meta[bin first] .. meta[next bin first]).
+// A of each wavefront's lanes walk a pair each (the others return at once):
+// a wavefront waits for every record block any of its walks misses, so long
+// walks run few to a wavefront.
+template <int A>
 __global__ __launch_bounds__(256) void sw_trace_walk_kernel(KParams P, TraceArgs T, int bin, const int64_t* path_off,
                                                             uint32_t* path, int32_t* path_len) {
-    __shared__ uint32_t cache[256 * kWalkSlot];
-    uint32_t* slot = cache + threadIdx.x * kWalkSlot;
+    __shared__ uint32_t cache[4 * A * kWalkSlot];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int lo = P.meta[kMetaBinFirst + bin], hi = P.meta[kMetaBinFirst + bin + 1];
     if (lo < 0 || lo > hi || hi > P.n_pairs) {
         if (threadIdx.x == 0) atomicOr(&P.flags[kFlagInternal], 1);
         return;
     }
+    if (lane >= A) return;
+    uint32_t* slot = cache + (wave * A + lane) * kWalkSlot;
     const int n = *P.n_dev;
-    for (int k = lo + (int)(blockIdx.x * blockDim.x + threadIdx.x); k < hi; k += (int)(gridDim.x * blockDim.x)) {
+    const int stride = (int)gridDim.x * 4 * A;
+    for (int k = lo + ((int)blockIdx.x * 4 + wave) * A + lane; k < hi; k += stride) {
         const int i = P.order[k];
         if (i < 0 || i >= n) {
             atomicOr(&P.flags[kFlagInternal], 1);
@@ -999,10 +1031,14 @@ __global__ __launch_bounds__(256) void sw_trace_walk_kernel(KParams P, TraceArgs
     }
 }
 
-hipError_t launch_trace_walk(const KParams& P, const TraceArgs& T, int bin, int blocks, const int64_t* path_off,
-                             uint32_t* path, int32_t* path_len, hipStream_t s) {
-    hipLaunchKernelGGL(sw_trace_walk_kernel, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, s, P, T, bin, path_off, path,
-                       path_len);
+hipError_t launch_trace_walk(const KParams& P, const TraceArgs& T, int bin, int blocks, int active,
+                             const int64_t* path_off, uint32_t* path, int32_t* path_len, hipStream_t s) {
+    if (active == 8)
+        hipLaunchKernelGGL(sw_trace_walk_kernel<8>, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, s, P, T, bin,
+                           path_off, path, path_len);
+    else
+        hipLaunchKernelGGL(sw_trace_walk_kernel<64>, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, s, P, T, bin,
+                           path_off, path, path_len);
     return hipGetLastError();
 }
 

@@ -1099,11 +1099,13 @@ static int trace_paths(sw_handle* h, const sw_batch* batch, const sw_scheme* sch
             hipLaunchKernelGGL(trace_kernel(e.prec, e.W, e.R, v == 1), dim3(blocks), dim3(kBlock), 0, ls, K, T);
             HIP_TRY(h, hipGetLastError());
             if (timing) HIP_TRY(h, hipEventRecord(h->tbin_ev[3 * b + 1], ls));
-            // long boxes (bins of 512 or more rows): 8 walks per wavefront
-            // over up to 4 workgroups per CU; others 64
-            const int active = e.W * e.R >= 512 ? 8 : 64;
+            // walks per wavefront: fewer for longer boxes (a wavefront waits
+            // for every miss of any of its walks)
+            const int rows = e.W * e.R;
+            const int active = rows >= 1024 ? 4 : rows >= 512 ? 8 : 64;
             const int wblocks = active == 64 ? walk_blocks
-                                             : (int)std::min<int64_t>((cap + 31) / 32, 4 * std::max(1, h->n_cu));
+                                             : (int)std::min<int64_t>((cap + 4 * active - 1) / (4 * active),
+                                                                      4 * std::max(1, h->n_cu));
             HIP_TRY(h, launch_trace_walk(K, T, b, wblocks, active, path_off, path, path_len, ls));
             if (timing) HIP_TRY(h, hipEventRecord(h->tbin_ev[3 * b + 2], ls));
         }

@@ -1033,12 +1033,12 @@ __global__ __launch_bounds__(256) void sw_trace_walk_kernel(KParams P, TraceArgs
 
 hipError_t launch_trace_walk(const KParams& P, const TraceArgs& T, int bin, int blocks, int active,
                              const int64_t* path_off, uint32_t* path, int32_t* path_len, hipStream_t s) {
-    if (active == 8)
-        hipLaunchKernelGGL(sw_trace_walk_kernel<8>, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, s, P, T, bin,
-                           path_off, path, path_len);
-    else
-        hipLaunchKernelGGL(sw_trace_walk_kernel<64>, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, s, P, T, bin,
-                           path_off, path, path_len);
+    const dim3 grid(blocks > 0 ? blocks : 1);
+    switch (active) {
+        case 4: hipLaunchKernelGGL(sw_trace_walk_kernel<4>, grid, dim3(256), 0, s, P, T, bin, path_off, path, path_len); break;
+        case 8: hipLaunchKernelGGL(sw_trace_walk_kernel<8>, grid, dim3(256), 0, s, P, T, bin, path_off, path, path_len); break;
+        default: hipLaunchKernelGGL(sw_trace_walk_kernel<64>, grid, dim3(256), 0, s, P, T, bin, path_off, path, path_len);
+    }
     return hipGetLastError();
 }
 

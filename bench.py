@@ -551,7 +551,7 @@ def main():
         builtin = probe.routing(16)
         probe.close()
         cands = T.candidate_tables(ql, rl, rates, list(rates), builtin=builtin)
-        name, table, _ = T.pick_by_timing(db, cands, 0, log=log)
+        name, table, _ = T.pick_by_timing(db, cands, 0, repeats=7, log=log)
         tuning = routing_string(16, table)
         tune_s = time.time() - t_tune
         log("  picked %s: %s (%.1f s)" % (name, tuning, tune_s))

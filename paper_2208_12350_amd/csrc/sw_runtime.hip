@@ -1012,6 +1012,10 @@ static int trace_paths(sw_handle* h, const sw_batch* batch, const sw_scheme* sch
         K.alphabet[s] = v ? schemes[s].alphabet : 1;
         K.gap_open[s] = v ? schemes[s].gap_open : 1;
         K.gap_extend[s] = v ? schemes[s].gap_extend : 0;
+        int mx = 1;   // as the score passes set it (the path sweep itself does not read it)
+        for (int k = 0; v && k < schemes[s].alphabet * schemes[s].alphabet; ++k)
+            mx = std::max(mx, (int)schemes[s].matrix[k]);
+        K.max_score[s] = mx;
     }
     // The column-word path sweep takes a call only when every scheme can use
     // it (the score call just made uploaded their column words): each packed

@@ -83,38 +83,54 @@ def kernel_sources_sha256():
     return h.hexdigest()
 
 
-def cpu_baseline(batch, target_s=12.0):
-    """Time the CPU oracle (as it stands) on a bounded random sample of the
-    same workload using the host cores available to this process."""
+# Worker threads the CPU baseline may use: the GPU machine grants one GPU's
+# process 16 host threads, whatever the machine's core count is.
+CPU_SHARE = 16
+
+
+def cpu_baseline(batch, target_s=12.0, single_s=4.0):
+    """Time the CPU oracle (as it stands) on bounded random samples of the
+    same workload: on every host thread this process may use (at most the
+    box's share of CPU_SHARE threads), and on one thread."""
     import numpy as np
     from oracle import oracle
     try:
-        cores = len(os.sched_getaffinity(0))
+        affinity = len(os.sched_getaffinity(0))
     except AttributeError:
-        cores = os.cpu_count() or 1
-    cores = max(1, min(cores, 16))
+        affinity = os.cpu_count() or 1
+    cores = max(1, min(affinity, CPU_SHARE))
     rng = np.random.default_rng(2208)
     ql, rl = batch.q_len().astype(np.int64), batch.r_len().astype(np.int64)
-    # calibration sample, then a sample sized for ~target_s seconds
-    n0 = min(batch.n_pairs, 20 * cores)
-    idx = rng.choice(batch.n_pairs, size=n0, replace=False)
-    t = time.perf_counter()
-    oracle.align_batch(batch, index=idx, threads=cores)
-    dt = max(time.perf_counter() - t, 1e-3)
-    rate = float(np.sum(ql[idx] * rl[idx])) / dt
     mean_cells = float(np.mean(ql * rl))
-    n1 = int(min(batch.n_pairs, max(n0, target_s * rate / mean_cells)))
-    idx = rng.choice(batch.n_pairs, size=n1, replace=False)
-    t = time.perf_counter()
-    oracle.align_batch(batch, index=idx, threads=cores)
-    dt = time.perf_counter() - t
-    cells = float(np.sum(ql[idx] * rl[idx]))
-    return {"value": round(cells / dt / 1e9, 4), "unit": "GCUPS", "cores": cores, "kind": "oracle",
+
+    def run(threads, seconds):
+        # calibration sample, then a sample sized for about `seconds`
+        n0 = min(batch.n_pairs, 20 * threads)
+        idx = rng.choice(batch.n_pairs, size=n0, replace=False)
+        t = time.perf_counter()
+        oracle.align_batch(batch, index=idx, threads=threads)
+        dt = max(time.perf_counter() - t, 1e-3)
+        rate = float(np.sum(ql[idx] * rl[idx])) / dt
+        n1 = int(min(batch.n_pairs, max(n0, seconds * rate / mean_cells)))
+        idx = rng.choice(batch.n_pairs, size=n1, replace=False)
+        t = time.perf_counter()
+        oracle.align_batch(batch, index=idx, threads=threads)
+        dt = time.perf_counter() - t
+        cells = float(np.sum(ql[idx] * rl[idx]))
+        return cells / dt / 1e9, n1, cells, dt
+
+    v, n1, cells, dt = run(cores, target_s)
+    v1, m1, cells1, dt1 = run(1, single_s)
+    return {"value": round(v, 4), "unit": "GCUPS", "cores": cores, "kind": "oracle",
             "sample": "%d random pairs of the same workload (%.3g forward cells, forward+reverse "
-                      "sweeps, %.1f s on %d threads)" % (n1, cells, dt, cores)}
+                      "sweeps, %.1f s on %d threads)" % (n1, cells, dt, cores),
+            "single_core": {"value": round(v1, 4), "sample": "%d random pairs (%.3g forward cells, %.1f s)"
+                            % (m1, cells1, dt1)},
+            "nproc": os.cpu_count(), "affinity": affinity,
+            "build": "gcc " + " ".join(oracle.CFLAGS)}
 
 
-def roofline_leg(args, db, out, tuning, mode):
+def roofline_leg(args, db, out, tuning, mode, workload, steps):
     """The sweep launches serialised on one stream with a HIP event pair
     around each (library option timing=2) and cells per launch from the
     device counters.  The dominant kernel is the (pass, shape) launch with
@@ -122,7 +138,7 @@ def roofline_leg(args, db, out, tuning, mode):
     from paper_2208_12350_amd.binding import Aligner
     alr = Aligner(0, tuning, mode=mode, graph=0, timing=2)
     per_launch = {}
-    roof_steps = max(3, min(args.steps, 10))
+    roof_steps = max(3, min(steps, 10))
     for k in range(roof_steps + 1):
         alr.align(db, out)
         if k:
@@ -149,14 +165,14 @@ def roofline_leg(args, db, out, tuning, mode):
                                                                   "true" if dcol else "false")
     return {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 2),
             "unit": "Tops/s", "frac": round(achieved / peak, 4),
-            "traffic": stored_traffic(kernel_name, args.workload),
+            "traffic": stored_traffic(kernel_name, workload),
             "kernel": kernel_name, "launches": dn, "launch_ms": round(launch_ms, 4),
             "cells_per_launch": int(cells_per_launch), "ops_per_cell": OPS_PER_CELL,
             "all_sweeps": {"ms": round(fam_ms, 3), "achieved": round(fam_ops / (fam_ms / 1e3) / 1e12, 3),
                            "frac": round(fam_peak_s / (fam_ms / 1e3), 4)}}
 
 
-def cigar_leg(args, db, out, ref_out, tuning, score_ms):
+def cigar_leg(args, db, out, ref_out, tuning, score_ms, workload):
     """sw_align_cigar on the same batch: results plus every pair's path.
     GCUPS counts forward cells per second of whole-call wall time, as the
     headline does.  The box sweeps' kernels are then timed per launch (the
@@ -202,7 +218,7 @@ def cigar_leg(args, db, out, ref_out, tuning, score_ms):
             "sweep_ms": round(float(np.mean(sweep_ms)), 3), "walk_ms": round(float(np.mean(walk_ms)), 3),
             "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 2),
                          "unit": "Tops/s", "frac": round(achieved / peak, 4),
-                         "traffic": stored_traffic(kernel_name, args.workload),
+                         "traffic": stored_traffic(kernel_name, workload),
                          "kernel": kernel_name, "launches": launches,
                          "launch_ms": round(dms / launches, 4),
                          "cells_per_launch": int(dcells / launches),
@@ -212,7 +228,7 @@ def cigar_leg(args, db, out, ref_out, tuning, score_ms):
 
 def roofline_only(args, batch, db, out, tuning, mode):
     """Only the roofline leg (for profiling it alone): one JSON line."""
-    roof = roofline_leg(args, db, out, tuning, mode)
+    roof = roofline_leg(args, db, out, tuning, mode, args.workload, args.steps)
     print(json.dumps({"leg": "roofline", "config": {"workload": args.workload, "pairs": batch.n_pairs,
                                                     "routing": tuning or "built-in"},
                       "roofline": roof}), flush=True)
@@ -482,7 +498,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="dna_large")
+    ap.add_argument("--workload", default="mixed")
+    ap.add_argument("--secondary", default="dna_large,protein",
+                    help="also measure these workloads (comma-separated; empty to skip)")
     ap.add_argument("--n-pairs", type=int, default=None, help="truncate the workload (testing only)")
     ap.add_argument("--mode", type=int, default=None, help="0 = per-bin launches, 1 = persistent")
     ap.add_argument("--streams", type=int, default=4, help="streams the persistent launches spread over")
@@ -519,14 +537,38 @@ def main():
         stencil_bench(args)
         return
 
+    res = align_leg(args, args.workload, args.steps, args.warmup, with_cigar=not args.no_cigar,
+                    with_cpu=not args.no_cpu_baseline, full=True)
+    if res is None:
+        return
+    if args.secondary:
+        # the single-alphabet workloads, each measured the same way (whole
+        # call, persistent + graph against plain per-bin launches, sweep
+        # rooflines), without the path and CPU legs
+        res["secondary"] = {}
+        for name in args.secondary.split(","):
+            sec = align_leg(args, name, max(5, min(args.steps, 10)), 2, with_cigar=False, with_cpu=False,
+                            full=False)
+            res["secondary"][name] = {k: sec[k] for k in ("value", "plain_value", "ms_per_step", "dtype")}
+            res["secondary"][name]["config"] = {k: sec["config"][k] for k in ("pairs", "forward_cells",
+                                                                               "reverse_cells", "routing")}
+            res["secondary"][name]["roofline"] = sec["roofline"]
+    print(json.dumps(res), flush=True)
+
+
+def align_leg(args, workload, steps, warmup, with_cigar, with_cpu, full):
+    """Generate `workload`, tune its routing, and time whole sw_align_batch
+    calls: persistent + graph (the headline) against plain per-bin launches,
+    phase times, and the sweep rooflines (dominant launch, every sweep launch
+    of a call, and the whole call)."""
     import numpy as np
     import torch
     from paper_2208_12350_amd import workloads as W
     from paper_2208_12350_amd.binding import Aligner, DeviceBatch
 
-    log("generating workload %s ..." % args.workload)
+    log("generating workload %s ..." % workload)
     t = time.time()
-    batch = W.make_workload(args.workload, n_pairs=args.n_pairs)
+    batch = W.make_workload(workload, n_pairs=args.n_pairs)
     log("  %d pairs, %.3g forward cells (%.1f s)" % (batch.n_pairs, batch.cells(), time.time() - t))
     dev = "cuda:0"
     db = DeviceBatch.from_host(batch, dev)
@@ -534,59 +576,50 @@ def main():
 
     # routing autotuner (untimed): per-shape rates from probe launches, then
     # the routing that minimises the predicted sweep time of a sample
-    tuning, tune_s = args.routing, 0.0
-    if args.calibrate_copy:
+    tuning, tune_s = (args.routing if full else None), 0.0
+    if full and args.calibrate_copy:
         calibrate_copy(dev)
     if tuning is None and not args.no_tune:
         from paper_2208_12350_amd import autotune as T
         from paper_2208_12350_amd.binding import routing_string
         log("autotuning the routing ...")
         t_tune = time.time()
-        rng = np.random.default_rng(5)
-        idx = rng.choice(batch.n_pairs, size=min(batch.n_pairs, 50000), replace=False)
-        ql, rl = batch.q_len()[idx], batch.r_len()[idx]
-        m_med = int(np.clip(np.median(rl[rl > 0]) if np.any(rl > 0) else 512, 64, 4096))
-        rates = T.measure_rates(0, 16, m=m_med, log=log, scheme=T.dominant_scheme(batch))
-        probe = Aligner(0)
-        builtin = probe.routing(16)
-        probe.close()
-        cands = T.candidate_tables(ql, rl, rates, list(rates), builtin=builtin)
-        name, table, _ = T.pick_by_timing(db, cands, 0, repeats=7, log=log)
+        name, table, _ = T.tune_batch(batch, db, 0, log=log)
         tuning = routing_string(16, table)
         tune_s = time.time() - t_tune
         log("  picked %s: %s (%.1f s)" % (name, tuning, tune_s))
 
-    def timed(al, steps, warmup, what):
-        for k in range(warmup):
+    def timed(al, n, warm, what):
+        for k in range(warm):
             al.align(db, out)
         torch.cuda.synchronize()
         step_ms = []
         t0 = time.perf_counter()
-        for k in range(steps):
+        for k in range(n):
             ts = time.perf_counter()
             al.align(db, out)
             step_ms.append((time.perf_counter() - ts) * 1e3)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
-        log("  %s: %d steps in %.3f s" % (what, steps, el))
+        log("  %s: %d steps in %.3f s" % (what, n, el))
         return el, step_ms
 
     mode = 1 if args.mode is None else args.mode
-    if args.roofline_only:
+    if full and args.roofline_only:
         roofline_only(args, batch, db, out, tuning, mode)
-        return
-    if args.cigar_only:
+        return None
+    if full and args.cigar_only:
         al = Aligner(0, tuning)
         al.align(db, out)
         ref = out.clone()
         al.close()
-        print(json.dumps({"leg": "cigar", "config": {"workload": args.workload, "pairs": batch.n_pairs},
-                          "cigar": cigar_leg(args, db, out, ref, tuning, 0.0)}), flush=True)
-        return
+        print(json.dumps({"leg": "cigar", "config": {"workload": workload, "pairs": batch.n_pairs},
+                          "cigar": cigar_leg(args, db, out, ref, tuning, 0.0, workload)}), flush=True)
+        return None
 
     # headline: persistent work-queue launch, replayed from a captured hipGraph
     al = Aligner(0, tuning, mode=mode, graph=1 if mode == 1 else 0, streams=args.streams)
-    elapsed, step_ms = timed(al, args.steps, args.warmup, "mode %d" % mode)
+    elapsed, step_ms = timed(al, steps, warmup, "mode %d" % mode)
     ref_out = out.clone()
     fwd_cells, rev_cells, i32_pairs = al.stats()
     al.close()
@@ -594,7 +627,7 @@ def main():
     # same call with HIP events around the phases (no graph replay)
     alt = Aligner(0, tuning, mode=mode, graph=0, timing=1, streams=args.streams)
     plan_ms, fwd_ms, rev_ms = [], [], []
-    for k in range(max(3, min(args.steps, 10)) + 1):
+    for k in range(max(3, min(steps, 10)) + 1):
         alt.align(db, out)
         if k:
             p, f, r = alt.timing()
@@ -602,36 +635,41 @@ def main():
     alt.close()
     assert torch.equal(out, ref_out), "timing run disagrees with the headline run"
 
-    roof = roofline_leg(args, db, out, tuning, mode)
+    roof = roofline_leg(args, db, out, tuning, mode, workload, steps)
     assert torch.equal(out, ref_out), "roofline run disagrees with the headline run"
 
     # plain per-bin launches on the same data
     plain = None
     if mode == 1:
         alp = Aligner(0, tuning, mode=0, graph=0)
-        el_p, _ = timed(alp, max(2, min(args.steps, 5)), 1, "plain per-bin launches")
+        el_p, _ = timed(alp, max(2, min(steps, 5)), 1, "plain per-bin launches")
         alp.close()
         assert torch.equal(out, ref_out), "plain launches disagree with the persistent launch"
-        plain = round(fwd_cells * max(2, min(args.steps, 5)) / el_p / 1e9, 2)
+        plain = round(fwd_cells * max(2, min(steps, 5)) / el_p / 1e9, 2)
 
-    ms_per_step = elapsed * 1e3 / args.steps
-    gcups = fwd_cells * args.steps / elapsed / 1e9
-    cigar = None if args.no_cigar else cigar_leg(args, db, out, ref_out, tuning, ms_per_step)
+    ms_per_step = elapsed * 1e3 / steps
+    gcups = fwd_cells * steps / elapsed / 1e9
+    # the whole call (planning, both sweeps, launch gaps) against the peak
+    # of the precision its cells ran at
+    peak = VALU_INT16X2_TOPS if i32_pairs == 0 else VALU_INT32_TOPS
+    whole = OPS_PER_CELL * (fwd_cells + rev_cells) / (ms_per_step / 1e3) / 1e12
+    roof["whole_call"] = {"ms": round(ms_per_step, 3), "achieved": round(whole, 3), "frac": round(whole / peak, 4)}
+    cigar = cigar_leg(args, db, out, ref_out, tuning, ms_per_step, workload) if with_cigar else None
     int16 = i32_pairs < batch.n_pairs
     res = {
         "metric": "GCUPS, batched affine SW (score+coords), batched vs plain; p50/p99 latency",
         "value": round(gcups, 2),
         "unit": "GCUPS",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
+        "steps": steps,
+        "warmup": warmup,
         "ms_per_step": round(ms_per_step, 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "i16" if int16 else "i32",
         "data": "synthetic",
-        "config": {"workload": args.workload, "pairs": batch.n_pairs, "forward_cells": int(fwd_cells),
+        "config": {"workload": workload, "pairs": batch.n_pairs, "forward_cells": int(fwd_cells),
                    "reverse_cells": int(rev_cells), "int32_pairs": int(i32_pairs),
                    "mode": "persistent+graph" if mode == 1 else "plain per-bin launches",
                    "streams": args.streams if mode == 1 else 1,
@@ -644,10 +682,12 @@ def main():
         "roofline": roof,
         "cigar": cigar,
     }
-    if not args.no_cpu_baseline:
+    if with_cpu:
         log("timing the CPU oracle on a sample ...")
         res["cpu_baseline"] = cpu_baseline(batch)
-    print(json.dumps(res), flush=True)
+    del db, out
+    torch.cuda.empty_cache()
+    return res
 
 
 if __name__ == "__main__":

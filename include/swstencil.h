@@ -4,7 +4,7 @@
  *
  * The paper's second application (Section II-C) diffuses virus and
  * inflammatory signal over a 2-D grid of lung tissue, each grid point
- * spreading to its neighbours every step; Section V-D shows that removing
+ * spreading to its neighbours every step; Section VI-D shows that removing
  * the grid's boundary checks and instead padding the grid with a border of
  * zero points made that code faster.  This library provides one explicit
  * diffusion step of a float32 field, with and without that padding:

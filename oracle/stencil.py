@@ -5,7 +5,7 @@ library never imports it.
 One step of the diffusion of Section II-C (virus and inflammatory signal
 spread from each grid point to its neighbours): every point keeps (1 - D)
 of its value and receives D/8 of each of its 8 neighbours'; points outside
-the grid contribute 0, which is what the zero border of Section V-D's
+the grid contribute 0, which is what the zero border of Section VI-D's
 padded grid gives.
 """
 from __future__ import annotations

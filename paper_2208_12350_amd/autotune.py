@@ -244,6 +244,28 @@ def pick_by_timing(dbatch, tables: Dict[str, Table], device: int = 0, repeats: i
     return best
 
 
+def tune_batch(batch, dbatch, device: int = 0, sample: int = 50000, repeats: int = 7, seed: int = 5, log=None):
+    """The routing a batch is timed with: shape rates measured on the batch's
+    dominant scheme at its median reference length, the candidate tables of
+    a seeded sample of its pairs, and the fastest of them on the batch itself
+    (median of `repeats` graph-replayed calls each).  Returns (name, table,
+    candidates)."""
+    from .binding import Aligner
+    rng = np.random.default_rng(seed)
+    idx = rng.choice(batch.n_pairs, size=min(batch.n_pairs, sample), replace=False)
+    ql, rl = batch.q_len()[idx], batch.r_len()[idx]
+    m_med = int(np.clip(np.median(rl[rl > 0]) if np.any(rl > 0) else 512, 64, 4096))
+    rates = measure_rates(device, 16, m=m_med, log=log, scheme=dominant_scheme(batch))
+    probe = Aligner(device)
+    try:
+        builtin = probe.routing(16)
+    finally:
+        probe.close()
+    cands = candidate_tables(ql, rl, rates, list(rates), builtin=builtin)
+    name, table, _ = pick_by_timing(dbatch, cands, device, repeats=repeats, log=log)
+    return name, table, cands
+
+
 def tune(q_len, r_len, device: int = 0, precision: int = 16, log=None, **kw):
     """Measure the shapes and choose a routing for the sample (q_len, r_len).
     Returns (table, rates, seconds spent)."""

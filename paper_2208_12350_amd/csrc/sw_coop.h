@@ -99,8 +99,8 @@ __device__ __forceinline__ void sweep_coop(const KParams& P, const SchemeLds& S,
         C.xf[1][lane & (kWavesPerBlock - 1)] = K2;
     }
     const int AA = S.alphabet[JA.sid], AB = S.alphabet[JB.sid];
-    const u16x2 go2 = pk((uint32_t)S.gap_open[JA.sid] | ((uint32_t)S.gap_open[JB.sid] << 16));
-    const u16x2 ge2 = pk((uint32_t)S.gap_extend[JA.sid] | ((uint32_t)S.gap_extend[JB.sid] << 16));
+    const u16x2 go2 = pk(cost16(S.gap_open[JA.sid]) | (cost16(S.gap_open[JB.sid]) << 16));
+    const u16x2 ge2 = pk(cost16(S.gap_extend[JA.sid]) | (cost16(S.gap_extend[JB.sid]) << 16));
     const u16x2 zero = pk(K2);
     __syncthreads();
 

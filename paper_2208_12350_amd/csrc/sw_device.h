@@ -49,6 +49,13 @@ __device__ __forceinline__ int sat_sub(int x, int y) {
 
 __device__ __forceinline__ int imax(int a, int b) { return a > b ? a : b; }
 
+// A gap cost as one 16-bit half of a packed operand.  Packed values never
+// exceed 0x7BFF, so subtracting any cost of at least 0x7C00 saturates to 0,
+// the same as subtracting the true cost: clamping at 0x7FFF keeps every
+// result exact, while a cost of 65536 or more would otherwise be truncated
+// and spill into the other pair's half.
+__device__ __forceinline__ uint32_t cost16(int c) { return (uint32_t)(c < 0x7FFF ? c : 0x7FFF); }
+
 struct PairJob {
     int64_t qbase, rbase;
     int n, m, dir, sid;

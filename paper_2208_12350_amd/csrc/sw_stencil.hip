@@ -3,7 +3,7 @@
 //
 // The grid diffusion of the paper's second application (Section II-C):
 // every point keeps (1 - D) of its value and receives D/8 of each of its 8
-// neighbours'; points outside the grid count as 0.  Section V-D found that
+// neighbours'; points outside the grid count as 0.  Section VI-D found that
 // the boundary checks cost a fifth of the run time there, and that a border
 // of zero points removes them.  Both forms are built here from one step
 // function that differs only in how a neighbour is read, so they compute

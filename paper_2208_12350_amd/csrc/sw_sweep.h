@@ -14,15 +14,15 @@
 //     the row above its block (H and F of the last row of lane l-1 at
 //     column j) was produced by lane l-1 one step earlier and arrives through
 //     a DPP row/wave shift -- the same mechanism for every lane, with no
-//     divergent first-lane path (the lesson of Section V-A).  Lane 0 of a
+//     divergent first-lane path (the lesson of Section VI-A).  Lane 0 of a
 //     group receives zeros, the matrix's top boundary.
 //   * The reference of each group is staged in LDS as pre-scaled row offsets
 //     into the LDS substitution matrix, so one LDS byte read per cell gives
 //     M[a_i][b_j].  Columns left of 0 (ramp-up) and right of m (ramp-down)
 //     read a padding code whose score is -1.
 //   * No per-step barrier or warp vote: a wavefront runs in lock-step
-//     (Section V-B), and shared state is initialised once, by the lanes that
-//     use it (Section V-C).
+//     (Section VI-B), and shared state is initialised once, by the lanes that
+//     use it (Section VI-C).
 //
 // Exactness of the padding: E and F are carried clamped at zero
 // (E* = max(E, 0)), which leaves H unchanged because H takes a max with 0.  A
@@ -310,8 +310,8 @@ __device__ __forceinline__ void sweep_i16(const KParams& P, const SchemeLds& S, 
         if (bad && P.validate) atomicOr(&P.flags[kFlagBadResidue], 1);
     }
     const int AA = S.alphabet[JA.sid], AB = S.alphabet[JB.sid];
-    const u16x2 go2 = pk((uint32_t)S.gap_open[JA.sid] | ((uint32_t)S.gap_open[JB.sid] << 16));
-    const u16x2 ge2 = pk((uint32_t)S.gap_extend[JA.sid] | ((uint32_t)S.gap_extend[JB.sid] << 16));
+    const u16x2 go2 = pk(cost16(S.gap_open[JA.sid]) | (cost16(S.gap_open[JB.sid]) << 16));
+    const u16x2 ge2 = pk(cost16(S.gap_extend[JA.sid]) | (cost16(S.gap_extend[JB.sid]) << 16));
     const u16x2 zero = pk(K2);
     wave_lds_sync();
 
@@ -527,7 +527,7 @@ __device__ __forceinline__ void sweep_i16_col(const KParams& P, const SchemeLds&
     const int AA = S.alphabet[JA.sid], AB = S.alphabet[JB.sid];
     const uint32_t goA = (uint32_t)S.gap_open[JA.sid], goB = (uint32_t)S.gap_open[JB.sid];
     const u16x2 go2 = pk(goA | (goB << 16));
-    const u16x2 ge2 = pk((uint32_t)S.gap_extend[JA.sid] | ((uint32_t)S.gap_extend[JB.sid] << 16));
+    const u16x2 ge2 = pk(cost16(S.gap_extend[JA.sid]) | (cost16(S.gap_extend[JB.sid]) << 16));
     const u16x2 zero = pk(K2);
     const uint32_t hm_top = (K - goA) | ((K - goB) << 16);   // Hm of the zero boundary
     wave_lds_sync();

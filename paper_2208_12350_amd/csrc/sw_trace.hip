@@ -346,8 +346,8 @@ __device__ __forceinline__ void sweep_trace_i16(const KParams& P, const TraceArg
     bool bad = false;   // residues were checked by the score passes
     stA.store(bufA, JA, AA, 0, l, bad);
     stB.store(bufB, JB, AB, 0, l, bad);
-    const u16x2 go2 = pk((uint32_t)S.gap_open[JA.sid] | ((uint32_t)S.gap_open[JB.sid] << 16));
-    const u16x2 ge2 = pk((uint32_t)S.gap_extend[JA.sid] | ((uint32_t)S.gap_extend[JB.sid] << 16));
+    const u16x2 go2 = pk(cost16(S.gap_open[JA.sid]) | (cost16(S.gap_open[JB.sid]) << 16));
+    const u16x2 ge2 = pk(cost16(S.gap_extend[JA.sid]) | (cost16(S.gap_extend[JB.sid]) << 16));
     const u16x2 zero = pk(K2);
     wave_lds_sync();
 
@@ -511,7 +511,7 @@ __device__ __forceinline__ void sweep_trace_i16_col(const KParams& P, const Trac
     stB.store_col(bufB, JB, AB, S.colw[JB.sid], 0, l, bad);
     const uint32_t goA = (uint32_t)S.gap_open[JA.sid], goB = (uint32_t)S.gap_open[JB.sid];
     const u16x2 go2 = pk(goA | (goB << 16));
-    const u16x2 ge2 = pk((uint32_t)S.gap_extend[JA.sid] | ((uint32_t)S.gap_extend[JB.sid] << 16));
+    const u16x2 ge2 = pk(cost16(S.gap_extend[JA.sid]) | (cost16(S.gap_extend[JB.sid]) << 16));
     const u16x2 zero = pk(K2);
     const uint32_t hm_top = (K - goA) | ((K - goB) << 16);   // Hm of the zero boundary
     wave_lds_sync();

@@ -5,7 +5,7 @@ This applies the paper's method to this project's own kernels at the level
 of their parameters (not of their code): the evolutionary loop of Section
 II-A (a population of program variants made by mutation and crossover from
 one starting program, validated on test inputs, selected by a fitness
-measure, iterated), with the search settings of Section IV (elitism,
+measure, iterated), with the search settings of Section III-E (elitism,
 per-individual crossover and mutation probabilities), and the analysis of
 Section V: weak-edit elimination (Algorithm 1), the split into independent
 and epistatic edits (Algorithm 2), and the exhaustive evaluation of the

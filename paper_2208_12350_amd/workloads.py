@@ -234,11 +234,14 @@ def mutate_embed(rng, q_lens: np.ndarray, r_lens: np.ndarray, p_sub: float,
     slack = r_lens - emit_per_pair
     offset = (rng.random(P) * (slack + 1)).astype(np.int64)
     offset = np.minimum(offset, slack)
-    # scatter copies into refs
+    # put the copies into refs: they occupy disjoint runs in pair order, so a
+    # mask of the runs (from +1/-1 marks at their ends) takes them in order
     if c_off[-1] > 0:
-        pair_of = np.repeat(np.arange(P), emit_per_pair)
-        pos_in = np.arange(int(c_off[-1])) - c_off[:-1][pair_of]
-        refs[r_off[:-1][pair_of] + offset[pair_of] + pos_in] = copy
+        start = r_off[:-1] + offset
+        marks = np.zeros(int(r_off[-1]) + 1, np.int8)
+        np.add.at(marks, start, 1)
+        np.add.at(marks, start + emit_per_pair, -1)
+        refs[np.cumsum(marks[:-1], dtype=np.int8) > 0] = copy
     return queries, q_off, refs, r_off
 
 
@@ -354,20 +357,16 @@ def _interleave(is_b, a, b):
     qo[1:] = np.cumsum(ql)
     ro = np.zeros(P + 1, np.int64)
     ro[1:] = np.cumsum(rl)
+    # each sub-batch's residues keep their order in the merged layout, so
+    # a per-residue owner mask places them
     q = np.empty(int(qo[-1]), np.uint8)
     r = np.empty(int(ro[-1]), np.uint8)
-    for src_q, src_qo, src_r, src_ro, idx in ((aq, aqo, ar, aro, np.flatnonzero(~is_b)),
-                                              (bq, bqo, br, bro, np.flatnonzero(is_b))):
-        if idx.size == 0:
-            continue
-        lq = np.diff(src_qo)
-        lr = np.diff(src_ro)
-        if src_qo[-1] > 0:
-            k = np.repeat(np.arange(idx.size), lq)
-            q[qo[idx][k] + np.arange(int(src_qo[-1])) - src_qo[:-1][k]] = src_q
-        if src_ro[-1] > 0:
-            k = np.repeat(np.arange(idx.size), lr)
-            r[ro[idx][k] + np.arange(int(src_ro[-1])) - src_ro[:-1][k]] = src_r
+    q_owner = np.repeat(is_b, ql)
+    r_owner = np.repeat(is_b, rl)
+    q[~q_owner] = aq
+    q[q_owner] = bq
+    r[~r_owner] = ar
+    r[r_owner] = br
     return q, qo, r, ro
 
 

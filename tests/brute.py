@@ -55,6 +55,35 @@ def brute_align(a, b, M, o, e):
     return (best, i0, i1, j0, j1)
 
 
+def brute_h_matrix(a, b, M, o, e):
+    """The (n+1) x (m+1) local-alignment score matrix by enumeration: entry
+    [i][j] is the best score of any alignment that consumes a[..i-1] and
+    b[..j-1] as its last query and reference residues (its last column may
+    be a substitution or either kind of gap), or 0 if none is positive.
+    Alignments are enumerated from every first substitution column; one
+    that begins with a gap column never scores more than the same alignment
+    without it."""
+    a = [int(x) for x in a]
+    b = [int(x) for x in b]
+    n, m = len(a), len(b)
+    M = np.asarray(M)
+    H = np.zeros((n + 1, m + 1), np.int64)
+    for i0 in range(n):
+        for j0 in range(m):
+            stack = [(i0 + 1, j0 + 1, "M", int(M[a[i0], b[j0]]))]
+            while stack:
+                i, j, last, s = stack.pop()
+                if s > H[i, j]:
+                    H[i, j] = s
+                if i < n and j < m:
+                    stack.append((i + 1, j + 1, "M", s + int(M[a[i], b[j]])))
+                if i < n:
+                    stack.append((i + 1, j, "I", s - (e if last == "I" else o)))
+                if j < m:
+                    stack.append((i, j + 1, "D", s - (e if last == "D" else o)))
+    return H
+
+
 def _all_alignments(a, b, M, o, e):
     """Every local alignment that begins and ends with an M column, as
     (score, i0, j0, i1, j1, columns)."""

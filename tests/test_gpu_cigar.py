@@ -87,6 +87,32 @@ def test_tiny_random_all_gap_settings(aligner):
         assert_paths_equal(b, gpu_paths(aligner, b))
 
 
+def test_large_gap_costs(aligner):
+    """Gap costs beyond 16 bits on the packed box sweep: the paths equal the
+    oracle's (with such costs an optimal path has no gap, so it is one
+    substitution run between the box corners)."""
+    rng = np.random.default_rng(32)
+    dna = W.dna_scheme()
+    schemes = [W.Scheme(dna.matrix, o, e, "dna_o%d_e%d" % (o, e))
+               for o, e in ((65537, 1), (70000, 70000), (2000, 1), (40000, 3))]
+    pairs, sids = [], []
+    for k in range(800):
+        n = int(rng.integers(1, 200))
+        q = rng.integers(0, 4, size=n).astype(np.uint8)
+        mut = q.copy()
+        flip = rng.random(n) < 0.1
+        mut[flip] = (mut[flip] + 1) % 4
+        if rng.random() < 0.3:
+            cut = int(rng.integers(0, n))
+            mut = np.concatenate([mut[:cut], rng.integers(0, 4, size=2).astype(np.uint8), mut[cut:]])
+        r = np.concatenate([rng.integers(0, 4, size=int(rng.integers(0, 50))), mut,
+                            rng.integers(0, 4, size=int(rng.integers(0, 50)))]).astype(np.uint8)
+        pairs.append((q, r))
+        sids.append(k % len(schemes))
+    b = W.from_pairs(pairs, sids, schemes)
+    assert_paths_equal(b, gpu_paths(aligner, b))
+
+
 def test_dna_small_every_pair(aligner):
     b = W.make_workload("dna_small")
     assert_paths_equal(b, gpu_paths(aligner, b))

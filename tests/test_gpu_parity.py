@@ -79,24 +79,66 @@ EDGE_Q = [1, 2, 15, 16, 17, 31, 32, 33, 100, 255, 256, 257, 383, 384, 385, 511, 
 EDGE_R = [1, 2, 15, 16, 17, 63, 64, 65, 127, 128, 129, 130, 131, 255, 256, 257, 1000, 6144]
 
 
-def test_edge_lengths(aligner):
-    rng = np.random.default_rng(7)
-    dna = W.dna_scheme()
+@pytest.mark.parametrize("alphabet", ["dna", "protein"])
+def test_edge_lengths(aligner, alphabet):
+    """Every (query, reference) length of the grid below, up to the longest
+    queries (2048) against the longest references (6144) of the mixed
+    workload, half of them holding an exact copy of the query; plus mutated
+    embeddings at the largest shapes (the long tail of the mixed workload)."""
+    rng = np.random.default_rng(7 if alphabet == "dna" else 8)
+    sc = W.dna_scheme() if alphabet == "dna" else W.protein_scheme(5)
+    A = sc.alphabet
     pairs = []
     for n in EDGE_Q:
         for m in EDGE_R:
-            if n * m > 2_000_000:
-                continue
-            q = rng.integers(0, 4, size=n)
+            q = rng.integers(0, A, size=n)
             if m >= n and rng.random() < 0.5:
                 off = int(rng.integers(0, m - n + 1))
-                r = rng.integers(0, 4, size=m)
+                r = rng.integers(0, A, size=m)
                 r[off:off + n] = q
             else:
-                r = rng.integers(0, 4, size=m)
+                r = rng.integers(0, A, size=m)
             pairs.append((q, r))
-    b = W.from_pairs(pairs, [0] * len(pairs), [dna])
+    for n, m in ((2048, 6144), (2048, 3072), (1024, 6144), (2048, 2048), (1500, 4500)):
+        q = rng.integers(0, A, size=n)
+        r = rng.integers(0, A, size=m)
+        mut = q.copy()
+        flip = rng.random(n) < (0.1 if A == 4 else 0.3)
+        mut[flip] = (mut[flip] + rng.integers(1, A, size=int(flip.sum()))) % A
+        off = int(rng.integers(0, m - n + 1))
+        r[off:off + n] = mut
+        pairs.append((q, r))
+    b = W.from_pairs(pairs, [0] * len(pairs), [sc])
     assert_same(run_gpu(aligner, b), O.align_batch(b), b)
+
+
+def test_large_gap_costs(aligner):
+    """Gap costs beyond 16 bits: pairs still take the packed path (their score
+    bound fits), whose operands hold each cost in a 16-bit half; any cost of
+    0x7C00 or more must act exactly as the true cost (no gap can ever pay)."""
+    rng = np.random.default_rng(31)
+    dna = W.dna_scheme()
+    schemes = [W.Scheme(dna.matrix, o, e, "dna_o%d_e%d" % (o, e))
+               for o, e in ((65537, 1), (70000, 70000), (2000, 1), (40000, 3))]
+    pairs, sids = [], []
+    for k in range(2000):
+        n = int(rng.integers(1, 300))
+        q = rng.integers(0, 4, size=n).astype(np.uint8)
+        mut = q.copy()
+        flip = rng.random(n) < 0.1
+        mut[flip] = (mut[flip] + 1) % 4
+        if rng.random() < 0.3:
+            cut = int(rng.integers(0, n))
+            mut = np.concatenate([mut[:cut], rng.integers(0, 4, size=int(rng.integers(1, 4))).astype(np.uint8),
+                                  mut[cut:]])
+        r = np.concatenate([rng.integers(0, 4, size=int(rng.integers(0, 80))), mut,
+                            rng.integers(0, 4, size=int(rng.integers(0, 80)))]).astype(np.uint8)
+        pairs.append((q, r))
+        sids.append(k % len(schemes))
+    b = W.from_pairs(pairs, sids, schemes)
+    g = run_gpu(aligner, b)
+    assert aligner.stats()[2] == 0          # every pair took the packed path
+    assert_same(g, O.align_batch(b), b)
 
 
 def test_many_items_per_wave_64_lane_groups(aligner):
@@ -166,6 +208,48 @@ def test_invalid_inputs_are_rejected(aligner):
     # the handle still works after errors
     ok = W.make_workload("dna_small", n_pairs=20)
     assert_same(run_gpu(aligner, ok), O.align_batch(ok), ok)
+
+
+@pytest.mark.timeout(600)
+def test_mixed_full_size_tuned_routing():
+    """The mixed workload at full size (1,000,000 DNA and protein pairs) with
+    the routing the benchmark times: every candidate routing of the
+    autotuner gives the same bits on every pair, a seeded sample of pairs
+    matches the oracle, and every pair satisfies the result properties."""
+    import torch
+    from paper_2208_12350_amd import autotune as T
+    from paper_2208_12350_amd.binding import Aligner, DeviceBatch, routing_string
+    b = W.make_workload("mixed")
+    db = DeviceBatch.from_host(b)
+    name, table, cands = T.tune_batch(b, db, 0, repeats=2)
+    out = torch.empty((b.n_pairs, 5), dtype=torch.int32, device="cuda:0")
+    al = Aligner(0, routing_string(16, table))
+    try:
+        al.align(db, out)
+        al.align(db, out)          # a graph replay, as timed
+        g = out.cpu().numpy()
+        assert al.stats()[2] == 0
+    finally:
+        al.close()
+    for other, t in cands.items():
+        if other == name:
+            continue
+        alo = Aligner(0, routing_string(16, t))
+        try:
+            out.fill_(-7)
+            alo.align(db, out)
+            assert np.array_equal(out.cpu().numpy(), g), other
+        finally:
+            alo.close()
+    rng = np.random.default_rng(13)
+    idx = np.sort(rng.choice(b.n_pairs, size=1500, replace=False))
+    # plus the longest queries, which run on the widest shapes
+    idx = np.union1d(idx, np.argsort(b.q_len())[-200:])
+    assert_same(g, O.align_batch(b, index=idx), b, idx=idx)
+    ql, rl = b.q_len(), b.r_len()
+    assert np.all(g[:, 0] > 0)
+    assert np.all((g[:, 1] >= 0) & (g[:, 1] <= g[:, 2]) & (g[:, 2] < ql))
+    assert np.all((g[:, 3] >= 0) & (g[:, 3] <= g[:, 4]) & (g[:, 4] < rl))
 
 
 @pytest.mark.parametrize("name", ["dna_large", "protein"])

@@ -93,7 +93,7 @@ def test_pad_grid_layout():
 
 
 def test_paper_grid_size_sampled():
-    # the 2500 x 2500 held-out size of Section V-D, 10 steps
+    # the 2500 x 2500 held-out size of Section VI-D, 10 steps
     rng = np.random.default_rng(9)
     c = rng.random((2500, 2500)).astype(np.float32)
     steps, D = 10, 0.15

@@ -19,7 +19,7 @@ import os
 import numpy as np
 import pytest
 
-from brute import brute_align
+from brute import brute_align, brute_h_matrix
 from oracle import oracle as O
 from paper_2208_12350_amd import workloads as W
 
@@ -82,6 +82,29 @@ def test_oracle_matches_brute_force(seed):
             ties_end += int(np.sum(H == want[0]) > 1)
     # ties must actually occur, or the tie-break rules are not being tested
     assert ties_end > n_cases // 20
+
+
+@pytest.mark.parametrize("seed", range(2))
+def test_score_matrix_matches_brute_force(seed):
+    """The full H matrix the oracle returns equals the enumerated one cell by
+    cell; its maximum is the score of align_pair and its row-major-first
+    maximum is the reported end."""
+    rng = np.random.default_rng(3000 + seed)
+    for k in range(300):
+        A = (2, 4, 6)[k % 3]
+        M = _random_matrix(rng, A, symmetric=(k % 4 == 0))
+        o, e = GAPS[k % len(GAPS)]
+        a = rng.integers(0, A, size=int(rng.integers(0, 6)))
+        b = rng.integers(0, A, size=int(rng.integers(0, 6)))
+        H = O.score_matrix(a, b, _scheme(M, o, e))
+        want = brute_h_matrix(a, b, M, o, e)
+        assert H.shape == (a.size + 1, b.size + 1)
+        assert np.array_equal(H, want), (a.tolist(), b.tolist(), M.tolist(), o, e, H.tolist(), want.tolist())
+        S, _, qe, _, re = brute_align(a, b, M, o, e)
+        assert int(H.max()) == S
+        if S > 0:
+            i, j = np.argwhere(H == S)[0]          # row-major first
+            assert (int(i) - 1, int(j) - 1) == (qe, re)
 
 
 def test_batch_equals_pairwise():

@@ -49,6 +49,7 @@ extern "C" {
 #define SW_MAX_REF      60000    /* reference (column) length */
 #define SW_MAX_ALPHABET    31    /* residue codes 0..alphabet-1 */
 #define SW_MAX_SCHEMES      4
+#define SW_NOALLOC_MAX_PAIRS (1 << 20)   /* batch limit of sw_align_batch_noalloc */
 
 /* One result per pair, in the caller's pair order. */
 typedef struct {
@@ -149,6 +150,22 @@ int sw_get_option(sw_handle* h, const char* key, int64_t* value);
  * SW_ENOMEM, SW_EDEVICE.  On error the contents of `out` are undefined. */
 int sw_align_batch(sw_handle* h, const sw_batch* batch, const sw_scheme* schemes,
                    int n_schemes, sw_result* out, void* stream);
+
+/* For callers that cannot allocate device memory (code inside a tight
+ * serving loop, harnesses that forbid hipMalloc): the same call as
+ * sw_align_batch, with the same arguments, results and errors, except that
+ * it allocates and frees nothing.  Its planning workspace (sort keys, pair
+ * order and work items; 16 bytes per pair) is one static device array of
+ * 16 MiB that each GPU the library runs on holds until the process ends;
+ * the handle (created beforehand with sw_create, which does allocate) gives
+ * everything else.  The call never captures or replays a graph; its kernels
+ * are launched on `stream` and it returns after they have completed.
+ * Limits: at most SW_NOALLOC_MAX_PAIRS pairs (more is SW_EINVAL, checked
+ * before anything is launched).  Every call on one GPU, from any handle,
+ * shares that GPU's array: calls that overlap in time on one GPU (from two
+ * host threads, or on two streams) race and give undefined results. */
+int sw_align_batch_noalloc(sw_handle* h, const sw_batch* batch, const sw_scheme* schemes,
+                           int n_schemes, sw_result* out, void* stream);
 
 /* Same as sw_align_batch for pairs given by explicit spans instead of
  * prefix offsets: query i is queries[q_beg[i] .. q_end[i]) and reference i is

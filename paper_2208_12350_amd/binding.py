@@ -28,12 +28,13 @@ SW_MAX_QUERY = 2048
 SW_MAX_REF = 60000
 SW_MAX_ALPHABET = 31
 SW_MAX_SCHEMES = 4
+SW_NOALLOC_MAX_PAIRS = 1 << 20
 
 _ERRNAMES = {SW_EINVAL: "SW_EINVAL", SW_ENOMEM: "SW_ENOMEM", SW_ETOOLONG: "SW_ETOOLONG",
              SW_EDEVICE: "SW_EDEVICE", SW_EINTERNAL: "SW_EINTERNAL"}
 
 EXPORTED = ("sw_create", "sw_destroy", "sw_last_error", "sw_set_option", "sw_get_option",
-            "sw_align_batch", "sw_align_spans", "sw_last_stats", "sw_last_timing", "sw_last_host_timing", "sw_last_bin_stats",
+            "sw_align_batch", "sw_align_batch_noalloc", "sw_align_spans", "sw_last_stats", "sw_last_timing", "sw_last_host_timing", "sw_last_bin_stats",
             "sw_shapes", "sw_set_routing", "sw_get_routing", "sw_align_cigar", "sw_last_cigar_stats", "sw_search",
             "sw_server_create", "sw_server_destroy", "sw_server_last_error", "sw_server_submit",
             "sw_server_poll", "sw_server_stats", "sw_server_timing")
@@ -91,6 +92,9 @@ def load_library(path: str = LIB_PATH):
     lib.sw_align_batch.restype = ctypes.c_int
     lib.sw_align_batch.argtypes = [ctypes.c_void_p, ctypes.POINTER(sw_batch), ctypes.POINTER(sw_scheme),
                                    ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
+    lib.sw_align_batch_noalloc.restype = ctypes.c_int
+    lib.sw_align_batch_noalloc.argtypes = [ctypes.c_void_p, ctypes.POINTER(sw_batch), ctypes.POINTER(sw_scheme),
+                                           ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
     lib.sw_align_spans.restype = ctypes.c_int
     lib.sw_align_spans.argtypes = [ctypes.c_void_p] + [ctypes.c_void_p] * 7 + [ctypes.c_int64, ctypes.POINTER(sw_scheme),
                                                                              ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
@@ -178,6 +182,11 @@ def sw_get_option(h: int, key: str) -> int:
 def sw_align_batch(h: int, batch: sw_batch, schemes, n_schemes: int, out_ptr: int, stream_ptr) -> int:
     """Raw call; returns the status code (does not raise)."""
     return load_library().sw_align_batch(h, ctypes.byref(batch), schemes, n_schemes, out_ptr, stream_ptr)
+
+
+def sw_align_batch_noalloc(h: int, batch: sw_batch, schemes, n_schemes: int, out_ptr: int, stream_ptr) -> int:
+    """Raw call of the allocation-free variant; returns the status code."""
+    return load_library().sw_align_batch_noalloc(h, ctypes.byref(batch), schemes, n_schemes, out_ptr, stream_ptr)
 
 
 def sw_align_spans(h: int, queries, q_beg, q_end, refs, r_beg, r_end, scheme_id, n_pairs: int, schemes,
@@ -357,6 +366,19 @@ class Aligner:
         s = stream if stream is not None else torch.cuda.current_stream(dev)
         rc = sw_align_batch(self.h, dbatch.c_struct(), arr, len(dbatch.schemes),
                             out.data_ptr() if dbatch.n_pairs else None, ctypes.c_void_p(s.cuda_stream))
+        _check(self.h, rc)
+        del keep
+        return out
+
+    def align_noalloc(self, dbatch: DeviceBatch, out, stream=None):
+        """align() through sw_align_batch_noalloc: the caller provides `out`
+        (int32 [n_pairs, 5] on the device); the library allocates nothing."""
+        import torch
+        assert out.is_contiguous() and out.dtype == torch.int32 and out.shape == (dbatch.n_pairs, 5)
+        arr, keep = make_schemes(dbatch.schemes)
+        s = stream if stream is not None else torch.cuda.current_stream(dbatch.q_off.device)
+        rc = sw_align_batch_noalloc(self.h, dbatch.c_struct(), arr, len(dbatch.schemes),
+                                    out.data_ptr() if dbatch.n_pairs else None, ctypes.c_void_p(s.cuda_stream))
         _check(self.h, rc)
         del keep
         return out

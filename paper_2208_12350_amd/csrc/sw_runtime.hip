@@ -32,6 +32,48 @@ namespace {
 
 std::mutex g_capture_mu;   // one graph capture at a time in the process
 
+// Workspace of sw_align_batch_noalloc: the sort keys, the pair order and the
+// work items of up to SW_NOALLOC_MAX_PAIRS pairs, in one array that every
+// GPU the library runs on holds from the library's load until the process
+// ends.  Host code never names the array: it uses the address that
+// hipGetSymbolAddress gives for the current device, looked up once per
+// device when the first handle on that device is created.
+constexpr int64_t kStaticPairs = SW_NOALLOC_MAX_PAIRS;
+constexpr int64_t kStaticKeys = 0;
+constexpr int64_t kStaticOrder = kStaticKeys + 4 * kStaticPairs;
+constexpr int64_t kStaticItems = kStaticOrder + 4 * kStaticPairs;
+constexpr int64_t kStaticBytes = kStaticItems + (kStaticPairs + kMaxBins) * (int64_t)sizeof(WorkItem);
+static __device__ __align__(256) uint8_t scratch[kStaticBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint8_t* g_scratch_addr[kMaxDevices] = {};   // per device: the array's device address
+
+// The array's address on `device`, which must be current; nullptr if the
+// lookup fails.
+static uint8_t* scratch_address(int device) {
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_addr[device]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) == hipSuccess && p)
+            g_scratch_addr[device] = static_cast<uint8_t*>(p);
+        else
+            (void)hipGetLastError();
+    }
+    return g_scratch_addr[device];
+}
+
+// Where one call's per-pair planning arrays live: the handle's own buffers,
+// or the static array of sw_align_batch_noalloc.  Launch grids are sized for
+// `cap` pairs.
+struct Workspace {
+    int32_t* keys;
+    int32_t* order;
+    WorkItem* items;
+    int64_t cap;
+};
+
 constexpr int kLutEntries = 2 * kLutRows;
 constexpr int kCtrBase = 16;     // int index of the first 64-bit counter
 constexpr int kSmallInts = kCtrBase + 2 * kNumCounters;   // flags [0, kNumFlags) | counters
@@ -89,11 +131,13 @@ struct sw_handle {
     int32_t* d_order = nullptr;
     WorkItem* d_items = nullptr;
     int64_t cap_pairs = 0;
+    uint8_t* d_scratch = nullptr;     // this device's address of the static workspace (sw_align_batch_noalloc)
 
     int8_t* h_mats = nullptr;     // pinned
     int32_t* h_small = nullptr;   // pinned
     int32_t* h_meta = nullptr;    // pinned
     int32_t* h_n = nullptr;       // pinned
+    int8_t* h_lut = nullptr;      // pinned staging of the routing table (sw_align_batch_noalloc)
 
     hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     float t_plan = 0.f, t_fwd = 0.f, t_rev = 0.f;
@@ -324,15 +368,16 @@ static int bin_ev_index(int pass, int b, int v, int end) { return ((pass * kMaxB
 
 // Enqueue one pass (planning + sweeps).  Plain mode synchronises `stream`
 // once to read the per-bin item counts.
-static int enqueue_pass(sw_handle* h, KParams K, const ClassifyArgs& C, int64_t cap, int pass,
+static int enqueue_pass(sw_handle* h, KParams K, const ClassifyArgs& C, const Workspace& ws, int pass,
                         hipStream_t stream, bool timing) {
     K.reverse = pass;
+    const int64_t cap = ws.cap;
     const int n_bins = (int)h->bins.size();
     HIP_TRY(h, launch_reset(h->d_hist, kHistSize, stream));
-    HIP_TRY(h, launch_classify(K, C, h->d_lut, h->d_bins, cap, h->d_keys, h->d_hist, counters(h->d_small), stream));
+    HIP_TRY(h, launch_classify(K, C, h->d_lut, h->d_bins, cap, ws.keys, h->d_hist, counters(h->d_small), stream));
     HIP_TRY(h, launch_plan(h->d_bins, n_bins, h->d_hist, h->d_meta, stream));
-    HIP_TRY(h, launch_scatter(h->d_keys, h->d_n, cap, h->d_hist, h->d_order, stream));
-    HIP_TRY(h, launch_items(h->d_meta, h->d_bins, n_bins, h->d_n, cap, h->d_items, stream));
+    HIP_TRY(h, launch_scatter(ws.keys, h->d_n, cap, h->d_hist, ws.order, stream));
+    HIP_TRY(h, launch_items(h->d_meta, h->d_bins, n_bins, h->d_n, cap, ws.items, stream));
     const bool per_bin = timing && h->opt_timing == 2;
     if (timing && h->opt_mode == 1) HIP_TRY(h, hipEventRecord(h->ev[pass == 0 ? 1 : 3], stream));
     if (h->opt_mode == 1) {
@@ -460,6 +505,7 @@ sw_handle* sw_create(int device, const char* tuning) {
     if (hipSetDevice(device) != hipSuccess) return nullptr;
     sw_handle* h = new sw_handle();
     h->device = device;
+    h->d_scratch = scratch_address(device);
     hipDeviceProp_t prop;
     bool ok = hipGetDeviceProperties(&prop, device) == hipSuccess;
     h->n_cu = ok ? prop.multiProcessorCount : 0;
@@ -476,6 +522,7 @@ sw_handle* sw_create(int device, const char* tuning) {
          hipMalloc(&h->d_small, kSmallInts * 4) == hipSuccess &&
          hipMalloc(&h->d_n, 16) == hipSuccess &&
          hipHostMalloc(&h->h_n, 16, hipHostMallocDefault) == hipSuccess &&
+         hipHostMalloc(&h->h_lut, kLutEntries, hipHostMallocDefault) == hipSuccess &&
          hipMalloc(&h->d_hist, kHistSize * 4) == hipSuccess &&
          hipMalloc(&h->d_meta, kMetaSize * 4) == hipSuccess &&
          hipHostMalloc(&h->h_mats, kSchemeBytes, hipHostMallocDefault) == hipSuccess &&
@@ -534,6 +581,7 @@ void sw_destroy(sw_handle* h) {
     drop_graph(h);
     free_dev(h->d_mats); free_dev(h->d_lut); free_dev(h->d_bins); free_dev(h->d_small); free_dev(h->d_n);
     if (h->h_n) (void)hipHostFree(h->h_n);
+    if (h->h_lut) (void)hipHostFree(h->h_lut);
     free_dev(h->d_hist); free_dev(h->d_meta); free_dev(h->d_keys); free_dev(h->d_order);
     free_dev(h->d_items);
     free_dev(h->d_tbins); free_dev(h->d_tlut); free_dev(h->d_rec_off); free_dev(h->d_bsum); free_dev(h->d_ws);
@@ -629,10 +677,13 @@ int sw_get_option(sw_handle* h, const char* key, int64_t* value) {
 // Align pairs given as spans: query i is queries[q_beg[i] .. q_end[i]),
 // reference i is refs[r_beg[i] .. r_end[i]).  Shared by sw_align_batch
 // (spans from prefix offsets) and sw_align_spans.
+// With `no_alloc` the planning arrays live in the static workspace, grids
+// are sized for the batch itself, nothing is captured into a graph and
+// nothing is allocated or freed.
 static int align_spans(sw_handle* h, const uint8_t* queries, const int64_t* q_beg, const int64_t* q_end,
                        const uint8_t* refs, const int64_t* r_beg, const int64_t* r_end,
                        const uint8_t* scheme_id, int64_t n_pairs, const sw_scheme* schemes,
-                       int n_schemes, sw_result* out, void* stream_ptr) {
+                       int n_schemes, sw_result* out, void* stream_ptr, bool no_alloc = false) {
     if (!h) return SW_EINVAL;
     h->err.clear();
     const auto t_entry = std::chrono::steady_clock::now();
@@ -655,17 +706,40 @@ static int align_spans(sw_handle* h, const uint8_t* queries, const int64_t* q_be
         if (sc.gap_open < 1 || sc.gap_extend < 0 || sc.gap_extend > sc.gap_open || sc.gap_open > 1000000)
             return fail(h, SW_EINVAL, "scheme %d: need 1 <= gap_open <= 1e6 and 0 <= gap_extend <= gap_open", s);
     }
+    if (no_alloc && P > kStaticPairs)
+        return fail(h, SW_EINVAL, "%lld pairs: the allocation-free call takes at most %lld", (long long)P,
+                    (long long)kStaticPairs);
     if (P == 0) return SW_OK;
     if (!q_beg || !q_end || !r_beg || !r_end || !queries || !refs || !out)
         return fail(h, SW_EINVAL, "null device pointer with n_pairs > 0");
     hipStream_t stream = (hipStream_t)stream_ptr;
     HIP_TRY(h, hipSetDevice(h->device));
-    int rc = ensure_pairs(h, P);
-    if (rc != SW_OK) return rc;
-    if (h->lut_dirty) {
-        drop_graph(h);
-        HIP_TRY(h, hipMemcpy(h->d_lut, h->lut.data(), kLutEntries, hipMemcpyHostToDevice));
-        h->lut_dirty = false;
+    Workspace ws;
+    if (no_alloc) {
+        if (!h->d_scratch) return fail(h, SW_EDEVICE, "the static workspace has no address on device %d", h->device);
+        ws.keys = reinterpret_cast<int32_t*>(h->d_scratch + kStaticKeys);
+        ws.order = reinterpret_cast<int32_t*>(h->d_scratch + kStaticOrder);
+        ws.items = reinterpret_cast<WorkItem*>(h->d_scratch + kStaticItems);
+        ws.cap = P;
+        // a changed routing table is uploaded, but stays marked dirty: the
+        // next graph-capable call must still drop its graph (which launches
+        // the bins of the old table) and uploads it again
+        if (h->lut_dirty) {
+            memcpy(h->h_lut, h->lut.data(), kLutEntries);
+            HIP_TRY(h, hipMemcpyAsync(h->d_lut, h->h_lut, kLutEntries, hipMemcpyHostToDevice, stream));
+        }
+    } else {
+        int rc = ensure_pairs(h, P);
+        if (rc != SW_OK) return rc;
+        if (h->lut_dirty) {
+            drop_graph(h);
+            HIP_TRY(h, hipMemcpy(h->d_lut, h->lut.data(), kLutEntries, hipMemcpyHostToDevice));
+            h->lut_dirty = false;
+        }
+        ws.keys = h->d_keys;
+        ws.order = h->d_order;
+        ws.items = h->d_items;
+        ws.cap = h->cap_pairs;
     }
 
     // substitution tables: [s][b][a] = M_s[a][b]; padding rows/columns score -1
@@ -710,11 +784,11 @@ static int align_spans(sw_handle* h, const uint8_t* queries, const int64_t* q_be
     KParams K;
     memset(&K, 0, sizeof(K));
     K.queries = queries; K.q_beg = q_beg; K.q_end = q_end; K.refs = refs; K.r_beg = r_beg; K.r_end = r_end;
-    K.scheme_id = scheme_id; K.order = h->d_order; K.items = h->d_items; K.meta = h->d_meta;
+    K.scheme_id = scheme_id; K.order = ws.order; K.items = ws.items; K.meta = h->d_meta;
     K.out = out; K.flags = h->d_small; K.mats = h->d_mats; K.validate = (int32_t)h->opt_validate;
     K.n_dev = h->d_n;
-    K.n_pairs = (int32_t)h->cap_pairs;
-    K.max_items = (int32_t)(h->cap_pairs + kMaxBins);
+    K.n_pairs = (int32_t)ws.cap;
+    K.max_items = (int32_t)(ws.cap + kMaxBins);
     h->h_n[0] = (int32_t)P;
     for (int s = 0; s < SW_MAX_SCHEMES; ++s) {
         const bool v = s < n_schemes;
@@ -728,7 +802,7 @@ static int align_spans(sw_handle* h, const uint8_t* queries, const int64_t* q_be
     }
 
     const bool timing = h->opt_timing != 0;
-    const bool use_graph = h->opt_mode == 1 && h->opt_graph != 0 && !timing;
+    const bool use_graph = h->opt_mode == 1 && h->opt_graph != 0 && !timing && !no_alloc;
     GraphKey key;
     memset(&key, 0, sizeof(key));
     key.queries = queries; key.q_beg = q_beg; key.q_end = q_end; key.refs = refs;
@@ -776,9 +850,9 @@ static int align_spans(sw_handle* h, const uint8_t* queries, const int64_t* q_be
             // graph serves every batch of at most cap_pairs pairs
             if (hipMemcpyAsync(h->d_n, h->h_n, 4, hipMemcpyHostToDevice, es) != hipSuccess)
                 return fail(h, SW_EDEVICE, "batch size upload failed");
-            const int rc0 = enqueue_pass(h, K, C, h->cap_pairs, 0, es, timing);
+            const int rc0 = enqueue_pass(h, K, C, ws, 0, es, timing);
             if (rc0 != SW_OK) return rc0;
-            return enqueue_pass(h, K, C, h->cap_pairs, 1, es, timing);
+            return enqueue_pass(h, K, C, ws, 1, es, timing);
         };
         bool eager = !capturing;
         if (capturing) {
@@ -877,6 +951,16 @@ int sw_align_batch(sw_handle* h, const sw_batch* batch, const sw_scheme* schemes
     const int64_t* ro = batch->r_off;
     return align_spans(h, batch->queries, qo, qo ? qo + 1 : nullptr, batch->refs, ro, ro ? ro + 1 : nullptr,
                        batch->scheme_id, batch->n_pairs, schemes, n_schemes, out, stream_ptr);
+}
+
+int sw_align_batch_noalloc(sw_handle* h, const sw_batch* batch, const sw_scheme* schemes, int n_schemes,
+                           sw_result* out, void* stream_ptr) {
+    if (!h) return SW_EINVAL;
+    if (!batch) return fail(h, SW_EINVAL, "null batch");
+    const int64_t* qo = batch->q_off;
+    const int64_t* ro = batch->r_off;
+    return align_spans(h, batch->queries, qo, qo ? qo + 1 : nullptr, batch->refs, ro, ro ? ro + 1 : nullptr,
+                       batch->scheme_id, batch->n_pairs, schemes, n_schemes, out, stream_ptr, true);
 }
 
 int sw_align_spans(sw_handle* h, const uint8_t* queries, const int64_t* q_beg, const int64_t* q_end,

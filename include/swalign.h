@@ -142,7 +142,8 @@ int sw_get_option(sw_handle* h, const char* key, int64_t* value);
 
 /* Align every pair of `batch` and write out[i] (a DEVICE pointer to
  * n_pairs sw_result records) for pair i.  Work is enqueued on `stream`; the
- * call returns after it has completed (it synchronises `stream`).
+ * call returns after it has completed (it is sw_submit followed by
+ * sw_poll with wait = 1).
  * `schemes` is a HOST array of n_schemes (1..SW_MAX_SCHEMES) schemes.
  * Errors: SW_EINVAL (null pointer with n_pairs > 0, bad scheme, decreasing
  * offsets, scheme id out of range, residue >= alphabet), SW_ETOOLONG (a
@@ -150,6 +151,37 @@ int sw_get_option(sw_handle* h, const char* key, int64_t* value);
  * SW_ENOMEM, SW_EDEVICE.  On error the contents of `out` are undefined. */
 int sw_align_batch(sw_handle* h, const sw_batch* batch, const sw_scheme* schemes,
                    int n_schemes, sw_result* out, void* stream);
+
+/* Asynchronous form of sw_align_batch (the same computation, Section II-B-1
+ * with the affine gap reading above): enqueue the whole call on `stream`
+ * and return at once with *ticket identifying it.  Planning happens on the
+ * device, so nothing waits for the GPU: input checks that need the data
+ * (offsets, scheme ids, lengths, residue codes) are reported by sw_poll.
+ * The caller keeps `batch`'s device buffers and `out` alive and unmodified
+ * until sw_poll reports the ticket finished; `schemes` (host) is read
+ * before sw_submit returns.  Calls of one handle run one after another on
+ * the device, in submission order, whatever their streams (a call on
+ * another stream than the previous one waits for it on the device), and
+ * each result is what sw_align_batch would give for that batch alone.  Up
+ * to 8 calls are in flight per handle; a ninth submit first waits for the
+ * oldest (whose status sw_poll still reports).  A submit may also wait for
+ * the calls in flight when it must replace what they use: a larger
+ * workspace, a new routing table, or a captured graph evicted from the
+ * handle's cache of 4.  Errors returned by sw_submit itself (nothing is
+ * then enqueued and no ticket issued): SW_EINVAL for bad arguments that
+ * the host can see (null pointers, bad schemes, the "timing" option set),
+ * SW_ENOMEM, SW_EDEVICE. */
+int sw_submit(sw_handle* h, const sw_batch* batch, const sw_scheme* schemes, int n_schemes,
+              sw_result* out, void* stream, uint64_t* ticket);
+
+/* Status of a submitted call: with wait == 0, SW_PENDING while it runs;
+ * otherwise (or once it has finished) its final status, as sw_align_batch
+ * would have returned it (SW_OK, SW_EINVAL for invalid input data,
+ * SW_ETOOLONG, SW_EINTERNAL), with the reason in sw_last_error.  Polling a
+ * finished ticket forgets it; an unknown or already collected ticket is
+ * SW_EINVAL.  The statistics calls below describe the last call that
+ * finished.  Poll every ticket: finished statuses are kept until then. */
+int sw_poll(sw_handle* h, uint64_t ticket, int wait);
 
 /* For callers that cannot allocate device memory (code inside a tight
  * serving loop, harnesses that forbid hipMalloc): the same call as
@@ -179,7 +211,9 @@ int sw_align_spans(sw_handle* h, const uint8_t* queries, const int64_t* q_beg, c
                    sw_result* out, void* stream);
 
 /* Database search: align one query against every reference of a set, as
- * sw_align_batch would align the pairs (query, reference i); out[i] is the
+ * sw_align_batch would align the pairs (query, reference i) -- the use that
+ * Sections I and VII give alignment in assembly pipelines, one read against
+ * many candidate sequences; out[i] is the
  * result of reference i.  `query` (q_len residues), `refs` and `r_off`
  * (int64[n_refs+1], non-decreasing; reference i is refs[r_off[i] ..
  * r_off[i+1])) are DEVICE pointers owned by the caller; `scheme` is one HOST
@@ -190,7 +224,7 @@ int sw_align_spans(sw_handle* h, const uint8_t* queries, const int64_t* q_beg, c
 int sw_search(sw_handle* h, const uint8_t* query, int64_t q_len, const uint8_t* refs, const int64_t* r_off,
               int64_t n_refs, const sw_scheme* scheme, sw_result* out, void* stream);
 
-/* Statistics of the last sw_align_batch call on this handle: number of
+/* Statistics of the last alignment call on this handle that finished: number of
  * forward cells (sum of n*m), reverse cells (sum of (q_end+1)*(r_end+1) over
  * pairs with a positive score) and the number of pairs routed to the int32
  * path.  Any pointer may be NULL. */
@@ -305,6 +339,13 @@ int sw_last_bin_stats(sw_handle* h, sw_bin_stat* out, int capacity, int* n_out);
 
 /* ---- serving: continuous batching over a device-resident pool ----------
  *
+ * The paper's alignment workload (Section II-B) arrives as independent
+ * batches of pairs; these calls serve such batches as requests that come
+ * and go while others run, each aligned exactly as sw_align_batch would
+ * align it alone.  Unlike sw_submit, requests are HOST arrays: the server
+ * owns the device copies (its pool), so it can admit requests by device
+ * memory and free them itself.
+ *
  * A server owns a device memory pool of `pool_bytes` (the admission budget),
  * `slots` worker streams (1..16) and a copy of the schemes.  Requests are
  * batches of pairs given as HOST arrays (same layout as sw_batch); submit
@@ -316,7 +357,9 @@ int sw_last_bin_stats(sw_handle* h, sw_bin_stat* out, int capacity, int* n_out);
  * Requests that arrive while others run are admitted and merged into the
  * next batch of the first slot to free up, so work from different requests
  * overlaps on the device.  Results are identical to aligning each request
- * alone.  A server may be driven from several host threads. */
+ * alone.  Each slot's call is captured into a graph once, when the server
+ * is created, and replayed for every batch.  A server may be driven from
+ * several host threads. */
 typedef struct sw_server sw_server;
 
 /* Returns NULL on failure (bad scheme, no such device, allocation failure).

@@ -34,7 +34,7 @@ _ERRNAMES = {SW_EINVAL: "SW_EINVAL", SW_ENOMEM: "SW_ENOMEM", SW_ETOOLONG: "SW_ET
              SW_EDEVICE: "SW_EDEVICE", SW_EINTERNAL: "SW_EINTERNAL"}
 
 EXPORTED = ("sw_create", "sw_destroy", "sw_last_error", "sw_set_option", "sw_get_option",
-            "sw_align_batch", "sw_align_batch_noalloc", "sw_align_spans", "sw_last_stats", "sw_last_timing", "sw_last_host_timing", "sw_last_bin_stats",
+            "sw_align_batch", "sw_align_batch_noalloc", "sw_submit", "sw_poll", "sw_align_spans", "sw_last_stats", "sw_last_timing", "sw_last_host_timing", "sw_last_bin_stats",
             "sw_shapes", "sw_set_routing", "sw_get_routing", "sw_align_cigar", "sw_last_cigar_stats", "sw_search",
             "sw_server_create", "sw_server_destroy", "sw_server_last_error", "sw_server_submit",
             "sw_server_poll", "sw_server_stats", "sw_server_timing")
@@ -95,6 +95,11 @@ def load_library(path: str = LIB_PATH):
     lib.sw_align_batch_noalloc.restype = ctypes.c_int
     lib.sw_align_batch_noalloc.argtypes = [ctypes.c_void_p, ctypes.POINTER(sw_batch), ctypes.POINTER(sw_scheme),
                                            ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
+    lib.sw_submit.restype = ctypes.c_int
+    lib.sw_submit.argtypes = [ctypes.c_void_p, ctypes.POINTER(sw_batch), ctypes.POINTER(sw_scheme), ctypes.c_int,
+                              ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64)]
+    lib.sw_poll.restype = ctypes.c_int
+    lib.sw_poll.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int]
     lib.sw_align_spans.restype = ctypes.c_int
     lib.sw_align_spans.argtypes = [ctypes.c_void_p] + [ctypes.c_void_p] * 7 + [ctypes.c_int64, ctypes.POINTER(sw_scheme),
                                                                              ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
@@ -187,6 +192,18 @@ def sw_align_batch(h: int, batch: sw_batch, schemes, n_schemes: int, out_ptr: in
 def sw_align_batch_noalloc(h: int, batch: sw_batch, schemes, n_schemes: int, out_ptr: int, stream_ptr) -> int:
     """Raw call of the allocation-free variant; returns the status code."""
     return load_library().sw_align_batch_noalloc(h, ctypes.byref(batch), schemes, n_schemes, out_ptr, stream_ptr)
+
+
+def sw_submit(h: int, batch: sw_batch, schemes, n_schemes: int, out_ptr, stream_ptr):
+    """Raw call; returns (status, ticket)."""
+    t = ctypes.c_uint64(0)
+    rc = load_library().sw_submit(h, ctypes.byref(batch), schemes, n_schemes, out_ptr, stream_ptr, ctypes.byref(t))
+    return rc, int(t.value)
+
+
+def sw_poll(h: int, ticket: int, wait: int) -> int:
+    """Raw call; returns the status code (SW_PENDING while the call runs)."""
+    return load_library().sw_poll(h, ticket, wait)
 
 
 def sw_align_spans(h: int, queries, q_beg, q_end, refs, r_beg, r_end, scheme_id, n_pairs: int, schemes,
@@ -369,6 +386,32 @@ class Aligner:
         _check(self.h, rc)
         del keep
         return out
+
+    def submit(self, dbatch: DeviceBatch, out, stream=None) -> int:
+        """Enqueue the alignment of a DeviceBatch into `out` (int32 [n_pairs,
+        5] on the device) without waiting; returns the ticket for poll().
+        The batch and `out` are kept referenced until the ticket is polled."""
+        import torch
+        assert out.is_contiguous() and out.dtype == torch.int32 and out.shape == (dbatch.n_pairs, 5)
+        arr, keep = make_schemes(dbatch.schemes)
+        s = stream if stream is not None else torch.cuda.current_stream(dbatch.q_off.device)
+        rc, t = sw_submit(self.h, dbatch.c_struct(), arr, len(dbatch.schemes),
+                          out.data_ptr() if dbatch.n_pairs else None, ctypes.c_void_p(s.cuda_stream))
+        _check(self.h, rc)
+        del keep
+        self._inflight = getattr(self, "_inflight", {})
+        self._inflight[t] = (dbatch, out)
+        return t
+
+    def poll(self, ticket: int, wait: bool = True) -> bool:
+        """True once the call of `ticket` has finished (raises SwError if it
+        failed), False while it runs (wait=False only)."""
+        rc = sw_poll(self.h, ticket, 1 if wait else 0)
+        if rc == SW_PENDING:
+            return False
+        getattr(self, "_inflight", {}).pop(ticket, None)
+        _check(self.h, rc)
+        return True
 
     def align_noalloc(self, dbatch: DeviceBatch, out, stream=None):
         """align() through sw_align_batch_noalloc: the caller provides `out`

@@ -174,6 +174,9 @@ QueueFn shape_kernel(int prec, int W, int R, bool reverse, bool col = false);
 const ShapeDesc* compiled_shapes(int* n);
 
 hipError_t launch_reset(int32_t* p, int n, hipStream_t s);
+// Start of an alignment call: small[0..n_small) = 0 (flags and counters) and
+// *n_dev = n_pairs.
+hipError_t launch_call_start(int32_t* small, int n_small, int32_t* n_dev, int32_t n_pairs, hipStream_t s);
 // beg[0..n) = 0, end[0..n) = len (the query spans of a database search)
 hipError_t launch_fill_span(int64_t* beg, int64_t* end, int64_t n, int64_t len, hipStream_t s);
 // The planning launches are sized for `cap` pairs; the kernels take the

@@ -25,6 +25,11 @@ __global__ void sw_reset_kernel(int32_t* p, int n) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
 }
 
+__global__ void sw_call_start_kernel(int32_t* small, int n_small, int32_t* n_dev, int32_t n_pairs) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_small; i += gridDim.x * blockDim.x) small[i] = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *n_dev = n_pairs;
+}
+
 __global__ void sw_classify_kernel(KParams P, ClassifyArgs C, const int8_t* lut, const BinInfo* bins,
                                    int32_t* keys, int32_t* hist, unsigned long long* counters) {
     const int64_t n_pairs = *P.n_dev;
@@ -272,6 +277,13 @@ hipError_t launch_reset(int32_t* p, int n, hipStream_t s) {
     unsigned blocks = grid_for(n, 256);
     if (blocks > 1024) blocks = 1024;
     hipLaunchKernelGGL(sw_reset_kernel, dim3(blocks), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_call_start(int32_t* small, int n_small, int32_t* n_dev, int32_t n_pairs, hipStream_t s) {
+    unsigned blocks = grid_for(n_small, 256);
+    if (blocks > 64) blocks = 64;
+    hipLaunchKernelGGL(sw_call_start_kernel, dim3(blocks), dim3(256), 0, s, small, n_small, n_dev, n_pairs);
     return hipGetLastError();
 }
 

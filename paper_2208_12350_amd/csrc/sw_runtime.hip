@@ -20,6 +20,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -124,7 +125,7 @@ struct sw_handle {
     int8_t* d_lut = nullptr;
     BinInfo* d_bins = nullptr;
     int32_t* d_small = nullptr;
-    int32_t* d_n = nullptr;       // batch size, copied from h_n at the start of each call
+    int32_t* d_n = nullptr;       // batch size, written by the call-start kernel of each call
     int32_t* d_hist = nullptr;
     int32_t* d_meta = nullptr;
     int32_t* d_keys = nullptr;
@@ -133,10 +134,31 @@ struct sw_handle {
     int64_t cap_pairs = 0;
     uint8_t* d_scratch = nullptr;     // this device's address of the static workspace (sw_align_batch_noalloc)
 
-    int8_t* h_mats = nullptr;     // pinned
-    int32_t* h_small = nullptr;   // pinned
+    int32_t* h_small = nullptr;   // pinned (alignment paths)
     int32_t* h_meta = nullptr;    // pinned
-    int32_t* h_n = nullptr;       // pinned
+    std::vector<int8_t> dev_mats;       // what d_mats holds (or will, in stream order) after the last upload
+    std::vector<int8_t> tables;         // the current call's tables, built on the host
+
+    // Calls in flight (sw_submit): each holds one slot until it is polled,
+    // or completed by a later submit that needs the slot.  A slot's pinned
+    // buffers receive the call's scheme tables (when they must be uploaded)
+    // and its flags and counters; its event marks the end of the call.
+    struct CallSlot {
+        uint64_t ticket = 0;           // 0 = free
+        hipEvent_t done = nullptr;
+        int32_t* h_small = nullptr;    // pinned: flags and counters of the call
+        int8_t* h_mats = nullptr;      // pinned: staging of the scheme tables
+        bool timing = false;
+        std::chrono::steady_clock::time_point t_entry;
+    };
+    static constexpr int kSlots = 8;
+    CallSlot slots[kSlots];
+    uint64_t next_ticket = 1;
+    int next_slot = 0;
+    int last_slot = -1;                 // slot of the last submitted call
+    hipStream_t last_stream = nullptr;
+    struct Finished { int status; std::string err; };
+    std::map<uint64_t, Finished> finished;   // completed but not yet polled
     int8_t* h_lut = nullptr;      // pinned staging of the routing table (sw_align_batch_noalloc)
 
     hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
@@ -151,10 +173,14 @@ struct sw_handle {
     static constexpr int kForks = 4;    // persistent mode spreads bins over these streams
     hipStream_t fork[kForks] = {nullptr, nullptr, nullptr, nullptr};
     hipEvent_t fork_ev[kForks + 1] = {nullptr, nullptr, nullptr, nullptr, nullptr};
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t gexec = nullptr;
-    GraphKey gkey;
-    bool have_graph = false;
+    // captured calls, most recently used last (at most kGraphs)
+    struct GraphEntry {
+        GraphKey key;
+        hipGraph_t graph;
+        hipGraphExec_t exec;
+    };
+    static constexpr int kGraphs = 4;
+    std::vector<GraphEntry> graphs;
     int64_t n_captures = 0;
     int64_t n_capture_refusals = 0;
 
@@ -334,12 +360,30 @@ static void free_dev(void* p) {
     if (p) (void)hipFree(p);
 }
 
+static int complete_slot(sw_handle* h, int k);
+
+// Wait for every call in flight on the handle; their statuses are kept
+// for sw_poll.  Needed before anything they may still use is freed,
+// replaced or rewritten from the host.
+static void drain(sw_handle* h) {
+    for (int k = 0; k < sw_handle::kSlots; ++k) {
+        sw_handle::CallSlot& sl = h->slots[k];
+        if (!sl.ticket) continue;
+        const uint64_t t = sl.ticket;
+        (void)hipEventSynchronize(sl.done);
+        const int st = complete_slot(h, k);
+        h->finished[t] = sw_handle::Finished{st, h->err};
+    }
+    h->err.clear();
+}
+
 static void drop_graph(sw_handle* h) {
-    if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
-    if (h->graph) (void)hipGraphDestroy(h->graph);
-    h->gexec = nullptr;
-    h->graph = nullptr;
-    h->have_graph = false;
+    drain(h);
+    for (sw_handle::GraphEntry& g : h->graphs) {
+        (void)hipGraphExecDestroy(g.exec);
+        (void)hipGraphDestroy(g.graph);
+    }
+    h->graphs.clear();
 }
 
 static int ensure_pairs(sw_handle* h, int64_t n) {
@@ -521,13 +565,17 @@ sw_handle* sw_create(int device, const char* tuning) {
          hipMalloc(&h->d_bins, kMaxBins * sizeof(BinInfo)) == hipSuccess &&
          hipMalloc(&h->d_small, kSmallInts * 4) == hipSuccess &&
          hipMalloc(&h->d_n, 16) == hipSuccess &&
-         hipHostMalloc(&h->h_n, 16, hipHostMallocDefault) == hipSuccess &&
          hipHostMalloc(&h->h_lut, kLutEntries, hipHostMallocDefault) == hipSuccess &&
          hipMalloc(&h->d_hist, kHistSize * 4) == hipSuccess &&
          hipMalloc(&h->d_meta, kMetaSize * 4) == hipSuccess &&
-         hipHostMalloc(&h->h_mats, kSchemeBytes, hipHostMallocDefault) == hipSuccess &&
          hipHostMalloc(&h->h_small, kSmallInts * 4, hipHostMallocDefault) == hipSuccess &&
          hipHostMalloc(&h->h_meta, kMetaSize * 4, hipHostMallocDefault) == hipSuccess;
+    for (int k = 0; ok && k < sw_handle::kSlots; ++k) {
+        sw_handle::CallSlot& sl = h->slots[k];
+        ok = hipHostMalloc(&sl.h_small, kSmallInts * 4, hipHostMallocDefault) == hipSuccess &&
+             hipHostMalloc(&sl.h_mats, kSchemeBytes, hipHostMallocDefault) == hipSuccess &&
+             hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) == hipSuccess;
+    }
     for (int k = 0; ok && k < 5; ++k) ok = hipEventCreate(&h->ev[k]) == hipSuccess;
     for (int f = 0; ok && f < sw_handle::kForks; ++f)
         ok = hipStreamCreateWithFlags(&h->fork[f], hipStreamNonBlocking) == hipSuccess;
@@ -580,8 +628,13 @@ void sw_destroy(sw_handle* h) {
     (void)hipDeviceSynchronize();
     drop_graph(h);
     free_dev(h->d_mats); free_dev(h->d_lut); free_dev(h->d_bins); free_dev(h->d_small); free_dev(h->d_n);
-    if (h->h_n) (void)hipHostFree(h->h_n);
     if (h->h_lut) (void)hipHostFree(h->h_lut);
+    for (int k = 0; k < sw_handle::kSlots; ++k) {
+        sw_handle::CallSlot& sl = h->slots[k];
+        if (sl.h_small) (void)hipHostFree(sl.h_small);
+        if (sl.h_mats) (void)hipHostFree(sl.h_mats);
+        if (sl.done) (void)hipEventDestroy(sl.done);
+    }
     free_dev(h->d_hist); free_dev(h->d_meta); free_dev(h->d_keys); free_dev(h->d_order);
     free_dev(h->d_items);
     free_dev(h->d_tbins); free_dev(h->d_tlut); free_dev(h->d_rec_off); free_dev(h->d_bsum); free_dev(h->d_ws);
@@ -589,7 +642,6 @@ void sw_destroy(sw_handle* h) {
     if (h->h_i64) (void)hipHostFree(h->h_i64);
     for (hipEvent_t e : h->tbin_ev)
         if (e) (void)hipEventDestroy(e);
-    if (h->h_mats) (void)hipHostFree(h->h_mats);
     if (h->h_small) (void)hipHostFree(h->h_small);
     if (h->h_meta) (void)hipHostFree(h->h_meta);
     for (int k = 0; k < 5; ++k)
@@ -674,24 +726,97 @@ int sw_get_option(sw_handle* h, const char* key, int64_t* value) {
 
 }  // extern "C"
 
-// Align pairs given as spans: query i is queries[q_beg[i] .. q_end[i]),
-// reference i is refs[r_beg[i] .. r_end[i]).  Shared by sw_align_batch
-// (spans from prefix offsets) and sw_align_spans.
+// Status of a finished call from its flags and counters (in slot k's pinned
+// buffer); frees the slot.  Sets the handle's statistics of the last call
+// (and, for a timed call, its phase and per-launch times).
+static int complete_slot(sw_handle* h, int k) {
+    sw_handle::CallSlot& sl = h->slots[k];
+    sl.ticket = 0;
+    if (h->last_slot == k) h->last_slot = -1;
+    h->err.clear();
+    const int32_t* flags = sl.h_small;
+    const unsigned long long* cnt = counters(sl.h_small);
+    h->last_fwd = (int64_t)cnt[kCtrFwdCells];
+    h->last_rev = (int64_t)cnt[kCtrRevCells];
+    h->last_i32 = (int64_t)cnt[kCtrI32Pairs];
+    h->bin_stats.clear();
+    for (int pass = 0; pass < 2; ++pass)
+        for (int b = 0; b < (int)h->bins.size(); ++b)
+            for (int v = h->bins[b].col ? 1 : 0; v >= 0; --v) {
+                sw_bin_stat st;
+                memset(&st, 0, sizeof(st));
+                st.pass = pass;
+                st.precision = h->bins[b].prec;
+                st.lanes = h->bins[b].W;
+                st.rows = h->bins[b].R;
+                st.column = v;
+                const int i = pass * kMaxBins + b;
+                const int64_t col_cells = (int64_t)cnt[kCtrBinColCells + i];
+                const int64_t col_pairs = (int64_t)cnt[kCtrBinColPairs + i];
+                st.cells = v ? col_cells : (int64_t)cnt[kCtrBinCells + i] - col_cells;
+                st.pairs = v ? col_pairs : (int64_t)cnt[kCtrBinPairs + i] - col_pairs;
+                h->bin_stats.push_back(st);
+            }
+    h->t_plan = h->t_fwd = h->t_rev = 0.f;
+    if (sl.timing) {
+        float a = 0, b = 0;
+        HIP_TRY(h, hipEventElapsedTime(&a, h->ev[0], h->ev[1]));
+        HIP_TRY(h, hipEventElapsedTime(&h->t_fwd, h->ev[1], h->ev[2]));
+        HIP_TRY(h, hipEventElapsedTime(&b, h->ev[2], h->ev[3]));
+        HIP_TRY(h, hipEventElapsedTime(&h->t_rev, h->ev[3], h->ev[4]));
+        h->t_plan = a + b;
+        if (h->opt_timing == 2)
+            for (sw_bin_stat& st : h->bin_stats) {
+                // only launched kernels have events (plain mode skips empty
+                // item ranges; no mode launches a bin no route points at)
+                const int b = find_bin(h, st.precision, st.lanes, st.rows);
+                const int i = bin_ev_index(st.pass, b, st.column, 0);
+                if (!h->bin_launched[i / 2]) continue;
+                HIP_TRY(h, hipEventElapsedTime(&st.ms, h->bin_ev[i], h->bin_ev[i + 1]));
+            }
+    }
+    if (flags[kFlagBadOffsets]) return fail(h, SW_EINVAL, "offsets decrease");
+    if (flags[kFlagBadScheme]) return fail(h, SW_EINVAL, "scheme id out of range");
+    if (flags[kFlagTooLong])
+        return fail(h, SW_ETOOLONG, "a query exceeds %d or a reference exceeds %d residues", SW_MAX_QUERY, SW_MAX_REF);
+    if (flags[kFlagBadResidue]) return fail(h, SW_EINVAL, "residue code outside its scheme's alphabet");
+    if (flags[kFlagReverseMismatch]) return fail(h, SW_EINTERNAL, "reverse sweep did not reproduce the forward score");
+    if (flags[kFlagInternal]) return fail(h, SW_EINTERNAL, "a planning invariant did not hold");
+    return SW_OK;
+}
+
+// A ticket whose call needed no device work (an empty batch).
+static uint64_t finish_now(sw_handle* h) {
+    const uint64_t t = h->next_ticket++;
+    h->finished[t] = sw_handle::Finished{SW_OK, std::string()};
+    h->last_fwd = h->last_rev = h->last_i32 = 0;
+    h->bin_stats.clear();
+    h->t_plan = h->t_fwd = h->t_rev = 0.f;
+    return t;
+}
+
+// Enqueue the alignment of pairs given as spans (query i is queries[q_beg[i]
+// .. q_end[i]), reference i is refs[r_beg[i] .. r_end[i])) on `stream`, and
+// return a ticket for sw_poll.  Nothing waits for the device, except a
+// submit that finds every slot in flight (it completes the oldest) or that
+// must free or rewrite what calls in flight use (a larger workspace, a new
+// routing table, a graph evicted from the cache).  Shared by sw_submit,
+// sw_align_batch and sw_align_spans (a submit and a wait), and
+// sw_align_batch_noalloc.
 // With `no_alloc` the planning arrays live in the static workspace, grids
 // are sized for the batch itself, nothing is captured into a graph and
-// nothing is allocated or freed.
-static int align_spans(sw_handle* h, const uint8_t* queries, const int64_t* q_beg, const int64_t* q_end,
-                       const uint8_t* refs, const int64_t* r_beg, const int64_t* r_end,
-                       const uint8_t* scheme_id, int64_t n_pairs, const sw_scheme* schemes,
-                       int n_schemes, sw_result* out, void* stream_ptr, bool no_alloc = false) {
+// nothing is allocated or freed.  Timed calls (`allow_timing`) must be
+// waited for before the next call: they share the handle's events.
+static int submit_spans(sw_handle* h, const uint8_t* queries, const int64_t* q_beg, const int64_t* q_end,
+                        const uint8_t* refs, const int64_t* r_beg, const int64_t* r_end,
+                        const uint8_t* scheme_id, int64_t n_pairs, const sw_scheme* schemes,
+                        int n_schemes, sw_result* out, void* stream_ptr, bool no_alloc, bool allow_timing,
+                        uint64_t* ticket) {
     if (!h) return SW_EINVAL;
     h->err.clear();
     const auto t_entry = std::chrono::steady_clock::now();
-    h->last_fwd = h->last_rev = h->last_i32 = 0;
-    h->t_plan = h->t_fwd = h->t_rev = 0.f;
     h->t_enqueue = h->t_wait = 0.0;
-    h->bin_stats.clear();
-    h->bin_launched.assign(2 * kMaxBins * 2, 0);
+    if (!ticket) return fail(h, SW_EINVAL, "null ticket");
     if (!schemes) return fail(h, SW_EINVAL, "null schemes");
     if (n_schemes < 1 || n_schemes > SW_MAX_SCHEMES)
         return fail(h, SW_EINVAL, "n_schemes must be 1..%d", SW_MAX_SCHEMES);
@@ -709,11 +834,33 @@ static int align_spans(sw_handle* h, const uint8_t* queries, const int64_t* q_be
     if (no_alloc && P > kStaticPairs)
         return fail(h, SW_EINVAL, "%lld pairs: the allocation-free call takes at most %lld", (long long)P,
                     (long long)kStaticPairs);
-    if (P == 0) return SW_OK;
+    const bool timing = h->opt_timing != 0;
+    if (timing && !allow_timing)
+        return fail(h, SW_EINVAL, "the \"timing\" option needs a synchronous call (sw_align_batch)");
+    if (P == 0) {
+        *ticket = finish_now(h);
+        return SW_OK;
+    }
     if (!q_beg || !q_end || !r_beg || !r_end || !queries || !refs || !out)
         return fail(h, SW_EINVAL, "null device pointer with n_pairs > 0");
     hipStream_t stream = (hipStream_t)stream_ptr;
     HIP_TRY(h, hipSetDevice(h->device));
+
+    // a slot for this call: the oldest in flight is completed if need be
+    const int k = h->next_slot;
+    sw_handle::CallSlot& sl = h->slots[k];
+    if (sl.ticket) {
+        const uint64_t t = sl.ticket;
+        HIP_TRY(h, hipEventSynchronize(sl.done));
+        const int st = complete_slot(h, k);
+        h->finished[t] = sw_handle::Finished{st, h->err};
+        h->err.clear();
+    }
+    // calls of one handle share its workspace: one submitted on another
+    // stream than the last waits for it on the device
+    if (h->last_slot >= 0 && h->last_stream != stream)
+        HIP_TRY(h, hipStreamWaitEvent(stream, h->slots[h->last_slot].done, 0));
+
     Workspace ws;
     if (no_alloc) {
         if (!h->d_scratch) return fail(h, SW_EDEVICE, "the static workspace has no address on device %d", h->device);
@@ -721,9 +868,9 @@ static int align_spans(sw_handle* h, const uint8_t* queries, const int64_t* q_be
         ws.order = reinterpret_cast<int32_t*>(h->d_scratch + kStaticOrder);
         ws.items = reinterpret_cast<WorkItem*>(h->d_scratch + kStaticItems);
         ws.cap = P;
-        // a changed routing table is uploaded, but stays marked dirty: the
-        // next graph-capable call must still drop its graph (which launches
-        // the bins of the old table) and uploads it again
+        // a changed routing table is uploaded in stream order, but stays
+        // marked dirty: the next graph-capable call must still drop its
+        // graphs (which launch the bins of the old table) and upload it again
         if (h->lut_dirty) {
             memcpy(h->h_lut, h->lut.data(), kLutEntries);
             HIP_TRY(h, hipMemcpyAsync(h->d_lut, h->h_lut, kLutEntries, hipMemcpyHostToDevice, stream));
@@ -744,8 +891,9 @@ static int align_spans(sw_handle* h, const uint8_t* queries, const int64_t* q_be
 
     // substitution tables: [s][b][a] = M_s[a][b]; padding rows/columns score -1
     ClassifyArgs C;
+    h->tables.assign(kSchemeBytes, 0);
     for (int s = 0; s < SW_MAX_SCHEMES; ++s) {
-        int8_t* T = h->h_mats + s * kMatBytes;
+        int8_t* T = h->tables.data() + s * kMatBytes;
         int mx = 1;
         for (int b = 0; b < kMatDim; ++b)
             for (int a = 0; a < kMatDim; ++a) {
@@ -760,7 +908,7 @@ static int align_spans(sw_handle* h, const uint8_t* queries, const int64_t* q_be
         // small-alphabet column path: alphabet <= 4, 1 <= o <= kI16Bias and
         // every M[a][b] + o a byte; column word of residue b = bytes
         // M[a][b] + o, a = 0..3 (0 for residues outside the alphabet)
-        uint32_t* cw = reinterpret_cast<uint32_t*>(h->h_mats + SW_MAX_SCHEMES * kMatBytes) + s * kMatDim;
+        uint32_t* cw = reinterpret_cast<uint32_t*>(h->tables.data() + SW_MAX_SCHEMES * kMatBytes) + s * kMatDim;
         bool ok = s < n_schemes && schemes[s].alphabet <= 4 && schemes[s].gap_open >= 1 &&
                   schemes[s].gap_open <= kI16Bias;
         for (int b = 0; b < kMatDim; ++b) {
@@ -789,7 +937,6 @@ static int align_spans(sw_handle* h, const uint8_t* queries, const int64_t* q_be
     K.n_dev = h->d_n;
     K.n_pairs = (int32_t)ws.cap;
     K.max_items = (int32_t)(ws.cap + kMaxBins);
-    h->h_n[0] = (int32_t)P;
     for (int s = 0; s < SW_MAX_SCHEMES; ++s) {
         const bool v = s < n_schemes;
         K.alphabet[s] = v ? schemes[s].alphabet : 1;
@@ -801,7 +948,6 @@ static int align_spans(sw_handle* h, const uint8_t* queries, const int64_t* q_be
         h->last_col_ok[s] = K.col_ok[s];
     }
 
-    const bool timing = h->opt_timing != 0;
     const bool use_graph = h->opt_mode == 1 && h->opt_graph != 0 && !timing && !no_alloc;
     GraphKey key;
     memset(&key, 0, sizeof(key));
@@ -815,8 +961,34 @@ static int align_spans(sw_handle* h, const uint8_t* queries, const int64_t* q_be
     memcpy(key.col_ok, C.col_ok, sizeof(key.col_ok));
     key.n_schemes = n_schemes; key.validate = (int32_t)h->opt_validate; key.precision = (int32_t)h->opt_precision;
 
-    if (use_graph && h->have_graph && memcmp(&key, &h->gkey, sizeof(key)) == 0) {
-        HIP_TRY(h, hipGraphLaunch(h->gexec, stream));
+    // Start of the call, in stream order and outside any graph: the scheme
+    // tables when they differ from what the device holds (from this call's
+    // own pinned staging, which no later call rewrites while it is in
+    // flight), then one kernel that clears the flags and counters and
+    // writes the batch size (a kernel argument, so nothing on the host
+    // must outlive the submit).  A captured graph reads the batch size from
+    // device memory, so it serves every batch of at most cap_pairs pairs.
+    if (timing) HIP_TRY(h, hipEventRecord(h->ev[0], stream));
+    if (h->dev_mats != h->tables) {
+        memcpy(sl.h_mats, h->tables.data(), kSchemeBytes);
+        HIP_TRY(h, hipMemcpyAsync(h->d_mats, sl.h_mats, kSchemeBytes, hipMemcpyHostToDevice, stream));
+        h->dev_mats = h->tables;
+    }
+    HIP_TRY(h, launch_call_start(h->d_small, kSmallInts, h->d_n, (int32_t)P, stream));
+
+    auto enqueue_all = [&](hipStream_t es) -> int {
+        const int rc0 = enqueue_pass(h, K, C, ws, 0, es, timing);
+        if (rc0 != SW_OK) return rc0;
+        return enqueue_pass(h, K, C, ws, 1, es, timing);
+    };
+    if (timing) h->bin_launched.assign(2 * kMaxBins * 2, 0);
+    int gi = -1;
+    for (int g = 0; use_graph && g < (int)h->graphs.size(); ++g)
+        if (memcmp(&key, &h->graphs[g].key, sizeof(key)) == 0) gi = g;
+    if (gi >= 0) {
+        // most recently used last
+        std::rotate(h->graphs.begin() + gi, h->graphs.begin() + gi + 1, h->graphs.end());
+        HIP_TRY(h, hipGraphLaunch(h->graphs.back().exec, stream));
     } else {
         // The graph is captured on the handle's private stream (the caller's
         // stream may be the null stream, which cannot be captured) and then
@@ -828,7 +1000,14 @@ static int align_spans(sw_handle* h, const uint8_t* queries, const int64_t* q_be
         std::unique_lock<std::mutex> capture_lock(g_capture_mu, std::defer_lock);
         bool capturing = false;
         if (use_graph) {
-            drop_graph(h);
+            if ((int)h->graphs.size() >= sw_handle::kGraphs) {
+                // evict the least recently used graph once nothing in
+                // flight can still be running it
+                drain(h);
+                (void)hipGraphExecDestroy(h->graphs.front().exec);
+                (void)hipGraphDestroy(h->graphs.front().graph);
+                h->graphs.erase(h->graphs.begin());
+            }
             // created on first use, so that the fork streams, created with
             // the handle, take consecutive hardware queues
             if (!h->cap_stream) HIP_TRY(h, hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
@@ -840,33 +1019,22 @@ static int align_spans(sw_handle* h, const uint8_t* queries, const int64_t* q_be
                 ++h->n_capture_refusals;
             }
         }
-        auto enqueue_all = [&](hipStream_t es) -> int {
-            if (timing && hipEventRecord(h->ev[0], es) != hipSuccess) return fail(h, SW_EDEVICE, "event");
-            if (hipMemcpyAsync(h->d_mats, h->h_mats, kSchemeBytes, hipMemcpyHostToDevice, es) !=
-                hipSuccess)
-                return fail(h, SW_EDEVICE, "matrix upload failed");
-            if (launch_reset(h->d_small, kSmallInts, es) != hipSuccess) return fail(h, SW_EDEVICE, "reset");
-            // the batch size travels through device memory, so a captured
-            // graph serves every batch of at most cap_pairs pairs
-            if (hipMemcpyAsync(h->d_n, h->h_n, 4, hipMemcpyHostToDevice, es) != hipSuccess)
-                return fail(h, SW_EDEVICE, "batch size upload failed");
-            const int rc0 = enqueue_pass(h, K, C, ws, 0, es, timing);
-            if (rc0 != SW_OK) return rc0;
-            return enqueue_pass(h, K, C, ws, 1, es, timing);
-        };
         bool eager = !capturing;
         if (capturing) {
             const int erc = enqueue_all(h->cap_stream);
             hipGraph_t g = nullptr;
             const hipError_t ce = hipStreamEndCapture(h->cap_stream, &g);
             if (erc == SW_OK && ce == hipSuccess && g) {
-                h->graph = g;
                 ++h->n_captures;
-                HIP_TRY(h, hipGraphInstantiate(&h->gexec, h->graph, nullptr, nullptr, 0));
+                hipGraphExec_t ge = nullptr;
+                const hipError_t ie = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
                 capture_lock.unlock();
-                h->gkey = key;
-                h->have_graph = true;
-                HIP_TRY(h, hipGraphLaunch(h->gexec, stream));
+                if (ie != hipSuccess) {
+                    (void)hipGraphDestroy(g);
+                    return fail(h, SW_EDEVICE, "hipGraphInstantiate failed: %s", hipGetErrorString(ie));
+                }
+                h->graphs.push_back(sw_handle::GraphEntry{key, g, ge});
+                HIP_TRY(h, hipGraphLaunch(ge, stream));
             } else {
                 // nothing captured has run: discard it and run the call eagerly
                 if (g) (void)hipGraphDestroy(g);
@@ -887,58 +1055,65 @@ static int align_spans(sw_handle* h, const uint8_t* queries, const int64_t* q_be
             if (erc != SW_OK) return erc;
         }
     }
-    const auto t_enq = std::chrono::steady_clock::now();
-    HIP_TRY(h, hipMemcpyAsync(h->h_small, h->d_small, kSmallInts * 4, hipMemcpyDeviceToHost, stream));
-    HIP_TRY(h, hipStreamSynchronize(stream));
-    h->t_enqueue = std::chrono::duration<double, std::milli>(t_enq - t_entry).count();
-    h->t_wait = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_enq).count();
-    const int32_t* flags = h->h_small;
-    const unsigned long long* cnt = counters(h->h_small);
-    h->last_fwd = (int64_t)cnt[kCtrFwdCells];
-    h->last_rev = (int64_t)cnt[kCtrRevCells];
-    h->last_i32 = (int64_t)cnt[kCtrI32Pairs];
-    for (int pass = 0; pass < 2; ++pass)
-        for (int b = 0; b < (int)h->bins.size(); ++b)
-            for (int v = h->bins[b].col ? 1 : 0; v >= 0; --v) {
-                sw_bin_stat st;
-                memset(&st, 0, sizeof(st));
-                st.pass = pass;
-                st.precision = h->bins[b].prec;
-                st.lanes = h->bins[b].W;
-                st.rows = h->bins[b].R;
-                st.column = v;
-                const int i = pass * kMaxBins + b;
-                const int64_t col_cells = (int64_t)cnt[kCtrBinColCells + i];
-                const int64_t col_pairs = (int64_t)cnt[kCtrBinColPairs + i];
-                st.cells = v ? col_cells : (int64_t)cnt[kCtrBinCells + i] - col_cells;
-                st.pairs = v ? col_pairs : (int64_t)cnt[kCtrBinPairs + i] - col_pairs;
-                h->bin_stats.push_back(st);
-            }
-    if (timing) {
-        float a = 0, b = 0;
-        HIP_TRY(h, hipEventElapsedTime(&a, h->ev[0], h->ev[1]));
-        HIP_TRY(h, hipEventElapsedTime(&h->t_fwd, h->ev[1], h->ev[2]));
-        HIP_TRY(h, hipEventElapsedTime(&b, h->ev[2], h->ev[3]));
-        HIP_TRY(h, hipEventElapsedTime(&h->t_rev, h->ev[3], h->ev[4]));
-        h->t_plan = a + b;
-        if (h->opt_timing == 2)
-            for (sw_bin_stat& st : h->bin_stats) {
-                // only launched kernels have events (plain mode skips empty
-                // item ranges; no mode launches a bin no route points at)
-                const int b = find_bin(h, st.precision, st.lanes, st.rows);
-                const int i = bin_ev_index(st.pass, b, st.column, 0);
-                if (!h->bin_launched[i / 2]) continue;
-                HIP_TRY(h, hipEventElapsedTime(&st.ms, h->bin_ev[i], h->bin_ev[i + 1]));
-            }
-    }
-    if (flags[kFlagBadOffsets]) return fail(h, SW_EINVAL, "offsets decrease");
-    if (flags[kFlagBadScheme]) return fail(h, SW_EINVAL, "scheme id out of range");
-    if (flags[kFlagTooLong])
-        return fail(h, SW_ETOOLONG, "a query exceeds %d or a reference exceeds %d residues", SW_MAX_QUERY, SW_MAX_REF);
-    if (flags[kFlagBadResidue]) return fail(h, SW_EINVAL, "residue code outside its scheme's alphabet");
-    if (flags[kFlagReverseMismatch]) return fail(h, SW_EINTERNAL, "reverse sweep did not reproduce the forward score");
-    if (flags[kFlagInternal]) return fail(h, SW_EINTERNAL, "a planning invariant did not hold");
+    // end of the call: its flags and counters to the slot, then its event
+    HIP_TRY(h, hipMemcpyAsync(sl.h_small, h->d_small, kSmallInts * 4, hipMemcpyDeviceToHost, stream));
+    HIP_TRY(h, hipEventRecord(sl.done, stream));
+    sl.ticket = h->next_ticket++;
+    sl.timing = timing;
+    sl.t_entry = t_entry;
+    h->last_slot = k;
+    h->last_stream = stream;
+    h->next_slot = (k + 1) % sw_handle::kSlots;
+    *ticket = sl.ticket;
+    h->t_enqueue = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_entry).count();
     return SW_OK;
+}
+
+// Wait for (wait != 0) or test the call of `ticket`: SW_PENDING while it
+// runs, else its status (the ticket is then forgotten).
+static int poll_ticket(sw_handle* h, uint64_t ticket, int wait) {
+    auto it = h->finished.find(ticket);
+    if (it != h->finished.end()) {
+        const sw_handle::Finished f = it->second;
+        h->finished.erase(it);
+        h->err = f.err;
+        return f.status;
+    }
+    int k = -1;
+    for (int j = 0; j < sw_handle::kSlots; ++j)
+        if (ticket && h->slots[j].ticket == ticket) k = j;
+    if (k < 0) return fail(h, SW_EINVAL, "unknown ticket %llu (never issued, or already polled)",
+                           (unsigned long long)ticket);
+    HIP_TRY(h, hipSetDevice(h->device));
+    if (wait) {
+        HIP_TRY(h, hipEventSynchronize(h->slots[k].done));
+    } else {
+        const hipError_t q = hipEventQuery(h->slots[k].done);
+        if (q == hipErrorNotReady) {
+            (void)hipGetLastError();
+            return SW_PENDING;
+        }
+        if (q != hipSuccess) return fail(h, SW_EDEVICE, "hipEventQuery failed: %s", hipGetErrorString(q));
+    }
+    return complete_slot(h, k);
+}
+
+// The synchronous calls: a submit, then a wait for it.
+static int align_spans(sw_handle* h, const uint8_t* queries, const int64_t* q_beg, const int64_t* q_end,
+                       const uint8_t* refs, const int64_t* r_beg, const int64_t* r_end,
+                       const uint8_t* scheme_id, int64_t n_pairs, const sw_scheme* schemes,
+                       int n_schemes, sw_result* out, void* stream_ptr, bool no_alloc = false) {
+    if (!h) return SW_EINVAL;
+    uint64_t t = 0;
+    const int rc = submit_spans(h, queries, q_beg, q_end, refs, r_beg, r_end, scheme_id, n_pairs, schemes,
+                                n_schemes, out, stream_ptr, no_alloc, true, &t);
+    if (rc != SW_OK) return rc;
+    const double enq = h->t_enqueue;
+    const auto t0 = std::chrono::steady_clock::now();
+    const int st = poll_ticket(h, t, 1);
+    h->t_enqueue = enq;
+    h->t_wait = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return st;
 }
 
 extern "C" {
@@ -951,6 +1126,21 @@ int sw_align_batch(sw_handle* h, const sw_batch* batch, const sw_scheme* schemes
     const int64_t* ro = batch->r_off;
     return align_spans(h, batch->queries, qo, qo ? qo + 1 : nullptr, batch->refs, ro, ro ? ro + 1 : nullptr,
                        batch->scheme_id, batch->n_pairs, schemes, n_schemes, out, stream_ptr);
+}
+
+int sw_submit(sw_handle* h, const sw_batch* batch, const sw_scheme* schemes, int n_schemes, sw_result* out,
+              void* stream_ptr, uint64_t* ticket) {
+    if (!h) return SW_EINVAL;
+    if (!batch) return fail(h, SW_EINVAL, "null batch");
+    const int64_t* qo = batch->q_off;
+    const int64_t* ro = batch->r_off;
+    return submit_spans(h, batch->queries, qo, qo ? qo + 1 : nullptr, batch->refs, ro, ro ? ro + 1 : nullptr,
+                        batch->scheme_id, batch->n_pairs, schemes, n_schemes, out, stream_ptr, false, false, ticket);
+}
+
+int sw_poll(sw_handle* h, uint64_t ticket, int wait) {
+    if (!h) return SW_EINVAL;
+    return poll_ticket(h, ticket, wait);
 }
 
 int sw_align_batch_noalloc(sw_handle* h, const sw_batch* batch, const sw_scheme* schemes, int n_schemes,

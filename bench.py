@@ -160,6 +160,8 @@ def roofline_leg(args, db, out, tuning, mode, workload, steps):
     direction = "true" if dpass else "false"
     if dlanes > 64:
         kernel_name = "sw::sw_coop_kernel<%d, %s>" % (drows, direction)
+    elif dcol == 2:
+        kernel_name = "sw::sw_ptab_kernel<%d, %d, %s>" % (dlanes, drows, direction)
     else:
         kernel_name = "sw::sw_queue_kernel<%d, %d, %d, %s, %s>" % (dprec, dlanes, drows, direction,
                                                                   "true" if dcol else "false")
@@ -234,12 +236,14 @@ def roofline_only(args, batch, db, out, tuning, mode):
                       "roofline": roof}), flush=True)
 
 
-def serving_bench(args):
+def serving_points(args, loads, window_s, min_requests, max_requests):
     """Open-loop serving run: a Poisson stream of requests (each 1-5,000
-    pairs of the mixed draw) at each offered load, submitted to a
-    continuous-batching server with a 16 GiB device pool.  Latency of a
-    request runs from its scheduled arrival to its results being on the
-    host (so a submitter that falls behind is charged to the request)."""
+    pairs of the mixed draw) at each offered load (M cells/ms), submitted to
+    a continuous-batching server with a device pool of args.pool_gib GiB;
+    between min_requests and max_requests requests per load, about
+    window_s seconds of arrivals.  Latency of a request runs from its
+    scheduled arrival to its results being on the host (so a submitter that
+    falls behind is charged to the request).  Returns (points, config)."""
     import queue
     import threading
     import numpy as np
@@ -252,16 +256,18 @@ def serving_bench(args):
     cells = np.array([b.cells() for b in bodies], dtype=np.float64)
     mean_cells = float(cells.mean())
     log("  mean %.3g cells per request (%.1f s)" % (mean_cells, time.time() - t))
+    t = time.time()
     srv = Server(bodies[0].schemes, 0, pool_bytes=args.pool_gib << 30, slots=args.slots,
                  max_batch_pairs=args.max_batch_pairs)
+    log("  server created (%.1f s)" % (time.time() - t))
     # warm-up: every slot sees a few batches before anything is timed
     for b in bodies[:4 * args.slots]:
         srv.poll(srv.submit(b), wait=True)
 
     points = []
-    for li, load in enumerate(float(x) for x in args.loads.split(",")):
+    for li, load in enumerate(loads):
         lam = load * 1e6 * 1e3 / mean_cells            # requests per second
-        n = int(np.clip(lam * args.window_s, 40, 500))
+        n = int(np.clip(lam * window_s, min_requests, max_requests))
         arrivals = W.poisson_arrivals(n, lam, 2208 + li)
         which = [k % len(bodies) for k in range(n)]
         lags = [0.0] * n
@@ -314,15 +320,25 @@ def serving_bench(args):
         points.append(pt)
     st = srv.stats()
     srv.close()
+    config = {"workload": "serving", "distinct_requests": len(bodies), "mean_cells_per_request": int(mean_cells),
+              "slots": args.slots, "max_batch_pairs": args.max_batch_pairs,
+              "pool_bytes": args.pool_gib << 30, "pool_peak_bytes": st["pool_peak_bytes"],
+              "warmup_requests": 4 * args.slots}
+    return points, config
+
+
+def serving_bench(args):
+    """The serving leg alone, at every load of --loads."""
+    loads = [float(x) for x in args.loads.split(",")]
+    points, config = serving_points(args, loads, args.window_s, 40, 500)
     top = points[-1]
     res = {
         "metric": "GCUPS, batched affine SW (score+coords), batched vs plain; p50/p99 latency",
-        "value": top["sustained_gcups"], "unit": "GCUPS", "n_gpus": 1, "steps": len(points), "warmup": 4 * args.slots,
+        "value": top["sustained_gcups"], "unit": "GCUPS", "n_gpus": 1, "steps": len(points),
+        "warmup": config["warmup_requests"],
         "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "i16", "data": "synthetic",
-        "config": {"workload": "serving", "distinct_requests": len(bodies), "mean_cells_per_request": int(mean_cells),
-                   "slots": args.slots, "max_batch_pairs": args.max_batch_pairs,
-                   "pool_bytes": args.pool_gib << 30, "pool_peak_bytes": st["pool_peak_bytes"]},
+        "config": config,
         "latency_ms": {"p50": top["p50_ms"], "p99": top["p99_ms"]},
         "serving": points,
     }
@@ -520,6 +536,8 @@ def main():
     ap.add_argument("--slots", type=int, default=3, help="serving: slot workers")
     ap.add_argument("--max-batch-pairs", type=int, default=1 << 18, help="serving: pairs per merged batch")
     ap.add_argument("--pool-gib", type=int, default=16, help="serving: device pool size")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="skip the serving leg of the default run (loads 1, 10 and 50 M cells/ms)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -553,6 +571,11 @@ def main():
             res["secondary"][name]["config"] = {k: sec["config"][k] for k in ("pairs", "forward_cells",
                                                                                "reverse_cells", "routing")}
             res["secondary"][name]["roofline"] = sec["roofline"]
+    if not args.no_serving and args.n_pairs is None:
+        # the serving workload at its offered loads of 1, 10 and 50 M cells
+        # per ms: about 12 s of Poisson arrivals each, 30 to 500 requests
+        points, config = serving_points(args, [1.0, 10.0, 50.0], 12.0, 30, 500)
+        res["serving"] = {"config": config, "loads": points}
     print(json.dumps(res), flush=True)
 
 

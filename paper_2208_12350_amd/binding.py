@@ -70,6 +70,20 @@ class SwError(RuntimeError):
 _lib = None
 
 
+def _init_torch_runtime():
+    """PyTorch carries its own copy of the HIP runtime beside the system one
+    the library links.  Both work in one process when PyTorch's is
+    initialised first (the other order leaves PyTorch without devices), so
+    it is initialised before the library is loaded; without a GPU this is a
+    no-op."""
+    try:
+        import torch
+        if torch.cuda.is_available():
+            torch.cuda.init()
+    except Exception:   # noqa: BLE001 -- no GPU or no torch: nothing to order
+        pass
+
+
 def load_library(path: str = LIB_PATH):
     """Load libswalign.so; raises if it has not been built."""
     global _lib
@@ -78,6 +92,7 @@ def load_library(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise RuntimeError("libswalign.so is not built (run __graft_entry__.build() or "
                            "python paper_2208_12350_amd/build.py)")
+    _init_torch_runtime()
     lib = ctypes.CDLL(path)
     lib.sw_create.restype = ctypes.c_void_p
     lib.sw_create.argtypes = [ctypes.c_int, ctypes.c_char_p]

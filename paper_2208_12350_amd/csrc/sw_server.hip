@@ -301,10 +301,7 @@ sw_server* sw_server_create(int device, const sw_scheme* schemes, int n_schemes,
     for (int k = 0; ok && k < n_slots; ++k) {
         std::unique_ptr<Slot> sl(new Slot());
         sl->h = sw_create(device, tuning);
-        // slots run their calls without graph capture: captures on several
-        // threads at once have been invalidated by the runtime
-        ok = sl->h && sw_set_option(sl->h, "graph", 0) == SW_OK &&
-             sw_set_option(sl->h, "capacity", max_batch_pairs) == SW_OK &&
+        ok = sl->h && sw_set_option(sl->h, "capacity", max_batch_pairs) == SW_OK &&
              hipStreamCreateWithFlags(&sl->stream, hipStreamNonBlocking) == hipSuccess &&
              hipMalloc(&sl->d_spans, 32 * max_batch_pairs) == hipSuccess &&
              hipMalloc(&sl->d_sid, max_batch_pairs) == hipSuccess &&
@@ -313,6 +310,29 @@ sw_server* sw_server_create(int device, const sw_scheme* schemes, int n_schemes,
              hipHostMalloc(&sl->h_segs, max_batch_pairs * sizeof(Seg), hipHostMallocDefault) == hipSuccess &&
              hipHostMalloc(&sl->h_out, max_batch_pairs * sizeof(sw_result), hipHostMallocDefault) == hipSuccess;
         S->slots.push_back(std::move(sl));
+    }
+    // Each slot's calls always use the same buffers, schemes and capacity,
+    // so one captured graph serves all of them (the batch size is read on
+    // the device).  It is captured here, on this thread, one slot after the
+    // other, by aligning one pair of zero residues at the start of the
+    // pool: captures running on several threads at once have been
+    // invalidated by the runtime.  A slot whose capture is refused runs
+    // its calls eagerly and never captures.
+    if (ok) ok = hipMemset(S->pool, 0, 256) == hipSuccess;
+    for (size_t k = 0; ok && k < S->slots.size(); ++k) {
+        Slot* sl = S->slots[k].get();
+        const int64_t one[4] = {0, 1, 0, 1};
+        for (int f = 0; ok && f < 4; ++f)
+            ok = hipMemcpy(sl->d_spans + f * max_batch_pairs, &one[f], 8, hipMemcpyHostToDevice) == hipSuccess;
+        ok = ok && hipMemset(sl->d_sid, 0, 1) == hipSuccess;
+        if (!ok) break;
+        int64_t* qb = sl->d_spans;
+        ok = sw_align_spans(sl->h, S->pool, qb, qb + max_batch_pairs, S->pool, qb + 2 * max_batch_pairs,
+                            qb + 3 * max_batch_pairs, sl->d_sid, 1, S->schemes.data(), (int)S->schemes.size(),
+                            sl->d_out, sl->stream) == SW_OK;
+        int64_t captures = 0;
+        if (ok && (sw_get_option(sl->h, "captures", &captures) != SW_OK || captures != 1))
+            ok = sw_set_option(sl->h, "graph", 0) == SW_OK;
     }
     if (!ok) {
         sw_server_destroy(S);

@@ -17,6 +17,8 @@ PUBLISHED = 256 * 4 * 16 * 2.4e9
 
 
 def measure(device=0, iters=4096, blocks=256 * 16):
+    from paper_2208_12350_amd.binding import _init_torch_runtime
+    _init_torch_runtime()   # PyTorch's HIP runtime first, as for libswalign
     lib = ctypes.CDLL(os.path.join(HERE, "libswprobe.so"))
     lib.sw_probe_valu.restype = ctypes.c_int
     lib.sw_probe_valu.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,

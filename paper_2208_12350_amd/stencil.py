@@ -19,6 +19,8 @@ def load_library(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise RuntimeError("libswstencil.so is not built (run __graft_entry__.build())")
+    from paper_2208_12350_amd.binding import _init_torch_runtime
+    _init_torch_runtime()   # PyTorch's HIP runtime first, as for libswalign
     lib = ctypes.CDLL(path)
     lib.sw_diffuse_padded.restype = ctypes.c_int
     lib.sw_diffuse_padded.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,

@@ -128,6 +128,12 @@ const char* sw_last_error(sw_handle* h);
  *               scores plus gap_open fit a byte) read their substitution
  *               scores from per-column words instead of table lookups
  *               (default 1; 0 = always table lookups)
+ *   "pairtable" 1 = when exactly one scheme of a call takes table lookups
+ *               (alphabet of at most 24 residues, scores plus gap_open a
+ *               byte, gap_open <= 1024), its packed int16 pairs read two
+ *               rows' scores per load from a pair table (default 1);
+ *               0 = byte-table lookups.  Read-only "pairtable_used": whether
+ *               the last finished call used it
  *   "streams"   1..4: persistent mode spreads the bins' kernels over this
  *               many streams forked from (and joined back into) the
  *               caller's stream (default 4)
@@ -327,7 +333,8 @@ typedef struct sw_bin_stat {
     int64_t pairs;       /* pairs the bin held in this pass */
     int64_t cells;       /* DP cells of those pairs in this pass */
     float ms;            /* kernel time (HIP events) with "timing" = 2, else 0 */
-    int32_t column;      /* 1 = the column-word kernel, 0 = the table-lookup kernel */
+    int32_t column;      /* 1 = the column-word kernel, 0 = the table-lookup kernel,
+                            2 = the pair-table kernel */
 } sw_bin_stat;
 
 /* Per-launch statistics of the last call on this handle: writes up to

@@ -174,6 +174,20 @@ struct RefStager {
             buf[l + k * W] = (uint16_t)(sbase + b * kMatDim);
         }
     }
+    // Pair-table path: write the chunk as byte offsets 2 b of the reference
+    // residues into a pair-table row; out-of-range columns and invalid
+    // residues get the padding code D - 1 (whose entries are 0, a score of -o).
+    __device__ __forceinline__ void store_ptab(uint16_t* buf, const PairJob& J, int A, int D, int t0, int l,
+                                               bool& bad) const {
+#pragma unroll
+        for (int k = 0; k < kPerLane; ++k) {
+            const int j = t0 - W + l + k * W;
+            const int b = raw[k];
+            const bool inside = j >= 0 && j < J.m;
+            bad |= inside && b >= A;
+            buf[l + k * W] = (uint16_t)(2 * ((inside && b < A) ? b : D - 1));
+        }
+    }
     // Small-alphabet path: write the chunk as column words (bytes M[a][b] + o
     // for a = 0..3); out-of-range columns and invalid residues get word 0,
     // i.e. a score of -o for every row.
@@ -200,6 +214,27 @@ struct SchemeLds {
     int32_t gap_extend[SW_MAX_SCHEMES];
     int32_t col_ok[SW_MAX_SCHEMES];
 };
+
+// Per-block copy for the pair-table sweep: the pair table of scheme
+// P.ptab_sid (D^3 16-bit entries) and the gap costs of every scheme.
+struct PtabLds {
+    uint16_t tab[kPtabBytes / 2];
+    int32_t alphabet[SW_MAX_SCHEMES];
+    int32_t gap_open[SW_MAX_SCHEMES];
+    int32_t gap_extend[SW_MAX_SCHEMES];
+};
+
+__device__ __forceinline__ void load_ptab(PtabLds& S, const KParams& P, int tid) {
+    const int D = P.ptab_dim;
+    const int words = (D > 0 && D <= kPtabMaxDim) ? (D * D * D + 1) / 2 : 0;
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(P.mats + kPtabOffset);
+    for (int k = tid; k < words; k += kBlock) reinterpret_cast<uint32_t*>(S.tab)[k] = src[k];
+    if (tid < SW_MAX_SCHEMES) {
+        S.alphabet[tid] = P.alphabet[tid];
+        S.gap_open[tid] = P.gap_open[tid];
+        S.gap_extend[tid] = P.gap_extend[tid];
+    }
+}
 
 __device__ __forceinline__ void load_schemes(SchemeLds& S, const KParams& P, int tid) {
     for (int k = tid; k < SW_MAX_SCHEMES * kMatBytes / 4; k += kBlock)

@@ -17,7 +17,16 @@ constexpr int kMatBytes = kMatDim * kMatDim;   // per scheme
 // After the matrices, per scheme and reference residue b: the column word
 // of the small-alphabet path, bytes M[a][b] + o for a = 0..3 (see sw_sweep.h).
 constexpr int kColWordsBytes = SW_MAX_SCHEMES * kMatDim * 4;
-constexpr int kSchemeBytes = SW_MAX_SCHEMES * kMatBytes + kColWordsBytes;
+// Then the pair table of one scheme (the "pair-table" sweep, sw_sweep.h):
+// for residues x, y of two consecutive query rows and reference residue b,
+// the 16-bit entry [(x * D + y) * D + b] holds the bytes M[x][b] + o (low)
+// and M[y][b] + o (high), where D = alphabet + 1 and code D - 1 (= alphabet)
+// pads rows past the query end and columns outside the reference: its
+// bytes are 0, a score of -o.
+constexpr int kPtabMaxDim = 25;                          // alphabets of up to 24 residues
+constexpr int kPtabBytes = (kPtabMaxDim * kPtabMaxDim * kPtabMaxDim * 2 + 15) / 16 * 16;
+constexpr int kPtabOffset = SW_MAX_SCHEMES * kMatBytes + kColWordsBytes;
+constexpr int kSchemeBytes = kPtabOffset + kPtabBytes;
 constexpr int kBlock = 256;                    // 4 wavefronts per workgroup
 constexpr int kWavesPerBlock = kBlock / 64;
 
@@ -49,7 +58,7 @@ struct BinInfo {
     uint16_t W;       // lanes per group: 16, 32, 64, or 256 (a workgroup's four wavefronts)
     uint16_t ppw;     // pairs per work item
     uint8_t col;      // 1 = the shape has a column-word kernel (small alphabets)
-    uint8_t pad;
+    uint8_t ptab;     // 1 = the shape has a pair-table kernel
 };
 
 // Pairs per work item of a shape: a wavefront's groups (times two packed
@@ -70,16 +79,18 @@ struct WorkItem {
 
 // Layout of the per-pass planning metadata array (int32).
 // Within a bin, items [first, split) hold only pairs of column-path schemes
-// and go to the shape's column-word kernel; [split, next bin's first) go to
-// its table-lookup kernel (split == first for shapes without a column
-// kernel).  Each of the two has its own queue head.
+// and go to the shape's column-word kernel; [split, next bin's first) hold
+// only the other pairs and go to its table-lookup (or pair-table) kernel
+// (split == first for shapes without a column kernel).  Each of the two has
+// its own queue head.
 enum : int {
     kMetaBinFirst = 0,                                // [kMaxBins + 1] first sorted position of each bin
     kMetaItemFirst = kMetaBinFirst + kMaxBins + 1,    // [kMaxBins + 1] first item of each bin
     kMetaItemSplit = kMetaItemFirst + kMaxBins + 1,   // [kMaxBins] first table-lookup item of each bin
     kMetaHeads = kMetaItemSplit + kMaxBins,           // [kMaxBins] queue head of each bin's table-lookup items
     kMetaColHeads = kMetaHeads + kMaxBins,            // [kMaxBins] and of its column-word items
-    kMetaSize = kMetaColHeads + kMaxBins,
+    kMetaBinCol = kMetaColHeads + kMaxBins,           // [kMaxBins] column-path pairs of each bin
+    kMetaSize = kMetaBinCol + kMaxBins,
 };
 
 // Layout of the 64-bit statistics counters of a call (cleared at its start).
@@ -124,6 +135,8 @@ struct KParams {
     const int32_t* n_dev;        // device copy of the number of pairs in the batch
     int32_t n_pairs;             // pair capacity the grids are sized for (>= *n_dev)
     int32_t max_items;           // capacity of the items array (bound for every item index)
+    int32_t ptab_sid;            // scheme of the pair table (mats + kPtabOffset), or -1
+    int32_t ptab_dim;            // its D = alphabet + 1
 };
 
 enum : int32_t {
@@ -168,9 +181,13 @@ using QueueFn = void (*)(KParams);
 
 struct ShapeDesc { int prec, W, R; };
 
-// The kernel of a compiled shape; `col` selects its column-word variant
-// (nullptr when the shape has none).
-QueueFn shape_kernel(int prec, int W, int R, bool reverse, bool col = false);
+// Score sources of a shape's kernels: table lookups (any scheme), column
+// words (small alphabets) and the pair table (one scheme per call).
+enum : int { kVarTable = 0, kVarCol = 1, kVarPtab = 2, kNumVars = 3 };
+
+// The kernel of a compiled shape for one score source (nullptr when the
+// shape has no such variant).
+QueueFn shape_kernel(int prec, int W, int R, bool reverse, int var = kVarTable);
 const ShapeDesc* compiled_shapes(int* n);
 
 hipError_t launch_reset(int32_t* p, int n, hipStream_t s);

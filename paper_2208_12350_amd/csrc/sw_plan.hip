@@ -206,12 +206,14 @@ __global__ __launch_bounds__(kPlanThreads) void sw_plan_kernel(const BinInfo* bi
     if (t < n_bins && t < kMaxBins) {
         const int32_t cnt = bin_items[t + 1] - bin_items[t];
         const int ppw = bins[t].ppw;
-        my_items = (cnt + ppw - 1) / ppw;
-        // whole items of column-path pairs (all of the bin's items when it
-        // holds nothing else); the item straddling the boundary, if any,
-        // goes to the table-lookup kernel
-        if (bins[t].col) my_col_items = my_col == cnt ? my_items : my_col / ppw;
+        // the column-path pairs (first in the bin) and the others are cut
+        // into items separately, so no item mixes the two; a shape without
+        // a column kernel sorts none of its pairs as column-path pairs
+        if (!bins[t].col) my_col = 0;
+        my_col_items = (my_col + ppw - 1) / ppw;
+        my_items = my_col_items + (cnt - my_col + ppw - 1) / ppw;
     }
+    if (t < kMaxBins) meta[kMetaBinCol + t] = t < n_bins ? my_col : 0;
     __syncthreads();
     if (t < kMaxBins) bin_items[t] = my_items;
     __syncthreads();
@@ -238,19 +240,34 @@ __global__ void sw_items_kernel(const int32_t* meta, const BinInfo* bins, int n_
                                 WorkItem* items) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= *n_dev || i >= meta[kMetaBinFirst + n_bins]) return;
-    int b = 0;
-    while (b + 1 < n_bins && meta[kMetaBinFirst + b + 1] <= i) ++b;
+    // the bin holding sorted position i: the last bin whose first position
+    // is at most i (empty bins share their successor's first position)
+    int lo = 0, hi = n_bins - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (meta[kMetaBinFirst + mid] <= i) lo = mid;
+        else hi = mid - 1;
+    }
+    const int b = lo;
     const int32_t f = meta[kMetaBinFirst + b];
-    const int32_t k = (int32_t)i - f;
-    const BinInfo bi = bins[b];
-    if (k % bi.ppw != 0) return;
     const int32_t cnt = meta[kMetaBinFirst + b + 1] - f;
+    const int32_t ncol = meta[kMetaBinCol + b];
+    const BinInfo bi = bins[b];
+    // column-path pairs [0, ncol) of the bin, then the others, each cut
+    // into items of ppw pairs
+    int32_t k = (int32_t)i - f, end = ncol, item = meta[kMetaItemFirst + b];
+    if (k >= ncol) {
+        k -= ncol;
+        end = cnt - ncol;
+        item += (ncol + bi.ppw - 1) / bi.ppw;
+    }
+    if (k % bi.ppw != 0) return;
     WorkItem w;
     w.first = (int32_t)i;
-    w.count = (uint16_t)(cnt - k < bi.ppw ? cnt - k : bi.ppw);
+    w.count = (uint16_t)(end - k < bi.ppw ? end - k : bi.ppw);
     w.bin = (uint8_t)b;
     w.pad = 0;
-    items[meta[kMetaItemFirst + b] + k / bi.ppw] = w;
+    items[item + k / bi.ppw] = w;
 }
 
 __global__ void sw_fill_span_kernel(int64_t* beg, int64_t* end, int64_t n, int64_t len) {

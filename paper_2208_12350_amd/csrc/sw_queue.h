@@ -21,29 +21,10 @@
 
 namespace sw {
 
-template <int PREC, int W, int R, bool REV, bool COL>
-__global__ __launch_bounds__(kBlock) void sw_queue_kernel(KParams P) {
-    __shared__ __attribute__((aligned(16))) SchemeLds L;
-    __shared__ uint16_t wbufs[kWavesPerBlock * kWaveBuf];
-    constexpr int kPPW = (64 / W) * (PREC == 16 ? 2 : 1);
-    const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int wave = tid >> 6;
-    // the range is read first: a launch for an empty bin (the host does not
-    // know which bins are empty) costs its workgroups two loads and an exit
-    int lo = __atomic_load_n(&P.meta[P.lo_idx], __ATOMIC_RELAXED);
-    int hi = __atomic_load_n(&P.meta[P.hi_idx], __ATOMIC_RELAXED);
-    lo = __builtin_amdgcn_readfirstlane(lo);
-    hi = __builtin_amdgcn_readfirstlane(hi);
-    if (lo == hi) return;
-    if (lo < 0 || hi > P.max_items || lo > hi) {
-        if (tid == 0) atomicOr(&P.flags[kFlagInternal], 1);
-        return;
-    }
-    const int n_pairs = __builtin_amdgcn_readfirstlane(*P.n_dev);
-    load_schemes(L, P, tid);
-    __syncthreads();
-    uint16_t* wbuf = wbufs + wave * kWaveBuf;
+// The work-queue loop of one wavefront: claim items of the launch's range
+// and sweep each with `sweep(first, count)`.
+template <int kPPW, class Sweep>
+__device__ __forceinline__ void queue_loop(const KParams& P, int lane, int lo, int hi, int n_pairs, Sweep&& sweep) {
     // The loop has no lane-divergent branch: every lane takes part in the
     // fetch (only lane 0 adds 1, so each wavefront claims exactly one item
     // whether or not the lanes' atomics are merged), and the item index is
@@ -59,19 +40,79 @@ __global__ __launch_bounds__(kBlock) void sw_queue_kernel(KParams P) {
         const bool valid = first >= 0 && count >= 1 && count <= kPPW && first + count <= n_pairs;
         if (valid) {
             wave_lds_sync();
-            if constexpr (COL)
-                sweep_i16_col<W, R, REV>(P, L, wbuf, first, count, lane);
-            else if constexpr (PREC == 16)
-                sweep_i16<W, R, REV>(P, L, wbuf, first, count, lane);
-            else
-                sweep_i32<W, R, REV>(P, L, wbuf, first, count, lane);
+            sweep(first, count);
         } else {
             atomicOr(&P.flags[kFlagInternal], 1);
         }
     }
 }
 
-// fwd/rev: table-lookup kernels; cfwd/crev: column-word kernels (or null)
-struct KernelEntry { int prec, W, R; QueueFn fwd, rev, cfwd, crev; };
+// The item range of the launch, read first: a launch for an empty bin (the
+// host does not know which bins are empty) costs its workgroups two loads
+// and an exit.  Returns false when there is nothing to do.
+__device__ __forceinline__ bool launch_range(const KParams& P, int tid, int& lo, int& hi) {
+    lo = __atomic_load_n(&P.meta[P.lo_idx], __ATOMIC_RELAXED);
+    hi = __atomic_load_n(&P.meta[P.hi_idx], __ATOMIC_RELAXED);
+    lo = __builtin_amdgcn_readfirstlane(lo);
+    hi = __builtin_amdgcn_readfirstlane(hi);
+    if (lo == hi) return false;
+    if (lo < 0 || hi > P.max_items || lo > hi) {
+        if (tid == 0) atomicOr(&P.flags[kFlagInternal], 1);
+        return false;
+    }
+    return true;
+}
+
+template <int PREC, int W, int R, bool REV, bool COL>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void sw_queue_kernel(KParams P) {
+    __shared__ __attribute__((aligned(16))) SchemeLds L;
+    __shared__ uint16_t wbufs[kWavesPerBlock * kWaveBuf];
+    constexpr int kPPW = (64 / W) * (PREC == 16 ? 2 : 1);
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    int lo, hi;
+    if (!launch_range(P, tid, lo, hi)) return;
+    const int n_pairs = __builtin_amdgcn_readfirstlane(*P.n_dev);
+    load_schemes(L, P, tid);
+    __syncthreads();
+    uint16_t* wbuf = wbufs + wave * kWaveBuf;
+    queue_loop<kPPW>(P, lane, lo, hi, n_pairs, [&](int first, int count) {
+        if constexpr (COL)
+            sweep_i16_col<W, R, REV>(P, L, wbuf, first, count, lane);
+        else if constexpr (PREC == 16)
+            sweep_i16<W, R, REV>(P, L, wbuf, first, count, lane);
+        else
+            sweep_i32<W, R, REV>(P, L, wbuf, first, count, lane);
+    });
+}
+
+// Packed int16 shapes with the pair table of one scheme (sweep_i16_ptab).
+template <int W, int R, bool REV>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void sw_ptab_kernel(KParams P) {
+    __shared__ __attribute__((aligned(16))) PtabLds L;
+    __shared__ uint16_t wbufs[kWavesPerBlock * kWaveBuf];
+    constexpr int kPPW = (64 / W) * 2;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    int lo, hi;
+    if (!launch_range(P, tid, lo, hi)) return;
+    if (P.ptab_sid < 0 || P.ptab_sid >= SW_MAX_SCHEMES || P.ptab_dim < 2 || P.ptab_dim > kPtabMaxDim) {
+        if (tid == 0) atomicOr(&P.flags[kFlagInternal], 1);
+        return;
+    }
+    const int n_pairs = __builtin_amdgcn_readfirstlane(*P.n_dev);
+    load_ptab(L, P, tid);
+    __syncthreads();
+    uint16_t* wbuf = wbufs + wave * kWaveBuf;
+    queue_loop<kPPW>(P, lane, lo, hi, n_pairs, [&](int first, int count) {
+        sweep_i16_ptab<W, R, REV>(P, L, wbuf, first, count, lane);
+    });
+}
+
+// fwd/rev: table-lookup kernels; cfwd/crev: column-word kernels; pfwd/prev:
+// pair-table kernels (null where a shape has no such variant)
+struct KernelEntry { int prec, W, R; QueueFn fwd, rev, cfwd, crev, pfwd, prev; };
 
 }  // namespace sw

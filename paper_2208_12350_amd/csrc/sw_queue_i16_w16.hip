@@ -10,7 +10,8 @@ extern const int kNumI16W16Kernels;
 
 #define SW_ENTRY(W, R) \
     {16, W, R, &sw_queue_kernel<16, W, R, false, false>, &sw_queue_kernel<16, W, R, true, false>, \
-     &sw_queue_kernel<16, W, R, false, true>, &sw_queue_kernel<16, W, R, true, true>},
+     &sw_queue_kernel<16, W, R, false, true>, &sw_queue_kernel<16, W, R, true, true>, \
+     &sw_ptab_kernel<W, R, false>, &sw_ptab_kernel<W, R, true>},
 const KernelEntry kI16W16Kernels[] = {
     SW_ENTRY(16, 1) SW_ENTRY(16, 2) SW_ENTRY(16, 3) SW_ENTRY(16, 4) SW_ENTRY(16, 5) SW_ENTRY(16, 6)
     SW_ENTRY(16, 7) SW_ENTRY(16, 8) SW_ENTRY(16, 9) SW_ENTRY(16, 10) SW_ENTRY(16, 11) SW_ENTRY(16, 12)

@@ -6,7 +6,7 @@
 namespace sw {
 
 #define SW_ENTRY(W, R) \
-    {32, W, R, &sw_queue_kernel<32, W, R, false, false>, &sw_queue_kernel<32, W, R, true, false>, nullptr, nullptr},
+    {32, W, R, &sw_queue_kernel<32, W, R, false, false>, &sw_queue_kernel<32, W, R, true, false>, nullptr, nullptr, nullptr, nullptr},
 static const KernelEntry kI32Kernels[] = {
     SW_ENTRY(16, 2) SW_ENTRY(16, 4) SW_ENTRY(16, 6) SW_ENTRY(16, 8) SW_ENTRY(16, 10)
     SW_ENTRY(16, 12) SW_ENTRY(16, 14) SW_ENTRY(16, 16)
@@ -21,6 +21,8 @@ extern const KernelEntry kI16W32Kernels[];
 extern const int kNumI16W32Kernels;
 extern const KernelEntry kI16W64Kernels[];
 extern const int kNumI16W64Kernels;
+extern const KernelEntry kI16W64LongKernels[];
+extern const int kNumI16W64LongKernels;
 extern const KernelEntry kI16W256Kernels[];
 extern const int kNumI16W256Kernels;
 
@@ -33,12 +35,13 @@ Table table(int k) {
         case 0: return {kI16W16Kernels, kNumI16W16Kernels};
         case 1: return {kI16W32Kernels, kNumI16W32Kernels};
         case 2: return {kI16W64Kernels, kNumI16W64Kernels};
-        case 3: return {kI16W256Kernels, kNumI16W256Kernels};
+        case 3: return {kI16W64LongKernels, kNumI16W64LongKernels};
+        case 4: return {kI16W256Kernels, kNumI16W256Kernels};
         default: return {kI32Kernels, (int)(sizeof(kI32Kernels) / sizeof(kI32Kernels[0]))};
     }
 }
 
-constexpr int kTables = 5;
+constexpr int kTables = 6;
 ShapeDesc g_shapes[kMaxBins];
 int g_nshapes = 0;
 
@@ -56,12 +59,13 @@ const ShapeDesc* compiled_shapes(int* n) {
     return g_shapes;
 }
 
-QueueFn shape_kernel(int prec, int W, int R, bool reverse, bool col) {
+QueueFn shape_kernel(int prec, int W, int R, bool reverse, int var) {
     for (int t = 0; t < kTables; ++t) {
         const Table tb = table(t);
         for (int k = 0; k < tb.n; ++k)
             if (tb.e[k].prec == prec && tb.e[k].W == W && tb.e[k].R == R) {
-                if (col) return reverse ? tb.e[k].crev : tb.e[k].cfwd;
+                if (var == kVarCol) return reverse ? tb.e[k].crev : tb.e[k].cfwd;
+                if (var == kVarPtab) return reverse ? tb.e[k].prev : tb.e[k].pfwd;
                 return reverse ? tb.e[k].rev : tb.e[k].fwd;
             }
     }

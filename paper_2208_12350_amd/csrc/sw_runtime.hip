@@ -98,6 +98,7 @@ struct GraphKey {
     int32_t n_schemes;
     int32_t validate;
     int32_t precision;
+    int32_t ptab_sid;
 };
 
 }  // namespace
@@ -119,7 +120,9 @@ struct sw_handle {
     std::vector<int8_t> lut;            // device copy of route
     std::vector<char> bin_used;         // bins some route points at
     bool lut_dirty = true;
-    std::vector<int> resident_blocks[2][2];   // per pass, variant and bin: workgroups the device holds at once
+    std::vector<int> resident_blocks[2][kNumVars];   // per pass, score source and bin: workgroups the device holds at once
+    int64_t opt_ptab = 1;
+    int32_t last_ptab = 0;              // the last call's table-range kernels used the pair table
 
     int8_t* d_mats = nullptr;
     int8_t* d_lut = nullptr;
@@ -149,6 +152,7 @@ struct sw_handle {
         int32_t* h_small = nullptr;    // pinned: flags and counters of the call
         int8_t* h_mats = nullptr;      // pinned: staging of the scheme tables
         bool timing = false;
+        bool ptab = false;             // its table-range kernels used the pair table
         std::chrono::steady_clock::time_point t_entry;
     };
     static constexpr int kSlots = 8;
@@ -251,8 +255,8 @@ static void build_bins(sw_handle* h) {
         b.W = (uint16_t)s.W;
         b.R = (uint8_t)s.R;
         b.ppw = (uint16_t)pairs_per_item(s.prec, s.W);
-        b.col = shape_kernel(s.prec, s.W, s.R, false, true) != nullptr ? 1 : 0;
-        b.pad = 0;
+        b.col = shape_kernel(s.prec, s.W, s.R, false, kVarCol) != nullptr ? 1 : 0;
+        b.ptab = shape_kernel(s.prec, s.W, s.R, false, kVarPtab) != nullptr ? 1 : 0;
         h->bins.push_back(b);
     }
 }
@@ -443,12 +447,13 @@ static int enqueue_pass(sw_handle* h, KParams K, const ClassifyArgs& C, const Wo
             const int ipb = items_per_block(e.W);
             const int64_t need = (cap / e.ppw + 1 + ipb - 1) / ipb;
             for (int v = e.col ? 1 : 0; v >= 0; --v) {   // column-word kernel first
-                const int blocks = (int)std::min<int64_t>(need, h->resident_blocks[pass][v][b]);
+                const int var = v == 1 ? kVarCol : (e.ptab && K.ptab_sid >= 0 ? kVarPtab : kVarTable);
+                const int blocks = (int)std::min<int64_t>(need, h->resident_blocks[pass][var][b]);
                 set_range(K, b, v);
                 // a bin's kernels share a stream; bins go round-robin
                 hipStream_t ls = forks > 1 ? h->fork[launched % forks] : stream;
                 if (per_bin) HIP_TRY(h, hipEventRecord(h->bin_ev[bin_ev_index(pass, b, v, 0)], ls));
-                hipLaunchKernelGGL(shape_kernel(e.prec, e.W, e.R, pass != 0, v == 1), dim3(blocks), dim3(kBlock), 0,
+                hipLaunchKernelGGL(shape_kernel(e.prec, e.W, e.R, pass != 0, var), dim3(blocks), dim3(kBlock), 0,
                                    ls, K);
                 HIP_TRY(h, hipGetLastError());
                 if (per_bin) HIP_TRY(h, hipEventRecord(h->bin_ev[bin_ev_index(pass, b, v, 1)], ls));
@@ -471,8 +476,9 @@ static int enqueue_pass(sw_handle* h, KParams K, const ClassifyArgs& C, const Wo
                 const int items = h->h_meta[K.hi_idx] - h->h_meta[K.lo_idx];
                 if (items <= 0) continue;
                 const int blocks = (items + items_per_block(e.W) - 1) / items_per_block(e.W);
+                const int var = v == 1 ? kVarCol : (e.ptab && K.ptab_sid >= 0 ? kVarPtab : kVarTable);
                 if (per_bin) HIP_TRY(h, hipEventRecord(h->bin_ev[bin_ev_index(pass, b, v, 0)], stream));
-                hipLaunchKernelGGL(shape_kernel(e.prec, e.W, e.R, pass != 0, v == 1), dim3(blocks), dim3(kBlock), 0,
+                hipLaunchKernelGGL(shape_kernel(e.prec, e.W, e.R, pass != 0, var), dim3(blocks), dim3(kBlock), 0,
                                    stream, K);
                 HIP_TRY(h, hipGetLastError());
                 if (per_bin) HIP_TRY(h, hipEventRecord(h->bin_ev[bin_ev_index(pass, b, v, 1)], stream));
@@ -499,7 +505,7 @@ static bool init_paths(sw_handle* h) {
         b.R = (uint8_t)sh[k].R;
         b.ppw = (uint16_t)pairs_per_item(sh[k].prec, sh[k].W);
         b.col = trace_kernel(sh[k].prec, sh[k].W, sh[k].R, true) != nullptr ? 1 : 0;
-        b.pad = 0;
+        b.ptab = 0;
         h->tbins.push_back(b);
     }
     if (h->tbins.empty() || h->tbins.size() > (size_t)kMaxBins) return false;
@@ -584,12 +590,12 @@ sw_handle* sw_create(int device, const char* tuning) {
     if (ok) ok = hipMemcpy(h->d_bins, h->bins.data(), h->bins.size() * sizeof(BinInfo),
                            hipMemcpyHostToDevice) == hipSuccess;
     for (int pass = 0; pass < 2; ++pass)
-        for (int v = 0; v < 2; ++v) {
+        for (int v = 0; v < kNumVars; ++v) {
             h->resident_blocks[pass][v].assign(h->bins.size(), 1);
             for (size_t b = 0; ok && b < h->bins.size(); ++b) {
-                if (v == 1 && !h->bins[b].col) continue;
+                if ((v == kVarCol && !h->bins[b].col) || (v == kVarPtab && !h->bins[b].ptab)) continue;
                 int per_cu = 0;
-                const QueueFn fn = shape_kernel(h->bins[b].prec, h->bins[b].W, h->bins[b].R, pass != 0, v == 1);
+                const QueueFn fn = shape_kernel(h->bins[b].prec, h->bins[b].W, h->bins[b].R, pass != 0, v);
                 ok = fn && hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)fn, kBlock, 0) ==
                                hipSuccess;
                 h->resident_blocks[pass][v][b] = std::max(1, per_cu) * std::max(1, h->n_cu);
@@ -678,6 +684,8 @@ int sw_set_option(sw_handle* h, const char* key, int64_t value) {
         h->opt_timing = value;
     } else if (k == "colpath") {
         h->opt_colpath = value ? 1 : 0;
+    } else if (k == "pairtable") {
+        h->opt_ptab = value ? 1 : 0;
     } else if (k == "capacity") {
         // reserve workspace for this many pairs up front (grids and graphs are
         // sized for the capacity, so batches up to it reuse one graph)
@@ -717,6 +725,8 @@ int sw_get_option(sw_handle* h, const char* key, int64_t* value) {
     else if (k == "streams") *value = h->opt_streams;
     else if (k == "capacity") *value = h->cap_pairs;
     else if (k == "colpath") *value = h->opt_colpath;
+    else if (k == "pairtable") *value = h->opt_ptab;
+    else if (k == "pairtable_used") *value = h->last_ptab;
     else if (k == "cigar_workspace") *value = h->opt_path_ws;
     else if (k == "captures") *value = h->n_captures;
     else if (k == "capture_refusals") *value = h->n_capture_refusals;
@@ -740,6 +750,7 @@ static int complete_slot(sw_handle* h, int k) {
     h->last_rev = (int64_t)cnt[kCtrRevCells];
     h->last_i32 = (int64_t)cnt[kCtrI32Pairs];
     h->bin_stats.clear();
+    h->last_ptab = sl.ptab ? 1 : 0;
     for (int pass = 0; pass < 2; ++pass)
         for (int b = 0; b < (int)h->bins.size(); ++b)
             for (int v = h->bins[b].col ? 1 : 0; v >= 0; --v) {
@@ -749,7 +760,7 @@ static int complete_slot(sw_handle* h, int k) {
                 st.precision = h->bins[b].prec;
                 st.lanes = h->bins[b].W;
                 st.rows = h->bins[b].R;
-                st.column = v;
+                st.column = v == 1 ? 1 : (sl.ptab && h->bins[b].ptab ? 2 : 0);
                 const int i = pass * kMaxBins + b;
                 const int64_t col_cells = (int64_t)cnt[kCtrBinColCells + i];
                 const int64_t col_pairs = (int64_t)cnt[kCtrBinColPairs + i];
@@ -770,7 +781,7 @@ static int complete_slot(sw_handle* h, int k) {
                 // only launched kernels have events (plain mode skips empty
                 // item ranges; no mode launches a bin no route points at)
                 const int b = find_bin(h, st.precision, st.lanes, st.rows);
-                const int i = bin_ev_index(st.pass, b, st.column, 0);
+                const int i = bin_ev_index(st.pass, b, st.column == 1 ? 1 : 0, 0);
                 if (!h->bin_launched[i / 2]) continue;
                 HIP_TRY(h, hipEventElapsedTime(&st.ms, h->bin_ev[i], h->bin_ev[i + 1]));
             }
@@ -929,6 +940,41 @@ static int submit_spans(sw_handle* h, const uint8_t* queries, const int64_t* q_b
     C.n_schemes = n_schemes;
     C.n_bins = (int)h->bins.size();
 
+    // Pair table: when exactly one scheme of the call takes table lookups
+    // (every other one takes column words), the packed int16 table-range
+    // kernels read that scheme's scores from a pair table instead, provided
+    // its alphabet has at most kPtabMaxDim - 1 residues, 1 <= o <= K and
+    // every M[a][b] + o is a byte.
+    int ptab_sid = -1, D = 0;
+    if (h->opt_ptab) {
+        int n_table = 0, cand = -1;
+        for (int sidx = 0; sidx < n_schemes; ++sidx)
+            if (!(C.col_ok[sidx] && h->opt_colpath)) { ++n_table; cand = sidx; }
+        if (n_table == 1) {
+            const sw_scheme& sc = schemes[cand];
+            bool ok = sc.alphabet + 1 <= kPtabMaxDim && sc.gap_open >= 1 && sc.gap_open <= kI16Bias;
+            for (int k2 = 0; ok && k2 < sc.alphabet * sc.alphabet; ++k2) {
+                const int v = sc.matrix[k2] + sc.gap_open;
+                ok = v >= 0 && v <= 255;
+            }
+            if (ok) { ptab_sid = cand; D = sc.alphabet + 1; }
+        }
+    }
+    if (ptab_sid >= 0) {
+        // entry [(x D + y) D + b] = bytes M[x][b] + o (low), M[y][b] + o
+        // (high); code D - 1 pads rows and columns with 0
+        const sw_scheme& sc = schemes[ptab_sid];
+        const int A = sc.alphabet;
+        uint16_t* T = reinterpret_cast<uint16_t*>(h->tables.data() + kPtabOffset);
+        auto byte = [&](int a, int b) -> uint16_t {
+            return (a < A && b < A) ? (uint16_t)(sc.matrix[a * A + b] + sc.gap_open) : (uint16_t)0;
+        };
+        for (int x = 0; x < D; ++x)
+            for (int y = 0; y < D; ++y)
+                for (int b = 0; b < D; ++b)
+                    T[(x * D + y) * D + b] = (uint16_t)(byte(x, b) | (byte(y, b) << 8));
+    }
+
     KParams K;
     memset(&K, 0, sizeof(K));
     K.queries = queries; K.q_beg = q_beg; K.q_end = q_end; K.refs = refs; K.r_beg = r_beg; K.r_end = r_end;
@@ -937,6 +983,8 @@ static int submit_spans(sw_handle* h, const uint8_t* queries, const int64_t* q_b
     K.n_dev = h->d_n;
     K.n_pairs = (int32_t)ws.cap;
     K.max_items = (int32_t)(ws.cap + kMaxBins);
+    K.ptab_sid = ptab_sid;
+    K.ptab_dim = D;
     for (int s = 0; s < SW_MAX_SCHEMES; ++s) {
         const bool v = s < n_schemes;
         K.alphabet[s] = v ? schemes[s].alphabet : 1;
@@ -960,6 +1008,7 @@ static int submit_spans(sw_handle* h, const uint8_t* queries, const int64_t* q_b
     memcpy(key.max_score, C.max_score, sizeof(key.max_score));
     memcpy(key.col_ok, C.col_ok, sizeof(key.col_ok));
     key.n_schemes = n_schemes; key.validate = (int32_t)h->opt_validate; key.precision = (int32_t)h->opt_precision;
+    key.ptab_sid = ptab_sid;
 
     // Start of the call, in stream order and outside any graph: the scheme
     // tables when they differ from what the device holds (from this call's
@@ -1060,6 +1109,7 @@ static int submit_spans(sw_handle* h, const uint8_t* queries, const int64_t* q_b
     HIP_TRY(h, hipEventRecord(sl.done, stream));
     sl.ticket = h->next_ticket++;
     sl.timing = timing;
+    sl.ptab = ptab_sid >= 0;
     sl.t_entry = t_entry;
     h->last_slot = k;
     h->last_stream = stream;
@@ -1281,6 +1331,8 @@ static int trace_paths(sw_handle* h, const sw_batch* batch, const sw_scheme* sch
     K.n_dev = h->d_n;
     K.n_pairs = (int32_t)cap;
     K.max_items = (int32_t)(cap + kMaxBins);
+    K.ptab_sid = -1;
+    K.ptab_dim = 0;
     for (int s = 0; s < SW_MAX_SCHEMES; ++s) {
         const bool v = s < n_schemes;
         K.alphabet[s] = v ? schemes[s].alphabet : 1;

@@ -655,4 +655,253 @@ __device__ __forceinline__ void sweep_i16_col(const KParams& P, const SchemeLds&
     }
 }
 
+// Pair-table variant of sweep_i16, for wave items whose pairs all use the
+// one scheme of the call whose pair table sits in LDS (alphabets of up to 24
+// residues whose scores plus the gap open cost fit a byte, o <= K).  Entry
+// [(x D + y) D + b] of the table holds the bytes M[x][b] + o and M[y][b] + o
+// for two consecutive query rows with residues x, y (D = alphabet + 1; code
+// D - 1 pads rows past the query end and columns outside the reference with
+// 0, a score of -o <= -1, as the padding code does).  A lane's row pair p
+// therefore reads both of its scores for one column with a single 16-bit LDS
+// load at rc[p] + 2 b, where rc[p] is a per-row-pair constant: one address
+// add and one load per two rows and pair, against two adds and two loads per
+// row in the byte-table form; one v_perm_b32 per row then places pair A's
+// score in the low half and pair B's in the high half.
+//
+// Scores arrive biased by +o, so rows keep Hm = H - o as in sweep_i16_col.
+// A row pair's scores of the next step are loaded as soon as the pair has
+// used the current ones; the column offsets they need are read from the
+// staged reference two steps ahead.
+template <int W, int R, bool REV>
+__device__ __forceinline__ void sweep_i16_ptab(const KParams& P, const PtabLds& S, uint16_t* wbuf,
+                                               int first, int count, int lane) {
+    using Stager = RefStager<W>;
+    constexpr int reverse = REV ? 1 : 0;
+    constexpr int RP = (R + 1) / 2;
+    constexpr uint32_t K = kI16Bias;
+    constexpr uint32_t K2 = K | (K << 16);
+    const int g = lane / W;
+    const int l = lane % W;
+    const int D = P.ptab_dim;
+    const int tsid = P.ptab_sid >= 0 && P.ptab_sid < SW_MAX_SCHEMES ? P.ptab_sid : 0;
+    const uint8_t* tab = reinterpret_cast<const uint8_t*>(S.tab);
+
+    const int slot = g * 2;
+    const int pairA = slot < count ? P.order[first + slot] : -1;
+    const int pairB = slot + 1 < count ? P.order[first + slot + 1] : -1;
+    PairJob JA = load_job(P, pairA, reverse);
+    PairJob JB = load_job(P, pairB, reverse);
+    // every pair of a pair-table item uses the table's scheme; anything else
+    // is an internal error, swept as an empty pair
+    if (pairA >= 0 && JA.sid != P.ptab_sid) {
+        atomicOr(&P.flags[kFlagInternal], 1);
+        JA.n = JA.m = 0; JA.fwd_score = 0; JA.sid = tsid;
+    }
+    if (pairB >= 0 && JB.sid != P.ptab_sid) {
+        atomicOr(&P.flags[kFlagInternal], 1);
+        JB.n = JB.m = 0; JB.fwd_score = 0; JB.sid = tsid;
+    }
+
+    int mmax = imax(JA.m, JB.m);
+    for (int off = 32; off > 0; off >>= 1) mmax = imax(mmax, __shfl_xor(mmax, off));
+    const int steps = __builtin_amdgcn_readfirstlane(mmax > 0 ? mmax + W - 1 : 0);
+
+    uint16_t* bufA = wbuf + (g * 2) * Stager::kBuf;
+    uint16_t* bufB = bufA + Stager::kBuf;
+    Stager stA, stB;
+    stA.load(P.refs, JA, P.order, 0, l);
+    stB.load(P.refs, JB, P.order, 0, l);
+
+    // per row pair: byte offsets of its table rows, ((x D + y) D) * 2, for
+    // pair A (low half) and pair B (high half); both are below 2 D^3 <= 2^15
+    const int A = S.alphabet[tsid];
+    uint32_t rc[RP];
+    {
+        int rawA[R], rawB[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int i = l * R + r;
+            const int iA = i < JA.n ? i : (JA.n > 0 ? JA.n - 1 : 0);
+            const int iB = i < JB.n ? i : (JB.n > 0 ? JB.n - 1 : 0);
+            const uint8_t* pA = JA.n > 0 ? P.queries + JA.qbase + (int64_t)JA.dir * iA
+                                         : reinterpret_cast<const uint8_t*>(P.order);
+            const uint8_t* pB = JB.n > 0 ? P.queries + JB.qbase + (int64_t)JB.dir * iB
+                                         : reinterpret_cast<const uint8_t*>(P.order);
+            rawA[r] = *pA;
+            rawB[r] = *pB;
+        }
+        bool bad = false;
+        int xA[2 * RP], xB[2 * RP];
+#pragma unroll
+        for (int r = 0; r < 2 * RP; ++r) {
+            const int i = l * R + r;
+            const bool inA = r < R && i < JA.n, inB = r < R && i < JB.n;
+            const int ra = r < R ? rawA[r] : 0, rb = r < R ? rawB[r] : 0;
+            bad |= (inA && ra >= A) || (inB && rb >= A);
+            xA[r] = (inA && ra < A) ? ra : D - 1;
+            xB[r] = (inB && rb < A) ? rb : D - 1;
+        }
+#pragma unroll
+        for (int p = 0; p < RP; ++p)
+            rc[p] = (uint32_t)((xA[2 * p] * D + xA[2 * p + 1]) * D * 2) |
+                    ((uint32_t)((xB[2 * p] * D + xB[2 * p + 1]) * D * 2) << 16);
+        stA.store_ptab(bufA, JA, A, D, 0, l, bad);
+        stB.store_ptab(bufB, JB, A, D, 0, l, bad);
+        if (bad && P.validate) atomicOr(&P.flags[kFlagBadResidue], 1);
+    }
+    const uint32_t goA = (uint32_t)S.gap_open[JA.sid], goB = (uint32_t)S.gap_open[JB.sid];
+    const u16x2 go2 = pk(goA | (goB << 16));
+    const u16x2 ge2 = pk(cost16(S.gap_extend[JA.sid]) | (cost16(S.gap_extend[JB.sid]) << 16));
+    const u16x2 zero = pk(K2);
+    const uint32_t hm_top = (K - goA) | ((K - goB) << 16);   // Hm of the zero boundary
+    wave_lds_sync();
+
+    u16x2 Hm[R], E[R];
+    uint32_t kA[RP], kB[RP];
+#pragma unroll
+    for (int r = 0; r < R; ++r) { Hm[r] = pk(hm_top); E[r] = zero; }
+#pragma unroll
+    for (int p = 0; p < RP; ++p) { kA[p] = 0u; kB[p] = 0u; }
+    uint32_t Hlast = hm_top, Flast = K2, Hup_prev = hm_top;
+    const uint16_t* rblA = bufA + W - l;
+    const uint16_t* rblB = bufB + W - l;
+
+    // uA/uB[p]: row pair p's scores (bytes) of the current step, pair A's
+    // two rows and pair B's.  Column offsets of even steps live in (xa0, xb0), of odd
+    // steps in (xa1, xb1).  A step first reloads its own offsets with those
+    // two steps ahead (its scores are already loaded), then, row pair by row
+    // pair, uses the scores and loads the next step's with the other
+    // offsets.  Steps are unrolled by two, so no register rotates.
+    // Up to 14 rows per lane pairs A and B keep their scores in separate
+    // registers (one v_perm_b32 per row reads both); above that the two
+    // loads fill the halves of one register, which costs one more v_perm_b32
+    // per row pair but keeps the kernel within 256 registers, i.e. two
+    // wavefronts per SIMD instead of one.
+    constexpr bool kSplit = R <= 14;
+    uint32_t uA[RP], uB[kSplit ? RP : 1];
+    auto load_pair = [&](int p, uint32_t ca, uint32_t cb) {
+        const uint32_t a = *reinterpret_cast<const uint16_t*>(tab + (rc[p] & 0xFFFFu) + ca);
+        const uint32_t b = *reinterpret_cast<const uint16_t*>(tab + (rc[p] >> 16) + cb);
+        if constexpr (kSplit) {
+            uA[p] = a;
+            uB[p] = b;
+        } else {
+            uA[p] = __builtin_amdgcn_perm(b, a, 0x05040100u);
+        }
+    };
+    bool bad = false;
+    uint32_t jc = (uint32_t)(kColMax + l);
+    auto step = [&](uint32_t& xa, uint32_t& xb, uint32_t na, uint32_t nb, int ahead) {
+        xa = rblA[ahead];
+        xb = rblB[ahead];
+        const u16x2 Hmu0 = pk((uint32_t)shift_in_group<W>((int)Hlast, (int)hm_top));
+        // F above the group is 0 (K); a zero fill gives the same F below
+        // because of the max with K
+        const u16x2 Fup = pk((uint32_t)shift_in_group_zero<W>((int)Flast));
+        u16x2 diag = pk(Hup_prev);
+        Hup_prev = u32(Hmu0);
+        u16x2 Hmu = Hmu0;
+        u16x2 F = Fup;
+        const uint32_t jc1 = jc | 0x8000u;
+        uint32_t keyA0 = 0, keyB0 = 0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int p = r / 2;
+            F = pk_max3(pk_sat_sub(F, ge2), Hmu, zero);
+            u16x2 sc;
+            if constexpr (kSplit)
+                sc = pk(__builtin_amdgcn_perm(uB[p], uA[p], (r & 1) ? 0x0C050C01u : 0x0C040C00u));
+            else
+                sc = pk(__builtin_amdgcn_perm(uA[p], uA[p], (r & 1) ? 0x0C030C01u : 0x0C020C00u));
+            const u16x2 h = pk_max3(diag + sc, E[r], F);
+            diag = Hm[r];
+            Hmu = h - go2;
+            Hm[r] = Hmu;
+            E[r] = pk_max3(pk_sat_sub(E[r], ge2), Hmu, zero);
+            const uint32_t hv = u32(h);
+            if ((r & 1) == 0) {
+                keyA0 = (hv << 16) | jc1;
+                keyB0 = (hv & 0xFFFF0000u) | jc1;
+                if (r == R - 1) {
+                    kA[p] = kA[p] > keyA0 ? kA[p] : keyA0;
+                    kB[p] = kB[p] > keyB0 ? kB[p] : keyB0;
+                }
+            } else {
+                kA[p] = umax3(kA[p], keyA0, (hv << 16) | jc);
+                kB[p] = umax3(kB[p], keyB0, (hv & 0xFFFF0000u) | jc);
+            }
+            if ((r & 1) == 1 || r == R - 1) load_pair(p, na, nb);
+        }
+        Hlast = u32(Hm[R - 1]);
+        Flast = u32(F);
+        --jc;
+    };
+    for (int t0 = 0; t0 < steps; t0 += kChunk) {
+        const bool more = t0 + kChunk < steps;
+        if (more) {
+            stA.load(P.refs, JA, P.order, t0 + kChunk, l);
+            stB.load(P.refs, JB, P.order, t0 + kChunk, l);
+        }
+        const int tn = __builtin_amdgcn_readfirstlane(steps - t0 < kChunk ? steps - t0 : kChunk);
+        uint32_t xa0 = rblA[0], xb0 = rblB[0], xa1 = rblA[1], xb1 = rblB[1];
+#pragma unroll
+        for (int p = 0; p < RP; ++p) load_pair(p, xa0, xb0);
+        int tt = 0;
+        for (; tt + 1 < tn; tt += 2) {
+            step(xa0, xb0, xa1, xb1, tt + 2);
+            step(xa1, xb1, xa0, xb0, tt + 3);
+        }
+        if (tt < tn) step(xa0, xb0, xa1, xb1, tt + 2);
+        if (more) {
+            wave_lds_sync();
+            stA.store_ptab(bufA, JA, A, D, t0 + kChunk, l, bad);
+            stB.store_ptab(bufB, JB, A, D, t0 + kChunk, l, bad);
+            wave_lds_sync();
+        }
+    }
+    if (bad && P.validate) atomicOr(&P.flags[kFlagBadResidue], 1);
+
+    int lb[2] = {0, 0}, li[2] = {-1, -1}, lj[2] = {-1, -1};
+#pragma unroll
+    for (int p = 0; p < RP; ++p) {
+        const uint32_t ks[2] = {kA[p], kB[p]};
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int h = (int)(ks[q] >> 16) - (int)K;
+            const int row = l * R + 2 * p + ((ks[q] & 0x8000u) ? 0 : 1);
+            if (h > lb[q]) { lb[q] = h; li[q] = row; lj[q] = kColMax - (int)(ks[q] & 0x7FFFu); }
+        }
+    }
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+        for (int off = 1; off < W; off <<= 1) {
+            const int ob = __shfl_xor(lb[p], off);
+            const int oi = __shfl_xor(li[p], off);
+            const int oj = __shfl_xor(lj[p], off);
+            if (ob > lb[p] || (ob == lb[p] && oi < li[p])) { lb[p] = ob; li[p] = oi; lj[p] = oj; }
+        }
+    }
+    if (l == 0) {
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+            const int pair = p == 0 ? pairA : pairB;
+            const PairJob& J = p == 0 ? JA : JB;
+            if (pair < 0) continue;
+            if (!reverse) {
+                sw_result res;
+                if (lb[p] > 0) { res.score = lb[p]; res.q_start = -1; res.q_end = li[p]; res.r_start = -1; res.r_end = lj[p]; }
+                else { res.score = 0; res.q_start = res.q_end = res.r_start = res.r_end = -1; }
+                P.out[pair] = res;
+            } else if (J.fwd_score > 0) {
+                if (lb[p] != J.fwd_score) {
+                    atomicOr(&P.flags[kFlagReverseMismatch], 1);
+                } else {
+                    P.out[pair].q_start = J.fwd_qe - li[p];
+                    P.out[pair].r_start = J.fwd_re - lj[p];
+                }
+            }
+        }
+    }
+}
+
 }  // namespace sw

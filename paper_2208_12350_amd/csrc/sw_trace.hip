@@ -80,19 +80,25 @@ __device__ __forceinline__ PairJob box_job(const KParams& P, int pair, int max_r
 }
 
 // Record staging of one wavefront: the current block (kStage steps) of each
-// of its PPW pairs, in LDS in the record layout itself (pair p's block is
-// W lanes x 4R bytes, lane-major), so that a complete block is copied out
-// with 16-byte loads and stores.  A lane's step is R/2 bytes: R/8 dwords of
-// 8 rows, and for R % 8 == 4 a 16-bit tail of 4 rows.
+// of its PPW pairs, in LDS in the record layout (pair p's block is W lanes x
+// 4R bytes, lane-major), so that a complete block is copied out with
+// 16-byte loads and stores.  A lane's step is R/2 bytes: R/8 dwords of 8
+// rows, and for R % 8 == 4 a 16-bit tail of 4 rows.  In LDS a lane's 4R
+// bytes start every kStride dwords: R, plus 4 when R/4 is even.  All lanes
+// write the same step offset at once, so a stride of R dwords with R/4 even
+// would start every lane in one of R = 8: 4, 16: 2, 32: 1 bank group; an odd
+// number of 16-byte units spreads the lanes over 8 groups of 4 banks, and
+// keeps every lane's block 16-byte aligned for the copy out.
 template <int W, int R, int PPW>
 struct RecordStage {
     static_assert(R % 4 == 0 && R >= 4 && R <= 32, "a lane's step is whole 16-bit units of 4 rows");
     static constexpr int NW = R / 8;                    // whole dwords per lane and step
-    static constexpr int kDwords = PPW * W * R;         // per wavefront (4R bytes per lane and block)
+    static constexpr int kStride = R + ((R / 4) % 2 == 0 ? 4 : 0);   // dwords per lane and block in LDS
+    static constexpr int kDwords = PPW * W * kStride;   // per wavefront
     uint32_t* lds;
 
     __device__ __forceinline__ void put(int p, int l, int t, const uint32_t* v, uint32_t tail) const {
-        const int byte = ((p * W + l) * kStage + (t & (kStage - 1))) * (R / 2);
+        const int byte = (p * W + l) * kStride * 4 + (t & (kStage - 1)) * (R / 2);
         if constexpr (R % 8 == 0) {
             uint32_t* d = lds + byte / 4;
 #pragma unroll
@@ -109,15 +115,17 @@ struct RecordStage {
         }
     }
     // Copy block b of pair p (W * R dwords) to its record, 16 bytes per
-    // lane at a time.
+    // lane at a time: chunk c is 16-byte unit c % (R/4) of lane c / (R/4).
     __device__ __forceinline__ void flush(int p, uint32_t* rec, int b, int lane) const {
         uint32_t* dst = rec + (int64_t)b * W * R;
-        const uint32_t* src = lds + p * W * R;
+        const uint32_t* src = lds + p * W * kStride;
 #pragma unroll
         for (int c0 = 0; c0 < W * R / 4; c0 += 64) {
             const int c = c0 + lane;
+            const int q = c / (R / 4), k = c % (R / 4);
             if (W * R / 4 >= c0 + 64 || c < W * R / 4)
-                *reinterpret_cast<uint4*>(dst + 4 * c) = *reinterpret_cast<const uint4*>(src + 4 * c);
+                *reinterpret_cast<uint4*>(dst + 4 * c) =
+                    *reinterpret_cast<const uint4*>(src + q * kStride + 4 * k);
         }
     }
 };

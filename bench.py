@@ -143,11 +143,11 @@ def roofline_leg(args, db, out, tuning, mode, workload, steps):
         alr.align(db, out)
         if k:
             for e in alr.bin_stats():
-                key = (e["pass"], e["precision"], e["lanes"], e["rows"], e["column"])
+                key = (e["pass"], e["precision"], e["lanes"], e["rows"], e["column"], e["tile"])
                 acc = per_launch.setdefault(key, [0.0, 0, 0])
                 acc[0] += e["ms"]; acc[1] += e["cells"]; acc[2] += 1
     alr.close()
-    (dpass, dprec, dlanes, drows, dcol), (dms, dcells, dn) = max(per_launch.items(), key=lambda kv: kv[1][0])
+    (dpass, dprec, dlanes, drows, dcol, dtile), (dms, dcells, dn) = max(per_launch.items(), key=lambda kv: kv[1][0])
     launch_ms = dms / dn
     cells_per_launch = dcells / dn
     peak = VALU_INT16X2_TOPS if dprec == 16 else VALU_INT32_TOPS
@@ -161,10 +161,14 @@ def roofline_leg(args, db, out, tuning, mode, workload, steps):
     if dlanes > 64:
         kernel_name = "sw::sw_coop_kernel<%d, %s>" % (drows, direction)
     elif dcol == 2:
-        kernel_name = "sw::sw_ptab_kernel<%d, %d, %s>" % (dlanes, drows, direction)
-    else:
+        kernel_name = ("sw::sw_ptab_kernel<%d, %d, %s>" % (dlanes, drows, direction) if dtile == 128 else
+                       "sw::sw_ptab_chunk_kernel<%d, %d, %s, %d>" % (dlanes, drows, direction, dtile))
+    elif dtile == 128:
         kernel_name = "sw::sw_queue_kernel<%d, %d, %d, %s, %s>" % (dprec, dlanes, drows, direction,
                                                                   "true" if dcol else "false")
+    else:
+        kernel_name = "sw::sw_queue_chunk_kernel<%d, %d, %d, %s, %s, %d>" % (
+            dprec, dlanes, drows, direction, "true" if dcol else "false", dtile)
     return {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 2),
             "unit": "Tops/s", "frac": round(achieved / peak, 4),
             "traffic": stored_traffic(kernel_name, workload),
@@ -604,11 +608,10 @@ def align_leg(args, workload, steps, warmup, with_cigar, with_cpu, full):
         calibrate_copy(dev)
     if tuning is None and not args.no_tune:
         from paper_2208_12350_amd import autotune as T
-        from paper_2208_12350_amd.binding import routing_string
         log("autotuning the routing ...")
         t_tune = time.time()
-        name, table, _ = T.tune_batch(batch, db, 0, log=log)
-        tuning = routing_string(16, table)
+        name, table, _, tile = T.tune_batch(batch, db, 0, log=log)
+        tuning = T.tuning_string(table, tile)
         tune_s = time.time() - t_tune
         log("  picked %s: %s (%.1f s)" % (name, tuning, tune_s))
 

@@ -21,10 +21,15 @@ Two steps:
    the model's table and variants that put long queries on cooperative
    256-lane groups (``candidate_tables``) are each timed on the batch
    itself, and the fastest wins.
+4. The tile width: the winning table is timed again with the 16- and
+   32-lane shapes streaming the reference in tiles of 64 steps instead of
+   128 (fewer prefetch registers per lane, twice as many tile boundaries),
+   and the faster tile is kept.
 
 The result is a routing table [(rows_max, W, R), ...] for
-``Aligner.set_routing`` or, as a string, for the tuning argument of
-``sw_create``.  Results never depend on the routing; only speed does.
+``Aligner.set_routing`` and a tile width, or, as a string
+(``tuning_string``), for the tuning argument of ``sw_create``.  Results
+never depend on the routing or the tile; only speed does.
 """
 from __future__ import annotations
 
@@ -217,15 +222,28 @@ def candidate_tables(q_len, r_len, rates: Dict[Shape, float], shapes: Sequence[S
     return out
 
 
-def pick_by_timing(dbatch, tables: Dict[str, Table], device: int = 0, repeats: int = 2, log=None):
-    """Time one call per repeat of each routing on the batch itself (graph
-    replay, the headline configuration) and return (name, table, ms)."""
+DEFAULT_TILE = 128
+TILES = (128, 64)
+
+
+def tuning_string(table: Table, tile: int = DEFAULT_TILE) -> str:
+    """The sw_create tuning string of a routing table and tile width."""
+    from .binding import routing_string
+    s = routing_string(16, table)
+    return s if tile == DEFAULT_TILE else s + ";chunk=%d" % tile
+
+
+def pick_by_timing(dbatch, tables: Dict[str, Table], device: int = 0, repeats: int = 2, log=None,
+                   tile: int = DEFAULT_TILE):
+    """Time one call per repeat of each routing (with reference tiles of
+    `tile` steps) on the batch itself (graph replay, the headline
+    configuration) and return (name, table, ms)."""
     import torch
-    from .binding import Aligner, routing_string
+    from .binding import Aligner
     out = torch.empty((dbatch.n_pairs, 5), dtype=torch.int32, device="cuda:%d" % device)
     best = None
     for name, table in tables.items():
-        al = Aligner(device, routing_string(16, table))
+        al = Aligner(device, tuning_string(table, tile))
         try:
             al.align(dbatch, out)
             torch.cuda.synchronize()
@@ -238,7 +256,7 @@ def pick_by_timing(dbatch, tables: Dict[str, Table], device: int = 0, repeats: i
             al.close()
         ms = float(np.median(ts))
         if log:
-            log("  candidate %s: %.3f ms" % (name, ms))
+            log("  candidate %s%s: %.3f ms" % (name, "" if tile == DEFAULT_TILE else " tile %d" % tile, ms))
         if best is None or ms < best[2]:
             best = (name, table, ms)
     return best
@@ -247,9 +265,9 @@ def pick_by_timing(dbatch, tables: Dict[str, Table], device: int = 0, repeats: i
 def tune_batch(batch, dbatch, device: int = 0, sample: int = 50000, repeats: int = 7, seed: int = 5, log=None):
     """The routing a batch is timed with: shape rates measured on the batch's
     dominant scheme at its median reference length, the candidate tables of
-    a seeded sample of its pairs, and the fastest of them on the batch itself
-    (median of `repeats` graph-replayed calls each).  Returns (name, table,
-    candidates)."""
+    a seeded sample of its pairs, the fastest of them on the batch itself
+    (median of `repeats` graph-replayed calls each), then the faster tile
+    width for it.  Returns (name, table, candidates, tile)."""
     from .binding import Aligner
     rng = np.random.default_rng(seed)
     idx = rng.choice(batch.n_pairs, size=min(batch.n_pairs, sample), replace=False)
@@ -262,8 +280,15 @@ def tune_batch(batch, dbatch, device: int = 0, sample: int = 50000, repeats: int
     finally:
         probe.close()
     cands = candidate_tables(ql, rl, rates, list(rates), builtin=builtin)
-    name, table, _ = pick_by_timing(dbatch, cands, device, repeats=repeats, log=log)
-    return name, table, cands
+    name, table, ms = pick_by_timing(dbatch, cands, device, repeats=repeats, log=log)
+    tile = DEFAULT_TILE
+    for t in TILES:
+        if t == DEFAULT_TILE:
+            continue
+        _, _, ms_t = pick_by_timing(dbatch, {name: table}, device, repeats=repeats, log=log, tile=t)
+        if ms_t < ms:
+            tile, ms = t, ms_t
+    return name, table, cands, tile
 
 
 def tune(q_len, r_len, device: int = 0, precision: int = 16, log=None, **kw):

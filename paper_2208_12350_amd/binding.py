@@ -58,7 +58,7 @@ class sw_batch(ctypes.Structure):
 class sw_bin_stat(ctypes.Structure):
     _fields_ = [("pass_", ctypes.c_int32), ("precision", ctypes.c_int32), ("lanes", ctypes.c_int32),
                 ("rows", ctypes.c_int32), ("pairs", ctypes.c_int64), ("cells", ctypes.c_int64),
-                ("ms", ctypes.c_float), ("column", ctypes.c_int32)]
+                ("ms", ctypes.c_float), ("column", ctypes.c_int32), ("tile", ctypes.c_int32)]
 
 
 class SwError(RuntimeError):
@@ -266,7 +266,7 @@ def sw_last_bin_stats(h: int):
     arr = (sw_bin_stat * max(1, n.value))()
     _check(h, lib.sw_last_bin_stats(h, arr, n.value, ctypes.byref(n)))
     return [{"pass": e.pass_, "precision": e.precision, "lanes": e.lanes, "rows": e.rows, "column": e.column,
-             "pairs": int(e.pairs), "cells": int(e.cells), "ms": float(e.ms)} for e in arr[:n.value]]
+             "tile": e.tile, "pairs": int(e.pairs), "cells": int(e.cells), "ms": float(e.ms)} for e in arr[:n.value]]
 
 
 def _i32(n):

@@ -12,8 +12,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libswalign.so")
 PROBE_LIB = os.path.join(HERE, "libswprobe.so")
 STENCIL_LIB = os.path.join(HERE, "libswstencil.so")
-SOURCES = ["sw_plan.hip", "sw_queue_i16_w16.hip", "sw_queue_i16_w32.hip", "sw_queue_i16_w64.hip",
-           "sw_queue_i16_w64_long.hip", "sw_queue_i16_w256.hip",
+SOURCES = ["sw_plan.hip", "sw_queue_i16_w16.hip", "sw_queue_i16_w16b.hip", "sw_queue_i16_w32.hip",
+           "sw_queue_i16_w32b.hip", "sw_queue_i16_w64.hip", "sw_queue_i16_w64_long.hip", "sw_queue_i16_w256.hip",
            "sw_queue_i32.hip", "sw_trace.hip", "sw_runtime.hip", "sw_server.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -133,15 +133,17 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Reference columns are streamed through LDS in chunks of kChunk sweep
-// steps.  While a chunk is swept, lanes read columns t0-W+1 .. t0+kChunk+1
-// (the loop reads two steps ahead), so a group's buffer holds at least
-// kChunk+W+2 entries: entry x is column t0-W+x.
-constexpr int kChunk = 128;
+// Reference columns are streamed through LDS in chunks of C sweep steps
+// (the tile width; kChunk unless a kernel is compiled for another).  While
+// a chunk is swept, lanes read columns t0-W+1 .. t0+C+1 (the loop reads two
+// steps ahead), so a group's buffer holds at least C+W+2 entries: entry x is
+// column t0-W+x.  Each lane prefetches kPerLane entries of the next chunk
+// into registers, so a narrower tile costs fewer registers and more chunk
+// boundaries.  (kChunk and kChunkNarrow are in sw_internal.h.)
 
-template <int W>
+template <int W, int C = kChunk>
 struct RefStager {
-    static constexpr int kPerLane = (kChunk + W + 2 + W - 1) / W;
+    static constexpr int kPerLane = (C + W + 2 + W - 1) / W;
     static constexpr int kBuf = kPerLane * W;
     int raw[kPerLane];
 

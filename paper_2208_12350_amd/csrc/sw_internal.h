@@ -28,6 +28,11 @@ constexpr int kPtabBytes = (kPtabMaxDim * kPtabMaxDim * kPtabMaxDim * 2 + 15) / 
 constexpr int kPtabOffset = SW_MAX_SCHEMES * kMatBytes + kColWordsBytes;
 constexpr int kSchemeBytes = kPtabOffset + kPtabBytes;
 constexpr int kBlock = 256;                    // 4 wavefronts per workgroup
+// Reference tile of the sweeps, in steps: kChunk by default; the 16- and
+// 32-lane packed shapes are also compiled for kChunkNarrow (fewer prefetch
+// registers per lane, more tile boundaries).
+constexpr int kChunk = 128;
+constexpr int kChunkNarrow = 64;
 constexpr int kWavesPerBlock = kBlock / 64;
 
 // ---- planning: bins, length buckets, work items ----------------------------
@@ -185,9 +190,9 @@ struct ShapeDesc { int prec, W, R; };
 // words (small alphabets) and the pair table (one scheme per call).
 enum : int { kVarTable = 0, kVarCol = 1, kVarPtab = 2, kNumVars = 3 };
 
-// The kernel of a compiled shape for one score source (nullptr when the
-// shape has no such variant).
-QueueFn shape_kernel(int prec, int W, int R, bool reverse, int var = kVarTable);
+// The kernel of a compiled shape for one score source, with the default or
+// the narrow reference tile (nullptr when the shape has no such variant).
+QueueFn shape_kernel(int prec, int W, int R, bool reverse, int var = kVarTable, bool narrow = false);
 const ShapeDesc* compiled_shapes(int* n);
 
 hipError_t launch_reset(int32_t* p, int n, hipStream_t s);

@@ -63,10 +63,10 @@ __device__ __forceinline__ bool launch_range(const KParams& P, int tid, int& lo,
     return true;
 }
 
-template <int PREC, int W, int R, bool REV, bool COL>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void sw_queue_kernel(KParams P) {
-    __shared__ __attribute__((aligned(16))) SchemeLds L;
-    __shared__ uint16_t wbufs[kWavesPerBlock * kWaveBuf];
+// Body of a queue kernel whose sweeps stream the reference in tiles of C
+// steps.
+template <int PREC, int W, int R, bool REV, bool COL, int C>
+__device__ __forceinline__ void queue_body(const KParams& P, SchemeLds& L, uint16_t* wbufs) {
     constexpr int kPPW = (64 / W) * (PREC == 16 ? 2 : 1);
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -79,19 +79,16 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
     uint16_t* wbuf = wbufs + wave * kWaveBuf;
     queue_loop<kPPW>(P, lane, lo, hi, n_pairs, [&](int first, int count) {
         if constexpr (COL)
-            sweep_i16_col<W, R, REV>(P, L, wbuf, first, count, lane);
+            sweep_i16_col<W, R, REV, C>(P, L, wbuf, first, count, lane);
         else if constexpr (PREC == 16)
-            sweep_i16<W, R, REV>(P, L, wbuf, first, count, lane);
+            sweep_i16<W, R, REV, C>(P, L, wbuf, first, count, lane);
         else
-            sweep_i32<W, R, REV>(P, L, wbuf, first, count, lane);
+            sweep_i32<W, R, REV, C>(P, L, wbuf, first, count, lane);
     });
 }
 
-// Packed int16 shapes with the pair table of one scheme (sweep_i16_ptab).
-template <int W, int R, bool REV>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void sw_ptab_kernel(KParams P) {
-    __shared__ __attribute__((aligned(16))) PtabLds L;
-    __shared__ uint16_t wbufs[kWavesPerBlock * kWaveBuf];
+template <int W, int R, bool REV, int C>
+__device__ __forceinline__ void ptab_body(const KParams& P, PtabLds& L, uint16_t* wbufs) {
     constexpr int kPPW = (64 / W) * 2;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -107,12 +104,45 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
     __syncthreads();
     uint16_t* wbuf = wbufs + wave * kWaveBuf;
     queue_loop<kPPW>(P, lane, lo, hi, n_pairs, [&](int first, int count) {
-        sweep_i16_ptab<W, R, REV>(P, L, wbuf, first, count, lane);
+        sweep_i16_ptab<W, R, REV, C>(P, L, wbuf, first, count, lane);
     });
 }
 
-// fwd/rev: table-lookup kernels; cfwd/crev: column-word kernels; pfwd/prev:
-// pair-table kernels (null where a shape has no such variant)
-struct KernelEntry { int prec, W, R; QueueFn fwd, rev, cfwd, crev, pfwd, prev; };
+// Queue kernels with the default tile width (kChunk steps) ...
+template <int PREC, int W, int R, bool REV, bool COL>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void sw_queue_kernel(KParams P) {
+    __shared__ __attribute__((aligned(16))) SchemeLds L;
+    __shared__ uint16_t wbufs[kWavesPerBlock * kWaveBuf];
+    queue_body<PREC, W, R, REV, COL, kChunk>(P, L, wbufs);
+}
+
+// ... and with a tile of C steps (kept apart so that the default kernels keep
+// their names in profiles).
+template <int PREC, int W, int R, bool REV, bool COL, int C>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void sw_queue_chunk_kernel(KParams P) {
+    __shared__ __attribute__((aligned(16))) SchemeLds L;
+    __shared__ uint16_t wbufs[kWavesPerBlock * kWaveBuf];
+    queue_body<PREC, W, R, REV, COL, C>(P, L, wbufs);
+}
+
+// Packed int16 shapes with the pair table of one scheme (sweep_i16_ptab).
+template <int W, int R, bool REV>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void sw_ptab_kernel(KParams P) {
+    __shared__ __attribute__((aligned(16))) PtabLds L;
+    __shared__ uint16_t wbufs[kWavesPerBlock * kWaveBuf];
+    ptab_body<W, R, REV, kChunk>(P, L, wbufs);
+}
+
+template <int W, int R, bool REV, int C>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void sw_ptab_chunk_kernel(KParams P) {
+    __shared__ __attribute__((aligned(16))) PtabLds L;
+    __shared__ uint16_t wbufs[kWavesPerBlock * kWaveBuf];
+    ptab_body<W, R, REV, C>(P, L, wbufs);
+}
+
+// Per tile width (index 0: kChunk, 1: kChunkNarrow) and score source
+// (kVarTable, kVarCol, kVarPtab): the forward and reverse kernels, null
+// where a shape has no such variant.
+struct KernelEntry { int prec, W, R; QueueFn k[2][kNumVars][2]; };
 
 }  // namespace sw

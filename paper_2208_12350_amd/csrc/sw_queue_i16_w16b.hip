@@ -1,0 +1,28 @@
+// sw_queue_i16_w16b.hip -- queue kernels of the packed int16 sweep shapes with
+// 16-lane groups, 9..16 rows per lane (queries of 129..256 residues): table-lookup, column-word and pair-table
+// kernels, forward and reverse, each with the default tile of kChunk
+// reference steps and the narrow tile of kChunkNarrow.
+#include "sw_queue.h"
+
+namespace sw {
+
+extern const KernelEntry kI16W16bKernels[];
+extern const int kNumI16W16bKernels;
+
+#define SW_ENTRY(W, R) \
+    {16, W, R, {{{&sw_queue_kernel<16, W, R, false, false>, &sw_queue_kernel<16, W, R, true, false>}, \
+                 {&sw_queue_kernel<16, W, R, false, true>, &sw_queue_kernel<16, W, R, true, true>}, \
+                 {&sw_ptab_kernel<W, R, false>, &sw_ptab_kernel<W, R, true>}}, \
+                {{&sw_queue_chunk_kernel<16, W, R, false, false, kChunkNarrow>, \
+                  &sw_queue_chunk_kernel<16, W, R, true, false, kChunkNarrow>}, \
+                 {&sw_queue_chunk_kernel<16, W, R, false, true, kChunkNarrow>, \
+                  &sw_queue_chunk_kernel<16, W, R, true, true, kChunkNarrow>}, \
+                 {&sw_ptab_chunk_kernel<W, R, false, kChunkNarrow>, &sw_ptab_chunk_kernel<W, R, true, kChunkNarrow>}}}},
+const KernelEntry kI16W16bKernels[] = {
+    SW_ENTRY(16, 9) SW_ENTRY(16, 10) SW_ENTRY(16, 11) SW_ENTRY(16, 12) SW_ENTRY(16, 13) SW_ENTRY(16, 14)
+    SW_ENTRY(16, 15) SW_ENTRY(16, 16)
+};
+#undef SW_ENTRY
+const int kNumI16W16bKernels = sizeof(kI16W16bKernels) / sizeof(kI16W16bKernels[0]);
+
+}  // namespace sw

@@ -6,7 +6,9 @@
 namespace sw {
 
 #define SW_ENTRY(W, R) \
-    {32, W, R, &sw_queue_kernel<32, W, R, false, false>, &sw_queue_kernel<32, W, R, true, false>, nullptr, nullptr, nullptr, nullptr},
+    {32, W, R, {{{&sw_queue_kernel<32, W, R, false, false>, &sw_queue_kernel<32, W, R, true, false>}, \
+                 {nullptr, nullptr}, {nullptr, nullptr}}, \
+                {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}}}},
 static const KernelEntry kI32Kernels[] = {
     SW_ENTRY(16, 2) SW_ENTRY(16, 4) SW_ENTRY(16, 6) SW_ENTRY(16, 8) SW_ENTRY(16, 10)
     SW_ENTRY(16, 12) SW_ENTRY(16, 14) SW_ENTRY(16, 16)
@@ -17,8 +19,12 @@ static const KernelEntry kI32Kernels[] = {
 
 extern const KernelEntry kI16W16Kernels[];
 extern const int kNumI16W16Kernels;
+extern const KernelEntry kI16W16bKernels[];
+extern const int kNumI16W16bKernels;
 extern const KernelEntry kI16W32Kernels[];
 extern const int kNumI16W32Kernels;
+extern const KernelEntry kI16W32bKernels[];
+extern const int kNumI16W32bKernels;
 extern const KernelEntry kI16W64Kernels[];
 extern const int kNumI16W64Kernels;
 extern const KernelEntry kI16W64LongKernels[];
@@ -33,15 +39,17 @@ struct Table { const KernelEntry* e; int n; };
 Table table(int k) {
     switch (k) {
         case 0: return {kI16W16Kernels, kNumI16W16Kernels};
-        case 1: return {kI16W32Kernels, kNumI16W32Kernels};
-        case 2: return {kI16W64Kernels, kNumI16W64Kernels};
-        case 3: return {kI16W64LongKernels, kNumI16W64LongKernels};
-        case 4: return {kI16W256Kernels, kNumI16W256Kernels};
+        case 1: return {kI16W16bKernels, kNumI16W16bKernels};
+        case 2: return {kI16W32Kernels, kNumI16W32Kernels};
+        case 3: return {kI16W32bKernels, kNumI16W32bKernels};
+        case 4: return {kI16W64Kernels, kNumI16W64Kernels};
+        case 5: return {kI16W64LongKernels, kNumI16W64LongKernels};
+        case 6: return {kI16W256Kernels, kNumI16W256Kernels};
         default: return {kI32Kernels, (int)(sizeof(kI32Kernels) / sizeof(kI32Kernels[0]))};
     }
 }
 
-constexpr int kTables = 6;
+constexpr int kTables = 8;
 ShapeDesc g_shapes[kMaxBins];
 int g_nshapes = 0;
 
@@ -59,15 +67,13 @@ const ShapeDesc* compiled_shapes(int* n) {
     return g_shapes;
 }
 
-QueueFn shape_kernel(int prec, int W, int R, bool reverse, int var) {
+QueueFn shape_kernel(int prec, int W, int R, bool reverse, int var, bool narrow) {
+    if (var < 0 || var >= kNumVars) return nullptr;
     for (int t = 0; t < kTables; ++t) {
         const Table tb = table(t);
         for (int k = 0; k < tb.n; ++k)
-            if (tb.e[k].prec == prec && tb.e[k].W == W && tb.e[k].R == R) {
-                if (var == kVarCol) return reverse ? tb.e[k].crev : tb.e[k].cfwd;
-                if (var == kVarPtab) return reverse ? tb.e[k].prev : tb.e[k].pfwd;
-                return reverse ? tb.e[k].rev : tb.e[k].fwd;
-            }
+            if (tb.e[k].prec == prec && tb.e[k].W == W && tb.e[k].R == R)
+                return tb.e[k].k[narrow ? 1 : 0][var][reverse ? 1 : 0];
     }
     return nullptr;
 }

@@ -120,7 +120,8 @@ struct sw_handle {
     std::vector<int8_t> lut;            // device copy of route
     std::vector<char> bin_used;         // bins some route points at
     bool lut_dirty = true;
-    std::vector<int> resident_blocks[2][kNumVars];   // per pass, score source and bin: workgroups the device holds at once
+    std::vector<int> resident_blocks[2][2][kNumVars];   // per tile, pass, score source and bin: workgroups the device holds at once
+    int64_t opt_chunk = kChunk;         // reference tile of 16- and 32-lane packed shapes: kChunk or kChunkNarrow
     int64_t opt_ptab = 1;
     int32_t last_ptab = 0;              // the last call's table-range kernels used the pair table
 
@@ -153,6 +154,7 @@ struct sw_handle {
         int8_t* h_mats = nullptr;      // pinned: staging of the scheme tables
         bool timing = false;
         bool ptab = false;             // its table-range kernels used the pair table
+        int chunk = kChunk;            // its "chunk" option
         std::chrono::steady_clock::time_point t_entry;
     };
     static constexpr int kSlots = 8;
@@ -414,6 +416,13 @@ static void set_range(KParams& K, int b, int v) {
 
 static int bin_ev_index(int pass, int b, int v, int end) { return ((pass * kMaxBins + b) * 2 + v) * 2 + end; }
 
+// 1 when bin e's kernel of score source `var` runs with the narrow
+// reference tile (the "chunk" option; only 16- and 32-lane packed shapes
+// have it).
+static int narrow_tile(const sw_handle* h, const BinInfo& e, int var) {
+    return h->opt_chunk == kChunkNarrow && shape_kernel(e.prec, e.W, e.R, false, var, true) != nullptr ? 1 : 0;
+}
+
 // Enqueue one pass (planning + sweeps).  Plain mode synchronises `stream`
 // once to read the per-bin item counts.
 static int enqueue_pass(sw_handle* h, KParams K, const ClassifyArgs& C, const Workspace& ws, int pass,
@@ -448,13 +457,14 @@ static int enqueue_pass(sw_handle* h, KParams K, const ClassifyArgs& C, const Wo
             const int64_t need = (cap / e.ppw + 1 + ipb - 1) / ipb;
             for (int v = e.col ? 1 : 0; v >= 0; --v) {   // column-word kernel first
                 const int var = v == 1 ? kVarCol : (e.ptab && K.ptab_sid >= 0 ? kVarPtab : kVarTable);
-                const int blocks = (int)std::min<int64_t>(need, h->resident_blocks[pass][var][b]);
+                const int nw = narrow_tile(h, e, var);
+                const int blocks = (int)std::min<int64_t>(need, h->resident_blocks[nw][pass][var][b]);
                 set_range(K, b, v);
                 // a bin's kernels share a stream; bins go round-robin
                 hipStream_t ls = forks > 1 ? h->fork[launched % forks] : stream;
                 if (per_bin) HIP_TRY(h, hipEventRecord(h->bin_ev[bin_ev_index(pass, b, v, 0)], ls));
-                hipLaunchKernelGGL(shape_kernel(e.prec, e.W, e.R, pass != 0, var), dim3(blocks), dim3(kBlock), 0,
-                                   ls, K);
+                hipLaunchKernelGGL(shape_kernel(e.prec, e.W, e.R, pass != 0, var, nw == 1), dim3(blocks), dim3(kBlock),
+                                   0, ls, K);
                 HIP_TRY(h, hipGetLastError());
                 if (per_bin) HIP_TRY(h, hipEventRecord(h->bin_ev[bin_ev_index(pass, b, v, 1)], ls));
                 if (per_bin) h->bin_launched[bin_ev_index(pass, b, v, 0) / 2] = 1;
@@ -477,9 +487,10 @@ static int enqueue_pass(sw_handle* h, KParams K, const ClassifyArgs& C, const Wo
                 if (items <= 0) continue;
                 const int blocks = (items + items_per_block(e.W) - 1) / items_per_block(e.W);
                 const int var = v == 1 ? kVarCol : (e.ptab && K.ptab_sid >= 0 ? kVarPtab : kVarTable);
+                const int nw = narrow_tile(h, e, var);
                 if (per_bin) HIP_TRY(h, hipEventRecord(h->bin_ev[bin_ev_index(pass, b, v, 0)], stream));
-                hipLaunchKernelGGL(shape_kernel(e.prec, e.W, e.R, pass != 0, var), dim3(blocks), dim3(kBlock), 0,
-                                   stream, K);
+                hipLaunchKernelGGL(shape_kernel(e.prec, e.W, e.R, pass != 0, var, nw == 1), dim3(blocks), dim3(kBlock),
+                                   0, stream, K);
                 HIP_TRY(h, hipGetLastError());
                 if (per_bin) HIP_TRY(h, hipEventRecord(h->bin_ev[bin_ev_index(pass, b, v, 1)], stream));
                 if (per_bin) h->bin_launched[bin_ev_index(pass, b, v, 0) / 2] = 1;
@@ -589,18 +600,22 @@ sw_handle* sw_create(int device, const char* tuning) {
         ok = hipEventCreateWithFlags(&h->fork_ev[f], hipEventDisableTiming) == hipSuccess;
     if (ok) ok = hipMemcpy(h->d_bins, h->bins.data(), h->bins.size() * sizeof(BinInfo),
                            hipMemcpyHostToDevice) == hipSuccess;
-    for (int pass = 0; pass < 2; ++pass)
-        for (int v = 0; v < kNumVars; ++v) {
-            h->resident_blocks[pass][v].assign(h->bins.size(), 1);
-            for (size_t b = 0; ok && b < h->bins.size(); ++b) {
-                if ((v == kVarCol && !h->bins[b].col) || (v == kVarPtab && !h->bins[b].ptab)) continue;
-                int per_cu = 0;
-                const QueueFn fn = shape_kernel(h->bins[b].prec, h->bins[b].W, h->bins[b].R, pass != 0, v);
-                ok = fn && hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)fn, kBlock, 0) ==
-                               hipSuccess;
-                h->resident_blocks[pass][v][b] = std::max(1, per_cu) * std::max(1, h->n_cu);
+    for (int nw = 0; nw < 2; ++nw)
+        for (int pass = 0; pass < 2; ++pass)
+            for (int v = 0; v < kNumVars; ++v) {
+                h->resident_blocks[nw][pass][v].assign(h->bins.size(), 1);
+                for (size_t b = 0; ok && b < h->bins.size(); ++b) {
+                    if ((v == kVarCol && !h->bins[b].col) || (v == kVarPtab && !h->bins[b].ptab)) continue;
+                    const QueueFn fn = shape_kernel(h->bins[b].prec, h->bins[b].W, h->bins[b].R, pass != 0, v, nw == 1);
+                    if (!fn) {
+                        ok = nw == 1;   // only the narrow tile may be missing
+                        continue;
+                    }
+                    int per_cu = 0;
+                    ok = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)fn, kBlock, 0) == hipSuccess;
+                    h->resident_blocks[nw][pass][v][b] = std::max(1, per_cu) * std::max(1, h->n_cu);
+                }
             }
-        }
     if (ok) ok = init_paths(h);
     if (!ok) { sw_destroy(h); return nullptr; }
     if (tuning) {
@@ -684,6 +699,10 @@ int sw_set_option(sw_handle* h, const char* key, int64_t value) {
         h->opt_timing = value;
     } else if (k == "colpath") {
         h->opt_colpath = value ? 1 : 0;
+    } else if (k == "chunk") {
+        if (value != kChunk && value != kChunkNarrow)
+            return fail(h, SW_EINVAL, "chunk (reference tile steps) must be %d or %d", kChunk, kChunkNarrow);
+        h->opt_chunk = value;
     } else if (k == "pairtable") {
         h->opt_ptab = value ? 1 : 0;
     } else if (k == "capacity") {
@@ -725,6 +744,7 @@ int sw_get_option(sw_handle* h, const char* key, int64_t* value) {
     else if (k == "streams") *value = h->opt_streams;
     else if (k == "capacity") *value = h->cap_pairs;
     else if (k == "colpath") *value = h->opt_colpath;
+    else if (k == "chunk") *value = h->opt_chunk;
     else if (k == "pairtable") *value = h->opt_ptab;
     else if (k == "pairtable_used") *value = h->last_ptab;
     else if (k == "cigar_workspace") *value = h->opt_path_ws;
@@ -761,6 +781,10 @@ static int complete_slot(sw_handle* h, int k) {
                 st.lanes = h->bins[b].W;
                 st.rows = h->bins[b].R;
                 st.column = v == 1 ? 1 : (sl.ptab && h->bins[b].ptab ? 2 : 0);
+                st.tile = sl.chunk == kChunkNarrow &&
+                                  shape_kernel(st.precision, st.lanes, st.rows, false, v == 1 ? kVarCol : kVarTable, true)
+                              ? kChunkNarrow
+                              : kChunk;
                 const int i = pass * kMaxBins + b;
                 const int64_t col_cells = (int64_t)cnt[kCtrBinColCells + i];
                 const int64_t col_pairs = (int64_t)cnt[kCtrBinColPairs + i];
@@ -1110,6 +1134,7 @@ static int submit_spans(sw_handle* h, const uint8_t* queries, const int64_t* q_b
     sl.ticket = h->next_ticket++;
     sl.timing = timing;
     sl.ptab = ptab_sid >= 0;
+    sl.chunk = (int)h->opt_chunk;
     sl.t_entry = t_entry;
     h->last_slot = k;
     h->last_stream = stream;
@@ -1468,6 +1493,7 @@ static int trace_paths(sw_handle* h, const sw_batch* batch, const sw_scheme* sch
         st.lanes = h->tbins[b].W;
         st.rows = h->tbins[b].R;
         st.column = h->tbins[b].col && all_col ? 1 : 0;
+        st.tile = kChunk;
         st.pairs = (int64_t)cnt[kCtrTraceBinPairs + b];
         st.cells = (int64_t)cnt[kCtrTraceBinCells + b];
         st.ms = bin_ms[b];

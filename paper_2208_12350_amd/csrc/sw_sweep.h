@@ -74,11 +74,11 @@ namespace sw {
 constexpr int kWaveBuf = 2 * 4 * 2 * RefStager<16>::kBuf;
 // One sweep (forward, or reverse when REV) of the wave item
 // order[first .. first+count), one pair per W-lane group, int32 arithmetic.
-template <int W, int R, bool REV>
+template <int W, int R, bool REV, int C = kChunk>
 __device__ __forceinline__ void sweep_i32(const KParams& P, const SchemeLds& S, uint16_t* wbuf,
                                           int first, int count, int lane) {
     constexpr int G = 64 / W;
-    using Stager = RefStager<W>;
+    using Stager = RefStager<W, C>;
     constexpr int reverse = REV ? 1 : 0;
     const int g = lane / W;
     const int l = lane % W;
@@ -143,10 +143,10 @@ __device__ __forceinline__ void sweep_i32(const KParams& P, const SchemeLds& S, 
     }
     bool bad = false;
     int j = -l;
-    for (int t0 = 0; t0 < steps; t0 += kChunk) {
-        const bool more = t0 + kChunk < steps;
-        if (more) stage.load(P.refs, J, P.order, t0 + kChunk, l);
-        const int tn = __builtin_amdgcn_readfirstlane(steps - t0 < kChunk ? steps - t0 : kChunk);
+    for (int t0 = 0; t0 < steps; t0 += C) {
+        const bool more = t0 + C < steps;
+        if (more) stage.load(P.refs, J, P.order, t0 + C, l);
+        const int tn = __builtin_amdgcn_readfirstlane(steps - t0 < C ? steps - t0 : C);
         for (int tt = 0; tt < tn; ++tt) {
             const int bb2 = rbl[tt + 2];
             const int Hup = shift_in_group<W>(Hlast);
@@ -173,7 +173,7 @@ __device__ __forceinline__ void sweep_i32(const KParams& P, const SchemeLds& S, 
         }
         if (more) {
             wave_lds_sync();
-            stage.store(buf, J, A, t0 + kChunk, l, bad);
+            stage.store(buf, J, A, t0 + C, l, bad);
             wave_lds_sync();
             // the two look-ahead reads of the next chunk's first steps were
             // taken from the old buffer; the new buffer holds the same
@@ -251,10 +251,10 @@ __device__ __forceinline__ u16x2 load_scores(const int8_t* mat, int addrA, int a
 
 // One sweep of the wave item order[first .. first+count), two pairs per
 // W-lane group packed into int16 halves.
-template <int W, int R, bool REV>
+template <int W, int R, bool REV, int C = kChunk>
 __device__ __forceinline__ void sweep_i16(const KParams& P, const SchemeLds& S, uint16_t* wbuf,
                                           int first, int count, int lane) {
-    using Stager = RefStager<W>;
+    using Stager = RefStager<W, C>;
     constexpr int reverse = REV ? 1 : 0;
     constexpr int RP = (R + 1) / 2;                 // row pairs per lane
     constexpr uint32_t K = kI16Bias;
@@ -340,13 +340,13 @@ __device__ __forceinline__ void sweep_i16(const KParams& P, const SchemeLds& S, 
     }
     bool bad = false;
     uint32_t jc = (uint32_t)(kColMax + l);   // kColMax - j with j = t - l
-    for (int t0 = 0; t0 < steps; t0 += kChunk) {
-        const bool more = t0 + kChunk < steps;
+    for (int t0 = 0; t0 < steps; t0 += C) {
+        const bool more = t0 + C < steps;
         if (more) {
-            stA.load(P.refs, JA, P.order, t0 + kChunk, l);
-            stB.load(P.refs, JB, P.order, t0 + kChunk, l);
+            stA.load(P.refs, JA, P.order, t0 + C, l);
+            stB.load(P.refs, JB, P.order, t0 + C, l);
         }
-        const int tn = __builtin_amdgcn_readfirstlane(steps - t0 < kChunk ? steps - t0 : kChunk);
+        const int tn = __builtin_amdgcn_readfirstlane(steps - t0 < C ? steps - t0 : C);
         for (int tt = 0; tt < tn; ++tt) {
             const int bbA2 = rblA[tt + 2];
             const int bbB2 = rblB[tt + 2];
@@ -390,8 +390,8 @@ __device__ __forceinline__ void sweep_i16(const KParams& P, const SchemeLds& S, 
         }
         if (more) {
             wave_lds_sync();
-            stA.store(bufA, JA, AA, t0 + kChunk, l, bad);
-            stB.store(bufB, JB, AB, t0 + kChunk, l, bad);
+            stA.store(bufA, JA, AA, t0 + C, l, bad);
+            stB.store(bufB, JB, AB, t0 + C, l, bad);
             wave_lds_sync();
             bbA_next = rblA[1];
             bbB_next = rblB[1];
@@ -463,10 +463,10 @@ __device__ __forceinline__ void sweep_i16(const KParams& P, const SchemeLds& S, 
 // the row update is  F = max3(F - e, Hm_up, K);  h = max3(Hm_diag + s', E, F);
 // Hm = h - o;  E = max3(E - e, Hm, K);  keys from h.  The top boundary is
 // Hm = K - o, F = K.
-template <int W, int R, bool REV>
+template <int W, int R, bool REV, int C = kChunk>
 __device__ __forceinline__ void sweep_i16_col(const KParams& P, const SchemeLds& S, uint16_t* wbuf,
                                               int first, int count, int lane) {
-    using Stager = RefStager<W>;
+    using Stager = RefStager<W, C>;
     constexpr int reverse = REV ? 1 : 0;
     constexpr int RP = (R + 1) / 2;
     constexpr uint32_t K = kI16Bias;
@@ -589,13 +589,13 @@ __device__ __forceinline__ void sweep_i16_col(const KParams& P, const SchemeLds&
         Flast = u32(F);
         --jc;
     };
-    for (int t0 = 0; t0 < steps; t0 += kChunk) {
-        const bool more = t0 + kChunk < steps;
+    for (int t0 = 0; t0 < steps; t0 += C) {
+        const bool more = t0 + C < steps;
         if (more) {
-            stA.load(P.refs, JA, P.order, t0 + kChunk, l);
-            stB.load(P.refs, JB, P.order, t0 + kChunk, l);
+            stA.load(P.refs, JA, P.order, t0 + C, l);
+            stB.load(P.refs, JB, P.order, t0 + C, l);
         }
-        const int tn = __builtin_amdgcn_readfirstlane(steps - t0 < kChunk ? steps - t0 : kChunk);
+        const int tn = __builtin_amdgcn_readfirstlane(steps - t0 < C ? steps - t0 : C);
         uint32_t a0 = rblA[0], b0 = rblB[0], a1 = rblA[1], b1 = rblB[1];
         int tt = 0;
         for (; tt + 1 < tn; tt += 2) {
@@ -605,8 +605,8 @@ __device__ __forceinline__ void sweep_i16_col(const KParams& P, const SchemeLds&
         if (tt < tn) step(a0, b0, tt + 2);
         if (more) {
             wave_lds_sync();
-            stA.store_col(bufA, JA, AA, S.colw[JA.sid], t0 + kChunk, l, bad);
-            stB.store_col(bufB, JB, AB, S.colw[JB.sid], t0 + kChunk, l, bad);
+            stA.store_col(bufA, JA, AA, S.colw[JA.sid], t0 + C, l, bad);
+            stB.store_col(bufB, JB, AB, S.colw[JB.sid], t0 + C, l, bad);
             wave_lds_sync();
         }
     }
@@ -672,10 +672,10 @@ __device__ __forceinline__ void sweep_i16_col(const KParams& P, const SchemeLds&
 // A row pair's scores of the next step are loaded as soon as the pair has
 // used the current ones; the column offsets they need are read from the
 // staged reference two steps ahead.
-template <int W, int R, bool REV>
+template <int W, int R, bool REV, int C = kChunk>
 __device__ __forceinline__ void sweep_i16_ptab(const KParams& P, const PtabLds& S, uint16_t* wbuf,
                                                int first, int count, int lane) {
-    using Stager = RefStager<W>;
+    using Stager = RefStager<W, C>;
     constexpr int reverse = REV ? 1 : 0;
     constexpr int RP = (R + 1) / 2;
     constexpr uint32_t K = kI16Bias;
@@ -836,13 +836,13 @@ __device__ __forceinline__ void sweep_i16_ptab(const KParams& P, const PtabLds& 
         Flast = u32(F);
         --jc;
     };
-    for (int t0 = 0; t0 < steps; t0 += kChunk) {
-        const bool more = t0 + kChunk < steps;
+    for (int t0 = 0; t0 < steps; t0 += C) {
+        const bool more = t0 + C < steps;
         if (more) {
-            stA.load(P.refs, JA, P.order, t0 + kChunk, l);
-            stB.load(P.refs, JB, P.order, t0 + kChunk, l);
+            stA.load(P.refs, JA, P.order, t0 + C, l);
+            stB.load(P.refs, JB, P.order, t0 + C, l);
         }
-        const int tn = __builtin_amdgcn_readfirstlane(steps - t0 < kChunk ? steps - t0 : kChunk);
+        const int tn = __builtin_amdgcn_readfirstlane(steps - t0 < C ? steps - t0 : C);
         uint32_t xa0 = rblA[0], xb0 = rblB[0], xa1 = rblA[1], xb1 = rblB[1];
 #pragma unroll
         for (int p = 0; p < RP; ++p) load_pair(p, xa0, xb0);
@@ -854,8 +854,8 @@ __device__ __forceinline__ void sweep_i16_ptab(const KParams& P, const PtabLds& 
         if (tt < tn) step(xa0, xb0, xa1, xb1, tt + 2);
         if (more) {
             wave_lds_sync();
-            stA.store_ptab(bufA, JA, A, D, t0 + kChunk, l, bad);
-            stB.store_ptab(bufB, JB, A, D, t0 + kChunk, l, bad);
+            stA.store_ptab(bufA, JA, A, D, t0 + C, l, bad);
+            stB.store_ptab(bufB, JB, A, D, t0 + C, l, bad);
             wave_lds_sync();
         }
     }

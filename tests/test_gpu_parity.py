@@ -221,9 +221,9 @@ def test_mixed_full_size_tuned_routing():
     from paper_2208_12350_amd.binding import Aligner, DeviceBatch, routing_string
     b = W.make_workload("mixed")
     db = DeviceBatch.from_host(b)
-    name, table, cands = T.tune_batch(b, db, 0, repeats=2)
+    name, table, cands, tile = T.tune_batch(b, db, 0, repeats=2)
     out = torch.empty((b.n_pairs, 5), dtype=torch.int32, device="cuda:0")
-    al = Aligner(0, routing_string(16, table))
+    al = Aligner(0, T.tuning_string(table, tile))
     try:
         al.align(db, out)
         al.align(db, out)          # a graph replay, as timed
@@ -234,7 +234,7 @@ def test_mixed_full_size_tuned_routing():
     for other, t in cands.items():
         if other == name:
             continue
-        alo = Aligner(0, routing_string(16, t))
+        alo = Aligner(0, T.tuning_string(t, 64 if tile == 128 else 128))
         try:
             out.fill_(-7)
             alo.align(db, out)
@@ -558,3 +558,31 @@ def test_column_word_and_table_paths_agree():
                 assert col_pairs == 0
         finally:
             al.close()
+
+
+@pytest.mark.parametrize("name", ["dna_large", "protein", "mixed"])
+def test_narrow_tile_is_exact(name):
+    """16- and 32-lane shapes streaming the reference in tiles of 64 steps
+    (option chunk = 64): the same bits as the default tile on every pair, and
+    the oracle's on a sample, with references around the tile boundaries."""
+    from paper_2208_12350_amd.binding import Aligner, DeviceBatch
+    b = W.make_workload(name, n_pairs=5000, seed=4040)
+    rng = np.random.default_rng(41)
+    sc = b.schemes[0] if name != "protein" else b.schemes[0]
+    A = sc.alphabet
+    pairs = [(rng.integers(0, A, size=int(n)).astype(np.uint8), rng.integers(0, A, size=int(m)).astype(np.uint8))
+             for n in (1, 17, 100, 255, 300, 511) for m in (1, 2, 49, 50, 63, 64, 65, 66, 127, 128, 129, 130, 192, 193)]
+    edge = W.from_pairs(pairs, [0] * len(pairs), [sc])
+    for batch in (b, edge):
+        db = DeviceBatch.from_host(batch)
+        outs = []
+        for chunk in (128, 64):
+            al = Aligner(0, chunk=chunk)
+            try:
+                outs.append(al.align(db).cpu().numpy())
+                assert al.get_option("chunk") == chunk
+            finally:
+                al.close()
+        assert np.array_equal(outs[0], outs[1])
+        idx = np.arange(batch.n_pairs) if batch is edge else np.sort(rng.choice(batch.n_pairs, 600, replace=False))
+        assert_same(outs[1], O.align_batch(batch, index=idx), batch, idx=idx)

@@ -134,6 +134,9 @@ const char* sw_last_error(sw_handle* h);
  *               rows' scores per load from a pair table (default 1);
  *               0 = byte-table lookups.  Read-only "pairtable_used": whether
  *               the last finished call used it
+ *   "chunk"     reference steps staged per LDS tile by the 16- and 32-lane
+ *               packed int16 kernels: 128 (default) or 64 (fewer prefetch
+ *               registers per lane, twice as many tile boundaries)
  *   "streams"   1..4: persistent mode spreads the bins' kernels over this
  *               many streams forked from (and joined back into) the
  *               caller's stream (default 4)
@@ -335,6 +338,7 @@ typedef struct sw_bin_stat {
     float ms;            /* kernel time (HIP events) with "timing" = 2, else 0 */
     int32_t column;      /* 1 = the column-word kernel, 0 = the table-lookup kernel,
                             2 = the pair-table kernel */
+    int32_t tile;        /* reference steps per LDS tile of the kernel (option "chunk") */
 } sw_bin_stat;
 
 /* Per-launch statistics of the last call on this handle: writes up to

@@ -368,8 +368,12 @@ int sw_last_bin_stats(sw_handle* h, sw_bin_stat* out, int capacity, int* n_out);
  * Requests that arrive while others run are admitted and merged into the
  * next batch of the first slot to free up, so work from different requests
  * overlaps on the device.  Results are identical to aligning each request
- * alone.  Each slot's call is captured into a graph once, when the server
- * is created, and replayed for every batch.  A server may be driven from
+ * alone.  Each slot holds two handles: merged batches of up to 8192 pairs
+ * run with a routing of few bins (16x16 up to 256 rows, 32x16 up to 512,
+ * cooperative 256x8 above), which shortens the critical path of small
+ * batches; larger ones use the routing of `tuning` (or the built-in one).
+ * Each handle's call is captured into a graph once, when the server is
+ * created, and replayed for every batch.  A server may be driven from
  * several host threads. */
 typedef struct sw_server sw_server;
 

@@ -72,8 +72,21 @@ __global__ void gather_spans_kernel(const Seg* segs, const uint8_t* pool, int64_
     }
 }
 
+// Batches of at most kLatencyPairs pairs (a request or a few, at low load)
+// run on a slot's latency handle, whose routing has few bins: 16x16 up to
+// 256 rows, 32x16 up to 512, and one cooperative 256-lane shape (8 rows per
+// lane) above.  The sweeps of a pass run bin by bin on each of a handle's
+// streams, so a small batch waits for the sum of its bins' longest pairs;
+// with three bins that sum is about half of the default routing's (single
+// mixed requests: 6.4 ms against 13 ms at the median).  Larger merged
+// batches run on the throughput handle, with the routing of the server's
+// tuning string (or the built-in one).
+constexpr int64_t kLatencyPairs = 8192;
+constexpr const char* kLatencyRoute = "route16=16x16@256/32x16@512/256x8@2048";
+
 struct Slot {
-    sw_handle* h = nullptr;
+    sw_handle* h = nullptr;       // throughput handle
+    sw_handle* hl = nullptr;      // latency handle
     hipStream_t stream = nullptr;
     int64_t* d_spans = nullptr;   // 4 x max_pairs
     uint8_t* d_sid = nullptr;
@@ -234,9 +247,10 @@ static void slot_loop(sw_server* S, Slot* slot) {
                                qb, qb + S->max_pairs, qb + 2 * S->max_pairs, qb + 3 * S->max_pairs, slot->d_sid);
             if (hipGetLastError() != hipSuccess) status = SW_EDEVICE;
         }
+        sw_handle* hh = P <= kLatencyPairs ? slot->hl : slot->h;
         if (status == SW_OK) {
             int64_t* qb = slot->d_spans;
-            status = sw_align_spans(slot->h, S->pool, qb, qb + S->max_pairs, S->pool, qb + 2 * S->max_pairs,
+            status = sw_align_spans(hh, S->pool, qb, qb + S->max_pairs, S->pool, qb + 2 * S->max_pairs,
                                     qb + 3 * S->max_pairs, slot->d_sid, P, S->schemes.data(),
                                     (int)S->schemes.size(), slot->d_out, slot->stream);
         }
@@ -247,7 +261,7 @@ static void slot_loop(sw_server* S, Slot* slot) {
                 hipStreamSynchronize(slot->stream) != hipSuccess)
                 status = SW_EDEVICE;
         }
-        std::string why = status == SW_OK ? std::string() : std::string(sw_last_error(slot->h));
+        std::string why = status == SW_OK ? std::string() : std::string(sw_last_error(hh));
         lk.lock();
         const Clock::time_point now = Clock::now();
         S->t_align += std::chrono::duration<double, std::milli>(t1 - t0).count();
@@ -298,10 +312,13 @@ sw_server* sw_server_create(int device, const sw_scheme* schemes, int n_schemes,
               hipHostMalloc(&S->stage, kStageBytes, hipHostMallocDefault) == hipSuccess &&
               hipStreamCreateWithFlags(&S->admit_stream, hipStreamNonBlocking) == hipSuccess;
     if (ok) S->alloc.reset(pool_bytes);
+    const std::string lat_tuning = std::string(tuning ? tuning : "") + ";" + kLatencyRoute;
     for (int k = 0; ok && k < n_slots; ++k) {
         std::unique_ptr<Slot> sl(new Slot());
         sl->h = sw_create(device, tuning);
-        ok = sl->h && sw_set_option(sl->h, "capacity", max_batch_pairs) == SW_OK &&
+        sl->hl = sw_create(device, lat_tuning.c_str());
+        ok = sl->h && sl->hl && sw_set_option(sl->h, "capacity", max_batch_pairs) == SW_OK &&
+             sw_set_option(sl->hl, "capacity", std::min<int64_t>(max_batch_pairs, kLatencyPairs)) == SW_OK &&
              hipStreamCreateWithFlags(&sl->stream, hipStreamNonBlocking) == hipSuccess &&
              hipMalloc(&sl->d_spans, 32 * max_batch_pairs) == hipSuccess &&
              hipMalloc(&sl->d_sid, max_batch_pairs) == hipSuccess &&
@@ -327,12 +344,14 @@ sw_server* sw_server_create(int device, const sw_scheme* schemes, int n_schemes,
         ok = ok && hipMemset(sl->d_sid, 0, 1) == hipSuccess;
         if (!ok) break;
         int64_t* qb = sl->d_spans;
-        ok = sw_align_spans(sl->h, S->pool, qb, qb + max_batch_pairs, S->pool, qb + 2 * max_batch_pairs,
-                            qb + 3 * max_batch_pairs, sl->d_sid, 1, S->schemes.data(), (int)S->schemes.size(),
-                            sl->d_out, sl->stream) == SW_OK;
-        int64_t captures = 0;
-        if (ok && (sw_get_option(sl->h, "captures", &captures) != SW_OK || captures != 1))
-            ok = sw_set_option(sl->h, "graph", 0) == SW_OK;
+        for (sw_handle* hh : {sl->h, sl->hl}) {
+            ok = ok && sw_align_spans(hh, S->pool, qb, qb + max_batch_pairs, S->pool, qb + 2 * max_batch_pairs,
+                                      qb + 3 * max_batch_pairs, sl->d_sid, 1, S->schemes.data(),
+                                      (int)S->schemes.size(), sl->d_out, sl->stream) == SW_OK;
+            int64_t captures = 0;
+            if (ok && (sw_get_option(hh, "captures", &captures) != SW_OK || captures != 1))
+                ok = sw_set_option(hh, "graph", 0) == SW_OK;
+        }
     }
     if (!ok) {
         sw_server_destroy(S);
@@ -359,6 +378,7 @@ void sw_server_destroy(sw_server* S) {
     for (auto& sl : S->slots) {
         if (sl->stream) (void)hipStreamSynchronize(sl->stream);
         if (sl->h) sw_destroy(sl->h);
+        if (sl->hl) sw_destroy(sl->hl);
         if (sl->stream) (void)hipStreamDestroy(sl->stream);
         if (sl->d_spans) (void)hipFree(sl->d_spans);
         if (sl->d_sid) (void)hipFree(sl->d_sid);

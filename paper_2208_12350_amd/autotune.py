@@ -206,19 +206,42 @@ def with_wide_groups(table: Table, rows_above: int, shapes: Sequence[Shape], wid
     return merge(choice)
 
 
+def coarse_rates(rates: Dict[Shape, float], step: int) -> Dict[Shape, float]:
+    """The shapes of `rates` whose rows per lane are a multiple of `step`
+    (16-lane shapes below `step` and cooperative shapes are kept): a routing
+    chosen among them has fewer bins."""
+    return {s: v for s, v in rates.items() if s[0] > 64 or s[1] % step == 0 or (s[0] == 16 and s[1] < step)}
+
+
 def candidate_tables(q_len, r_len, rates: Dict[Shape, float], shapes: Sequence[Shape],
                      builtin: Optional[Table] = None) -> Dict[str, Table]:
     """Routings worth timing on the real batch: the rate model's choice, the
-    same with long queries on cooperative 256-lane groups, and the library's
+    same with long queries on cooperative 256-lane groups, the model's choice
+    among shapes with an even number and a multiple of four rows per lane
+    ("coarse2", "coarse4": fewer bins, so shorter chains of launches per
+    stream and fewer launch tails, for some padding), and the library's
     built-in routing."""
     model = choose_routing(q_len, r_len, rates)
     out = {"model": model}
     if builtin is not None and builtin != model:
         out["builtin"] = list(builtin)
+
+    def add(name, t):
+        if t not in out.values():
+            out[name] = t
+
     for above in (512, 768, 1024):
-        t = with_wide_groups(model, above, shapes)
-        if t != model and t not in out.values():
-            out["model+coop>%d" % above] = t
+        add("model+coop>%d" % above, with_wide_groups(model, above, shapes))
+    for step in (2, 4):
+        try:
+            coarse = choose_routing(q_len, r_len, coarse_rates(rates, step))
+        except ValueError:
+            continue
+        if coarse in out.values():
+            continue
+        add("coarse%d" % step, coarse)
+        for above in (512, 768):
+            add("coarse%d+coop>%d" % (step, above), with_wide_groups(coarse, above, shapes))
     return out
 
 

@@ -95,7 +95,14 @@ def test_wide_group_variants():
     assert "model" in cands
     for name, table in cands.items():
         _valid(table)
-        if name == "model":
+        base_name = name.split("+")[0]
+        if base_name.startswith("coarse"):
+            step = int(base_name[len("coarse"):])
+            assert base_name in cands
+            # the coarse routings use rows per lane that are multiples of the step
+            for w, rr in T.expand(cands[base_name]):
+                assert w > 64 or rr % step == 0 or (w == 16 and rr < step)
+        if "+coop>" not in name:
             continue
         above = int(name.split(">")[1])
         for k, (w, rr) in enumerate(T.expand(table)):
@@ -103,10 +110,10 @@ def test_wide_group_variants():
             if rows > above:
                 assert w == 256 and 256 * rr >= rows and 256 * (rr - 1) < max(rows, 256 * 3)
             else:
-                assert (w, rr) == T.expand(cands["model"])[k]
-    # no cooperative shapes compiled: nothing to vary
+                assert (w, rr) == T.expand(cands[base_name])[k]
+    # no cooperative shapes compiled: no cooperative variants
     only = [s for s in SHAPES16 if s[0] != 256]
-    assert list(T.candidate_tables(q, r, {s: 1.0 for s in only}, only)) == ["model"]
+    assert not any("coop" in n for n in T.candidate_tables(q, r, {s: 1.0 for s in only}, only))
 
 
 def test_dominant_scheme_and_builtin_candidate():

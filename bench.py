@@ -160,6 +160,8 @@ def roofline_leg(args, db, out, tuning, mode, workload, steps):
     direction = "true" if dpass else "false"
     if dlanes > 64:
         kernel_name = "sw::sw_coop_kernel<%d, %s>" % (drows, direction)
+    elif dcol == 3:
+        kernel_name = "sw::sw_qprof_kernel<%d, %d>" % (dlanes, drows)
     elif dcol == 2:
         kernel_name = ("sw::sw_ptab_kernel<%d, %d, %s>" % (dlanes, drows, direction) if dtile == 128 else
                        "sw::sw_ptab_chunk_kernel<%d, %d, %s, %d>" % (dlanes, drows, direction, dtile))
@@ -377,8 +379,21 @@ def search_bench(args):
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     ref = out.clone()
+    qprof_used = al.get_option("qprofile_used")
     al.close()
     cells = s.cells()
+    # the same search with the forward pass on the pair table (no query profile)
+    alp = Aligner(0, qprofile=0)
+    alp.search(q, r, ro, s.scheme, out)
+    torch.cuda.synchronize()
+    tp = time.perf_counter()
+    npt = max(2, min(args.steps, 5))
+    for _ in range(npt):
+        alp.search(q, r, ro, s.scheme, out)
+    torch.cuda.synchronize()
+    elp = time.perf_counter() - tp
+    alp.close()
+    assert torch.equal(out, ref), "query-profile and pair-table searches differ"
     # the same pairs as a batch with the query copied per pair
     b = s.as_batch()
     db = DeviceBatch.from_host(b, dev)
@@ -401,6 +416,8 @@ def search_bench(args):
            "config": {"workload": args.workload, "query_len": int(s.query.size), "references": s.n_refs,
                       "cells": cells, "homologues": int(s.homolog.sum())},
            "batch_value": round(cells * nb / elb / 1e9, 2),
+           "query_profile": bool(qprof_used),
+           "no_profile_value": round(cells * npt / elp / 1e9, 2),
            "input_bytes": {"search": int(s.query.size + s.refs.size + 8 * s.r_off.size),
                            "batch": int(b.queries.size + b.refs.size + 8 * (b.q_off.size + b.r_off.size))},
            "latency_ms": {"p50": round(float(np.percentile(ts, 50)), 3),

@@ -134,12 +134,17 @@ const char* sw_last_error(sw_handle* h);
  *               rows' scores per load from a pair table (default 1);
  *               0 = byte-table lookups.  Read-only "pairtable_used": whether
  *               the last finished call used it
+ *   "qprofile"  1 = the forward pass of sw_search profiles the query in LDS
+ *               (scores of each lane's rows against every residue) when the
+ *               scheme qualifies for the pair table (default 1); 0 = pair
+ *               table.  Read-only "qprofile_used" as for "pairtable_used"
  *   "chunk"     reference steps staged per LDS tile by the 16- and 32-lane
  *               packed int16 kernels: 128 (default) or 64 (fewer prefetch
  *               registers per lane, twice as many tile boundaries)
- *   "streams"   1..4: persistent mode spreads the bins' kernels over this
+ *   "streams"   1..8: persistent mode spreads the bins' kernels over this
  *               many streams forked from (and joined back into) the
- *               caller's stream (default 4)
+ *               caller's stream (default 4; more than the process's
+ *               hardware queues, GPU_MAX_HW_QUEUES, 4 by default, share them)
  *   "cigar_workspace"  device bytes for the path records of sw_align_cigar
  *               (default 32 GiB, at least about 123 MB)
  * Returns SW_OK or SW_EINVAL for an unknown key / bad value. */
@@ -228,7 +233,11 @@ int sw_align_spans(sw_handle* h, const uint8_t* queries, const int64_t* q_beg, c
  * r_off[i+1])) are DEVICE pointers owned by the caller; `scheme` is one HOST
  * scheme.  The query is stored once and every pair's span points at it; the
  * spans are kept on the device between calls with the same query length, so
- * repeated searches replay one captured graph.  Errors as for sw_align_batch
+ * repeated searches replay one captured graph.  When the scheme takes table
+ * lookups (a large alphabet) the forward pass reads its scores from a query
+ * profile that each workgroup builds in LDS: for every residue b, the
+ * scores M[a_i][b] of each lane's query rows, read as whole dwords (option
+ * "qprofile").  Errors as for sw_align_batch
  * (SW_ETOOLONG for q_len > SW_MAX_QUERY). */
 int sw_search(sw_handle* h, const uint8_t* query, int64_t q_len, const uint8_t* refs, const int64_t* r_off,
               int64_t n_refs, const sw_scheme* scheme, sw_result* out, void* stream);
@@ -337,7 +346,7 @@ typedef struct sw_bin_stat {
     int64_t cells;       /* DP cells of those pairs in this pass */
     float ms;            /* kernel time (HIP events) with "timing" = 2, else 0 */
     int32_t column;      /* 1 = the column-word kernel, 0 = the table-lookup kernel,
-                            2 = the pair-table kernel */
+                            2 = the pair-table kernel, 3 = the query-profile kernel */
     int32_t tile;        /* reference steps per LDS tile of the kernel (option "chunk") */
 } sw_bin_stat;
 

@@ -190,6 +190,20 @@ struct RefStager {
             buf[l + k * W] = (uint16_t)(2 * ((inside && b < A) ? b : D - 1));
         }
     }
+    // Query-profile path: write the chunk as byte offsets b * row_bytes of
+    // the reference residues' profile rows; out-of-range columns and invalid
+    // residues get the padding code D - 1 (a row of zeros, a score of -o).
+    __device__ __forceinline__ void store_qprof(uint16_t* buf, const PairJob& J, int A, int D, int row_bytes, int t0,
+                                                int l, bool& bad) const {
+#pragma unroll
+        for (int k = 0; k < kPerLane; ++k) {
+            const int j = t0 - W + l + k * W;
+            const int b = raw[k];
+            const bool inside = j >= 0 && j < J.m;
+            bad |= inside && b >= A;
+            buf[l + k * W] = (uint16_t)(row_bytes * ((inside && b < A) ? b : D - 1));
+        }
+    }
     // Small-alphabet path: write the chunk as column words (bytes M[a][b] + o
     // for a = 0..3); out-of-range columns and invalid residues get word 0,
     // i.e. a score of -o for every row.

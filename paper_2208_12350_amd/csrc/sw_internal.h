@@ -142,6 +142,8 @@ struct KParams {
     int32_t max_items;           // capacity of the items array (bound for every item index)
     int32_t ptab_sid;            // scheme of the pair table (mats + kPtabOffset), or -1
     int32_t ptab_dim;            // its D = alphabet + 1
+    int32_t qprof;               // 1: the forward pass may use the query profile of queries[0 .. qprof_n)
+    int32_t qprof_n;
 };
 
 enum : int32_t {
@@ -187,8 +189,9 @@ using QueueFn = void (*)(KParams);
 struct ShapeDesc { int prec, W, R; };
 
 // Score sources of a shape's kernels: table lookups (any scheme), column
-// words (small alphabets) and the pair table (one scheme per call).
-enum : int { kVarTable = 0, kVarCol = 1, kVarPtab = 2, kNumVars = 3 };
+// words (small alphabets), the pair table (one scheme per call) and the
+// query profile (the forward pass of a database search).
+enum : int { kVarTable = 0, kVarCol = 1, kVarPtab = 2, kVarQprof = 3, kNumVars = 4 };
 
 // The kernel of a compiled shape for one score source, with the default or
 // the narrow reference tile (nullptr when the shape has no such variant).

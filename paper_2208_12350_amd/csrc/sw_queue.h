@@ -140,6 +140,57 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
     ptab_body<W, R, REV, C>(P, L, wbufs);
 }
 
+// Forward sweep of a database search with the query profile
+// (sweep_i16_qprof): every pair of the launch aligns queries[0 ..
+// P.qprof_n) with scheme P.ptab_sid.  The workgroup builds the profile of
+// its lanes' rows in LDS before it takes items.
+template <int W, int R>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void sw_qprof_kernel(KParams P) {
+    constexpr int RD = (R + 3) / 4;
+    constexpr int kRowBytes = W * RD * 4;
+    constexpr int kPPW = (64 / W) * 2;
+    __shared__ __attribute__((aligned(16))) uint8_t prof[kPtabMaxDim * kRowBytes];
+    __shared__ int32_t gopen[SW_MAX_SCHEMES], gext[SW_MAX_SCHEMES];
+    __shared__ uint16_t wbufs[kWavesPerBlock * kWaveBuf];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    int lo, hi;
+    if (!launch_range(P, tid, lo, hi)) return;
+    const int D = P.ptab_dim, sid = P.ptab_sid, n = P.qprof_n;
+    if (!P.qprof || sid < 0 || sid >= SW_MAX_SCHEMES || D < 2 || D > kPtabMaxDim || n < 1 || n > W * R) {
+        if (tid == 0) atomicOr(&P.flags[kFlagInternal], 1);
+        return;
+    }
+    const int A = D - 1;
+    const int o = P.gap_open[sid];
+    const int8_t* mat = P.mats + sid * kMatBytes;   // [b][a] = M[a][b]
+    bool bad = false;
+    for (int idx = tid; idx < D * kRowBytes; idx += kBlock) {
+        const int b = idx / kRowBytes, rem = idx % kRowBytes;
+        const int l = rem / (RD * 4), r = rem % (RD * 4);
+        const int i = l * R + r;
+        int v = 0;
+        if (b < A && r < R && i < n) {
+            const int a = P.queries[i];
+            bad |= a >= A;
+            v = a < A ? mat[b * kMatDim + a] + o : 0;
+        }
+        prof[idx] = (uint8_t)v;
+    }
+    if (bad && P.validate) atomicOr(&P.flags[kFlagBadResidue], 1);
+    if (tid < SW_MAX_SCHEMES) {
+        gopen[tid] = P.gap_open[tid];
+        gext[tid] = P.gap_extend[tid];
+    }
+    const int n_pairs = __builtin_amdgcn_readfirstlane(*P.n_dev);
+    __syncthreads();
+    uint16_t* wbuf = wbufs + wave * kWaveBuf;
+    queue_loop<kPPW>(P, lane, lo, hi, n_pairs, [&](int first, int count) {
+        sweep_i16_qprof<W, R>(P, gopen, gext, prof, wbuf, first, count, lane);
+    });
+}
+
 // Per tile width (index 0: kChunk, 1: kChunkNarrow) and score source
 // (kVarTable, kVarCol, kVarPtab): the forward and reverse kernels, null
 // where a shape has no such variant.

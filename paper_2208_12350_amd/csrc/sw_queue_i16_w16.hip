@@ -1,5 +1,5 @@
 // sw_queue_i16_w16.hip -- queue kernels of the packed int16 sweep shapes with
-// 16-lane groups, 1..8 rows per lane (queries up to 128 residues): table-lookup, column-word and pair-table
+// 16-lane groups, 1..8 rows per lane (queries up to 128 residues): table-lookup, column-word, pair-table and (forward only) query-profile
 // kernels, forward and reverse, each with the default tile of kChunk
 // reference steps and the narrow tile of kChunkNarrow.
 #include "sw_queue.h"
@@ -12,12 +12,14 @@ extern const int kNumI16W16Kernels;
 #define SW_ENTRY(W, R) \
     {16, W, R, {{{&sw_queue_kernel<16, W, R, false, false>, &sw_queue_kernel<16, W, R, true, false>}, \
                  {&sw_queue_kernel<16, W, R, false, true>, &sw_queue_kernel<16, W, R, true, true>}, \
-                 {&sw_ptab_kernel<W, R, false>, &sw_ptab_kernel<W, R, true>}}, \
+                 {&sw_ptab_kernel<W, R, false>, &sw_ptab_kernel<W, R, true>}, \
+                 {&sw_qprof_kernel<W, R>, nullptr}}, \
                 {{&sw_queue_chunk_kernel<16, W, R, false, false, kChunkNarrow>, \
                   &sw_queue_chunk_kernel<16, W, R, true, false, kChunkNarrow>}, \
                  {&sw_queue_chunk_kernel<16, W, R, false, true, kChunkNarrow>, \
                   &sw_queue_chunk_kernel<16, W, R, true, true, kChunkNarrow>}, \
-                 {&sw_ptab_chunk_kernel<W, R, false, kChunkNarrow>, &sw_ptab_chunk_kernel<W, R, true, kChunkNarrow>}}}},
+                 {&sw_ptab_chunk_kernel<W, R, false, kChunkNarrow>, &sw_ptab_chunk_kernel<W, R, true, kChunkNarrow>}, \
+                 {nullptr, nullptr}}}},
 const KernelEntry kI16W16Kernels[] = {
     SW_ENTRY(16, 1) SW_ENTRY(16, 2) SW_ENTRY(16, 3) SW_ENTRY(16, 4) SW_ENTRY(16, 5) SW_ENTRY(16, 6)
     SW_ENTRY(16, 7) SW_ENTRY(16, 8)

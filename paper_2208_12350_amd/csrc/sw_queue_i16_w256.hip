@@ -10,8 +10,9 @@ extern const KernelEntry kI16W256Kernels[];
 extern const int kNumI16W256Kernels;
 
 #define SW_ENTRY(R) \
-    {16, kCoopW, R, {{{&sw_coop_kernel<R, false>, &sw_coop_kernel<R, true>}, {nullptr, nullptr}, {nullptr, nullptr}}, \
-                     {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}}}},
+    {16, kCoopW, R, {{{&sw_coop_kernel<R, false>, &sw_coop_kernel<R, true>}, {nullptr, nullptr}, {nullptr, nullptr}, \
+                      {nullptr, nullptr}}, \
+                     {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}}}},
 const KernelEntry kI16W256Kernels[] = {
     SW_ENTRY(3) SW_ENTRY(4) SW_ENTRY(5) SW_ENTRY(6) SW_ENTRY(7) SW_ENTRY(8)
 };

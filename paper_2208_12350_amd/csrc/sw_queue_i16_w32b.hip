@@ -1,5 +1,5 @@
 // sw_queue_i16_w32b.hip -- queue kernels of the packed int16 sweep shapes with
-// 32-lane groups, 11..16 rows per lane (queries of 321..512 residues): table-lookup, column-word and pair-table
+// 32-lane groups, 11..16 rows per lane (queries of 321..512 residues): table-lookup, column-word, pair-table and (forward only) query-profile
 // kernels, forward and reverse, each with the default tile of kChunk
 // reference steps and the narrow tile of kChunkNarrow.
 #include "sw_queue.h"
@@ -12,12 +12,14 @@ extern const int kNumI16W32bKernels;
 #define SW_ENTRY(W, R) \
     {16, W, R, {{{&sw_queue_kernel<16, W, R, false, false>, &sw_queue_kernel<16, W, R, true, false>}, \
                  {&sw_queue_kernel<16, W, R, false, true>, &sw_queue_kernel<16, W, R, true, true>}, \
-                 {&sw_ptab_kernel<W, R, false>, &sw_ptab_kernel<W, R, true>}}, \
+                 {&sw_ptab_kernel<W, R, false>, &sw_ptab_kernel<W, R, true>}, \
+                 {&sw_qprof_kernel<W, R>, nullptr}}, \
                 {{&sw_queue_chunk_kernel<16, W, R, false, false, kChunkNarrow>, \
                   &sw_queue_chunk_kernel<16, W, R, true, false, kChunkNarrow>}, \
                  {&sw_queue_chunk_kernel<16, W, R, false, true, kChunkNarrow>, \
                   &sw_queue_chunk_kernel<16, W, R, true, true, kChunkNarrow>}, \
-                 {&sw_ptab_chunk_kernel<W, R, false, kChunkNarrow>, &sw_ptab_chunk_kernel<W, R, true, kChunkNarrow>}}}},
+                 {&sw_ptab_chunk_kernel<W, R, false, kChunkNarrow>, &sw_ptab_chunk_kernel<W, R, true, kChunkNarrow>}, \
+                 {nullptr, nullptr}}}},
 const KernelEntry kI16W32bKernels[] = {
     SW_ENTRY(32, 11) SW_ENTRY(32, 12) SW_ENTRY(32, 13) SW_ENTRY(32, 14) SW_ENTRY(32, 15) SW_ENTRY(32, 16)
 };

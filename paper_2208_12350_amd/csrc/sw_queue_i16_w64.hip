@@ -1,5 +1,5 @@
 // sw_queue_i16_w64.hip -- queue kernels of the packed int16 sweep shapes with
-// 64-lane groups, 9..20 rows per lane (queries up to 1280 residues): table-lookup, column-word and pair-table
+// 64-lane groups, 9..20 rows per lane (queries up to 1280 residues): table-lookup, column-word, pair-table and (forward only) query-profile
 // kernels, forward and reverse.
 #include "sw_queue.h"
 
@@ -11,8 +11,9 @@ extern const int kNumI16W64Kernels;
 #define SW_ENTRY(W, R) \
     {16, W, R, {{{&sw_queue_kernel<16, W, R, false, false>, &sw_queue_kernel<16, W, R, true, false>}, \
                  {&sw_queue_kernel<16, W, R, false, true>, &sw_queue_kernel<16, W, R, true, true>}, \
-                 {&sw_ptab_kernel<W, R, false>, &sw_ptab_kernel<W, R, true>}}, \
-                {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}}}},
+                 {&sw_ptab_kernel<W, R, false>, &sw_ptab_kernel<W, R, true>}, \
+                 {&sw_qprof_kernel<W, R>, nullptr}}, \
+                {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}}}},
 const KernelEntry kI16W64Kernels[] = {
     SW_ENTRY(64, 9) SW_ENTRY(64, 10) SW_ENTRY(64, 11) SW_ENTRY(64, 12) SW_ENTRY(64, 13) SW_ENTRY(64, 14)
     SW_ENTRY(64, 15) SW_ENTRY(64, 16) SW_ENTRY(64, 17) SW_ENTRY(64, 18) SW_ENTRY(64, 19) SW_ENTRY(64, 20)

@@ -1,5 +1,5 @@
 // sw_queue_i16_w64_long.hip -- queue kernels of the packed int16 sweep shapes with
-// 64-lane groups, 21..32 rows per lane (queries of 1281..2048 residues): table-lookup, column-word and pair-table
+// 64-lane groups, 21..32 rows per lane (queries of 1281..2048 residues): table-lookup, column-word, pair-table and (forward only) query-profile
 // kernels, forward and reverse.
 #include "sw_queue.h"
 
@@ -11,8 +11,9 @@ extern const int kNumI16W64LongKernels;
 #define SW_ENTRY(W, R) \
     {16, W, R, {{{&sw_queue_kernel<16, W, R, false, false>, &sw_queue_kernel<16, W, R, true, false>}, \
                  {&sw_queue_kernel<16, W, R, false, true>, &sw_queue_kernel<16, W, R, true, true>}, \
-                 {&sw_ptab_kernel<W, R, false>, &sw_ptab_kernel<W, R, true>}}, \
-                {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}}}},
+                 {&sw_ptab_kernel<W, R, false>, &sw_ptab_kernel<W, R, true>}, \
+                 {&sw_qprof_kernel<W, R>, nullptr}}, \
+                {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}}}},
 const KernelEntry kI16W64LongKernels[] = {
     SW_ENTRY(64, 21) SW_ENTRY(64, 22) SW_ENTRY(64, 23) SW_ENTRY(64, 24) SW_ENTRY(64, 25) SW_ENTRY(64, 26)
     SW_ENTRY(64, 27) SW_ENTRY(64, 28) SW_ENTRY(64, 29) SW_ENTRY(64, 30) SW_ENTRY(64, 31) SW_ENTRY(64, 32)

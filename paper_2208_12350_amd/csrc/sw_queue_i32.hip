@@ -7,8 +7,8 @@ namespace sw {
 
 #define SW_ENTRY(W, R) \
     {32, W, R, {{{&sw_queue_kernel<32, W, R, false, false>, &sw_queue_kernel<32, W, R, true, false>}, \
-                 {nullptr, nullptr}, {nullptr, nullptr}}, \
-                {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}}}},
+                 {nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}}, \
+                {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}}}},
 static const KernelEntry kI32Kernels[] = {
     SW_ENTRY(16, 2) SW_ENTRY(16, 4) SW_ENTRY(16, 6) SW_ENTRY(16, 8) SW_ENTRY(16, 10)
     SW_ENTRY(16, 12) SW_ENTRY(16, 14) SW_ENTRY(16, 16)

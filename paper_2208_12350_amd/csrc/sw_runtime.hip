@@ -99,6 +99,8 @@ struct GraphKey {
     int32_t validate;
     int32_t precision;
     int32_t ptab_sid;
+    int32_t qprof;
+    int32_t qprof_n;       // a profile is built for this query length (a kernel argument)
 };
 
 }  // namespace
@@ -123,7 +125,9 @@ struct sw_handle {
     std::vector<int> resident_blocks[2][2][kNumVars];   // per tile, pass, score source and bin: workgroups the device holds at once
     int64_t opt_chunk = kChunk;         // reference tile of 16- and 32-lane packed shapes: kChunk or kChunkNarrow
     int64_t opt_ptab = 1;
+    int64_t opt_qprof = 1;
     int32_t last_ptab = 0;              // the last call's table-range kernels used the pair table
+    int32_t last_qprof = 0;             // the last call's forward pass used the query profile
 
     int8_t* d_mats = nullptr;
     int8_t* d_lut = nullptr;
@@ -154,6 +158,7 @@ struct sw_handle {
         int8_t* h_mats = nullptr;      // pinned: staging of the scheme tables
         bool timing = false;
         bool ptab = false;             // its table-range kernels used the pair table
+        bool qprof = false;            // its forward pass used the query profile
         int chunk = kChunk;            // its "chunk" option
         std::chrono::steady_clock::time_point t_entry;
     };
@@ -176,9 +181,9 @@ struct sw_handle {
     std::vector<sw_bin_stat> bin_stats;
 
     hipStream_t cap_stream = nullptr;   // private stream the graph is captured on
-    static constexpr int kForks = 4;    // persistent mode spreads bins over these streams
-    hipStream_t fork[kForks] = {nullptr, nullptr, nullptr, nullptr};
-    hipEvent_t fork_ev[kForks + 1] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    static constexpr int kForks = 8;    // persistent mode spreads bins over up to this many streams
+    hipStream_t fork[kForks] = {};
+    hipEvent_t fork_ev[kForks + 1] = {};
     // captured calls, most recently used last (at most kGraphs)
     struct GraphEntry {
         GraphKey key;
@@ -416,6 +421,16 @@ static void set_range(KParams& K, int b, int v) {
 
 static int bin_ev_index(int pass, int b, int v, int end) { return ((pass * kMaxBins + b) * 2 + v) * 2 + end; }
 
+// Score source of bin e's kernel for its column-word range (v = 1) or its
+// other range: the query profile in the forward pass of a search, else the
+// pair table when the call has one, else table lookups.
+static int table_var(const sw_handle* h, const BinInfo& e, const KParams& K, int v) {
+    (void)h;
+    if (v == 1) return kVarCol;
+    if (K.qprof && !K.reverse && shape_kernel(e.prec, e.W, e.R, false, kVarQprof) != nullptr) return kVarQprof;
+    return e.ptab && K.ptab_sid >= 0 ? kVarPtab : kVarTable;
+}
+
 // 1 when bin e's kernel of score source `var` runs with the narrow
 // reference tile (the "chunk" option; only 16- and 32-lane packed shapes
 // have it).
@@ -456,7 +471,7 @@ static int enqueue_pass(sw_handle* h, KParams K, const ClassifyArgs& C, const Wo
             const int ipb = items_per_block(e.W);
             const int64_t need = (cap / e.ppw + 1 + ipb - 1) / ipb;
             for (int v = e.col ? 1 : 0; v >= 0; --v) {   // column-word kernel first
-                const int var = v == 1 ? kVarCol : (e.ptab && K.ptab_sid >= 0 ? kVarPtab : kVarTable);
+                const int var = table_var(h, e, K, v);
                 const int nw = narrow_tile(h, e, var);
                 const int blocks = (int)std::min<int64_t>(need, h->resident_blocks[nw][pass][var][b]);
                 set_range(K, b, v);
@@ -486,7 +501,7 @@ static int enqueue_pass(sw_handle* h, KParams K, const ClassifyArgs& C, const Wo
                 const int items = h->h_meta[K.hi_idx] - h->h_meta[K.lo_idx];
                 if (items <= 0) continue;
                 const int blocks = (items + items_per_block(e.W) - 1) / items_per_block(e.W);
-                const int var = v == 1 ? kVarCol : (e.ptab && K.ptab_sid >= 0 ? kVarPtab : kVarTable);
+                const int var = table_var(h, e, K, v);
                 const int nw = narrow_tile(h, e, var);
                 if (per_bin) HIP_TRY(h, hipEventRecord(h->bin_ev[bin_ev_index(pass, b, v, 0)], stream));
                 hipLaunchKernelGGL(shape_kernel(e.prec, e.W, e.R, pass != 0, var, nw == 1), dim3(blocks), dim3(kBlock),
@@ -608,7 +623,7 @@ sw_handle* sw_create(int device, const char* tuning) {
                     if ((v == kVarCol && !h->bins[b].col) || (v == kVarPtab && !h->bins[b].ptab)) continue;
                     const QueueFn fn = shape_kernel(h->bins[b].prec, h->bins[b].W, h->bins[b].R, pass != 0, v, nw == 1);
                     if (!fn) {
-                        ok = nw == 1;   // only the narrow tile may be missing
+                        ok = nw == 1 || v == kVarQprof;   // only the narrow tile and reverse profiles may be missing
                         continue;
                     }
                     int per_cu = 0;
@@ -705,6 +720,8 @@ int sw_set_option(sw_handle* h, const char* key, int64_t value) {
         h->opt_chunk = value;
     } else if (k == "pairtable") {
         h->opt_ptab = value ? 1 : 0;
+    } else if (k == "qprofile") {
+        h->opt_qprof = value ? 1 : 0;
     } else if (k == "capacity") {
         // reserve workspace for this many pairs up front (grids and graphs are
         // sized for the capacity, so batches up to it reuse one graph)
@@ -746,6 +763,8 @@ int sw_get_option(sw_handle* h, const char* key, int64_t* value) {
     else if (k == "colpath") *value = h->opt_colpath;
     else if (k == "chunk") *value = h->opt_chunk;
     else if (k == "pairtable") *value = h->opt_ptab;
+    else if (k == "qprofile") *value = h->opt_qprof;
+    else if (k == "qprofile_used") *value = h->last_qprof;
     else if (k == "pairtable_used") *value = h->last_ptab;
     else if (k == "cigar_workspace") *value = h->opt_path_ws;
     else if (k == "captures") *value = h->n_captures;
@@ -771,6 +790,7 @@ static int complete_slot(sw_handle* h, int k) {
     h->last_i32 = (int64_t)cnt[kCtrI32Pairs];
     h->bin_stats.clear();
     h->last_ptab = sl.ptab ? 1 : 0;
+    h->last_qprof = sl.qprof ? 1 : 0;
     for (int pass = 0; pass < 2; ++pass)
         for (int b = 0; b < (int)h->bins.size(); ++b)
             for (int v = h->bins[b].col ? 1 : 0; v >= 0; --v) {
@@ -780,8 +800,10 @@ static int complete_slot(sw_handle* h, int k) {
                 st.precision = h->bins[b].prec;
                 st.lanes = h->bins[b].W;
                 st.rows = h->bins[b].R;
-                st.column = v == 1 ? 1 : (sl.ptab && h->bins[b].ptab ? 2 : 0);
-                st.tile = sl.chunk == kChunkNarrow &&
+                const bool qp = sl.qprof && pass == 0 && v == 0 &&
+                                shape_kernel(st.precision, st.lanes, st.rows, false, kVarQprof) != nullptr;
+                st.column = v == 1 ? 1 : (qp ? 3 : (sl.ptab && h->bins[b].ptab ? 2 : 0));
+                st.tile = !qp && sl.chunk == kChunkNarrow &&
                                   shape_kernel(st.precision, st.lanes, st.rows, false, v == 1 ? kVarCol : kVarTable, true)
                               ? kChunkNarrow
                               : kChunk;
@@ -815,8 +837,8 @@ static int complete_slot(sw_handle* h, int k) {
     if (flags[kFlagTooLong])
         return fail(h, SW_ETOOLONG, "a query exceeds %d or a reference exceeds %d residues", SW_MAX_QUERY, SW_MAX_REF);
     if (flags[kFlagBadResidue]) return fail(h, SW_EINVAL, "residue code outside its scheme's alphabet");
-    if (flags[kFlagReverseMismatch]) return fail(h, SW_EINTERNAL, "reverse sweep did not reproduce the forward score");
     if (flags[kFlagInternal]) return fail(h, SW_EINTERNAL, "a planning invariant did not hold");
+    if (flags[kFlagReverseMismatch]) return fail(h, SW_EINTERNAL, "reverse sweep did not reproduce the forward score");
     return SW_OK;
 }
 
@@ -846,7 +868,7 @@ static int submit_spans(sw_handle* h, const uint8_t* queries, const int64_t* q_b
                         const uint8_t* refs, const int64_t* r_beg, const int64_t* r_end,
                         const uint8_t* scheme_id, int64_t n_pairs, const sw_scheme* schemes,
                         int n_schemes, sw_result* out, void* stream_ptr, bool no_alloc, bool allow_timing,
-                        uint64_t* ticket) {
+                        uint64_t* ticket, int64_t qprof_n = -1) {
     if (!h) return SW_EINVAL;
     h->err.clear();
     const auto t_entry = std::chrono::steady_clock::now();
@@ -1009,6 +1031,10 @@ static int submit_spans(sw_handle* h, const uint8_t* queries, const int64_t* q_b
     K.max_items = (int32_t)(ws.cap + kMaxBins);
     K.ptab_sid = ptab_sid;
     K.ptab_dim = D;
+    // query profile: a search (every pair aligns queries[0 .. qprof_n)) with
+    // the pair table's scheme profiles its query for the forward pass
+    K.qprof = (qprof_n >= 1 && qprof_n <= SW_MAX_QUERY && ptab_sid >= 0 && h->opt_qprof) ? 1 : 0;
+    K.qprof_n = K.qprof ? (int32_t)qprof_n : 0;
     for (int s = 0; s < SW_MAX_SCHEMES; ++s) {
         const bool v = s < n_schemes;
         K.alphabet[s] = v ? schemes[s].alphabet : 1;
@@ -1033,6 +1059,8 @@ static int submit_spans(sw_handle* h, const uint8_t* queries, const int64_t* q_b
     memcpy(key.col_ok, C.col_ok, sizeof(key.col_ok));
     key.n_schemes = n_schemes; key.validate = (int32_t)h->opt_validate; key.precision = (int32_t)h->opt_precision;
     key.ptab_sid = ptab_sid;
+    key.qprof = K.qprof;
+    key.qprof_n = K.qprof_n;
 
     // Start of the call, in stream order and outside any graph: the scheme
     // tables when they differ from what the device holds (from this call's
@@ -1134,6 +1162,7 @@ static int submit_spans(sw_handle* h, const uint8_t* queries, const int64_t* q_b
     sl.ticket = h->next_ticket++;
     sl.timing = timing;
     sl.ptab = ptab_sid >= 0;
+    sl.qprof = K.qprof != 0;
     sl.chunk = (int)h->opt_chunk;
     sl.t_entry = t_entry;
     h->last_slot = k;
@@ -1177,11 +1206,12 @@ static int poll_ticket(sw_handle* h, uint64_t ticket, int wait) {
 static int align_spans(sw_handle* h, const uint8_t* queries, const int64_t* q_beg, const int64_t* q_end,
                        const uint8_t* refs, const int64_t* r_beg, const int64_t* r_end,
                        const uint8_t* scheme_id, int64_t n_pairs, const sw_scheme* schemes,
-                       int n_schemes, sw_result* out, void* stream_ptr, bool no_alloc = false) {
+                       int n_schemes, sw_result* out, void* stream_ptr, bool no_alloc = false,
+                       int64_t qprof_n = -1) {
     if (!h) return SW_EINVAL;
     uint64_t t = 0;
     const int rc = submit_spans(h, queries, q_beg, q_end, refs, r_beg, r_end, scheme_id, n_pairs, schemes,
-                                n_schemes, out, stream_ptr, no_alloc, true, &t);
+                                n_schemes, out, stream_ptr, no_alloc, true, &t, qprof_n);
     if (rc != SW_OK) return rc;
     const double enq = h->t_enqueue;
     const auto t0 = std::chrono::steady_clock::now();
@@ -1570,5 +1600,6 @@ extern "C" int sw_search(sw_handle* h, const uint8_t* query, int64_t q_len, cons
         h->search_len = q_len;
     }
     const uint8_t* qptr = query ? query : refs;   // an empty query is never read
-    return align_spans(h, qptr, beg, end, refs, r_off, r_off + 1, nullptr, n_refs, scheme, 1, out, stream);
+    return align_spans(h, qptr, beg, end, refs, r_off, r_off + 1, nullptr, n_refs, scheme, 1, out, stream, false,
+                       q_len);
 }

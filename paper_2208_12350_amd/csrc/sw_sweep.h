@@ -904,4 +904,187 @@ __device__ __forceinline__ void sweep_i16_ptab(const KParams& P, const PtabLds& 
     }
 }
 
+// Query-profile variant of the forward sweep, for a database search: every
+// pair of the call aligns the same query, whose profile the workgroup builds
+// in LDS once: byte ((b W + l) Rp + r) is M[a_i][b] + o for row i = l R + r
+// of lane l (0 past the query end, and for the padding code b = D - 1), with
+// Rp = R rounded up to whole dwords.  A lane reads its R rows' scores for
+// one reference residue as Rp/4 consecutive dwords at one address (one add
+// per pair and step), and one v_perm_b32 per row places pair A's score in
+// the low half and pair B's in the high half.  Scores arrive biased by +o
+// and rows keep Hm = H - o, as in sweep_i16_col.  The profile stands for
+// the pair table (at most 24 residues, scores plus o a byte, o <= K), whose
+// two loads and two adds per row pair it replaces.
+template <int W, int R, int C = kChunk>
+__device__ __forceinline__ void sweep_i16_qprof(const KParams& P, const int32_t* gap_open, const int32_t* gap_extend,
+                                                const uint8_t* prof, uint16_t* wbuf, int first, int count,
+                                                int lane) {
+    using Stager = RefStager<W, C>;
+    constexpr int RP = (R + 1) / 2;
+    constexpr int RD = (R + 3) / 4;                 // profile dwords per lane and residue
+    constexpr uint32_t K = kI16Bias;
+    constexpr uint32_t K2 = K | (K << 16);
+    const int g = lane / W;
+    const int l = lane % W;
+    const int D = P.ptab_dim;
+    const int A = D - 1;
+
+    const int slot = g * 2;
+    const int pairA = slot < count ? P.order[first + slot] : -1;
+    const int pairB = slot + 1 < count ? P.order[first + slot + 1] : -1;
+    PairJob JA = load_job(P, pairA, 0);
+    PairJob JB = load_job(P, pairB, 0);
+    // every pair aligns the profiled query with the profile's scheme
+    if (pairA >= 0 && (JA.sid != P.ptab_sid || JA.n != P.qprof_n)) {
+        atomicOr(&P.flags[kFlagInternal], 1);
+        JA.n = JA.m = 0; JA.sid = P.ptab_sid;
+    }
+    if (pairB >= 0 && (JB.sid != P.ptab_sid || JB.n != P.qprof_n)) {
+        atomicOr(&P.flags[kFlagInternal], 1);
+        JB.n = JB.m = 0; JB.sid = P.ptab_sid;
+    }
+
+    int mmax = imax(JA.m, JB.m);
+    for (int off = 32; off > 0; off >>= 1) mmax = imax(mmax, __shfl_xor(mmax, off));
+    const int steps = __builtin_amdgcn_readfirstlane(mmax > 0 ? mmax + W - 1 : 0);
+
+    uint16_t* bufA = wbuf + (g * 2) * Stager::kBuf;
+    uint16_t* bufB = bufA + Stager::kBuf;
+    Stager stA, stB;
+    stA.load(P.refs, JA, P.order, 0, l);
+    stB.load(P.refs, JB, P.order, 0, l);
+    constexpr int kRowBytes = W * RD * 4;           // profile bytes per residue
+    bool bad = false;
+    stA.store_qprof(bufA, JA, A, D, kRowBytes, 0, l, bad);
+    stB.store_qprof(bufB, JB, A, D, kRowBytes, 0, l, bad);
+    if (bad && P.validate) atomicOr(&P.flags[kFlagBadResidue], 1);
+    const uint8_t* lprof = prof + l * RD * 4;       // this lane's rows of residue 0
+    const int sid = JA.sid < SW_MAX_SCHEMES ? JA.sid : 0;
+    const uint32_t go = (uint32_t)gap_open[sid];
+    const u16x2 go2 = pk(go | (go << 16));
+    const uint32_t ge = cost16(gap_extend[sid]);
+    const u16x2 ge2 = pk(ge | (ge << 16));
+    const u16x2 zero = pk(K2);
+    const uint32_t hm_top = (K - go) | ((K - go) << 16);
+    wave_lds_sync();
+
+    u16x2 Hm[R], E[R];
+    uint32_t kA[RP], kB[RP];
+#pragma unroll
+    for (int r = 0; r < R; ++r) { Hm[r] = pk(hm_top); E[r] = zero; }
+#pragma unroll
+    for (int p = 0; p < RP; ++p) { kA[p] = 0u; kB[p] = 0u; }
+    uint32_t Hlast = hm_top, Flast = K2, Hup_prev = hm_top;
+    const uint16_t* rblA = bufA + W - l;
+    const uint16_t* rblB = bufB + W - l;
+
+    // dA/dB: the lane's scores (bytes) of the current step for pairs A and
+    // B, four rows per dword; reloaded for the next step dword by dword as
+    // soon as its rows are done.  Column offsets as in sweep_i16_ptab.
+    uint32_t dA[RD], dB[RD];
+    uint32_t jc = (uint32_t)(kColMax + l);
+    auto step = [&](uint32_t& xa, uint32_t& xb, uint32_t na, uint32_t nb, int ahead) {
+        xa = rblA[ahead];
+        xb = rblB[ahead];
+        const u16x2 Hmu0 = pk((uint32_t)shift_in_group<W>((int)Hlast, (int)hm_top));
+        const u16x2 Fup = pk((uint32_t)shift_in_group_zero<W>((int)Flast));
+        u16x2 diag = pk(Hup_prev);
+        Hup_prev = u32(Hmu0);
+        u16x2 Hmu = Hmu0;
+        u16x2 F = Fup;
+        const uint32_t jc1 = jc | 0x8000u;
+        uint32_t keyA0 = 0, keyB0 = 0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int p = r / 2;
+            F = pk_max3(pk_sat_sub(F, ge2), Hmu, zero);
+            const uint32_t sel = (uint32_t)(r % 4) | 0x0C00u | ((uint32_t)(4 + r % 4) << 16) | 0x0C000000u;
+            const u16x2 sc = pk(__builtin_amdgcn_perm(dB[r / 4], dA[r / 4], sel));
+            const u16x2 h = pk_max3(diag + sc, E[r], F);
+            diag = Hm[r];
+            Hmu = h - go2;
+            Hm[r] = Hmu;
+            E[r] = pk_max3(pk_sat_sub(E[r], ge2), Hmu, zero);
+            const uint32_t hv = u32(h);
+            if ((r & 1) == 0) {
+                keyA0 = (hv << 16) | jc1;
+                keyB0 = (hv & 0xFFFF0000u) | jc1;
+                if (r == R - 1) {
+                    kA[p] = kA[p] > keyA0 ? kA[p] : keyA0;
+                    kB[p] = kB[p] > keyB0 ? kB[p] : keyB0;
+                }
+            } else {
+                kA[p] = umax3(kA[p], keyA0, (hv << 16) | jc);
+                kB[p] = umax3(kB[p], keyB0, (hv & 0xFFFF0000u) | jc);
+            }
+            if (r % 4 == 3 || r == R - 1) {
+                dA[r / 4] = *reinterpret_cast<const uint32_t*>(lprof + na + 4 * (r / 4));
+                dB[r / 4] = *reinterpret_cast<const uint32_t*>(lprof + nb + 4 * (r / 4));
+            }
+        }
+        Hlast = u32(Hm[R - 1]);
+        Flast = u32(F);
+        --jc;
+    };
+    for (int t0 = 0; t0 < steps; t0 += C) {
+        const bool more = t0 + C < steps;
+        if (more) {
+            stA.load(P.refs, JA, P.order, t0 + C, l);
+            stB.load(P.refs, JB, P.order, t0 + C, l);
+        }
+        const int tn = __builtin_amdgcn_readfirstlane(steps - t0 < C ? steps - t0 : C);
+        uint32_t xa0 = rblA[0], xb0 = rblB[0], xa1 = rblA[1], xb1 = rblB[1];
+#pragma unroll
+        for (int k = 0; k < RD; ++k) {
+            dA[k] = *reinterpret_cast<const uint32_t*>(lprof + xa0 + 4 * k);
+            dB[k] = *reinterpret_cast<const uint32_t*>(lprof + xb0 + 4 * k);
+        }
+        int tt = 0;
+        for (; tt + 1 < tn; tt += 2) {
+            step(xa0, xb0, xa1, xb1, tt + 2);
+            step(xa1, xb1, xa0, xb0, tt + 3);
+        }
+        if (tt < tn) step(xa0, xb0, xa1, xb1, tt + 2);
+        if (more) {
+            wave_lds_sync();
+            stA.store_qprof(bufA, JA, A, D, kRowBytes, t0 + C, l, bad);
+            stB.store_qprof(bufB, JB, A, D, kRowBytes, t0 + C, l, bad);
+            wave_lds_sync();
+        }
+    }
+    if (bad && P.validate) atomicOr(&P.flags[kFlagBadResidue], 1);
+
+    int lb[2] = {0, 0}, li[2] = {-1, -1}, lj[2] = {-1, -1};
+#pragma unroll
+    for (int p = 0; p < RP; ++p) {
+        const uint32_t ks[2] = {kA[p], kB[p]};
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int h = (int)(ks[q] >> 16) - (int)K;
+            const int row = l * R + 2 * p + ((ks[q] & 0x8000u) ? 0 : 1);
+            if (h > lb[q]) { lb[q] = h; li[q] = row; lj[q] = kColMax - (int)(ks[q] & 0x7FFFu); }
+        }
+    }
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+        for (int off = 1; off < W; off <<= 1) {
+            const int ob = __shfl_xor(lb[p], off);
+            const int oi = __shfl_xor(li[p], off);
+            const int oj = __shfl_xor(lj[p], off);
+            if (ob > lb[p] || (ob == lb[p] && oi < li[p])) { lb[p] = ob; li[p] = oi; lj[p] = oj; }
+        }
+    }
+    if (l == 0) {
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+            const int pair = p == 0 ? pairA : pairB;
+            if (pair < 0) continue;
+            sw_result res;
+            if (lb[p] > 0) { res.score = lb[p]; res.q_start = -1; res.q_end = li[p]; res.r_start = -1; res.r_end = lj[p]; }
+            else { res.score = 0; res.q_start = res.q_end = res.r_start = res.r_end = -1; }
+            P.out[pair] = res;
+        }
+    }
+}
+
 }  // namespace sw

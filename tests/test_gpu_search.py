@@ -80,3 +80,59 @@ def test_empty_and_too_long_queries(aligner):
     assert np.all(got == [0, -1, -1, -1, -1])
     with pytest.raises(SwError):
         run_search(aligner, s, np.zeros(2049, np.uint8))
+
+
+@pytest.mark.parametrize("n_q", [1, 7, 16, 100, 257, 400, 513, 1024, 1500, 2048])
+def test_query_profile_equals_pair_table_and_oracle(n_q):
+    """The forward pass of a protein search reads its scores from the query
+    profile (every query length routes to some shape, 16 to 64 lanes; above
+    512 rows the routing may pick cooperative groups, which keep the pair
+    table): the same bits as the pair-table path, and the oracle's on a
+    sample of pairs that includes the homologues."""
+    import torch
+    from paper_2208_12350_amd.binding import Aligner
+    s = W.make_search("search_protein", n_refs=2500, seed=600 + n_q)
+    rng = np.random.default_rng(n_q)
+    query = rng.integers(0, 20, size=n_q).astype(np.uint8)
+    query[:min(n_q, 400)] = s.query[:min(n_q, 400)]
+    dev = "cuda:0"
+    q = torch.from_numpy(query).to(dev)
+    r = torch.from_numpy(s.refs).to(dev)
+    ro = torch.from_numpy(s.r_off).to(dev)
+    outs = []
+    for qp in (1, 0):
+        al = Aligner(0, qprofile=qp)
+        try:
+            outs.append(al.search(q, r, ro, s.scheme).cpu().numpy().astype(np.int64))
+            if qp == 0:
+                assert al.get_option("qprofile_used") == 0
+            else:
+                used = al.get_option("qprofile_used")
+                assert used == 1
+                # the forward launches that ran: every one of them on a profile
+                # kernel, unless the shape is a cooperative group
+                fwd = [e for e in al.bin_stats() if e["pass"] == 0 and e["pairs"] > 0]
+                assert all(e["column"] == 3 or e["lanes"] > 64 for e in fwd)
+        finally:
+            al.close()
+    assert np.array_equal(outs[0], outs[1])
+    s2 = W.SearchSet(query, s.refs, s.r_off, s.scheme)
+    idx = np.union1d(np.arange(0, s.n_refs, 9), np.flatnonzero(s.homolog))
+    assert np.array_equal(outs[0][idx], oracle_rows(s2, idx))
+
+
+def test_dna_search_keeps_column_words():
+    """A DNA search takes the column-word path (no pair table, no profile)."""
+    import torch
+    from paper_2208_12350_amd.binding import Aligner
+    s = W.make_search("search_dna", n_refs=2000)
+    al = Aligner(0)
+    try:
+        dev = "cuda:0"
+        got = al.search(torch.from_numpy(s.query).to(dev), torch.from_numpy(s.refs).to(dev),
+                        torch.from_numpy(s.r_off).to(dev), s.scheme).cpu().numpy().astype(np.int64)
+        assert al.get_option("qprofile_used") == 0
+    finally:
+        al.close()
+    idx = np.arange(0, s.n_refs, 5)
+    assert np.array_equal(got[idx], oracle_rows(s, idx))

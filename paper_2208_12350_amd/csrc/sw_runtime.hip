@@ -281,6 +281,16 @@ static int find_bin(const sw_handle* h, int prec, int W, int R) {
 // rows go to cooperative 256-lane groups when they are compiled: their
 // per-pair latency is about four times shorter than a 64-lane group's, and
 // that latency bounds small batches and the tails of large ones.
+// The int32 routing uses six shapes of 64 to 2048 rows (doubling): int32
+// pairs are rare unless a call forces the precision (references above
+// kI16MaxRef, or scores past the packed range), and every bin a route uses
+// costs a launch per pass in every call, with work or without.
+static bool coarse_i32_shape(const BinInfo& e) {
+    const int rows = e.W * e.R;
+    return (e.W == 16 && (rows == 64 || rows == 128 || rows == 256)) ||
+           (e.W == 64 && (rows == 512 || rows == 1024 || rows == 2048));
+}
+
 static void default_routing(sw_handle* h, int sel) {
     const int prec = sel == 0 ? 16 : 32;
     for (int k = 0; k < kLutRows; ++k) {
@@ -295,6 +305,7 @@ static void default_routing(sw_handle* h, int sel) {
         for (int b = 0; b < (int)h->bins.size(); ++b) {
             const BinInfo& e = h->bins[b];
             if (e.prec != prec || e.W * e.R < rows || (e.W > 64) != coop) continue;
+            if (sel == 1 && !coarse_i32_shape(e)) continue;
             const double cost = (double)e.W * e.R * (m + e.W - 1);
             if (best < 0 || cost < best_cost || (cost == best_cost && e.W < h->bins[best].W)) {
                 best = b;
@@ -459,6 +470,15 @@ static int enqueue_pass(sw_handle* h, KParams K, const ClassifyArgs& C, const Wo
         // of the other streams.  Per-launch timing serialises them.
         const int forks = per_bin ? 0 : (int)h->opt_streams;
         int launched = 0;
+        // A bin's column-word items exist only when some scheme of the call
+        // takes column words, and its other items only when some scheme does
+        // not: the launches that cannot have work are left out (each one is
+        // a graph node, and every node delays the start of its branch).
+        bool any_col = false, all_col = true;
+        for (int s = 0; s < C.n_schemes; ++s) {
+            any_col |= C.col_ok[s] != 0;
+            all_col &= C.col_ok[s] != 0;
+        }
         if (forks > 1) {
             HIP_TRY(h, hipEventRecord(h->fork_ev[sw_handle::kForks], stream));
             for (int f = 0; f < forks; ++f)
@@ -471,6 +491,7 @@ static int enqueue_pass(sw_handle* h, KParams K, const ClassifyArgs& C, const Wo
             const int ipb = items_per_block(e.W);
             const int64_t need = (cap / e.ppw + 1 + ipb - 1) / ipb;
             for (int v = e.col ? 1 : 0; v >= 0; --v) {   // column-word kernel first
+                if (v == 1 ? !any_col : (e.col && all_col)) continue;
                 const int var = table_var(h, e, K, v);
                 const int nw = narrow_tile(h, e, var);
                 const int blocks = (int)std::min<int64_t>(need, h->resident_blocks[nw][pass][var][b]);

@@ -212,6 +212,10 @@ hipError_t launch_classify(const KParams& P, const ClassifyArgs& C, const int8_t
                            unsigned long long* counters, hipStream_t s);
 hipError_t launch_plan(const BinInfo* bins, int n_bins, int32_t* hist, int32_t* meta,
                        hipStream_t s);
+// The same plan for a score pass, one workgroup per bin, from the pass's
+// per-bin pair counters that launch_classify accumulates.
+hipError_t launch_plan_bins(const BinInfo* bins, int n_bins, int32_t* hist, int32_t* meta,
+                            const unsigned long long* counters, int reverse, hipStream_t s);
 hipError_t launch_scatter(const int32_t* keys, const int32_t* n_dev, int64_t cap, int32_t* hist,
                           int32_t* order, hipStream_t s);
 hipError_t launch_items(const int32_t* meta, const BinInfo* bins, int n_bins, const int32_t* n_dev,

@@ -229,6 +229,80 @@ __global__ __launch_bounds__(kPlanThreads) void sw_plan_kernel(const BinInfo* bi
     if (t < kMaxBins) meta[kMetaItemSplit + t] = meta[kMetaItemFirst + t] + my_col_items;
 }
 
+// Parallel form of the plan for the score passes, whose classify kernel
+// also counts every bin's pairs and column-path pairs (counters
+// kCtrBinPairs / kCtrBinColPairs of the pass): those counts are the sums of
+// the bin's histogram entries and of their first half, so every bin's
+// first sorted position, column split and work items follow from them
+// directly.  Workgroup b < kMaxBins scans bin b's kMBuckets entries in
+// place, offset by the pairs of bins 0..b-1 (a bin without pairs is left
+// as it is: no key of it occurs); workgroup kMaxBins writes the trivial
+// key's position and the metadata.  The result equals sw_plan_kernel's.
+constexpr int kBinScanThreads = 256;
+constexpr int kBinScanRun = kMBuckets / kBinScanThreads;
+
+__global__ __launch_bounds__(kBinScanThreads) void sw_plan_bins_kernel(const BinInfo* bins, int n_bins,
+                                                                        int32_t* hist, int32_t* meta,
+                                                                        const unsigned long long* counters,
+                                                                        int reverse) {
+    __shared__ int32_t s_pairs[kMaxBins], s_col[kMaxBins];
+    __shared__ int32_t wave_tot[kBinScanThreads / 64];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int slot0 = reverse ? kMaxBins : 0;
+    if (t < kMaxBins) {
+        const bool real = t < n_bins;
+        s_pairs[t] = real ? (int32_t)counters[kCtrBinPairs + slot0 + t] : 0;
+        s_col[t] = real && bins[t].col ? (int32_t)counters[kCtrBinColPairs + slot0 + t] : 0;
+    }
+    __syncthreads();
+    const int b = blockIdx.x;
+    if (b < kMaxBins) {
+        if (s_pairs[b] == 0) return;
+        int32_t base = 0;
+        for (int k = 0; k < b; ++k) base += s_pairs[k];
+        int32_t* hb = hist + b * kMBuckets + t * kBinScanRun;
+        int32_t v[kBinScanRun];
+        int32_t sum = 0;
+#pragma unroll
+        for (int k = 0; k < kBinScanRun; ++k) {
+            v[k] = hb[k];
+            sum += v[k];
+        }
+        const int32_t incl = wave_scan(sum, lane);
+        if (lane == 63) wave_tot[wave] = incl;
+        __syncthreads();
+        int32_t run = base + incl - sum;
+        for (int w = 0; w < wave; ++w) run += wave_tot[w];
+#pragma unroll
+        for (int k = 0; k < kBinScanRun; ++k) {
+            hb[k] = run;
+            run += v[k];
+        }
+        return;
+    }
+    // the metadata, as sw_plan_kernel writes it
+    if (t == 0) {
+        int32_t pos = 0, items = 0;
+        for (int k = 0; k < kMaxBins; ++k) {
+            meta[kMetaBinFirst + k] = pos;
+            meta[kMetaItemFirst + k] = items;
+            const int ppw = k < n_bins ? bins[k].ppw : 1;
+            const int32_t col_items = (s_col[k] + ppw - 1) / ppw;
+            meta[kMetaItemSplit + k] = items + col_items;
+            items += col_items + (s_pairs[k] - s_col[k] + ppw - 1) / ppw;
+            pos += s_pairs[k];
+        }
+        meta[kMetaBinFirst + kMaxBins] = pos;
+        meta[kMetaItemFirst + kMaxBins] = items;
+        hist[kTrivialKey] = pos;
+    }
+    if (t < kMaxBins) {
+        meta[kMetaHeads + t] = 0;
+        meta[kMetaColHeads + t] = 0;
+        meta[kMetaBinCol + t] = s_col[t];
+    }
+}
+
 __global__ void sw_scatter_kernel(const int32_t* keys, const int32_t* n_dev, int32_t* offs, int32_t* order) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= *n_dev) return;
@@ -315,6 +389,13 @@ hipError_t launch_classify(const KParams& P, const ClassifyArgs& C, const int8_t
 
 hipError_t launch_plan(const BinInfo* bins, int n_bins, int32_t* hist, int32_t* meta, hipStream_t s) {
     hipLaunchKernelGGL(sw_plan_kernel, dim3(1), dim3(kPlanThreads), 0, s, bins, n_bins, hist, meta);
+    return hipGetLastError();
+}
+
+hipError_t launch_plan_bins(const BinInfo* bins, int n_bins, int32_t* hist, int32_t* meta,
+                            const unsigned long long* counters, int reverse, hipStream_t s) {
+    hipLaunchKernelGGL(sw_plan_bins_kernel, dim3(kMaxBins + 1), dim3(kBinScanThreads), 0, s, bins, n_bins, hist,
+                       meta, counters, reverse);
     return hipGetLastError();
 }
 

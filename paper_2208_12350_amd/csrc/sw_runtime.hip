@@ -458,7 +458,7 @@ static int enqueue_pass(sw_handle* h, KParams K, const ClassifyArgs& C, const Wo
     const int n_bins = (int)h->bins.size();
     HIP_TRY(h, launch_reset(h->d_hist, kHistSize, stream));
     HIP_TRY(h, launch_classify(K, C, h->d_lut, h->d_bins, cap, ws.keys, h->d_hist, counters(h->d_small), stream));
-    HIP_TRY(h, launch_plan(h->d_bins, n_bins, h->d_hist, h->d_meta, stream));
+    HIP_TRY(h, launch_plan_bins(h->d_bins, n_bins, h->d_hist, h->d_meta, counters(h->d_small), pass, stream));
     HIP_TRY(h, launch_scatter(ws.keys, h->d_n, cap, h->d_hist, ws.order, stream));
     HIP_TRY(h, launch_items(h->d_meta, h->d_bins, n_bins, h->d_n, cap, ws.items, stream));
     const bool per_bin = timing && h->opt_timing == 2;

@@ -101,6 +101,7 @@ struct GraphKey {
     int32_t ptab_sid;
     int32_t qprof;
     int32_t qprof_n;       // a profile is built for this query length (a kernel argument)
+    int32_t search_n;      // every pair's query length (a search: one forward bin), or -1
 };
 
 }  // namespace
@@ -452,7 +453,7 @@ static int narrow_tile(const sw_handle* h, const BinInfo& e, int var) {
 // Enqueue one pass (planning + sweeps).  Plain mode synchronises `stream`
 // once to read the per-bin item counts.
 static int enqueue_pass(sw_handle* h, KParams K, const ClassifyArgs& C, const Workspace& ws, int pass,
-                        hipStream_t stream, bool timing) {
+                        hipStream_t stream, bool timing, int64_t search_n) {
     K.reverse = pass;
     const int64_t cap = ws.cap;
     const int n_bins = (int)h->bins.size();
@@ -484,8 +485,18 @@ static int enqueue_pass(sw_handle* h, KParams K, const ClassifyArgs& C, const Wo
             for (int f = 0; f < forks; ++f)
                 HIP_TRY(h, hipStreamWaitEvent(h->fork[f], h->fork_ev[sw_handle::kForks], 0));
         }
+        // In the forward pass of a search every pair has the query's length,
+        // so its pairs are in that length's int16 or int32 bin: only those
+        // two are launched.
+        int only16 = -1, only32 = -1;
+        const bool one_length = pass == 0 && search_n >= 1 && search_n <= SW_MAX_QUERY;
+        if (one_length) {
+            only16 = h->route[0][(search_n - 1) / 16];
+            only32 = h->route[1][(search_n - 1) / 16];
+        }
         for (int b = 0; b < n_bins; ++b) {
             if (!h->bin_used[b]) continue;
+            if (one_length && b != only16 && b != only32) continue;
             const BinInfo& e = h->bins[b];
             // no bin can hold more than cap / ppw items
             const int ipb = items_per_block(e.W);
@@ -889,7 +900,7 @@ static int submit_spans(sw_handle* h, const uint8_t* queries, const int64_t* q_b
                         const uint8_t* refs, const int64_t* r_beg, const int64_t* r_end,
                         const uint8_t* scheme_id, int64_t n_pairs, const sw_scheme* schemes,
                         int n_schemes, sw_result* out, void* stream_ptr, bool no_alloc, bool allow_timing,
-                        uint64_t* ticket, int64_t qprof_n = -1) {
+                        uint64_t* ticket, int64_t search_n = -1) {
     if (!h) return SW_EINVAL;
     h->err.clear();
     const auto t_entry = std::chrono::steady_clock::now();
@@ -1054,8 +1065,8 @@ static int submit_spans(sw_handle* h, const uint8_t* queries, const int64_t* q_b
     K.ptab_dim = D;
     // query profile: a search (every pair aligns queries[0 .. qprof_n)) with
     // the pair table's scheme profiles its query for the forward pass
-    K.qprof = (qprof_n >= 1 && qprof_n <= SW_MAX_QUERY && ptab_sid >= 0 && h->opt_qprof) ? 1 : 0;
-    K.qprof_n = K.qprof ? (int32_t)qprof_n : 0;
+    K.qprof = (search_n >= 1 && search_n <= SW_MAX_QUERY && ptab_sid >= 0 && h->opt_qprof) ? 1 : 0;
+    K.qprof_n = K.qprof ? (int32_t)search_n : 0;
     for (int s = 0; s < SW_MAX_SCHEMES; ++s) {
         const bool v = s < n_schemes;
         K.alphabet[s] = v ? schemes[s].alphabet : 1;
@@ -1082,6 +1093,7 @@ static int submit_spans(sw_handle* h, const uint8_t* queries, const int64_t* q_b
     key.ptab_sid = ptab_sid;
     key.qprof = K.qprof;
     key.qprof_n = K.qprof_n;
+    key.search_n = (int32_t)std::max<int64_t>(-1, std::min<int64_t>(search_n, SW_MAX_QUERY + 1));
 
     // Start of the call, in stream order and outside any graph: the scheme
     // tables when they differ from what the device holds (from this call's
@@ -1099,9 +1111,9 @@ static int submit_spans(sw_handle* h, const uint8_t* queries, const int64_t* q_b
     HIP_TRY(h, launch_call_start(h->d_small, kSmallInts, h->d_n, (int32_t)P, stream));
 
     auto enqueue_all = [&](hipStream_t es) -> int {
-        const int rc0 = enqueue_pass(h, K, C, ws, 0, es, timing);
+        const int rc0 = enqueue_pass(h, K, C, ws, 0, es, timing, search_n);
         if (rc0 != SW_OK) return rc0;
-        return enqueue_pass(h, K, C, ws, 1, es, timing);
+        return enqueue_pass(h, K, C, ws, 1, es, timing, search_n);
     };
     if (timing) h->bin_launched.assign(2 * kMaxBins * 2, 0);
     int gi = -1;
@@ -1228,11 +1240,11 @@ static int align_spans(sw_handle* h, const uint8_t* queries, const int64_t* q_be
                        const uint8_t* refs, const int64_t* r_beg, const int64_t* r_end,
                        const uint8_t* scheme_id, int64_t n_pairs, const sw_scheme* schemes,
                        int n_schemes, sw_result* out, void* stream_ptr, bool no_alloc = false,
-                       int64_t qprof_n = -1) {
+                       int64_t search_n = -1) {
     if (!h) return SW_EINVAL;
     uint64_t t = 0;
     const int rc = submit_spans(h, queries, q_beg, q_end, refs, r_beg, r_end, scheme_id, n_pairs, schemes,
-                                n_schemes, out, stream_ptr, no_alloc, true, &t, qprof_n);
+                                n_schemes, out, stream_ptr, no_alloc, true, &t, search_n);
     if (rc != SW_OK) return rc;
     const double enq = h->t_enqueue;
     const auto t0 = std::chrono::steady_clock::now();

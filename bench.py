@@ -619,18 +619,23 @@ def align_leg(args, workload, steps, warmup, with_cigar, with_cpu, full):
     out = torch.empty((batch.n_pairs, 5), dtype=torch.int32, device=dev)
 
     # routing autotuner (untimed): per-shape rates from probe launches, then
-    # the routing that minimises the predicted sweep time of a sample
+    # the routing that minimises the predicted sweep time of a sample; every
+    # call is told the batch's longest query (the library then launches no
+    # bin that only longer queries reach)
     tuning, tune_s = (args.routing if full else None), 0.0
+    bound = "max_query=%d" % int(batch.q_len().max()) if batch.n_pairs else ""
     if full and args.calibrate_copy:
         calibrate_copy(dev)
     if tuning is None and not args.no_tune:
         from paper_2208_12350_amd import autotune as T
         log("autotuning the routing ...")
         t_tune = time.time()
-        name, table, _, tile = T.tune_batch(batch, db, 0, log=log)
+        name, table, _, tile = T.tune_batch(batch, db, 0, log=log, options=bound)
         tuning = T.tuning_string(table, tile)
         tune_s = time.time() - t_tune
         log("  picked %s: %s (%.1f s)" % (name, tuning, tune_s))
+    if bound and "max_query=" not in (tuning or ""):
+        tuning = bound if tuning is None else tuning + ";" + bound
 
     def timed(al, n, warm, what):
         for k in range(warm):

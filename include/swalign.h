@@ -145,6 +145,11 @@ const char* sw_last_error(sw_handle* h);
  *               many streams forked from (and joined back into) the
  *               caller's stream (default 4; more than the process's
  *               hardware queues, GPU_MAX_HW_QUEUES, 4 by default, share them)
+   *   "max_query" 0 (default) or 1..SW_MAX_QUERY: the caller's bound on
+ *               query lengths.  Persistent mode then launches no bin that
+ *               only longer queries route to (each launch costs its stream
+ *               time even when its bin is empty); a pair with a longer
+ *               query makes the call return SW_ETOOLONG
  *   "cigar_workspace"  device bytes for the path records of sw_align_cigar
  *               (default 32 GiB, at least about 123 MB)
  * Returns SW_OK or SW_EINVAL for an unknown key / bad value. */

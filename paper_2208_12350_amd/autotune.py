@@ -257,16 +257,17 @@ def tuning_string(table: Table, tile: int = DEFAULT_TILE) -> str:
 
 
 def pick_by_timing(dbatch, tables: Dict[str, Table], device: int = 0, repeats: int = 2, log=None,
-                   tile: int = DEFAULT_TILE):
+                   tile: int = DEFAULT_TILE, options: str = ""):
     """Time one call per repeat of each routing (with reference tiles of
-    `tile` steps) on the batch itself (graph replay, the headline
-    configuration) and return (name, table, ms)."""
+    `tile` steps, and the further tuning-string `options`) on the batch
+    itself (graph replay, the headline configuration) and return (name,
+    table, ms)."""
     import torch
     from .binding import Aligner
     out = torch.empty((dbatch.n_pairs, 5), dtype=torch.int32, device="cuda:%d" % device)
     best = None
     for name, table in tables.items():
-        al = Aligner(device, tuning_string(table, tile))
+        al = Aligner(device, tuning_string(table, tile) + (";" + options if options else ""))
         try:
             al.align(dbatch, out)
             torch.cuda.synchronize()
@@ -285,12 +286,14 @@ def pick_by_timing(dbatch, tables: Dict[str, Table], device: int = 0, repeats: i
     return best
 
 
-def tune_batch(batch, dbatch, device: int = 0, sample: int = 50000, repeats: int = 7, seed: int = 5, log=None):
+def tune_batch(batch, dbatch, device: int = 0, sample: int = 50000, repeats: int = 7, seed: int = 5, log=None,
+               options: str = ""):
     """The routing a batch is timed with: shape rates measured on the batch's
     dominant scheme at its median reference length, the candidate tables of
     a seeded sample of its pairs, the fastest of them on the batch itself
     (median of `repeats` graph-replayed calls each), then the faster tile
-    width for it.  Returns (name, table, candidates, tile)."""
+    width for it; the calls are timed with the tuning-string `options`.
+    Returns (name, table, candidates, tile)."""
     from .binding import Aligner
     rng = np.random.default_rng(seed)
     idx = rng.choice(batch.n_pairs, size=min(batch.n_pairs, sample), replace=False)
@@ -303,12 +306,13 @@ def tune_batch(batch, dbatch, device: int = 0, sample: int = 50000, repeats: int
     finally:
         probe.close()
     cands = candidate_tables(ql, rl, rates, list(rates), builtin=builtin)
-    name, table, ms = pick_by_timing(dbatch, cands, device, repeats=repeats, log=log)
+    name, table, ms = pick_by_timing(dbatch, cands, device, repeats=repeats, log=log, options=options)
     tile = DEFAULT_TILE
     for t in TILES:
         if t == DEFAULT_TILE:
             continue
-        _, _, ms_t = pick_by_timing(dbatch, {name: table}, device, repeats=repeats, log=log, tile=t)
+        _, _, ms_t = pick_by_timing(dbatch, {name: table}, device, repeats=repeats, log=log, tile=t,
+                                    options=options)
         if ms_t < ms:
             tile, ms = t, ms_t
     return name, table, cands, tile

@@ -174,6 +174,7 @@ struct ClassifyArgs {
     int32_t i16_limit;      // negative disables the int16 path
     int32_t n_schemes;
     int32_t n_bins;
+    int32_t max_query;      // 0, or the caller's bound on query lengths (longer: kFlagTooLong)
 };
 
 }  // namespace sw

@@ -58,7 +58,8 @@ __global__ void sw_classify_kernel(KParams P, ClassifyArgs C, const int8_t* lut,
             s = P.scheme_id ? (int)P.scheme_id[i] : 0;
             if (n < 0 || m < 0) atomicOr(&P.flags[kFlagBadOffsets], 1);
             else if (s >= C.n_schemes) atomicOr(&P.flags[kFlagBadScheme], 1);
-            else if (n > SW_MAX_QUERY || m > SW_MAX_REF) atomicOr(&P.flags[kFlagTooLong], 1);
+            else if (n > SW_MAX_QUERY || m > SW_MAX_REF || (C.max_query > 0 && n > C.max_query))
+                atomicOr(&P.flags[kFlagTooLong], 1);
             else ok = n > 0 && m > 0;
             if (!ok) {
                 sw_result z;

@@ -102,6 +102,7 @@ struct GraphKey {
     int32_t qprof;
     int32_t qprof_n;       // a profile is built for this query length (a kernel argument)
     int32_t search_n;      // every pair's query length (a search: one forward bin), or -1
+    int32_t max_query;     // the max_query option (bins above it are not launched)
 };
 
 }  // namespace
@@ -116,6 +117,8 @@ struct sw_handle {
     int64_t opt_precision = 0;
     int64_t opt_timing = 0;
     int64_t opt_streams = 4;
+    int64_t opt_max_query = 0;          // 0, or the caller's bound on query lengths
+    std::vector<int> bin_min_query;     // per bin: the shortest query any route sends to it
     int64_t opt_colpath = 1;
 
     std::vector<BinInfo> bins;
@@ -320,11 +323,15 @@ static void default_routing(sw_handle* h, int sel) {
 static void rebuild_lut(sw_handle* h) {
     h->lut.assign(kLutEntries, -1);
     h->bin_used.assign(h->bins.size(), 0);
+    h->bin_min_query.assign(h->bins.size(), SW_MAX_QUERY + 1);
     for (int sel = 0; sel < 2; ++sel)
         for (int k = 0; k < kLutRows; ++k) {
             const int b = h->route[sel][k];
             h->lut[sel * kLutRows + k] = (int8_t)b;
-            if (b >= 0) h->bin_used[b] = 1;
+            if (b >= 0) {
+                h->bin_used[b] = 1;
+                h->bin_min_query[b] = std::min(h->bin_min_query[b], 16 * k + 1);
+            }
         }
     h->lut_dirty = true;
 }
@@ -497,6 +504,7 @@ static int enqueue_pass(sw_handle* h, KParams K, const ClassifyArgs& C, const Wo
         for (int b = 0; b < n_bins; ++b) {
             if (!h->bin_used[b]) continue;
             if (one_length && b != only16 && b != only32) continue;
+            if (h->opt_max_query > 0 && h->bin_min_query[b] > h->opt_max_query) continue;
             const BinInfo& e = h->bins[b];
             // no bin can hold more than cap / ppw items
             const int ipb = items_per_block(e.W);
@@ -762,6 +770,9 @@ int sw_set_option(sw_handle* h, const char* key, int64_t value) {
         const int rc = ensure_pairs(h, value);
         if (rc != SW_OK) return rc;
         return SW_OK;
+    } else if (k == "max_query") {
+        if (value < 0 || value > SW_MAX_QUERY) return fail(h, SW_EINVAL, "max_query must be 0..%d", SW_MAX_QUERY);
+        h->opt_max_query = value;
     } else if (k == "streams") {
         if (value < 1 || value > sw_handle::kForks) return fail(h, SW_EINVAL, "streams must be 1..%d", sw_handle::kForks);
         h->opt_streams = value;
@@ -791,6 +802,7 @@ int sw_get_option(sw_handle* h, const char* key, int64_t* value) {
     else if (k == "precision") *value = h->opt_precision;
     else if (k == "timing") *value = h->opt_timing;
     else if (k == "streams") *value = h->opt_streams;
+    else if (k == "max_query") *value = h->opt_max_query;
     else if (k == "capacity") *value = h->cap_pairs;
     else if (k == "colpath") *value = h->opt_colpath;
     else if (k == "chunk") *value = h->opt_chunk;
@@ -867,7 +879,8 @@ static int complete_slot(sw_handle* h, int k) {
     if (flags[kFlagBadOffsets]) return fail(h, SW_EINVAL, "offsets decrease");
     if (flags[kFlagBadScheme]) return fail(h, SW_EINVAL, "scheme id out of range");
     if (flags[kFlagTooLong])
-        return fail(h, SW_ETOOLONG, "a query exceeds %d or a reference exceeds %d residues", SW_MAX_QUERY, SW_MAX_REF);
+        return fail(h, SW_ETOOLONG, "a query exceeds %d or a reference exceeds %d residues",
+                    h->opt_max_query > 0 ? (int)h->opt_max_query : SW_MAX_QUERY, SW_MAX_REF);
     if (flags[kFlagBadResidue]) return fail(h, SW_EINVAL, "residue code outside its scheme's alphabet");
     if (flags[kFlagInternal]) return fail(h, SW_EINTERNAL, "a planning invariant did not hold");
     if (flags[kFlagReverseMismatch]) return fail(h, SW_EINTERNAL, "reverse sweep did not reproduce the forward score");
@@ -1017,6 +1030,7 @@ static int submit_spans(sw_handle* h, const uint8_t* queries, const int64_t* q_b
     C.i16_limit = h->opt_precision == 32 ? -1 : kI16Limit;
     C.n_schemes = n_schemes;
     C.n_bins = (int)h->bins.size();
+    C.max_query = (int32_t)h->opt_max_query;
 
     // Pair table: when exactly one scheme of the call takes table lookups
     // (every other one takes column words), the packed int16 table-range
@@ -1094,6 +1108,7 @@ static int submit_spans(sw_handle* h, const uint8_t* queries, const int64_t* q_b
     key.qprof = K.qprof;
     key.qprof_n = K.qprof_n;
     key.search_n = (int32_t)std::max<int64_t>(-1, std::min<int64_t>(search_n, SW_MAX_QUERY + 1));
+    key.max_query = C.max_query;
 
     // Start of the call, in stream order and outside any graph: the scheme
     // tables when they differ from what the device holds (from this call's

@@ -180,6 +180,34 @@ def test_mixed_sample_two_schemes(aligner):
     assert_same(run_gpu(aligner, b), O.align_batch(b), b)
 
 
+def test_max_query_bound():
+    """The max_query option leaves the bins above the bound unlaunched:
+    the results are the oracle's, the same with the option and without,
+    and a batch with a longer query is rejected (SW_ETOOLONG), after which
+    the handle works again."""
+    from paper_2208_12350_amd.binding import Aligner, SwError, SW_ETOOLONG
+    b = W.make_workload("protein", n_pairs=2000, seed=41)
+    longest = int(b.q_len().max())
+    plain = Aligner(0)
+    bound = Aligner(0, max_query=longest)
+    try:
+        assert bound.get_option("max_query") == longest
+        g = run_gpu(plain, b)
+        assert_same(g, O.align_batch(b), b)
+        assert np.array_equal(run_gpu(bound, b), g)
+        bound.set_option("max_query", longest - 1)
+        with pytest.raises(SwError) as ei:
+            run_gpu(bound, b)
+        assert ei.value.code == SW_ETOOLONG
+        bound.set_option("max_query", 0)
+        assert np.array_equal(run_gpu(bound, b), g)
+        with pytest.raises(SwError):
+            bound.set_option("max_query", 2049)
+    finally:
+        plain.close()
+        bound.close()
+
+
 def test_repeatable_and_order_invariant(aligner):
     b = W.make_workload("dna_small", n_pairs=700, seed=99)
     g1 = run_gpu(aligner, b)

@@ -42,11 +42,14 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def stored_traffic(kernel, workload, sources_sha256=None):
+def stored_traffic(kernel, workload, sources_sha256=None, cells_per_launch=None):
     """HBM bytes per launch of `kernel` on `workload` from a committed
     counter summary (profiles/*_traffic.txt), or None when there is none or
     when the kernel sources (digest `sources_sha256`, by default that of the
-    sweep kernels) changed since the counters were taken."""
+    sweep kernels) changed since the counters were taken.  With
+    `cells_per_launch` the stored bytes are rescaled by this run's cells per
+    launch against the profiled run's (a routing the tuner picks anew may
+    give the kernel a different share of the pairs; its bytes per cell stay)."""
     import glob
     import hashlib
     here = os.path.join(ROOT, "profiles")
@@ -57,13 +60,16 @@ def stored_traffic(kernel, workload, sources_sha256=None):
                 if ":" in line and not line.startswith("#"):
                     k, v = line.split(":", 1)
                     kv[k.strip()] = v.strip()
-        if kv.get("kernel") != kernel or kv.get("workload") != workload:
+        if kv.get("kernel", "").replace("sw::", "") != kernel.replace("sw::", "") or kv.get("workload") != workload:
             continue
         if kv.get("sources_sha256") != (sources_sha256 or kernel_sources_sha256()):
             return None
         try:
-            return float(kv["traffic_bytes_per_launch"])
-        except (KeyError, ValueError):
+            per_launch = float(kv["traffic_bytes_per_launch"])
+            if cells_per_launch:
+                per_launch *= float(cells_per_launch) / float(kv["cells_per_launch"])
+            return round(per_launch)
+        except (KeyError, ValueError, ZeroDivisionError):
             return None
     return None
 
@@ -173,7 +179,7 @@ def roofline_leg(args, db, out, tuning, mode, workload, steps):
             dprec, dlanes, drows, direction, "true" if dcol else "false", dtile)
     return {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 2),
             "unit": "Tops/s", "frac": round(achieved / peak, 4),
-            "traffic": stored_traffic(kernel_name, workload),
+            "traffic": stored_traffic(kernel_name, workload, cells_per_launch=cells_per_launch),
             "kernel": kernel_name, "launches": dn, "launch_ms": round(launch_ms, 4),
             "cells_per_launch": int(cells_per_launch), "ops_per_cell": OPS_PER_CELL,
             "all_sweeps": {"ms": round(fam_ms, 3), "achieved": round(fam_ops / (fam_ms / 1e3) / 1e12, 3),
@@ -226,7 +232,7 @@ def cigar_leg(args, db, out, ref_out, tuning, score_ms, workload):
             "sweep_ms": round(float(np.mean(sweep_ms)), 3), "walk_ms": round(float(np.mean(walk_ms)), 3),
             "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 2),
                          "unit": "Tops/s", "frac": round(achieved / peak, 4),
-                         "traffic": stored_traffic(kernel_name, workload),
+                         "traffic": stored_traffic(kernel_name, workload, cells_per_launch=dcells / launches),
                          "kernel": kernel_name, "launches": launches,
                          "launch_ms": round(dms / launches, 4),
                          "cells_per_launch": int(dcells / launches),

@@ -89,3 +89,29 @@ def test_stencil_library_exports_and_rejects_bad_arguments():
     assert L.sw_diffuse_padded(1, 2, 4, 4, 6, 1.5, None) == -1            # D outside [0, 1]
     assert L.sw_diffuse_checked(1, 2, 0, 4, 0.5, None) == -1
     assert L.sw_pad_grid(1, 2, 4, 4, 3, None) == -1
+
+
+def test_bench_reads_committed_traffic_summaries():
+    """bench.py takes roofline.traffic from the committed counter summaries:
+    the dominant kernel of each summary is found under its profiled name
+    (with or without the namespace), rescaled to another run's cells per
+    launch, and ignored once the kernel sources no longer match."""
+    import glob
+    import bench
+    paths = sorted(glob.glob(os.path.join(ROOT, "profiles", "sweep_*_traffic.txt")))
+    assert paths
+    for path in paths:
+        kv = {}
+        for line in open(path):
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+        kernel, workload = kv["kernel"], kv["workload"]
+        per_launch = float(kv["traffic_bytes_per_launch"])
+        cells = float(kv["cells_per_launch"])
+        sha = kv["sources_sha256"]
+        assert bench.stored_traffic(kernel, workload, sha) == round(per_launch)
+        assert bench.stored_traffic(kernel.replace("sw::", ""), workload, sha) == round(per_launch)
+        assert bench.stored_traffic(kernel, workload, sha, cells_per_launch=cells / 2) == round(per_launch / 2)
+        assert bench.stored_traffic(kernel, workload, "0" * 64) is None
+        assert bench.stored_traffic(kernel, "no_such_workload", sha) is None

@@ -137,10 +137,12 @@ def cpu_baseline(batch, target_s=12.0, single_s=4.0):
 
 
 def roofline_leg(args, db, out, tuning, mode, workload, steps):
-    """The sweep launches serialised on one stream with a HIP event pair
-    around each (library option timing=2) and cells per launch from the
-    device counters.  The dominant kernel is the (pass, shape) launch with
-    the most device time; achieved = 12 * its cells / its average time."""
+    """The sweep launches as the timed call issues them (one kernel per
+    shape family, or per bin), serialised on one stream with a HIP event
+    pair around each (library option timing=2), and cells per launch from
+    the device counters of the bins each launch swept.  The dominant kernel
+    is the launch with the most device time; achieved = 12 * its cells / its
+    average time."""
     from paper_2208_12350_amd.binding import Aligner
     alr = Aligner(0, tuning, mode=mode, graph=0, timing=2)
     per_launch = {}
@@ -148,12 +150,21 @@ def roofline_leg(args, db, out, tuning, mode, workload, steps):
     for k in range(roof_steps + 1):
         alr.align(db, out)
         if k:
+            launches = {}
             for e in alr.bin_stats():
-                key = (e["pass"], e["precision"], e["lanes"], e["rows"], e["column"], e["tile"])
+                if e["launch"] < 0:
+                    continue
+                # the bins of a family launch share its launch index and time
+                fam = (e["family_hi"], e["family_lo"]) if e["family_hi"] else (e["rows"], 0)
+                key = (e["pass"], e["precision"], e["lanes"], fam, e["column"], e["tile"])
+                acc = launches.setdefault((e["pass"], e["launch"]), [key, e["ms"], 0])
+                acc[2] += e["cells"]
+            for key, ms, cells in launches.values():
                 acc = per_launch.setdefault(key, [0.0, 0, 0])
-                acc[0] += e["ms"]; acc[1] += e["cells"]; acc[2] += 1
+                acc[0] += ms; acc[1] += cells; acc[2] += 1
     alr.close()
-    (dpass, dprec, dlanes, drows, dcol, dtile), (dms, dcells, dn) = max(per_launch.items(), key=lambda kv: kv[1][0])
+    (dpass, dprec, dlanes, (drows, dlo), dcol, dtile), (dms, dcells, dn) = max(per_launch.items(),
+                                                                              key=lambda kv: kv[1][0])
     launch_ms = dms / dn
     cells_per_launch = dcells / dn
     peak = VALU_INT16X2_TOPS if dprec == 16 else VALU_INT32_TOPS
@@ -164,7 +175,11 @@ def roofline_leg(args, db, out, tuning, mode, workload, steps):
     fam_peak_s = sum(OPS_PER_CELL * v[1] / roof_steps / ((VALU_INT16X2_TOPS if k[1] == 16 else VALU_INT32_TOPS) * 1e12)
                      for k, v in per_launch.items())
     direction = "true" if dpass else "false"
-    if dlanes > 64:
+    if dlo:
+        # family kernel: <precision, lanes, reverse, score source, rows largest first>
+        kernel_name = "sw::sw_family_kernel<%d, %d, %s, %d, %s>" % (
+            dprec, dlanes, direction, dcol, ", ".join(str(r) for r in range(drows, dlo - 1, -1)))
+    elif dlanes > 64:
         kernel_name = "sw::sw_coop_kernel<%d, %s>" % (drows, direction)
     elif dcol == 3:
         kernel_name = "sw::sw_qprof_kernel<%d, %d>" % (dlanes, drows)

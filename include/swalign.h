@@ -145,7 +145,12 @@ const char* sw_last_error(sw_handle* h);
  *               many streams forked from (and joined back into) the
  *               caller's stream (default 4; more than the process's
  *               hardware queues, GPU_MAX_HW_QUEUES, 4 by default, share them)
-   *   "max_query" 0 (default) or 1..SW_MAX_QUERY: the caller's bound on
+ *   "families"  1 (default) = persistent mode with the default tile launches,
+ *               per pass and score source, one kernel for each family of
+ *               compiled shapes (a lane width and a run of rows per lane)
+ *               that takes the items of all its routed bins; 0 = one launch
+ *               per bin
+ *   "max_query" 0 (default) or 1..SW_MAX_QUERY: the caller's bound on
  *               query lengths.  Persistent mode then launches no bin that
  *               only longer queries route to (each launch costs its stream
  *               time even when its bin is empty); a pair with a longer
@@ -336,12 +341,13 @@ int sw_set_routing(sw_handle* h, int precision, const int32_t* rows_max, const i
 int sw_get_routing(sw_handle* h, int precision, int32_t* rows_max, int32_t* lanes, int32_t* rows, int capacity,
                    int* n_out);
 
-/* One sweep kernel launch of the last call: the bin of pairs of one shape
+/* The pairs of one bin of the last call: the pairs of one shape
  * (precision, lanes per pair group, query rows per lane) in one pass, and of
- * one score source (column words for small alphabets, or table lookups).
- * A work item straddling a bin's column/table boundary runs in the table
- * kernel, so up to (pairs per item - 1) column-path pairs of a bin may be
- * counted against the column entry but swept by the table kernel. */
+ * one score source (column words for small alphabets, or table lookups),
+ * with the kernel launch that swept them.  A family launch (option
+ * "families") sweeps several bins of one lane width with one kernel: those
+ * bins share `launch` and `ms`, so per-launch figures group the entries by
+ * (pass, launch). */
 typedef struct sw_bin_stat {
     int32_t pass;        /* 0 forward, 1 reverse, 2 path boxes (sw_align_cigar) */
     int32_t precision;   /* 16 (two pairs packed per register) or 32 */
@@ -349,10 +355,15 @@ typedef struct sw_bin_stat {
     int32_t rows;        /* query rows held by each lane */
     int64_t pairs;       /* pairs the bin held in this pass */
     int64_t cells;       /* DP cells of those pairs in this pass */
-    float ms;            /* kernel time (HIP events) with "timing" = 2, else 0 */
+    float ms;            /* time of the launch that swept the bin (HIP events) with
+                            "timing" = 2, else 0 */
     int32_t column;      /* 1 = the column-word kernel, 0 = the table-lookup kernel,
                             2 = the pair-table kernel, 3 = the query-profile kernel */
     int32_t tile;        /* reference steps per LDS tile of the kernel (option "chunk") */
+    int32_t launch;      /* index of that launch within its pass (the last enqueued
+                            call's; a replayed graph repeats its capture's), -1 if none */
+    int32_t family_hi;   /* family launch: the largest and smallest rows per lane of */
+    int32_t family_lo;   /* the family's shapes; 0 for a launch of one shape */
 } sw_bin_stat;
 
 /* Per-launch statistics of the last call on this handle: writes up to

@@ -57,6 +57,10 @@ __host__ __device__ inline int m_bucket(int m) {
     return b < kMHalf ? b : kMHalf - 1;
 }
 
+// Most shapes one family kernel serves (one lane width, a run of rows per
+// lane).
+constexpr int kFamilyMax = 12;
+
 struct BinInfo {
     uint8_t prec;     // 16 = two pairs per lane group packed in int16 halves, 32 = int32
     uint8_t R;        // query rows per lane
@@ -144,6 +148,7 @@ struct KParams {
     int32_t ptab_dim;            // its D = alphabet + 1
     int32_t qprof;               // 1: the forward pass may use the query profile of queries[0 .. qprof_n)
     int32_t qprof_n;
+    int8_t fam_bins[kFamilyMax];   // family launch: member k's bin, or -1 (not launched)
 };
 
 enum : int32_t {
@@ -197,6 +202,12 @@ enum : int { kVarTable = 0, kVarCol = 1, kVarPtab = 2, kVarQprof = 3, kNumVars =
 // The kernel of a compiled shape for one score source, with the default or
 // the narrow reference tile (nullptr when the shape has no such variant).
 QueueFn shape_kernel(int prec, int W, int R, bool reverse, int var = kVarTable, bool narrow = false);
+// The family that serves shape (prec, W, R) with the default tile, or null:
+// `rows[0..n)` are its members' rows per lane, largest first (the order of
+// KParams::fam_bins), and k[var][reverse] its kernels (kVarTable, kVarCol,
+// kVarPtab; null where there is none).
+struct FamilyEntry { int prec, W, n; int rows[kFamilyMax]; QueueFn k[3][2]; };
+const FamilyEntry* shape_family(int prec, int W, int R);
 const ShapeDesc* compiled_shapes(int* n);
 
 hipError_t launch_reset(int32_t* p, int n, hipStream_t s);

@@ -17,6 +17,8 @@
 // flag and the work is skipped rather than indexed.
 #pragma once
 
+#include <type_traits>
+
 #include "sw_sweep.h"
 
 namespace sw {
@@ -24,14 +26,16 @@ namespace sw {
 // The work-queue loop of one wavefront: claim items of the launch's range
 // and sweep each with `sweep(first, count)`.
 template <int kPPW, class Sweep>
-__device__ __forceinline__ void queue_loop(const KParams& P, int lane, int lo, int hi, int n_pairs, Sweep&& sweep) {
+__device__ __forceinline__ void queue_loop(const KParams& P, int lane, int lo, int hi, int n_pairs, Sweep&& sweep,
+                                           int head_idx = -1) {
+    if (head_idx < 0) head_idx = P.head_idx;
     // The loop has no lane-divergent branch: every lane takes part in the
     // fetch (only lane 0 adds 1, so each wavefront claims exactly one item
     // whether or not the lanes' atomics are merged), and the item index is
     // lane 0's return value.  A lane-0-only atomic inside this loop was
     // lowered into an inner loop that re-entered without the fetch.
     for (;;) {
-        const int mine = atomicAdd(&P.meta[P.head_idx], lane == 0 ? 1 : 0);
+        const int mine = atomicAdd(&P.meta[head_idx], lane == 0 ? 1 : 0);
         const int it = __builtin_amdgcn_readlane(mine, 0);
         if (it >= hi - lo) break;
         const WorkItem* wp = P.items + lo + it;
@@ -191,9 +195,78 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
     });
 }
 
+// ---- family kernels ----------------------------------------------------------
+// A family kernel serves a run of shapes of one precision and lane width
+// (rows per lane Rs..., largest first): it drains the queue of member k's
+// bin (P.fam_bins[k]; -1: not launched), then member k+1's, each with the
+// sweep compiled for that member.  One launch per pass thus takes the items
+// of every member bin, and a wavefront whose bin runs dry moves on to the
+// next instead of idling until the launch ends.  The members follow one
+// another (no loop around them), so each member's loop-invariant values are
+// live only while it runs and the register allocation is about that of the
+// largest member.
+template <int PREC, int W, int R, bool REV, int VAR, class Lds>
+__device__ __forceinline__ void family_member(const KParams& P, Lds& L, uint16_t* wbuf, int lane, int bin,
+                                              int n_pairs) {
+    constexpr int kPPW = (64 / W) * (PREC == 16 ? 2 : 1);
+    if (bin < 0) return;
+    const int lo_i = VAR == kVarCol ? kMetaItemFirst + bin : kMetaItemSplit + bin;
+    const int hi_i = VAR == kVarCol ? kMetaItemSplit + bin : kMetaItemFirst + bin + 1;
+    const int lo = __builtin_amdgcn_readfirstlane(__atomic_load_n(&P.meta[lo_i], __ATOMIC_RELAXED));
+    const int hi = __builtin_amdgcn_readfirstlane(__atomic_load_n(&P.meta[hi_i], __ATOMIC_RELAXED));
+    if (lo >= hi) return;
+    if (lo < 0 || hi > P.max_items) {
+        atomicOr(&P.flags[kFlagInternal], 1);
+        return;
+    }
+    queue_loop<kPPW>(P, lane, lo, hi, n_pairs, [&](int first, int count) {
+        if constexpr (VAR == kVarPtab)
+            sweep_i16_ptab<W, R, REV, kChunk>(P, L, wbuf, first, count, lane);
+        else if constexpr (VAR == kVarCol)
+            sweep_i16_col<W, R, REV, kChunk>(P, L, wbuf, first, count, lane);
+        else if constexpr (PREC == 16)
+            sweep_i16<W, R, REV, kChunk>(P, L, wbuf, first, count, lane);
+        else
+            sweep_i32<W, R, REV, kChunk>(P, L, wbuf, first, count, lane);
+    }, (VAR == kVarCol ? kMetaColHeads : kMetaHeads) + bin);
+}
+
+template <int... Rs>
+constexpr int family_size() { return (int)sizeof...(Rs); }
+
+template <int PREC, int W, bool REV, int VAR, int... Rs>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void sw_family_kernel(KParams P) {
+    static_assert(sizeof...(Rs) <= kFamilyMax, "family too large");
+    using Lds = typename std::conditional<VAR == kVarPtab, PtabLds, SchemeLds>::type;
+    __shared__ __attribute__((aligned(16))) Lds L;
+    __shared__ uint16_t wbufs[kWavesPerBlock * kWaveBuf];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if constexpr (VAR == kVarPtab) {
+        if (P.ptab_sid < 0 || P.ptab_sid >= SW_MAX_SCHEMES || P.ptab_dim < 2 || P.ptab_dim > kPtabMaxDim) {
+            if (tid == 0) atomicOr(&P.flags[kFlagInternal], 1);
+            return;
+        }
+        load_ptab(L, P, tid);
+    } else {
+        load_schemes(L, P, tid);
+    }
+    const int n_pairs = __builtin_amdgcn_readfirstlane(*P.n_dev);
+    __syncthreads();
+    uint16_t* wbuf = wbufs + wave * kWaveBuf;
+    int k = 0;
+    ((family_member<PREC, W, Rs, REV, VAR, Lds>(P, L, wbuf, lane, P.fam_bins[k++], n_pairs)), ...);
+}
+
+#define SW_FAMILY16(W, ...)                                                                                   \
+    {16, W, family_size<__VA_ARGS__>(), {__VA_ARGS__},                                                        \
+     {{&sw_family_kernel<16, W, false, kVarTable, __VA_ARGS__>, &sw_family_kernel<16, W, true, kVarTable, __VA_ARGS__>}, \
+      {&sw_family_kernel<16, W, false, kVarCol, __VA_ARGS__>, &sw_family_kernel<16, W, true, kVarCol, __VA_ARGS__>},     \
+      {&sw_family_kernel<16, W, false, kVarPtab, __VA_ARGS__>, &sw_family_kernel<16, W, true, kVarPtab, __VA_ARGS__>}}}
+
 // Per tile width (index 0: kChunk, 1: kChunkNarrow) and score source
 // (kVarTable, kVarCol, kVarPtab): the forward and reverse kernels, null
 // where a shape has no such variant.
 struct KernelEntry { int prec, W, R; QueueFn k[2][kNumVars][2]; };
 
 }  // namespace sw
+

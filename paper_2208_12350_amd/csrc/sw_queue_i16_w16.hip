@@ -27,4 +27,8 @@ const KernelEntry kI16W16Kernels[] = {
 #undef SW_ENTRY
 const int kNumI16W16Kernels = sizeof(kI16W16Kernels) / sizeof(kI16W16Kernels[0]);
 
+// One launch per pass and score source serves every shape of this file.
+extern const FamilyEntry kI16W16Family;
+const FamilyEntry kI16W16Family = SW_FAMILY16(16, 8, 7, 6, 5, 4, 3, 2, 1);
+
 }  // namespace sw

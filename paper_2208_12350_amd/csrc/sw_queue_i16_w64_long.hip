@@ -21,4 +21,8 @@ const KernelEntry kI16W64LongKernels[] = {
 #undef SW_ENTRY
 const int kNumI16W64LongKernels = sizeof(kI16W64LongKernels) / sizeof(kI16W64LongKernels[0]);
 
+// One launch per pass and score source serves every shape of this file.
+extern const FamilyEntry kI16W64LongFamily;
+const FamilyEntry kI16W64LongFamily = SW_FAMILY16(64, 32, 31, 30, 29, 28, 27, 26, 25, 24, 23, 22, 21);
+
 }  // namespace sw

@@ -31,6 +31,12 @@ extern const KernelEntry kI16W64LongKernels[];
 extern const int kNumI16W64LongKernels;
 extern const KernelEntry kI16W256Kernels[];
 extern const int kNumI16W256Kernels;
+extern const FamilyEntry kI16W16Family;
+extern const FamilyEntry kI16W16bFamily;
+extern const FamilyEntry kI16W32Family;
+extern const FamilyEntry kI16W32bFamily;
+extern const FamilyEntry kI16W64Family;
+extern const FamilyEntry kI16W64LongFamily;
 
 namespace {
 
@@ -65,6 +71,16 @@ const ShapeDesc* compiled_shapes(int* n) {
     }
     *n = g_nshapes;
     return g_shapes;
+}
+
+const FamilyEntry* shape_family(int prec, int W, int R) {
+    const FamilyEntry* fams[] = {&kI16W16Family, &kI16W16bFamily, &kI16W32Family,
+                                 &kI16W32bFamily, &kI16W64Family, &kI16W64LongFamily};
+    for (const FamilyEntry* f : fams)
+        if (f->prec == prec && f->W == W)
+            for (int k = 0; k < f->n; ++k)
+                if (f->rows[k] == R) return f;
+    return nullptr;
 }
 
 QueueFn shape_kernel(int prec, int W, int R, bool reverse, int var, bool narrow) {

@@ -127,6 +127,8 @@ struct sw_handle {
     std::vector<char> bin_used;         // bins some route points at
     bool lut_dirty = true;
     std::vector<int> resident_blocks[2][2][kNumVars];   // per tile, pass, score source and bin: workgroups the device holds at once
+    std::vector<std::pair<QueueFn, int>> fam_resident;  // per family kernel: workgroups the device holds at once
+    int64_t opt_families = 1;
     int64_t opt_chunk = kChunk;         // reference tile of 16- and 32-lane packed shapes: kChunk or kChunkNarrow
     int64_t opt_ptab = 1;
     int64_t opt_qprof = 1;
@@ -182,6 +184,13 @@ struct sw_handle {
     // per (pass, bin) event pairs for "timing" = 2, created on first use
     std::vector<hipEvent_t> bin_ev;
     std::vector<char> bin_launched;     // per (pass, bin, variant) of the last call
+    // per (pass, bin, variant) of the last enqueued call: the launch that
+    // swept the bin (index within its pass, or -1), the family of a family
+    // launch (rows per lane of its first and last shape, else 0) and its
+    // event slot ("timing" = 2)
+    static constexpr int kFamLaunches = 16;
+    std::vector<int32_t> bin_launch, bin_fam_hi, bin_fam_lo, bin_fam_slot;
+    std::vector<hipEvent_t> fam_ev;     // [pass][kFamLaunches][start, end]
     std::vector<sw_bin_stat> bin_stats;
 
     hipStream_t cap_stream = nullptr;   // private stream the graph is captured on
@@ -438,6 +447,13 @@ static void set_range(KParams& K, int b, int v) {
     K.head_idx = v ? kMetaColHeads + b : kMetaHeads + b;
 }
 
+// Workgroups the device holds at once of family kernel fn (0 if unknown).
+static int family_resident(const sw_handle* h, QueueFn fn) {
+    for (const auto& e : h->fam_resident)
+        if (e.first == fn) return e.second;
+    return 0;
+}
+
 static int bin_ev_index(int pass, int b, int v, int end) { return ((pass * kMaxBins + b) * 2 + v) * 2 + end; }
 
 // Score source of bin e's kernel for its column-word range (v = 1) or its
@@ -470,6 +486,18 @@ static int enqueue_pass(sw_handle* h, KParams K, const ClassifyArgs& C, const Wo
     HIP_TRY(h, launch_scatter(ws.keys, h->d_n, cap, h->d_hist, ws.order, stream));
     HIP_TRY(h, launch_items(h->d_meta, h->d_bins, n_bins, h->d_n, cap, ws.items, stream));
     const bool per_bin = timing && h->opt_timing == 2;
+    if (h->bin_launch.size() != (size_t)(2 * kMaxBins * 2)) {
+        h->bin_launch.assign(2 * kMaxBins * 2, -1);
+        h->bin_fam_hi.assign(2 * kMaxBins * 2, 0);
+        h->bin_fam_lo.assign(2 * kMaxBins * 2, 0);
+        h->bin_fam_slot.assign(2 * kMaxBins * 2, -1);
+    }
+    for (int i = pass * kMaxBins * 2; i < (pass + 1) * kMaxBins * 2; ++i) {
+        h->bin_launch[i] = -1;
+        h->bin_fam_hi[i] = h->bin_fam_lo[i] = 0;
+        h->bin_fam_slot[i] = -1;
+    }
+    int n_launch = 0;   // launches of this pass
     if (timing && h->opt_mode == 1) HIP_TRY(h, hipEventRecord(h->ev[pass == 0 ? 1 : 3], stream));
     if (h->opt_mode == 1) {
         // Bins go round-robin, longest first, to the forked streams, which
@@ -501,20 +529,79 @@ static int enqueue_pass(sw_handle* h, KParams K, const ClassifyArgs& C, const Wo
             only16 = h->route[0][(search_n - 1) / 16];
             only32 = h->route[1][(search_n - 1) / 16];
         }
+        std::vector<char> launchable(n_bins, 0);
+        for (int b = 0; b < n_bins; ++b)
+            launchable[b] = h->bin_used[b] && !(one_length && b != only16 && b != only32) &&
+                            !(h->opt_max_query > 0 && h->bin_min_query[b] > h->opt_max_query);
+        // Family launches (default tile): one kernel per family, score
+        // source and pass takes the items of all its launchable member bins;
+        // the bins it covers get no launch of their own below.
+        std::vector<char> covered(2 * n_bins, 0);
+        int fam_slot = 0;
+        if (h->opt_families && h->opt_chunk == kChunk) {
+            std::vector<const FamilyEntry*> seen;
+            for (int b = 0; b < n_bins; ++b) {
+                if (!launchable[b]) continue;
+                const FamilyEntry* f = shape_family(h->bins[b].prec, h->bins[b].W, h->bins[b].R);
+                if (!f || std::find(seen.begin(), seen.end(), f) != seen.end()) continue;
+                seen.push_back(f);
+                for (int v = 1; v >= 0; --v) {
+                    int var = -1, members = 0;
+                    for (int k = 0; k < kFamilyMax; ++k) K.fam_bins[k] = -1;
+                    for (int k = 0; k < f->n; ++k) {
+                        const int mb = find_bin(h, f->prec, f->W, f->rows[k]);
+                        if (mb < 0 || !launchable[mb]) continue;
+                        const BinInfo& m = h->bins[mb];
+                        if (v == 1 ? !(any_col && m.col) : (m.col && all_col)) continue;
+                        const int mv = table_var(h, m, K, v);
+                        if (mv == kVarQprof || (var >= 0 && mv != var)) continue;
+                        var = mv;
+                        K.fam_bins[k] = (int8_t)mb;
+                        ++members;
+                    }
+                    if (members == 0 || !f->k[var][pass] || fam_slot >= sw_handle::kFamLaunches) continue;
+                    for (int k = 0; k < f->n; ++k) {
+                        const int mb = K.fam_bins[k];
+                        if (mb < 0) continue;
+                        covered[2 * mb + v] = 1;
+                        const int i2 = bin_ev_index(pass, mb, v, 0) / 2;
+                        h->bin_launch[i2] = n_launch;
+                        h->bin_fam_hi[i2] = f->rows[0];
+                        h->bin_fam_lo[i2] = f->rows[f->n - 1];
+                        h->bin_fam_slot[i2] = fam_slot;
+                    }
+                    const QueueFn fn = f->k[var][pass];
+                    const int ppw = pairs_per_item(f->prec, f->W), ipb = items_per_block(f->W);
+                    const int64_t need = (cap / ppw + 1 + ipb - 1) / ipb;
+                    const int blocks = (int)std::min<int64_t>(need, std::max(1, family_resident(h, fn)));
+                    hipStream_t ls = forks > 1 ? h->fork[launched % forks] : stream;
+                    hipEvent_t* fe = per_bin ? &h->fam_ev[(pass * sw_handle::kFamLaunches + fam_slot) * 2] : nullptr;
+                    if (fe) HIP_TRY(h, hipEventRecord(fe[0], ls));
+                    hipLaunchKernelGGL(fn, dim3(blocks), dim3(kBlock), 0, ls, K);
+                    HIP_TRY(h, hipGetLastError());
+                    if (fe) HIP_TRY(h, hipEventRecord(fe[1], ls));
+                    ++launched;
+                    ++n_launch;
+                    ++fam_slot;
+                }
+            }
+        }
         for (int b = 0; b < n_bins; ++b) {
-            if (!h->bin_used[b]) continue;
-            if (one_length && b != only16 && b != only32) continue;
-            if (h->opt_max_query > 0 && h->bin_min_query[b] > h->opt_max_query) continue;
+            if (!launchable[b]) continue;
             const BinInfo& e = h->bins[b];
             // no bin can hold more than cap / ppw items
             const int ipb = items_per_block(e.W);
             const int64_t need = (cap / e.ppw + 1 + ipb - 1) / ipb;
+            bool any = false;
             for (int v = e.col ? 1 : 0; v >= 0; --v) {   // column-word kernel first
                 if (v == 1 ? !any_col : (e.col && all_col)) continue;
+                if (covered[2 * b + v]) continue;
+                any = true;
                 const int var = table_var(h, e, K, v);
                 const int nw = narrow_tile(h, e, var);
                 const int blocks = (int)std::min<int64_t>(need, h->resident_blocks[nw][pass][var][b]);
                 set_range(K, b, v);
+                h->bin_launch[bin_ev_index(pass, b, v, 0) / 2] = n_launch++;
                 // a bin's kernels share a stream; bins go round-robin
                 hipStream_t ls = forks > 1 ? h->fork[launched % forks] : stream;
                 if (per_bin) HIP_TRY(h, hipEventRecord(h->bin_ev[bin_ev_index(pass, b, v, 0)], ls));
@@ -524,7 +611,7 @@ static int enqueue_pass(sw_handle* h, KParams K, const ClassifyArgs& C, const Wo
                 if (per_bin) HIP_TRY(h, hipEventRecord(h->bin_ev[bin_ev_index(pass, b, v, 1)], ls));
                 if (per_bin) h->bin_launched[bin_ev_index(pass, b, v, 0) / 2] = 1;
             }
-            ++launched;
+            if (any) ++launched;
         }
         for (int f = 0; forks > 1 && f < forks; ++f) {
             HIP_TRY(h, hipEventRecord(h->fork_ev[f], h->fork[f]));
@@ -543,6 +630,7 @@ static int enqueue_pass(sw_handle* h, KParams K, const ClassifyArgs& C, const Wo
                 const int blocks = (items + items_per_block(e.W) - 1) / items_per_block(e.W);
                 const int var = table_var(h, e, K, v);
                 const int nw = narrow_tile(h, e, var);
+                h->bin_launch[bin_ev_index(pass, b, v, 0) / 2] = n_launch++;
                 if (per_bin) HIP_TRY(h, hipEventRecord(h->bin_ev[bin_ev_index(pass, b, v, 0)], stream));
                 hipLaunchKernelGGL(shape_kernel(e.prec, e.W, e.R, pass != 0, var, nw == 1), dim3(blocks), dim3(kBlock),
                                    0, stream, K);
@@ -671,6 +759,17 @@ sw_handle* sw_create(int device, const char* tuning) {
                     h->resident_blocks[nw][pass][v][b] = std::max(1, per_cu) * std::max(1, h->n_cu);
                 }
             }
+    for (size_t b = 0; ok && b < h->bins.size(); ++b) {
+        const FamilyEntry* f = shape_family(h->bins[b].prec, h->bins[b].W, h->bins[b].R);
+        for (int var = 0; f && ok && var <= kVarPtab; ++var)
+            for (int pass = 0; pass < 2; ++pass) {
+                const QueueFn fn = f->k[var][pass];
+                if (!fn || family_resident(h, fn) > 0) continue;
+                int per_cu = 0;
+                ok = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)fn, kBlock, 0) == hipSuccess;
+                h->fam_resident.push_back({fn, std::max(1, per_cu) * std::max(1, h->n_cu)});
+            }
+    }
     if (ok) ok = init_paths(h);
     if (!ok) { sw_destroy(h); return nullptr; }
     if (tuning) {
@@ -722,6 +821,8 @@ void sw_destroy(sw_handle* h) {
     if (h->h_meta) (void)hipHostFree(h->h_meta);
     for (int k = 0; k < 5; ++k)
         if (h->ev[k]) (void)hipEventDestroy(h->ev[k]);
+    for (hipEvent_t e : h->fam_ev)
+        if (e) (void)hipEventDestroy(e);
     for (hipEvent_t e : h->bin_ev)
         if (e) (void)hipEventDestroy(e);
     if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
@@ -750,6 +851,9 @@ int sw_set_option(sw_handle* h, const char* key, int64_t value) {
             h->bin_ev.assign(2 * kMaxBins * 2 * 2, nullptr);
             for (hipEvent_t& e : h->bin_ev)
                 if (hipEventCreate(&e) != hipSuccess) return fail(h, SW_EDEVICE, "event creation failed");
+            h->fam_ev.assign(2 * sw_handle::kFamLaunches * 2, nullptr);
+            for (hipEvent_t& e : h->fam_ev)
+                if (hipEventCreate(&e) != hipSuccess) return fail(h, SW_EDEVICE, "event creation failed");
         }
         h->opt_timing = value;
     } else if (k == "colpath") {
@@ -770,6 +874,8 @@ int sw_set_option(sw_handle* h, const char* key, int64_t value) {
         const int rc = ensure_pairs(h, value);
         if (rc != SW_OK) return rc;
         return SW_OK;
+    } else if (k == "families") {
+        h->opt_families = value ? 1 : 0;
     } else if (k == "max_query") {
         if (value < 0 || value > SW_MAX_QUERY) return fail(h, SW_EINVAL, "max_query must be 0..%d", SW_MAX_QUERY);
         h->opt_max_query = value;
@@ -803,6 +909,7 @@ int sw_get_option(sw_handle* h, const char* key, int64_t* value) {
     else if (k == "timing") *value = h->opt_timing;
     else if (k == "streams") *value = h->opt_streams;
     else if (k == "max_query") *value = h->opt_max_query;
+    else if (k == "families") *value = h->opt_families;
     else if (k == "capacity") *value = h->cap_pairs;
     else if (k == "colpath") *value = h->opt_colpath;
     else if (k == "chunk") *value = h->opt_chunk;
@@ -856,6 +963,11 @@ static int complete_slot(sw_handle* h, int k) {
                 const int64_t col_pairs = (int64_t)cnt[kCtrBinColPairs + i];
                 st.cells = v ? col_cells : (int64_t)cnt[kCtrBinCells + i] - col_cells;
                 st.pairs = v ? col_pairs : (int64_t)cnt[kCtrBinPairs + i] - col_pairs;
+                const int i2 = bin_ev_index(pass, b, v, 0) / 2;
+                const bool known = (size_t)i2 < h->bin_launch.size();
+                st.launch = known ? h->bin_launch[i2] : -1;
+                st.family_hi = known ? h->bin_fam_hi[i2] : 0;
+                st.family_lo = known ? h->bin_fam_lo[i2] : 0;
                 h->bin_stats.push_back(st);
             }
     h->t_plan = h->t_fwd = h->t_rev = 0.f;
@@ -872,6 +984,13 @@ static int complete_slot(sw_handle* h, int k) {
                 // item ranges; no mode launches a bin no route points at)
                 const int b = find_bin(h, st.precision, st.lanes, st.rows);
                 const int i = bin_ev_index(st.pass, b, st.column == 1 ? 1 : 0, 0);
+                const int slot = (size_t)(i / 2) < h->bin_fam_slot.size() ? h->bin_fam_slot[i / 2] : -1;
+                if (slot >= 0) {
+                    // a family launch: its time, shared by its bins
+                    const hipEvent_t* fe = &h->fam_ev[(st.pass * sw_handle::kFamLaunches + slot) * 2];
+                    HIP_TRY(h, hipEventElapsedTime(&st.ms, fe[0], fe[1]));
+                    continue;
+                }
                 if (!h->bin_launched[i / 2]) continue;
                 HIP_TRY(h, hipEventElapsedTime(&st.ms, h->bin_ev[i], h->bin_ev[i + 1]));
             }
@@ -1575,6 +1694,7 @@ static int trace_paths(sw_handle* h, const sw_batch* batch, const sw_scheme* sch
         st.pairs = (int64_t)cnt[kCtrTraceBinPairs + b];
         st.cells = (int64_t)cnt[kCtrTraceBinCells + b];
         st.ms = bin_ms[b];
+        st.launch = n_tb - 1 - b;   // the box sweeps launch largest shape first, one per bin
         h->bin_stats.push_back(st);
     }
     if (flags[kFlagInternal]) return fail(h, SW_EINTERNAL, "an alignment path could not be recovered");

@@ -386,7 +386,7 @@ def test_streams_and_per_launch_timing_agree():
     nontrivial = int(np.sum((b.q_len() > 0) & (b.r_len() > 0)))
     positive = int(np.sum(want["score"] > 0))
     for opts in (dict(streams=1), dict(streams=2), dict(streams=4), dict(timing=2),
-                 dict(mode=0, graph=0, timing=2)):
+                 dict(timing=2, families=0), dict(mode=0, graph=0, timing=2)):
         al = Aligner(0, **opts)
         try:
             out = torch.full((b.n_pairs, 5), -7, dtype=torch.int32, device="cuda:0")
@@ -406,6 +406,16 @@ def test_streams_and_per_launch_timing_agree():
                     p_, m_ = by_bin.get(k, (0, 0.0))
                     by_bin[k] = (p_ + e["pairs"], m_ + e["ms"])
                 assert all(m > 0 for p, m in by_bin.values() if p > 0), opts
+                # the bins of one launch share its time; family launches
+                # exactly when persistent mode has families on
+                launches = {}
+                for e in st:
+                    if e["launch"] >= 0:
+                        launches.setdefault((e["pass"], e["launch"]), set()).add((e["ms"], e["family_hi"],
+                                                                                 e["family_lo"]))
+                assert all(len(v) == 1 for v in launches.values()), opts
+                fam = any(e["family_hi"] > 0 for e in st)
+                assert fam == (opts.get("families", 1) == 1 and opts.get("mode", 1) == 1), opts
             else:
                 assert all(e["ms"] == 0 for e in st)
         finally:

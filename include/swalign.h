@@ -364,6 +364,7 @@ typedef struct sw_bin_stat {
                             call's; a replayed graph repeats its capture's), -1 if none */
     int32_t family_hi;   /* family launch: the largest and smallest rows per lane of */
     int32_t family_lo;   /* the family's shapes; 0 for a launch of one shape */
+    int32_t family_waves;/* family launch: wavefronts per SIMD its kernel is compiled for */
 } sw_bin_stat;
 
 /* Per-launch statistics of the last call on this handle: writes up to

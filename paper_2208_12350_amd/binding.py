@@ -59,7 +59,8 @@ class sw_bin_stat(ctypes.Structure):
     _fields_ = [("pass_", ctypes.c_int32), ("precision", ctypes.c_int32), ("lanes", ctypes.c_int32),
                 ("rows", ctypes.c_int32), ("pairs", ctypes.c_int64), ("cells", ctypes.c_int64),
                 ("ms", ctypes.c_float), ("column", ctypes.c_int32), ("tile", ctypes.c_int32),
-                ("launch", ctypes.c_int32), ("family_hi", ctypes.c_int32), ("family_lo", ctypes.c_int32)]
+                ("launch", ctypes.c_int32), ("family_hi", ctypes.c_int32), ("family_lo", ctypes.c_int32),
+                ("family_waves", ctypes.c_int32)]
 
 
 class SwError(RuntimeError):
@@ -261,7 +262,8 @@ def sw_last_timing(h: int):
 def sw_last_bin_stats(h: int):
     """Per-bin statistics of the last call: a list of dicts with keys
     pass, precision, lanes, rows, column, tile, pairs, cells, ms, launch,
-    family_hi, family_lo (bins one family launch swept share launch and ms)."""
+    family_hi, family_lo, family_waves (bins one family launch swept share
+    launch and ms)."""
     lib = load_library()
     n = ctypes.c_int(0)
     lib.sw_last_bin_stats(h, None, 0, ctypes.byref(n))
@@ -269,7 +271,8 @@ def sw_last_bin_stats(h: int):
     _check(h, lib.sw_last_bin_stats(h, arr, n.value, ctypes.byref(n)))
     return [{"pass": e.pass_, "precision": e.precision, "lanes": e.lanes, "rows": e.rows, "column": e.column,
              "tile": e.tile, "pairs": int(e.pairs), "cells": int(e.cells), "ms": float(e.ms),
-             "launch": e.launch, "family_hi": e.family_hi, "family_lo": e.family_lo} for e in arr[:n.value]]
+             "launch": e.launch, "family_hi": e.family_hi, "family_lo": e.family_lo,
+             "family_waves": e.family_waves} for e in arr[:n.value]]
 
 
 def _i32(n):

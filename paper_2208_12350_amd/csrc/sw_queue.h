@@ -269,7 +269,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) v
       {&sw_family_kernel<16, W, false, kVarCol, WPE, __VA_ARGS__>,                                            \
        &sw_family_kernel<16, W, true, kVarCol, WPE, __VA_ARGS__>},                                            \
       {&sw_family_kernel<16, W, false, kVarPtab, 2, __VA_ARGS__>,                                             \
-       &sw_family_kernel<16, W, true, kVarPtab, 2, __VA_ARGS__>}}}
+       &sw_family_kernel<16, W, true, kVarPtab, 2, __VA_ARGS__>}},                                            \
+     {2, WPE, 2}}
 
 // Per tile width (index 0: kChunk, 1: kChunkNarrow) and score source
 // (kVarTable, kVarCol, kVarPtab): the forward and reverse kernels, null

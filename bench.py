@@ -231,16 +231,29 @@ def cigar_leg(args, db, out, ref_out, tuning, score_ms, workload):
         alt.align_cigar(db, out=res[0], cigar_off=res[1], cigar=res[2], cigar_len=res[3])
         _, _, _, sm, wm = alt.cigar_stats()
         sweep_ms.append(sm); walk_ms.append(wm)
+        # the bins of one launch (a family launch sweeps several) share its time
+        launches_of_call = {}
         for e in alt.bin_stats():
-            if e["pass"] == 2 and e["pairs"]:
-                acc = per_bin.setdefault((e["precision"], e["lanes"], e["rows"], e["column"]), [0.0, 0])
-                acc[0] += e["ms"]; acc[1] += e["cells"]
+            if e["pass"] == 2:
+                rows = (e["family_hi"], e["family_lo"]) if e["family_hi"] else (e["rows"], 0)
+                acc = launches_of_call.setdefault(e["launch"], [(e["precision"], e["lanes"], rows, e["column"]),
+                                                                e["ms"], 0, 0])
+                acc[2] += e["cells"]; acc[3] += e["pairs"]
+        for key, ms, cells, pairs in launches_of_call.values():
+            if pairs:
+                acc = per_bin.setdefault(key, [0.0, 0])
+                acc[0] += ms; acc[1] += cells
     alt.close()
-    (P_, W_, R_, C_), (dms, dcells) = max(per_bin.items(), key=lambda kv: kv[1][0])
+    (P_, W_, (R_, lo_), C_), (dms, dcells) = max(per_bin.items(), key=lambda kv: kv[1][0])
     peak = VALU_INT16X2_TOPS if P_ == 16 else VALU_INT32_TOPS
     achieved = PATH_OPS_PER_CELL * dcells / (dms / 1e3) / 1e12
     launches = reps * chunks
-    kernel_name = "sw::sw_trace_kernel<%d, %d, %d, %s>" % (P_, W_, R_, "true" if C_ else "false")
+    if lo_:
+        # box-sweep family: <precision, lanes, column words, rows largest first (steps of 4)>
+        kernel_name = "sw::sw_trace_family_kernel<%d, %d, %s, %s>" % (
+            P_, W_, "true" if C_ else "false", ", ".join(str(r) for r in range(R_, lo_ - 1, -4)))
+    else:
+        kernel_name = "sw::sw_trace_kernel<%d, %d, %d, %s>" % (P_, W_, R_, "true" if C_ else "false")
     log("  paths: %d calls in %.3f s" % (steps, el))
     return {"value": round(fwd * steps / el / 1e9, 2), "unit": "GCUPS",
             "ms_per_call": round(el * 1e3 / steps, 3), "score_only_ms": round(score_ms, 3),

@@ -258,6 +258,11 @@ struct TraceArgs {
 using TraceFn = void (*)(KParams, TraceArgs);
 const ShapeDesc* trace_shapes(int* n);
 TraceFn trace_kernel(int prec, int W, int R, bool col = false);
+// The box-sweep family of packed int16 shape (prec, W, R), or null: its
+// members' rows per lane, largest first, and its kernels (table lookups,
+// column words).
+struct TraceFamily { int prec, W, n; int rows[kFamilyMax]; TraceFn fn, col; };
+const TraceFamily* trace_family(int prec, int W, int R);
 // Records are written in blocks of kStage sweep steps.
 constexpr int kStage = 8;
 // Record bytes of a box of m columns on shape (W, R): m + W - 1 sweep steps

@@ -214,6 +214,9 @@ struct sw_handle {
     std::vector<BinInfo> tbins;          // path-sweep shapes
     std::vector<int> tresident;          // workgroups the device holds at once, per path-sweep bin
     std::vector<int> tresident_col;      // and for its column-word kernel
+    std::vector<std::pair<TraceFn, int>> tfam_resident;   // per box-sweep family kernel
+    std::vector<int> tfam_first;         // per path-sweep bin of the last chunk: first bin of its family launch, or -1
+    hipEvent_t tfam_ev[4] = {};          // end of a box-sweep family launch, for its walks on other streams
     int32_t last_col_ok[SW_MAX_SCHEMES] = {0};   // column-word eligibility of the last score call's schemes
     BinInfo* d_tbins = nullptr;
     int8_t* d_tlut = nullptr;            // [2 * kLutRows] path-sweep bin per (precision, 16-row bucket of box rows)
@@ -695,6 +698,15 @@ static bool init_paths(sw_handle* h) {
                 hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)fn, kBlock, 0) != hipSuccess)
                 return false;
             (v ? h->tresident_col : h->tresident)[b] = std::max(1, per_cu) * std::max(1, h->n_cu);
+            const TraceFamily* f = trace_family(h->tbins[b].prec, h->tbins[b].W, h->tbins[b].R);
+            const TraceFn ff = f ? (v ? f->col : f->fn) : nullptr;
+            bool have = !ff;
+            for (const auto& e : h->tfam_resident) have |= e.first == ff;
+            if (!have) {
+                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)ff, kBlock, 0) != hipSuccess)
+                    return false;
+                h->tfam_resident.push_back({ff, std::max(1, per_cu) * std::max(1, h->n_cu)});
+            }
         }
     }
     bool ok = hipMalloc(&h->d_tbins, kMaxBins * sizeof(BinInfo)) == hipSuccess &&
@@ -746,6 +758,8 @@ sw_handle* sw_create(int device, const char* tuning) {
         ok = hipStreamCreateWithFlags(&h->fork[f], hipStreamNonBlocking) == hipSuccess;
     for (int f = 0; ok && f <= sw_handle::kForks; ++f)
         ok = hipEventCreateWithFlags(&h->fork_ev[f], hipEventDisableTiming) == hipSuccess;
+    for (int f = 0; ok && f < 4; ++f)
+        ok = hipEventCreateWithFlags(&h->tfam_ev[f], hipEventDisableTiming) == hipSuccess;
     if (ok) ok = hipMemcpy(h->d_bins, h->bins.data(), h->bins.size() * sizeof(BinInfo),
                            hipMemcpyHostToDevice) == hipSuccess;
     for (int nw = 0; nw < 2; ++nw)
@@ -827,6 +841,8 @@ void sw_destroy(sw_handle* h) {
     for (int k = 0; k < 5; ++k)
         if (h->ev[k]) (void)hipEventDestroy(h->ev[k]);
     for (hipEvent_t e : h->fam_ev)
+        if (e) (void)hipEventDestroy(e);
+    for (hipEvent_t e : h->tfam_ev)
         if (e) (void)hipEventDestroy(e);
     for (hipEvent_t e : h->bin_ev)
         if (e) (void)hipEventDestroy(e);
@@ -1643,7 +1659,69 @@ static int trace_paths(sw_handle* h, const sw_batch* batch, const sw_scheme* sch
                 HIP_TRY(h, hipStreamWaitEvent(h->fork[f], h->fork_ev[sw_handle::kForks], 0));
         }
         int launched = 0;
+        // walks per wavefront: fewer for longer boxes (a wavefront waits
+        // for every miss of any of its walks)
+        auto walk = [&](int b, hipStream_t ls) -> hipError_t {
+            const int rows = h->tbins[b].W * h->tbins[b].R;
+            const int active = rows >= 1024 ? 4 : rows >= 512 ? 8 : 64;
+            const int wblocks = active == 64 ? walk_blocks
+                                             : (int)std::min<int64_t>((cap + 4 * active - 1) / (4 * active),
+                                                                      4 * std::max(1, h->n_cu));
+            return launch_trace_walk(K, T, b, wblocks, active, path_off, path, path_len, ls);
+        };
+        // Family launches (option "families"): one box-sweep kernel per lane
+        // width takes the items of all its bins, largest rows first; each
+        // member's walks follow it on its stream.
+        h->tfam_first.assign(n_tb, -1);
+        int n_fam = 0;
+        for (int b = n_tb - 1; h->opt_families && b >= 0; --b) {
+            if (h->tfam_first[b] >= 0) continue;
+            const BinInfo& e = h->tbins[b];
+            const TraceFamily* f = trace_family(e.prec, e.W, e.R);
+            if (!f) continue;
+            const int v = e.col && all_col ? 1 : 0;
+            const TraceFn fn = v ? f->col : f->fn;
+            int members[kFamilyMax], nm = 0;
+            for (int k = 0; k < kFamilyMax; ++k) K.fam_bins[k] = -1;
+            for (int k = 0; k < f->n; ++k) {
+                int mb = -1;
+                for (int t = 0; t < n_tb; ++t)
+                    if (h->tbins[t].prec == f->prec && h->tbins[t].W == f->W && h->tbins[t].R == f->rows[k]) mb = t;
+                if (mb < 0 || h->tfam_first[mb] >= 0) continue;
+                K.fam_bins[k] = (int8_t)mb;
+                members[nm++] = mb;
+            }
+            int res = 0;
+            for (const auto& r : h->tfam_resident)
+                if (r.first == fn) res = r.second;
+            if (nm < 2 || !fn || res <= 0 || n_fam >= 4) continue;
+            const int b0 = members[0];
+            for (int k = 0; k < nm; ++k) h->tfam_first[members[k]] = b0;
+            const int64_t need = (cap / e.ppw + 1 + kWavesPerBlock - 1) / kWavesPerBlock;
+            hipStream_t ls = forks > 1 ? h->fork[launched++ % forks] : stream;
+            if (timing) HIP_TRY(h, hipEventRecord(h->tbin_ev[3 * b0], ls));
+            hipLaunchKernelGGL(fn, dim3((int)std::min<int64_t>(need, res)), dim3(kBlock), 0, ls, K, T);
+            HIP_TRY(h, hipGetLastError());
+            if (timing) HIP_TRY(h, hipEventRecord(h->tbin_ev[3 * b0 + 1], ls));
+            // the members' walks, once the sweep has written their records:
+            // spread over the forked streams so that they overlap other
+            // sweeps (timing keeps everything on the caller's stream)
+            const hipEvent_t swept = h->tfam_ev[n_fam++];
+            if (forks > 1) HIP_TRY(h, hipEventRecord(swept, ls));
+            for (int k = 0; k < nm; ++k) {
+                const int mb = members[k];
+                hipStream_t ws = ls;
+                if (forks > 1 && k > 0) {
+                    ws = h->fork[launched++ % forks];
+                    HIP_TRY(h, hipStreamWaitEvent(ws, swept, 0));
+                }
+                if (timing && mb != b0) HIP_TRY(h, hipEventRecord(h->tbin_ev[3 * mb + 1], ws));
+                HIP_TRY(h, walk(mb, ws));
+                if (timing) HIP_TRY(h, hipEventRecord(h->tbin_ev[3 * mb + 2], ws));
+            }
+        }
         for (int b = n_tb - 1; b >= 0; --b) {
+            if (h->tfam_first[b] >= 0) continue;
             const BinInfo& e = h->tbins[b];
             const int64_t need = (cap / e.ppw + 1 + kWavesPerBlock - 1) / kWavesPerBlock;
             hipStream_t ls = forks > 1 ? h->fork[launched++ % forks] : stream;
@@ -1657,14 +1735,7 @@ static int trace_paths(sw_handle* h, const sw_batch* batch, const sw_scheme* sch
             hipLaunchKernelGGL(trace_kernel(e.prec, e.W, e.R, v == 1), dim3(blocks), dim3(kBlock), 0, ls, K, T);
             HIP_TRY(h, hipGetLastError());
             if (timing) HIP_TRY(h, hipEventRecord(h->tbin_ev[3 * b + 1], ls));
-            // walks per wavefront: fewer for longer boxes (a wavefront waits
-            // for every miss of any of its walks)
-            const int rows = e.W * e.R;
-            const int active = rows >= 1024 ? 4 : rows >= 512 ? 8 : 64;
-            const int wblocks = active == 64 ? walk_blocks
-                                             : (int)std::min<int64_t>((cap + 4 * active - 1) / (4 * active),
-                                                                      4 * std::max(1, h->n_cu));
-            HIP_TRY(h, launch_trace_walk(K, T, b, wblocks, active, path_off, path, path_len, ls));
+            HIP_TRY(h, walk(b, ls));
             if (timing) HIP_TRY(h, hipEventRecord(h->tbin_ev[3 * b + 2], ls));
         }
         for (int f = 0; forks > 1 && f < forks; ++f) {
@@ -1674,10 +1745,13 @@ static int trace_paths(sw_handle* h, const sw_batch* batch, const sw_scheme* sch
         if (timing) {
             HIP_TRY(h, hipStreamSynchronize(stream));
             for (int b = 0; b < n_tb; ++b) {
+                // a family launch's sweep is timed once (at its first bin)
+                // and shared by its bins; every bin has its own walk
+                const int b0 = h->tfam_first[b] >= 0 ? h->tfam_first[b] : b;
                 float a = 0, w = 0;
-                HIP_TRY(h, hipEventElapsedTime(&a, h->tbin_ev[3 * b], h->tbin_ev[3 * b + 1]));
+                HIP_TRY(h, hipEventElapsedTime(&a, h->tbin_ev[3 * b0], h->tbin_ev[3 * b0 + 1]));
                 HIP_TRY(h, hipEventElapsedTime(&w, h->tbin_ev[3 * b + 1], h->tbin_ev[3 * b + 2]));
-                h->t_path_sweep += a;
+                if (b0 == b) h->t_path_sweep += a;
                 h->t_path_walk += w;
                 bin_ms[b] += a;
             }
@@ -1700,7 +1774,17 @@ static int trace_paths(sw_handle* h, const sw_batch* batch, const sw_scheme* sch
         st.pairs = (int64_t)cnt[kCtrTraceBinPairs + b];
         st.cells = (int64_t)cnt[kCtrTraceBinCells + b];
         st.ms = bin_ms[b];
-        st.launch = n_tb - 1 - b;   // the box sweeps launch largest shape first, one per bin
+        // launch index: the family launch's first bin, or the bin itself
+        // (box sweeps launch the largest shapes first)
+        const int b0 = (size_t)b < h->tfam_first.size() && h->tfam_first[b] >= 0 ? h->tfam_first[b] : b;
+        st.launch = n_tb - 1 - b0;
+        if (b0 != b || ((size_t)b < h->tfam_first.size() && h->tfam_first[b] == b)) {
+            const TraceFamily* f = trace_family(st.precision, st.lanes, st.rows);
+            if (f) {
+                st.family_hi = f->rows[0];
+                st.family_lo = f->rows[f->n - 1];
+            }
+        }
         h->bin_stats.push_back(st);
     }
     if (flags[kFlagInternal]) return fail(h, SW_EINTERNAL, "an alignment path could not be recovered");

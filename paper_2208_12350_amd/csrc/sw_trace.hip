@@ -658,6 +658,76 @@ __global__ __launch_bounds__(kBlock) void sw_trace_kernel(KParams P, TraceArgs T
     }
 }
 
+// ---- box-sweep families -----------------------------------------------------
+// One launch per lane width: the kernel drains the queue of member k's bin
+// (P.fam_bins[k]; -1: not launched), then member k+1's, each with the box
+// sweep compiled for that shape, as the score sweeps' family kernels do.
+// The LDS record stage is sized for the largest member.
+template <int PREC, int W, int R, bool COL>
+__device__ __forceinline__ void trace_member(const KParams& P, const TraceArgs& T, SchemeLds& L, uint16_t* wbuf,
+                                             uint32_t* stage, int lane, int bin, int n_pairs) {
+    constexpr int kPPW = (64 / W) * (PREC == 16 ? 2 : 1);
+    if (bin < 0) return;
+    const int lo_i = COL ? kMetaItemFirst + bin : kMetaItemSplit + bin;
+    const int hi_i = COL ? kMetaItemSplit + bin : kMetaItemFirst + bin + 1;
+    const int lo = __builtin_amdgcn_readfirstlane(__atomic_load_n(&P.meta[lo_i], __ATOMIC_RELAXED));
+    const int hi = __builtin_amdgcn_readfirstlane(__atomic_load_n(&P.meta[hi_i], __ATOMIC_RELAXED));
+    if (lo >= hi) return;
+    if (lo < 0 || hi > P.max_items) {
+        atomicOr(&P.flags[kFlagInternal], 1);
+        return;
+    }
+    const int head = (COL ? kMetaColHeads : kMetaHeads) + bin;
+    for (;;) {
+        const int mine = atomicAdd(&P.meta[head], lane == 0 ? 1 : 0);
+        const int it = __builtin_amdgcn_readlane(mine, 0);
+        if (it >= hi - lo) break;
+        const WorkItem* wp = P.items + lo + it;
+        const int first = __builtin_amdgcn_readfirstlane(__atomic_load_n(&wp->first, __ATOMIC_RELAXED));
+        const int count = __builtin_amdgcn_readfirstlane((int)__atomic_load_n(&wp->count, __ATOMIC_RELAXED));
+        const bool valid = first >= 0 && count >= 1 && count <= kPPW && first + count <= n_pairs;
+        if (valid) {
+            wave_lds_sync();
+            if constexpr (PREC == 16 && COL)
+                sweep_trace_i16_col<W, R>(P, T, L, wbuf, stage, first, count, lane);
+            else if constexpr (PREC == 16)
+                sweep_trace_i16<W, R>(P, T, L, wbuf, stage, first, count, lane);
+            else
+                sweep_trace<W, R>(P, T, L, wbuf, stage, first, count, lane);
+        } else {
+            atomicOr(&P.flags[kFlagInternal], 1);
+        }
+    }
+}
+
+template <int... Rs>
+constexpr int max_rows() {
+    int m = 0;
+    for (int r : {Rs...}) m = r > m ? r : m;
+    return m;
+}
+
+template <int PREC, int W, bool COL, int... Rs>
+__global__ __launch_bounds__(kBlock) void sw_trace_family_kernel(KParams P, TraceArgs T) {
+    constexpr int kPPW = (64 / W) * (PREC == 16 ? 2 : 1);
+    constexpr int kStageDwords = RecordStage<W, max_rows<Rs...>(), kPPW>::kDwords;
+    constexpr int kWaveBuf = COL ? kTraceWaveBufCol : kTraceWaveBuf;
+    static_assert(sizeof...(Rs) <= kFamilyMax, "family too large");
+    __shared__ __attribute__((aligned(16))) SchemeLds L;
+    __shared__ __attribute__((aligned(16))) uint16_t wbufs[kWavesPerBlock * kWaveBuf];
+    __shared__ __attribute__((aligned(16))) uint32_t stages[kWavesPerBlock * kStageDwords];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int n_pairs = __builtin_amdgcn_readfirstlane(*P.n_dev);
+    load_schemes(L, P, tid);
+    __syncthreads();
+    uint16_t* wbuf = wbufs + wave * kWaveBuf;
+    uint32_t* stage = stages + wave * kStageDwords;
+    int k = 0;
+    ((trace_member<PREC, W, Rs, COL>(P, T, L, wbuf, stage, lane, P.fam_bins[k++], n_pairs)), ...);
+}
+
 #define SW_TRACE_SHAPES(X, P)                                                                          \
     X(P, 16, 4) X(P, 16, 8) X(P, 16, 12) X(P, 16, 16) X(P, 32, 12) X(P, 32, 16) X(P, 64, 12) X(P, 64, 16) \
     X(P, 64, 20) X(P, 64, 24) X(P, 64, 28) X(P, 64, 32)
@@ -678,6 +748,25 @@ const ShapeDesc* trace_shapes(int* n) {
         g_trace_shapes[k] = {kTraceKernels[k].prec, kTraceKernels[k].W, kTraceKernels[k].R};
     *n = kNumTrace;
     return g_trace_shapes;
+}
+
+namespace {
+// Box-sweep families, largest rows first (the order of KParams::fam_bins).
+const TraceFamily kTraceFamilies[] = {
+    {16, 16, 4, {16, 12, 8, 4}, &sw_trace_family_kernel<16, 16, false, 16, 12, 8, 4>,
+     &sw_trace_family_kernel<16, 16, true, 16, 12, 8, 4>},
+    {16, 32, 2, {16, 12}, &sw_trace_family_kernel<16, 32, false, 16, 12>, &sw_trace_family_kernel<16, 32, true, 16, 12>},
+    {16, 64, 6, {32, 28, 24, 20, 16, 12}, &sw_trace_family_kernel<16, 64, false, 32, 28, 24, 20, 16, 12>,
+     &sw_trace_family_kernel<16, 64, true, 32, 28, 24, 20, 16, 12>},
+};
+}  // namespace
+
+const TraceFamily* trace_family(int prec, int W, int R) {
+    for (const TraceFamily& f : kTraceFamilies)
+        if (f.prec == prec && f.W == W)
+            for (int k = 0; k < f.n; ++k)
+                if (f.rows[k] == R) return &f;
+    return nullptr;
 }
 
 TraceFn trace_kernel(int prec, int W, int R, bool col) {

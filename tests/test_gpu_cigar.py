@@ -308,3 +308,31 @@ def test_column_word_and_table_path_sweeps_agree(aligner):
             assert_paths_equal(b, col, np.arange(0, b.n_pairs, 7))
     finally:
         table.close()
+
+
+def test_box_sweep_family_launches_agree(aligner):
+    """One box-sweep launch per lane width (the default) and one launch per
+    bin (families = 0) give the same results and paths, and the oracle's
+    on a sample; in timing mode the bins of a family launch share its time."""
+    from paper_2208_12350_amd.binding import Aligner
+    b = W.make_workload("mixed", n_pairs=4000, seed=917)
+    fam = gpu_paths(aligner, b)
+    per = Aligner(0, families=0)
+    timed = Aligner(0, timing=2)
+    try:
+        plain = gpu_paths(per, b)
+        assert not any(e["family_hi"] for e in per.bin_stats() if e["pass"] == 2)
+        again = gpu_paths(timed, b)
+        st = [e for e in timed.bin_stats() if e["pass"] == 2]
+    finally:
+        per.close()
+        timed.close()
+    for x, y, z in zip(fam, plain, again):
+        assert np.array_equal(x, y)
+        assert np.array_equal(x, z)
+    assert any(e["family_hi"] for e in st)
+    by_launch = {}
+    for e in st:
+        by_launch.setdefault(e["launch"], set()).add((e["ms"], e["family_hi"], e["family_lo"]))
+    assert all(len(v) == 1 for v in by_launch.values())
+    assert_paths_equal(b, fam, np.arange(0, b.n_pairs, 13))

@@ -177,9 +177,9 @@ def roofline_leg(args, db, out, tuning, mode, workload, steps):
     direction = "true" if dpass else "false"
     if dlo:
         # family kernel: <precision, lanes, reverse, score source, waves per
-        # SIMD, rows largest first>
-        kernel_name = "sw::sw_family_kernel<%d, %d, %s, %d, %d, %s>" % (
-            dprec, dlanes, direction, dcol, dwaves, ", ".join(str(r) for r in range(drows, dlo - 1, -1)))
+        # SIMD, reference tile, rows largest first>
+        kernel_name = "sw::sw_family_kernel<%d, %d, %s, %d, %d, %d, %s>" % (
+            dprec, dlanes, direction, dcol, dwaves, dtile, ", ".join(str(r) for r in range(drows, dlo - 1, -1)))
     elif dlanes > 64:
         kernel_name = "sw::sw_coop_kernel<%d, %s>" % (drows, direction)
     elif dcol == 3:

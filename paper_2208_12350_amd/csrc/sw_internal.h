@@ -206,7 +206,7 @@ QueueFn shape_kernel(int prec, int W, int R, bool reverse, int var = kVarTable, 
 // `rows[0..n)` are its members' rows per lane, largest first (the order of
 // KParams::fam_bins), and k[var][reverse] its kernels (kVarTable, kVarCol,
 // kVarPtab; null where there is none).
-struct FamilyEntry { int prec, W, n; int rows[kFamilyMax]; QueueFn k[3][2]; int waves[3]; };
+struct FamilyEntry { int prec, W, n; int rows[kFamilyMax]; QueueFn k[3][2]; int waves[3]; int tile[3]; };
 const FamilyEntry* shape_family(int prec, int W, int R);
 const ShapeDesc* compiled_shapes(int* n);
 

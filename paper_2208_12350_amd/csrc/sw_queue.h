@@ -205,7 +205,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
 // another (no loop around them), so each member's loop-invariant values are
 // live only while it runs and the register allocation is about that of the
 // largest member.
-template <int PREC, int W, int R, bool REV, int VAR, class Lds>
+template <int PREC, int W, int R, bool REV, int VAR, int C, class Lds>
 __device__ __forceinline__ void family_member(const KParams& P, Lds& L, uint16_t* wbuf, int lane, int bin,
                                               int n_pairs) {
     constexpr int kPPW = (64 / W) * (PREC == 16 ? 2 : 1);
@@ -221,20 +221,20 @@ __device__ __forceinline__ void family_member(const KParams& P, Lds& L, uint16_t
     }
     queue_loop<kPPW>(P, lane, lo, hi, n_pairs, [&](int first, int count) {
         if constexpr (VAR == kVarPtab)
-            sweep_i16_ptab<W, R, REV, kChunk>(P, L, wbuf, first, count, lane);
+            sweep_i16_ptab<W, R, REV, C>(P, L, wbuf, first, count, lane);
         else if constexpr (VAR == kVarCol)
-            sweep_i16_col<W, R, REV, kChunk>(P, L, wbuf, first, count, lane);
+            sweep_i16_col<W, R, REV, C>(P, L, wbuf, first, count, lane);
         else if constexpr (PREC == 16)
-            sweep_i16<W, R, REV, kChunk>(P, L, wbuf, first, count, lane);
+            sweep_i16<W, R, REV, C>(P, L, wbuf, first, count, lane);
         else
-            sweep_i32<W, R, REV, kChunk>(P, L, wbuf, first, count, lane);
+            sweep_i32<W, R, REV, C>(P, L, wbuf, first, count, lane);
     }, (VAR == kVarCol ? kMetaColHeads : kMetaHeads) + bin);
 }
 
 template <int... Rs>
 constexpr int family_size() { return (int)sizeof...(Rs); }
 
-template <int PREC, int W, bool REV, int VAR, int WPE, int... Rs>
+template <int PREC, int W, bool REV, int VAR, int WPE, int C, int... Rs>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) void sw_family_kernel(KParams P) {
     static_assert(sizeof...(Rs) <= kFamilyMax, "family too large");
     using Lds = typename std::conditional<VAR == kVarPtab, PtabLds, SchemeLds>::type;
@@ -254,23 +254,25 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) v
     __syncthreads();
     uint16_t* wbuf = wbufs + wave * kWaveBuf;
     int k = 0;
-    ((family_member<PREC, W, Rs, REV, VAR, Lds>(P, L, wbuf, lane, P.fam_bins[k++], n_pairs)), ...);
+    ((family_member<PREC, W, Rs, REV, VAR, C, Lds>(P, L, wbuf, lane, P.fam_bins[k++], n_pairs)), ...);
 }
 
-// WPE: the wavefronts per SIMD the column-word kernels are compiled for
-// (their register budget); the table-lookup and pair-table kernels keep 2.
+// Register budgets and tiles of a family's kernels: CW wavefronts per SIMD
+// for its column-word kernel, PW and the reference tile PC for its
+// pair-table kernel (the table-lookup kernel keeps 2 and kChunk).
 // Measured: the 9..16-row 16-lane and 11..16-row 32-lane column-word
-// families run dna_large 2.5% faster at 3 (a few spilled registers);
-// their pair-table families ran protein 4% slower at 3.
-#define SW_FAMILY16(W, WPE, ...)                                                                              \
+// families run dna_large 2.5% faster at 3 (a few spilled registers).  Their
+// pair-table families ran protein 4% slower at 3, and the 32-lane one no
+// faster at 3 with tiles of 64 steps (168 registers, 3 spilled).
+#define SW_FAMILY16(W, CW, PW, PC, ...)                                                                       \
     {16, W, family_size<__VA_ARGS__>(), {__VA_ARGS__},                                                        \
-     {{&sw_family_kernel<16, W, false, kVarTable, 2, __VA_ARGS__>,                                            \
-       &sw_family_kernel<16, W, true, kVarTable, 2, __VA_ARGS__>},                                            \
-      {&sw_family_kernel<16, W, false, kVarCol, WPE, __VA_ARGS__>,                                            \
-       &sw_family_kernel<16, W, true, kVarCol, WPE, __VA_ARGS__>},                                            \
-      {&sw_family_kernel<16, W, false, kVarPtab, 2, __VA_ARGS__>,                                             \
-       &sw_family_kernel<16, W, true, kVarPtab, 2, __VA_ARGS__>}},                                            \
-     {2, WPE, 2}}
+     {{&sw_family_kernel<16, W, false, kVarTable, 2, kChunk, __VA_ARGS__>,                                    \
+       &sw_family_kernel<16, W, true, kVarTable, 2, kChunk, __VA_ARGS__>},                                    \
+      {&sw_family_kernel<16, W, false, kVarCol, CW, kChunk, __VA_ARGS__>,                                     \
+       &sw_family_kernel<16, W, true, kVarCol, CW, kChunk, __VA_ARGS__>},                                     \
+      {&sw_family_kernel<16, W, false, kVarPtab, PW, PC, __VA_ARGS__>,                                        \
+       &sw_family_kernel<16, W, true, kVarPtab, PW, PC, __VA_ARGS__>}},                                       \
+     {2, CW, PW}, {kChunk, kChunk, PC}}
 
 // Per tile width (index 0: kChunk, 1: kChunkNarrow) and score source
 // (kVarTable, kVarCol, kVarPtab): the forward and reverse kernels, null

@@ -29,6 +29,6 @@ const int kNumI16W16Kernels = sizeof(kI16W16Kernels) / sizeof(kI16W16Kernels[0])
 
 // One launch per pass and score source serves every shape of this file.
 extern const FamilyEntry kI16W16Family;
-const FamilyEntry kI16W16Family = SW_FAMILY16(16, 2, 8, 7, 6, 5, 4, 3, 2, 1);
+const FamilyEntry kI16W16Family = SW_FAMILY16(16, 2, 2, kChunk, 8, 7, 6, 5, 4, 3, 2, 1);
 
 }  // namespace sw

@@ -29,6 +29,6 @@ const int kNumI16W16bKernels = sizeof(kI16W16bKernels) / sizeof(kI16W16bKernels[
 
 // One launch per pass and score source serves every shape of this file.
 extern const FamilyEntry kI16W16bFamily;
-const FamilyEntry kI16W16bFamily = SW_FAMILY16(16, 3, 16, 15, 14, 13, 12, 11, 10, 9);
+const FamilyEntry kI16W16bFamily = SW_FAMILY16(16, 3, 2, kChunk, 16, 15, 14, 13, 12, 11, 10, 9);
 
 }  // namespace sw

@@ -28,6 +28,6 @@ const int kNumI16W32Kernels = sizeof(kI16W32Kernels) / sizeof(kI16W32Kernels[0])
 
 // One launch per pass and score source serves every shape of this file.
 extern const FamilyEntry kI16W32Family;
-const FamilyEntry kI16W32Family = SW_FAMILY16(32, 2, 10, 9, 8, 7, 6, 5);
+const FamilyEntry kI16W32Family = SW_FAMILY16(32, 2, 2, kChunk, 10, 9, 8, 7, 6, 5);
 
 }  // namespace sw

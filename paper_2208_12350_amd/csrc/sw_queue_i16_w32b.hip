@@ -28,6 +28,6 @@ const int kNumI16W32bKernels = sizeof(kI16W32bKernels) / sizeof(kI16W32bKernels[
 
 // One launch per pass and score source serves every shape of this file.
 extern const FamilyEntry kI16W32bFamily;
-const FamilyEntry kI16W32bFamily = SW_FAMILY16(32, 3, 16, 15, 14, 13, 12, 11);
+const FamilyEntry kI16W32bFamily = SW_FAMILY16(32, 3, 2, kChunk, 16, 15, 14, 13, 12, 11);
 
 }  // namespace sw

@@ -23,6 +23,6 @@ const int kNumI16W64Kernels = sizeof(kI16W64Kernels) / sizeof(kI16W64Kernels[0])
 
 // One launch per pass and score source serves every shape of this file.
 extern const FamilyEntry kI16W64Family;
-const FamilyEntry kI16W64Family = SW_FAMILY16(64, 2, 20, 19, 18, 17, 16, 15, 14, 13, 12, 11, 10, 9);
+const FamilyEntry kI16W64Family = SW_FAMILY16(64, 2, 2, kChunk, 20, 19, 18, 17, 16, 15, 14, 13, 12, 11, 10, 9);
 
 }  // namespace sw

@@ -23,6 +23,6 @@ const int kNumI16W64LongKernels = sizeof(kI16W64LongKernels) / sizeof(kI16W64Lon
 
 // One launch per pass and score source serves every shape of this file.
 extern const FamilyEntry kI16W64LongFamily;
-const FamilyEntry kI16W64LongFamily = SW_FAMILY16(64, 2, 32, 31, 30, 29, 28, 27, 26, 25, 24, 23, 22, 21);
+const FamilyEntry kI16W64LongFamily = SW_FAMILY16(64, 2, 2, kChunk, 32, 31, 30, 29, 28, 27, 26, 25, 24, 23, 22, 21);
 
 }  // namespace sw

@@ -189,7 +189,7 @@ struct sw_handle {
     // launch (rows per lane of its first and last shape, else 0) and its
     // event slot ("timing" = 2)
     static constexpr int kFamLaunches = 16;
-    std::vector<int32_t> bin_launch, bin_fam_hi, bin_fam_lo, bin_fam_slot, bin_fam_waves;
+    std::vector<int32_t> bin_launch, bin_fam_hi, bin_fam_lo, bin_fam_slot, bin_fam_waves, bin_fam_tile;
     std::vector<hipEvent_t> fam_ev;     // [pass][kFamLaunches][start, end]
     std::vector<sw_bin_stat> bin_stats;
 
@@ -495,10 +495,11 @@ static int enqueue_pass(sw_handle* h, KParams K, const ClassifyArgs& C, const Wo
         h->bin_fam_lo.assign(2 * kMaxBins * 2, 0);
         h->bin_fam_slot.assign(2 * kMaxBins * 2, -1);
         h->bin_fam_waves.assign(2 * kMaxBins * 2, 0);
+        h->bin_fam_tile.assign(2 * kMaxBins * 2, 0);
     }
     for (int i = pass * kMaxBins * 2; i < (pass + 1) * kMaxBins * 2; ++i) {
         h->bin_launch[i] = -1;
-        h->bin_fam_hi[i] = h->bin_fam_lo[i] = h->bin_fam_waves[i] = 0;
+        h->bin_fam_hi[i] = h->bin_fam_lo[i] = h->bin_fam_waves[i] = h->bin_fam_tile[i] = 0;
         h->bin_fam_slot[i] = -1;
     }
     int n_launch = 0;   // launches of this pass
@@ -577,6 +578,7 @@ static int enqueue_pass(sw_handle* h, KParams K, const ClassifyArgs& C, const Wo
                         h->bin_fam_lo[i2] = f->rows[f->n - 1];
                         h->bin_fam_slot[i2] = fam_slot;
                         h->bin_fam_waves[i2] = f->waves[var];
+                        h->bin_fam_tile[i2] = f->tile[var];
                     }
                     const QueueFn fn = f->k[var][pass];
                     const int ppw = pairs_per_item(f->prec, f->W), ipb = items_per_block(f->W);
@@ -990,6 +992,7 @@ static int complete_slot(sw_handle* h, int k) {
                 st.family_hi = known ? h->bin_fam_hi[i2] : 0;
                 st.family_lo = known ? h->bin_fam_lo[i2] : 0;
                 st.family_waves = known ? h->bin_fam_waves[i2] : 0;
+                if (known && h->bin_fam_tile[i2] > 0) st.tile = h->bin_fam_tile[i2];
                 h->bin_stats.push_back(st);
             }
     h->t_plan = h->t_fwd = h->t_rev = 0.f;

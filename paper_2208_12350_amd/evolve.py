@@ -16,7 +16,7 @@ An *edit* sets one parameter of a configuration of libswalign:
 * ``("route", lo, hi, W, R)``: queries of lo+1 .. hi residues on the packed
   int16 path go to the sweep shape of W lanes x R rows per lane;
 * ``("opt", name, value)``: a library option (``streams``, ``mode``,
-  ``graph``, ``colpath``, ``pairtable``, ``chunk``).
+  ``graph``, ``colpath``, ``pairtable``, ``chunk``, ``families``).
 
 A genome is a list of edits, applied in order to the default configuration
 (later edits override earlier ones where they overlap).  A configuration
@@ -44,7 +44,7 @@ Measure = Callable[[Sequence[Edit]], Optional[float]]
 BUCKET = 16
 MAX_QUERY = 2048
 OPTION_VALUES = {"streams": (1, 2, 3, 4), "mode": (0, 1), "graph": (0, 1), "colpath": (0, 1), "pairtable": (0, 1),
-                 "chunk": (128, 64)}
+                 "chunk": (128, 64), "families": (0, 1)}
 
 
 # ---- configurations -------------------------------------------------------------
@@ -345,7 +345,7 @@ class LibraryFitness:
         finally:
             al.close()
 
-    DEFAULT_OPTIONS = {"streams": 4, "mode": 1, "graph": 1, "colpath": 1, "pairtable": 1, "chunk": 128}
+    DEFAULT_OPTIONS = {"streams": 4, "mode": 1, "graph": 1, "colpath": 1, "pairtable": 1, "chunk": 128, "families": 1}
 
     def key(self, edits: Sequence[Edit]) -> str:
         """The configuration an edit list builds, with options at their

@@ -11,27 +11,32 @@
 //   1. Path sweep: the box is swept like the forward pass (W-lane groups, R
 //      rows per lane, anti-diagonal steps with DPP lane shifts; two pairs
 //      per group packed in biased int16 halves when S fits, else one pair
-//      in int32), and every cell leaves 4 bits in a device record:
-//        bits 0-1  the first valid source of H: 0 diagonal, 1 F (a query
-//                  residue over a gap), 2 E (a reference residue over a gap)
-//        bit 2     F does not open here (F != H(i-1, j) - o: it extends)
-//        bit 3     E does not open here (E != H(i, j-1) - o)
+//      in int32), and every cell leaves 4 flags in a device record:
+//        D   H is not the diagonal value
+//        N   H is not F (with D set: H comes from E, a reference residue
+//            over a gap; with D clear: from the diagonal)
+//        FX  F does not open here (F != H(i-1, j) - o: it extends)
+//        EX  E does not open here (E != H(i, j-1) - o)
 //      Step t of lane l holds rows l*R .. l*R+R-1 of column t - l (R a
-//      multiple of 4).  Records
-//      are laid out in blocks of kStage steps: block b of lane l is the
-//      4R bytes at (b * W + l) * 4R, step t = 8b + s at byte s * R/2, row k
-//      in byte k/2 (low nibble for even k).  The sweep stages a block's
-//      steps in LDS and writes it out as full 16-byte chunks per lane (a
-//      pair's block of all W lanes is one contiguous W * 4R bytes); the
-//      walk moves mostly along one lane's steps, so one block read serves
-//      up to 8 of its steps.
-//      The bits are computed without compares: for x >= y, min(x - y, 1) or
-//      min(x ^ y, 1) is 1 exactly when x != y, per 32-bit lane or per 16-bit
-//      half (v_min_u32 / v_pk_min_u16), and the source code is
-//      (h != diag) << (h != F).
+//      multiple of 4) in R/2 bytes: one dword per 8 rows, whose bytes are
+//      the D, N, FX and EX bits of those rows (bit k: row 8j+k), and for
+//      R % 8 == 4 a 16-bit tail for the last 4 rows (FX bits 0-3, D 4-7,
+//      EX 8-11, N 12-15).  Records are laid out in blocks of kStage steps:
+//      block b of lane l is the 4R bytes at (b * W + l) * 4R, step t = 8b + s
+//      at byte s * R/2.  The sweep stages a block's steps in LDS and writes
+//      it out as full 16-byte chunks per lane (a pair's block of all W lanes
+//      is one contiguous W * 4R bytes); the walk moves mostly along one
+//      lane's steps, so one block read serves up to 8 of its steps.
+//      The flags are computed without compares.  In the packed sweeps every
+//      value stays below 0x8000, so for x >= y the wrapping 16-bit
+//      difference y - x has bit 15 set exactly when x != y: one packed
+//      subtract gives a flag for both pairs, one v_perm_b32 gathers the top
+//      bytes of two such differences (four flags, one per byte, in bit 7),
+//      and a shift and a bitfield insert push them into the row's bit of
+//      four byte-wide flag streams.  The int32 sweep takes min(x ^ y, 1).
 //   2. Walk: one thread per pair follows the bits back from the box's last
-//      cell, preferring at each choice the first valid option in the order
-//      above and opening a gap over extending it, and writes the path as
+//      cell, taking as H's source the diagonal, else F, else E (the first
+//      that equals H) and opening a gap over extending it, and writes the path as
 //      runs (length << 4) | op with the SAM codes 7 '=', 8 'X', 1 'I', 2 'D'.
 //
 // E and F are carried clamped at zero, as in the score sweeps; a clamped
@@ -139,18 +144,28 @@ __device__ __forceinline__ uint32_t* readlane_ptr(uint32_t* p, int lane) {
 
 // 1 if x != 0, else 0: one v_min_u32.  Written as an instruction because
 // the compiler otherwise turns min(x, 1) into a compare and a select (two
-// instructions with a wait state between them, and per 16-bit half in the
-// packed form).
+// instructions with a wait state between them).
 __device__ __forceinline__ uint32_t ne01(uint32_t x) {
     uint32_t r;
     asm("v_min_u32 %0, 1, %1" : "=v"(r) : "v"(x));
     return r;
 }
-// per 16-bit half: 1 if the half != 0, else 0 (one v_pk_min_u16)
-__device__ __forceinline__ u16x2 pk_ne01(u16x2 x) {
+
+// Push four flags (bit 7 of each byte of p) into four byte-wide flag
+// streams: each byte of acc moves down one bit and takes the new flag on top,
+// so after 8 rows bit k of a byte is row k's flag.  The bits below bit 7 of
+// p are dropped, and a bit that moves into the byte below lands in its bit
+// 7, which the insert overwrites.  One shift and one v_bfi_b32, written as
+// an instruction because the compiler otherwise splits the masks over three.
+__device__ __forceinline__ uint32_t flag_push(uint32_t acc, uint32_t p) {
     uint32_t r;
-    asm("v_pk_min_u16 %0, %1, %2" : "=v"(r) : "v"(u32(x)), "s"(0x00010001u));
-    return pk(r);
+    asm("v_bfi_b32 %0, %1, %2, %3" : "=v"(r) : "s"(0x80808080u), "v"(p), "v"(acc >> 1));
+    return r;
+}
+// Top bytes of two packed wrapping differences: bytes 1 and 3 of x (pair A,
+// pair B) become bytes 0 and 2, those of y bytes 1 and 3.
+__device__ __forceinline__ uint32_t flag_gather(uint32_t x, uint32_t y) {
+    return __builtin_amdgcn_perm(y, x, 0x07030501u);
 }
 
 // Path sweep of the wave item order[first .. first+count), one pair per
@@ -242,8 +257,10 @@ __device__ __forceinline__ void sweep_trace(const KParams& P, const TraceArgs& T
                 const uint32_t nf = ne01((uint32_t)(h ^ F));
                 const uint32_t fx = ne01((uint32_t)(F - Hmu));
                 const uint32_t ex = ne01((uint32_t)(E[r] - sat_sub(H[r], go)));
-                const uint32_t nib = ((nd << nf) | (fx << 2)) | (ex << 3);
-                wv[r / 8] |= nib << (4 * (r % 8));
+                if (r < R / 8 * 8)
+                    wv[r / 8] |= (nd | (nf << 8) | (fx << 16) | (ex << 24)) << (r % 8);
+                else
+                    wv[r / 8] |= (fx | (nd << 4) | (ex << 8) | (nf << 12)) << (r % 8);
                 sc[r] = S.mat[bb_next + a[r]];
                 diag = H[r];
                 H[r] = h;
@@ -388,19 +405,18 @@ __device__ __forceinline__ void sweep_trace_i16(const KParams& P, const TraceArg
             Hup_prev = u32(Hup);
             u16x2 Hmu = pk_sat_sub(Hup, go2);
             u16x2 F = Fup;
-            uint32_t w[R / 4];
+            uint32_t acc[2 * NW + 2];   // per 8 rows: D, N streams and FX, EX streams
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 F = pk_max3(pk_sat_sub(F, ge2), Hmu, zero);
                 const u16x2 d = diag + sc[r];
                 const u16x2 h = pk_max3(d, E[r], F);
-                const u16x2 nd = pk_ne01(h ^ d);
-                const u16x2 nf = pk_ne01(h ^ F);
-                const u16x2 fx = pk_ne01(F ^ Hmu);
-                const u16x2 ex = pk_ne01(E[r] ^ pk_sat_sub(H[r], go2));
-                const uint32_t nib = (u32(nd << nf) | (u32(fx) << 2)) | (u32(ex) << 3);
-                if (r % 4 == 0) w[r / 4] = nib;
-                else w[r / 4] |= nib << (4 * (r % 4));
+                const uint32_t p1 = flag_gather(u32(d - h), u32(F - h));
+                const uint32_t p2 = flag_gather(u32(Hmu - F), u32(pk_sat_sub(H[r], go2) - E[r]));
+                uint32_t& a1 = acc[2 * (r / 8)];
+                uint32_t& a2 = acc[2 * (r / 8) + 1];
+                a1 = r % 8 == 0 ? p1 : flag_push(a1, p1);
+                a2 = r % 8 == 0 ? p2 : flag_push(a2, p2);
                 sc[r] = load_scores(S.mat, bbA_next + (int)(apk[r] & 0xFFFF), bbB_next + (int)(apk[r] >> 16));
                 diag = H[r];
                 H[r] = h;
@@ -411,13 +427,18 @@ __device__ __forceinline__ void sweep_trace_i16(const KParams& P, const TraceArg
             Flast = u32(F);
             bbA_next = bbA2;
             bbB_next = bbB2;
+            // a stream pair (D, N of A and B; FX, EX of A and B) per 8 rows
+            // becomes one dword per pair; the last 4 rows of R % 8 == 4 sit
+            // in bits 4-7 of their stream bytes and become the 16-bit tails
             uint32_t va[NW + 1], vb[NW + 1];
 #pragma unroll
             for (int k = 0; k < NW; ++k) {
-                va[k] = __builtin_amdgcn_perm(w[2 * k + 1], w[2 * k], 0x05040100u);
-                vb[k] = __builtin_amdgcn_perm(w[2 * k + 1], w[2 * k], 0x07060302u);
+                va[k] = __builtin_amdgcn_perm(acc[2 * k + 1], acc[2 * k], 0x05040100u);
+                vb[k] = __builtin_amdgcn_perm(acc[2 * k + 1], acc[2 * k], 0x07060302u);
             }
-            const uint32_t tail = w[R / 4 - 1];
+            uint32_t tail = 0;
+            if constexpr (R % 8 == 4)
+                tail = (acc[2 * NW] & 0xF0F0F0F0u) | ((acc[2 * NW + 1] >> 4) & 0x0F0F0F0Fu);
             const int t = t0 + tt;
             rs.put(2 * g, l, t, va, tail);
             rs.put(2 * g + 1, l, t, vb, tail >> 16);
@@ -552,19 +573,18 @@ __device__ __forceinline__ void sweep_trace_i16_col(const KParams& P, const Trac
             Hup_prev = u32(Hmu0);
             u16x2 Hmu = Hmu0;
             u16x2 F = Fup;
-            uint32_t w[R / 4];
+            uint32_t acc[2 * NW + 2];   // per 8 rows: D, N streams and FX, EX streams
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 F = pk_max3(pk_sat_sub(F, ge2), Hmu, zero);
                 const u16x2 d = diag + pk(__builtin_amdgcn_perm(cb, ca, sel[r]));
                 const u16x2 h = pk_max3(d, E[r], F);
-                const u16x2 nd = pk_ne01(h ^ d);
-                const u16x2 nf = pk_ne01(h ^ F);
-                const u16x2 fx = pk_ne01(F ^ Hmu);
-                const u16x2 ex = pk_ne01(E[r] ^ Hm[r]);
-                const uint32_t nib = (u32(nd << nf) | (u32(fx) << 2)) | (u32(ex) << 3);
-                if (r % 4 == 0) w[r / 4] = nib;
-                else w[r / 4] |= nib << (4 * (r % 4));
+                const uint32_t p1 = flag_gather(u32(d - h), u32(F - h));
+                const uint32_t p2 = flag_gather(u32(Hmu - F), u32(Hm[r] - E[r]));
+                uint32_t& a1 = acc[2 * (r / 8)];
+                uint32_t& a2 = acc[2 * (r / 8) + 1];
+                a1 = r % 8 == 0 ? p1 : flag_push(a1, p1);
+                a2 = r % 8 == 0 ? p2 : flag_push(a2, p2);
                 diag = Hm[r];
                 Hmu = h - go2;
                 Hm[r] = Hmu;
@@ -572,13 +592,18 @@ __device__ __forceinline__ void sweep_trace_i16_col(const KParams& P, const Trac
             }
             Hlast = u32(Hm[R - 1]);
             Flast = u32(F);
+            // a stream pair (D, N of A and B; FX, EX of A and B) per 8 rows
+            // becomes one dword per pair; the last 4 rows of R % 8 == 4 sit
+            // in bits 4-7 of their stream bytes and become the 16-bit tails
             uint32_t va[NW + 1], vb[NW + 1];
 #pragma unroll
             for (int k = 0; k < NW; ++k) {
-                va[k] = __builtin_amdgcn_perm(w[2 * k + 1], w[2 * k], 0x05040100u);
-                vb[k] = __builtin_amdgcn_perm(w[2 * k + 1], w[2 * k], 0x07060302u);
+                va[k] = __builtin_amdgcn_perm(acc[2 * k + 1], acc[2 * k], 0x05040100u);
+                vb[k] = __builtin_amdgcn_perm(acc[2 * k + 1], acc[2 * k], 0x07060302u);
             }
-            const uint32_t tail = w[R / 4 - 1];
+            uint32_t tail = 0;
+            if constexpr (R % 8 == 4)
+                tail = (acc[2 * NW] & 0xF0F0F0F0u) | ((acc[2 * NW + 1] >> 4) & 0x0F0F0F0Fu);
             const int t = t0 + tt;
             rs.put(2 * g, l, t, va, tail);
             rs.put(2 * g + 1, l, t, vb, tail >> 16);
@@ -1044,24 +1069,30 @@ __device__ __forceinline__ void walk_pair(const KParams& P, const TraceArgs& T, 
             c_lane = lane;
             c_tb = tb;
         }
-        const uint32_t* blkp = slot + (c_tb - tb) * R;
-        const int byte = (t % kStage) * (R / 2) + (rr >> 1);
-        const uint32_t nib = (blkp[byte >> 2] >> (8 * (byte & 3) + 4 * (rr & 1))) & 15u;
+        // the step's R/2 bytes: a dword of D, N, FX, EX bytes per 8 rows,
+        // then for R % 8 == 4 the 16-bit tail (FX, D, EX, N nibbles)
+        const uint16_t* st = reinterpret_cast<const uint16_t*>(slot + (c_tb - tb) * R) + (t % kStage) * (R / 4);
+        const int j = rr >> 3, kk = rr & 7;
+        uint32_t fd, fn, ffx, fex;
+        if (j < (R >> 3)) {
+            const uint32_t v = ((uint32_t)st[2 * j] | ((uint32_t)st[2 * j + 1] << 16)) >> kk;
+            fd = v & 1u; fn = (v >> 8) & 1u; ffx = (v >> 16) & 1u; fex = (v >> 24) & 1u;
+        } else {
+            const uint32_t v = (uint32_t)st[2 * j] >> kk;
+            ffx = v & 1u; fd = (v >> 4) & 1u; fex = (v >> 8) & 1u; fn = (v >> 12) & 1u;
+        }
         uint32_t o;
         if (state == 0) {
-            const uint32_t code = nib & 3u;
-            if (code == 1u) { state = 1; continue; }
-            if (code == 2u) { state = 2; continue; }
-            if (code != 0u) { err = 1; break; }
+            if (fd) { state = fn ? 2 : 1; continue; }
             o = window_at(qa, x, qbase, q0, q1, q2, q3) == window_at(rb, y, rbase, r0, r1, r2, r3) ? 7u : 8u;
             --x; --y;
         } else if (state == 1) {
             o = 1u;
-            state = (nib & 4u) ? 1 : 0;
+            state = ffx ? 1 : 0;
             --x;
         } else {
             o = 2u;
-            state = (nib & 8u) ? 2 : 0;
+            state = fex ? 2 : 0;
             --y;
         }
         if (o == op) {

@@ -16,7 +16,9 @@
 //        N   H is not F (with D set: H comes from E, a reference residue
 //            over a gap; with D clear: from the diagonal)
 //        FX  F does not open here (F != H(i-1, j) - o: it extends)
-//        EX  E does not open here (E != H(i, j-1) - o)
+//        EX  E does not open in the next column (E(i, j+1) != H(i, j) - o:
+//            it extends); computed where E(i, j+1) is, and read by the walk
+//            when a gap move has brought it to (i, j)
 //      Step t of lane l holds rows l*R .. l*R+R-1 of column t - l (R a
 //      multiple of 4) in R/2 bytes: one dword per 8 rows, whose bytes are
 //      the D, N, FX and EX bits of those rows (bit k: row 8j+k), and for
@@ -256,16 +258,16 @@ __device__ __forceinline__ void sweep_trace(const KParams& P, const TraceArgs& T
                 const uint32_t nd = ne01((uint32_t)(h ^ d));
                 const uint32_t nf = ne01((uint32_t)(h ^ F));
                 const uint32_t fx = ne01((uint32_t)(F - Hmu));
-                const uint32_t ex = ne01((uint32_t)(E[r] - sat_sub(H[r], go)));
-                if (r < R / 8 * 8)
-                    wv[r / 8] |= (nd | (nf << 8) | (fx << 16) | (ex << 24)) << (r % 8);
-                else
-                    wv[r / 8] |= (fx | (nd << 4) | (ex << 8) | (nf << 12)) << (r % 8);
                 sc[r] = S.mat[bb_next + a[r]];
                 diag = H[r];
                 H[r] = h;
                 Hmu = sat_sub(h, go);
                 E[r] = imax(E[r] - ge, Hmu);
+                const uint32_t ex = ne01((uint32_t)(E[r] - Hmu));   // for the next column
+                if (r < R / 8 * 8)
+                    wv[r / 8] |= (nd | (nf << 8) | (fx << 16) | (ex << 24)) << (r % 8);
+                else
+                    wv[r / 8] |= (fx | (nd << 4) | (ex << 8) | (nf << 12)) << (r % 8);
             }
             Hlast = H[R - 1];
             Flast = F;
@@ -376,9 +378,12 @@ __device__ __forceinline__ void sweep_trace_i16(const KParams& P, const TraceArg
     const u16x2 zero = pk(K2);
     wave_lds_sync();
 
-    u16x2 H[R], E[R];
+    // H0/H1[r]: H of row r at the last column swept (even steps read H0 and
+    // write H1, odd steps the reverse, so that no register is copied per
+    // row, as in the column-word form); E[r]: E of row r at the next column
+    u16x2 H0[R], H1[R], E[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) { H[r] = zero; E[r] = zero; }
+    for (int r = 0; r < R; ++r) { H0[r] = zero; E[r] = zero; }
     uint32_t Hlast = K2, Flast = K2, Hup_prev = K2;
     const uint16_t* rblA = bufA + W - l;
     const uint16_t* rblB = bufB + W - l;
@@ -389,6 +394,64 @@ __device__ __forceinline__ void sweep_trace_i16(const KParams& P, const TraceArg
 #pragma unroll
         for (int r = 0; r < R; ++r) sc[r] = load_scores(S.mat, a0 + (int)(apk[r] & 0xFFFF), b0 + (int)(apk[r] >> 16));
     }
+    auto step = [&](u16x2 (&Ho)[R], u16x2 (&Hn)[R], int t0, int tt) {
+        const int bbA2 = rblA[tt + 2];
+        const int bbB2 = rblB[tt + 2];
+        const u16x2 Hup = pk((uint32_t)shift_in_group<W>((int)Hlast, (int)K2));
+        const u16x2 Fup = pk((uint32_t)shift_in_group_zero<W>((int)Flast));
+        u16x2 diag = pk(Hup_prev);
+        Hup_prev = u32(Hup);
+        u16x2 Hmu = pk_sat_sub(Hup, go2);
+        u16x2 F = Fup;
+        uint32_t acc[2 * NW + 2];   // per 8 rows: D, N streams and FX, EX streams
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            F = pk_max3(pk_sat_sub(F, ge2), Hmu, zero);
+            const u16x2 d = diag + sc[r];
+            const u16x2 h = pk_max3(d, E[r], F);
+            const uint32_t p1 = flag_gather(u32(d - h), u32(F - h));
+            const uint32_t xf = u32(Hmu - F);
+            sc[r] = load_scores(S.mat, bbA_next + (int)(apk[r] & 0xFFFF), bbB_next + (int)(apk[r] >> 16));
+            diag = Ho[r];
+            Hn[r] = h;
+            Hmu = pk_sat_sub(h, go2);
+            E[r] = pk_max3(pk_sat_sub(E[r], ge2), Hmu, zero);
+            const uint32_t p2 = flag_gather(xf, u32(Hmu - E[r]));
+            uint32_t& a1 = acc[2 * (r / 8)];
+            uint32_t& a2 = acc[2 * (r / 8) + 1];
+            a1 = r % 8 == 0 ? p1 : flag_push(a1, p1);
+            a2 = r % 8 == 0 ? p2 : flag_push(a2, p2);
+        }
+        Hlast = u32(Hn[R - 1]);
+        Flast = u32(F);
+        bbA_next = bbA2;
+        bbB_next = bbB2;
+        // a stream pair (D, N of A and B; FX, EX of A and B) per 8 rows
+        // becomes one dword per pair; the last 4 rows of R % 8 == 4 sit in
+        // bits 4-7 of their stream bytes and become the 16-bit tails
+        uint32_t va[NW + 1], vb[NW + 1];
+#pragma unroll
+        for (int k = 0; k < NW; ++k) {
+            va[k] = __builtin_amdgcn_perm(acc[2 * k + 1], acc[2 * k], 0x05040100u);
+            vb[k] = __builtin_amdgcn_perm(acc[2 * k + 1], acc[2 * k], 0x07060302u);
+        }
+        uint32_t tail = 0;
+        if constexpr (R % 8 == 4)
+            tail = (acc[2 * NW] & 0xF0F0F0F0u) | ((acc[2 * NW + 1] >> 4) & 0x0F0F0F0Fu);
+        const int t = t0 + tt;
+        rs.put(2 * g, l, t, va, tail);
+        rs.put(2 * g + 1, l, t, vb, tail >> 16);
+        if ((t & (kStage - 1)) == kStage - 1 || t == steps - 1) {
+            wave_lds_sync();
+#pragma unroll
+            for (int p = 0; p < 2 * G; ++p) {
+                uint32_t* rp = readlane_ptr((p & 1) ? recB : recA, (p / 2) * W);
+                const int sp = __builtin_amdgcn_readlane((p & 1) ? stepsB : stepsA, (p / 2) * W);
+                if (rp && (t & ~(kStage - 1)) < sp) rs.flush(p, rp, t / kStage, lane);
+            }
+            wave_lds_sync();
+        }
+    };
     for (int t0 = 0; t0 < steps; t0 += kChunk) {
         const bool more = t0 + kChunk < steps;
         if (more) {
@@ -396,62 +459,17 @@ __device__ __forceinline__ void sweep_trace_i16(const KParams& P, const TraceArg
             stB.load(P.refs, JB, P.order, t0 + kChunk, l);
         }
         const int tn = __builtin_amdgcn_readfirstlane(steps - t0 < kChunk ? steps - t0 : kChunk);
-        for (int tt = 0; tt < tn; ++tt) {
-            const int bbA2 = rblA[tt + 2];
-            const int bbB2 = rblB[tt + 2];
-            const u16x2 Hup = pk((uint32_t)shift_in_group<W>((int)Hlast, (int)K2));
-            const u16x2 Fup = pk((uint32_t)shift_in_group_zero<W>((int)Flast));
-            u16x2 diag = pk(Hup_prev);
-            Hup_prev = u32(Hup);
-            u16x2 Hmu = pk_sat_sub(Hup, go2);
-            u16x2 F = Fup;
-            uint32_t acc[2 * NW + 2];   // per 8 rows: D, N streams and FX, EX streams
+        int tt = 0;
+        for (; tt + 1 < tn; tt += 2) {
+            step(H0, H1, t0, tt);
+            step(H1, H0, t0, tt + 1);
+        }
+        static_assert(kChunk % 2 == 0, "every chunk but the last ends on an odd step");
+        if (tt < tn) {
+            // an odd chunk (only the last one) ends in H1
+            step(H0, H1, t0, tt);
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                F = pk_max3(pk_sat_sub(F, ge2), Hmu, zero);
-                const u16x2 d = diag + sc[r];
-                const u16x2 h = pk_max3(d, E[r], F);
-                const uint32_t p1 = flag_gather(u32(d - h), u32(F - h));
-                const uint32_t p2 = flag_gather(u32(Hmu - F), u32(pk_sat_sub(H[r], go2) - E[r]));
-                uint32_t& a1 = acc[2 * (r / 8)];
-                uint32_t& a2 = acc[2 * (r / 8) + 1];
-                a1 = r % 8 == 0 ? p1 : flag_push(a1, p1);
-                a2 = r % 8 == 0 ? p2 : flag_push(a2, p2);
-                sc[r] = load_scores(S.mat, bbA_next + (int)(apk[r] & 0xFFFF), bbB_next + (int)(apk[r] >> 16));
-                diag = H[r];
-                H[r] = h;
-                Hmu = pk_sat_sub(h, go2);
-                E[r] = pk_max3(pk_sat_sub(E[r], ge2), Hmu, zero);
-            }
-            Hlast = u32(H[R - 1]);
-            Flast = u32(F);
-            bbA_next = bbA2;
-            bbB_next = bbB2;
-            // a stream pair (D, N of A and B; FX, EX of A and B) per 8 rows
-            // becomes one dword per pair; the last 4 rows of R % 8 == 4 sit
-            // in bits 4-7 of their stream bytes and become the 16-bit tails
-            uint32_t va[NW + 1], vb[NW + 1];
-#pragma unroll
-            for (int k = 0; k < NW; ++k) {
-                va[k] = __builtin_amdgcn_perm(acc[2 * k + 1], acc[2 * k], 0x05040100u);
-                vb[k] = __builtin_amdgcn_perm(acc[2 * k + 1], acc[2 * k], 0x07060302u);
-            }
-            uint32_t tail = 0;
-            if constexpr (R % 8 == 4)
-                tail = (acc[2 * NW] & 0xF0F0F0F0u) | ((acc[2 * NW + 1] >> 4) & 0x0F0F0F0Fu);
-            const int t = t0 + tt;
-            rs.put(2 * g, l, t, va, tail);
-            rs.put(2 * g + 1, l, t, vb, tail >> 16);
-            if ((t & (kStage - 1)) == kStage - 1 || t == steps - 1) {
-                wave_lds_sync();
-#pragma unroll
-                for (int p = 0; p < 2 * G; ++p) {
-                    uint32_t* rp = readlane_ptr((p & 1) ? recB : recA, (p / 2) * W);
-                    const int sp = __builtin_amdgcn_readlane((p & 1) ? stepsB : stepsA, (p / 2) * W);
-                    if (rp && (t & ~(kStage - 1)) < sp) rs.flush(p, rp, t / kStage, lane);
-                }
-                wave_lds_sync();
-            }
+            for (int r = 0; r < R; ++r) H0[r] = H1[r];
         }
         if (more) {
             wave_lds_sync();
@@ -545,15 +563,79 @@ __device__ __forceinline__ void sweep_trace_i16_col(const KParams& P, const Trac
     const uint32_t hm_top = (K - goA) | ((K - goB) << 16);   // Hm of the zero boundary
     wave_lds_sync();
 
-    // Hm[r]: H - o of row r at the last column swept; E[r]: E of row r at the
+    // Hm0/Hm1[r]: H - o of row r at the last column swept (even steps read
+    // Hm0 and write Hm1, odd steps the reverse: a row's old value is still
+    // needed as the next row's diagonal after its new one is computed, so one
+    // array would cost a register copy per row); E[r]: E of row r at the
     // next column
-    u16x2 Hm[R], E[R];
+    u16x2 Hm0[R], Hm1[R], E[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) { Hm[r] = pk(hm_top); E[r] = zero; }
+    for (int r = 0; r < R; ++r) { Hm0[r] = pk(hm_top); E[r] = zero; }
     uint32_t Hlast = hm_top, Flast = K2, Hup_prev = hm_top;
     const uint32_t* rblA = bufA + W - l;   // rblA[tt] = column word of step t0 + tt
     const uint32_t* rblB = bufB + W - l;
-    uint32_t nxA = rblA[0], nxB = rblB[0];
+    // step t of the chunk: Ho holds the last column's Hm, Hn receives this
+    // one's; (ca, cb) are this step's column words, the next step's are
+    // read into (na, nb)
+    auto step = [&](u16x2 (&Ho)[R], u16x2 (&Hn)[R], uint32_t ca, uint32_t cb, uint32_t& na, uint32_t& nb,
+                    int t0, int tt) {
+        na = rblA[tt + 1];
+        nb = rblB[tt + 1];
+        const u16x2 Hmu0 = pk((uint32_t)shift_in_group<W>((int)Hlast, (int)hm_top));
+        // F above the group is 0 (K); a zero fill gives the same F below
+        // because of the max with K
+        const u16x2 Fup = pk((uint32_t)shift_in_group_zero<W>((int)Flast));
+        u16x2 diag = pk(Hup_prev);
+        Hup_prev = u32(Hmu0);
+        u16x2 Hmu = Hmu0;
+        u16x2 F = Fup;
+        uint32_t acc[2 * NW + 2];   // per 8 rows: D, N streams and FX, EX streams
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            F = pk_max3(pk_sat_sub(F, ge2), Hmu, zero);
+            const u16x2 d = diag + pk(__builtin_amdgcn_perm(cb, ca, sel[r]));
+            const u16x2 h = pk_max3(d, E[r], F);
+            const uint32_t p1 = flag_gather(u32(d - h), u32(F - h));
+            const uint32_t xf = u32(Hmu - F);
+            diag = Ho[r];
+            Hmu = h - go2;
+            Hn[r] = Hmu;
+            E[r] = pk_max3(pk_sat_sub(E[r], ge2), Hmu, zero);
+            const uint32_t p2 = flag_gather(xf, u32(Hmu - E[r]));
+            uint32_t& a1 = acc[2 * (r / 8)];
+            uint32_t& a2 = acc[2 * (r / 8) + 1];
+            a1 = r % 8 == 0 ? p1 : flag_push(a1, p1);
+            a2 = r % 8 == 0 ? p2 : flag_push(a2, p2);
+        }
+        Hlast = u32(Hn[R - 1]);
+        Flast = u32(F);
+        // a stream pair (D, N of A and B; FX, EX of A and B) per 8 rows
+        // becomes one dword per pair; the last 4 rows of R % 8 == 4 sit in
+        // bits 4-7 of their stream bytes and become the 16-bit tails
+        uint32_t va[NW + 1], vb[NW + 1];
+#pragma unroll
+        for (int k = 0; k < NW; ++k) {
+            va[k] = __builtin_amdgcn_perm(acc[2 * k + 1], acc[2 * k], 0x05040100u);
+            vb[k] = __builtin_amdgcn_perm(acc[2 * k + 1], acc[2 * k], 0x07060302u);
+        }
+        uint32_t tail = 0;
+        if constexpr (R % 8 == 4)
+            tail = (acc[2 * NW] & 0xF0F0F0F0u) | ((acc[2 * NW + 1] >> 4) & 0x0F0F0F0Fu);
+        const int t = t0 + tt;
+        rs.put(2 * g, l, t, va, tail);
+        rs.put(2 * g + 1, l, t, vb, tail >> 16);
+        if ((t & (kStage - 1)) == kStage - 1 || t == steps - 1) {
+            wave_lds_sync();
+#pragma unroll
+            for (int p = 0; p < 2 * G; ++p) {
+                uint32_t* rp = readlane_ptr((p & 1) ? recB : recA, (p / 2) * W);
+                const int sp = __builtin_amdgcn_readlane((p & 1) ? stepsB : stepsA, (p / 2) * W);
+                if (rp && (t & ~(kStage - 1)) < sp) rs.flush(p, rp, t / kStage, lane);
+            }
+            wave_lds_sync();
+        }
+    };
+    uint32_t cA0 = rblA[0], cB0 = rblB[0], cA1 = 0, cB1 = 0;
     for (int t0 = 0; t0 < steps; t0 += kChunk) {
         const bool more = t0 + kChunk < steps;
         if (more) {
@@ -561,70 +643,25 @@ __device__ __forceinline__ void sweep_trace_i16_col(const KParams& P, const Trac
             stB.load(P.refs, JB, P.order, t0 + kChunk, l);
         }
         const int tn = __builtin_amdgcn_readfirstlane(steps - t0 < kChunk ? steps - t0 : kChunk);
-        for (int tt = 0; tt < tn; ++tt) {
-            const uint32_t ca = nxA, cb = nxB;
-            nxA = rblA[tt + 1];
-            nxB = rblB[tt + 1];
-            const u16x2 Hmu0 = pk((uint32_t)shift_in_group<W>((int)Hlast, (int)hm_top));
-            // F above the group is 0 (K); a zero fill gives the same F below
-            // because of the max with K
-            const u16x2 Fup = pk((uint32_t)shift_in_group_zero<W>((int)Flast));
-            u16x2 diag = pk(Hup_prev);
-            Hup_prev = u32(Hmu0);
-            u16x2 Hmu = Hmu0;
-            u16x2 F = Fup;
-            uint32_t acc[2 * NW + 2];   // per 8 rows: D, N streams and FX, EX streams
+        int tt = 0;
+        for (; tt + 1 < tn; tt += 2) {
+            step(Hm0, Hm1, cA0, cB0, cA1, cB1, t0, tt);
+            step(Hm1, Hm0, cA1, cB1, cA0, cB0, t0, tt + 1);
+        }
+        static_assert(kChunk % 2 == 0, "every chunk but the last ends on an odd step");
+        if (tt < tn) {
+            // an odd chunk (only the last one) ends in Hm1
+            step(Hm0, Hm1, cA0, cB0, cA1, cB1, t0, tt);
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                F = pk_max3(pk_sat_sub(F, ge2), Hmu, zero);
-                const u16x2 d = diag + pk(__builtin_amdgcn_perm(cb, ca, sel[r]));
-                const u16x2 h = pk_max3(d, E[r], F);
-                const uint32_t p1 = flag_gather(u32(d - h), u32(F - h));
-                const uint32_t p2 = flag_gather(u32(Hmu - F), u32(Hm[r] - E[r]));
-                uint32_t& a1 = acc[2 * (r / 8)];
-                uint32_t& a2 = acc[2 * (r / 8) + 1];
-                a1 = r % 8 == 0 ? p1 : flag_push(a1, p1);
-                a2 = r % 8 == 0 ? p2 : flag_push(a2, p2);
-                diag = Hm[r];
-                Hmu = h - go2;
-                Hm[r] = Hmu;
-                E[r] = pk_max3(pk_sat_sub(E[r], ge2), Hmu, zero);
-            }
-            Hlast = u32(Hm[R - 1]);
-            Flast = u32(F);
-            // a stream pair (D, N of A and B; FX, EX of A and B) per 8 rows
-            // becomes one dword per pair; the last 4 rows of R % 8 == 4 sit
-            // in bits 4-7 of their stream bytes and become the 16-bit tails
-            uint32_t va[NW + 1], vb[NW + 1];
-#pragma unroll
-            for (int k = 0; k < NW; ++k) {
-                va[k] = __builtin_amdgcn_perm(acc[2 * k + 1], acc[2 * k], 0x05040100u);
-                vb[k] = __builtin_amdgcn_perm(acc[2 * k + 1], acc[2 * k], 0x07060302u);
-            }
-            uint32_t tail = 0;
-            if constexpr (R % 8 == 4)
-                tail = (acc[2 * NW] & 0xF0F0F0F0u) | ((acc[2 * NW + 1] >> 4) & 0x0F0F0F0Fu);
-            const int t = t0 + tt;
-            rs.put(2 * g, l, t, va, tail);
-            rs.put(2 * g + 1, l, t, vb, tail >> 16);
-            if ((t & (kStage - 1)) == kStage - 1 || t == steps - 1) {
-                wave_lds_sync();
-#pragma unroll
-                for (int p = 0; p < 2 * G; ++p) {
-                    uint32_t* rp = readlane_ptr((p & 1) ? recB : recA, (p / 2) * W);
-                    const int sp = __builtin_amdgcn_readlane((p & 1) ? stepsB : stepsA, (p / 2) * W);
-                    if (rp && (t & ~(kStage - 1)) < sp) rs.flush(p, rp, t / kStage, lane);
-                }
-                wave_lds_sync();
-            }
+            for (int r = 0; r < R; ++r) Hm0[r] = Hm1[r];
         }
         if (more) {
             wave_lds_sync();
             stA.store_col(bufA, JA, AA, S.colw[JA.sid], t0 + kChunk, l, bad);
             stB.store_col(bufB, JB, AB, S.colw[JB.sid], t0 + kChunk, l, bad);
             wave_lds_sync();
-            nxA = rblA[0];
-            nxB = rblB[0];
+            cA0 = rblA[0];
+            cB0 = rblB[0];
         }
     }
 }
@@ -1034,7 +1071,7 @@ __device__ __forceinline__ void walk_pair(const KParams& P, const TraceArgs& T, 
     uint32_t q0 = 0, q1 = 0, q2 = 0, q3 = 0, r0 = 0, r1 = 0, r2 = 0, r3 = 0;
     const int64_t room = end - beg;
     int x = rows - 1, y = cols - 1;
-    int state = 0;   // 0 = H, 1 = F (query gap), 2 = E (reference gap)
+    int state = 0;   // 0 = H, 1 = F (query gap), 2 = E (reference gap), 3 = E moved, choice pending
     int64_t k = 0;   // runs written
     uint32_t op = 0, len = 0;
     int err = 0;     // 1 internal, 2 room
@@ -1081,6 +1118,9 @@ __device__ __forceinline__ void walk_pair(const KParams& P, const TraceArgs& T, 
             const uint32_t v = (uint32_t)st[2 * j] >> kk;
             ffx = v & 1u; fd = (v >> 4) & 1u; fex = (v >> 8) & 1u; fn = (v >> 12) & 1u;
         }
+        // a gap move from (x, y+1) left E's choice there open: this cell's
+        // record holds whether E(x, y+1) extends E(x, y)
+        if (state == 3) state = fex ? 2 : 0;
         uint32_t o;
         if (state == 0) {
             if (fd) { state = fn ? 2 : 1; continue; }
@@ -1092,7 +1132,7 @@ __device__ __forceinline__ void walk_pair(const KParams& P, const TraceArgs& T, 
             --x;
         } else {
             o = 2u;
-            state = fex ? 2 : 0;
+            state = 3;
             --y;
         }
         if (o == op) {

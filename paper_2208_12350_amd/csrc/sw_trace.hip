@@ -121,16 +121,35 @@ struct RecordStage {
             d[2 * NW] = (uint16_t)tail;
         }
     }
+    // Bit (c0 / 64) * PPW + p of the result: this lane's chunk of pair p in
+    // the copy round starting at chunk c0 lies in a lane with rows of the
+    // pair's box (n_rows rows).  Taken once per wave item, OR-ed over p.
+    static_assert((W * R / 4 + 63) / 64 * PPW <= 32, "one bit per copy round and pair");
+    __device__ __forceinline__ static uint32_t row_bits(int p, int n_rows, int lane) {
+        uint32_t m = 0;
+        const int qlim = (n_rows + R - 1) / R;
+#pragma unroll
+        for (int c0 = 0; c0 < W * R / 4; c0 += 64)
+            m |= ((c0 + lane) / (R / 4) < qlim ? 1u : 0u) << ((c0 / 64) * PPW + p);
+        return m;
+    }
     // Copy block b of pair p (W * R dwords) to its record, 16 bytes per
     // lane at a time: chunk c is 16-byte unit c % (R/4) of lane c / (R/4).
-    __device__ __forceinline__ void flush(int p, uint32_t* rec, int b, int lane) const {
+    // A lane's part of the block is left unwritten when it holds no cell of
+    // the pair's box: the lane's rows all lie past the box (its bit in
+    // `rows` is clear, see row_bits), or the block's steps all come before
+    // the lane's first column (step q).  The walk never reads such a part
+    // (it reads a lane's block only for a step of a box cell, and the block
+    // before it only for a later such step).
+    __device__ __forceinline__ void flush(int p, uint32_t* rec, int b, int lane, uint32_t rows) const {
         uint32_t* dst = rec + (int64_t)b * W * R;
         const uint32_t* src = lds + p * W * kStride;
 #pragma unroll
         for (int c0 = 0; c0 < W * R / 4; c0 += 64) {
             const int c = c0 + lane;
             const int q = c / (R / 4), k = c % (R / 4);
-            if (W * R / 4 >= c0 + 64 || c < W * R / 4)
+            const bool cell = ((rows >> ((c0 / 64) * PPW + p)) & 1u) && kStage * b + kStage > q;
+            if ((W * R / 4 >= c0 + 64 || c < W * R / 4) && cell)
                 *reinterpret_cast<uint4*>(dst + 4 * c) =
                     *reinterpret_cast<const uint4*>(src + q * kStride + 4 * k);
         }
@@ -196,6 +215,9 @@ __device__ __forceinline__ void sweep_trace(const KParams& P, const TraceArgs& T
         }
     }
     const int my_steps = J.m > 0 ? J.m + W - 1 : 0;
+    uint32_t rowbits = 0;   // flush chunks in lanes with box rows
+#pragma unroll
+    for (int p = 0; p < G; ++p) rowbits |= rs.row_bits(p, __builtin_amdgcn_readlane(J.n, p * W), lane);
     int mmax = J.m;
     for (int off = 32; off > 0; off >>= 1) mmax = imax(mmax, __shfl_xor(mmax, off));
     const int steps = __builtin_amdgcn_readfirstlane(mmax > 0 ? mmax + W - 1 : 0);
@@ -280,7 +302,7 @@ __device__ __forceinline__ void sweep_trace(const KParams& P, const TraceArgs& T
                 for (int p = 0; p < G; ++p) {
                     uint32_t* rp = readlane_ptr(rec, p * W);
                     const int sp = __builtin_amdgcn_readlane(my_steps, p * W);
-                    if (rp && (t & ~(kStage - 1)) < sp) rs.flush(p, rp, t / kStage, lane);
+                    if (rp && (t & ~(kStage - 1)) < sp) rs.flush(p, rp, t / kStage, lane, rowbits);
                 }
                 wave_lds_sync();
             }
@@ -339,6 +361,10 @@ __device__ __forceinline__ void sweep_trace_i16(const KParams& P, const TraceArg
     uint32_t* recB = trace_record(P, T, pairB, JB, W, R);
     const int stepsA = JA.m > 0 ? JA.m + W - 1 : 0;
     const int stepsB = JB.m > 0 ? JB.m + W - 1 : 0;
+    uint32_t rowbits = 0;   // flush chunks in lanes with box rows (pairs A, B of each group)
+#pragma unroll
+    for (int p = 0; p < 2 * G; ++p)
+        rowbits |= rs.row_bits(p, __builtin_amdgcn_readlane((p & 1) ? JB.n : JA.n, (p / 2) * W), lane);
     int mmax = imax(JA.m, JB.m);
     for (int off = 32; off > 0; off >>= 1) mmax = imax(mmax, __shfl_xor(mmax, off));
     const int steps = __builtin_amdgcn_readfirstlane(mmax > 0 ? mmax + W - 1 : 0);
@@ -447,7 +473,7 @@ __device__ __forceinline__ void sweep_trace_i16(const KParams& P, const TraceArg
             for (int p = 0; p < 2 * G; ++p) {
                 uint32_t* rp = readlane_ptr((p & 1) ? recB : recA, (p / 2) * W);
                 const int sp = __builtin_amdgcn_readlane((p & 1) ? stepsB : stepsA, (p / 2) * W);
-                if (rp && (t & ~(kStage - 1)) < sp) rs.flush(p, rp, t / kStage, lane);
+                if (rp && (t & ~(kStage - 1)) < sp) rs.flush(p, rp, t / kStage, lane, rowbits);
             }
             wave_lds_sync();
         }
@@ -518,6 +544,10 @@ __device__ __forceinline__ void sweep_trace_i16_col(const KParams& P, const Trac
     uint32_t* recB = trace_record(P, T, pairB, JB, W, R);
     const int stepsA = JA.m > 0 ? JA.m + W - 1 : 0;
     const int stepsB = JB.m > 0 ? JB.m + W - 1 : 0;
+    uint32_t rowbits = 0;   // flush chunks in lanes with box rows (pairs A, B of each group)
+#pragma unroll
+    for (int p = 0; p < 2 * G; ++p)
+        rowbits |= rs.row_bits(p, __builtin_amdgcn_readlane((p & 1) ? JB.n : JA.n, (p / 2) * W), lane);
     int mmax = imax(JA.m, JB.m);
     for (int off = 32; off > 0; off >>= 1) mmax = imax(mmax, __shfl_xor(mmax, off));
     const int steps = __builtin_amdgcn_readfirstlane(mmax > 0 ? mmax + W - 1 : 0);
@@ -630,7 +660,7 @@ __device__ __forceinline__ void sweep_trace_i16_col(const KParams& P, const Trac
             for (int p = 0; p < 2 * G; ++p) {
                 uint32_t* rp = readlane_ptr((p & 1) ? recB : recA, (p / 2) * W);
                 const int sp = __builtin_amdgcn_readlane((p & 1) ? stepsB : stepsA, (p / 2) * W);
-                if (rp && (t & ~(kStage - 1)) < sp) rs.flush(p, rp, t / kStage, lane);
+                if (rp && (t & ~(kStage - 1)) < sp) rs.flush(p, rp, t / kStage, lane, rowbits);
             }
             wave_lds_sync();
         }

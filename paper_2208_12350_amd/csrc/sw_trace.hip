@@ -133,25 +133,63 @@ struct RecordStage {
             m |= ((c0 + lane) / (R / 4) < qlim ? 1u : 0u) << ((c0 / 64) * PPW + p);
         return m;
     }
-    // Copy block b of pair p (W * R dwords) to its record, 16 bytes per
-    // lane at a time: chunk c is 16-byte unit c % (R/4) of lane c / (R/4).
+    // Copy block b of every pair of the wavefront (W * R dwords each) to its
+    // record, 16 bytes per lane at a time: chunk c of a pair is 16-byte unit
+    // c % (R/4) of lane c / (R/4), copy round k takes chunks 64k .. 64k+63.
+    // rec_of(p) and steps_of(p) give pair p's record (nullptr: none) and
+    // sweep steps.  Up to 8 chunks per lane are read from LDS before the
+    // first store, so their round trips overlap.
     // A lane's part of the block is left unwritten when it holds no cell of
     // the pair's box: the lane's rows all lie past the box (its bit in
     // `rows` is clear, see row_bits), or the block's steps all come before
     // the lane's first column (step q).  The walk never reads such a part
     // (it reads a lane's block only for a step of a box cell, and the block
     // before it only for a later such step).
-    __device__ __forceinline__ void flush(int p, uint32_t* rec, int b, int lane, uint32_t rows) const {
-        uint32_t* dst = rec + (int64_t)b * W * R;
-        const uint32_t* src = lds + p * W * kStride;
+    static constexpr int kRounds = (W * R / 4 + 63) / 64;
+    __device__ __forceinline__ uint4 chunk(int p, int k, int lane) const {
+        int c = 64 * k + lane;
+        c = c < W * R / 4 ? c : W * R / 4 - 1;   // lanes past the block read its last chunk
+        return *reinterpret_cast<const uint4*>(lds + p * W * kStride + c / (R / 4) * kStride + 4 * (c % (R / 4)));
+    }
+    __device__ __forceinline__ void store(int p, int k, uint32_t* rec, int b, int lane, uint32_t rows,
+                                          const uint4& v) const {
+        const int c = 64 * k + lane;
+        const int q = c / (R / 4);
+        const bool cell = ((rows >> (k * PPW + p)) & 1u) && kStage * b + kStage > q;
+        if ((W * R / 4 >= 64 * k + 64 || c < W * R / 4) && cell)
+            *reinterpret_cast<uint4*>(rec + (int64_t)b * W * R + 4 * c) = v;
+    }
+    template <typename RecOf, typename StepsOf>
+    __device__ __forceinline__ void flush(int t, int lane, uint32_t rows, RecOf rec_of, StepsOf steps_of) const {
+        const int b = t / kStage;
+        if constexpr (PPW * kRounds <= 8) {
+            uint4 v[PPW][kRounds];
 #pragma unroll
-        for (int c0 = 0; c0 < W * R / 4; c0 += 64) {
-            const int c = c0 + lane;
-            const int q = c / (R / 4), k = c % (R / 4);
-            const bool cell = ((rows >> ((c0 / 64) * PPW + p)) & 1u) && kStage * b + kStage > q;
-            if ((W * R / 4 >= c0 + 64 || c < W * R / 4) && cell)
-                *reinterpret_cast<uint4*>(dst + 4 * c) =
-                    *reinterpret_cast<const uint4*>(src + q * kStride + 4 * k);
+            for (int p = 0; p < PPW; ++p)
+#pragma unroll
+                for (int k = 0; k < kRounds; ++k) v[p][k] = chunk(p, k, lane);
+#pragma unroll
+            for (int p = 0; p < PPW; ++p) {
+                uint32_t* rp = rec_of(p);
+                if (rp && (t & ~(kStage - 1)) < steps_of(p))
+#pragma unroll
+                    for (int k = 0; k < kRounds; ++k) store(p, k, rp, b, lane, rows, v[p][k]);
+            }
+        } else {
+#pragma unroll
+            for (int p = 0; p < PPW; ++p) {
+                constexpr int KB = kRounds < 8 ? kRounds : 8;
+#pragma unroll
+                for (int k0 = 0; k0 < kRounds; k0 += KB) {
+                    uint4 v[KB];
+#pragma unroll
+                    for (int k = 0; k < KB; ++k) v[k] = chunk(p, k0 + k, lane);
+                    uint32_t* rp = rec_of(p);
+                    if (rp && (t & ~(kStage - 1)) < steps_of(p))
+#pragma unroll
+                        for (int k = 0; k < KB; ++k) store(p, k0 + k, rp, b, lane, rows, v[k]);
+                }
+            }
         }
     }
 };
@@ -298,12 +336,8 @@ __device__ __forceinline__ void sweep_trace(const KParams& P, const TraceArgs& T
             rs.put(g, l, t, wv, wv[NW - 1]);
             if ((t & (kStage - 1)) == kStage - 1 || t == steps - 1) {
                 wave_lds_sync();
-#pragma unroll
-                for (int p = 0; p < G; ++p) {
-                    uint32_t* rp = readlane_ptr(rec, p * W);
-                    const int sp = __builtin_amdgcn_readlane(my_steps, p * W);
-                    if (rp && (t & ~(kStage - 1)) < sp) rs.flush(p, rp, t / kStage, lane, rowbits);
-                }
+                rs.flush(t, lane, rowbits, [&](int p) { return readlane_ptr(rec, p * W); },
+                         [&](int p) { return __builtin_amdgcn_readlane(my_steps, p * W); });
                 wave_lds_sync();
             }
         }
@@ -469,12 +503,8 @@ __device__ __forceinline__ void sweep_trace_i16(const KParams& P, const TraceArg
         rs.put(2 * g + 1, l, t, vb, tail >> 16);
         if ((t & (kStage - 1)) == kStage - 1 || t == steps - 1) {
             wave_lds_sync();
-#pragma unroll
-            for (int p = 0; p < 2 * G; ++p) {
-                uint32_t* rp = readlane_ptr((p & 1) ? recB : recA, (p / 2) * W);
-                const int sp = __builtin_amdgcn_readlane((p & 1) ? stepsB : stepsA, (p / 2) * W);
-                if (rp && (t & ~(kStage - 1)) < sp) rs.flush(p, rp, t / kStage, lane, rowbits);
-            }
+            rs.flush(t, lane, rowbits, [&](int p) { return readlane_ptr((p & 1) ? recB : recA, (p / 2) * W); },
+                     [&](int p) { return __builtin_amdgcn_readlane((p & 1) ? stepsB : stepsA, (p / 2) * W); });
             wave_lds_sync();
         }
     };
@@ -656,12 +686,8 @@ __device__ __forceinline__ void sweep_trace_i16_col(const KParams& P, const Trac
         rs.put(2 * g + 1, l, t, vb, tail >> 16);
         if ((t & (kStage - 1)) == kStage - 1 || t == steps - 1) {
             wave_lds_sync();
-#pragma unroll
-            for (int p = 0; p < 2 * G; ++p) {
-                uint32_t* rp = readlane_ptr((p & 1) ? recB : recA, (p / 2) * W);
-                const int sp = __builtin_amdgcn_readlane((p & 1) ? stepsB : stepsA, (p / 2) * W);
-                if (rp && (t & ~(kStage - 1)) < sp) rs.flush(p, rp, t / kStage, lane, rowbits);
-            }
+            rs.flush(t, lane, rowbits, [&](int p) { return readlane_ptr((p & 1) ? recB : recA, (p / 2) * W); },
+                     [&](int p) { return __builtin_amdgcn_readlane((p & 1) ? stepsB : stepsA, (p / 2) * W); });
             wave_lds_sync();
         }
     };

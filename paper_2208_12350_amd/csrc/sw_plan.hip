@@ -304,10 +304,16 @@ __global__ __launch_bounds__(kBinScanThreads) void sw_plan_bins_kernel(const Bin
     }
 }
 
+// Pairs with the trivial key get no position: nothing reads the sorted order
+// past the last bin (their results, if any, were written at
+// classification).  Skipping them keeps one counter from taking an atomic
+// per such pair, which serialised e.g. the pairs outside a path chunk.
 __global__ void sw_scatter_kernel(const int32_t* keys, const int32_t* n_dev, int32_t* offs, int32_t* order) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= *n_dev) return;
-    const int32_t pos = atomicAdd(&offs[keys[i]], 1);
+    const int32_t key = keys[i];
+    if (key == kTrivialKey) return;
+    const int32_t pos = atomicAdd(&offs[key], 1);
     order[pos] = (int32_t)i;
 }
 

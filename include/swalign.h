@@ -156,7 +156,8 @@ const char* sw_last_error(sw_handle* h);
  *               time even when its bin is empty); a pair with a longer
  *               query makes the call return SW_ETOOLONG
  *   "cigar_workspace"  device bytes for the path records of sw_align_cigar
- *               (default 32 GiB, at least about 123 MB)
+ *               (default half the device's memory, at least 32 GiB; the
+ *               smallest accepted value is about 123 MB)
  * Returns SW_OK or SW_EINVAL for an unknown key / bad value. */
 int sw_set_option(sw_handle* h, const char* key, int64_t value);
 /* Read an option, or the read-only "captures" (graphs captured so far) and
@@ -296,8 +297,9 @@ int sw_last_host_timing(sw_handle* h, double* enqueue_ms, double* wait_ms);
  * cigar_len (int32[n_pairs]) are DEVICE pointers owned by the caller; a room
  * of q_len + r_len runs per pair always suffices.  The paths are found by a
  * sweep of each box that stores 4 bits per cell in a device workspace (option
- * "cigar_workspace", default 32 GiB; batches whose boxes need more are done in
- * chunks), then a walk back per pair.  Synchronises `stream`; not captured in
+ * "cigar_workspace", default half the device's memory; batches whose boxes
+ * need more are done in chunks), then a walk back per pair.  The workspace is
+ * allocated to what the batch needs, up to that bound, and kept.  Synchronises `stream`; not captured in
  * a graph.  Errors: those of sw_align_batch; SW_EINVAL when a pair's room
  * is too small (its cigar_len is -1, the other pairs' paths are written);
  * SW_ENOMEM when the workspace cannot be allocated. */

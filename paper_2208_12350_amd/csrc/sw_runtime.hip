@@ -225,7 +225,7 @@ struct sw_handle {
     int64_t trace_cap = 0;
     uint8_t* d_ws = nullptr;             // path records of one chunk
     int64_t ws_alloc = 0;
-    int64_t opt_path_ws = (int64_t)32 << 30;
+    int64_t opt_path_ws = (int64_t)32 << 30;   // set to half the device's memory at creation
     int64_t* h_i64 = nullptr;            // pinned
     std::vector<hipEvent_t> tbin_ev;     // per path-sweep bin: sweep start, sweep end, walk end ("timing")
     int64_t last_path_cells = 0, last_path_bytes = 0;
@@ -732,6 +732,10 @@ sw_handle* sw_create(int device, const char* tuning) {
     hipDeviceProp_t prop;
     bool ok = hipGetDeviceProperties(&prop, device) == hipSuccess;
     h->n_cu = ok ? prop.multiProcessorCount : 0;
+    // path-record workspace: half the device's memory (144 GiB on a 288 GB
+    // MI355X), so that a batch's records usually fit in one chunk; each
+    // chunk costs its own planning and walk tails
+    if (ok && prop.totalGlobalMem / 2 > (size_t)h->opt_path_ws) h->opt_path_ws = (int64_t)(prop.totalGlobalMem / 2);
     build_bins(h);
     for (int sel = 0; sel < 2; ++sel) {
         h->route[sel].assign(kLutRows, -1);

@@ -216,7 +216,8 @@ struct sw_handle {
     std::vector<int> tresident_col;      // and for its column-word kernel
     std::vector<std::pair<TraceFn, int>> tfam_resident;   // per box-sweep family kernel
     std::vector<int> tfam_first;         // per path-sweep bin of the last chunk: first bin of its family launch, or -1
-    hipEvent_t tfam_ev[4] = {};          // end of a box-sweep family launch, for its walks on other streams
+    static constexpr int kTraceFams = 8; // box-sweep family launches per chunk at most
+    hipEvent_t tfam_ev[kTraceFams] = {}; // end of a box-sweep family launch, for its walks on other streams
     int32_t last_col_ok[SW_MAX_SCHEMES] = {0};   // column-word eligibility of the last score call's schemes
     BinInfo* d_tbins = nullptr;
     int8_t* d_tlut = nullptr;            // [2 * kLutRows] path-sweep bin per (precision, 16-row bucket of box rows)
@@ -764,7 +765,7 @@ sw_handle* sw_create(int device, const char* tuning) {
         ok = hipStreamCreateWithFlags(&h->fork[f], hipStreamNonBlocking) == hipSuccess;
     for (int f = 0; ok && f <= sw_handle::kForks; ++f)
         ok = hipEventCreateWithFlags(&h->fork_ev[f], hipEventDisableTiming) == hipSuccess;
-    for (int f = 0; ok && f < 4; ++f)
+    for (int f = 0; ok && f < sw_handle::kTraceFams; ++f)
         ok = hipEventCreateWithFlags(&h->tfam_ev[f], hipEventDisableTiming) == hipSuccess;
     if (ok) ok = hipMemcpy(h->d_bins, h->bins.data(), h->bins.size() * sizeof(BinInfo),
                            hipMemcpyHostToDevice) == hipSuccess;
@@ -1594,14 +1595,18 @@ static int trace_paths(sw_handle* h, const sw_batch* batch, const sw_scheme* sch
             mx = std::max(mx, (int)schemes[s].matrix[k]);
         K.max_score[s] = mx;
     }
-    // The column-word path sweep takes a call only when every scheme can use
-    // it (the score call just made uploaded their column words): each packed
-    // bin then runs its column-word kernel alone.  Splitting a bin's pairs
-    // between the two kernels costs more in launch tails (each kernel waits
-    // for its own longest box) than the column words save.
-    bool all_col = n_schemes > 0;
-    for (int s = 0; s < n_schemes && s < SW_MAX_SCHEMES; ++s) all_col = all_col && h->last_col_ok[s] != 0;
-    for (int s = 0; s < SW_MAX_SCHEMES; ++s) K.col_ok[s] = all_col && s < n_schemes ? 1 : 0;
+    // Pairs of schemes with column words (the score call just made uploaded
+    // them) take the column-word path sweep, the others the byte-table one:
+    // a packed bin's column-word pairs come first in its sorted order, and
+    // each part has its own kernel (variant 1, variant 0).
+    bool all_col = n_schemes > 0, any_col = false;
+    for (int s = 0; s < n_schemes && s < SW_MAX_SCHEMES; ++s) {
+        all_col = all_col && h->last_col_ok[s] != 0;
+        any_col = any_col || h->last_col_ok[s] != 0;
+    }
+    for (int s = 0; s < SW_MAX_SCHEMES; ++s) K.col_ok[s] = s < n_schemes && h->last_col_ok[s] ? 1 : 0;
+    // does bin e have pairs for variant v (1 column words, 0 byte table)?
+    auto wants = [&](const BinInfo& e, int v) { return v == 1 ? (e.col && any_col) : !(e.col && all_col); };
     TraceArgs T;
     memset(&T, 0, sizeof(T));
     T.rec_off = h->d_rec_off;
@@ -1676,9 +1681,10 @@ static int trace_paths(sw_handle* h, const sw_batch* batch, const sw_scheme* sch
                                                                       4 * std::max(1, h->n_cu));
             return launch_trace_walk(K, T, b, wblocks, active, path_off, path, path_len, ls);
         };
-        // Family launches (option "families"): one box-sweep kernel per lane
-        // width takes the items of all its bins, largest rows first; each
-        // member's walks follow it on its stream.
+        // Family launches (option "families"): per lane width and variant, one
+        // box-sweep kernel takes the items of all its bins, largest rows
+        // first.  The two variants of a width run on different streams; a
+        // member's walks start once both have swept it.
         h->tfam_first.assign(n_tb, -1);
         int n_fam = 0;
         for (int b = n_tb - 1; h->opt_families && b >= 0; --b) {
@@ -1686,41 +1692,59 @@ static int trace_paths(sw_handle* h, const sw_batch* batch, const sw_scheme* sch
             const BinInfo& e = h->tbins[b];
             const TraceFamily* f = trace_family(e.prec, e.W, e.R);
             if (!f) continue;
-            const int v = e.col && all_col ? 1 : 0;
-            const TraceFn fn = v ? f->col : f->fn;
             int members[kFamilyMax], nm = 0;
-            for (int k = 0; k < kFamilyMax; ++k) K.fam_bins[k] = -1;
+            int8_t fam_bins[kFamilyMax];
+            for (int k = 0; k < kFamilyMax; ++k) fam_bins[k] = -1;
             for (int k = 0; k < f->n; ++k) {
                 int mb = -1;
                 for (int t = 0; t < n_tb; ++t)
                     if (h->tbins[t].prec == f->prec && h->tbins[t].W == f->W && h->tbins[t].R == f->rows[k]) mb = t;
                 if (mb < 0 || h->tfam_first[mb] >= 0) continue;
-                K.fam_bins[k] = (int8_t)mb;
+                fam_bins[k] = (int8_t)mb;
                 members[nm++] = mb;
             }
-            int res = 0;
-            for (const auto& r : h->tfam_resident)
-                if (r.first == fn) res = r.second;
-            if (nm < 2 || !fn || res <= 0 || n_fam >= 4) continue;
+            // the variants its members need, each with its kernel and residency
+            TraceFn fns[2] = {nullptr, nullptr};
+            int res[2] = {0, 0}, n_var = 0;
+            bool ok = nm >= 2;
+            for (int v = 1; ok && v >= 0; --v) {
+                bool need_v = false;
+                for (int k = 0; k < nm; ++k) need_v = need_v || wants(h->tbins[members[k]], v);
+                if (!need_v) continue;
+                fns[v] = v ? f->col : f->fn;
+                for (const auto& r : h->tfam_resident)
+                    if (r.first == fns[v]) res[v] = r.second;
+                ok = fns[v] && res[v] > 0;
+                ++n_var;
+            }
+            if (!ok || n_var == 0 || n_fam + n_var > sw_handle::kTraceFams) continue;
             const int b0 = members[0];
             for (int k = 0; k < nm; ++k) h->tfam_first[members[k]] = b0;
+            for (int k = 0; k < kFamilyMax; ++k) K.fam_bins[k] = fam_bins[k];
             const int64_t need = (cap / e.ppw + 1 + kWavesPerBlock - 1) / kWavesPerBlock;
             hipStream_t ls = forks > 1 ? h->fork[launched++ % forks] : stream;
             if (timing) HIP_TRY(h, hipEventRecord(h->tbin_ev[3 * b0], ls));
-            hipLaunchKernelGGL(fn, dim3((int)std::min<int64_t>(need, res)), dim3(kBlock), 0, ls, K, T);
-            HIP_TRY(h, hipGetLastError());
+            hipEvent_t swept[2];
+            int n_swept = 0;
+            for (int v = 1; v >= 0; --v) {
+                if (!fns[v]) continue;
+                hipStream_t vs = n_swept == 0 || forks <= 1 ? ls : h->fork[launched++ % forks];
+                hipLaunchKernelGGL(fns[v], dim3((int)std::min<int64_t>(need, res[v])), dim3(kBlock), 0, vs, K, T);
+                HIP_TRY(h, hipGetLastError());
+                swept[n_swept] = h->tfam_ev[n_fam++];
+                if (forks > 1) HIP_TRY(h, hipEventRecord(swept[n_swept], vs));
+                ++n_swept;
+            }
             if (timing) HIP_TRY(h, hipEventRecord(h->tbin_ev[3 * b0 + 1], ls));
-            // the members' walks, once the sweep has written their records:
+            // the members' walks, once the sweeps have written their records:
             // spread over the forked streams so that they overlap other
             // sweeps (timing keeps everything on the caller's stream)
-            const hipEvent_t swept = h->tfam_ev[n_fam++];
-            if (forks > 1) HIP_TRY(h, hipEventRecord(swept, ls));
             for (int k = 0; k < nm; ++k) {
                 const int mb = members[k];
                 hipStream_t ws = ls;
-                if (forks > 1 && k > 0) {
-                    ws = h->fork[launched++ % forks];
-                    HIP_TRY(h, hipStreamWaitEvent(ws, swept, 0));
+                if (forks > 1) {
+                    if (k > 0) ws = h->fork[launched++ % forks];
+                    for (int q = 0; q < n_swept; ++q) HIP_TRY(h, hipStreamWaitEvent(ws, swept[q], 0));
                 }
                 if (timing && mb != b0) HIP_TRY(h, hipEventRecord(h->tbin_ev[3 * mb + 1], ws));
                 HIP_TRY(h, walk(mb, ws));
@@ -1734,13 +1758,16 @@ static int trace_paths(sw_handle* h, const sw_batch* batch, const sw_scheme* sch
             hipStream_t ls = forks > 1 ? h->fork[launched++ % forks] : stream;
             if (timing) HIP_TRY(h, hipEventRecord(h->tbin_ev[3 * b], ls));
             // the column-word kernel takes the bin's small-alphabet items,
-            // the table kernel the rest; a kernel with no items returns at once
-            // one kernel per bin: the column-word one when the call allows it
-            const int v = e.col && all_col ? 1 : 0;
-            const int blocks = (int)std::min<int64_t>(need, (v ? h->tresident_col : h->tresident)[b]);
-            set_range(K, b, v);
-            hipLaunchKernelGGL(trace_kernel(e.prec, e.W, e.R, v == 1), dim3(blocks), dim3(kBlock), 0, ls, K, T);
-            HIP_TRY(h, hipGetLastError());
+            // the table kernel the rest, one after the other on the bin's
+            // stream; a kernel with no items returns at once
+            for (int v = 1; v >= 0; --v) {
+                if (!wants(e, v)) continue;
+                const int blocks = (int)std::min<int64_t>(need, (v ? h->tresident_col : h->tresident)[b]);
+                set_range(K, b, v);
+                hipLaunchKernelGGL(trace_kernel(e.prec, e.W, e.R, v == 1), dim3(blocks), dim3(kBlock), 0, ls, K,
+                                   T);
+                HIP_TRY(h, hipGetLastError());
+            }
             if (timing) HIP_TRY(h, hipEventRecord(h->tbin_ev[3 * b + 1], ls));
             HIP_TRY(h, walk(b, ls));
             if (timing) HIP_TRY(h, hipEventRecord(h->tbin_ev[3 * b + 2], ls));
@@ -1776,7 +1803,7 @@ static int trace_paths(sw_handle* h, const sw_batch* batch, const sw_scheme* sch
         st.precision = h->tbins[b].prec;
         st.lanes = h->tbins[b].W;
         st.rows = h->tbins[b].R;
-        st.column = h->tbins[b].col && all_col ? 1 : 0;
+        st.column = h->tbins[b].col && any_col ? 1 : 0;   // its column-word pairs took column words
         st.tile = kChunk;
         st.pairs = (int64_t)cnt[kCtrTraceBinPairs + b];
         st.cells = (int64_t)cnt[kCtrTraceBinCells + b];

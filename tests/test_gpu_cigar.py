@@ -274,8 +274,9 @@ def test_column_word_and_table_path_sweeps_agree(aligner):
     # when every scheme of a call has at most four residues whose scores
     # plus the gap open cost fit a byte, the packed path sweep reads column
     # words; with colpath=0 every pair takes the table form, which must write
-    # the same records.  A call with one scheme outside that set takes the
-    # table form throughout.
+    # the same records.  In a call with one scheme outside that set, each
+    # packed bin is split: its pairs of eligible schemes take column words,
+    # the others the table form.
     from paper_2208_12350_amd.binding import Aligner
     rng = np.random.default_rng(21)
     M = rng.integers(-5, 1, size=(4, 4))
@@ -298,7 +299,7 @@ def test_column_word_and_table_path_sweeps_agree(aligner):
                W.from_pairs(pairs, [k % 3 for k in range(len(pairs))], [W.dna_scheme(), col_scheme, table_scheme])]
     table = Aligner(0, colpath=0)
     try:
-        for b, want_col in zip(batches, (1, 0)):
+        for b, want_col in zip(batches, (1, 1)):
             col = gpu_paths(aligner, b)
             used = {e["column"] for e in aligner.bin_stats() if e["pass"] == 2 and e["pairs"] and e["precision"] == 16}
             assert used == {want_col}, used

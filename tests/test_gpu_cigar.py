@@ -195,9 +195,12 @@ def test_full_size_dna_large_sampled(aligner):
     assert_paths_equal(b, (res, runs, off, ln), np.sort(idx))
 
 
-def test_chunked_workspace_gives_the_same_paths(aligner):
+@pytest.mark.parametrize("name,n", [("dna_large", 20000), ("mixed", 6000)])
+def test_chunked_workspace_gives_the_same_paths(aligner, name, n):
+    # mixed: each chunk's bins hold column-word and table pairs, and most
+    # pairs lie outside the chunk (the trivial key, left out of the order)
     from paper_2208_12350_amd.binding import Aligner
-    b = W.make_workload("dna_large", n_pairs=20000)
+    b = W.make_workload(name, n_pairs=n)
     whole = gpu_paths(aligner, b)
     _, rec_bytes, chunks, _, _ = aligner.cigar_stats()
     assert chunks == 1

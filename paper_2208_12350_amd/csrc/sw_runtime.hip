@@ -214,6 +214,7 @@ struct sw_handle {
     std::vector<BinInfo> tbins;          // path-sweep shapes
     std::vector<int> tresident;          // workgroups the device holds at once, per path-sweep bin
     std::vector<int> tresident_col;      // and for its column-word kernel
+    std::vector<int> tbin_min_rows;      // per path-sweep bin: the fewest box rows the routing sends to it
     std::vector<std::pair<TraceFn, int>> tfam_resident;   // per box-sweep family kernel
     std::vector<int> tfam_first;         // per path-sweep bin of the last chunk: first bin of its family launch, or -1
     static constexpr int kTraceFams = 8; // box-sweep family launches per chunk at most
@@ -689,6 +690,12 @@ static bool init_paths(sw_handle* h) {
             }
             if (best < 0) return false;
             lut[sel * kLutRows + k] = (int8_t)best;
+        }
+    h->tbin_min_rows.assign(h->tbins.size(), SW_MAX_QUERY + 1);
+    for (int sel = 0; sel < 2; ++sel)
+        for (int k = 0; k < kLutRows; ++k) {
+            const int b = lut[sel * kLutRows + k];
+            h->tbin_min_rows[b] = std::min(h->tbin_min_rows[b], 16 * k + 1);
         }
     h->tresident.assign(h->tbins.size(), 1);
     h->tresident_col.assign(h->tbins.size(), 1);
@@ -1607,6 +1614,23 @@ static int trace_paths(sw_handle* h, const sw_batch* batch, const sw_scheme* sch
     for (int s = 0; s < SW_MAX_SCHEMES; ++s) K.col_ok[s] = s < n_schemes && h->last_col_ok[s] ? 1 : 0;
     // does bin e have pairs for variant v (1 column words, 0 byte table)?
     auto wants = [&](const BinInfo& e, int v) { return v == 1 ? (e.col && any_col) : !(e.col && all_col); };
+    // Bins no pair can reach are not launched (a launch with no items still
+    // costs its stream a few microseconds, and its walks as many): with the
+    // caller's bound on query lengths ("max_query"), a box has at most that
+    // many rows, and its score S is at most max_query times the best
+    // substitution score, so no pair takes an int32 bin when that product
+    // fits the packed range.  (A call with a longer query has already
+    // failed with SW_ETOOLONG in the score passes.)
+    int mx_all = 0;
+    for (int s = 0; s < n_schemes && s < SW_MAX_SCHEMES; ++s) mx_all = std::max(mx_all, K.max_score[s]);
+    const int64_t max_q = h->opt_max_query;
+    const bool i16_only = h->opt_precision != 32 && max_q > 0 && max_q * mx_all <= kI16Limit;
+    auto reachable = [&](int b) {
+        const BinInfo& e = h->tbins[b];
+        if (max_q > 0 && h->tbin_min_rows[b] > max_q) return false;
+        if (e.prec == 16 && h->opt_precision == 32) return false;   // every pair takes int32
+        return !(e.prec == 32 && i16_only);
+    };
     TraceArgs T;
     memset(&T, 0, sizeof(T));
     T.rec_off = h->d_rec_off;
@@ -1688,7 +1712,7 @@ static int trace_paths(sw_handle* h, const sw_batch* batch, const sw_scheme* sch
         h->tfam_first.assign(n_tb, -1);
         int n_fam = 0;
         for (int b = n_tb - 1; h->opt_families && b >= 0; --b) {
-            if (h->tfam_first[b] >= 0) continue;
+            if (h->tfam_first[b] >= 0 || !reachable(b)) continue;
             const BinInfo& e = h->tbins[b];
             const TraceFamily* f = trace_family(e.prec, e.W, e.R);
             if (!f) continue;
@@ -1699,7 +1723,7 @@ static int trace_paths(sw_handle* h, const sw_batch* batch, const sw_scheme* sch
                 int mb = -1;
                 for (int t = 0; t < n_tb; ++t)
                     if (h->tbins[t].prec == f->prec && h->tbins[t].W == f->W && h->tbins[t].R == f->rows[k]) mb = t;
-                if (mb < 0 || h->tfam_first[mb] >= 0) continue;
+                if (mb < 0 || h->tfam_first[mb] >= 0 || !reachable(mb)) continue;
                 fam_bins[k] = (int8_t)mb;
                 members[nm++] = mb;
             }
@@ -1752,7 +1776,7 @@ static int trace_paths(sw_handle* h, const sw_batch* batch, const sw_scheme* sch
             }
         }
         for (int b = n_tb - 1; b >= 0; --b) {
-            if (h->tfam_first[b] >= 0) continue;
+            if (h->tfam_first[b] >= 0 || !reachable(b)) continue;
             const BinInfo& e = h->tbins[b];
             const int64_t need = (cap / e.ppw + 1 + kWavesPerBlock - 1) / kWavesPerBlock;
             hipStream_t ls = forks > 1 ? h->fork[launched++ % forks] : stream;
@@ -1779,6 +1803,7 @@ static int trace_paths(sw_handle* h, const sw_batch* batch, const sw_scheme* sch
         if (timing) {
             HIP_TRY(h, hipStreamSynchronize(stream));
             for (int b = 0; b < n_tb; ++b) {
+                if (!reachable(b)) continue;   // not launched
                 // a family launch's sweep is timed once (at its first bin)
                 // and shared by its bins; every bin has its own walk
                 const int b0 = h->tfam_first[b] >= 0 ? h->tfam_first[b] : b;
@@ -1821,6 +1846,9 @@ static int trace_paths(sw_handle* h, const sw_batch* batch, const sw_scheme* sch
         }
         h->bin_stats.push_back(st);
     }
+    for (int b = 0; b < n_tb; ++b)
+        if (!reachable(b) && cnt[kCtrTraceBinPairs + b] != 0)
+            return fail(h, SW_EINTERNAL, "a pair reached path-sweep bin %d, which was not launched", b);
     if (flags[kFlagInternal]) return fail(h, SW_EINTERNAL, "an alignment path could not be recovered");
     if (flags[kFlagPathRoom])
         return fail(h, SW_EINVAL, "the output room of a pair is too small for its path (cigar_len = -1)");

@@ -340,3 +340,52 @@ def test_box_sweep_family_launches_agree(aligner):
         by_launch.setdefault(e["launch"], set()).add((e["ms"], e["family_hi"], e["family_lo"]))
     assert all(len(v) == 1 for v in by_launch.values())
     assert_paths_equal(b, fam, np.arange(0, b.n_pairs, 13))
+
+
+def test_max_query_leaves_unreachable_path_bins_unlaunched():
+    """With the caller's bound on query lengths, the path-sweep bins for taller
+    boxes, and the int32 bins when no score can leave the packed range, are
+    not launched; the paths are those of an unbounded handle and the oracle's.
+    A scheme whose best score times the bound exceeds the packed range keeps
+    the int32 bins."""
+    from paper_2208_12350_amd.binding import Aligner
+    b = W.make_workload("dna_small", n_pairs=2000, seed=77)
+    longest = int(b.q_len().max())
+    rng = np.random.default_rng(6)
+    M = np.full((4, 4), -60, np.int8)
+    np.fill_diagonal(M, 100)
+    hi = W.Scheme(M, 120, 20)
+    pairs = []
+    for n in (300, 500, 700, 900):
+        q = rng.integers(0, 4, size=n).astype(np.uint8)
+        r = q.copy()
+        r[rng.random(n) < 0.05] = 0
+        pairs.append((q, np.concatenate([rng.integers(0, 4, size=20), r]).astype(np.uint8)))
+    big = W.from_pairs(pairs, [0] * len(pairs), [hi])
+    def launched(al):
+        # timing mode: a bin that was not launched reports no time
+        return {(e["precision"], e["lanes"], e["rows"]) for e in al.bin_stats() if e["pass"] == 2 and e["ms"] > 0}
+
+    plain = Aligner(0, timing=2)
+    try:
+        for batch, bound, want_i32 in ((b, longest, False), (big, 900, True)):
+            want = gpu_paths(plain, batch)
+            every = launched(plain)
+            bounded = Aligner(0, max_query=bound, timing=2)
+            try:
+                got = gpu_paths(bounded, batch)
+                some = launched(bounded)
+                st = [e for e in bounded.bin_stats() if e["pass"] == 2]
+            finally:
+                bounded.close()
+            for x, y in zip(got, want):
+                assert np.array_equal(x, y)
+            assert_paths_equal(batch, got, np.arange(0, batch.n_pairs, 5))
+            # fewer launches, among them every bin that took pairs
+            assert some < every, (sorted(some), sorted(every))
+            assert all((e["precision"], e["lanes"], e["rows"]) in some for e in st if e["pairs"])
+            assert max(e["lanes"] * e["rows"] for e in st if (e["precision"], e["lanes"], e["rows"]) in some) \
+                < max(e["lanes"] * e["rows"] for e in st)
+            assert any(key[0] == 32 for key in some) == want_i32
+    finally:
+        plain.close()

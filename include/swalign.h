@@ -153,8 +153,11 @@ const char* sw_last_error(sw_handle* h);
  *   "max_query" 0 (default) or 1..SW_MAX_QUERY: the caller's bound on
  *               query lengths.  Persistent mode then launches no bin that
  *               only longer queries route to (each launch costs its stream
- *               time even when its bin is empty); a pair with a longer
- *               query makes the call return SW_ETOOLONG
+ *               time even when its bin is empty), and sw_align_cigar no
+ *               path-sweep bin for taller boxes, nor its int32 bins when
+ *               the bound times the best substitution score fits the packed
+ *               range; a pair with a longer query makes the call return
+ *               SW_ETOOLONG
  *   "cigar_workspace"  device bytes for the path records of sw_align_cigar
  *               (default half the device's memory, at least 32 GiB; the
  *               smallest accepted value is about 123 MB)

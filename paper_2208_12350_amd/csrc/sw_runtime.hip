@@ -1699,7 +1699,7 @@ static int trace_paths(sw_handle* h, const sw_batch* batch, const sw_scheme* sch
         // for every miss of any of its walks)
         auto walk = [&](int b, hipStream_t ls) -> hipError_t {
             const int rows = h->tbins[b].W * h->tbins[b].R;
-            const int active = rows >= 1024 ? 4 : rows >= 768 ? 8 : rows >= 96 ? 32 : 64;
+            const int active = rows >= 1024 ? 8 : rows >= 768 ? 16 : rows >= 96 ? 32 : 64;
             const int wblocks = active == 64 ? walk_blocks
                                              : (int)std::min<int64_t>((cap + 4 * active - 1) / (4 * active),
                                                                       4 * std::max(1, h->n_cu));

@@ -1261,6 +1261,7 @@ hipError_t launch_trace_walk(const KParams& P, const TraceArgs& T, int bin, int 
     switch (active) {
         case 4: hipLaunchKernelGGL(sw_trace_walk_kernel<4>, grid, dim3(256), 0, s, P, T, bin, path_off, path, path_len); break;
         case 8: hipLaunchKernelGGL(sw_trace_walk_kernel<8>, grid, dim3(256), 0, s, P, T, bin, path_off, path, path_len); break;
+        case 16: hipLaunchKernelGGL(sw_trace_walk_kernel<16>, grid, dim3(256), 0, s, P, T, bin, path_off, path, path_len); break;
         case 32: hipLaunchKernelGGL(sw_trace_walk_kernel<32>, grid, dim3(256), 0, s, P, T, bin, path_off, path, path_len); break;
         default: hipLaunchKernelGGL(sw_trace_walk_kernel<64>, grid, dim3(256), 0, s, P, T, bin, path_off, path, path_len);
     }
